@@ -1,0 +1,145 @@
+"""FP64 CPU oracle for the HHL state-vector path.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product library never imports it, and it
+shares no code with it.
+
+The numerical work lives in oracle.c (plain loops, FP64); this module only
+marshals numpy arrays.  `mlp` holds the FP64 reference of the T0 predictor.
+States are numpy complex128 arrays of length 2^n, qubit q = bit q of the index.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_c128p = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_apply_gate.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, _f64p, ip, ip, ctypes.c_int]
+    lib.orc_apply_swap.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ctypes.c_int]
+    lib.orc_qft.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc_apply_ctrl_unitary.argtypes = [_c128p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc_norm2.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.orc_norm2.restype = ctypes.c_double
+    lib.orc_postselect.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    lib.orc_eigh.argtypes = [ctypes.c_int, _c128p, _f64p, _c128p]
+    lib.orc_hhl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _c128p, _c128p, _c128p, _c128p,
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+def _ints(xs):
+    xs = list(xs or [])
+    arr = (ctypes.c_int * max(1, len(xs)))(*xs)
+    return arr, len(xs)
+
+
+def _nqubits(psi):
+    n = int(psi.size).bit_length() - 1
+    if psi.size != 1 << n:
+        raise ValueError("state length must be a power of two")
+    return n
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def apply_gate(psi, target, u, ctrls=(), cvals=None):
+    """psi <- (controlled) one-qubit gate u (2x2 complex) on `target`, in place."""
+    lib = _load()
+    u8 = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(2, 2)).view(np.float64).ravel()
+    c, nc = _ints(ctrls)
+    v, _ = _ints(cvals if cvals is not None else [1] * len(list(ctrls)))
+    _check(lib.orc_apply_gate(psi, _nqubits(psi), int(target), np.ascontiguousarray(u8), c, v, nc), "apply_gate")
+    return psi
+
+
+def apply_swap(psi, q1, q2, ctrls=(), cvals=None):
+    lib = _load()
+    c, nc = _ints(ctrls)
+    v, _ = _ints(cvals if cvals is not None else [1] * len(list(ctrls)))
+    _check(lib.orc_apply_swap(psi, _nqubits(psi), int(q1), int(q2), c, v, nc), "apply_swap")
+    return psi
+
+
+def qft(psi, lo, m, inverse=False):
+    _check(_load().orc_qft(psi, _nqubits(psi), int(lo), int(m), int(bool(inverse))), "qft")
+    return psi
+
+
+def apply_ctrl_unitary(psi, U, lo, m, ctrl=-1, cval=1, adjoint=False):
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    _check(_load().orc_apply_ctrl_unitary(psi, _nqubits(psi), U, int(lo), int(m), int(ctrl), int(cval),
+                                          int(bool(adjoint))), "apply_ctrl_unitary")
+    return psi
+
+
+def norm2(psi, mask=0, value=0):
+    return float(_load().orc_norm2(psi, _nqubits(psi), int(mask), int(value)))
+
+
+def postselect(psi, mask, value, want_vector=True):
+    n = _nqubits(psi)
+    p = ctypes.c_double(0.0)
+    out = None
+    ptr = None
+    if want_vector:
+        out = np.zeros(1 << (n - bin(int(mask)).count("1")), dtype=np.complex128)
+        ptr = out.ctypes.data_as(ctypes.c_void_p)
+    rc = _load().orc_postselect(psi, n, int(mask), int(value), ctypes.byref(p), ptr)
+    if rc != 0 and p.value != 0.0:
+        _check(rc, "postselect")
+    return p.value, out
+
+
+def eigh(A):
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    N = A.shape[0]
+    lam = np.zeros(N, dtype=np.float64)
+    V = np.zeros((N, N), dtype=np.complex128)
+    _check(_load().orc_eigh(N, A, lam, V), "eigh")
+    return lam, V
+
+
+def hhl(A, b, n_c, T0):
+    """Gate-level HHL (see oracle.c): returns (psi, x, p_post, p_anc)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    if N != 1 << n_s or b.shape != (N,):
+        raise ValueError("A must be 2^n_s square and b of length 2^n_s")
+    psi = np.zeros(1 << (n_s + n_c + 1), dtype=np.complex128)
+    x = np.zeros(N, dtype=np.complex128)
+    pp, pa = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_load().orc_hhl(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa)), "hhl")
+    return psi, x, pp.value, pa.value

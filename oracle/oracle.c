@@ -1,0 +1,444 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference for the HHL state-vector path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it (through oracle/__init__.py).
+ *
+ * Conventions (shared by definition, not by code, with the GPU library):
+ *   - a state on n qubits is 2^n complex doubles; qubit q is bit q of the
+ *     basis index (fixed by the paper's worked example U = H_1 (x) X_0 in the
+ *     appendix "QFlowS - a brief overview", whose 4x4 matrix only matches
+ *     the Kronecker product if qubit 1 is the most significant bit);
+ *   - a one-qubit gate u is row-major 2x2: (a0,a1) <- (u00 a0 + u01 a1,
+ *     u10 a0 + u11 a1) on the pair of indices that differ only in bit q
+ *     (the "algebraic" gate application of the same appendix);
+ *   - HHL register layout: bits [0,n_s) system x, [n_s,n_s+n_c) clock y,
+ *     bit n_s+n_c the ancilla a.
+ *
+ * Every loop here is written for clarity; the only parallelism is an
+ * OpenMP "parallel for" over iterations that are independent by
+ * construction (they touch disjoint amplitudes), which leaves every
+ * floating-point result bit-identical to the serial loop.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+
+static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+/* True when every control qubit of index i holds its required value. */
+static int controls_match(uint64_t i, const int *ctrls, const int *cvals, int nctrl)
+{
+    for (int c = 0; c < nctrl; ++c)
+        if ((int)((i >> ctrls[c]) & 1u) != (cvals ? cvals[c] : 1))
+            return 0;
+    return 1;
+}
+
+static int check_qubits(int n, int target, const int *ctrls, int nctrl)
+{
+    if (n < 1 || n > 40 || target < 0 || target >= n) return ORC_EINVAL;
+    for (int c = 0; c < nctrl; ++c) {
+        if (ctrls[c] < 0 || ctrls[c] >= n || ctrls[c] == target) return ORC_EINVAL;
+        for (int d = 0; d < c; ++d)
+            if (ctrls[d] == ctrls[c]) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+/*
+ * One-qubit gate u (row-major 2x2, interleaved re/im: 8 doubles) on qubit
+ * `target`, applied only where the control qubits match.  This is the pair
+ * update of the appendix's algebraic gate rule: for each index i0 with bit
+ * `target` clear, i1 = i0 | 2^target, the pair (psi[i0], psi[i1]) is
+ * multiplied by u.
+ */
+int orc_apply_gate(cplx *psi, int n, int target, const double *u8,
+                   const int *ctrls, const int *cvals, int nctrl)
+{
+    if (check_qubits(n, target, ctrls, nctrl) != ORC_OK) return ORC_EINVAL;
+    const cplx u00 = u8[0] + I * u8[1], u01 = u8[2] + I * u8[3];
+    const cplx u10 = u8[4] + I * u8[5], u11 = u8[6] + I * u8[7];
+    const uint64_t dim = (uint64_t)1 << n, bit = (uint64_t)1 << target;
+#pragma omp parallel for schedule(static)
+    for (int64_t ii = 0; ii < (int64_t)dim; ++ii) {
+        uint64_t i0 = (uint64_t)ii;
+        if (i0 & bit) continue;
+        if (!controls_match(i0, ctrls, cvals, nctrl)) continue;
+        uint64_t i1 = i0 | bit;
+        cplx a0 = psi[i0], a1 = psi[i1];
+        psi[i0] = u00 * a0 + u01 * a1;
+        psi[i1] = u10 * a0 + u11 * a1;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Exchange of qubits q1 and q2 (the SWAP gate), restricted to indices whose
+ * control qubits match.  A pure permutation: amplitudes are moved, never
+ * combined, so the result is bit-exact.
+ */
+int orc_apply_swap(cplx *psi, int n, int q1, int q2, const int *ctrls,
+                   const int *cvals, int nctrl)
+{
+    if (check_qubits(n, q1, ctrls, nctrl) != ORC_OK) return ORC_EINVAL;
+    if (check_qubits(n, q2, ctrls, nctrl) != ORC_OK || q1 == q2) return ORC_EINVAL;
+    const uint64_t dim = (uint64_t)1 << n;
+    const uint64_t b1 = (uint64_t)1 << q1, b2 = (uint64_t)1 << q2;
+#pragma omp parallel for schedule(static)
+    for (int64_t ii = 0; ii < (int64_t)dim; ++ii) {
+        uint64_t i = (uint64_t)ii;
+        /* visit each exchanged pair once: from the member with q1 set, q2 clear */
+        if (!(i & b1) || (i & b2)) continue;
+        if (!controls_match(i, ctrls, cvals, nctrl)) continue;
+        uint64_t j = (i & ~b1) | b2;
+        cplx t = psi[i];
+        psi[i] = psi[j];
+        psi[j] = t;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Quantum Fourier transform on the register of qubits [lo, lo+m), written
+ * out as its definition (the DFT kernels of the appendix on velocity
+ * gradients): QFT|j> = 2^{-m/2} sum_k exp(+2 pi i j k / 2^m) |k>, the
+ * inverse uses exp(-2 pi i j k / 2^m).  Output is in natural index order.
+ * The phase angle is reduced exactly in integers, (j k mod 2^m) / 2^m,
+ * before the cosine/sine, so no precision is lost for large m.
+ */
+int orc_qft(cplx *psi, int n, int lo, int m, int inverse)
+{
+    if (n < 1 || n > 40 || m < 1 || lo < 0 || lo + m > n) return ORC_EINVAL;
+    const uint64_t M = (uint64_t)1 << m, dim = (uint64_t)1 << n;
+    const uint64_t mask = (M - 1) << lo;
+    const double sgn = inverse ? -1.0 : 1.0, scale = 1.0 / sqrt((double)M);
+    cplx *tw = (cplx *)malloc(sizeof(cplx) * M);
+    if (!tw) return ORC_ENOMEM;
+    for (uint64_t r = 0; r < M; ++r)
+        tw[r] = cos(2.0 * ORC_PI * (double)r / (double)M) +
+                I * sgn * sin(2.0 * ORC_PI * (double)r / (double)M);
+    const uint64_t ncol = dim / M;
+    int err = ORC_OK;
+#pragma omp parallel
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * M);
+        if (!in) {
+#pragma omp atomic write
+            err = ORC_ENOMEM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t cc = 0; cc < (int64_t)ncol; ++cc) {
+            if (!in) continue;
+            /* spread the column index over the bits outside the register */
+            uint64_t c = (uint64_t)cc;
+            uint64_t base = (c & (((uint64_t)1 << lo) - 1)) | ((c >> lo) << (lo + m));
+            for (uint64_t j = 0; j < M; ++j) in[j] = psi[base | (j << lo)];
+            for (uint64_t k = 0; k < M; ++k) {
+                cplx acc = 0;
+                for (uint64_t j = 0; j < M; ++j) acc += tw[(j * k) & (M - 1)] * in[j];
+                psi[base | (k << lo)] = scale * acc;
+            }
+        }
+        free(in);
+    }
+    (void)mask;
+    free(tw);
+    return err;
+}
+
+/*
+ * Controlled dense unitary on the contiguous register [lo, lo+m): for every
+ * basis setting of the other qubits with qubit `ctrl` equal to `cval`
+ * (ctrl < 0: no control), the 2^m sub-vector v is replaced by U v (or U^H v
+ * when `adjoint`).  U is row-major, 2^m x 2^m, interleaved complex.
+ */
+int orc_apply_ctrl_unitary(cplx *psi, int n, const cplx *U, int lo, int m,
+                           int ctrl, int cval, int adjoint)
+{
+    if (n < 1 || n > 40 || m < 1 || lo < 0 || lo + m > n) return ORC_EINVAL;
+    if (ctrl >= n || (ctrl >= lo && ctrl < lo + m)) return ORC_EINVAL;
+    const uint64_t M = (uint64_t)1 << m, dim = (uint64_t)1 << n;
+    const uint64_t ncol = dim / M;
+    int err = ORC_OK;
+#pragma omp parallel
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * M);
+        if (!in) {
+#pragma omp atomic write
+            err = ORC_ENOMEM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t cc = 0; cc < (int64_t)ncol; ++cc) {
+            if (!in) continue;
+            uint64_t c = (uint64_t)cc;
+            uint64_t base = (c & (((uint64_t)1 << lo) - 1)) | ((c >> lo) << (lo + m));
+            if (ctrl >= 0 && (int)((base >> ctrl) & 1u) != cval) continue;
+            for (uint64_t j = 0; j < M; ++j) in[j] = psi[base | (j << lo)];
+            for (uint64_t r = 0; r < M; ++r) {
+                cplx acc = 0;
+                for (uint64_t j = 0; j < M; ++j)
+                    acc += (adjoint ? conj(U[j * M + r]) : U[r * M + j]) * in[j];
+                psi[base | (r << lo)] = acc;
+            }
+        }
+        free(in);
+    }
+    return err;
+}
+
+/* sum of |psi_i|^2 over indices with (i & mask) == value, in FP64 */
+double orc_norm2(const cplx *psi, int n, uint64_t mask, uint64_t value)
+{
+    const uint64_t dim = (uint64_t)1 << n;
+    double s = 0.0;
+    for (uint64_t i = 0; i < dim; ++i)
+        if ((i & mask) == value) s += creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
+    return s;
+}
+
+/*
+ * Post-selection on the qubits in `mask` having the values in `value`: the
+ * probability p of that outcome, and (if out != NULL) the surviving
+ * amplitudes, in increasing index order, divided by sqrt(p).
+ * Returns ORC_EINVAL when p == 0.
+ */
+int orc_postselect(const cplx *psi, int n, uint64_t mask, uint64_t value,
+                   double *prob, cplx *out)
+{
+    if ((value & ~mask) != 0) return ORC_EINVAL;
+    const uint64_t dim = (uint64_t)1 << n;
+    double p = orc_norm2(psi, n, mask, value);
+    if (prob) *prob = p;
+    if (!(p > 0.0)) return ORC_EINVAL;
+    if (out) {
+        const double inv = 1.0 / sqrt(p);
+        uint64_t k = 0;
+        for (uint64_t i = 0; i < dim; ++i)
+            if ((i & mask) == value) out[k++] = psi[i] * inv;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Eigen-decomposition of a Hermitian N x N matrix (row-major) by the cyclic
+ * Jacobi method: repeated 2x2 unitary rotations J, each zeroing one
+ * off-diagonal pair (p,q), until the off-diagonal mass is negligible.
+ * For a pivot a_pq = r e^{i alpha}, J = diag(1, e^{-i alpha}) R, with R the
+ * real Jacobi rotation (c, s; -s, c) that annihilates the now-real pair.
+ * On return lam[j] (ascending) and column j of V (row-major) are the
+ * eigen-pairs: A V = V diag(lam).
+ */
+int orc_eigh(int N, const cplx *A_in, double *lam, cplx *V)
+{
+    if (N < 1 || N > 8192) return ORC_EINVAL;
+    cplx *A = (cplx *)malloc(sizeof(cplx) * (size_t)N * N);
+    if (!A) return ORC_ENOMEM;
+    memcpy(A, A_in, sizeof(cplx) * (size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) V[(size_t)i * N + j] = (i == j) ? 1.0 : 0.0;
+
+    double fro = 0.0;
+    for (size_t k = 0; k < (size_t)N * N; ++k) fro += creal(A[k] * conj(A[k]));
+    fro = sqrt(fro);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < N; ++p)
+            for (int q = p + 1; q < N; ++q) off += 2.0 * creal(A[(size_t)p * N + q] * conj(A[(size_t)p * N + q]));
+        if (sqrt(off) <= 1e-15 * fro || fro == 0.0) break;
+        for (int p = 0; p < N - 1; ++p) {
+            for (int q = p + 1; q < N; ++q) {
+                cplx apq = A[(size_t)p * N + q];
+                double r = cabs(apq);
+                if (r == 0.0) continue;
+                double app = creal(A[(size_t)p * N + p]), aqq = creal(A[(size_t)q * N + q]);
+                cplx ph = conj(apq) / r; /* e^{-i alpha} */
+                double theta = (aqq - app) / (2.0 * r);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                /* J on the (p,q) plane: [[c, s], [-s ph, c ph]] */
+                cplx Jpp = c, Jpq = s, Jqp = -s * ph, Jqq = c * ph;
+                /* A <- A J (columns p, q) */
+                for (int k = 0; k < N; ++k) {
+                    cplx akp = A[(size_t)k * N + p], akq = A[(size_t)k * N + q];
+                    A[(size_t)k * N + p] = akp * Jpp + akq * Jqp;
+                    A[(size_t)k * N + q] = akp * Jpq + akq * Jqq;
+                }
+                /* A <- J^H A (rows p, q) */
+                for (int k = 0; k < N; ++k) {
+                    cplx apk = A[(size_t)p * N + k], aqk = A[(size_t)q * N + k];
+                    A[(size_t)p * N + k] = conj(Jpp) * apk + conj(Jqp) * aqk;
+                    A[(size_t)q * N + k] = conj(Jpq) * apk + conj(Jqq) * aqk;
+                }
+                A[(size_t)p * N + q] = 0.0;
+                A[(size_t)q * N + p] = 0.0;
+                /* V <- V J */
+                for (int k = 0; k < N; ++k) {
+                    cplx vkp = V[(size_t)k * N + p], vkq = V[(size_t)k * N + q];
+                    V[(size_t)k * N + p] = vkp * Jpp + vkq * Jqp;
+                    V[(size_t)k * N + q] = vkp * Jpq + vkq * Jqq;
+                }
+            }
+        }
+    }
+    for (int j = 0; j < N; ++j) lam[j] = creal(A[(size_t)j * N + j]);
+    /* sort ascending (selection sort keeps it obvious) */
+    for (int a = 0; a < N; ++a) {
+        int best = a;
+        for (int b = a + 1; b < N; ++b)
+            if (lam[b] < lam[best]) best = b;
+        if (best != a) {
+            double tl = lam[a]; lam[a] = lam[best]; lam[best] = tl;
+            for (int k = 0; k < N; ++k) {
+                cplx tv = V[(size_t)k * N + a];
+                V[(size_t)k * N + a] = V[(size_t)k * N + best];
+                V[(size_t)k * N + best] = tv;
+            }
+        }
+    }
+    free(A);
+    return ORC_OK;
+}
+
+/*
+ * The phase of eigen-component j under U^(2^k) = exp(i A T0 2^k):
+ * phi_j = lam_j T0 / (2 pi) is formed once in FP64 and the clock bit k
+ * contributes exp(2 pi i frac(phi_j 2^k)); multiplying by 2^k and taking
+ * the fractional part are exact in binary floating point.
+ */
+static double frac_phase(double phi, int k)
+{
+    double x = ldexp(phi, k);
+    return x - floor(x);
+}
+
+/*
+ * U_k = V diag(exp(2 pi i frac(phi_j 2^k))) V^H on the system register,
+ * written out as a dense matrix.
+ */
+static void build_uk(int N, const cplx *V, const double *phi, int k, cplx *Uk)
+{
+    for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) {
+            cplx acc = 0;
+            for (int j = 0; j < N; ++j) {
+                double f = frac_phase(phi[j], k);
+                cplx e = cos(2.0 * ORC_PI * f) + I * sin(2.0 * ORC_PI * f);
+                acc += V[(size_t)r * N + j] * e * conj(V[(size_t)c * N + j]);
+            }
+            Uk[(size_t)r * N + c] = acc;
+        }
+}
+
+/*
+ * HHL (QLSA-1) as a gate-level circuit, step by step:
+ *   1. |0>_a |0>_c |b/|b|>_s
+ *   2. Hadamard on every clock qubit
+ *   3. eigen-decomposition A = V diag(lam) V^H; phi_j = lam_j T0 / (2 pi)
+ *   4. for k = 0..n_c-1: controlled on clock qubit k, apply U_k = exp(i A T0 2^k)
+ *      on the system register (phase estimation with e^{i A T0}, least count
+ *      2^{-n_c} on lam T0 / 2 pi)
+ *   5. inverse QFT on the clock register
+ *   6. eigenvalue inversion: for clock value y >= 1, rotate the ancilla by
+ *      Ry(theta_y) with sin(theta_y / 2) = C / lam~_y = 1 / y, where
+ *      lam~_y = 2 pi y / (2^n_c T0) and C = 2 pi / (2^n_c T0) is the least
+ *      count; y = 0 is left untouched
+ *   7. uncompute: QFT on the clock, controlled U_k^H for k = n_c-1..0,
+ *      Hadamard on every clock qubit
+ *   8. post-select ancilla = 1 and clock = 0
+ * Outputs: the whole final state psi (2^(n_s+n_c+1)), the normalised
+ * post-selected system vector x (2^n_s), p_post = P(a=1, y=0) and
+ * p_anc = P(a=1).
+ */
+int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
+            cplx *psi, cplx *x_out, double *p_post, double *p_anc)
+{
+    if (n_s < 1 || n_c < 1 || n_s + n_c + 1 > 30 || !(T0 > 0.0)) return ORC_EINVAL;
+    const int N = 1 << n_s, n = n_s + n_c + 1;
+    const uint64_t dim = (uint64_t)1 << n;
+    const int anc = n_s + n_c;
+
+    double bn = 0.0;
+    for (int j = 0; j < N; ++j) bn += creal(b[j] * conj(b[j]));
+    bn = sqrt(bn);
+    if (!(bn > 0.0)) return ORC_EINVAL;
+
+    /* 1. initial state */
+    memset(psi, 0, sizeof(cplx) * dim);
+    for (int j = 0; j < N; ++j) psi[j] = b[j] / bn;
+
+    /* 2. Hadamards on the clock */
+    const double h = 1.0 / sqrt(2.0);
+    const double H8[8] = {h, 0, h, 0, h, 0, -h, 0};
+    for (int k = 0; k < n_c; ++k) orc_apply_gate(psi, n, n_s + k, H8, NULL, NULL, 0);
+
+    /* 3. spectrum */
+    double *lam = (double *)malloc(sizeof(double) * N);
+    double *phi = (double *)malloc(sizeof(double) * N);
+    cplx *V = (cplx *)malloc(sizeof(cplx) * (size_t)N * N);
+    cplx *Uk = (cplx *)malloc(sizeof(cplx) * (size_t)N * N);
+    if (!lam || !phi || !V || !Uk) {
+        free(lam); free(phi); free(V); free(Uk);
+        return ORC_ENOMEM;
+    }
+    orc_eigh(N, A, lam, V);
+    for (int j = 0; j < N; ++j) phi[j] = lam[j] * T0 / (2.0 * ORC_PI);
+
+    /* 4. controlled powers of exp(i A T0) */
+    for (int k = 0; k < n_c; ++k) {
+        build_uk(N, V, phi, k, Uk);
+        orc_apply_ctrl_unitary(psi, n, Uk, 0, n_s, n_s + k, 1, 0);
+    }
+
+    /* 5. inverse QFT on the clock */
+    orc_qft(psi, n, n_s, n_c, 1);
+
+    /* 6. controlled-Ry eigenvalue inversion, one clock value at a time */
+    const uint64_t Y = (uint64_t)1 << n_c;
+    for (uint64_t y = 1; y < Y; ++y) {
+        double s = 1.0 / (double)y, c = sqrt(1.0 - s * s);
+        for (uint64_t x = 0; x < (uint64_t)N; ++x) {
+            uint64_t i0 = x | (y << n_s), i1 = i0 | ((uint64_t)1 << anc);
+            cplx a0 = psi[i0], a1 = psi[i1];
+            psi[i0] = c * a0 - s * a1;
+            psi[i1] = s * a0 + c * a1;
+        }
+    }
+
+    /* 7. uncompute the phase estimation */
+    orc_qft(psi, n, n_s, n_c, 0);
+    for (int k = n_c - 1; k >= 0; --k) {
+        build_uk(N, V, phi, k, Uk);
+        orc_apply_ctrl_unitary(psi, n, Uk, 0, n_s, n_s + k, 1, 1);
+    }
+    for (int k = 0; k < n_c; ++k) orc_apply_gate(psi, n, n_s + k, H8, NULL, NULL, 0);
+
+    /* 8. post-selection */
+    const uint64_t amask = (uint64_t)1 << anc, cmask = (Y - 1) << n_s;
+    double pa = orc_norm2(psi, n, amask, amask);
+    if (p_anc) *p_anc = pa;
+    double pp = 0.0;
+    int rc = orc_postselect(psi, n, amask | cmask, amask, &pp, x_out);
+    if (p_post) *p_post = pp;
+    free(lam); free(phi); free(V); free(Uk);
+    return rc;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
