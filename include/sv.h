@@ -1,0 +1,253 @@
+/*
+ * sv.h -- C ABI of the MI355X state-vector library for gate-level HHL
+ * (QLSA-1) as used for the Poiseuille / Couette flow systems of
+ * "Hybrid quantum algorithms for flow problems" (arXiv:2307.00391).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - A state on n qubits is a device array of 2^n complex amplitudes,
+ *    interleaved (re, im): float2 for SV_C64, double2 for SV_C128.
+ *    Qubit q is bit q of the basis index.  This order is the one fixed by
+ *    the paper's worked two-qubit example U = H_1 (x) X_0 (appendix
+ *    "QFlowS - a brief overview", gates and circuits); it is the reverse of
+ *    the stride 2^(n-q-1) written in the same paragraph's Hadamard rule.
+ *  - HHL register layout: bits [0, n_s) system register x, bits
+ *    [n_s, n_s + n_c) clock register y, bit n_s + n_c the ancilla a.
+ *  - One-qubit gates are row-major 2x2 complex matrices given as 8 host
+ *    doubles (u00re, u00im, u01re, u01im, u10re, u10im, u11re, u11im) and act
+ *    on each index pair (i0, i1 = i0 | 2^target) as
+ *    (a_i0, a_i1) <- (u00 a_i0 + u01 a_i1, u10 a_i0 + u11 a_i1)
+ *    (the "algebraic" pair update of the same appendix).  Gate matrices are
+ *    taken in FP64; the SV_C64 path rounds them to FP32 once.
+ *  - Every call enqueues its kernels on the state's HIP stream (borrowed;
+ *    NULL = the null stream).  Calls that hand back host scalars or host
+ *    vectors synchronise that stream before returning.
+ *  - All functions return sv_status.  On a validation error nothing is
+ *    enqueued and the state is unchanged; sv_last_error() returns a
+ *    thread-local description of the last failure.
+ *  - Pointers passed in are borrowed for the duration of the call only
+ *    (device inputs must stay live until the stream has drained).
+ *    The library owns sv_state handles and any buffer it allocated.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_EINVAL = -1,          /* bad argument: qubit out of range, duplicate qubits, sizes */
+    SV_ENOMEM = -2,          /* device allocation failed (or state larger than device memory) */
+    SV_EDEVICE = -3,         /* HIP / library runtime error */
+    SV_ENOTHERMITIAN = -4,   /* |A - A^H|_max > 1e-12 |A|_max */
+    SV_ENOTPOSDEF = -5,      /* lambda_min <= 0 (the clock register is unsigned) */
+    SV_EZERONORM = -6,       /* |b| = 0, or a post-selected outcome of probability 0 */
+    SV_EUNSUPPORTED = -7     /* valid request outside what this build implements */
+} sv_status;
+
+typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
+
+typedef struct sv_state_s *sv_state;   /* opaque; owned by the library */
+
+/* ------------------------------------------------------------------------
+ * State management
+ * --------------------------------------------------------------------- */
+
+/* Create a state of n_qubits (1..34) amplitudes of type dt.
+ * device_buf: borrowed device memory of at least 2^n * sizeof(amplitude)
+ * bytes (e.g. a torch tensor's storage), or NULL to let the library
+ * allocate it (freed by sv_free).  hip_stream: a hipStream_t, or NULL.
+ * The contents are left as found (use sv_init_basis / sv_init_b).
+ * Errors: SV_EINVAL (n out of range), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_alloc(sv_state *out, int n_qubits, sv_dtype dt, void *device_buf, void *hip_stream);
+
+/* Release the handle (and the buffer if the library allocated it). */
+sv_status sv_free(sv_state s);
+
+/* Device pointer of the amplitudes, qubit count, dtype. */
+void *sv_data(sv_state s);
+int sv_num_qubits(sv_state s);
+sv_dtype sv_get_dtype(sv_state s);
+sv_status sv_set_stream(sv_state s, void *hip_stream);
+
+/* |index>: one amplitude 1, all others 0. */
+sv_status sv_init_basis(sv_state s, uint64_t index);
+
+/* HHL initial state |0>_a (H^{(x)c}|0>)_clock |b/|b|>_system, where the
+ * system register is bits [0, n_s) and c = n_clock_superpose clock qubits
+ * occupy bits [n_s, n_s + c) (c = 0: the clock stays |0>).  All other bits
+ * are |0>.  b: host, 2^n_s complex FP64 interleaved, not necessarily
+ * normalised (state preparation, main text "Quantum State Preparation";
+ * the clock superposition is the first layer of phase estimation).
+ * Errors: SV_EINVAL (n_s + c > n), SV_EZERONORM (|b| = 0). */
+sv_status sv_init_b(sv_state s, const double *b, int n_s, int n_clock_superpose);
+
+/* Copy the whole state from / to host memory as complex FP64 interleaved
+ * (2 * 2^n doubles); the SV_C64 path converts on the device. */
+sv_status sv_set_state(sv_state s, const double *host);
+sv_status sv_get_state(sv_state s, double *host);
+
+/* ------------------------------------------------------------------------
+ * Gates (appendix "QFlowS - a brief overview": gates applied as algebraic
+ * pair updates without forming 2^n x 2^n matrices)
+ * --------------------------------------------------------------------- */
+
+/* One-qubit gate u on `target`, applied where every control qubit ctrls[i]
+ * equals ctrl_vals[i] (ctrl_vals NULL: all 1).  A c-controlled gate touches
+ * 2^(n-c) amplitudes.  When u is exactly X = [[0,1],[1,0]] the update is a
+ * pure exchange of amplitudes (bit-exact); when u is diagonal only the
+ * amplitudes whose phase changes are rewritten.
+ * Errors: SV_EINVAL (qubit out of range or repeated, n_ctrls > 32). */
+sv_status sv_apply_gate(sv_state s, int target, const double u[8], const int *ctrls,
+                        const int *ctrl_vals, int n_ctrls);
+
+/* Exchange of qubits q1 and q2 where the controls match (bit-exact). */
+sv_status sv_apply_swap(sv_state s, int q1, int q2, const int *ctrls, const int *ctrl_vals,
+                        int n_ctrls);
+
+/* A gate of a circuit passed to sv_apply_circuit. */
+typedef enum {
+    SV_GATE_U = 0,      /* dense one-qubit u on target (diagonal u allowed) */
+    SV_GATE_X = 1,      /* bit-exact X on target (with controls: CNOT, Toffoli, ...) */
+    SV_GATE_SWAP = 2    /* bit-exact exchange of target and target2 */
+} sv_gate_kind;
+
+#define SV_MAX_CTRLS 8
+typedef struct {
+    int kind;                        /* sv_gate_kind */
+    int target, target2;             /* target2 only for SV_GATE_SWAP */
+    int n_ctrls;
+    int ctrls[SV_MAX_CTRLS];
+    int ctrl_vals[SV_MAX_CTRLS];
+    double u[8];                     /* SV_GATE_U only */
+} sv_gate;
+
+/* Apply gates[0..n_gates) in order.  The library groups the circuit into
+ * passes: each pass stages tiles of 2^k amplitudes (k "local" qubits: the
+ * lowest few bits plus the targets it needs) in LDS and applies every gate
+ * it can there, so a run of g gates costs one read and one write of the
+ * state instead of g.  Gates are only moved past gates on disjoint qubits;
+ * the result equals the in-order product.  max_local <= 0 lets the
+ * autotuner choose k. */
+sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, int n_gates, int max_local);
+
+/* Number of fused passes sv_apply_circuit would run (planning only). */
+int sv_plan_passes(int n_qubits, sv_dtype dt, const sv_gate *gates, int n_gates, int max_local);
+
+/* Controlled dense unitary on the contiguous register [sys_lo, sys_lo + m):
+ * for every setting of the other qubits with qubit ctrl == ctrl_val
+ * (ctrl < 0: unconditional) the 2^m sub-vector v becomes U v, or U^H v if
+ * `adjoint`.  U: device, 2^m x 2^m, row-major, in the state's dtype.  This
+ * is the controlled-U^(2^k) of phase estimation (main text: the operator is
+ * exponentiated as exp(i A T0)), computed as a complex GEMM on the matrix
+ * cores.  Only sys_lo == 0 is implemented (SV_EUNSUPPORTED otherwise).
+ * Errors: SV_EINVAL (register outside the state, ctrl inside it). */
+sv_status sv_apply_ctrl_unitary(sv_state s, const void *U, int sys_lo, int m, int ctrl,
+                                int ctrl_val, int adjoint);
+
+/* Quantum Fourier transform on qubits [q_lo, q_lo + m):
+ * QFT|j> = 2^(-m/2) sum_k exp(+2 pi i j k / 2^m) |k>, inverse with
+ * exp(-2 pi i j k / 2^m) (QFT / IQFT kernels of the appendix on spectral
+ * velocity gradients).  swaps = 1 gives exact DFT index order (the
+ * textbook final bit reversal, bit-exact); swaps = 0 leaves the register
+ * bit-reversed (the QFT) or expects it bit-reversed (the inverse).
+ * max_local as in sv_apply_circuit. */
+sv_status sv_qft(sv_state s, int q_lo, int m, int inverse, int swaps, int max_local);
+
+/* Uniformly controlled Ry: for each value v of the register [reg_lo,
+ * reg_lo + m), rotate qubit `target` by the real 2x2 [[c_v, -s_v], [s_v, c_v]]
+ * with (c_v, s_v) = cs[2v], cs[2v+1] (host FP64, 2^(m+1) doubles).  With
+ * s_v = C / lambda~_v this is the eigenvalue-inversion rotation of HHL.
+ * extra_ctrl >= 0 restricts it to indices whose qubit extra_ctrl equals
+ * extra_val. */
+sv_status sv_apply_uniform_ry(sv_state s, int target, int reg_lo, int m, const double *cs,
+                              int extra_ctrl, int extra_val);
+
+/* ------------------------------------------------------------------------
+ * Measurement-side reductions (FP64 accumulation)
+ * --------------------------------------------------------------------- */
+
+/* sum |a_i|^2 over indices with (i & mask) == value, accumulated in FP64
+ * with a fixed reduction order (repeatable bit for bit). */
+sv_status sv_norm2(sv_state s, uint64_t mask, uint64_t value, double *out);
+
+/* Post-selection of the outcome (i & mask) == value (main text: the
+ * post-selected state of the QLSA output).  *prob = its probability (FP64).
+ * out (may be NULL): 2^(n - popcount(mask)) complex amplitudes in
+ * increasing index order, divided by sqrt(prob); complex FP64 on the host
+ * if out_on_device == 0, else the state's dtype on the device.
+ * Errors: SV_EINVAL (value outside mask), SV_EZERONORM (prob == 0). */
+sv_status sv_postselect(sv_state s, uint64_t mask, uint64_t value, double *prob, void *out,
+                        int out_on_device);
+
+/* ------------------------------------------------------------------------
+ * HHL (QLSA-1, main text "Quantum Linear Systems Algorithm"; phase
+ * estimation with exp(i A T0) and least count 2^-n_c, "Flow simulation
+ * results")
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+    int n_s;       /* system qubits: A is 2^n_s x 2^n_s */
+    int n_c;       /* clock (phase-estimation) qubits */
+    double T0;     /* clock bit k applies exp(i A T0 2^k); y = 2^n_c lambda T0 / 2 pi */
+    int mode;      /* 0: gate-faithful (dense controlled-U_k on the matrix cores, every
+                      step on the full state);  1: eigen-frame (system register held in
+                      the eigenbasis of A; the controlled-U_k become one diagonal pass,
+                      uncompute runs on the ancilla = 1 half and ends in the fused
+                      clock = 0 projection) */
+    int signed_clock;  /* must be 0: unsigned clock, A positive definite */
+} sv_hhl_params;
+
+typedef struct {
+    double p_post;      /* P(ancilla = 1, clock = 0), FP64 */
+    double p_anc;       /* P(ancilla = 1) after the inversion rotation, FP64 */
+    double norm_total;  /* squared norm of the state after the rotation, FP64 */
+    double lambda_min, lambda_max;   /* spectrum edges of A (FP64 eigen-decomposition) */
+} sv_hhl_result;
+
+/* Solve A x = b by simulating the HHL circuit on the state s, which must
+ * hold n_s + n_c + 1 qubits.  Steps: |0>_a H^{(x)n_c}|0>_c |b^>_s; for
+ * k = 0..n_c-1 controlled on clock bit k apply U_k = V diag(exp(2 pi i
+ * frac(phi_j 2^k))) V^H with phi_j = lambda_j T0 / 2 pi (FP64
+ * eigen-decomposition A = V diag(lambda) V^H); inverse QFT on the clock;
+ * for clock value y >= 1 rotate the ancilla by Ry(theta_y) with
+ * sin(theta_y / 2) = 1 / y (inversion constant C = least count
+ * 2 pi / (2^n_c T0)), y = 0 untouched; QFT; controlled U_k^H for
+ * k = n_c-1..0; H^{(x)n_c}; post-select ancilla = 1, clock = 0.
+ * A: host, 2^n_s x 2^n_s complex FP64 row-major, Hermitian.  b: host,
+ * 2^n_s complex FP64.  x_out (may be NULL): host, 2^n_s complex FP64, the
+ * post-selected system vector divided by sqrt(p_post) (global phase as the
+ * circuit leaves it).  After mode 0 the state holds the final circuit state;
+ * after mode 1 its contents are unspecified.
+ * Errors: SV_EINVAL, SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM (|b| = 0 or
+ * p_post = 0), SV_EUNSUPPORTED (signed_clock != 0), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm,
+                 sv_hhl_result *res, double *x_out);
+
+/* HHL for a separable operator A = A_hi (x) I + I (x) A_lo (a Laplacian /
+ * Poisson operator on a 2-D tensor grid, main text: "d-dimensional Laplace,
+ * Poisson and heat equations"), A_hi 2^m_hi square acting on system bits
+ * [m_lo, n_s), A_lo 2^m_lo square on bits [0, m_lo), n_s = m_hi + m_lo.
+ * The eigen-decomposition is taken factor by factor (V = V_hi (x) V_lo,
+ * lambda = mu_p + nu_q), so n_s = 16 needs two 256-point solves instead of
+ * one 65536-point one.  Only mode 1 is implemented for n_s > 12.
+ * Other arguments and results as sv_hhl. */
+sv_status sv_hhl_kron(sv_state s, const double *A_hi, int m_hi, const double *A_lo, int m_lo,
+                      const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
+                      double *x_out);
+
+/* Last error message of the calling thread ("" if none). */
+const char *sv_last_error(void);
+
+/* Library build string (target, compiler) for reports. */
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

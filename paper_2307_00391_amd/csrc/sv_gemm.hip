@@ -1,0 +1,212 @@
+// Controlled dense unitary on the system register as a complex GEMM on the
+// matrix cores (MFMA): every amplitude row whose control bit matches is a
+// length-2^m vector v, replaced by U v.  Rows are gathered straight from
+// the state (row r lives at pdep(r, row_mask) | row_fix, its 2^m elements
+// contiguous), multiplied out of place into a compact buffer and scattered
+// back.  complex64 uses v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate);
+// complex128 uses v_mfma_f64_16x16x4f64.  A complex product is four real
+// MFMAs: re += ar br - ai bi, im += ar bi + ai br.
+#include <string.h>
+
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct MfmaT;
+template <> struct MfmaT<float> {
+    using acc = floatx4;
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfmaT<double> {
+    using acc = doublex4;
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <typename R>
+struct GemmArgs {
+    const cvec<R> *in;   // rows of length K
+    cvec<R> *out;        // M x N, row-major, compact
+    const cvec<R> *U;    // B(kk, n) = trans ? U[kk * N + n] : U[n * K + kk]  (conj if conjb)
+    uint64_t M;
+    int N, K;
+    uint64_t row_mask, row_fix;   // row r starts at pdep(r, row_mask) | row_fix
+    int trans, conjb;
+};
+
+// 256 threads: 4 waves as 2 x 2, each wave a 32 x 32 output block made of
+// 2 x 2 MFMA 16 x 16 tiles.  Operands are staged in LDS as separate real and
+// imaginary planes, k-major, so the 16 lanes that share a k read 16
+// consecutive words.
+template <typename R>
+__global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
+    using M_ = MfmaT<R>;
+    using acc_t = typename M_::acc;
+    __shared__ R As_re[GBK][GBM], As_im[GBK][GBM], Bs_re[GBK][GBN], Bs_im[GBK][GBN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const uint64_t row0 = (uint64_t)blockIdx.x * GBM;
+    const int n0 = blockIdx.y * GBN;
+
+    // this thread's A-load row and its base offset in the state
+    const int a_row = tid >> 2, a_k = (tid & 3) * 4;
+    const uint64_t ar = row0 + a_row;
+    const bool a_ok = ar < A.M;
+    const uint64_t a_base = a_ok ? (pdep64(ar, A.row_mask) | A.row_fix) : 0;
+
+    acc_t acc_re[2][2], acc_im[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) acc_re[i][j][v] = acc_im[i][j][v] = (R)0;
+
+    const R csgn = A.conjb ? (R)-1 : (R)1;
+    for (int k0 = 0; k0 < A.K; k0 += GBK) {
+        // A tile: 64 rows x 16 k
+        for (int i = 0; i < 4; ++i) {
+            const int kk = k0 + a_k + i;
+            cvec<R> v = cmake<R>((R)0, (R)0);
+            if (a_ok && kk < A.K) v = A.in[a_base + kk];
+            As_re[a_k + i][a_row] = v.x;
+            As_im[a_k + i][a_row] = v.y;
+        }
+        // B tile: 16 k x 64 n
+        if (!A.trans) {
+            const int bn = tid >> 2, bk = (tid & 3) * 4;
+            for (int i = 0; i < 4; ++i) {
+                const int kk = k0 + bk + i, nn = n0 + bn;
+                cvec<R> v = cmake<R>((R)0, (R)0);
+                if (kk < A.K && nn < A.N) v = A.U[(uint64_t)nn * A.K + kk];
+                Bs_re[bk + i][bn] = v.x;
+                Bs_im[bk + i][bn] = csgn * v.y;
+            }
+        } else {
+            const int bk = tid >> 4, bn = (tid & 15) * 4;
+            for (int i = 0; i < 4; ++i) {
+                const int kk = k0 + bk, nn = n0 + bn + i;
+                cvec<R> v = cmake<R>((R)0, (R)0);
+                if (kk < A.K && nn < A.N) v = A.U[(uint64_t)kk * A.N + nn];
+                Bs_re[bk][bn + i] = v.x;
+                Bs_im[bk][bn + i] = csgn * v.y;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kc = 0; kc < GBK / 4; ++kc) {
+            const int kr = kc * 4 + (lane >> 4), li = lane & 15;
+            R ar_[2], ai_[2], br_[2], bi_[2];
+            for (int i = 0; i < 2; ++i) {
+                ar_[i] = As_re[kr][wm * 32 + i * 16 + li];
+                ai_[i] = As_im[kr][wm * 32 + i * 16 + li];
+                br_[i] = Bs_re[kr][wn * 32 + i * 16 + li];
+                bi_[i] = Bs_im[kr][wn * 32 + i * 16 + li];
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    acc_re[i][j] = M_::mfma(ar_[i], br_[j], acc_re[i][j]);
+                    acc_re[i][j] = M_::mfma(-ai_[i], bi_[j], acc_re[i][j]);
+                    acc_im[i][j] = M_::mfma(ar_[i], bi_[j], acc_im[i][j]);
+                    acc_im[i][j] = M_::mfma(ai_[i], br_[j], acc_im[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+    // D[i][j] of a 16x16 tile sits in lane j + 16 (i / 4), element i % 4
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t r = row0 + wm * 32 + i * 16 + (lane >> 4) * 4 + v;
+                const int c = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (r < A.M && c < A.N) A.out[r * A.N + c] = cmake<R>(acc_re[i][j][v], acc_im[i][j][v]);
+            }
+}
+
+template <typename R>
+__global__ void k_scatter_rows(cvec<R> *__restrict__ psi, const cvec<R> *__restrict__ src, uint64_t M, int mbits,
+                               uint64_t row_mask, uint64_t row_fix) {
+    const uint64_t total = M << mbits;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t cm = (1ull << mbits) - 1ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t r = i >> mbits;
+        psi[(pdep64(r, row_mask) | row_fix) + (i & cm)] = src[i];
+    }
+}
+
+// host: Out(M x N) = rows(In) * B, with B as described in GemmArgs
+template <typename R>
+sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N, int K,
+                uint64_t row_mask, uint64_t row_fix, int trans, int conjb) {
+    GemmArgs<R> a;
+    a.in = in;
+    a.out = out;
+    a.U = U;
+    a.M = M;
+    a.N = N;
+    a.K = K;
+    a.row_mask = row_mask;
+    a.row_fix = row_fix;
+    a.trans = trans;
+    a.conjb = conjb;
+    const uint64_t gm = (M + GBM - 1) / GBM;
+    const unsigned gn = (unsigned)((N + GBN - 1) / GBN);
+    if (gm > 0x7fffffffull) return fail(SV_EUNSUPPORTED, "GEMM with too many rows");
+    hipLaunchKernelGGL(k_cgemm<R>, dim3((unsigned)gm, gn), dim3(256), 0, st, a);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+template sv_status cgemm<float>(hipStream_t, const float2 *, float2 *, const float2 *, uint64_t, int, int, uint64_t,
+                                uint64_t, int, int);
+template sv_status cgemm<double>(hipStream_t, const double2 *, double2 *, const double2 *, uint64_t, int, int,
+                                 uint64_t, uint64_t, int, int);
+
+template <typename R>
+sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint) {
+    const uint64_t all = (s->n >= 64) ? ~0ull : ((1ull << s->n) - 1ull);
+    uint64_t row_mask = all & ~((1ull << m) - 1ull);
+    uint64_t row_fix = 0;
+    if (ctrl >= 0) {
+        row_mask &= ~(1ull << ctrl);
+        row_fix = (uint64_t)(ctrl_val ? 1 : 0) << ctrl;
+    }
+    const uint64_t M = dim_of(popcount64(row_mask));
+    const int N = 1 << m;
+    SV_TRY(ensure_scratch(s, (size_t)M * N * sizeof(cvec<R>)));
+    cvec<R> *out = (cvec<R> *)s->scratch;
+    SV_TRY(cgemm<R>(s->stream, (const cvec<R> *)s->data, out, U, M, N, N, row_mask, row_fix, adjoint, adjoint));
+    const uint64_t total = M * (uint64_t)N;
+    uint64_t g = (total + 1023) / 1024;
+    if (g > (1u << 20)) g = 1u << 20;
+    hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)g), dim3(256), 0, s->stream, (cvec<R> *)s->data,
+                       (const cvec<R> *)out, M, m, row_mask, row_fix);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+template sv_status ctrl_unitary_impl<float>(sv_state, const float2 *, int, int, int, int);
+template sv_status ctrl_unitary_impl<double>(sv_state, const double2 *, int, int, int, int);
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" sv_status sv_apply_ctrl_unitary(sv_state s, const void *U, int sys_lo, int m, int ctrl, int ctrl_val,
+                                           int adjoint) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!U) return fail(SV_EINVAL, "U is NULL");
+    if (m < 1 || sys_lo < 0 || sys_lo + m > s->n) return fail(SV_EINVAL, "register [%d,%d) outside the state", sys_lo, sys_lo + m);
+    if (ctrl >= s->n || (ctrl >= sys_lo && ctrl < sys_lo + m)) return fail(SV_EINVAL, "control %d invalid", ctrl);
+    if (sys_lo != 0) return fail(SV_EUNSUPPORTED, "only sys_lo == 0 is implemented");
+    if (m > 16) return fail(SV_EUNSUPPORTED, "dense register of %d qubits", m);
+    if (s->dt == SV_C64) return ctrl_unitary_impl<float>(s, (const float2 *)U, m, ctrl, ctrl_val, adjoint ? 1 : 0);
+    return ctrl_unitary_impl<double>(s, (const double2 *)U, m, ctrl, ctrl_val, adjoint ? 1 : 0);
+}
