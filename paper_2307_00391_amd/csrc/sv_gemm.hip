@@ -17,17 +17,23 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct MfmaT;
+// Operands of both: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+// Results: the FP32 form keeps four consecutive rows per lane group
+// (row 4 (l / 16) + v), the FP64 form interleaves them (row l / 16 + 4 v);
+// the column is l % 16 in both.
 template <> struct MfmaT<float> {
     using acc = floatx4;
     static __device__ __forceinline__ acc mfma(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) * 4 + v; }
 };
 template <> struct MfmaT<double> {
     using acc = doublex4;
     static __device__ __forceinline__ acc mfma(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
 constexpr int GBM = 64, GBN = 64, GBK = 16;
@@ -120,11 +126,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
         }
         __syncthreads();
     }
-    // D[i][j] of a 16x16 tile sits in lane j + 16 (i / 4), element i % 4
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int v = 0; v < 4; ++v) {
-                const uint64_t r = row0 + wm * 32 + i * 16 + (lane >> 4) * 4 + v;
+                const uint64_t r = row0 + wm * 32 + i * 16 + M_::row(lane, v);
                 const int c = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (r < A.M && c < A.N) A.out[r * A.N + c] = cmake<R>(acc_re[i][j][v], acc_im[i][j][v]);
             }

@@ -1,0 +1,654 @@
+// HHL (QLSA-1) on the state vector.
+//
+// Register layout: bits [0, n_s) system x, [n_s, n_s + n_c) clock, bit
+// n_s + n_c ancilla.  Both modes simulate the same circuit:
+//   |0>_a H|0>_c |b^>  ->  controlled U_k = exp(i A T0 2^k)  ->  inverse QFT
+//   ->  Ry(theta_y), sin(theta_y/2) = 1/y  ->  QFT  ->  controlled U_k^H
+//   ->  H on the clock  ->  post-select a = 1, clock = 0.
+// The QFT's final bit reversal is never materialised in the middle of the
+// circuit: the clock qubit that controls U_k is relabelled n_c-1-k instead
+// (a bit reversal commutes with the Hadamard layer and maps the control of
+// U_k from bit k to bit n_c-1-k), so the cascades run without swaps.
+//
+// mode 0 (gate-faithful): every controlled U_k is a dense 2^n_s x 2^n_s
+// matrix, built in FP64 as V diag(exp(2 pi i frac(phi_j 2^k))) V^H and
+// applied to the state rows on the matrix cores; all steps act on the whole
+// state; a final bit reversal restores the textbook clock order.
+// mode 1 (eigen-frame): the system register is held in the eigenbasis of A
+// (beta = V^H b, x = V z): the controlled U_k are diagonal, so the state
+// after phase estimation is written directly; the inverse QFT runs on the
+// ancilla = 0 half, the rotation writes the ancilla = 1 half, the QFT runs
+// on that half, and the conjugate phases, Hadamards and clock = 0
+// projection are one reduction over the clock register.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <type_traits>
+#include <vector>
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include "sv_device.h"
+#include "sv_hhl_internal.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+template <typename R>
+sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N, int K,
+                uint64_t row_mask, uint64_t row_fix, int trans, int conjb);
+template <typename R>
+sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
+
+// --------------------------------------------------------------------------
+// small FP64 kernels
+// --------------------------------------------------------------------------
+
+__global__ void k_transpose_c128(double2 *__restrict__ out, const double2 *__restrict__ in, int N) {
+    const uint64_t total = (uint64_t)N * N;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = i / N, c = i % N;
+        out[c * N + r] = in[i];
+    }
+}
+
+// W[r][j] = V[r][j] * E[j]
+__global__ void k_scale_cols(double2 *__restrict__ W, const double2 *__restrict__ V, const double2 *__restrict__ E,
+                             int N) {
+    const uint64_t total = (uint64_t)N * N;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double2 v = V[i], e = E[i % N];
+        W[i] = make_double2(v.x * e.x - v.y * e.y, v.x * e.y + v.y * e.x);
+    }
+}
+
+__global__ void k_c128_to_c64(float2 *__restrict__ out, const double2 *__restrict__ in, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// One axis of a Kronecker basis change on a (n_hi x n_lo) array:
+//   axis 0: out[a][q] = sum_c op(V)[c -> q] in[a][c]   (V is n_lo x n_lo)
+//   axis 1: out[p][b] = sum_r op(V)[r -> p] in[r][b]   (V is n_hi x n_hi)
+// op(V)[c -> q] = conj(V[c][q]) for the adjoint (V^H in), V[q][c] otherwise.
+__global__ void k_axis_transform(double2 *__restrict__ out, const double2 *__restrict__ in,
+                                 const double2 *__restrict__ V, int n_hi, int n_lo, int axis, int adjoint) {
+    const uint64_t total = (uint64_t)n_hi * n_lo;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = i / n_lo, q = i % n_lo;
+        const int L = axis ? n_hi : n_lo;
+        const uint64_t o = axis ? a : q;        // output index along the axis
+        double re = 0.0, im = 0.0;
+        for (int c = 0; c < L; ++c) {
+            const double2 x = axis ? in[(uint64_t)c * n_lo + q] : in[a * n_lo + c];
+            double2 v;
+            if (adjoint) {
+                v = V[(uint64_t)c * L + o];
+                v.y = -v.y;
+            } else {
+                v = V[o * L + c];
+            }
+            re += v.x * x.x - v.y * x.y;
+            im += v.x * x.y + v.y * x.x;
+        }
+        out[i] = make_double2(re, im);
+    }
+}
+
+// ---- eigen-frame kernels ---------------------------------------------------
+// Thread layout: 64 consecutive eigen-indices j per wave, 4 waves splitting a
+// chunk of clock values; each thread walks its clock values in Gray-code
+// order so the phase sum changes by one table entry per step.  The phase of
+// clock index s (relabelled, see above) for eigen-index j is
+// sum_k bit(s, n_c-1-k) F[j][k] (exact 64-bit turn fractions).
+constexpr int EIG_MAXC = 24;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_eig_init(cvec<R> *__restrict__ psi, const double2 *__restrict__ beta,
+                                                  const uint64_t *__restrict__ F, uint64_t N, int n_s, int n_c,
+                                                  int log_len, double scale) {
+    __shared__ uint64_t Fs[EIG_MAXC][64];
+    const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const uint64_t j = (uint64_t)blockIdx.x * 64 + lane;
+    const bool ok = j < N;
+    if (rg == 0)
+        for (int k = 0; k < n_c; ++k) Fs[k][lane] = ok ? F[j * n_c + k] : 0ull;
+    __syncthreads();
+    if (!ok) return;
+    const uint64_t len = 1ull << log_len;
+    const uint64_t s0 = ((uint64_t)blockIdx.y * 4 + rg) << log_len;
+    uint64_t th = 0;
+    for (int b = log_len; b < n_c; ++b)
+        if (s0 >> b & 1) th += Fs[n_c - 1 - b][lane];
+    const double2 bj = beta[j];
+    const cvec<R> bv = cmake<R>((R)(bj.x * scale), (R)(bj.y * scale));
+    uint64_t g = 0;
+    for (uint64_t step = 0; step < len; ++step) {
+        if (step) {
+            const int b = __builtin_ctzll(step);
+            g ^= 1ull << b;
+            const uint64_t f = Fs[n_c - 1 - b][lane];
+            th += (g >> b & 1) ? f : (0ull - f);
+        }
+        psi[((s0 | g) << n_s) | j] = cmul<R>(bv, turn_phase<R>(th));
+    }
+}
+
+// ancilla = 1 half <- s_y * (ancilla = 0 half); FP64 partial sums of
+// |s_y a|^2 (P(a=1)) and |a|^2 (c_y^2 + s_y^2) (total norm)
+template <typename R>
+__global__ __launch_bounds__(256) void k_eig_ry(cvec<R> *__restrict__ psi, const double2 *__restrict__ cs,
+                                                uint64_t half, int n_s, uint64_t ymask, uint64_t abit, uint64_t chunk,
+                                                double *__restrict__ part) {
+    __shared__ double ws[2][4];
+    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = beg + chunk < half ? beg + chunk : half;
+    double pa = 0.0, nt = 0.0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        const double2 t = cs[(i >> n_s) & ymask];
+        const cvec<R> a = psi[i];
+        const R sr = (R)t.y;
+        psi[i | abit] = cmake<R>(sr * a.x, sr * a.y);
+        const double a2 = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        pa += t.y * t.y * a2;
+        nt += (t.x * t.x + t.y * t.y) * a2;
+    }
+    pa = wave_sum_f64(pa);
+    nt = wave_sum_f64(nt);
+    if ((threadIdx.x & 63) == 0) {
+        ws[0][threadIdx.x >> 6] = pa;
+        ws[1][threadIdx.x >> 6] = nt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (ws[0][0] + ws[0][1]) + (ws[0][2] + ws[0][3]);
+        part[2 * blockIdx.x + 1] = (ws[1][0] + ws[1][1]) + (ws[1][2] + ws[1][3]);
+    }
+}
+
+// z partials: part[(by * 4 + rg) * N + j] = sum over this thread's clock
+// values of psi[a=1, s, j] * exp(-2 pi i phase(s, j)), in FP64
+template <typename R>
+__global__ __launch_bounds__(256) void k_eig_project(const cvec<R> *__restrict__ psi, const uint64_t *__restrict__ F,
+                                                     uint64_t N, int n_s, int n_c, int log_len, uint64_t abit,
+                                                     double2 *__restrict__ part) {
+    __shared__ uint64_t Fs[EIG_MAXC][64];
+    const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const uint64_t j = (uint64_t)blockIdx.x * 64 + lane;
+    const bool ok = j < N;
+    if (rg == 0)
+        for (int k = 0; k < n_c; ++k) Fs[k][lane] = ok ? F[j * n_c + k] : 0ull;
+    __syncthreads();
+    if (!ok) return;
+    const uint64_t len = 1ull << log_len;
+    const uint64_t s0 = ((uint64_t)blockIdx.y * 4 + rg) << log_len;
+    uint64_t th = 0;
+    for (int b = log_len; b < n_c; ++b)
+        if (s0 >> b & 1) th += Fs[n_c - 1 - b][lane];
+    double zr = 0.0, zi = 0.0;
+    uint64_t g = 0;
+    for (uint64_t step = 0; step < len; ++step) {
+        if (step) {
+            const int b = __builtin_ctzll(step);
+            g ^= 1ull << b;
+            const uint64_t f = Fs[n_c - 1 - b][lane];
+            th += (g >> b & 1) ? f : (0ull - f);
+        }
+        const cvec<R> a = psi[abit | ((s0 | g) << n_s) | j];
+        const cvec<R> e = turn_phase<R>(0ull - th);
+        const cvec<R> p = cmul<R>(a, e);
+        zr += (double)p.x;
+        zi += (double)p.y;
+    }
+    part[((uint64_t)blockIdx.y * 4 + rg) * N + j] = make_double2(zr, zi);
+}
+
+__global__ void k_sum_cols(double2 *__restrict__ z, const double2 *__restrict__ part, uint64_t N, int rows,
+                           double scale) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (uint64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int r = 0; r < rows; ++r) {
+            re += part[(uint64_t)r * N + j].x;
+            im += part[(uint64_t)r * N + j].y;
+        }
+        z[j] = make_double2(re * scale, im * scale);
+    }
+}
+
+// --------------------------------------------------------------------------
+// host helpers
+// --------------------------------------------------------------------------
+
+static std::mutex g_blas_mu;
+static rocblas_handle g_blas = nullptr;
+
+static sv_status blas_handle(hipStream_t st, rocblas_handle *out) {
+    std::lock_guard<std::mutex> lk(g_blas_mu);
+    if (!g_blas && rocblas_create_handle(&g_blas) != rocblas_status_success)
+        return fail(SV_EDEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(g_blas, st) != rocblas_status_success) return fail(SV_EDEVICE, "rocblas_set_stream failed");
+    *out = g_blas;
+    return SV_OK;
+}
+
+static unsigned grid1(uint64_t items) {
+    uint64_t g = (items + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > (1u << 16)) g = 1u << 16;
+    return (unsigned)g;
+}
+
+DevBuf::~DevBuf() {
+    if (p) hipFree(p);
+}
+sv_status DevBuf::alloc(size_t bytes) {
+    if (p) hipFree(p);
+    p = nullptr;
+    if (!bytes) return SV_OK;
+    SV_HIP(hipMalloc(&p, bytes));
+    return SV_OK;
+}
+
+sv_status check_hermitian(const double *A, int N, const char *name) {
+    double amax = 0.0, dmax = 0.0;
+    for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) {
+            const double *x = A + 2 * ((size_t)r * N + c), *y = A + 2 * ((size_t)c * N + r);
+            if (!isfinite(x[0]) || !isfinite(x[1])) return fail(SV_EINVAL, "%s has a non-finite entry", name);
+            amax = fmax(amax, hypot(x[0], x[1]));
+            dmax = fmax(dmax, hypot(x[0] - y[0], x[1] + y[1]));
+        }
+    if (dmax > 1e-12 * amax) return fail(SV_ENOTHERMITIAN, "%s is not Hermitian (|A - A^H| = %g)", name, dmax);
+    return SV_OK;
+}
+
+// Residual check of an eigen-decomposition with one fixed pseudo-random
+// vector x: V must preserve its norm and A (V x) must equal V (lam .* x).
+// O(N^2) on the host; catches non-finite or non-orthonormal eigenvectors.
+static bool eig_residual_ok(const double *A, int N, const std::vector<double> &lam, const std::vector<double> &V,
+                            double *worst) {
+    std::vector<double> x(2 * (size_t)N), y(2 * (size_t)N, 0.0), z(2 * (size_t)N, 0.0);
+    uint64_t st = 0x9e3779b97f4a7c15ull;
+    double xn = 0.0, amax = 0.0;
+    for (size_t i = 0; i < 2 * (size_t)N; ++i) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        x[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        xn += x[i] * x[i];
+    }
+    for (int r = 0; r < N; ++r)
+        for (int j = 0; j < N; ++j) {
+            const double *v = &V[2 * ((size_t)r * N + j)];
+            if (!isfinite(v[0]) || !isfinite(v[1])) return false;
+            const double xr = x[2 * j], xi = x[2 * j + 1];
+            y[2 * r] += v[0] * xr - v[1] * xi;            // y = V x
+            y[2 * r + 1] += v[0] * xi + v[1] * xr;
+            z[2 * r] += lam[j] * (v[0] * xr - v[1] * xi);  // z = V (lam .* x)
+            z[2 * r + 1] += lam[j] * (v[0] * xi + v[1] * xr);
+        }
+    double yn = 0.0, rn = 0.0;
+    for (int r = 0; r < N; ++r) {
+        yn += y[2 * r] * y[2 * r] + y[2 * r + 1] * y[2 * r + 1];
+        double ar = 0.0, ai = 0.0;
+        for (int c = 0; c < N; ++c) {
+            const double *a = &A[2 * ((size_t)r * N + c)];
+            amax = fmax(amax, fabs(a[0]) + fabs(a[1]));
+            ar += a[0] * y[2 * c] - a[1] * y[2 * c + 1];
+            ai += a[0] * y[2 * c + 1] + a[1] * y[2 * c];
+        }
+        rn += (ar - z[2 * r]) * (ar - z[2 * r]) + (ai - z[2 * r + 1]) * (ai - z[2 * r + 1]);
+    }
+    const double lmax = fmax(fabs(lam.front()), fabs(lam.back()));
+    const double e1 = fabs(sqrt(yn) - sqrt(xn)) / sqrt(xn), e2 = sqrt(rn) / (sqrt(xn) * fmax(lmax, amax));
+    *worst = fmax(e1, e2);
+    return isfinite(*worst) && e1 < 1e-10 && e2 < 1e-10 * sqrt((double)N);
+}
+
+// Hermitian eigen-decomposition in FP64 on the device (rocSOLVER), validated
+// by eig_residual_ok; divide-and-conquer first, then QR iteration, then
+// Jacobi if a result fails the check.  dV receives V row-major (column j =
+// eigenvector j); lam ascending.
+sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vector<double> &lam) {
+    // rocSOLVER is column-major: the row-major conj(A) is A in column-major order
+    std::vector<double> Ac(2 * (size_t)N * N);
+    for (size_t i = 0; i < (size_t)N * N; ++i) {
+        Ac[2 * i] = A[2 * i];
+        Ac[2 * i + 1] = -A[2 * i + 1];
+    }
+    DevBuf dA, dD, dE, dInfo, dRes, dSweeps;
+    SV_TRY(dA.alloc((size_t)N * N * sizeof(double2)));
+    SV_TRY(dD.alloc(N * sizeof(double)));
+    SV_TRY(dE.alloc(N * sizeof(double)));
+    SV_TRY(dInfo.alloc(sizeof(int)));
+    SV_TRY(dRes.alloc(sizeof(double)));
+    SV_TRY(dSweeps.alloc(sizeof(int)));
+    SV_TRY(dV.alloc((size_t)N * N * sizeof(double2)));
+    rocblas_handle h;
+    SV_TRY(blas_handle(s->stream, &h));
+    std::vector<double> Vh(2 * (size_t)N * N);
+    const char *names[3] = {"zheevd", "zheev", "zheevj"};
+    double worst = 0.0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        SV_TRY(upload(s, dA.p, Ac.data(), Ac.size() * sizeof(double)));
+        rocblas_status rs;
+        if (attempt == 0)
+            rs = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, N, (rocblas_double_complex *)dA.p, N,
+                                  (double *)dD.p, (double *)dE.p, (rocblas_int *)dInfo.p);
+        else if (attempt == 1)
+            rs = rocsolver_zheev(h, rocblas_evect_original, rocblas_fill_upper, N, (rocblas_double_complex *)dA.p, N,
+                                 (double *)dD.p, (double *)dE.p, (rocblas_int *)dInfo.p);
+        else
+            rs = rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, N,
+                                  (rocblas_double_complex *)dA.p, N, 0.0, (double *)dRes.p, 100,
+                                  (rocblas_int *)dSweeps.p, (double *)dD.p, (rocblas_int *)dInfo.p);
+        if (rs != rocblas_status_success) continue;
+        int info = 0;
+        lam.resize(N);
+        SV_TRY(download(s, lam.data(), dD.p, N * sizeof(double)));
+        SV_TRY(download(s, &info, dInfo.p, sizeof(int)));
+        if (info != 0) continue;
+        // column-major eigenvectors read row-major are V^T; transpose to V
+        hipLaunchKernelGGL(k_transpose_c128, dim3(grid1((uint64_t)N * N)), dim3(256), 0, s->stream,
+                           (double2 *)dV.p, (const double2 *)dA.p, N);
+        SV_HIP(hipGetLastError());
+        SV_TRY(download(s, Vh.data(), dV.p, Vh.size() * sizeof(double)));
+        if (eig_residual_ok(A, N, lam, Vh, &worst)) return SV_OK;
+    }
+    return fail(SV_EDEVICE, "no eigen-solver passed the residual check for N = %d (last residual %g, %s..%s)", N, worst,
+                names[0], names[2]);
+}
+
+// turn fractions frac(phi_j 2^k), phi_j = lam_j T0 / 2 pi, as 64-bit fixed point
+void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<uint64_t> &F) {
+    const size_t N = lam.size();
+    F.assign(N * n_c, 0);
+    for (size_t j = 0; j < N; ++j) {
+        const double phi = lam[j] * T0 / (2.0 * M_PI);
+        for (int k = 0; k < n_c; ++k) {
+            const double x = ldexp(phi, k);
+            const double f = x - floor(x);   // exact
+            const double sc = ldexp(f, 64);
+            F[j * n_c + k] = sc >= 18446744073709551616.0 ? 0ull : (uint64_t)sc;
+        }
+    }
+}
+
+// (cos, sin) of the inversion rotation for every clock value: sin = 1/y, y >= 1
+void inversion_table(int n_c, std::vector<double> &cs) {
+    const size_t M = (size_t)1 << n_c;
+    cs.assign(2 * M, 0.0);
+    cs[0] = 1.0;
+    for (size_t y = 1; y < M; ++y) {
+        const double sv = 1.0 / (double)y;
+        cs[2 * y] = sqrt(1.0 - sv * sv);
+        cs[2 * y + 1] = sv;
+    }
+}
+
+// basis change out = (V_hi (x) V_lo)^(H) in on FP64 device vectors (V_lo may be null: dense V_hi)
+sv_status kron_apply(hipStream_t st, double2 *out, const double2 *in, double2 *tmp, const double2 *V_hi, int n_hi,
+                     const double2 *V_lo, int n_lo, int adjoint) {
+    const uint64_t total = (uint64_t)n_hi * n_lo;
+    if (V_lo && n_lo > 1) {
+        hipLaunchKernelGGL(k_axis_transform, dim3(grid1(total)), dim3(256), 0, st, tmp, in, V_lo, n_hi, n_lo, 0,
+                           adjoint);
+        in = tmp;
+    }
+    hipLaunchKernelGGL(k_axis_transform, dim3(grid1(total)), dim3(256), 0, st, out, in, V_hi, n_hi, n_lo, 1, adjoint);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+static int pick_log_len(uint64_t N, int n_c) {
+    // enough workgroups to fill the chip: ~8 per CU over the column blocks
+    const uint64_t colblocks = (N + 63) / 64;
+    int L = 0;
+    while (L < n_c - 2 && (((1ull << n_c) >> (L + 2)) * colblocks) > 8192) ++L;
+    if (L > n_c - 2) L = n_c - 2 > 0 ? n_c - 2 : 0;
+    if (n_c < 2) L = 0;
+    return L;
+}
+
+template <typename R>
+static sv_status eig_frame_run(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res,
+                               double *x_out) {
+    const int n_s = E.n_s;
+    const uint64_t N = dim_of(n_s);
+    const int anc = n_s + n_c;
+    const uint64_t abit = 1ull << anc;
+    const hipStream_t st = s->stream;
+
+    std::vector<uint64_t> F;
+    turn_table(E.lam, T0, n_c, F);
+    std::vector<double> cs;
+    inversion_table(n_c, cs);
+
+    DevBuf dF, dcs, dbeta, dtmp, dz, dx, dpart, dsum;
+    SV_TRY(dF.alloc(F.size() * sizeof(uint64_t)));
+    SV_TRY(dcs.alloc(cs.size() * sizeof(double)));
+    SV_TRY(upload(s, dF.p, F.data(), F.size() * sizeof(uint64_t)));
+    SV_TRY(upload(s, dcs.p, cs.data(), cs.size() * sizeof(double)));
+    SV_TRY(dbeta.alloc(N * sizeof(double2)));
+    SV_TRY(dtmp.alloc(N * sizeof(double2)));
+    SV_TRY(dz.alloc(N * sizeof(double2)));
+    SV_TRY(dx.alloc(N * sizeof(double2)));
+    SV_TRY(upload(s, dx.p, E.bhat.data(), N * sizeof(double2)));
+    // beta = V^H b^
+    SV_TRY(kron_apply(st, (double2 *)dbeta.p, (const double2 *)dx.p, (double2 *)dtmp.p, (const double2 *)E.V_hi.p,
+                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 1));
+
+    // 1. the state after phase estimation, written directly (ancilla = 0 half)
+    const int L = pick_log_len(N, n_c);
+    const dim3 g2((unsigned)((N + 63) / 64), (unsigned)(((1ull << n_c) >> L) / 4 ? ((1ull << n_c) >> L) / 4 : 1));
+    if (((1ull << n_c) >> L) < 4) return fail(SV_EUNSUPPORTED, "eigen-frame mode needs n_c >= 2");
+    hipLaunchKernelGGL(k_eig_init<R>, g2, dim3(256), 0, st, (cvec<R> *)s->data, (const double2 *)dbeta.p,
+                       (const uint64_t *)dF.p, N, n_s, n_c, L, 1.0 / sqrt((double)(1ull << n_c)));
+    SV_HIP(hipGetLastError());
+    // 2. inverse QFT cascade on the clock, ancilla = 0 half
+    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, abit, 0}, 0));
+    // 3. eigenvalue inversion: ancilla = 1 half <- s_y (ancilla = 0 half)
+    const uint64_t half = dim_of(n_s + n_c);
+    uint64_t nb = (half + 256 * 64 - 1) / (256 * 64);
+    if (nb > 4096) nb = 4096;
+    const uint64_t chunk = (half + nb - 1) / nb;
+    DevBuf dzpart;
+    SV_TRY(dpart.alloc(2 * nb * sizeof(double)));
+    SV_TRY(dzpart.alloc((size_t)g2.y * 4 * N * sizeof(double2)));
+    SV_TRY(dsum.alloc(4 * sizeof(double)));
+    hipLaunchKernelGGL(k_eig_ry<R>, dim3((unsigned)nb), dim3(256), 0, st, (cvec<R> *)s->data, (const double2 *)dcs.p,
+                       half, n_s, (1ull << n_c) - 1ull, abit, chunk, (double *)dpart.p);
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)dpart.p, (int)nb, 2,
+                       (double *)dsum.p);
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)dpart.p + 1, (int)nb, 2,
+                       (double *)dsum.p + 1);
+    SV_HIP(hipGetLastError());
+    // 4. QFT cascade on the clock, ancilla = 1 half
+    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 0, abit, abit}, 0));
+    // 5. conjugate phases + Hadamards + clock = 0 projection
+    double2 *zpart = (double2 *)dzpart.p;
+    hipLaunchKernelGGL(k_eig_project<R>, g2, dim3(256), 0, st, (const cvec<R> *)s->data, (const uint64_t *)dF.p, N,
+                       n_s, n_c, L, abit, zpart);
+    hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)dz.p, (const double2 *)zpart, N,
+                       (int)(g2.y * 4), 1.0 / sqrt((double)(1ull << n_c)));
+    SV_HIP(hipGetLastError());
+    // 6. back to the computational basis: x = V z
+    SV_TRY(kron_apply(st, (double2 *)dx.p, (const double2 *)dz.p, (double2 *)dtmp.p, (const double2 *)E.V_hi.p,
+                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 0));
+    std::vector<double> sums(2), xz(2 * N);
+    SV_TRY(download(s, sums.data(), dsum.p, 2 * sizeof(double)));
+    SV_TRY(download(s, xz.data(), dx.p, N * sizeof(double2)));
+    double p = 0.0;
+    for (uint64_t j = 0; j < N; ++j) p += xz[2 * j] * xz[2 * j] + xz[2 * j + 1] * xz[2 * j + 1];
+    res->p_post = p;
+    res->p_anc = sums[0];
+    res->norm_total = sums[1];
+    if (!(p > 0.0)) return fail(SV_EZERONORM, "post-selected outcome has probability 0");
+    if (x_out) {
+        const double inv = 1.0 / sqrt(p);
+        for (uint64_t j = 0; j < 2 * N; ++j) x_out[j] = xz[j] * inv;
+    }
+    return SV_OK;
+}
+
+sv_status eig_frame(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res, double *x_out) {
+    if (n_c > EIG_MAXC) return fail(SV_EUNSUPPORTED, "n_c %d > %d", n_c, EIG_MAXC);
+    return s->dt == SV_C64 ? eig_frame_run<float>(s, E, n_c, T0, res, x_out)
+                           : eig_frame_run<double>(s, E, n_c, T0, res, x_out);
+}
+
+template <typename R>
+static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, int n_s, int n_c,
+                                   double T0, const double *b, sv_hhl_result *res, double *x_out) {
+    const int N = 1 << n_s;
+    const hipStream_t st = s->stream;
+    // U_k = V diag(E_k) V^H for k = 0..n_c-1, FP64, then rounded to the state's precision
+    std::vector<double> Ek(2 * (size_t)N * n_c);
+    for (int k = 0; k < n_c; ++k)
+        for (int j = 0; j < N; ++j) {
+            const double phi = lam[j] * T0 / (2.0 * M_PI);
+            const double x = ldexp(phi, k), f = x - floor(x);
+            Ek[2 * ((size_t)k * N + j)] = cos(2.0 * M_PI * f);
+            Ek[2 * ((size_t)k * N + j) + 1] = sin(2.0 * M_PI * f);
+        }
+    DevBuf dE, dW, dU64, dUk;
+    SV_TRY(dE.alloc(Ek.size() * sizeof(double)));
+    SV_TRY(upload(s, dE.p, Ek.data(), Ek.size() * sizeof(double)));
+    SV_TRY(dW.alloc((size_t)N * N * sizeof(double2)));
+    SV_TRY(dU64.alloc((size_t)N * N * sizeof(double2)));
+    SV_TRY(dUk.alloc((size_t)n_c * N * N * sizeof(cvec<R>)));
+    const uint64_t NN = (uint64_t)N * N;
+    for (int k = 0; k < n_c; ++k) {
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid1(NN)), dim3(256), 0, st, (double2 *)dW.p, dV,
+                           (const double2 *)dE.p + (size_t)k * N, N);
+        double2 *dst = std::is_same<R, double>::value ? (double2 *)dUk.p + (size_t)k * NN : (double2 *)dU64.p;
+        SV_TRY(cgemm<double>(st, (const double2 *)dW.p, dst, dV, (uint64_t)N, N, N, (uint64_t)(N - 1) << n_s, 0, 0,
+                             1));
+        if (!std::is_same<R, double>::value)
+            hipLaunchKernelGGL(k_c128_to_c64, dim3(grid1(NN)), dim3(256), 0, st, (float2 *)dUk.p + (size_t)k * NN,
+                               (const double2 *)dU64.p, NN);
+    }
+    SV_HIP(hipGetLastError());
+    const cvec<R> *U = (const cvec<R> *)dUk.p;
+
+    SV_TRY(sv_init_b(s, b, n_s, n_c));
+    for (int k = 0; k < n_c; ++k) SV_TRY(ctrl_unitary_impl<R>(s, U + (size_t)k * NN, n_s, n_s + (n_c - 1 - k), 1, 0));
+    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, 0, 0}, 0));
+    std::vector<double> cs;
+    inversion_table(n_c, cs);
+    SV_TRY(sv_apply_uniform_ry(s, n_s + n_c, n_s, n_c, cs.data(), -1, 0));
+    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 0, 0, 0}, 0));
+    for (int k = n_c - 1; k >= 0; --k)
+        SV_TRY(ctrl_unitary_impl<R>(s, U + (size_t)k * NN, n_s, n_s + (n_c - 1 - k), 1, 1));
+    SV_TRY(run_hadamards(s, n_s, n_c, 0, 0));
+    SV_TRY(bitrev_register(s, n_s, n_c, 0, 0));
+
+    const uint64_t abit = 1ull << (n_s + n_c), cmask = ((1ull << n_c) - 1ull) << n_s;
+    SV_TRY(sv_norm2(s, abit, abit, &res->p_anc));
+    SV_TRY(sv_norm2(s, 0, 0, &res->norm_total));
+    return sv_postselect(s, abit | cmask, abit, &res->p_post, x_out, 0);
+}
+
+static sv_status check_params(sv_state s, const sv_hhl_params *prm, sv_hhl_result *res) {
+    if (!prm || !res) return fail(SV_EINVAL, "params/result is NULL");
+    if (prm->signed_clock) return fail(SV_EUNSUPPORTED, "signed clock register is not implemented");
+    if (prm->n_s < 1 || prm->n_c < 1 || prm->n_s + prm->n_c + 1 != s->n)
+        return fail(SV_EINVAL, "n_s %d + n_c %d + 1 != %d qubits", prm->n_s, prm->n_c, s->n);
+    if (!(prm->T0 > 0.0) || !isfinite(prm->T0)) return fail(SV_EINVAL, "T0 must be positive");
+    if (prm->mode != 0 && prm->mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    return SV_OK;
+}
+
+static sv_status normalise_b(const double *b, uint64_t N, std::vector<double> &bhat) {
+    double nrm = 0.0;
+    for (uint64_t j = 0; j < 2 * N; ++j) nrm += b[j] * b[j];
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !isfinite(nrm)) return fail(SV_EZERONORM, "|b| = 0 or not finite");
+    bhat.resize(2 * N);
+    for (uint64_t j = 0; j < 2 * N; ++j) bhat[j] = b[j] / nrm;
+    return SV_OK;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
+                 double *x_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    SV_TRY(check_params(s, prm, res));
+    if (!A || !b) return fail(SV_EINVAL, "A/b is NULL");
+    const int n_s = prm->n_s;
+    if (n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d (use sv_hhl_kron)", n_s);
+    const int N = 1 << n_s;
+    SV_TRY(check_hermitian(A, N, "A"));
+    EigFrame E;
+    E.n_s = n_s;
+    E.n_hi = N;
+    E.n_lo = 1;
+    SV_TRY(normalise_b(b, N, E.bhat));
+    SV_TRY(eigh_device(s, A, N, E.V_hi, E.lam));
+    res->lambda_min = E.lam.front();
+    res->lambda_max = E.lam.back();
+    if (!(E.lam.front() > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", E.lam.front());
+    if (prm->mode == 1) return eig_frame(s, E, prm->n_c, prm->T0, res, x_out);
+    if (s->dt == SV_C64)
+        return gate_faithful_run<float>(s, (const double2 *)E.V_hi.p, E.lam, n_s, prm->n_c, prm->T0, E.bhat.data(),
+                                        res, x_out);
+    return gate_faithful_run<double>(s, (const double2 *)E.V_hi.p, E.lam, n_s, prm->n_c, prm->T0, E.bhat.data(), res,
+                                     x_out);
+}
+
+sv_status sv_hhl_kron(sv_state s, const double *A_hi, int m_hi, const double *A_lo, int m_lo, const double *b,
+                      const sv_hhl_params *prm, sv_hhl_result *res, double *x_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    SV_TRY(check_params(s, prm, res));
+    if (!A_hi || !A_lo || !b) return fail(SV_EINVAL, "A_hi/A_lo/b is NULL");
+    if (m_hi < 1 || m_lo < 1 || m_hi + m_lo != prm->n_s) return fail(SV_EINVAL, "m_hi + m_lo != n_s");
+    if (m_hi > 13 || m_lo > 13) return fail(SV_EUNSUPPORTED, "factor larger than 2^13");
+    const int nh = 1 << m_hi, nl = 1 << m_lo;
+    SV_TRY(check_hermitian(A_hi, nh, "A_hi"));
+    SV_TRY(check_hermitian(A_lo, nl, "A_lo"));
+    if (prm->mode == 0) {
+        // gate-faithful needs the dense operator A_hi (x) I + I (x) A_lo
+        if (prm->n_s > 12) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 12", prm->n_s);
+        const int N = nh * nl;
+        std::vector<double> A(2 * (size_t)N * N, 0.0);
+        for (int p = 0; p < nh; ++p)
+            for (int q = 0; q < nl; ++q)
+                for (int r = 0; r < nh; ++r)
+                    for (int c = 0; c < nl; ++c) {
+                        const size_t i = (size_t)(p * nl + q) * N + (r * nl + c);
+                        if (q == c) {
+                            A[2 * i] += A_hi[2 * ((size_t)p * nh + r)];
+                            A[2 * i + 1] += A_hi[2 * ((size_t)p * nh + r) + 1];
+                        }
+                        if (p == r) {
+                            A[2 * i] += A_lo[2 * ((size_t)q * nl + c)];
+                            A[2 * i + 1] += A_lo[2 * ((size_t)q * nl + c) + 1];
+                        }
+                    }
+        return sv_hhl(s, A.data(), b, prm, res, x_out);
+    }
+    EigFrame E;
+    E.n_s = prm->n_s;
+    E.n_hi = nh;
+    E.n_lo = nl;
+    SV_TRY(normalise_b(b, (uint64_t)nh * nl, E.bhat));
+    std::vector<double> mu, nu;
+    SV_TRY(eigh_device(s, A_hi, nh, E.V_hi, mu));
+    SV_TRY(eigh_device(s, A_lo, nl, E.V_lo, nu));
+    E.lam.resize((size_t)nh * nl);
+    for (int p = 0; p < nh; ++p)
+        for (int q = 0; q < nl; ++q) E.lam[(size_t)p * nl + q] = mu[p] + nu[q];
+    res->lambda_min = mu.front() + nu.front();
+    res->lambda_max = mu.back() + nu.back();
+    if (!(res->lambda_min > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
+    return eig_frame(s, E, prm->n_c, prm->T0, res, x_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal pieces of the HHL drivers shared by sv_hhl.hip and sv_batch.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+// owning device buffer (freed with hipFree after a device-wide sync point)
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    sv_status alloc(size_t bytes);
+};
+
+// eigen-decomposition of A = A_hi (x) I + I (x) A_lo (dense A: n_lo = 1, V_lo empty)
+struct EigFrame {
+    int n_s = 0, n_hi = 0, n_lo = 1;
+    DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
+    std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
+    std::vector<double> bhat;     // normalised b, interleaved complex FP64
+};
+
+sv_status check_hermitian(const double *A, int N, const char *name);
+sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vector<double> &lam);
+void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<uint64_t> &F);
+void inversion_table(int n_c, std::vector<double> &cs);
+sv_status kron_apply(hipStream_t st, double2 *out, const double2 *in, double2 *tmp, const double2 *V_hi, int n_hi,
+                     const double2 *V_lo, int n_lo, int adjoint);
+sv_status eig_frame(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res, double *x_out);
+
+// fixed-order sum of `count` partials spaced `stride` apart into out[0]
+static __global__ __launch_bounds__(256) void k_sum_partials_strided(const double *__restrict__ part, int count,
+                                                                     int stride, double *__restrict__ out) {
+    __shared__ double ws[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[(size_t)i * stride];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+}  // namespace sv

@@ -1,0 +1,182 @@
+"""GPU parity for the controlled-U GEMM and for HHL (both modes) against the oracle.
+
+Bars: complex128 max-abs <= 1e-12, complex64 max-abs <= 1e-5 on the
+normalised post-selected vector and (mode 0) on the whole final state;
+probabilities to the same bars.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00391_amd import binding as B
+from paper_2307_00391_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+def _dev_matrix(U, dt):
+    import torch
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    return torch.tensor(np.ascontiguousarray(U), dtype=tdt, device="cuda")
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,m,ctrl,cval", [(6, 1, 3, 1), (9, 4, 8, 0), (12, 6, -1, 1), (14, 8, 10, 1),
+                                           (11, 10, 10, 1), (13, 5, 12, 1)])
+def test_ctrl_unitary_matches_oracle(dt, n, m, ctrl, cval):
+    rng = np.random.default_rng(50 + n + m)
+    U = inputs.random_unitary(rng, 1 << m)
+    Ur = U.astype(np.complex64).astype(np.complex128) if dt == "c64" else U
+    psi0 = inputs.random_state(rng, n)
+    if dt == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    dU = _dev_matrix(U, dt)
+    for adjoint in (False, True):
+        ref = oracle.apply_ctrl_unitary(psi0.copy(), Ur, 0, m, ctrl, cval, adjoint)
+        s = B.State(n, dt)
+        s.set(psi0)
+        B.sv_apply_ctrl_unitary(s.h, dU, 0, m, ctrl, cval, adjoint)
+        assert np.abs(s.get() - ref).max() <= TOL[dt]
+
+
+def _hhl_case(A, b, n_c, T0):
+    return oracle.hhl(A, b, n_c, T0)
+
+
+@pytest.fixture(scope="module")
+def poiseuille_ref():
+    s = inputs.poiseuille(16)
+    T0 = inputs.t0_top_of_clock(s.lambda_max, 6)
+    return s, 6, T0, _hhl_case(s.A, s.b, 6, T0)
+
+
+@pytest.fixture(scope="module")
+def couette_ref():
+    s = inputs.couette(256)
+    T0 = inputs.t0_top_of_clock(s.lambda_max, 10)
+    return s, 10, T0, _hhl_case(s.A, s.b, 10, T0)
+
+
+def _run(A, b, n_c, T0, dt, mode):
+    n_s = A.shape[0].bit_length() - 1
+    st = B.State(n_s + n_c + 1, dt)
+    x, res = B.sv_hhl(st.h, A, b, n_c, T0, mode)
+    return st, x, res
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_poiseuille_hhl(poiseuille_ref, dt, mode):
+    s, n_c, T0, (psi_r, x_r, pp_r, pa_r) = poiseuille_ref
+    st, x, res = _run(s.A, s.b, n_c, T0, dt, mode)
+    assert np.abs(x - x_r).max() <= TOL[dt]
+    assert abs(res.p_post - pp_r) <= TOL[dt]
+    assert abs(res.p_anc - pa_r) <= TOL[dt]
+    assert abs(res.norm_total - 1.0) <= TOL[dt] * 10
+    if mode == 0:
+        assert np.abs(st.get() - psi_r).max() <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_couette_hhl(couette_ref, dt, mode):
+    s, n_c, T0, (psi_r, x_r, pp_r, pa_r) = couette_ref
+    st, x, res = _run(s.A, s.b, n_c, T0, dt, mode)
+    # x is divided by sqrt(p_post) ~ 0.013: the FP32 path's absolute error on
+    # the state is amplified by 1/sqrt(p) on the post-selected vector
+    tol_x = TOL[dt] if dt == "c128" else 1e-5 / math.sqrt(pp_r) * 0.1
+    assert np.abs(x - x_r).max() <= max(TOL[dt], tol_x)
+    assert abs(res.p_post - pp_r) <= TOL[dt]
+    assert abs(res.p_anc - pa_r) <= TOL[dt]
+    if mode == 0:
+        assert np.abs(st.get() - psi_r).max() <= TOL[dt]
+
+
+@pytest.mark.parametrize("seed,n_s,n_c,kappa", [(1, 3, 5, 20.0), (2, 5, 7, 300.0), (3, 6, 9, 1000.0),
+                                                (4, 4, 8, 50.0)])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_random_spd_hhl_both_modes(seed, n_s, n_c, kappa, dt):
+    rng = np.random.default_rng(seed)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, kappa)
+    b = rng.standard_normal(1 << n_s)
+    T0 = inputs.t0_grid(lmax)[seed % 16]
+    psi_r, x_r, pp_r, pa_r = _hhl_case(A, b, n_c, T0)
+    for mode in (0, 1):
+        st, x, res = _run(A, b, n_c, T0, dt, mode)
+        tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
+        assert np.abs(x - x_r).max() <= tol, (mode, np.abs(x - x_r).max())
+        assert abs(res.p_post - pp_r) <= TOL[dt]
+        assert abs(res.lambda_min - lmin) <= 1e-9 * lmax
+
+
+def test_complex_hermitian_hhl():
+    rng = np.random.default_rng(77)
+    N, n_c = 16, 7
+    Z = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    A = Z @ Z.conj().T + 2.0 * np.eye(N)
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    T0 = inputs.t0_top_of_clock(np.linalg.eigvalsh(A)[-1], n_c)
+    psi_r, x_r, pp_r, _ = _hhl_case(A, b, n_c, T0)
+    for mode in (0, 1):
+        st, x, res = _run(A, b, n_c, T0, "c128", mode)
+        assert np.abs(x - x_r).max() <= 1e-12
+        assert abs(res.p_post - pp_r) <= 1e-12
+        if mode == 0:
+            assert np.abs(st.get() - psi_r).max() <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_kron_hhl_matches_dense_oracle(dt):
+    rng = inputs.rng_for(3, 99)
+    ks = inputs.kron_laplacian_system(rng, 3, 3, kappa=200.0)
+    n_c = 8
+    A = ks.dense()
+    T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
+    psi_r, x_r, pp_r, pa_r = _hhl_case(A, ks.b, n_c, T0)
+    for mode in (1, 0):
+        st = B.State(6 + n_c + 1, dt)
+        x, res = B.sv_hhl_kron(st.h, ks.A_hi, ks.A_lo, ks.b, n_c, T0, mode)
+        tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
+        assert np.abs(x - x_r).max() <= tol
+        assert abs(res.p_post - pp_r) <= TOL[dt]
+        assert abs(res.lambda_max - ks.lambda_max) <= 1e-12 * ks.lambda_max
+
+
+def test_hhl_repeatable_bit_for_bit():
+    s = inputs.poiseuille(16)
+    T0 = inputs.t0_top_of_clock(s.lambda_max, 6)
+    for mode in (0, 1):
+        _, x1, r1 = _run(s.A, s.b, 6, T0, "c64", mode)
+        _, x2, r2 = _run(s.A, s.b, 6, T0, "c64", mode)
+        assert np.array_equal(x1, x2) and r1.p_post == r2.p_post
+
+
+def test_hhl_error_paths():
+    st = B.State(8, "c128")
+    A = np.eye(8) * 2.0
+    with pytest.raises(B.SvError) as e:
+        B.sv_hhl(st.h, A, np.zeros(8), 4, 0.1)
+    assert e.value.status == B.SV_EZERONORM
+    bad = A.copy()
+    bad[0, 1] = 1.0
+    with pytest.raises(B.SvError) as e:
+        B.sv_hhl(st.h, bad, np.ones(8), 4, 0.1)
+    assert e.value.status == B.SV_ENOTHERMITIAN
+    with pytest.raises(B.SvError) as e:
+        B.sv_hhl(st.h, -A, np.ones(8), 4, 0.1)
+    assert e.value.status == B.SV_ENOTPOSDEF
+    with pytest.raises(B.SvError) as e:
+        B.sv_hhl(st.h, A, np.ones(8), 3, 0.1)      # 3 + 3 + 1 != 8 qubits
+    assert e.value.status == B.SV_EINVAL
