@@ -229,6 +229,29 @@ typedef struct {
 sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm,
                  sv_hhl_result *res, double *x_out);
 
+/* Classical preprocessing and the quantum solve, split so the FP64
+ * eigen-decomposition is computed once per operator and reused for every
+ * right-hand side and every T0 (the hybrid loop of the paper's Fig. 1b: the
+ * parameters beta, here the spectrum and T0, are prepared classically).
+ * sv_hhl_prepare: A = A_hi (x) I + I (x) A_lo with A_hi 2^m_hi and A_lo
+ * 2^m_lo square (host, complex FP64 row-major, Hermitian), or the dense
+ * A = A_hi when A_lo == NULL and m_lo == 0.  Uses the stream and staging
+ * buffers of s; the plan then serves any state with n_s = m_hi + m_lo
+ * system qubits on the same device.  Errors: SV_EINVAL, SV_ENOTHERMITIAN,
+ * SV_EUNSUPPORTED (a factor above 2^13), SV_EDEVICE (no eigen-solver result
+ * passed the residual check), SV_ENOMEM. */
+typedef struct sv_hhl_plan_s *sv_hhl_plan;
+sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m_hi, const double *A_lo,
+                         int m_lo);
+/* One HHL solve on a prepared operator; arguments and results as sv_hhl.
+ * The plan keeps device workspaces between calls: calls sharing a plan must
+ * not overlap. */
+sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm,
+                     sv_hhl_result *res, double *x_out);
+/* Smallest and largest eigenvalue of the prepared operator (FP64). */
+sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda_max);
+sv_status sv_hhl_plan_free(sv_hhl_plan p);
+
 /* HHL for a separable operator A = A_hi (x) I + I (x) A_lo (a Laplacian /
  * Poisson operator on a 2-D tensor grid, main text: "d-dimensional Laplace,
  * Poisson and heat equations"), A_hi 2^m_hi square acting on system bits
@@ -240,6 +263,27 @@ sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_para
 sv_status sv_hhl_kron(sv_state s, const double *A_hi, int m_hi, const double *A_lo, int m_lo,
                       const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
                       double *x_out);
+
+/* ------------------------------------------------------------------------
+ * Instrumentation
+ * --------------------------------------------------------------------- */
+
+/* Per-kernel tracing: while enabled, each state-vector kernel launch is
+ * bracketed by HIP events recorded on the stream it runs on, together with
+ * the algorithmic bytes (reads + writes the operation must make) and flops
+ * of that launch.  on != 0 clears earlier records and starts recording. */
+sv_status sv_trace_enable(int on);
+
+/* Synchronises the device and writes one line per kernel name,
+ * "name launches total_ms algorithmic_bytes flops", into buf (NUL
+ * terminated, truncated to len).  Returns the full report length. */
+int sv_trace_report(char *buf, int len);
+
+/* Name of the rocSOLVER routine whose eigen-decomposition was used by the
+ * calling thread's last HHL call (each result is accepted only after a
+ * residual check A V x = V diag(lambda) x, |V x| = |x| on a fixed vector;
+ * real symmetric A goes to the real routines).  "" before the first call. */
+const char *sv_last_eigensolver(void);
 
 /* Last error message of the calling thread ("" if none). */
 const char *sv_last_error(void);

@@ -78,6 +78,13 @@ _SIGS = {
     "sv_postselect": ([_P, _U64, _U64, _DP, _P, _I], _I),
     "sv_hhl": ([_P, _P, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
     "sv_hhl_kron": ([_P, _P, _I, _P, _I, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
+    "sv_hhl_prepare": ([ctypes.POINTER(_P), _P, _P, _I, _P, _I], _I),
+    "sv_hhl_run": ([_P, _P, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
+    "sv_hhl_plan_spectrum": ([_P, _DP, _DP], _I),
+    "sv_hhl_plan_free": ([_P], _I),
+    "sv_last_eigensolver": ([], ctypes.c_char_p),
+    "sv_trace_enable": ([_I], _I),
+    "sv_trace_report": ([ctypes.c_char_p, _I], _I),
     "sv_last_error": ([], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_char_p),
 }
@@ -298,6 +305,59 @@ def sv_hhl_kron(h, A_hi, A_lo, b, n_c, T0, mode=1):
     _check(lib().sv_hhl_kron(h, _ptr(Ahf), m_hi, _ptr(Alf), m_lo, _ptr(bf), ctypes.byref(prm), ctypes.byref(res),
                              _ptr(x)), "sv_hhl_kron")
     return x, res
+
+
+def sv_trace_enable(on=True):
+    _check(lib().sv_trace_enable(int(bool(on))), "sv_trace_enable")
+
+
+def sv_trace_report():
+    """{kernel: {"launches", "ms", "bytes", "flops"}} for the records since sv_trace_enable(1)."""
+    n = lib().sv_trace_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().sv_trace_report(buf, n + 1)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms, by, fl = line.split()
+        out[name] = {"launches": int(cnt), "ms": float(ms), "bytes": float(by), "flops": float(fl)}
+    return out
+
+
+def sv_last_eigensolver():
+    return lib().sv_last_eigensolver().decode()
+
+
+def sv_hhl_prepare(h, A_hi, A_lo=None):
+    """Plan for A (A_lo None) or for A_hi (x) I + I (x) A_lo."""
+    A_hi, Ahf = _f64(A_hi)
+    m_hi = A_hi.shape[0].bit_length() - 1
+    m_lo, Alf = 0, None
+    if A_lo is not None:
+        A_lo, Alf = _f64(A_lo)
+        m_lo = A_lo.shape[0].bit_length() - 1
+    p = ctypes.c_void_p()
+    _check(lib().sv_hhl_prepare(ctypes.byref(p), h, _ptr(Ahf), m_hi, _ptr(Alf), m_lo), "sv_hhl_prepare")
+    return p
+
+
+def sv_hhl_run(plan, h, b, n_c, T0, mode=1):
+    b, bf = _f64(b)
+    n_s = b.size.bit_length() - 1
+    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), 0)
+    res = sv_hhl_result()
+    x = np.zeros(b.size, dtype=np.complex128)
+    _check(lib().sv_hhl_run(plan, h, _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)), "sv_hhl_run")
+    return x, res
+
+
+def sv_hhl_plan_spectrum(plan):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sv_hhl_plan_spectrum(plan, ctypes.byref(lo), ctypes.byref(hi)), "sv_hhl_plan_spectrum")
+    return lo.value, hi.value
+
+
+def sv_hhl_plan_free(plan):
+    _check(lib().sv_hhl_plan_free(plan), "sv_hhl_plan_free")
 
 
 def sv_version():

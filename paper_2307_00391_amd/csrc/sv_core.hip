@@ -325,11 +325,17 @@ sv_status norm2_device(sv_state s, uint64_t mask, uint64_t value, double *dev_ou
     SV_TRY(ensure_small(s, (nb + 8) * sizeof(double)));
     double *part = (double *)s->small + 8;
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_norm_partial<float>, dim3((unsigned)nb), dim3(256), 0, s->stream,
+        {
+            TraceScope _ts(s->stream, "norm_partial_c64", (double)count * 8, 0.0);
+            hipLaunchKernelGGL(k_norm_partial<float>, dim3((unsigned)nb), dim3(256), 0, s->stream,
                            (const float2 *)s->data, count, chunk, f, part);
+        }
     else
-        hipLaunchKernelGGL(k_norm_partial<double>, dim3((unsigned)nb), dim3(256), 0, s->stream,
+        {
+            TraceScope _ts(s->stream, "norm_partial_c128", (double)count * 16, 0.0);
+            hipLaunchKernelGGL(k_norm_partial<double>, dim3((unsigned)nb), dim3(256), 0, s->stream,
                            (const double2 *)s->data, count, chunk, f, part);
+        }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s->stream, (const double *)part, (int)nb, 1, dev_out);
     SV_HIP(hipGetLastError());
     return SV_OK;
@@ -343,9 +349,15 @@ sv_status bitrev_register(sv_state s, int lo, int m, uint64_t fix_mask, uint64_t
     const uint64_t count = dim_of(s->n - popcount64(fix_mask));
     const unsigned g = grid_for(count, 4);
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_bitrev<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f, lo, m);
+        {
+            TraceScope _ts(s->stream, "bitrev_c64", (double)count * 16, 0.0);
+            hipLaunchKernelGGL(k_bitrev<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f, lo, m);
+        }
     else
-        hipLaunchKernelGGL(k_bitrev<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f, lo, m);
+        {
+            TraceScope _ts(s->stream, "bitrev_c128", (double)count * 32, 0.0);
+            hipLaunchKernelGGL(k_bitrev<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f, lo, m);
+        }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
@@ -365,19 +377,31 @@ static sv_status launch_gate(sv_state s, int target, const double *u, uint64_t c
     if (diag && u00_one) {
         if (u[6] == 1 && u[7] == 0) return SV_OK;    // identity
         const Ins f = make_ins(cmask | tbit, cval | tbit);
-        hipLaunchKernelGGL((k_gate<R, GK_PHASE1>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
+        {
+            TraceScope _ts(s->stream, "gate_phase", (double)count * 2 * sizeof(cvec<R>), 0.0);
+            hipLaunchKernelGGL((k_gate<R, GK_PHASE1>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
                            u10, u11);
+        }
     } else {
         const Ins f = make_ins(cmask | tbit, cval);
         if (is_x)
-            hipLaunchKernelGGL((k_gate<R, GK_X>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
+            {
+                TraceScope _ts(s->stream, "gate_x", (double)count * 4 * sizeof(cvec<R>), 0.0);
+                hipLaunchKernelGGL((k_gate<R, GK_X>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
                                u10, u11);
+            }
         else if (diag)
-            hipLaunchKernelGGL((k_gate<R, GK_DIAG>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
+            {
+                TraceScope _ts(s->stream, "gate_diag", (double)count * 4 * sizeof(cvec<R>), 0.0);
+                hipLaunchKernelGGL((k_gate<R, GK_DIAG>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00, u01,
                                u10, u11);
+            }
         else
-            hipLaunchKernelGGL((k_gate<R, GK_DENSE>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00,
+            {
+                TraceScope _ts(s->stream, "gate_dense", (double)count * 4 * sizeof(cvec<R>), (double)count * 28);
+                hipLaunchKernelGGL((k_gate<R, GK_DENSE>), dim3(g), dim3(256), 0, s->stream, psi, count, f, tbit, u00,
                                u01, u10, u11);
+            }
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
@@ -483,11 +507,17 @@ sv_status sv_init_b(sv_state s, const double *b, int n_s, int n_clock_superpose)
     const uint64_t dim = dim_of(s->n);
     const unsigned g = grid_for(dim, 8);
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_init_b<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, dim,
+        {
+            TraceScope _ts(s->stream, "init_b_c64", (double)dim * 8, 0.0);
+            hipLaunchKernelGGL(k_init_b<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, dim,
                            (const double2 *)db, n_s, dim_of(n_clock_superpose), scale);
+        }
     else
-        hipLaunchKernelGGL(k_init_b<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, dim,
+        {
+            TraceScope _ts(s->stream, "init_b_c128", (double)dim * 16, 0.0);
+            hipLaunchKernelGGL(k_init_b<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, dim,
                            (const double2 *)db, n_s, dim_of(n_clock_superpose), scale);
+        }
     SV_HIP(hipGetLastError());
     SV_HIP(hipStreamSynchronize(s->stream));   // db lives in the small arena
     return SV_OK;
@@ -544,9 +574,15 @@ sv_status sv_apply_swap(sv_state s, int q1, int q2, const int *ctrls, const int 
     const uint64_t count = dim_of(s->n - popcount64(cm) - 2);
     const unsigned g = grid_for(count, 4);
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_swap<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f, b1 | b2);
+        {
+            TraceScope _ts(s->stream, "swap_c64", (double)count * 32, 0.0);
+            hipLaunchKernelGGL(k_swap<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f, b1 | b2);
+        }
     else
-        hipLaunchKernelGGL(k_swap<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f, b1 | b2);
+        {
+            TraceScope _ts(s->stream, "swap_c128", (double)count * 64, 0.0);
+            hipLaunchKernelGGL(k_swap<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f, b1 | b2);
+        }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
@@ -581,11 +617,17 @@ sv_status sv_apply_uniform_ry(sv_state s, int target, int reg_lo, int m, const d
     const uint64_t count = dim_of(s->n - popcount64(fm));
     const unsigned g = grid_for(count, 4);
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_uniform_ry<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f,
+        {
+            TraceScope _ts(s->stream, "uniform_ry_c64", (double)count * 32, 0.0);
+            hipLaunchKernelGGL(k_uniform_ry<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)s->data, count, f,
                            1ull << target, reg_lo, M - 1, (const float2 *)dt);
+        }
     else
-        hipLaunchKernelGGL(k_uniform_ry<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f,
+        {
+            TraceScope _ts(s->stream, "uniform_ry_c128", (double)count * 64, 0.0);
+            hipLaunchKernelGGL(k_uniform_ry<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)s->data, count, f,
                            1ull << target, reg_lo, M - 1, (const double2 *)dt);
+        }
     SV_HIP(hipGetLastError());
     SV_HIP(hipStreamSynchronize(s->stream));   // the table lives in the small arena
     return SV_OK;

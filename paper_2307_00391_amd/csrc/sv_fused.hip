@@ -420,8 +420,11 @@ static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
         const FPass &h = passes[i].hdr;
         const uint64_t tiles = dim_of(s->n - h.k);
         const size_t lds = ((size_t)1 << h.k) * sizeof(cvec<R>);
-        hipLaunchKernelGGL(k_fused<R>, tile_grid(tiles), dim3(FUSE_BLOCK), lds, s->stream, (cvec<R> *)s->data, dp,
+        {
+            TraceScope _ts(s->stream, "fused_pass", 2.0 * (double)dim_of(s->n) * sizeof(cvec<R>), 0.0);
+            hipLaunchKernelGGL(k_fused<R>, tile_grid(tiles), dim3(FUSE_BLOCK), lds, s->stream, (cvec<R> *)s->data, dp,
                            (int)i, dops);
+        }
     }
     hipError_t e = hipGetLastError();
     hipFreeAsync(dev, s->stream);
@@ -514,7 +517,10 @@ static sv_status qft_cascade_impl(sv_state s, const QftSpec &q, int max_local) {
         A.fix_val = q.fix_val;
         const uint64_t tiles = dim_of(n - A.k - nfix);
         const size_t lds = ((size_t)1 << A.k) * sizeof(cvec<R>);
-        hipLaunchKernelGGL(k_qft_pass<R>, tile_grid(tiles), dim3(FUSE_BLOCK), lds, s->stream, (cvec<R> *)s->data, A);
+        {
+            TraceScope _ts(s->stream, "qft_pass", 2.0 * (double)dim_of(n - nfix) * sizeof(cvec<R>), 0.0);
+            hipLaunchKernelGGL(k_qft_pass<R>, tile_grid(tiles), dim3(FUSE_BLOCK), lds, s->stream, (cvec<R> *)s->data, A);
+        }
     }
     SV_HIP(hipGetLastError());
     return SV_OK;

@@ -165,7 +165,10 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
     const uint64_t gm = (M + GBM - 1) / GBM;
     const unsigned gn = (unsigned)((N + GBN - 1) / GBN);
     if (gm > 0x7fffffffull) return fail(SV_EUNSUPPORTED, "GEMM with too many rows");
-    hipLaunchKernelGGL(k_cgemm<R>, dim3((unsigned)gm, gn), dim3(256), 0, st, a);
+    {
+        TraceScope _ts(st, "cgemm", ((double)M * (N + K) + (double)N * K) * sizeof(cvec<R>), 8.0 * (double)M * N * K);
+        hipLaunchKernelGGL(k_cgemm<R>, dim3((unsigned)gm, gn), dim3(256), 0, st, a);
+    }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
@@ -191,8 +194,11 @@ sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int c
     const uint64_t total = M * (uint64_t)N;
     uint64_t g = (total + 1023) / 1024;
     if (g > (1u << 20)) g = 1u << 20;
-    hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)g), dim3(256), 0, s->stream, (cvec<R> *)s->data,
+    {
+        TraceScope _ts(s->stream, "scatter_rows", 2.0 * (double)total * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)g), dim3(256), 0, s->stream, (cvec<R> *)s->data,
                        (const cvec<R> *)out, M, m, row_mask, row_fix);
+    }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }

@@ -23,7 +23,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -61,6 +64,15 @@ __global__ void k_scale_cols(double2 *__restrict__ W, const double2 *__restrict_
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
         const double2 v = V[i], e = E[i % N];
         W[i] = make_double2(v.x * e.x - v.y * e.y, v.x * e.y + v.y * e.x);
+    }
+}
+
+// real column-major eigenvectors -> complex row-major V
+__global__ void k_real_cm_to_complex(double2 *__restrict__ V, const double *__restrict__ Acm, int N) {
+    const uint64_t total = (uint64_t)N * N;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = i / N, j = i % N;
+        V[i] = make_double2(Acm[j * N + r], 0.0);
     }
 }
 
@@ -243,11 +255,13 @@ static unsigned grid1(uint64_t items) {
 DevBuf::~DevBuf() {
     if (p) hipFree(p);
 }
-sv_status DevBuf::alloc(size_t bytes) {
+sv_status DevBuf::alloc(size_t nbytes) {
     if (p) hipFree(p);
     p = nullptr;
-    if (!bytes) return SV_OK;
-    SV_HIP(hipMalloc(&p, bytes));
+    bytes = 0;
+    if (!nbytes) return SV_OK;
+    SV_HIP(hipMalloc(&p, nbytes));
+    bytes = nbytes;
     return SV_OK;
 }
 
@@ -306,15 +320,48 @@ static bool eig_residual_ok(const double *A, int N, const std::vector<double> &l
 }
 
 // Hermitian eigen-decomposition in FP64 on the device (rocSOLVER), validated
-// by eig_residual_ok; divide-and-conquer first, then QR iteration, then
-// Jacobi if a result fails the check.  dV receives V row-major (column j =
-// eigenvector j); lam ascending.
+// by eig_residual_ok.  Real symmetric input goes to the real solvers.  The
+// solvers are tried in order (divide and conquer, Jacobi, QR iteration)
+// until one passes the check; SV_EIGH_ORDER (comma-separated names) can
+// override the order.  dV receives V row-major (column j = eigenvector j);
+// lam ascending.
+enum EigSolver { ES_ZHEEVD, ES_ZHEEVJ, ES_ZHEEV, ES_DSYEVD, ES_DSYEVJ, ES_DSYEV };
+static const char *es_name(int e) {
+    static const char *n[] = {"zheevd", "zheevj", "zheev", "dsyevd", "dsyevj", "dsyev"};
+    return n[e];
+}
+
+static thread_local std::string g_eigh_used;
+
 sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vector<double> &lam) {
+    bool real = true;
+    for (size_t i = 0; i < (size_t)N * N && real; ++i) real = A[2 * i + 1] == 0.0;
+    std::vector<int> order;
+    if (const char *env = getenv("SV_EIGH_ORDER")) {
+        std::string e(env);
+        size_t pos = 0;
+        while (pos <= e.size()) {
+            size_t q = e.find(',', pos);
+            if (q == std::string::npos) q = e.size();
+            std::string name = e.substr(pos, q - pos);
+            for (int k = 0; k < 6; ++k)
+                if (name == es_name(k) && (real || k < 3)) order.push_back(k);
+            pos = q + 1;
+        }
+    }
+    if (order.empty()) {
+        if (real) order = {ES_DSYEVD, ES_DSYEVJ, ES_ZHEEVJ, ES_DSYEV};
+        else order = {ES_ZHEEVD, ES_ZHEEVJ, ES_ZHEEV};
+    }
     // rocSOLVER is column-major: the row-major conj(A) is A in column-major order
-    std::vector<double> Ac(2 * (size_t)N * N);
+    std::vector<double> Ac(2 * (size_t)N * N), Ar;
     for (size_t i = 0; i < (size_t)N * N; ++i) {
         Ac[2 * i] = A[2 * i];
         Ac[2 * i + 1] = -A[2 * i + 1];
+    }
+    if (real) {
+        Ar.resize((size_t)N * N);
+        for (size_t i = 0; i < (size_t)N * N; ++i) Ar[i] = A[2 * i];   // symmetric: row-major == column-major
     }
     DevBuf dA, dD, dE, dInfo, dRes, dSweeps;
     SV_TRY(dA.alloc((size_t)N * N * sizeof(double2)));
@@ -327,37 +374,55 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
     rocblas_handle h;
     SV_TRY(blas_handle(s->stream, &h));
     std::vector<double> Vh(2 * (size_t)N * N);
-    const char *names[3] = {"zheevd", "zheev", "zheevj"};
     double worst = 0.0;
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        SV_TRY(upload(s, dA.p, Ac.data(), Ac.size() * sizeof(double)));
-        rocblas_status rs;
-        if (attempt == 0)
-            rs = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, N, (rocblas_double_complex *)dA.p, N,
-                                  (double *)dD.p, (double *)dE.p, (rocblas_int *)dInfo.p);
-        else if (attempt == 1)
-            rs = rocsolver_zheev(h, rocblas_evect_original, rocblas_fill_upper, N, (rocblas_double_complex *)dA.p, N,
-                                 (double *)dD.p, (double *)dE.p, (rocblas_int *)dInfo.p);
-        else
-            rs = rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, N,
-                                  (rocblas_double_complex *)dA.p, N, 0.0, (double *)dRes.p, 100,
-                                  (rocblas_int *)dSweeps.p, (double *)dD.p, (rocblas_int *)dInfo.p);
+    std::string tried;
+    for (int e : order) {
+        const bool rs_real = e >= ES_DSYEVD;
+        if (rs_real) SV_TRY(upload(s, dA.p, Ar.data(), Ar.size() * sizeof(double)));
+        else SV_TRY(upload(s, dA.p, Ac.data(), Ac.size() * sizeof(double)));
+        rocblas_double_complex *zA = (rocblas_double_complex *)dA.p;
+        double *rA = (double *)dA.p, *D = (double *)dD.p, *E = (double *)dE.p;
+        rocblas_int *info_p = (rocblas_int *)dInfo.p;
+        rocblas_status rs = rocblas_status_not_implemented;
+        switch (e) {
+        case ES_ZHEEVD: rs = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, N, zA, N, D, E, info_p); break;
+        case ES_ZHEEV: rs = rocsolver_zheev(h, rocblas_evect_original, rocblas_fill_upper, N, zA, N, D, E, info_p); break;
+        case ES_ZHEEVJ:
+            rs = rocsolver_zheevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, N, zA, N, 0.0,
+                                  (double *)dRes.p, 100, (rocblas_int *)dSweeps.p, D, info_p);
+            break;
+        case ES_DSYEVD: rs = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, N, rA, N, D, E, info_p); break;
+        case ES_DSYEV: rs = rocsolver_dsyev(h, rocblas_evect_original, rocblas_fill_upper, N, rA, N, D, E, info_p); break;
+        case ES_DSYEVJ:
+            rs = rocsolver_dsyevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, N, rA, N, 0.0,
+                                  (double *)dRes.p, 100, (rocblas_int *)dSweeps.p, D, info_p);
+            break;
+        }
+        tried += std::string(tried.empty() ? "" : ",") + es_name(e);
         if (rs != rocblas_status_success) continue;
         int info = 0;
         lam.resize(N);
         SV_TRY(download(s, lam.data(), dD.p, N * sizeof(double)));
         SV_TRY(download(s, &info, dInfo.p, sizeof(int)));
         if (info != 0) continue;
-        // column-major eigenvectors read row-major are V^T; transpose to V
-        hipLaunchKernelGGL(k_transpose_c128, dim3(grid1((uint64_t)N * N)), dim3(256), 0, s->stream,
-                           (double2 *)dV.p, (const double2 *)dA.p, N);
+        if (rs_real)
+            hipLaunchKernelGGL(k_real_cm_to_complex, dim3(grid1((uint64_t)N * N)), dim3(256), 0, s->stream,
+                               (double2 *)dV.p, (const double *)dA.p, N);
+        else   // column-major eigenvectors read row-major are V^T; transpose to V
+            hipLaunchKernelGGL(k_transpose_c128, dim3(grid1((uint64_t)N * N)), dim3(256), 0, s->stream,
+                               (double2 *)dV.p, (const double2 *)dA.p, N);
         SV_HIP(hipGetLastError());
         SV_TRY(download(s, Vh.data(), dV.p, Vh.size() * sizeof(double)));
-        if (eig_residual_ok(A, N, lam, Vh, &worst)) return SV_OK;
+        if (eig_residual_ok(A, N, lam, Vh, &worst)) {
+            g_eigh_used = es_name(e);
+            return SV_OK;
+        }
     }
-    return fail(SV_EDEVICE, "no eigen-solver passed the residual check for N = %d (last residual %g, %s..%s)", N, worst,
-                names[0], names[2]);
+    return fail(SV_EDEVICE, "no eigen-solver passed the residual check for N = %d (tried %s; last residual %g)", N,
+                tried.c_str(), worst);
 }
+
+const char *eigh_last_solver() { return g_eigh_used.c_str(); }
 
 // turn fractions frac(phi_j 2^k), phi_j = lam_j T0 / 2 pi, as 64-bit fixed point
 void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<uint64_t> &F) {
@@ -410,9 +475,16 @@ static int pick_log_len(uint64_t N, int n_c) {
     return L;
 }
 
+// device workspaces of a plan, grown on demand and reused by every solve
+struct Workspace {
+    DevBuf F, cs, beta, tmp, z, x, part, zpart, sum, E, W, U64, Uk;
+};
+
+static sv_status need(DevBuf &b, size_t bytes) { return b.ensure(bytes); }
+
 template <typename R>
-static sv_status eig_frame_run(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res,
-                               double *x_out) {
+static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c,
+                               double T0, sv_hhl_result *res, double *x_out) {
     const int n_s = E.n_s;
     const uint64_t N = dim_of(n_s);
     const int anc = n_s + n_c;
@@ -424,60 +496,67 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, int n_c, double T0
     std::vector<double> cs;
     inversion_table(n_c, cs);
 
-    DevBuf dF, dcs, dbeta, dtmp, dz, dx, dpart, dsum;
-    SV_TRY(dF.alloc(F.size() * sizeof(uint64_t)));
-    SV_TRY(dcs.alloc(cs.size() * sizeof(double)));
-    SV_TRY(upload(s, dF.p, F.data(), F.size() * sizeof(uint64_t)));
-    SV_TRY(upload(s, dcs.p, cs.data(), cs.size() * sizeof(double)));
-    SV_TRY(dbeta.alloc(N * sizeof(double2)));
-    SV_TRY(dtmp.alloc(N * sizeof(double2)));
-    SV_TRY(dz.alloc(N * sizeof(double2)));
-    SV_TRY(dx.alloc(N * sizeof(double2)));
-    SV_TRY(upload(s, dx.p, E.bhat.data(), N * sizeof(double2)));
-    // beta = V^H b^
-    SV_TRY(kron_apply(st, (double2 *)dbeta.p, (const double2 *)dx.p, (double2 *)dtmp.p, (const double2 *)E.V_hi.p,
-                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 1));
-
-    // 1. the state after phase estimation, written directly (ancilla = 0 half)
     const int L = pick_log_len(N, n_c);
-    const dim3 g2((unsigned)((N + 63) / 64), (unsigned)(((1ull << n_c) >> L) / 4 ? ((1ull << n_c) >> L) / 4 : 1));
     if (((1ull << n_c) >> L) < 4) return fail(SV_EUNSUPPORTED, "eigen-frame mode needs n_c >= 2");
-    hipLaunchKernelGGL(k_eig_init<R>, g2, dim3(256), 0, st, (cvec<R> *)s->data, (const double2 *)dbeta.p,
-                       (const uint64_t *)dF.p, N, n_s, n_c, L, 1.0 / sqrt((double)(1ull << n_c)));
-    SV_HIP(hipGetLastError());
-    // 2. inverse QFT cascade on the clock, ancilla = 0 half
-    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, abit, 0}, 0));
-    // 3. eigenvalue inversion: ancilla = 1 half <- s_y (ancilla = 0 half)
+    const dim3 g2((unsigned)((N + 63) / 64), (unsigned)(((1ull << n_c) >> L) / 4));
     const uint64_t half = dim_of(n_s + n_c);
     uint64_t nb = (half + 256 * 64 - 1) / (256 * 64);
     if (nb > 4096) nb = 4096;
     const uint64_t chunk = (half + nb - 1) / nb;
-    DevBuf dzpart;
-    SV_TRY(dpart.alloc(2 * nb * sizeof(double)));
-    SV_TRY(dzpart.alloc((size_t)g2.y * 4 * N * sizeof(double2)));
-    SV_TRY(dsum.alloc(4 * sizeof(double)));
-    hipLaunchKernelGGL(k_eig_ry<R>, dim3((unsigned)nb), dim3(256), 0, st, (cvec<R> *)s->data, (const double2 *)dcs.p,
-                       half, n_s, (1ull << n_c) - 1ull, abit, chunk, (double *)dpart.p);
-    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)dpart.p, (int)nb, 2,
-                       (double *)dsum.p);
-    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)dpart.p + 1, (int)nb, 2,
-                       (double *)dsum.p + 1);
+
+    SV_TRY(need(w.F, F.size() * sizeof(uint64_t)));
+    SV_TRY(need(w.cs, cs.size() * sizeof(double)));
+    SV_TRY(need(w.beta, N * sizeof(double2)));
+    SV_TRY(need(w.tmp, N * sizeof(double2)));
+    SV_TRY(need(w.z, N * sizeof(double2)));
+    SV_TRY(need(w.x, N * sizeof(double2)));
+    SV_TRY(need(w.part, 2 * nb * sizeof(double)));
+    SV_TRY(need(w.zpart, (size_t)g2.y * 4 * N * sizeof(double2)));
+    SV_TRY(need(w.sum, 4 * sizeof(double)));
+    SV_TRY(upload(s, w.F.p, F.data(), F.size() * sizeof(uint64_t)));
+    SV_TRY(upload(s, w.cs.p, cs.data(), cs.size() * sizeof(double)));
+    SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
+    // beta = V^H b^
+    SV_TRY(kron_apply(st, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
+                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 1));
+
+    // 1. the state after phase estimation, written directly (ancilla = 0 half)
+    {
+        TraceScope _ts(st, "eig_init", (double)half * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_eig_init<R>, g2, dim3(256), 0, st, (cvec<R> *)s->data, (const double2 *)w.beta.p,
+                           (const uint64_t *)w.F.p, N, n_s, n_c, L, 1.0 / sqrt((double)(1ull << n_c)));
+    }
+    SV_HIP(hipGetLastError());
+    // 2. inverse QFT cascade on the clock, ancilla = 0 half
+    SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, abit, 0}, 0));
+    // 3. eigenvalue inversion: ancilla = 1 half <- s_y (ancilla = 0 half)
+    {
+        TraceScope _ts(st, "eig_ry", 2.0 * (double)half * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_eig_ry<R>, dim3((unsigned)nb), dim3(256), 0, st, (cvec<R> *)s->data,
+                           (const double2 *)w.cs.p, half, n_s, (1ull << n_c) - 1ull, abit, chunk, (double *)w.part.p);
+    }
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)w.part.p, (int)nb, 2,
+                       (double *)w.sum.p);
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)w.part.p + 1, (int)nb, 2,
+                       (double *)w.sum.p + 1);
     SV_HIP(hipGetLastError());
     // 4. QFT cascade on the clock, ancilla = 1 half
     SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 0, abit, abit}, 0));
     // 5. conjugate phases + Hadamards + clock = 0 projection
-    double2 *zpart = (double2 *)dzpart.p;
-    hipLaunchKernelGGL(k_eig_project<R>, g2, dim3(256), 0, st, (const cvec<R> *)s->data, (const uint64_t *)dF.p, N,
-                       n_s, n_c, L, abit, zpart);
-    hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)dz.p, (const double2 *)zpart, N,
+    {
+        TraceScope _ts(st, "eig_project", (double)half * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_eig_project<R>, g2, dim3(256), 0, st, (const cvec<R> *)s->data,
+                           (const uint64_t *)w.F.p, N, n_s, n_c, L, abit, (double2 *)w.zpart.p);
+    }
+    hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.z.p, (const double2 *)w.zpart.p, N,
                        (int)(g2.y * 4), 1.0 / sqrt((double)(1ull << n_c)));
     SV_HIP(hipGetLastError());
     // 6. back to the computational basis: x = V z
-    SV_TRY(kron_apply(st, (double2 *)dx.p, (const double2 *)dz.p, (double2 *)dtmp.p, (const double2 *)E.V_hi.p,
+    SV_TRY(kron_apply(st, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
                       E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 0));
     std::vector<double> sums(2), xz(2 * N);
-    SV_TRY(download(s, sums.data(), dsum.p, 2 * sizeof(double)));
-    SV_TRY(download(s, xz.data(), dx.p, N * sizeof(double2)));
+    SV_TRY(download(s, sums.data(), w.sum.p, 2 * sizeof(double)));
+    SV_TRY(download(s, xz.data(), w.x.p, N * sizeof(double2)));
     double p = 0.0;
     for (uint64_t j = 0; j < N; ++j) p += xz[2 * j] * xz[2 * j] + xz[2 * j + 1] * xz[2 * j + 1];
     res->p_post = p;
@@ -491,15 +570,20 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, int n_c, double T0
     return SV_OK;
 }
 
-sv_status eig_frame(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res, double *x_out) {
-    if (n_c > EIG_MAXC) return fail(SV_EUNSUPPORTED, "n_c %d > %d", n_c, EIG_MAXC);
-    return s->dt == SV_C64 ? eig_frame_run<float>(s, E, n_c, T0, res, x_out)
-                           : eig_frame_run<double>(s, E, n_c, T0, res, x_out);
+// V = V_hi (x) V_lo as a dense row-major matrix
+__global__ void k_kron_matrix(double2 *__restrict__ V, const double2 *__restrict__ Vh, const double2 *__restrict__ Vl,
+                              int nh, int nl) {
+    const uint64_t N = (uint64_t)nh * nl, total = N * N;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t row = i / N, col = i % N;
+        const double2 a = Vh[(row / nl) * nh + col / nl], b = Vl[(row % nl) * nl + col % nl];
+        V[i] = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    }
 }
 
 template <typename R>
-static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, int n_s, int n_c,
-                                   double T0, const double *b, sv_hhl_result *res, double *x_out) {
+static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, Workspace &w,
+                                   int n_s, int n_c, double T0, const double *b, sv_hhl_result *res, double *x_out) {
     const int N = 1 << n_s;
     const hipStream_t st = s->stream;
     // U_k = V diag(E_k) V^H for k = 0..n_c-1, FP64, then rounded to the state's precision
@@ -511,25 +595,24 @@ static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vec
             Ek[2 * ((size_t)k * N + j)] = cos(2.0 * M_PI * f);
             Ek[2 * ((size_t)k * N + j) + 1] = sin(2.0 * M_PI * f);
         }
-    DevBuf dE, dW, dU64, dUk;
-    SV_TRY(dE.alloc(Ek.size() * sizeof(double)));
-    SV_TRY(upload(s, dE.p, Ek.data(), Ek.size() * sizeof(double)));
-    SV_TRY(dW.alloc((size_t)N * N * sizeof(double2)));
-    SV_TRY(dU64.alloc((size_t)N * N * sizeof(double2)));
-    SV_TRY(dUk.alloc((size_t)n_c * N * N * sizeof(cvec<R>)));
     const uint64_t NN = (uint64_t)N * N;
+    SV_TRY(need(w.E, Ek.size() * sizeof(double)));
+    SV_TRY(need(w.W, NN * sizeof(double2)));
+    SV_TRY(need(w.U64, NN * sizeof(double2)));
+    SV_TRY(need(w.Uk, (size_t)n_c * NN * sizeof(cvec<R>)));
+    SV_TRY(upload(s, w.E.p, Ek.data(), Ek.size() * sizeof(double)));
     for (int k = 0; k < n_c; ++k) {
-        hipLaunchKernelGGL(k_scale_cols, dim3(grid1(NN)), dim3(256), 0, st, (double2 *)dW.p, dV,
-                           (const double2 *)dE.p + (size_t)k * N, N);
-        double2 *dst = std::is_same<R, double>::value ? (double2 *)dUk.p + (size_t)k * NN : (double2 *)dU64.p;
-        SV_TRY(cgemm<double>(st, (const double2 *)dW.p, dst, dV, (uint64_t)N, N, N, (uint64_t)(N - 1) << n_s, 0, 0,
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid1(NN)), dim3(256), 0, st, (double2 *)w.W.p, dV,
+                           (const double2 *)w.E.p + (size_t)k * N, N);
+        double2 *dst = std::is_same<R, double>::value ? (double2 *)w.Uk.p + (size_t)k * NN : (double2 *)w.U64.p;
+        SV_TRY(cgemm<double>(st, (const double2 *)w.W.p, dst, dV, (uint64_t)N, N, N, (uint64_t)(N - 1) << n_s, 0, 0,
                              1));
         if (!std::is_same<R, double>::value)
-            hipLaunchKernelGGL(k_c128_to_c64, dim3(grid1(NN)), dim3(256), 0, st, (float2 *)dUk.p + (size_t)k * NN,
-                               (const double2 *)dU64.p, NN);
+            hipLaunchKernelGGL(k_c128_to_c64, dim3(grid1(NN)), dim3(256), 0, st, (float2 *)w.Uk.p + (size_t)k * NN,
+                               (const double2 *)w.U64.p, NN);
     }
     SV_HIP(hipGetLastError());
-    const cvec<R> *U = (const cvec<R> *)dUk.p;
+    const cvec<R> *U = (const cvec<R> *)w.Uk.p;
 
     SV_TRY(sv_init_b(s, b, n_s, n_c));
     for (int k = 0; k < n_c; ++k) SV_TRY(ctrl_unitary_impl<R>(s, U + (size_t)k * NN, n_s, n_s + (n_c - 1 - k), 1, 0));
@@ -556,6 +639,7 @@ static sv_status check_params(sv_state s, const sv_hhl_params *prm, sv_hhl_resul
         return fail(SV_EINVAL, "n_s %d + n_c %d + 1 != %d qubits", prm->n_s, prm->n_c, s->n);
     if (!(prm->T0 > 0.0) || !isfinite(prm->T0)) return fail(SV_EINVAL, "T0 must be positive");
     if (prm->mode != 0 && prm->mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    if (prm->n_c > EIG_MAXC) return fail(SV_EUNSUPPORTED, "n_c %d > %d", prm->n_c, EIG_MAXC);
     return SV_OK;
 }
 
@@ -571,9 +655,102 @@ static sv_status normalise_b(const double *b, uint64_t N, std::vector<double> &b
 
 }  // namespace sv
 
+struct sv_hhl_plan_s {
+    sv::EigFrame E;
+    sv::DevBuf V_dense;     // V_hi (x) V_lo, built on first gate-faithful run of a Kronecker plan
+    sv::Workspace w;
+};
+
 using namespace sv;
 
 extern "C" {
+
+const char *sv_last_eigensolver(void) { return eigh_last_solver(); }
+
+sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m_hi, const double *A_lo, int m_lo) {
+    clear_error();
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    SV_TRY(check_state(s));
+    if (!A_hi || m_hi < 1 || m_lo < 0 || (m_lo > 0 && !A_lo)) return fail(SV_EINVAL, "bad operator arguments");
+    if (m_hi > 13 || m_lo > 13) return fail(SV_EUNSUPPORTED, "factor larger than 2^13");
+    const int nh = 1 << m_hi, nl = 1 << m_lo;
+    SV_TRY(check_hermitian(A_hi, nh, m_lo ? "A_hi" : "A"));
+    if (m_lo) SV_TRY(check_hermitian(A_lo, nl, "A_lo"));
+    sv_hhl_plan p = new sv_hhl_plan_s();
+    p->E.n_s = m_hi + m_lo;
+    p->E.n_hi = nh;
+    p->E.n_lo = nl;
+    sv_status st = eigh_device(s, A_hi, nh, p->E.V_hi, p->E.lam);
+    if (st == SV_OK && m_lo) {
+        std::vector<double> mu = p->E.lam, nu;
+        st = eigh_device(s, A_lo, nl, p->E.V_lo, nu);
+        if (st == SV_OK) {
+            p->E.lam.resize((size_t)nh * nl);
+            for (int a = 0; a < nh; ++a)
+                for (int q = 0; q < nl; ++q) p->E.lam[(size_t)a * nl + q] = mu[a] + nu[q];
+        }
+    }
+    if (st != SV_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return SV_OK;
+}
+
+sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda_max) {
+    if (!p) return fail(SV_EINVAL, "null plan");
+    double lo = p->E.lam[0], hi = p->E.lam[0];
+    for (double v : p->E.lam) {
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    if (lambda_min) *lambda_min = lo;
+    if (lambda_max) *lambda_max = hi;
+    return SV_OK;
+}
+
+sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
+                     double *x_out) {
+    clear_error();
+    if (!p) return fail(SV_EINVAL, "null plan");
+    SV_TRY(check_state(s));
+    SV_TRY(check_params(s, prm, res));
+    if (!b) return fail(SV_EINVAL, "b is NULL");
+    if (prm->n_s != p->E.n_s) return fail(SV_EINVAL, "plan has n_s = %d, params n_s = %d", p->E.n_s, prm->n_s);
+    const uint64_t N = dim_of(p->E.n_s);
+    std::vector<double> bhat;
+    SV_TRY(normalise_b(b, N, bhat));
+    SV_TRY(sv_hhl_plan_spectrum(p, &res->lambda_min, &res->lambda_max));
+    if (!(res->lambda_min > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
+    if (prm->mode == 1)
+        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, prm->T0, res, x_out)
+                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, prm->T0, res, x_out);
+    // gate-faithful: dense eigenvectors
+    if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
+    const double2 *dV = (const double2 *)p->E.V_hi.p;
+    if (p->E.n_lo > 1) {
+        if (!p->V_dense.p) {
+            SV_TRY(p->V_dense.ensure(N * N * sizeof(double2)));
+            hipLaunchKernelGGL(k_kron_matrix, dim3(grid1(N * N)), dim3(256), 0, s->stream, (double2 *)p->V_dense.p,
+                               (const double2 *)p->E.V_hi.p, (const double2 *)p->E.V_lo.p, p->E.n_hi, p->E.n_lo);
+            SV_HIP(hipGetLastError());
+        }
+        dV = (const double2 *)p->V_dense.p;
+    }
+    if (s->dt == SV_C64)
+        return gate_faithful_run<float>(s, dV, p->E.lam, p->w, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
+    return gate_faithful_run<double>(s, dV, p->E.lam, p->w, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
+}
+
+sv_status sv_hhl_plan_free(sv_hhl_plan p) {
+    if (p) {
+        hipDeviceSynchronize();
+        delete p;
+    }
+    return SV_OK;
+}
 
 sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
                  double *x_out) {
@@ -581,25 +758,16 @@ sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_para
     SV_TRY(check_state(s));
     SV_TRY(check_params(s, prm, res));
     if (!A || !b) return fail(SV_EINVAL, "A/b is NULL");
-    const int n_s = prm->n_s;
-    if (n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d (use sv_hhl_kron)", n_s);
-    const int N = 1 << n_s;
-    SV_TRY(check_hermitian(A, N, "A"));
-    EigFrame E;
-    E.n_s = n_s;
-    E.n_hi = N;
-    E.n_lo = 1;
-    SV_TRY(normalise_b(b, N, E.bhat));
-    SV_TRY(eigh_device(s, A, N, E.V_hi, E.lam));
-    res->lambda_min = E.lam.front();
-    res->lambda_max = E.lam.back();
-    if (!(E.lam.front() > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", E.lam.front());
-    if (prm->mode == 1) return eig_frame(s, E, prm->n_c, prm->T0, res, x_out);
-    if (s->dt == SV_C64)
-        return gate_faithful_run<float>(s, (const double2 *)E.V_hi.p, E.lam, n_s, prm->n_c, prm->T0, E.bhat.data(),
-                                        res, x_out);
-    return gate_faithful_run<double>(s, (const double2 *)E.V_hi.p, E.lam, n_s, prm->n_c, prm->T0, E.bhat.data(), res,
-                                     x_out);
+    if (prm->n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d (use sv_hhl_kron)", prm->n_s);
+    std::vector<double> bhat;
+    SV_TRY(normalise_b(b, dim_of(prm->n_s), bhat));
+    sv_hhl_plan p = nullptr;
+    SV_TRY(sv_hhl_prepare(&p, s, A, prm->n_s, nullptr, 0));
+    sv_status st = sv_hhl_run(p, s, b, prm, res, x_out);
+    std::string keep = sv_last_error();
+    sv_hhl_plan_free(p);
+    if (st != SV_OK) fail(st, "%s", keep.c_str());
+    return st;
 }
 
 sv_status sv_hhl_kron(sv_state s, const double *A_hi, int m_hi, const double *A_lo, int m_lo, const double *b,
@@ -609,46 +777,15 @@ sv_status sv_hhl_kron(sv_state s, const double *A_hi, int m_hi, const double *A_
     SV_TRY(check_params(s, prm, res));
     if (!A_hi || !A_lo || !b) return fail(SV_EINVAL, "A_hi/A_lo/b is NULL");
     if (m_hi < 1 || m_lo < 1 || m_hi + m_lo != prm->n_s) return fail(SV_EINVAL, "m_hi + m_lo != n_s");
-    if (m_hi > 13 || m_lo > 13) return fail(SV_EUNSUPPORTED, "factor larger than 2^13");
-    const int nh = 1 << m_hi, nl = 1 << m_lo;
-    SV_TRY(check_hermitian(A_hi, nh, "A_hi"));
-    SV_TRY(check_hermitian(A_lo, nl, "A_lo"));
-    if (prm->mode == 0) {
-        // gate-faithful needs the dense operator A_hi (x) I + I (x) A_lo
-        if (prm->n_s > 12) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 12", prm->n_s);
-        const int N = nh * nl;
-        std::vector<double> A(2 * (size_t)N * N, 0.0);
-        for (int p = 0; p < nh; ++p)
-            for (int q = 0; q < nl; ++q)
-                for (int r = 0; r < nh; ++r)
-                    for (int c = 0; c < nl; ++c) {
-                        const size_t i = (size_t)(p * nl + q) * N + (r * nl + c);
-                        if (q == c) {
-                            A[2 * i] += A_hi[2 * ((size_t)p * nh + r)];
-                            A[2 * i + 1] += A_hi[2 * ((size_t)p * nh + r) + 1];
-                        }
-                        if (p == r) {
-                            A[2 * i] += A_lo[2 * ((size_t)q * nl + c)];
-                            A[2 * i + 1] += A_lo[2 * ((size_t)q * nl + c) + 1];
-                        }
-                    }
-        return sv_hhl(s, A.data(), b, prm, res, x_out);
-    }
-    EigFrame E;
-    E.n_s = prm->n_s;
-    E.n_hi = nh;
-    E.n_lo = nl;
-    SV_TRY(normalise_b(b, (uint64_t)nh * nl, E.bhat));
-    std::vector<double> mu, nu;
-    SV_TRY(eigh_device(s, A_hi, nh, E.V_hi, mu));
-    SV_TRY(eigh_device(s, A_lo, nl, E.V_lo, nu));
-    E.lam.resize((size_t)nh * nl);
-    for (int p = 0; p < nh; ++p)
-        for (int q = 0; q < nl; ++q) E.lam[(size_t)p * nl + q] = mu[p] + nu[q];
-    res->lambda_min = mu.front() + nu.front();
-    res->lambda_max = mu.back() + nu.back();
-    if (!(res->lambda_min > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
-    return eig_frame(s, E, prm->n_c, prm->T0, res, x_out);
+    std::vector<double> bhat;
+    SV_TRY(normalise_b(b, dim_of(prm->n_s), bhat));
+    sv_hhl_plan p = nullptr;
+    SV_TRY(sv_hhl_prepare(&p, s, A_hi, m_hi, A_lo, m_lo));
+    sv_status st = sv_hhl_run(p, s, b, prm, res, x_out);
+    std::string keep = sv_last_error();
+    sv_hhl_plan_free(p);
+    if (st != SV_OK) fail(st, "%s", keep.c_str());
+    return st;
 }
 
 }  // extern "C"

@@ -17,7 +17,9 @@ struct DevBuf {
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf();
+    size_t bytes = 0;
     sv_status alloc(size_t bytes);
+    sv_status ensure(size_t need) { return need <= bytes && p ? SV_OK : alloc(need); }
 };
 
 // eigen-decomposition of A = A_hi (x) I + I (x) A_lo (dense A: n_lo = 1, V_lo empty)
@@ -25,7 +27,6 @@ struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;
     DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
     std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
-    std::vector<double> bhat;     // normalised b, interleaved complex FP64
 };
 
 sv_status check_hermitian(const double *A, int N, const char *name);
@@ -34,7 +35,7 @@ void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<
 void inversion_table(int n_c, std::vector<double> &cs);
 sv_status kron_apply(hipStream_t st, double2 *out, const double2 *in, double2 *tmp, const double2 *V_hi, int n_hi,
                      const double2 *V_lo, int n_lo, int adjoint);
-sv_status eig_frame(sv_state s, const EigFrame &E, int n_c, double T0, sv_hhl_result *res, double *x_out);
+const char *eigh_last_solver();
 
 // fixed-order sum of `count` partials spaced `stride` apart into out[0]
 static __global__ __launch_bounds__(256) void k_sum_partials_strided(const double *__restrict__ part, int count,

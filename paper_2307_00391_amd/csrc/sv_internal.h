@@ -78,6 +78,20 @@ sv_status run_hadamards(sv_state s, int lo, int m, uint64_t fix_mask, uint64_t f
 // ---- tuning (sv_tune.cpp) ---------------------------------------------------
 int default_max_local(sv_dtype dt);
 
+// ---- per-kernel tracing (sv_trace.cpp) ------------------------------------
+bool trace_on();
+class TraceScope {
+  public:
+    TraceScope(hipStream_t st, const char *name, double bytes, double flops);
+    ~TraceScope();
+
+  private:
+    hipStream_t st_;
+    const char *name_;
+    double bytes_, flops_;
+    hipEvent_t e0_ = nullptr;
+};
+
 // bit deposit helpers (host)
 inline int popcount64(uint64_t x) { return __builtin_popcountll(x); }
 

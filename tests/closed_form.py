@@ -1,0 +1,58 @@
+"""Closed form of the whole HHL circuit (test helper, numpy FP64).
+
+With A = V diag(lam) V^H, beta = V^H b/|b|, phi_j = lam_j T0 / 2 pi and
+M = 2^n_c, phase estimation leaves |alpha_{y|j}|^2 = K(phi_j - y/M) (Fejer
+kernel [sin(pi M d) / (M sin(pi d))]^2), the rotation multiplies the
+ancilla-1 branch by 1/y (y >= 1) and the uncompute + clock = 0 projection
+returns sum_y |alpha_{y|j}|^2 / y; so the post-selected vector is
+proportional to V (beta * g) with g_j = sum_{y>=1} K(phi_j - y/M) / y,
+and p = sum_j |beta_j g_j|^2.  Pinned against the gate-level oracle in
+test_oracle_hhl.py.
+"""
+import math
+
+import numpy as np
+
+
+def fejer(delta, M):
+    d = np.asarray(delta, dtype=np.float64)
+    s = np.sin(np.pi * d)
+    out = np.ones_like(d)
+    nz = np.abs(s) > 1e-300
+    out[nz] = (np.sin(np.pi * M * d[nz]) / (M * s[nz])) ** 2
+    return out
+
+
+def g_of_phi(phi, n_c, chunk=64):
+    """g(phi) = sum_{y=1}^{M-1} K(phi - y/M) / y, vectorised in chunks of phi."""
+    M = 1 << n_c
+    y = np.arange(1, M, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    out = np.empty_like(phi)
+    for a in range(0, phi.size, chunk):
+        d = phi[a:a + chunk, None] - y[None, :] / M
+        out[a:a + chunk] = (fejer(d, M) / y[None, :]).sum(axis=1)
+    return out
+
+
+def hhl_closed_form(A, b, n_c, T0):
+    lam, V = np.linalg.eigh(A)
+    beta = V.conj().T @ (b / np.linalg.norm(b))
+    g = g_of_phi(lam * T0 / (2 * math.pi), n_c)
+    z = V @ (beta * g)
+    p = float(np.sum(np.abs(beta * g) ** 2))
+    return z / math.sqrt(p), p
+
+
+def hhl_closed_form_kron(A_hi, A_lo, b, n_c, T0):
+    """Same for A = A_hi (x) I + I (x) A_lo via the factor decompositions."""
+    mu, P = np.linalg.eigh(A_hi)
+    nu, Q = np.linalg.eigh(A_lo)
+    Bm = (np.asarray(b, dtype=np.complex128) / np.linalg.norm(b)).reshape(len(mu), len(nu))
+    beta = P.conj().T @ Bm @ Q.conj()
+    lam = mu[:, None] + nu[None, :]
+    g = g_of_phi((lam * T0 / (2 * math.pi)).ravel(), n_c).reshape(lam.shape)
+    Z = beta * g
+    p = float(np.sum(np.abs(Z) ** 2))
+    X = P @ Z @ Q.T
+    return X.reshape(-1) / math.sqrt(p), p

@@ -34,7 +34,7 @@ def _dev_matrix(U, dt):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n,m,ctrl,cval", [(6, 1, 3, 1), (9, 4, 8, 0), (12, 6, -1, 1), (14, 8, 10, 1),
-                                           (11, 10, 10, 1), (13, 5, 12, 1)])
+                                           (11, 10, 10, 1), (13, 5, 12, 1), (22, 10, 21, 1)])
 def test_ctrl_unitary_matches_oracle(dt, n, m, ctrl, cval):
     rng = np.random.default_rng(50 + n + m)
     U = inputs.random_unitary(rng, 1 << m)
@@ -152,6 +152,24 @@ def test_kron_hhl_matches_dense_oracle(dt):
         assert np.abs(x - x_r).max() <= tol
         assert abs(res.p_post - pp_r) <= TOL[dt]
         assert abs(res.lambda_max - ks.lambda_max) <= 1e-12 * ks.lambda_max
+
+
+def test_plan_reuse_matches_single_calls():
+    """One prepared operator, several right-hand sides and T0 values."""
+    rng = np.random.default_rng(5)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 32, 200.0)
+    st = B.State(5 + 7 + 1, "c128")
+    plan = B.sv_hhl_prepare(st.h, A)
+    lo, hi = B.sv_hhl_plan_spectrum(plan)
+    assert abs(lo - lmin) <= 1e-12 * lmax and abs(hi - lmax) <= 1e-12 * lmax
+    for T0 in inputs.t0_grid(lmax)[::5]:
+        b = rng.standard_normal(32)
+        _, x_r, pp_r, _ = oracle.hhl(A, b, 7, T0)
+        for mode in (0, 1):
+            x, res = B.sv_hhl_run(plan, st.h, b, 7, T0, mode)
+            assert np.abs(x - x_r).max() <= 1e-12
+            assert abs(res.p_post - pp_r) <= 1e-12
+    B.sv_hhl_plan_free(plan)
 
 
 def test_hhl_repeatable_bit_for_bit():

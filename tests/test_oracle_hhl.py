@@ -24,27 +24,7 @@ import oracle
 from paper_2307_00391_amd import inputs
 
 
-def fejer(delta, M):
-    """|2^-n_c sum_tau exp(2 pi i tau delta)|^2 in closed form (limit 1 at
-    integer delta)."""
-    d = np.asarray(delta, dtype=np.float64)
-    s = np.sin(np.pi * d)
-    out = np.ones_like(d)
-    nz = np.abs(s) > 1e-300
-    out[nz] = (np.sin(np.pi * M * d[nz]) / (M * s[nz])) ** 2
-    return out
-
-
-def hhl_closed_form(A, b, n_c, T0):
-    lam, V = np.linalg.eigh(A)
-    beta = V.conj().T @ (b / np.linalg.norm(b))
-    M = 1 << n_c
-    phi = lam * T0 / (2 * math.pi)
-    y = np.arange(1, M)
-    g = np.array([np.sum(fejer(p - y / M, M) / y) for p in phi])
-    z = V @ (beta * g)
-    p = float(np.sum(np.abs(beta * g) ** 2))
-    return z / math.sqrt(p), p
+from tests.closed_form import hhl_closed_form, hhl_closed_form_kron
 
 
 def fidelity(xq, xc):
@@ -108,6 +88,22 @@ def test_hhl_scale_invariance():
     _, x3, p3, _ = oracle.hhl(3.0 * A, b, 5, T0 / 3.0)      # generic scale
     np.testing.assert_allclose(x1, x3, atol=1e-10)
     assert abs(p1 - p3) < 1e-10
+
+
+def test_kron_closed_form_matches_dense_and_oracle():
+    """The factored closed form (used at full size on the GPU) agrees with the
+    dense closed form and with the oracle on a small Kronecker system."""
+    ks = inputs.kron_laplacian_system(inputs.rng_for(3, 7), 2, 3, kappa=300.0)
+    A = ks.dense()
+    T0 = inputs.t0_top_of_clock(ks.lambda_max, 7)
+    x1, p1 = hhl_closed_form(A, ks.b, 7, T0)
+    x2, p2 = hhl_closed_form_kron(ks.A_hi, ks.A_lo, ks.b, 7, T0)
+    _, xo, po, _ = oracle.hhl(A, ks.b, 7, T0)
+    np.testing.assert_allclose(x2, x1, atol=1e-12)
+    np.testing.assert_allclose(x2, xo, atol=1e-12)
+    assert abs(p2 - po) < 1e-12 and abs(p1 - p2) < 1e-12
+    ev = np.linalg.eigvalsh(A)
+    assert abs(ev[-1] / ev[0] - 300.0) < 1e-6 and abs(ev[-1] - ks.lambda_max) < 1e-12
 
 
 def test_classical_profiles_are_exact():
