@@ -187,7 +187,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"HHL {n} qubits: n_s={n_s} (2-D Laplacian on a {1 << m_hi}x{1 << m_lo} grid as a "
                                f"Kronecker sum + random symmetric perturbation |E|=0.1, kappa=1000), n_c={n_c}, "
-                               "1 ancilla, complex64, eigen-frame mode",
+                               "1 ancilla, complex64, eigen-frame mode (fused kernels)",
                    "global_batch": 1, "parallelism": "single GPU"},
         "hbm_gbs_step": step_bytes / (ms_per_step * 1e-3) / 1e9,
         "updates_per_step": upd,

@@ -196,10 +196,16 @@ typedef struct {
     int n_c;       /* clock (phase-estimation) qubits */
     double T0;     /* clock bit k applies exp(i A T0 2^k); y = 2^n_c lambda T0 / 2 pi */
     int mode;      /* 0: gate-faithful (dense controlled-U_k on the matrix cores, every
-                      step on the full state);  1: eigen-frame (system register held in
-                      the eigenbasis of A; the controlled-U_k become one diagonal pass,
-                      uncompute runs on the ancilla = 1 half and ends in the fused
-                      clock = 0 projection) */
+                      step on the full state);
+                      1: eigen-frame, fused: the system register is held in the eigenbasis
+                      of A, so the controlled-U_k are diagonal; the state after phase
+                      estimation is generated inside the first inverse-QFT kernel, the
+                      rotation sits between the two halves of the clock transforms, and
+                      the uncompute ends in the clock = 0 projection: three passes over
+                      half the state (n_c <= 16; larger n_c runs as mode 2);
+                      2: eigen-frame, one kernel per step (state write, inverse QFT on
+                      the ancilla = 0 half, rotation into the ancilla = 1 half, QFT there,
+                      projection) */
     int signed_clock;  /* must be 0: unsigned clock, A positive definite */
 } sv_hhl_params;
 
@@ -223,7 +229,7 @@ typedef struct {
  * 2^n_s complex FP64.  x_out (may be NULL): host, 2^n_s complex FP64, the
  * post-selected system vector divided by sqrt(p_post) (global phase as the
  * circuit leaves it).  After mode 0 the state holds the final circuit state;
- * after mode 1 its contents are unspecified.
+ * after modes 1 and 2 its contents are unspecified.
  * Errors: SV_EINVAL, SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM (|b| = 0 or
  * p_post = 0), SV_EUNSUPPORTED (signed_clock != 0), SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm,
@@ -278,6 +284,13 @@ sv_status sv_trace_enable(int on);
  * "name launches total_ms algorithmic_bytes flops", into buf (NUL
  * terminated, truncated to len).  Returns the full report length. */
 int sv_trace_report(char *buf, int len);
+
+/* The autotuner's current choices, one line per tuned shape:
+ * "op/dtype/shape... values".  For the fused eigen-frame kernels the values
+ * are (log2 columns per tile, threads per workgroup) for each of the three
+ * kernels.  Tuning runs on first use of a shape (SV_AUTOTUNE=0: defaults);
+ * SV_TUNE_CACHE=<file> persists the choices.  Returns the report length. */
+int sv_tune_report(char *buf, int len);
 
 /* Name of the rocSOLVER routine whose eigen-decomposition was used by the
  * calling thread's last HHL call (each result is accepted only after a

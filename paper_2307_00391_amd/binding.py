@@ -84,6 +84,7 @@ _SIGS = {
     "sv_hhl_plan_free": ([_P], _I),
     "sv_last_eigensolver": ([], ctypes.c_char_p),
     "sv_trace_enable": ([_I], _I),
+    "sv_tune_report": ([ctypes.c_char_p, _I], _I),
     "sv_trace_report": ([ctypes.c_char_p, _I], _I),
     "sv_last_error": ([], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_char_p),
@@ -321,6 +322,13 @@ def sv_trace_report():
         name, cnt, ms, by, fl = line.split()
         out[name] = {"launches": int(cnt), "ms": float(ms), "bytes": float(by), "flops": float(fl)}
     return out
+
+
+def sv_tune_report():
+    n = lib().sv_tune_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().sv_tune_report(buf, n + 1)
+    return buf.value.decode()
 
 
 def sv_last_eigensolver():

@@ -1,0 +1,590 @@
+// Eigen-frame HHL as three fused column-tile kernels.
+//
+// The clock register [n_s, n_s + n_c) is split into a low group G1 =
+// register bits [0, g1) and a high group G2 = [g1, n_c) (g1, g2 <= 8).  A
+// tile holds C consecutive system columns j (contiguous in memory) times the
+// 2^g clock values of one group, for one setting of the other group's bits
+// (and the ancilla).  Inside a tile every column is an independent length-2^g
+// line of the clock DFT: its butterflies run in registers, RA bits at a time
+// ("phase A": the register index k spans group bits [0, RA); "phase B": it
+// spans [RA, g)), with one LDS exchange between the two.
+//
+//   k_pipe_a: generate the state after phase estimation (product state over
+//             the clock bits, relabelled so the cascades need no swaps), then
+//             the inverse-QFT cascade on G1          -> ancilla = 0 half
+//   k_pipe_b: inverse-QFT cascade on G2, eigenvalue inversion a1 = (1/y) a0
+//             (FP64 sums of P(a=1) and the norm), QFT cascade on G2
+//                                                     -> ancilla = 1 half
+//   k_pipe_c: QFT cascade on G1, the conjugate phases of the uncompute, and
+//             the sum over the clock values of the tile (the Hadamard layer
+//             projected on clock = 0)                -> FP64 partial sums
+//
+// Cascade stages on register qubit j (relative to the clock register):
+//   inverse: a1 *= conj(phase), then (a0 + a1, a0 - a1)/sqrt 2
+//   forward: (a0 + a1, (a0 - a1) * phase)/sqrt 2
+// with phase = exp(2 pi i (v mod 2^j) / 2^(j+1)), v the register value: the
+// controlled phases of the textbook QFT circuit that target qubit j.  The
+// local part comes from a table of 2^g roots of unity, the part due to bits
+// outside the tile is one exact-turn phase per stage and tile.
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "sv_device.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+
+struct PipeArgs {
+    uint64_t N;          // 2^n_s columns
+    int n_s, n_c;
+    int g1, g2;          // clock groups
+    int cl;              // log2 of the columns per tile
+    uint64_t abit;       // ancilla bit
+    double scale;        // 2^(-n_c/2)
+};
+
+template <typename R>
+__device__ __forceinline__ cvec<R> cconjmul(cvec<R> a, cvec<R> b) {   // a * conj(b)
+    return cmake<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// One cascade stage on a register line v[0..2^RL): pairs differ in bit kb of
+// the register index.  tw is the stage's twiddle table (entry m = phase for
+// the register bits below the stage's qubit equal to m); tidx(k) gives that
+// m for element k.  The 1/sqrt(2) of the Hadamard is left out here and
+// applied once per group by the caller (butterflies are add/sub only).
+// has_tw = false for the lowest qubit of the register (phase 1).
+template <typename R, int RL, bool INV, typename TIDX>
+__device__ __forceinline__ void stage(cvec<R> (&v)[1 << RL], int kb, const cvec<R> *__restrict__ tw, bool has_tw,
+                                      TIDX tidx) {
+#pragma unroll
+    for (int k0 = 0; k0 < (1 << RL); ++k0) {
+        if (k0 & (1 << kb)) continue;
+        const int k1 = k0 | (1 << kb);
+        cvec<R> a0 = v[k0], a1 = v[k1];
+        if (INV) {
+            if (has_tw) a1 = cconjmul<R>(a1, tw[tidx(k0)]);
+            v[k0] = cmake<R>(a0.x + a1.x, a0.y + a1.y);
+            v[k1] = cmake<R>(a0.x - a1.x, a0.y - a1.y);
+        } else {
+            const cvec<R> d = cmake<R>(a0.x - a1.x, a0.y - a1.y);
+            v[k0] = cmake<R>(a0.x + a1.x, a0.y + a1.y);
+            v[k1] = has_tw ? cmul<R>(d, tw[tidx(k0)]) : d;
+        }
+    }
+}
+
+// Twiddle tables of one group, stage jb at offset 2^jb - 1 (2^jb entries):
+// entry m = exp(2 pi i (vlow + m 2^gbase) / 2^(gbase + jb + 1)), where vlow
+// (< 2^gbase) are the register bits below the group, fixed for the tile.
+template <typename R>
+__device__ __forceinline__ void fill_twiddles(cvec<R> *TW, int g, int gbase, uint64_t vlow) {
+    for (int i = threadIdx.x; i < (1 << g) - 1; i += blockDim.x) {
+        int jb = 0;
+        while ((2 << jb) - 1 <= i) ++jb;
+        const uint64_t m = (uint64_t)(i - ((1 << jb) - 1));
+        const int j = gbase + jb;
+        TW[i] = turn_phase<R>((vlow + (m << gbase)) << (63 - j));
+    }
+}
+__device__ __forceinline__ int tw_off(int jb) { return (1 << jb) - 1; }
+
+// tile decomposition: column block and the setting of the other group's bits
+__device__ __forceinline__ void tile_coords(const PipeArgs &A, uint64_t &j0, uint64_t &o) {
+    const uint64_t nb = A.N >> A.cl;
+    const uint64_t tid = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+    j0 = (tid % nb) << A.cl;
+    o = tid / nb;
+}
+
+// ---------------------------------------------------------------------------
+// k_pipe_a: phase-estimation state + inverse cascade on G1
+// ---------------------------------------------------------------------------
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_a(cvec<R> *__restrict__ psi, const double2 *__restrict__ beta,
+                                               const uint64_t *__restrict__ F, PipeArgs A) {
+    constexpr int G = RA + RB;
+    extern __shared__ unsigned char smem_raw[];
+    const int C = 1 << A.cl;
+    cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);          // [2^G][C]
+    cvec<R> *TW = tile + ((size_t)C << G);                           // [2^G - 1] (+1 pad)
+    cvec<R> *om = TW + (1 << G);                                     // [G][C] exp(2 pi i F) of the local bits
+    cvec<R> *cc = om + G * C;                                        // [C] column constants
+    uint64_t j0, o;
+    tile_coords(A, j0, o);
+    const int n_c = A.n_c;
+    fill_twiddles<R>(TW, G, 0, 0);
+    // the tile holds clock index s = (o << G) | l; bit b of s carries F[j][n_c-1-b].
+    // The G Hadamards below omit their 1/sqrt(2): 2^(-G/2) joins the amplitude scale.
+    const double sc = A.scale * exp2(-0.5 * G);
+    for (int c = threadIdx.x; c < C; c += NT) {
+        const uint64_t j = j0 + c;
+        uint64_t th = 0;
+        for (int b = G; b < n_c; ++b)
+            if (o >> (b - G) & 1) th += F[j * n_c + (n_c - 1 - b)];
+        const cvec<R> ph = turn_phase<R>(th);
+        const double2 bj = beta[j];
+        cc[c] = cmul<R>(cmake<R>((R)(bj.x * sc), (R)(bj.y * sc)), ph);
+        for (int b = 0; b < G; ++b) om[b * C + c] = turn_phase<R>(F[j * n_c + (n_c - 1 - b)]);
+    }
+    __syncthreads();
+    // phase A: line = (c, l_hi), register index = bits [0, RA)
+    const int nla = C << RB;
+    for (int line = threadIdx.x; line < nla; line += NT) {
+        const int c = line & (C - 1), lhi = line >> A.cl;
+        cvec<R> v[1 << RA];
+        cvec<R> base = cc[c];
+        for (int b = 0; b < RB; ++b)
+            if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
+        v[0] = base;
+#pragma unroll
+        for (int b = 0; b < RA; ++b) {
+            const cvec<R> w = om[b * C + c];
+#pragma unroll
+            for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
+        }
+#pragma unroll
+        for (int jb = 0; jb < RA; ++jb)
+            stage<R, RA, true>(v, jb, TW + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) tile[(((size_t)lhi << RA) | k) * C + c] = v[k];
+    }
+    __syncthreads();
+    // phase B: line = (c, l_lo), register index = bits [RA, G)
+    const int nlb = C << RA;
+    for (int line = threadIdx.x; line < nlb; line += NT) {
+        const int c = line & (C - 1), llo = line >> A.cl;
+        cvec<R> v[1 << RB];
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) v[k] = tile[(((size_t)k << RA) | llo) * C + c];
+#pragma unroll
+        for (int jb = RA; jb < G; ++jb)
+            stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
+                               [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        const uint64_t col = j0 + c;
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) {
+            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
+            psi[(s << A.n_s) | col] = v[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_pipe_b: inverse cascade on G2, inversion rotation, forward cascade on G2
+// ---------------------------------------------------------------------------
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_b(cvec<R> *__restrict__ psi, PipeArgs A, double *__restrict__ part) {
+    constexpr int G = RA + RB;
+    extern __shared__ unsigned char smem_raw[];
+    const int C = 1 << A.cl;
+    cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
+    cvec<R> *TW = tile + ((size_t)C << G);
+    double *s2t = reinterpret_cast<double *>(TW + (1 << G));        // [2^G] s_y^2 2^-G
+    double *n2t = s2t + (1 << G);                                    // [2^G] (c_y^2 + s_y^2) 2^-G
+    R *srt = reinterpret_cast<R *>(n2t + (1 << G));                  // [2^G] s_y 2^-G
+    __shared__ double red[2][NT / 64];
+    uint64_t j0, o;
+    tile_coords(A, j0, o);               // o = value of the G1 bits
+    const int g1 = A.g1;
+    fill_twiddles<R>(TW, G, g1, o);
+    // rotation of clock value y = o + l 2^g1 (natural order after the inverse
+    // transform): sin = 1/y (y >= 1).  The two groups of G Hadamards around it
+    // omit their 1/sqrt(2) each, so 2^-G is folded into the rotation (and into
+    // the FP64 weights of the sums, taken where the amplitudes are 2^(G/2) too large).
+    const double fold = exp2(-(double)G);
+    for (int l = threadIdx.x; l < (1 << G); l += NT) {
+        const uint64_t y = o | ((uint64_t)l << g1);
+        const double sd = y ? 1.0 / (double)y : 0.0;
+        const double cd = sqrt(1.0 - sd * sd);
+        s2t[l] = sd * sd * fold;
+        n2t[l] = (cd * cd + sd * sd) * fold;
+        srt[l] = (R)(sd * fold);
+    }
+    __syncthreads();
+    const int nla = C << RB, nlb = C << RA;
+    // phase A (inverse cascade, low bits of G2), straight from the ancilla = 0 half
+    for (int line = threadIdx.x; line < nla; line += NT) {
+        const int c = line & (C - 1), lhi = line >> A.cl;
+        const uint64_t col = j0 + c;
+        cvec<R> v[1 << RA];
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) {
+            const uint64_t s = o | ((((uint64_t)lhi << RA) | k) << g1);
+            v[k] = psi[(s << A.n_s) | col];
+        }
+#pragma unroll
+        for (int jb = 0; jb < RA; ++jb)
+            stage<R, RA, true>(v, jb, TW + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) tile[(((size_t)lhi << RA) | k) * C + c] = v[k];
+    }
+    __syncthreads();
+    // phase B: inverse cascade on the high bits, rotation, forward cascade on the high bits
+    double pa = 0.0, nt = 0.0;
+    for (int line = threadIdx.x; line < nlb; line += NT) {
+        const int c = line & (C - 1), llo = line >> A.cl;
+        cvec<R> v[1 << RB];
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) v[k] = tile[(((size_t)k << RA) | llo) * C + c];
+#pragma unroll
+        for (int jb = RA; jb < G; ++jb)
+            stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
+                               [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) {
+            const int l = (k << RA) | llo;
+            const double a2 = (double)v[k].x * (double)v[k].x + (double)v[k].y * (double)v[k].y;
+            pa += s2t[l] * a2;
+            nt += n2t[l] * a2;
+            const R sr = srt[l];
+            v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
+        }
+#pragma unroll
+        for (int jb = G - 1; jb >= RA; --jb)
+            stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
+                                [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) tile[(((size_t)k << RA) | llo) * C + c] = v[k];
+    }
+    __syncthreads();
+    // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
+    for (int line = threadIdx.x; line < nla; line += NT) {
+        const int c = line & (C - 1), lhi = line >> A.cl;
+        const uint64_t col = j0 + c;
+        cvec<R> v[1 << RA];
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
+#pragma unroll
+        for (int jb = RA - 1; jb >= 0; --jb)
+            stage<R, RA, false>(v, jb, TW + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) {
+            const uint64_t s = o | ((((uint64_t)lhi << RA) | k) << g1);
+            psi[A.abit | (s << A.n_s) | col] = v[k];
+        }
+    }
+    pa = wave_sum_f64(pa);
+    nt = wave_sum_f64(nt);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = pa;
+        red[1][threadIdx.x >> 6] = nt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sp = 0.0, sn = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+            sp += red[0][w];
+            sn += red[1][w];
+        }
+        const uint64_t bid = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+        part[2 * bid] = sp;
+        part[2 * bid + 1] = sn;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_pipe_c: forward cascade on G1, conjugate phases, clock sum of the tile
+// (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
+// ---------------------------------------------------------------------------
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_c(const cvec<R> *__restrict__ psi, const uint64_t *__restrict__ F,
+                                               PipeArgs A, double2 *__restrict__ zpart) {
+    constexpr int G = RA + RB;
+    extern __shared__ unsigned char smem_raw[];
+    const int C = 1 << A.cl;
+    cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
+    cvec<R> *TW = tile + ((size_t)C << G);
+    cvec<R> *om = TW + (1 << G);
+    cvec<R> *cc = om + G * C;
+    const size_t zoff = (((size_t)((unsigned char *)(cc + C) - smem_raw)) + 15) & ~(size_t)15;
+    double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [NT] per-thread partials
+    uint64_t j0, o;
+    tile_coords(A, j0, o);               // o = value of the G2 bits
+    const int n_c = A.n_c;
+    fill_twiddles<R>(TW, G, 0, 0);
+    for (int c = threadIdx.x; c < C; c += NT) {
+        const uint64_t j = j0 + c;
+        uint64_t th = 0;
+        for (int b = G; b < n_c; ++b)
+            if (o >> (b - G) & 1) th += F[j * n_c + (n_c - 1 - b)];
+        cc[c] = turn_phase<R>(0ull - th);
+        for (int b = 0; b < G; ++b) om[b * C + c] = turn_phase<R>(0ull - F[j * n_c + (n_c - 1 - b)]);
+    }
+    __syncthreads();
+    const int nla = C << RB, nlb = C << RA;
+    // phase B first: the forward cascade starts at the top bit of G1
+    for (int line = threadIdx.x; line < nlb; line += NT) {
+        const int c = line & (C - 1), llo = line >> A.cl;
+        const uint64_t col = j0 + c;
+        cvec<R> v[1 << RB];
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) {
+            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
+            v[k] = psi[A.abit | (s << A.n_s) | col];
+        }
+#pragma unroll
+        for (int jb = G - 1; jb >= RA; --jb)
+            stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
+                                [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) tile[(((size_t)k << RA) | llo) * C + c] = v[k];
+    }
+    __syncthreads();
+    // phase A: remaining stages, conjugate phases, sum over the line
+    double zr = 0.0, zi = 0.0;
+    for (int line = threadIdx.x; line < nla; line += NT) {
+        const int c = line & (C - 1), lhi = line >> A.cl;
+        cvec<R> v[1 << RA];
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
+#pragma unroll
+        for (int jb = RA - 1; jb >= 0; --jb)
+            stage<R, RA, false>(v, jb, TW + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
+        // conj phase of clock index (o << G) | (lhi << RA) | k
+        cvec<R> ph[1 << RA];
+        cvec<R> base = cc[c];
+        for (int b = 0; b < RB; ++b)
+            if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
+        ph[0] = base;
+#pragma unroll
+        for (int b = 0; b < RA; ++b) {
+            const cvec<R> w = om[b * C + c];
+#pragma unroll
+            for (int k = 0; k < (1 << b); ++k) ph[k | (1 << b)] = cmul<R>(ph[k], w);
+        }
+#pragma unroll
+        for (int k = 0; k < (1 << RA); ++k) {
+            const cvec<R> p = cmul<R>(v[k], ph[k]);
+            zr += (double)p.x;
+            zi += (double)p.y;
+        }
+    }
+    // every line of a thread has the thread's column (the line stride NT is a multiple of C)
+    zs[threadIdx.x] = make_double2(zr, zi);
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += NT) {
+        double r = 0.0, i = 0.0;
+        for (int t = c; t < NT; t += C) {
+            r += zs[t].x;
+            i += zs[t].y;
+        }
+        zpart[o * A.N + j0 + c] = make_double2(r, i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host
+// ---------------------------------------------------------------------------
+
+template <typename R, int RA, int RB, int NT>
+static sv_status launch_pipe(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
+                             const PipeArgs &A, double *part, double2 *zpart, int g, dim3 grid, size_t lds) {
+    // tiles above 64 KiB need a larger dynamic LDS limit; the request plus the
+    // kernels' static LDS must stay within the 160 KiB of a workgroup
+    constexpr int kLim = 144 * 1024;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e0 = hipFuncSetAttribute((const void *)k_pipe_a<R, RA, RB, NT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        hipError_t e1 = hipFuncSetAttribute((const void *)k_pipe_b<R, RA, RB, NT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        hipError_t e2 = hipFuncSetAttribute((const void *)k_pipe_c<R, RA, RB, NT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        (void)hipGetLastError();
+        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess)
+            return fail(SV_EDEVICE, "cannot raise the LDS limit of the pipeline kernels");
+        attr_done = true;
+    }
+    if (lds > (size_t)kLim) return fail(SV_EUNSUPPORTED, "pipeline tile needs %zu bytes of LDS", lds);
+    const double half = (double)A.N * (double)(1ull << A.n_c) * sizeof(cvec<R>);
+    if (which == 0) {
+        TraceScope ts(st, "pipe_a_init_iqft", half, 0.0);
+        hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, psi, beta, F, A);
+    } else if (which == 1) {
+        TraceScope ts(st, "pipe_b_iqft_ry_qft", 2.0 * half, 0.0);
+        hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, psi, A, part);
+    } else {
+        TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
+        hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, (const cvec<R> *)psi, F, A, zpart);
+    }
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+template <typename R, int RA, int RB>
+static sv_status launch_nt(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
+                           const PipeArgs &A, double *part, double2 *zpart, int g, int nt, dim3 grid, size_t lds) {
+    if (nt == 512) return launch_pipe<R, RA, RB, 512>(which, st, psi, beta, F, A, part, zpart, g, grid, lds);
+    return launch_pipe<R, RA, RB, 256>(which, st, psi, beta, F, A, part, zpart, g, grid, lds);
+}
+
+template <typename R>
+static sv_status dispatch_g(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
+                            const PipeArgs &A, double *part, double2 *zpart, int g, int nt, dim3 grid, size_t lds) {
+    switch (g) {
+    case 1: return launch_nt<R, 1, 0>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 2: return launch_nt<R, 1, 1>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 3: return launch_nt<R, 2, 1>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 4: return launch_nt<R, 2, 2>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 5: return launch_nt<R, 3, 2>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 6: return launch_nt<R, 3, 3>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 7: return launch_nt<R, 4, 3>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 8: return launch_nt<R, 4, 4>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    }
+    return fail(SV_EUNSUPPORTED, "clock group of %d bits", g);
+}
+
+int pipe_supported(int n_s, int n_c) { return n_c >= 2 && n_c <= 16 && n_s >= 0; }
+
+static const int PIPE_LDS_LIMIT = 144 * 1024;
+
+// columns per tile for a group of g bits by default (tile of at most 2^13
+// c64 / 2^12 c128 amplitudes)
+static int default_cl(int n_s, int g, size_t elem) {
+    const int tile_log = elem == 8 ? 13 : 12;
+    int cl = tile_log - g;
+    if (cl > 6) cl = 6;
+    if (cl > n_s) cl = n_s;
+    if (cl < 0) cl = 0;
+    return cl;
+}
+
+static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
+    const size_t C = (size_t)1 << cl;
+    size_t b = ((C << g) + ((size_t)1 << g)) * e;
+    if (which != 1) b += (size_t)(g + 1) * C * e;
+    if (which == 1) b += ((size_t)1 << g) * (2 * sizeof(double) + e / 2);
+    if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
+    return b;
+}
+
+struct PipePlan {
+    PipeArgs A[3];
+    int nt[3];
+    dim3 grid[3];
+    size_t lds[3];
+};
+
+static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], const int nt[3]) {
+    PipeArgs A;
+    A.N = dim_of(n_s);
+    A.n_s = n_s;
+    A.n_c = n_c;
+    A.g1 = (n_c + 1) / 2;
+    A.g2 = n_c - A.g1;
+    A.abit = 1ull << (n_s + n_c);
+    A.scale = 1.0 / sqrt((double)(1ull << n_c));
+    for (int w = 0; w < 3; ++w) {
+        const int g = w == 1 ? A.g2 : A.g1;
+        P.A[w] = A;
+        P.A[w].cl = cl[w];
+        P.nt[w] = nt[w];
+        const uint64_t tiles = (A.N >> cl[w]) << (n_c - g);
+        P.grid[w] = tiles <= 0x7fffffffull ? dim3((unsigned)tiles) : dim3(1u << 30, (unsigned)(tiles >> 30));
+        P.lds[w] = pipe_lds(w, cl[w], g, e, nt[w]);
+    }
+}
+
+template <typename R>
+static sv_status run_one(sv_state s, const PipePlan &P, int w, const double2 *beta, const uint64_t *F, double *part,
+                         double2 *zpart) {
+    const int g = w == 1 ? P.A[w].g2 : P.A[w].g1;
+    return dispatch_g<R>(w, s->stream, (cvec<R> *)s->data, beta, F, P.A[w], part, zpart, g, P.nt[w], P.grid[w],
+                         P.lds[w]);
+}
+
+// The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
+// tile, threads per workgroup) for each of the three kernels on the real
+// operands (each kernel is idempotent given its input half) and keep the
+// fastest; results live in the process-wide tuning cache.
+template <typename R>
+static sv_status tune_pipe(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
+                           double2 *zpart, int cl_out[3], int nt_out[3]) {
+    const size_t e = sizeof(cvec<R>);
+    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
+    for (int w = 0; w < 3; ++w) {
+        cl_out[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
+        nt_out[w] = 256;
+    }
+    for (int w = 0; w < 3; ++w) {
+        const int g = w == 1 ? g2 : g1;
+        float best = 1e30f;
+        int bcl = cl_out[w], bnt = nt_out[w];
+        for (int cl = 3; cl <= 6; ++cl) {
+            if (cl > n_s) break;
+            for (int nt : {256, 512}) {
+                if (pipe_lds(w, cl, g, e, nt) > (size_t)PIPE_LDS_LIMIT) continue;
+                int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
+                cls[w] = cl;
+                nts[w] = nt;
+                PipePlan P;
+                make_plan(P, n_s, n_c, e, cls, nts);
+                float ms = 0.f;
+                SV_TRY(time_stream(s->stream, 2, &ms, [&]() { return run_one<R>(s, P, w, beta, F, part, zpart); }));
+                if (ms < best) {
+                    best = ms;
+                    bcl = cl;
+                    bnt = nt;
+                }
+            }
+        }
+        cl_out[w] = bcl;
+        nt_out[w] = bnt;
+        // the next kernel reads what this one writes: leave its output in place
+        int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
+        PipePlan P;
+        make_plan(P, n_s, n_c, e, cls, nts);
+        SV_TRY(run_one<R>(s, P, w, beta, F, part, zpart));
+    }
+    return SV_OK;
+}
+
+template <typename R>
+sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
+                   double2 *zpart, uint64_t *nparts) {
+    const size_t e = sizeof(cvec<R>);
+    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
+    int cl[3], nt[3];
+    const std::string key = std::string("eigpipe/") + (e == 8 ? "c64/" : "c128/") + std::to_string(n_s) + "/" +
+                            std::to_string(n_c);
+    std::vector<int> cached;
+    if (tune_lookup(key, cached) && cached.size() == 6) {
+        for (int w = 0; w < 3; ++w) {
+            cl[w] = cached[2 * w];
+            nt[w] = cached[2 * w + 1];
+        }
+    } else if (autotune_enabled()) {
+        SV_TRY(tune_pipe<R>(s, n_s, n_c, beta, F, part, zpart, cl, nt));
+        tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
+    } else {
+        for (int w = 0; w < 3; ++w) {
+            cl[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
+            nt[w] = 256;
+        }
+    }
+    PipePlan P;
+    make_plan(P, n_s, n_c, e, cl, nt);
+    *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
+    for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s, P, w, beta, F, part, zpart));
+    return SV_OK;
+}
+template sv_status pipe_run<float>(sv_state, int, int, const double2 *, const uint64_t *, double *, double2 *,
+                                   uint64_t *);
+template sv_status pipe_run<double>(sv_state, int, int, const double2 *, const uint64_t *, double *, double2 *,
+                                    uint64_t *);
+
+// upper bounds of the k_pipe_b block count (one FP64 partial pair each) and
+// the k_pipe_c partial rows, over every configuration the tuner may pick
+uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem) {
+    const int g1 = (n_c + 1) / 2;
+    (void)elem;
+    const int cl = n_s < 3 ? n_s : 3;
+    return (dim_of(n_s) >> cl) << g1;
+}
+int pipe_c_rows(int n_c) { return 1 << (n_c - (n_c + 1) / 2); }
+
+}  // namespace sv

@@ -199,11 +199,17 @@ static int lds_limit_bytes() {
     int lim = 65536;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
         lim = (int)prop.sharedMemPerBlock;
-    if (lim > 163840) lim = 163840;
-    hipFuncSetAttribute((const void *)k_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_qft_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_qft_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (lim > 147456) lim = 147456;   // the largest power-of-two tile (128 KiB) plus headroom
+    bool ok = hipFuncSetAttribute((const void *)k_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
+              hipSuccess;
+    ok &= hipFuncSetAttribute((const void *)k_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
+          hipSuccess;
+    ok &= hipFuncSetAttribute((const void *)k_qft_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
+          hipSuccess;
+    ok &= hipFuncSetAttribute((const void *)k_qft_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
+          hipSuccess;
+    (void)hipGetLastError();
+    if (!ok) lim = 65536;
     g_lds_limit = lim;
     return lim;
 }

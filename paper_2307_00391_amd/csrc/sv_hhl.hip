@@ -44,6 +44,12 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
                 uint64_t row_mask, uint64_t row_fix, int trans, int conjb);
 template <typename R>
 sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
+template <typename R>
+sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
+                   double2 *zpart, uint64_t *nparts);
+int pipe_supported(int n_s, int n_c);
+uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem);
+int pipe_c_rows(int n_c);
 
 // --------------------------------------------------------------------------
 // small FP64 kernels
@@ -106,6 +112,23 @@ __global__ void k_axis_transform(double2 *__restrict__ out, const double2 *__res
             im += v.x * x.y + v.y * x.x;
         }
         out[i] = make_double2(re, im);
+    }
+}
+
+// F[j][k] = frac(phi_j 2^k) as a 64-bit fraction of a turn, phi_j = lam_j T0 / 2 pi:
+// the same IEEE operations as the host-side table (product, quotient, exact
+// scaling by 2^k, exact floor), so both give the same bits
+__global__ void k_turn_table(uint64_t *__restrict__ F, const double *__restrict__ lam, double T0, int n_c,
+                             uint64_t N) {
+    const uint64_t total = N * (uint64_t)n_c;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = i / n_c;
+        const int k = (int)(i % n_c);
+        const double phi = lam[j] * T0 / (2.0 * M_PI);
+        const double x = ldexp(phi, k);
+        const double f = x - floor(x);
+        const double sc = ldexp(f, 64);
+        F[i] = sc >= 18446744073709551616.0 ? 0ull : (uint64_t)sc;
     }
 }
 
@@ -477,24 +500,21 @@ static int pick_log_len(uint64_t N, int n_c) {
 
 // device workspaces of a plan, grown on demand and reused by every solve
 struct Workspace {
-    DevBuf F, cs, beta, tmp, z, x, part, zpart, sum, E, W, U64, Uk;
+    DevBuf F, cs, beta, tmp, tmp2, z, x, part, zpart, sum, E, W, U64, Uk;
 };
 
 static sv_status need(DevBuf &b, size_t bytes) { return b.ensure(bytes); }
+static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
+                            double *x_out);
 
 template <typename R>
 static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c,
-                               double T0, sv_hhl_result *res, double *x_out) {
+                               double T0, bool fused, sv_hhl_result *res, double *x_out) {
     const int n_s = E.n_s;
     const uint64_t N = dim_of(n_s);
     const int anc = n_s + n_c;
     const uint64_t abit = 1ull << anc;
     const hipStream_t st = s->stream;
-
-    std::vector<uint64_t> F;
-    turn_table(E.lam, T0, n_c, F);
-    std::vector<double> cs;
-    inversion_table(n_c, cs);
 
     const int L = pick_log_len(N, n_c);
     if (((1ull << n_c) >> L) < 4) return fail(SV_EUNSUPPORTED, "eigen-frame mode needs n_c >= 2");
@@ -504,8 +524,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     if (nb > 4096) nb = 4096;
     const uint64_t chunk = (half + nb - 1) / nb;
 
-    SV_TRY(need(w.F, F.size() * sizeof(uint64_t)));
-    SV_TRY(need(w.cs, cs.size() * sizeof(double)));
+    SV_TRY(need(w.F, N * n_c * sizeof(uint64_t)));
     SV_TRY(need(w.beta, N * sizeof(double2)));
     SV_TRY(need(w.tmp, N * sizeof(double2)));
     SV_TRY(need(w.z, N * sizeof(double2)));
@@ -513,13 +532,40 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     SV_TRY(need(w.part, 2 * nb * sizeof(double)));
     SV_TRY(need(w.zpart, (size_t)g2.y * 4 * N * sizeof(double2)));
     SV_TRY(need(w.sum, 4 * sizeof(double)));
-    SV_TRY(upload(s, w.F.p, F.data(), F.size() * sizeof(uint64_t)));
-    SV_TRY(upload(s, w.cs.p, cs.data(), cs.size() * sizeof(double)));
+    hipLaunchKernelGGL(k_turn_table, dim3(grid1(N * n_c)), dim3(256), 0, st, (uint64_t *)w.F.p,
+                       (const double *)E.lam_dev.p, T0, n_c, N);
+    SV_HIP(hipGetLastError());
     SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
     // beta = V^H b^
     SV_TRY(kron_apply(st, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
                       E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 1));
 
+    if (fused && pipe_supported(n_s, n_c)) {
+        // fused three-kernel pipeline: (state + inverse QFT on the low clock bits),
+        // (inverse QFT high + rotation + QFT high), (QFT low + conj phases + projection)
+        const uint64_t nbp = pipe_b_blocks(n_s, n_c, sizeof(cvec<R>));
+        const int rows = pipe_c_rows(n_c);
+        SV_TRY(need(w.part, 2 * nbp * sizeof(double)));
+        SV_TRY(need(w.zpart, (size_t)rows * N * sizeof(double2)));
+        uint64_t nparts = 0;
+        SV_TRY(pipe_run<R>(s, n_s, n_c, (const double2 *)w.beta.p, (const uint64_t *)w.F.p, (double *)w.part.p,
+                           (double2 *)w.zpart.p, &nparts));
+        if (nparts > nbp) return fail(SV_EDEVICE, "pipeline partial count exceeds its buffer");
+        SV_TRY(need(w.tmp2, 512 * sizeof(double)));
+        sum_partials(st, (const double *)w.part.p, nparts, 2, (double *)w.tmp2.p, (double *)w.sum.p);
+        sum_partials(st, (const double *)w.part.p + 1, nparts, 2, (double *)w.tmp2.p + 256, (double *)w.sum.p + 1);
+        // 2^(-n_c/2) of the final Hadamard layer, and 2^(-g1/2) the fused forward
+        // transform on the low clock group leaves out of its butterflies
+        const int g1 = (n_c + 1) / 2;
+        hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.z.p,
+                           (const double2 *)w.zpart.p, N, rows, exp2(-0.5 * (n_c + g1)));
+        SV_HIP(hipGetLastError());
+        return eig_finish(s, E, w, N, res, x_out);
+    }
+    std::vector<double> cs;
+    inversion_table(n_c, cs);
+    SV_TRY(need(w.cs, cs.size() * sizeof(double)));
+    SV_TRY(upload(s, w.cs.p, cs.data(), cs.size() * sizeof(double)));
     // 1. the state after phase estimation, written directly (ancilla = 0 half)
     {
         TraceScope _ts(st, "eig_init", (double)half * sizeof(cvec<R>), 0.0);
@@ -551,7 +597,13 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.z.p, (const double2 *)w.zpart.p, N,
                        (int)(g2.y * 4), 1.0 / sqrt((double)(1ull << n_c)));
     SV_HIP(hipGetLastError());
-    // 6. back to the computational basis: x = V z
+    return eig_finish(s, E, w, N, res, x_out);
+}
+
+// x = V z on the device, then P(a=1, clock=0) = |z|^2 and the normalised x on the host
+static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
+                            double *x_out) {
+    const hipStream_t st = s->stream;
     SV_TRY(kron_apply(st, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
                       E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 0));
     std::vector<double> sums(2), xz(2 * N);
@@ -638,7 +690,7 @@ static sv_status check_params(sv_state s, const sv_hhl_params *prm, sv_hhl_resul
     if (prm->n_s < 1 || prm->n_c < 1 || prm->n_s + prm->n_c + 1 != s->n)
         return fail(SV_EINVAL, "n_s %d + n_c %d + 1 != %d qubits", prm->n_s, prm->n_c, s->n);
     if (!(prm->T0 > 0.0) || !isfinite(prm->T0)) return fail(SV_EINVAL, "T0 must be positive");
-    if (prm->mode != 0 && prm->mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    if (prm->mode < 0 || prm->mode > 2) return fail(SV_EINVAL, "mode must be 0, 1 or 2");
     if (prm->n_c > EIG_MAXC) return fail(SV_EUNSUPPORTED, "n_c %d > %d", prm->n_c, EIG_MAXC);
     return SV_OK;
 }
@@ -691,6 +743,8 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
                 for (int q = 0; q < nl; ++q) p->E.lam[(size_t)a * nl + q] = mu[a] + nu[q];
         }
     }
+    if (st == SV_OK) st = p->E.lam_dev.alloc(p->E.lam.size() * sizeof(double));
+    if (st == SV_OK) st = upload(s, p->E.lam_dev.p, p->E.lam.data(), p->E.lam.size() * sizeof(double));
     if (st != SV_OK) {
         delete p;
         return st;
@@ -724,9 +778,11 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
     SV_TRY(normalise_b(b, N, bhat));
     SV_TRY(sv_hhl_plan_spectrum(p, &res->lambda_min, &res->lambda_max));
     if (!(res->lambda_min > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
-    if (prm->mode == 1)
-        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, prm->T0, res, x_out)
-                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, prm->T0, res, x_out);
+    if (prm->mode >= 1) {
+        const bool fused = prm->mode == 1;
+        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, prm->T0, fused, res, x_out)
+                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, prm->T0, fused, res, x_out);
+    }
     // gate-faithful: dense eigenvectors
     if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
     const double2 *dV = (const double2 *)p->E.V_hi.p;

@@ -26,6 +26,7 @@ struct DevBuf {
 struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;
     DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
+    DevBuf lam_dev;               // the eigenvalues on the device (FP64)
     std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
 };
 
@@ -48,6 +49,33 @@ static __global__ __launch_bounds__(256) void k_sum_partials_strided(const doubl
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) out[0] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// first level of a two-level fixed-order sum: block b sums the strided
+// entries [b*chunk, (b+1)*chunk) of `part` into tmp[b]
+static __global__ __launch_bounds__(256) void k_sum_chunks(const double *__restrict__ part, uint64_t count,
+                                                           int stride, uint64_t chunk, double *__restrict__ tmp) {
+    __shared__ double ws[4];
+    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = beg + chunk < count ? beg + chunk : count;
+    double acc = 0.0;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) acc += part[i * stride];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) tmp[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// out[0] = sum of count strided partials, fixed order; tmp holds >= 256 doubles
+static inline void sum_partials(hipStream_t st, const double *part, uint64_t count, int stride, double *tmp,
+                                double *out) {
+    uint64_t nb = (count + 4095) / 4096;
+    if (nb > 256) nb = 256;
+    if (nb < 1) nb = 1;
+    const uint64_t chunk = (count + nb - 1) / nb;
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)nb), dim3(256), 0, st, part, count, stride, chunk, tmp);
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)tmp, (int)nb, 1, out);
 }
 
 }  // namespace sv

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -77,6 +78,11 @@ sv_status run_hadamards(sv_state s, int lo, int m, uint64_t fix_mask, uint64_t f
 
 // ---- tuning (sv_tune.cpp) ---------------------------------------------------
 int default_max_local(sv_dtype dt);
+bool autotune_enabled();
+bool tune_lookup(const std::string &key, std::vector<int> &out);
+void tune_store(const std::string &key, const std::vector<int> &v);
+// mean duration of fn() over `reps` runs on stream st (after one warm-up run)
+sv_status time_stream(hipStream_t st, int reps, float *ms_out, const std::function<sv_status()> &fn);
 
 // ---- per-kernel tracing (sv_trace.cpp) ------------------------------------
 bool trace_on();

@@ -33,8 +33,8 @@ def _free_mem():
     return torch.cuda.mem_get_info()[0]
 
 
-@pytest.mark.parametrize("dt,tol", [("c64", 1e-5), ("c128", 1e-12)])
-def test_hhl_32_qubits_against_closed_form(dt, tol):
+@pytest.mark.parametrize("dt,tol,mode", [("c64", 1e-5, 1), ("c128", 1e-12, 1), ("c64", 1e-5, 2)])
+def test_hhl_32_qubits_against_closed_form(dt, tol, mode):
     m_hi = m_lo = 8
     n_c = 15
     n = m_hi + m_lo + n_c + 1
@@ -45,7 +45,7 @@ def test_hhl_32_qubits_against_closed_form(dt, tol):
     T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
     st = B.State(n, dt)
     plan = B.sv_hhl_prepare(st.h, ks.A_hi, ks.A_lo)
-    x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, 1)
+    x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, mode)
     B.sv_hhl_plan_free(plan)
     st.close()
     # eigen-basis view of the GPU result: z = V^H x sqrt(p)

@@ -77,7 +77,7 @@ def _run(A, b, n_c, T0, dt, mode):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_poiseuille_hhl(poiseuille_ref, dt, mode):
     s, n_c, T0, (psi_r, x_r, pp_r, pa_r) = poiseuille_ref
     st, x, res = _run(s.A, s.b, n_c, T0, dt, mode)
@@ -90,7 +90,7 @@ def test_poiseuille_hhl(poiseuille_ref, dt, mode):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_couette_hhl(couette_ref, dt, mode):
     s, n_c, T0, (psi_r, x_r, pp_r, pa_r) = couette_ref
     st, x, res = _run(s.A, s.b, n_c, T0, dt, mode)
@@ -113,7 +113,7 @@ def test_random_spd_hhl_both_modes(seed, n_s, n_c, kappa, dt):
     b = rng.standard_normal(1 << n_s)
     T0 = inputs.t0_grid(lmax)[seed % 16]
     psi_r, x_r, pp_r, pa_r = _hhl_case(A, b, n_c, T0)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         st, x, res = _run(A, b, n_c, T0, dt, mode)
         tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
         assert np.abs(x - x_r).max() <= tol, (mode, np.abs(x - x_r).max())
@@ -129,7 +129,7 @@ def test_complex_hermitian_hhl():
     b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
     T0 = inputs.t0_top_of_clock(np.linalg.eigvalsh(A)[-1], n_c)
     psi_r, x_r, pp_r, _ = _hhl_case(A, b, n_c, T0)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         st, x, res = _run(A, b, n_c, T0, "c128", mode)
         assert np.abs(x - x_r).max() <= 1e-12
         assert abs(res.p_post - pp_r) <= 1e-12
@@ -145,7 +145,7 @@ def test_kron_hhl_matches_dense_oracle(dt):
     A = ks.dense()
     T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
     psi_r, x_r, pp_r, pa_r = _hhl_case(A, ks.b, n_c, T0)
-    for mode in (1, 0):
+    for mode in (1, 2, 0):
         st = B.State(6 + n_c + 1, dt)
         x, res = B.sv_hhl_kron(st.h, ks.A_hi, ks.A_lo, ks.b, n_c, T0, mode)
         tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
@@ -165,17 +165,37 @@ def test_plan_reuse_matches_single_calls():
     for T0 in inputs.t0_grid(lmax)[::5]:
         b = rng.standard_normal(32)
         _, x_r, pp_r, _ = oracle.hhl(A, b, 7, T0)
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             x, res = B.sv_hhl_run(plan, st.h, b, 7, T0, mode)
             assert np.abs(x - x_r).max() <= 1e-12
             assert abs(res.p_post - pp_r) <= 1e-12
     B.sv_hhl_plan_free(plan)
 
 
+@pytest.mark.parametrize("n_s,n_c", [(1, 2), (2, 3), (4, 16), (7, 11), (9, 4)])
+def test_fused_pipeline_shapes(n_s, n_c):
+    """Edge shapes of the fused eigen-frame kernels (tiny column counts,
+    odd clock groups, the largest n_c the pipeline takes) against the oracle."""
+    rng = np.random.default_rng(100 + n_s * 17 + n_c)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, 60.0) if n_s > 1 else (np.diag([1.0, 3.0]), 1.0, 3.0)
+    b = rng.standard_normal(1 << n_s)
+    T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.77
+    if n_c > 11:
+        from tests.closed_form import hhl_closed_form
+        x_r, pp_r = hhl_closed_form(A, b, n_c, T0)
+    else:
+        _, x_r, pp_r, _ = _hhl_case(A, b, n_c, T0)
+    for dt in ("c128", "c64"):
+        st, x, res = _run(A, b, n_c, T0, dt, 1)
+        tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
+        assert np.abs(x - x_r).max() <= tol, (dt, np.abs(x - x_r).max())
+        assert abs(res.p_post - pp_r) <= TOL[dt]
+
+
 def test_hhl_repeatable_bit_for_bit():
     s = inputs.poiseuille(16)
     T0 = inputs.t0_top_of_clock(s.lambda_max, 6)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         _, x1, r1 = _run(s.A, s.b, 6, T0, "c64", mode)
         _, x2, r2 = _run(s.A, s.b, 6, T0, "c64", mode)
         assert np.array_equal(x1, x2) and r1.p_post == r2.p_post
