@@ -298,6 +298,86 @@ int sv_tune_report(char *buf, int len);
  * real symmetric A goes to the real routines).  "" before the first call. */
 const char *sv_last_eigensolver(void);
 
+/* ------------------------------------------------------------------------
+ * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
+ * study of Fig. 4b): many HHL instances of uneven size, each over its own
+ * list of T0 values, solved in the fused eigen-frame mode with one launch per
+ * kernel and shape class, recorded once as a hipGraph and replayed.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    int n_s, n_c;          /* 1 <= n_s <= 13, 2 <= n_c <= 16, n_s + n_c + 1 <= 32 */
+    const double *A;       /* host, 2^n_s x 2^n_s complex FP64 row-major, Hermitian positive definite */
+    const double *b;       /* host, 2^n_s complex FP64 */
+    int n_t0;              /* number of T0 values (>= 1) */
+    const double *t0;      /* host, n_t0 values > 0 */
+} sv_batch_instance;
+
+typedef struct sv_batch_s *sv_batch;
+
+/* Classical preprocessing for every instance (FP64 eigen-decomposition,
+ * beta = V^H b^, the eigen-coefficients of the exact solution A^{-1} b),
+ * device buffers for every (instance, T0) state, launch configurations per
+ * shape class (autotuned on first use), and the captured graph.  All inputs
+ * are copied; the caller's arrays may be freed on return.  hip_stream NULL:
+ * the batch creates and owns a stream.  Errors: SV_EINVAL, SV_EUNSUPPORTED,
+ * SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM, SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const sv_batch_instance *inst,
+                           int n_inst);
+
+/* Run every solve of the batch (use_graph != 0: replay the graph; 0: the same
+ * launches eagerly).  results (may be NULL): host, 4 doubles per solve in
+ * instance-major, T0-minor order: P(a=1, clock=0), P(a=1), the norm after the
+ * rotation, and the fidelity |<x_C|x_Q>| against x_C = A^{-1} b / |A^{-1} b|,
+ * all accumulated in FP64.  Synchronises the batch's stream. */
+sv_status sv_batch_run(sv_batch b, int use_graph, double *results);
+int sv_batch_num_solves(sv_batch b);
+sv_status sv_batch_free(sv_batch b);
+
+/* prepare + one graph replay + free */
+sv_status sv_hhl_batch(sv_dtype dt, void *hip_stream, const sv_batch_instance *inst, int n_inst,
+                       double *results);
+
+/* ------------------------------------------------------------------------
+ * Learned T0: a 5 -> 64 -> 64 -> 1 perceptron with exact (erf) GELU
+ * activations in FP32 whose input is the spectrum features of an instance and
+ * whose output predicts log(T0 lambda_max / 2 pi) (the "QPE optimizer" of the
+ * main text, which estimates T0* from kappa, generalised to several cheap
+ * features).  Parameter layout (SV_MLP_PARAMS floats): W1[64][5], b1[64],
+ * W2[64][64], b2[64], W3[64], b3.  All pointers are device pointers;
+ * calls run on hip_stream (NULL = null stream).
+ * --------------------------------------------------------------------- */
+#define SV_MLP_IN 5
+#define SV_MLP_HIDDEN 64
+#define SV_MLP_PARAMS 4609
+
+/* y[i] = net(X[i, 0..5)) for i < B (B = 0: nothing, X and y may be NULL).
+ * Errors: SV_EINVAL. */
+sv_status sv_mlp_forward(const float *params, const float *X, int B, float *y, void *hip_stream);
+
+/* Gradient of the mean squared error L = mean_i (net(X_i) - t_i)^2 with
+ * respect to the parameters (grad, SV_MLP_PARAMS floats, overwritten) and L
+ * itself (loss, 1 float).  Per-block partial gradients are summed in a fixed
+ * order (repeatable bit for bit). */
+sv_status sv_mlp_backward(const float *params, const float *X, const float *t, int B, float *grad, float *loss,
+                          void *hip_stream);
+
+/* One Adam step (step >= 1 is the 1-based step count used for bias
+ * correction) on n parameters with first/second moment buffers m, v. */
+sv_status sv_mlp_adam(float *params, float *m, float *v, const float *grad, int n, int step, float lr,
+                      float beta1, float beta2, float eps, void *hip_stream);
+
+/* Extreme eigenvalues of a Hermitian matrix (host, complex FP64 row-major,
+ * 1 <= N <= 8192) by Lanczos iteration on the GPU: a seeded start vector
+ * (xorshift64* stream, uniform entries), min(iters, N) steps with full
+ * reorthogonalisation (two classical Gram-Schmidt passes per step), then
+ * Sturm-sequence bisection of the Lanczos tridiagonal matrix on the host.
+ * These are the cheap spectrum features of the learned T0; the paper bounds
+ * the same two quantities from the trace (Wolkowicz-Styan, Sec. 3.2).
+ * Runs on hip_stream (NULL = null stream) and synchronises it.  Errors:
+ * SV_EINVAL, SV_ENOTHERMITIAN, SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, double *lambda_min,
+                              double *lambda_max, void *hip_stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char *sv_last_error(void);
 

@@ -47,6 +47,13 @@ class sv_hhl_result(ctypes.Structure):
                 ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
 
 
+class sv_batch_instance(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int), ("n_c", ctypes.c_int), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("n_t0", ctypes.c_int), ("t0", ctypes.c_void_p)]
+
+
+SV_MLP_IN, SV_MLP_HIDDEN, SV_MLP_PARAMS = 5, 64, 4609
+
 _lib = None
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -83,6 +90,16 @@ _SIGS = {
     "sv_hhl_plan_spectrum": ([_P, _DP, _DP], _I),
     "sv_hhl_plan_free": ([_P], _I),
     "sv_last_eigensolver": ([], ctypes.c_char_p),
+    "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
+    "sv_batch_run": ([_P, _I, _P], _I),
+    "sv_batch_num_solves": ([_P], _I),
+    "sv_batch_free": ([_P], _I),
+    "sv_hhl_batch": ([_I, _P, ctypes.POINTER(sv_batch_instance), _I, _P], _I),
+    "sv_mlp_forward": ([_P, _P, _I, _P, _P], _I),
+    "sv_mlp_backward": ([_P, _P, _P, _I, _P, _P, _P], _I),
+    "sv_mlp_adam": ([_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
+                    _I),
+    "sv_spectrum_lanczos": ([_P, _I, _I, _U64, _DP, _DP, _P], _I),
     "sv_trace_enable": ([_I], _I),
     "sv_tune_report": ([ctypes.c_char_p, _I], _I),
     "sv_trace_report": ([ctypes.c_char_p, _I], _I),
@@ -370,6 +387,120 @@ def sv_hhl_plan_free(plan):
 
 def sv_version():
     return lib().sv_version().decode()
+
+
+# --------------------------------------------------------------------------
+# batched T0 sweeps
+# --------------------------------------------------------------------------
+
+def _dtype_code(dtype):
+    return SV_C64 if dtype in ("c64", SV_C64) else SV_C128
+
+
+def _batch_instances(instances):
+    """instances: iterable of (A, b, n_c, t0_list).  Returns the ctypes array
+    and the host arrays it points into (kept alive by the caller)."""
+    keep, arr = [], (sv_batch_instance * max(1, len(instances)))()
+    for i, (A, b, n_c, t0) in enumerate(instances):
+        A, Af = _f64(A)
+        b, bf = _f64(b)
+        t0 = np.ascontiguousarray(np.atleast_1d(np.asarray(t0, dtype=np.float64)))
+        keep += [A, Af, b, bf, t0]
+        n_s = b.size.bit_length() - 1
+        arr[i] = sv_batch_instance(n_s, int(n_c), Af.ctypes.data, bf.ctypes.data, t0.size, t0.ctypes.data)
+    return arr, keep
+
+
+def sv_batch_prepare(instances, dtype="c64", stream=None):
+    arr, keep = _batch_instances(instances)
+    h = ctypes.c_void_p()
+    _check(lib().sv_batch_prepare(ctypes.byref(h), _dtype_code(dtype), stream, arr, len(instances)),
+           "sv_batch_prepare")
+    del keep
+    return h
+
+
+def sv_batch_num_solves(b):
+    return int(lib().sv_batch_num_solves(b))
+
+
+def sv_batch_run(b, use_graph=True, want_results=True):
+    """-> (n_solves, 4) array of [p_post, p_anc, norm_total, fidelity] or None"""
+    out = np.zeros((sv_batch_num_solves(b), 4)) if want_results else None
+    _check(lib().sv_batch_run(b, int(bool(use_graph)), _ptr(out)), "sv_batch_run")
+    return out
+
+
+def sv_batch_free(b):
+    _check(lib().sv_batch_free(b), "sv_batch_free")
+
+
+def sv_hhl_batch(instances, dtype="c64", stream=None):
+    arr, keep = _batch_instances(instances)
+    out = np.zeros((sum(np.atleast_1d(t).size for *_, t in instances), 4))
+    _check(lib().sv_hhl_batch(_dtype_code(dtype), stream, arr, len(instances), _ptr(out)), "sv_hhl_batch")
+    del keep
+    return out
+
+
+# --------------------------------------------------------------------------
+# learned-T0 perceptron (device tensors, float32)
+# --------------------------------------------------------------------------
+
+def _stream_ptr(stream):
+    if stream is None:
+        return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(t, n=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sv_mlp_forward(params, X, y=None, stream=None):
+    torch = _torch()
+    B = X.shape[0]
+    if X.shape[1:] != (SV_MLP_IN,):
+        raise ValueError("X must be (B, 5)")
+    if y is None:
+        y = torch.empty(B, dtype=torch.float32, device=X.device)
+    _check(lib().sv_mlp_forward(_dev_f32(params, SV_MLP_PARAMS), _dev_f32(X), B, _dev_f32(y, B),
+                                _stream_ptr(stream)), "sv_mlp_forward")
+    return y
+
+
+def sv_mlp_backward(params, X, t, grad=None, loss=None, stream=None):
+    torch = _torch()
+    B = X.shape[0]
+    if X.shape[1:] != (SV_MLP_IN,):
+        raise ValueError("X must be (B, 5)")
+    if grad is None:
+        grad = torch.empty(SV_MLP_PARAMS, dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().sv_mlp_backward(_dev_f32(params, SV_MLP_PARAMS), _dev_f32(X), _dev_f32(t, B), B,
+                                 _dev_f32(grad, SV_MLP_PARAMS), _dev_f32(loss, 1), _stream_ptr(stream)),
+           "sv_mlp_backward")
+    return grad, loss
+
+
+def sv_mlp_adam(params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = params.numel()
+    _check(lib().sv_mlp_adam(_dev_f32(params), _dev_f32(m, n), _dev_f32(v, n), _dev_f32(grad, n), n, int(step),
+                             lr, beta1, beta2, eps, _stream_ptr(stream)), "sv_mlp_adam")
+
+
+def sv_spectrum_lanczos(A, iters=96, seed=0, stream=None):
+    A, Af = _f64(A)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sv_spectrum_lanczos(_ptr(Af), A.shape[0], int(iters), int(seed), ctypes.byref(lo),
+                                     ctypes.byref(hi), _stream_ptr(stream)), "sv_spectrum_lanczos")
+    return lo.value, hi.value
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,412 @@
+// Batched T0 sweep: many HHL instances of uneven size (each with its own
+// grid of T0 values) solved by the fused eigen-frame kernels with one launch
+// per kernel and shape class, recorded once as a hipGraph and replayed.
+//
+// Per instance (classical preprocessing, once): FP64 eigen-decomposition,
+// beta = V^H b^, and the eigen-basis coefficients of the exact solution
+// A^{-1} b (beta_j / lambda_j, normalised) for the fidelity.
+// Per solve (instance, T0), inside the graph:
+//   turn tables (all solves, one kernel)
+//   -> per (n_s, n_c) class: the three pipeline kernels, blockIdx.z = solve
+//   -> one finishing kernel (all solves): FP64 sums of P(a=1) and the norm,
+//      the post-selected eigen-coefficients z_j (column sums of the clock
+//      projection), p_post = |z|^2 and F = |<x_C|x_Q>| = |sum conj(c_j) z_j| / |z|,
+//      all in FP64, fixed summation order.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "sv_device.h"
+#include "sv_hhl_internal.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+struct TurnJob {
+    const double *lam;
+    uint64_t *F;
+    double T0;
+    int n_c;
+    uint64_t N;
+};
+
+// all turn tables of the batch: blockIdx.y = solve
+__global__ void k_turn_batch(const TurnJob *__restrict__ jobs) {
+    const TurnJob J = jobs[blockIdx.y];
+    const uint64_t total = J.N * (uint64_t)J.n_c;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = i / J.n_c;
+        const int k = (int)(i % J.n_c);
+        const double phi = J.lam[j] * J.T0 / (2.0 * M_PI);
+        const double x = ldexp(phi, k);
+        const double f = x - floor(x);
+        const double sc = ldexp(f, 64);
+        J.F[i] = sc >= 18446744073709551616.0 ? 0ull : (uint64_t)sc;
+    }
+}
+
+struct FinishJob {
+    const double *part;     // k_pipe_b partials, 2 per block
+    uint64_t nparts;
+    const double2 *zpart;   // [rows][N]
+    int rows;
+    uint64_t N;
+    double scale;           // 2^(-(n_c + g1)/2)
+    const double2 *cexact;  // normalised eigen-coefficients of A^{-1} b
+    double *out;            // p_post, p_anc, norm_total, fidelity
+};
+
+__device__ __forceinline__ double block_sum(double v, double *ws) {
+    v = wave_sum_f64(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// one block (256 threads) per solve
+__global__ __launch_bounds__(256) void k_batch_finish(const FinishJob *__restrict__ jobs) {
+    __shared__ double ws[4];
+    const FinishJob J = jobs[blockIdx.x];
+    double pa = 0.0, nt = 0.0, pp = 0.0, orr = 0.0, oi = 0.0;
+    for (uint64_t i = threadIdx.x; i < J.nparts; i += blockDim.x) {
+        pa += J.part[2 * i];
+        nt += J.part[2 * i + 1];
+    }
+    for (uint64_t j = threadIdx.x; j < J.N; j += blockDim.x) {
+        double zr = 0.0, zi = 0.0;
+        for (int r = 0; r < J.rows; ++r) {
+            const double2 v = J.zpart[(uint64_t)r * J.N + j];
+            zr += v.x;
+            zi += v.y;
+        }
+        zr *= J.scale;
+        zi *= J.scale;
+        pp += zr * zr + zi * zi;
+        const double2 c = J.cexact[j];
+        orr += c.x * zr + c.y * zi;      // conj(c) z
+        oi += c.x * zi - c.y * zr;
+    }
+    pa = block_sum(pa, ws);
+    nt = block_sum(nt, ws);
+    pp = block_sum(pp, ws);
+    orr = block_sum(orr, ws);
+    oi = block_sum(oi, ws);
+    if (threadIdx.x == 0) {
+        J.out[0] = pp;
+        J.out[1] = pa;
+        J.out[2] = nt;
+        J.out[3] = pp > 0.0 ? sqrt(orr * orr + oi * oi) / sqrt(pp) : 0.0;
+    }
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+struct sv_batch_s {
+    sv_dtype dt = SV_C64;
+    hipStream_t stream = nullptr;
+    sv_state_s ctx;                       // staging buffers for uploads (no amplitudes)
+    int n_solves = 0;
+    std::vector<DevBuf *> bufs;           // every device allocation of the batch
+    DevBuf *arena = nullptr;              // states, tables, partials
+    DevBuf *desc = nullptr;               // descriptor arrays
+    const TurnJob *d_turn = nullptr;
+    const FinishJob *d_finish = nullptr;
+    double *d_out = nullptr;
+    struct Class {
+        int n_s, n_c, cl[3], nt[3];
+        const PipeSolve *d_solves;
+        int count;
+        uint64_t nparts;      // k_pipe_b partial pairs per solve, as laid out for the finish
+    };
+    std::vector<Class> classes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t own_stream = nullptr;
+    ~sv_batch_s() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (own_stream) hipStreamDestroy(own_stream);
+        for (auto *b : bufs) delete b;
+        if (ctx.pinned) hipHostFree(ctx.pinned);
+        if (ctx.small) hipFree(ctx.small);
+        if (ctx.scratch) hipFree(ctx.scratch);
+    }
+};
+
+namespace sv {
+
+template <typename R>
+static sv_status enqueue_batch(sv_batch b) {
+    const hipStream_t st = b->stream;
+    hipLaunchKernelGGL(k_turn_batch, dim3(64, b->n_solves), dim3(256), 0, st, b->d_turn);
+    SV_HIP(hipGetLastError());
+    for (auto &c : b->classes) {
+        uint64_t np = 0;
+        SV_TRY(pipe_run_batch<R>(st, c.n_s, c.n_c, c.cl, c.nt, c.d_solves, c.count, &np));
+        if (np != c.nparts) return fail(SV_EDEVICE, "partial count %llu != %llu", (unsigned long long)np,
+                                        (unsigned long long)c.nparts);
+    }
+    hipLaunchKernelGGL(k_batch_finish, dim3(b->n_solves), dim3(256), 0, st, b->d_finish);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+}  // namespace sv
+
+extern "C" {
+
+sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const sv_batch_instance *inst, int n_inst) {
+    clear_error();
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!inst || n_inst < 1) return fail(SV_EINVAL, "no instances");
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_EINVAL, "bad dtype");
+    const size_t e = amp_bytes(dt);
+    // validate
+    int total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const sv_batch_instance &I = inst[i];
+        if (!I.A || !I.b || !I.t0 || I.n_t0 < 1) return fail(SV_EINVAL, "instance %d: missing data", i);
+        if (I.n_s < 1 || I.n_s > 13 || !pipe_supported(I.n_s, I.n_c) || I.n_s + I.n_c + 1 > 32)
+            return fail(SV_EUNSUPPORTED, "instance %d: n_s %d, n_c %d outside the batched path", i, I.n_s, I.n_c);
+        for (int t = 0; t < I.n_t0; ++t)
+            if (!(I.t0[t] > 0.0) || !isfinite(I.t0[t])) return fail(SV_EINVAL, "instance %d: T0 must be > 0", i);
+        total += I.n_t0;
+    }
+    if (total > 65535) return fail(SV_EUNSUPPORTED, "more than 65535 solves in one batch");
+    sv_batch b = new sv_batch_s();
+    b->dt = dt;
+    b->stream = (hipStream_t)hip_stream;
+    if (!b->stream) {   // graphs are captured from a stream of our own, not the null stream
+        hipError_t he = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            delete b;
+            return hip_fail(he, "hipStreamCreateWithFlags");
+        }
+        b->stream = b->own_stream;
+    }
+    b->ctx.stream = b->stream;
+    b->ctx.dt = dt;
+    b->n_solves = total;
+    hipGetDevice(&b->ctx.device);
+    auto fail_del = [&](sv_status s) {
+        delete b;
+        return s;
+    };
+    // --- per instance: eigen-decomposition, beta, exact-solution coefficients
+    std::vector<DevBuf *> V(n_inst), lamd(n_inst), beta(n_inst), cex(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const sv_batch_instance &I = inst[i];
+        const int N = 1 << I.n_s;
+        sv_status st = check_hermitian(I.A, N, "A");
+        if (st != SV_OK) return fail_del(st);
+        V[i] = new DevBuf();
+        lamd[i] = new DevBuf();
+        beta[i] = new DevBuf();
+        cex[i] = new DevBuf();
+        b->bufs.push_back(V[i]);
+        b->bufs.push_back(lamd[i]);
+        b->bufs.push_back(beta[i]);
+        b->bufs.push_back(cex[i]);
+        std::vector<double> lam;
+        st = eigh_device(&b->ctx, I.A, N, *V[i], lam);
+        if (st != SV_OK) return fail_del(st);
+        if (!(lam[0] > 0.0)) return fail_del(fail(SV_ENOTPOSDEF, "instance %d: lambda_min <= 0", i));
+        double nb = 0.0;
+        for (int j = 0; j < 2 * N; ++j) nb += I.b[j] * I.b[j];
+        nb = sqrt(nb);
+        if (!(nb > 0.0)) return fail_del(fail(SV_EZERONORM, "instance %d: |b| = 0", i));
+        std::vector<double> bh(2 * (size_t)N);
+        for (int j = 0; j < 2 * N; ++j) bh[j] = I.b[j] / nb;
+        DevBuf tmp, bdev;
+        if ((st = tmp.alloc(N * sizeof(double2))) != SV_OK || (st = bdev.alloc(N * sizeof(double2))) != SV_OK ||
+            (st = beta[i]->alloc(N * sizeof(double2))) != SV_OK || (st = lamd[i]->alloc(N * sizeof(double))) != SV_OK ||
+            (st = cex[i]->alloc(N * sizeof(double2))) != SV_OK)
+            return fail_del(st);
+        if ((st = upload(&b->ctx, bdev.p, bh.data(), bh.size() * sizeof(double))) != SV_OK) return fail_del(st);
+        if ((st = upload(&b->ctx, lamd[i]->p, lam.data(), N * sizeof(double))) != SV_OK) return fail_del(st);
+        if ((st = kron_apply(b->stream, (double2 *)beta[i]->p, (const double2 *)bdev.p, (double2 *)tmp.p,
+                             (const double2 *)V[i]->p, N, nullptr, 1, 1)) != SV_OK)
+            return fail_del(st);
+        std::vector<double> bt(2 * (size_t)N);
+        if ((st = download(&b->ctx, bt.data(), beta[i]->p, bt.size() * sizeof(double))) != SV_OK) return fail_del(st);
+        double cn = 0.0;
+        for (int j = 0; j < N; ++j) {
+            bt[2 * j] /= lam[j];
+            bt[2 * j + 1] /= lam[j];
+            cn += bt[2 * j] * bt[2 * j] + bt[2 * j + 1] * bt[2 * j + 1];
+        }
+        cn = sqrt(cn);
+        for (auto &v : bt) v /= cn;
+        if ((st = upload(&b->ctx, cex[i]->p, bt.data(), bt.size() * sizeof(double))) != SV_OK) return fail_del(st);
+    }
+    // --- arena layout: per solve state, F, part, zpart, out
+    struct SolveLay {
+        int inst, t;
+        size_t psi, F, part, zpart;
+        uint64_t nparts_max;
+    };
+    std::vector<SolveLay> lay;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    for (int i = 0; i < n_inst; ++i) {
+        const sv_batch_instance &I = inst[i];
+        const uint64_t N = dim_of(I.n_s);
+        for (int t = 0; t < I.n_t0; ++t) {
+            SolveLay L;
+            L.inst = i;
+            L.t = t;
+            L.psi = take(dim_of(I.n_s + I.n_c + 1) * e);
+            L.F = take(N * I.n_c * sizeof(uint64_t));
+            L.nparts_max = pipe_b_blocks(I.n_s, I.n_c, e);
+            L.part = take(2 * L.nparts_max * sizeof(double));
+            L.zpart = take((size_t)pipe_c_rows(I.n_c) * N * sizeof(double2));
+            lay.push_back(L);
+        }
+    }
+    const size_t out_off = take((size_t)total * 4 * sizeof(double));
+    b->arena = new DevBuf();
+    b->bufs.push_back(b->arena);
+    sv_status st = b->arena->alloc(off);
+    if (st != SV_OK) return fail_del(st);
+    char *base = (char *)b->arena->p;
+    b->d_out = (double *)(base + out_off);
+    // --- classes by (n_s, n_c)
+    std::map<std::pair<int, int>, std::vector<int>> cls;
+    for (int k = 0; k < total; ++k) cls[{inst[lay[k].inst].n_s, inst[lay[k].inst].n_c}].push_back(k);
+    // host descriptors
+    std::vector<TurnJob> turn(total);
+    std::vector<FinishJob> fin(total);
+    std::vector<PipeSolve> solves;
+    for (int k = 0; k < total; ++k) {
+        const SolveLay &L = lay[k];
+        const sv_batch_instance &I = inst[L.inst];
+        turn[k] = TurnJob{(const double *)lamd[L.inst]->p, (uint64_t *)(base + L.F), I.t0[L.t], I.n_c,
+                          dim_of(I.n_s)};
+    }
+    std::vector<std::pair<int, int>> class_keys;
+    std::vector<std::vector<int>> class_members;
+    for (auto &kv : cls) {
+        class_keys.push_back(kv.first);
+        class_members.push_back(kv.second);
+    }
+    // descriptor arena: turn jobs, finish jobs, per-class solve arrays
+    b->desc = new DevBuf();
+    b->bufs.push_back(b->desc);
+    const size_t dbytes = total * (sizeof(TurnJob) + sizeof(FinishJob) + sizeof(PipeSolve)) + 4096;
+    if ((st = b->desc->alloc(dbytes)) != SV_OK) return fail_del(st);
+    char *dbase = (char *)b->desc->p;
+    b->d_turn = (const TurnJob *)dbase;
+    b->d_finish = (const FinishJob *)(dbase + ((total * sizeof(TurnJob) + 255) & ~(size_t)255));
+    char *dsol = (char *)b->d_finish + ((total * sizeof(FinishJob) + 255) & ~(size_t)255);
+    if ((st = upload(&b->ctx, (void *)b->d_turn, turn.data(), total * sizeof(TurnJob))) != SV_OK) return fail_del(st);
+    hipLaunchKernelGGL(k_turn_batch, dim3(64, total), dim3(256), 0, b->stream, b->d_turn);
+    {
+        const hipError_t ke = hipGetLastError();
+        if (ke != hipSuccess) return fail_del(hip_fail(ke, "k_turn_batch"));
+    }
+    size_t sol_off = 0;
+    for (size_t c = 0; c < class_keys.size(); ++c) {
+        const int n_s = class_keys[c].first, n_c = class_keys[c].second;
+        std::vector<PipeSolve> ps;
+        for (int k : class_members[c]) {
+            const SolveLay &L = lay[k];
+            ps.push_back(PipeSolve{base + L.psi, (const double2 *)beta[L.inst]->p, (const uint64_t *)(base + L.F),
+                                   (double *)(base + L.part), (double2 *)(base + L.zpart)});
+        }
+        sv_batch_s::Class C;
+        C.n_s = n_s;
+        C.n_c = n_c;
+        C.count = (int)ps.size();
+        C.d_solves = (const PipeSolve *)(dsol + sol_off);
+        sol_off += ps.size() * sizeof(PipeSolve);
+        if ((st = upload(&b->ctx, (void *)C.d_solves, ps.data(), ps.size() * sizeof(PipeSolve))) != SV_OK)
+            return fail_del(st);
+        // launch configuration: cached or tuned on the first solve of the class
+        st = dt == SV_C64 ? pipe_config<float>(b->stream, n_s, n_c, &ps[0], C.cl, C.nt)
+                          : pipe_config<double>(b->stream, n_s, n_c, &ps[0], C.cl, C.nt);
+        if (st != SV_OK) return fail_del(st);
+        const uint64_t np = pipe_b_blocks_for(n_s, n_c, C.cl[1]);
+        if (np > pipe_b_blocks(n_s, n_c, e)) return fail_del(fail(SV_EDEVICE, "partials exceed their buffer"));
+        C.nparts = np;
+        for (int k : class_members[c]) {
+            const SolveLay &L = lay[k];
+            const int g1 = (n_c + 1) / 2;
+            fin[k] = FinishJob{(const double *)(base + L.part), np, (const double2 *)(base + L.zpart),
+                               pipe_c_rows(n_c), dim_of(n_s), exp2(-0.5 * (n_c + g1)),
+                               (const double2 *)cex[L.inst]->p, b->d_out + 4 * (size_t)k};
+        }
+        b->classes.push_back(C);
+    }
+    if ((st = upload(&b->ctx, (void *)b->d_finish, fin.data(), total * sizeof(FinishJob))) != SV_OK)
+        return fail_del(st);
+    // record the whole sweep once (event tracing is paused while capturing)
+    SV_HIP(hipStreamSynchronize(b->stream));
+    const bool tr = trace_set(false);
+    hipError_t he = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) {
+        trace_set(tr);
+        return fail_del(hip_fail(he, "hipStreamBeginCapture"));
+    }
+    st = dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b);
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(b->stream, &g);
+    trace_set(tr);
+    if (st != SV_OK) {
+        if (g) hipGraphDestroy(g);
+        return fail_del(st);
+    }
+    if (he != hipSuccess) return fail_del(hip_fail(he, "hipStreamEndCapture"));
+    b->graph = g;
+    he = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (he != hipSuccess) return fail_del(hip_fail(he, "hipGraphInstantiate"));
+    *out = b;
+    return SV_OK;
+}
+
+sv_status sv_batch_run(sv_batch b, int use_graph, double *results) {
+    clear_error();
+    if (!b) return fail(SV_EINVAL, "null batch");
+    if (use_graph) {
+        SV_HIP(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        SV_TRY(b->dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b));
+    }
+    if (results) {
+        SV_TRY(download(&b->ctx, results, b->d_out, (size_t)b->n_solves * 4 * sizeof(double)));
+    } else {
+        SV_HIP(hipStreamSynchronize(b->stream));
+    }
+    return SV_OK;
+}
+
+int sv_batch_num_solves(sv_batch b) { return b ? b->n_solves : 0; }
+
+sv_status sv_batch_free(sv_batch b) {
+    if (b) {
+        hipStreamSynchronize(b->stream);
+        delete b;
+    }
+    return SV_OK;
+}
+
+sv_status sv_hhl_batch(sv_dtype dt, void *hip_stream, const sv_batch_instance *inst, int n_inst, double *results) {
+    sv_batch b = nullptr;
+    SV_TRY(sv_batch_prepare(&b, dt, hip_stream, inst, n_inst));
+    sv_status st = sv_batch_run(b, 1, results);
+    sv_batch_free(b);
+    return st;
+}
+
+}  // extern "C"

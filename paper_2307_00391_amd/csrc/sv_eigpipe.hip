@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "sv_device.h"
+#include "sv_hhl_internal.h"
 #include "sv_internal.h"
 
 namespace sv {
@@ -104,9 +105,12 @@ __device__ __forceinline__ void tile_coords(const PipeArgs &A, uint64_t &j0, uin
 // k_pipe_a: phase-estimation state + inverse cascade on G1
 // ---------------------------------------------------------------------------
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_a(cvec<R> *__restrict__ psi, const double2 *__restrict__ beta,
-                                               const uint64_t *__restrict__ F, PipeArgs A) {
+__global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
+    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
+    const double2 *__restrict__ beta = S.beta;
+    const uint64_t *__restrict__ F = S.F;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);          // [2^G][C]
@@ -177,8 +181,11 @@ __global__ __launch_bounds__(NT) void k_pipe_a(cvec<R> *__restrict__ psi, const 
 // k_pipe_b: inverse cascade on G2, inversion rotation, forward cascade on G2
 // ---------------------------------------------------------------------------
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_b(cvec<R> *__restrict__ psi, PipeArgs A, double *__restrict__ part) {
+__global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
+    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
+    double *__restrict__ part = S.part;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
@@ -291,9 +298,12 @@ __global__ __launch_bounds__(NT) void k_pipe_b(cvec<R> *__restrict__ psi, PipeAr
 // (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_c(const cvec<R> *__restrict__ psi, const uint64_t *__restrict__ F,
-                                               PipeArgs A, double2 *__restrict__ zpart) {
+__global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
+    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
+    const uint64_t *__restrict__ F = S.F;
+    double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
@@ -381,8 +391,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(const cvec<R> *__restrict__ psi, 
 // ---------------------------------------------------------------------------
 
 template <typename R, int RA, int RB, int NT>
-static sv_status launch_pipe(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
-                             const PipeArgs &A, double *part, double2 *zpart, int g, dim3 grid, size_t lds) {
+static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
+                             const PipeArgs &A, int g, dim3 grid, size_t lds) {
     // tiles above 64 KiB need a larger dynamic LDS limit; the request plus the
     // kernels' static LDS must stay within the 160 KiB of a workgroup
     constexpr int kLim = 144 * 1024;
@@ -400,40 +410,40 @@ static sv_status launch_pipe(int which, hipStream_t st, cvec<R> *psi, const doub
         attr_done = true;
     }
     if (lds > (size_t)kLim) return fail(SV_EUNSUPPORTED, "pipeline tile needs %zu bytes of LDS", lds);
-    const double half = (double)A.N * (double)(1ull << A.n_c) * sizeof(cvec<R>);
+    const double half = (double)A.N * (double)(1ull << A.n_c) * sizeof(cvec<R>) * grid.z;
     if (which == 0) {
         TraceScope ts(st, "pipe_a_init_iqft", half, 0.0);
-        hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, psi, beta, F, A);
+        hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else if (which == 1) {
         TraceScope ts(st, "pipe_b_iqft_ry_qft", 2.0 * half, 0.0);
-        hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, psi, A, part);
+        hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else {
         TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
-        hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, (const cvec<R> *)psi, F, A, zpart);
+        hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
 
 template <typename R, int RA, int RB>
-static sv_status launch_nt(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
-                           const PipeArgs &A, double *part, double2 *zpart, int g, int nt, dim3 grid, size_t lds) {
-    if (nt == 512) return launch_pipe<R, RA, RB, 512>(which, st, psi, beta, F, A, part, zpart, g, grid, lds);
-    return launch_pipe<R, RA, RB, 256>(which, st, psi, beta, F, A, part, zpart, g, grid, lds);
+static sv_status launch_nt(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
+                           const PipeArgs &A, int g, int nt, dim3 grid, size_t lds) {
+    if (nt == 512) return launch_pipe<R, RA, RB, 512>(which, st, one, many, A, g, grid, lds);
+    return launch_pipe<R, RA, RB, 256>(which, st, one, many, A, g, grid, lds);
 }
 
 template <typename R>
-static sv_status dispatch_g(int which, hipStream_t st, cvec<R> *psi, const double2 *beta, const uint64_t *F,
-                            const PipeArgs &A, double *part, double2 *zpart, int g, int nt, dim3 grid, size_t lds) {
+static sv_status dispatch_g(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
+                            const PipeArgs &A, int g, int nt, dim3 grid, size_t lds) {
     switch (g) {
-    case 1: return launch_nt<R, 1, 0>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 2: return launch_nt<R, 1, 1>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 3: return launch_nt<R, 2, 1>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 4: return launch_nt<R, 2, 2>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 5: return launch_nt<R, 3, 2>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 6: return launch_nt<R, 3, 3>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 7: return launch_nt<R, 4, 3>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
-    case 8: return launch_nt<R, 4, 4>(which, st, psi, beta, F, A, part, zpart, g, nt, grid, lds);
+    case 1: return launch_nt<R, 1, 0>(which, st, one, many, A, g, nt, grid, lds);
+    case 2: return launch_nt<R, 1, 1>(which, st, one, many, A, g, nt, grid, lds);
+    case 3: return launch_nt<R, 2, 1>(which, st, one, many, A, g, nt, grid, lds);
+    case 4: return launch_nt<R, 2, 2>(which, st, one, many, A, g, nt, grid, lds);
+    case 5: return launch_nt<R, 3, 2>(which, st, one, many, A, g, nt, grid, lds);
+    case 6: return launch_nt<R, 3, 3>(which, st, one, many, A, g, nt, grid, lds);
+    case 7: return launch_nt<R, 4, 3>(which, st, one, many, A, g, nt, grid, lds);
+    case 8: return launch_nt<R, 4, 4>(which, st, one, many, A, g, nt, grid, lds);
     }
     return fail(SV_EUNSUPPORTED, "clock group of %d bits", g);
 }
@@ -469,7 +479,7 @@ struct PipePlan {
     size_t lds[3];
 };
 
-static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], const int nt[3]) {
+static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], const int nt[3], int nsolves) {
     PipeArgs A;
     A.N = dim_of(n_s);
     A.n_s = n_s;
@@ -484,26 +494,24 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
         P.A[w].cl = cl[w];
         P.nt[w] = nt[w];
         const uint64_t tiles = (A.N >> cl[w]) << (n_c - g);
-        P.grid[w] = tiles <= 0x7fffffffull ? dim3((unsigned)tiles) : dim3(1u << 30, (unsigned)(tiles >> 30));
+        P.grid[w] = tiles <= 0x7fffffffull ? dim3((unsigned)tiles, 1, nsolves)
+                                           : dim3(1u << 30, (unsigned)(tiles >> 30), nsolves);
         P.lds[w] = pipe_lds(w, cl[w], g, e, nt[w]);
     }
 }
 
 template <typename R>
-static sv_status run_one(sv_state s, const PipePlan &P, int w, const double2 *beta, const uint64_t *F, double *part,
-                         double2 *zpart) {
+static sv_status run_one(hipStream_t st, const PipePlan &P, int w, const PipeSolve &one, const PipeSolve *many) {
     const int g = w == 1 ? P.A[w].g2 : P.A[w].g1;
-    return dispatch_g<R>(w, s->stream, (cvec<R> *)s->data, beta, F, P.A[w], part, zpart, g, P.nt[w], P.grid[w],
-                         P.lds[w]);
+    return dispatch_g<R>(w, st, one, many, P.A[w], g, P.nt[w], P.grid[w], P.lds[w]);
 }
 
 // The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
 // tile, threads per workgroup) for each of the three kernels on the real
-// operands (each kernel is idempotent given its input half) and keep the
-// fastest; results live in the process-wide tuning cache.
+// operands of one solve (each kernel is idempotent given its input half)
+// and keep the fastest; results live in the process-wide tuning cache.
 template <typename R>
-static sv_status tune_pipe(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
-                           double2 *zpart, int cl_out[3], int nt_out[3]) {
+static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &one, int cl_out[3], int nt_out[3]) {
     const size_t e = sizeof(cvec<R>);
     const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
     for (int w = 0; w < 3; ++w) {
@@ -522,9 +530,9 @@ static sv_status tune_pipe(sv_state s, int n_s, int n_c, const double2 *beta, co
                 cls[w] = cl;
                 nts[w] = nt;
                 PipePlan P;
-                make_plan(P, n_s, n_c, e, cls, nts);
+                make_plan(P, n_s, n_c, e, cls, nts, 1);
                 float ms = 0.f;
-                SV_TRY(time_stream(s->stream, 2, &ms, [&]() { return run_one<R>(s, P, w, beta, F, part, zpart); }));
+                SV_TRY(time_stream(st, 2, &ms, [&]() { return run_one<R>(st, P, w, one, nullptr); }));
                 if (ms < best) {
                     best = ms;
                     bcl = cl;
@@ -535,20 +543,18 @@ static sv_status tune_pipe(sv_state s, int n_s, int n_c, const double2 *beta, co
         cl_out[w] = bcl;
         nt_out[w] = bnt;
         // the next kernel reads what this one writes: leave its output in place
-        int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
         PipePlan P;
-        make_plan(P, n_s, n_c, e, cls, nts);
-        SV_TRY(run_one<R>(s, P, w, beta, F, part, zpart));
+        make_plan(P, n_s, n_c, e, cl_out, nt_out, 1);
+        SV_TRY(run_one<R>(st, P, w, one, nullptr));
     }
     return SV_OK;
 }
 
+// launch parameters for a shape: cached, tuned on `one` if allowed, else defaults
 template <typename R>
-sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
-                   double2 *zpart, uint64_t *nparts) {
+sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]) {
     const size_t e = sizeof(cvec<R>);
     const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
-    int cl[3], nt[3];
     const std::string key = std::string("eigpipe/") + (e == 8 ? "c64/" : "c128/") + std::to_string(n_s) + "/" +
                             std::to_string(n_c);
     std::vector<int> cached;
@@ -557,19 +563,31 @@ sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint
             cl[w] = cached[2 * w];
             nt[w] = cached[2 * w + 1];
         }
-    } else if (autotune_enabled()) {
-        SV_TRY(tune_pipe<R>(s, n_s, n_c, beta, F, part, zpart, cl, nt));
-        tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
-    } else {
-        for (int w = 0; w < 3; ++w) {
-            cl[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
-            nt[w] = 256;
-        }
+        return SV_OK;
     }
+    if (tune_on && autotune_enabled()) {
+        SV_TRY(tune_pipe<R>(st, n_s, n_c, *tune_on, cl, nt));
+        tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
+        return SV_OK;
+    }
+    for (int w = 0; w < 3; ++w) {
+        cl[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
+        nt[w] = 256;
+    }
+    return SV_OK;
+}
+
+template <typename R>
+sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
+                   double2 *zpart, uint64_t *nparts) {
+    const size_t e = sizeof(cvec<R>);
+    PipeSolve one{s->data, beta, F, part, zpart};
+    int cl[3], nt[3];
+    SV_TRY(pipe_config<R>(s->stream, n_s, n_c, &one, cl, nt));
     PipePlan P;
-    make_plan(P, n_s, n_c, e, cl, nt);
+    make_plan(P, n_s, n_c, e, cl, nt, 1);
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
-    for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s, P, w, beta, F, part, zpart));
+    for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s->stream, P, w, one, nullptr));
     return SV_OK;
 }
 template sv_status pipe_run<float>(sv_state, int, int, const double2 *, const uint64_t *, double *, double2 *,
@@ -577,13 +595,36 @@ template sv_status pipe_run<float>(sv_state, int, int, const double2 *, const ui
 template sv_status pipe_run<double>(sv_state, int, int, const double2 *, const uint64_t *, double *, double2 *,
                                     uint64_t *);
 
+// a class of solves sharing (n_s, n_c): the three kernels once each, blockIdx.z = solve
+template <typename R>
+sv_status pipe_run_batch(hipStream_t st, int n_s, int n_c, const int cl[3], const int nt[3],
+                         const PipeSolve *dev_solves, int nsolves, uint64_t *nparts) {
+    const size_t e = sizeof(cvec<R>);
+    if (nsolves < 1 || nsolves > 65535) return fail(SV_EINVAL, "batch of %d solves", nsolves);
+    PipePlan P;
+    make_plan(P, n_s, n_c, e, cl, nt, nsolves);
+    *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
+    PipeSolve none{};
+    for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(st, P, w, none, dev_solves));
+    return SV_OK;
+}
+template sv_status pipe_run_batch<float>(hipStream_t, int, int, const int *, const int *, const PipeSolve *, int,
+                                         uint64_t *);
+template sv_status pipe_run_batch<double>(hipStream_t, int, int, const int *, const int *, const PipeSolve *, int,
+                                          uint64_t *);
+template sv_status pipe_config<float>(hipStream_t, int, int, const PipeSolve *, int *, int *);
+template sv_status pipe_config<double>(hipStream_t, int, int, const PipeSolve *, int *, int *);
+
+uint64_t pipe_b_blocks_for(int n_s, int n_c, int cl) {
+    const int g1 = (n_c + 1) / 2;
+    return (dim_of(n_s) >> cl) << g1;
+}
+
 // upper bounds of the k_pipe_b block count (one FP64 partial pair each) and
 // the k_pipe_c partial rows, over every configuration the tuner may pick
 uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem) {
-    const int g1 = (n_c + 1) / 2;
     (void)elem;
-    const int cl = n_s < 3 ? n_s : 3;
-    return (dim_of(n_s) >> cl) << g1;
+    return pipe_b_blocks_for(n_s, n_c, n_s < 3 ? n_s : 3);
 }
 int pipe_c_rows(int n_c) { return 1 << (n_c - (n_c + 1) / 2); }
 

@@ -47,9 +47,6 @@ sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int c
 template <typename R>
 sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
                    double2 *zpart, uint64_t *nparts);
-int pipe_supported(int n_s, int n_c);
-uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem);
-int pipe_c_rows(int n_c);
 
 // --------------------------------------------------------------------------
 // small FP64 kernels

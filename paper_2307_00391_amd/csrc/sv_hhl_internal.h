@@ -22,6 +22,30 @@ struct DevBuf {
     sv_status ensure(size_t need) { return need <= bytes && p ? SV_OK : alloc(need); }
 };
 
+// per-solve operands of the fused eigen-frame kernels (one solve: passed by
+// value; a batch: a device array indexed by blockIdx.z)
+struct PipeSolve {
+    void *psi;              // the state
+    const double2 *beta;    // V^H b^ (FP64)
+    const uint64_t *F;      // turn table [N][n_c]
+    double *part;           // k_pipe_b partial sums (2 per block)
+    double2 *zpart;         // k_pipe_c partial column sums [2^g2][N]
+};
+
+template <typename R>
+sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]);
+template <typename R>
+sv_status pipe_run_batch(hipStream_t st, int n_s, int n_c, const int cl[3], const int nt[3],
+                         const PipeSolve *dev_solves, int nsolves, uint64_t *nparts);
+int pipe_supported(int n_s, int n_c);
+uint64_t pipe_b_blocks_for(int n_s, int n_c, int cl);
+uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem);
+int pipe_c_rows(int n_c);
+
+// F[j][k] = frac(lam_j T0 / 2 pi 2^k) as 64-bit turn fractions (sv_hhl.hip)
+__global__ void k_turn_table(uint64_t *__restrict__ F, const double *__restrict__ lam, double T0, int n_c,
+                             uint64_t N);
+
 // eigen-decomposition of A = A_hi (x) I + I (x) A_lo (dense A: n_lo = 1, V_lo empty)
 struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;

@@ -86,6 +86,7 @@ sv_status time_stream(hipStream_t st, int reps, float *ms_out, const std::functi
 
 // ---- per-kernel tracing (sv_trace.cpp) ------------------------------------
 bool trace_on();
+bool trace_set(bool on);   // returns the previous setting
 class TraceScope {
   public:
     TraceScope(hipStream_t st, const char *name, double bytes, double flops);

@@ -27,6 +27,13 @@ static std::vector<hipEvent_t> g_pool;
 
 bool trace_on() { return g_on; }
 
+bool trace_set(bool on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const bool was = g_on;
+    g_on = on;
+    return was;
+}
+
 static hipEvent_t get_event() {
     hipEvent_t e = nullptr;
     if (!g_pool.empty()) {

@@ -23,6 +23,8 @@ import math
 from dataclasses import dataclass
 
 import numpy as np
+from scipy.linalg import eigvalsh_tridiagonal
+from scipy.optimize import brentq
 
 SEED_BASE = 230700391
 
@@ -130,11 +132,17 @@ def random_spd_tridiag(rng: np.random.Generator, N: int, kappa: float):
     w = rng.uniform(0.5, 1.0, N - 1)
     base = -w * np.sqrt(d[:-1] * d[1:])
 
+    def extremes(s):
+        off = s * base
+        lo_ = eigvalsh_tridiagonal(d, off, select="i", select_range=(0, 0))[0]
+        hi_ = eigvalsh_tridiagonal(d, off, select="i", select_range=(N - 1, N - 1))[0]
+        return lo_, hi_
+
     def cond(s):
-        ev = np.linalg.eigvalsh(_tridiag(d, s * base))
-        if ev[0] <= 0:
+        lo_, hi_ = extremes(s)
+        if lo_ <= 0:
             return math.inf
-        return ev[-1] / ev[0]
+        return hi_ / lo_
 
     lo, hi = 0.0, 1.0
     while cond(hi) < kappa:        # widen if needed (rare)
@@ -143,17 +151,18 @@ def random_spd_tridiag(rng: np.random.Generator, N: int, kappa: float):
             break
     if cond(lo) >= kappa:
         s = 0.0
+    elif cond(hi) <= kappa:
+        s = hi
     else:
-        for _ in range(200):
-            mid = 0.5 * (lo + hi)
-            if cond(mid) < kappa:
-                lo = mid
-            else:
-                hi = mid
-        s = lo
+        # log cond(s) - log kappa changes sign on [lo, hi]; cond is infinite
+        # past the loss of definiteness, which brentq only sees as "large"
+        def f(s_):
+            c = cond(s_)
+            return (math.log(c) if math.isfinite(c) else 800.0) - math.log(kappa)
+        s = brentq(f, lo, hi, xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=200)
     A = _tridiag(d, s * base)
-    ev = np.linalg.eigvalsh(A)
-    return A, float(ev[0]), float(ev[-1])
+    lmin, lmax = extremes(s)
+    return A, float(lmin), float(lmax)
 
 
 @dataclass

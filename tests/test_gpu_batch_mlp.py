@@ -1,0 +1,286 @@
+"""GPU checks of the batched T0 sweep, the MLP kernels, the Lanczos features
+and the learned T0.
+
+* Batched sweep: every (instance, T0) result of one graph launch against the
+  FP64 oracle's HHL on the same inputs (P(a=1, clock=0), P(a=1) to 1e-12 in
+  complex128 and 1e-5 in complex64; the fidelity to the bound those amplitude
+  bars imply), and graph replays bit-identical to eager launches.
+* MLP: forward to 1e-5 and the gradient to 1e-4 (relative to the largest
+  entry) against oracle/mlp.py in FP64; Adam against its FP64 update; the
+  gradient repeatable bit for bit.
+* Lanczos: extreme eigenvalues against numpy's dense eigensolver.
+* Learned T0: trained on the library's own sweeps, the predicted T0 beats the
+  textbook choice 2 pi (1 - 2^-n_c) / lambda_max on held-out instances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2307_00391_amd import binding as B
+from paper_2307_00391_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+def _complex_hermitian(rng, N, lo=1.0, hi=6.0):
+    Q = inputs.random_unitary(rng, N)
+    lam = rng.uniform(lo, hi, N)
+    A = (Q * lam) @ Q.conj().T
+    return 0.5 * (A + A.conj().T), lam.min(), lam.max()
+
+
+def _batch_problems():
+    """uneven sizes; two instances share a (n_s, n_c) class"""
+    probs = []
+    s = inputs.poiseuille(16)
+    probs.append((s.A, s.b, 6, np.array([0.7, 1.0, 1.6]) * 2 * math.pi / s.lambda_max))
+    rng = inputs.rng_for(7, 0)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 8, 40.0)
+    probs.append((A, rng.standard_normal(8), 7, inputs.t0_grid(lmax, 4)))
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 32, 15.0)
+    probs.append((A, rng.standard_normal(32) + 1j * rng.standard_normal(32), 5, inputs.t0_grid(lmax, 2)))
+    A, lmin, lmax = _complex_hermitian(rng, 4)
+    probs.append((A, rng.standard_normal(4), 4, np.array([2 * math.pi / lmax])))
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 16, 100.0)
+    probs.append((A, rng.standard_normal(16), 6, np.array([0.9, 2.2]) * 2 * math.pi / lmax))
+    return probs
+
+
+def _fidelity_ref(A, b, x):
+    xc = np.linalg.solve(A, b)
+    xc /= np.linalg.norm(xc)
+    return abs(np.vdot(xc, x)) / np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_matches_oracle(dt):
+    probs = _batch_problems()
+    h = B.sv_batch_prepare(probs, dt)
+    try:
+        assert B.sv_batch_num_solves(h) == sum(len(p[3]) for p in probs)
+        res = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    k = 0
+    for A, b, n_c, t0s in probs:
+        N = A.shape[0]
+        for T0 in t0s:
+            psi, x, p_post, p_anc = oracle.hhl(A, b, n_c, T0)
+            pp, pa, nt, F = res[k]
+            assert abs(pp - p_post) <= TOL[dt], (k, pp, p_post)
+            assert abs(pa - p_anc) <= TOL[dt], (k, pa, p_anc)
+            assert abs(nt - 1.0) <= TOL[dt]
+            # amplitude error <= tol per entry => |dz| <= tol sqrt(N) => |dF| <= 2 tol sqrt(N) / |z|
+            Fr = _fidelity_ref(A, b, x)
+            assert abs(F - Fr) <= 2 * TOL[dt] * math.sqrt(N) / math.sqrt(p_post) + 1e-13, (k, F, Fr)
+            k += 1
+
+
+def test_batch_graph_replays_match_eager_bitwise():
+    probs = _batch_problems()
+    h = B.sv_batch_prepare(probs, "c64")
+    try:
+        eager = B.sv_batch_run(h, use_graph=False)
+        for _ in range(3):
+            g = B.sv_batch_run(h, use_graph=True)
+            assert np.array_equal(g, eager)
+            e2 = B.sv_batch_run(h, use_graph=False)
+            assert np.array_equal(e2, eager)
+    finally:
+        B.sv_batch_free(h)
+    once = B.sv_hhl_batch(probs, "c64")
+    assert np.array_equal(once, eager)
+
+
+def test_batch_matches_single_solves():
+    probs = _batch_problems()
+    res = B.sv_hhl_batch(probs, "c128")
+    k = 0
+    for A, b, n_c, t0s in probs:
+        n_s = A.shape[0].bit_length() - 1
+        for T0 in t0s:
+            st = B.State(n_s + n_c + 1, "c128")
+            x, r = B.sv_hhl(st.h, A, b, n_c, T0, 1)
+            st.close()
+            assert abs(res[k, 0] - r.p_post) <= 1e-13
+            assert abs(res[k, 1] - r.p_anc) <= 1e-13
+            assert abs(res[k, 3] - _fidelity_ref(A, b, x)) <= 1e-11
+            k += 1
+
+
+def test_batch_error_paths():
+    s = inputs.poiseuille(16)
+    good = (s.A, s.b, 6, np.array([1.0]))
+    with pytest.raises(B.SvError) as e:
+        B.sv_batch_prepare([(s.A, s.b, 6, np.array([-1.0]))])
+    assert e.value.status == B.SV_EINVAL
+    with pytest.raises(B.SvError) as e:
+        B.sv_batch_prepare([good, (s.A, np.zeros(16), 6, np.array([1.0]))])
+    assert e.value.status == B.SV_EZERONORM
+    with pytest.raises(B.SvError) as e:
+        B.sv_batch_prepare([(-s.A, s.b, 6, np.array([1.0]))])
+    assert e.value.status == B.SV_ENOTPOSDEF
+    Anh = s.A.astype(complex)
+    Anh[0, 1] += 0.5j
+    with pytest.raises(B.SvError) as e:
+        B.sv_batch_prepare([(Anh, s.b, 6, np.array([1.0]))])
+    assert e.value.status == B.SV_ENOTHERMITIAN
+    with pytest.raises(B.SvError) as e:
+        B.sv_batch_prepare([(np.eye(2), np.ones(2), 40, np.array([1.0]))])
+    assert e.value.status == B.SV_EUNSUPPORTED
+    # a failed prepare leaves the library usable
+    res = B.sv_hhl_batch([good], "c128")
+    assert res.shape == (1, 4) and 0 < res[0, 0] <= res[0, 1] <= 1
+
+
+# --------------------------------------------------------------------------
+# MLP kernels
+# --------------------------------------------------------------------------
+
+def _f32(a):
+    import torch
+    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = omlp.init_params(seed) + rng.normal(0, 0.05, omlp.N_PARAMS)
+    return p.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("Bn", [1, 31, 32, 777])
+def test_mlp_forward_matches_oracle(Bn):
+    rng = np.random.default_rng(Bn)
+    p = _params(1)
+    X = rng.normal(0, 1.5, (Bn, 5)).astype(np.float32).astype(np.float64)
+    y = B.sv_mlp_forward(_f32(p), _f32(X)).double().cpu().numpy()
+    yr = omlp.forward(p, X)
+    assert np.abs(y - yr).max() <= 1e-5 * max(1.0, np.abs(yr).max())
+
+
+@pytest.mark.parametrize("Bn", [1, 33, 777])
+def test_mlp_gradient_matches_oracle(Bn):
+    rng = np.random.default_rng(100 + Bn)
+    p = _params(2)
+    X = rng.normal(0, 1.0, (Bn, 5)).astype(np.float32).astype(np.float64)
+    t = rng.normal(0, 1.0, Bn).astype(np.float32).astype(np.float64)
+    g, loss = B.sv_mlp_backward(_f32(p), _f32(X), _f32(t))
+    g = g.double().cpu().numpy()
+    Lr, gr = omlp.loss_and_grad(p, X, t)
+    assert abs(float(loss.item()) - Lr) <= 1e-5 * max(1.0, Lr)
+    assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+    g2, _ = B.sv_mlp_backward(_f32(p), _f32(X), _f32(t))
+    assert np.array_equal(g2.double().cpu().numpy(), g)
+
+
+def test_mlp_adam_matches_oracle():
+    import torch
+    rng = np.random.default_rng(9)
+    p = rng.normal(0, 1, omlp.N_PARAMS).astype(np.float32).astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    P, M, V = _f32(p), _f32(m), _f32(v)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-2, omlp.N_PARAMS).astype(np.float32).astype(np.float64)
+        B.sv_mlp_adam(P, M, V, _f32(g), step, lr=1e-3)
+        p, m, v = omlp.adam_step(p, m, v, g, step, lr=1e-3)
+        torch.cuda.synchronize()
+        assert np.abs(P.double().cpu().numpy() - p).max() <= 1e-6
+        assert np.abs(M.double().cpu().numpy() - m).max() <= 1e-8
+
+
+def test_mlp_training_on_gpu_reduces_loss():
+    import torch
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (256, 5))
+    t = np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]
+    P = _f32(omlp.init_params(1))
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    Xd, td = _f32(X), _f32(t)
+    L0 = omlp.loss_and_grad(omlp.init_params(1), X, t)[0]
+    for step in range(1, 401):
+        g, _ = B.sv_mlp_backward(P, Xd, td)
+        B.sv_mlp_adam(P, M, V, g, step, lr=3e-3)
+    L = omlp.loss_and_grad(P.double().cpu().numpy(), X, t)[0]
+    assert L < 0.05 * L0, (L, L0)
+
+
+def test_mlp_error_paths():
+    import torch
+    P = torch.zeros(B.SV_MLP_PARAMS, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        B.sv_mlp_forward(P, torch.zeros((4, 3), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        B.sv_mlp_forward(P[:10], torch.zeros((4, 5), dtype=torch.float32, device="cuda"))
+    y = B.sv_mlp_forward(P, torch.zeros((0, 5), dtype=torch.float32, device="cuda"))
+    assert y.numel() == 0
+
+
+# --------------------------------------------------------------------------
+# Lanczos
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,iters,kind", [(1, 4, "real"), (2, 2, "complex"), (50, 50, "complex"),
+                                          (256, 96, "tridiag"), (1024, 96, "tridiag")])
+def test_lanczos_extremes(N, iters, kind):
+    rng = np.random.default_rng(N)
+    if kind == "tridiag":
+        A, lmin, lmax = inputs.random_spd_tridiag(rng, N, 1000.0)
+    elif kind == "complex":
+        A, _, _ = _complex_hermitian(rng, N)
+    else:
+        A = np.array([[2.5]])
+    ev = np.linalg.eigvalsh(A)
+    lo, hi = B.sv_spectrum_lanczos(A, iters, seed=3)
+    assert abs(hi - ev[-1]) <= 1e-10 * abs(ev[-1])
+    assert abs(lo - ev[0]) <= 1e-6 * abs(ev[0])
+
+
+def test_lanczos_error_paths():
+    with pytest.raises(B.SvError) as e:
+        B.sv_spectrum_lanczos(np.array([[1.0, 2.0], [0.0, 1.0]]))
+    assert e.value.status == B.SV_ENOTHERMITIAN
+    with pytest.raises(B.SvError) as e:
+        B.sv_spectrum_lanczos(np.eye(2), iters=0)
+    assert e.value.status == B.SV_EINVAL
+
+
+# --------------------------------------------------------------------------
+# learned T0
+# --------------------------------------------------------------------------
+
+def test_learned_t0_beats_textbook_choice():
+    """Small sweep family (n_s 2..5, n_c 5..7, kappa 10..1e3): train on 160
+    instances' sweeps, predict T0 for 48 held-out ones.  The gain is the mean
+    fidelity at the predicted T0 minus the mean fidelity at the textbook
+    2 pi (1 - 2^-n_c) / lambda_max, and minus that of the untrained network."""
+    from paper_2307_00391_amd import t0model as T
+    train = T.make_instances(160, 0, (2, 5), (5, 7), (1.0, 3.0), config=40)
+    test = T.make_instances(48, 10000, (2, 5), (5, 7), (1.0, 3.0), config=40)
+    Xtr, _, Ftr, _, _ = T.sweep_dataset(train, "c64")
+    ytr = T.smooth_labels(Ftr, np.log(T.grid_factors()), 1)
+    model = T.T0Predictor().fit(Xtr, ytr, steps=1500, lr=3e-3)
+    assert model.history[-1][1] < 0.5 * model.history[0][1]
+    Xte, lam, Fte, _, _ = T.sweep_dataset(test, "c64")
+    Fp = T.single_shot(test, model.predict_t0(Xte, lam[:, 1]), "c64")
+    t0_text = np.array([2 * math.pi * (1 - 2.0 ** -i.n_c) / l for i, l in zip(test, lam[:, 1])])
+    Ft = T.single_shot(test, t0_text, "c64")
+    untrained = T.T0Predictor(params=T.glorot_params(0))
+    Fu = T.single_shot(test, untrained.predict_t0(Xte, lam[:, 1]), "c64")
+    Fbest = Fte.max(axis=1)
+    assert Fp.mean() - Ft.mean() > 0.02, (Fp.mean(), Ft.mean(), Fbest.mean())
+    assert Fp.mean() - Fu.mean() > 0.02, (Fp.mean(), Fu.mean())
+    assert np.all(Fp <= Fbest + 0.05)
