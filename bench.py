@@ -15,8 +15,10 @@ hhl_updates, eigen-frame count).  The JSON line also carries: the HBM rate
 of the whole step, the per-kernel roofline of the dominant kernel (HIP
 events around its launches on its own stream, during the timed steps), the
 33-qubit U3 + CNOT-ladder throughput probe, the matrix-core rate of the dense
-controlled-U GEMM, the solution's fidelity against the classical solve, and
-the FP64 oracle timed on the host cores as the CPU baseline.
+controlled-U GEMM, the batched T0 sweep (64 random SPD tridiagonal instances,
+n_s 4..10, n_c 8..12, 16 T0 each: 1024 solves replayed as one hipGraph), the
+solution's fidelity against the classical solve, and the FP64 oracle timed on
+the host cores as the CPU baseline.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -100,6 +102,9 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-mfma", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-instances", type=int, default=64)
+    ap.add_argument("--sweep-replays", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 4 GiB device copy first (reference kernel for HBM counters)")
@@ -264,6 +269,35 @@ def main():
                               "ms_per_apply": g["ms"] / g["launches"],
                               "scatter_ms_per_apply": tr.get("scatter_rows", {"ms": 0})["ms"] / reps}
         ms_.close()
+
+    # ---------------- batched T0 sweep: one graph of 64 x 16 solves ----------------
+    if not args.no_sweep:
+        ni = args.sweep_instances
+        log(f"[bench] sweep: {ni} instances x 16 T0 (n_s 4..10, n_c 8..12), complex64")
+        insts = inputs.sweep_instances(ni)
+        probs = [(i.A, i.b, i.n_c, i.t0) for i in insts]
+        t = time.perf_counter()
+        h = B.sv_batch_prepare(probs, "c64")
+        prep = time.perf_counter() - t
+        B.sv_batch_run(h, use_graph=True)          # warm-up replay
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.sweep_replays):
+            B.sv_batch_run(h, use_graph=True, want_results=False)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / args.sweep_replays
+        res = B.sv_batch_run(h, use_graph=True)
+        B.sv_batch_free(h)
+        nsol = res.shape[0]
+        Fm = res[:, 3].reshape(ni, 16)
+        upd = sum(metrics.hhl_updates(i.n_s, i.n_c, 1)["total"] * 16 for i in insts)
+        amps = sum((1 << (i.n_s + i.n_c + 1)) * 16 for i in insts)
+        out["sweep"] = {"instances": ni, "solves": nsol, "graph_replay_s": el, "solves_per_s": nsol / el,
+                        "updates_per_s": upd / el, "amplitudes": amps, "prepare_s": prep,
+                        "best_F_mean": float(Fm.max(1).mean()),
+                        "best_factor_hist": np.bincount(Fm.argmax(1), minlength=16).tolist()}
+        log(f"[bench] sweep {nsol} solves in {el * 1e3:.2f} ms per replay ({nsol / el:.0f} solves/s), "
+            f"prepare {prep:.2f} s")
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------
     if not args.no_cpu:

@@ -7,7 +7,16 @@
 // (2^c amplitudes per segment); the gathered bits are the targets the pass
 // needs.  All other bits are fixed per tile (the tile id is deposited into
 // them), so controls and phases on them are uniform over a workgroup.
+//
+// Inside a tile the gates run from registers: the pass's gate list is cut
+// into segments whose targets fall in at most RB tile positions S.  For a
+// segment every thread holds the 2^RB amplitudes that differ only in S (its
+// other tile bits come from the thread index), applies the segment's gates
+// without any exchange, and hands the tile back through LDS.  The LDS
+// layout is XOR-swizzled so that threads whose amplitudes sit 2^p apart hit
+// distinct banks.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -33,11 +42,30 @@ struct FOp {
     double u[8];           // OP_U
 };
 
+// an op as a segment runs it: targets as register bits, its local condition
+// split into the register part and the part fixed per thread
+struct ROp {
+    int type;
+    int j0, j1;            // register bits of the target(s)
+    uint32_t rmask, rval;  // condition on the register index
+    uint32_t tmask, tval;  // condition on the tile bits outside the segment's set
+    uint32_t pad;
+    uint64_t gmask, gval;  // condition on non-local bits
+    double u[8];           // OP_U matrix; OP_PHASE: (cos, sin) of the phase in u[0], u[1]
+};
+
+constexpr int MAX_RB = 5;
+
+struct FSeg {
+    int pos[MAX_RB];       // tile positions held in registers (register bit i = pos[i])
+    int nops, op_off;
+};
+
 struct FPass {
     uint64_t nl_mask;      // non-local, non-fixed bits (the tile id is deposited here)
     uint64_t fix_val;      // fixed non-local bits
     int k, c, r;           // local count, low contiguous bits, gathered high bits
-    int nops, op_off;
+    int nseg, seg_off;
     int hpos[MAX_HI];      // global positions of the gathered bits, ascending
 };
 
@@ -54,9 +82,113 @@ __device__ __forceinline__ uint32_t insert0(uint32_t p, int pos) {
     return ((p >> pos) << (pos + 1)) | (p & ((1u << pos) - 1u));
 }
 
+// LDS slot of tile coordinate t: the bank index (low log2(256 B / elem) bits)
+// is XOR-ed with the folded higher bits
 template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t t) {
+    constexpr int e = sizeof(cvec<R>) == 8 ? 5 : 4;
+    constexpr uint32_t m = (1u << e) - 1u;
+    const uint32_t h = t >> e;
+    return t ^ ((h ^ (h >> e) ^ (h >> (2 * e))) & m);
+}
+
+__device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
+    uint32_t r = 0;
+    for (uint32_t b = 1; mask; b <<= 1) {
+        const uint32_t low = mask & (0u - mask);
+        if (v & b) r |= low;
+        mask ^= low;
+    }
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ cvec<R> csel(bool c, cvec<R> a, cvec<R> b) {
+    return cmake<R>(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// the register-bit condition of an op is uniform: without one every pair is
+// updated (no branches, so the pairs interleave); with one, results are
+// selected per pair
+template <typename R, int RB, int J>
+__device__ __forceinline__ void reg_u(cvec<R> (&v)[1 << RB], const ROp &f) {
+    const cvec<R> u00 = cmake<R>((R)f.u[0], (R)f.u[1]), u01 = cmake<R>((R)f.u[2], (R)f.u[3]);
+    const cvec<R> u10 = cmake<R>((R)f.u[4], (R)f.u[5]), u11 = cmake<R>((R)f.u[6], (R)f.u[7]);
+    const uint32_t rm = f.rmask, rv = f.rval;
+    if (rm == 0) {
+#pragma unroll
+        for (int m = 0; m < (1 << RB); ++m) {
+            if (m & (1 << J)) continue;
+            const cvec<R> a0 = v[m], a1 = v[m | (1 << J)];
+            v[m] = cmac2<R>(u00, a0, u01, a1);
+            v[m | (1 << J)] = cmac2<R>(u10, a0, u11, a1);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < (1 << RB); ++m) {
+            if (m & (1 << J)) continue;
+            const bool on = (m & rm) == rv;
+            const cvec<R> a0 = v[m], a1 = v[m | (1 << J)];
+            const cvec<R> b0 = cmac2<R>(u00, a0, u01, a1), b1 = cmac2<R>(u10, a0, u11, a1);
+            v[m] = csel<R>(on, b0, a0);
+            v[m | (1 << J)] = csel<R>(on, b1, a1);
+        }
+    }
+}
+
+template <typename R, int RB, int J>
+__device__ __forceinline__ void reg_x(cvec<R> (&v)[1 << RB], const ROp &f) {
+    const uint32_t rm = f.rmask, rv = f.rval;
+#pragma unroll
+    for (int m = 0; m < (1 << RB); ++m) {
+        if (m & (1 << J)) continue;
+        const bool on = (m & rm) == rv;
+        const cvec<R> a0 = v[m], a1 = v[m | (1 << J)];
+        v[m] = csel<R>(on, a1, a0);
+        v[m | (1 << J)] = csel<R>(on, a0, a1);
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void reg_phase(cvec<R> (&v)[1 << RB], const ROp &f) {
+    const cvec<R> ph = cmake<R>((R)f.u[0], (R)f.u[1]);
+    const uint32_t rm = f.rmask, rv = f.rval;
+#pragma unroll
+    for (int m = 0; m < (1 << RB); ++m) {
+        const cvec<R> p = cmul<R>(v[m], ph);
+        v[m] = csel<R>((m & rm) == rv, p, v[m]);
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void reg_apply(cvec<R> (&v)[1 << RB], const ROp &f) {
+    switch (f.type) {
+    case OP_PHASE: reg_phase<R, RB>(v, f); break;
+    case OP_X:
+        switch (f.j0) {
+        case 0: reg_x<R, RB, 0>(v, f); break;
+        case 1: reg_x<R, RB, 1 < RB ? 1 : 0>(v, f); break;
+        case 2: reg_x<R, RB, 2 < RB ? 2 : 0>(v, f); break;
+        case 3: reg_x<R, RB, 3 < RB ? 3 : 0>(v, f); break;
+        default: reg_x<R, RB, 4 < RB ? 4 : 0>(v, f); break;
+        }
+        break;
+    default:
+        switch (f.j0) {
+        case 0: reg_u<R, RB, 0>(v, f); break;
+        case 1: reg_u<R, RB, 1 < RB ? 1 : 0>(v, f); break;
+        case 2: reg_u<R, RB, 2 < RB ? 2 : 0>(v, f); break;
+        case 3: reg_u<R, RB, 3 < RB ? 3 : 0>(v, f); break;
+        default: reg_u<R, RB, 4 < RB ? 4 : 0>(v, f); break;
+        }
+        break;
+    }
+}
+
+template <typename R, int RB>
 __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi, const FPass *__restrict__ passes,
-                                                       int pi, const FOp *__restrict__ ops) {
+                                                       int pi, const FSeg *__restrict__ segs,
+                                                       const ROp *__restrict__ ops) {
     extern __shared__ unsigned char smem_raw[];
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
     const FPass &P = passes[pi];
@@ -66,64 +198,70 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     const uint64_t base = pdep64(tid, P.nl_mask) | P.fix_val;
     const int *hpos = P.hpos;
 
-    for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[t] = psi[base | scatter_t(t, c, r, hpos)];
+    // HBM -> LDS with U loads in flight per thread.  scatter_t is a bit
+    // deposit, so the thread's part (bits below log2 FUSE_BLOCK) and the
+    // uniform part of t combine by OR.
+    constexpr int U = sizeof(R) == 4 ? 16 : 8;
+    const uint64_t gthr = scatter_t(threadIdx.x & (T - 1u), c, r, hpos);
+    if (T >= FUSE_BLOCK * U) {
+        for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            cvec<R> buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) buf[u] = psi[base | gthr | scatter_t(t0 + u * FUSE_BLOCK, c, r, hpos)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) tile[swz<R>(t0 + u * FUSE_BLOCK + threadIdx.x)] = buf[u];
+        }
+    } else {
+        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
+    }
     __syncthreads();
 
-    const FOp *op0 = ops + P.op_off;
-    int o = 0;
-    while (o < P.nops) {
-        const int type = op0[o].type;
-        if (type == OP_PHASE) {
-            int e = o;
-            while (e < P.nops && op0[e].type == OP_PHASE) ++e;
-            for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) {
-                uint64_t acc = 0;
-                for (int q = o; q < e; ++q) {
-                    const FOp &f = op0[q];
-                    if ((base & f.gmask) == f.gval && (t & f.lmask) == f.lval) acc += f.turns;
-                }
-                if (acc) tile[t] = cmul<R>(tile[t], turn_phase<R>(acc));
+    const uint32_t lines = T >> RB;                  // register lines per tile
+    for (int sg = 0; sg < P.nseg; ++sg) {
+        const FSeg &S = segs[P.seg_off + sg];
+        uint32_t smask = 0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) smask |= 1u << S.pos[i];
+        // swz is XOR-linear and bt, off[m] have disjoint bits, so the slot of
+        // bt | off[m] is swz(bt) ^ swz(off[m]) (the second part is uniform)
+        uint32_t off[1 << RB];
+#pragma unroll
+        for (int m = 0; m < (1 << RB); ++m) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (m >> i & 1) o |= 1u << S.pos[i];
+            off[m] = swz<R>(o);
+        }
+        const ROp *op0 = ops + S.op_off;
+        for (uint32_t line = threadIdx.x; line < lines; line += FUSE_BLOCK) {
+            const uint32_t bt = pdep32(line, (T - 1u) & ~smask);
+            const uint32_t sbt = swz<R>(bt);
+            cvec<R> v[1 << RB];
+#pragma unroll
+            for (int m = 0; m < (1 << RB); ++m) v[m] = tile[sbt ^ off[m]];
+            for (int o = 0; o < S.nops; ++o) {
+                const ROp &f = op0[o];
+                if ((base & f.gmask) != f.gval || (bt & f.tmask) != f.tval) continue;
+                reg_apply<R, RB>(v, f);
             }
-            o = e;
-        } else {
-            const FOp &f = op0[o];
-            if ((base & f.gmask) == f.gval) {
-                if (type == OP_SWAP) {
-                    // elements with bit p0 = 1, p1 = 0 exchange with their mirror
-                    const int lo_p = f.p0 < f.p1 ? f.p0 : f.p1, hi_p = f.p0 < f.p1 ? f.p1 : f.p0;
-                    const uint32_t flip = (1u << f.p0) | (1u << f.p1);
-                    for (uint32_t p = threadIdx.x; p < T / 4; p += FUSE_BLOCK) {
-                        uint32_t t = insert0(insert0(p, lo_p), hi_p) | (1u << f.p0);
-                        if ((t & f.lmask) != f.lval) continue;
-                        const uint32_t u = t ^ flip;
-                        const cvec<R> a = tile[t], b = tile[u];
-                        tile[t] = b;
-                        tile[u] = a;
-                    }
-                } else {
-                    const cvec<R> u00 = cmake<R>((R)f.u[0], (R)f.u[1]), u01 = cmake<R>((R)f.u[2], (R)f.u[3]);
-                    const cvec<R> u10 = cmake<R>((R)f.u[4], (R)f.u[5]), u11 = cmake<R>((R)f.u[6], (R)f.u[7]);
-                    const uint32_t tb = 1u << f.p0;
-                    for (uint32_t p = threadIdx.x; p < T / 2; p += FUSE_BLOCK) {
-                        const uint32_t t0 = insert0(p, f.p0);
-                        if ((t0 & f.lmask) != f.lval) continue;
-                        const cvec<R> a0 = tile[t0], a1 = tile[t0 | tb];
-                        if (type == OP_X) {
-                            tile[t0] = a1;
-                            tile[t0 | tb] = a0;
-                        } else {
-                            tile[t0] = cmac2<R>(u00, a0, u01, a1);
-                            tile[t0 | tb] = cmac2<R>(u10, a0, u11, a1);
-                        }
-                    }
-                }
-            }
-            ++o;
+#pragma unroll
+            for (int m = 0; m < (1 << RB); ++m) tile[sbt ^ off[m]] = v[m];
         }
         __syncthreads();
     }
 
-    for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[t];
+    if (T >= FUSE_BLOCK * U) {
+        for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            cvec<R> buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) buf[u] = tile[swz<R>(t0 + u * FUSE_BLOCK + threadIdx.x)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) psi[base | gthr | scatter_t(t0 + u * FUSE_BLOCK, c, r, hpos)] = buf[u];
+        }
+    } else {
+        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
+    }
 }
 
 // One group of the QFT cascade on the register [lo, lo+m): local qubits are
@@ -154,7 +292,18 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_qft_pass(cvec<R> *__restrict__ p
     auto gidx = [&](uint32_t t) -> uint64_t {
         return base | ((uint64_t)t & cm) | (A.r ? ((uint64_t)(t >> A.c) << A.gpos0) : 0ull);
     };
-    for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[t] = psi[gidx(t)];
+    constexpr int U = sizeof(R) == 4 ? 16 : 8;
+    if (T >= FUSE_BLOCK * U) {
+        for (uint32_t t0 = threadIdx.x; t0 < T; t0 += FUSE_BLOCK * U) {
+            cvec<R> buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) buf[u] = psi[gidx(t0 + u * FUSE_BLOCK)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) tile[t0 + u * FUSE_BLOCK] = buf[u];
+        }
+    } else {
+        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[t] = psi[gidx(t)];
+    }
     __syncthreads();
 
     const R h = (R)0.70710678118654752440;
@@ -182,7 +331,17 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_qft_pass(cvec<R> *__restrict__ p
         }
         __syncthreads();
     }
-    for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[gidx(t)] = tile[t];
+    if (T >= FUSE_BLOCK * U) {
+        for (uint32_t t0 = threadIdx.x; t0 < T; t0 += FUSE_BLOCK * U) {
+            cvec<R> buf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) buf[u] = tile[t0 + u * FUSE_BLOCK];
+#pragma unroll
+            for (int u = 0; u < U; ++u) psi[gidx(t0 + u * FUSE_BLOCK)] = buf[u];
+        }
+    } else {
+        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[gidx(t)] = tile[t];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -200,10 +359,11 @@ static int lds_limit_bytes() {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.sharedMemPerBlock > 0)
         lim = (int)prop.sharedMemPerBlock;
     if (lim > 147456) lim = 147456;   // the largest power-of-two tile (128 KiB) plus headroom
-    bool ok = hipFuncSetAttribute((const void *)k_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
-              hipSuccess;
-    ok &= hipFuncSetAttribute((const void *)k_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
-          hipSuccess;
+    bool ok = true;
+    const void *fk[] = {(const void *)k_fused<float, 5>, (const void *)k_fused<float, 4>,
+                        (const void *)k_fused<float, 3>, (const void *)k_fused<double, 4>,
+                        (const void *)k_fused<double, 3>};
+    for (const void *f : fk) ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) == hipSuccess;
     ok &= hipFuncSetAttribute((const void *)k_qft_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
           hipSuccess;
     ok &= hipFuncSetAttribute((const void *)k_qft_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
@@ -214,7 +374,15 @@ static int lds_limit_bytes() {
     return lim;
 }
 
-static int low_bits_for(sv_dtype dt) { return dt == SV_C128 ? 3 : 4; }   // 128-byte segments
+// low index bits every pass keeps local (contiguous HBM segments of 2^c
+// amplitudes): 128-byte segments by default; SV_FUSED_LOWBITS (2..10) overrides
+static int low_bits_for(sv_dtype dt) {
+    if (const char *e = getenv("SV_FUSED_LOWBITS")) {
+        const int v = atoi(e);
+        if (v >= 2 && v <= 10) return v;
+    }
+    return dt == SV_C128 ? 3 : 4;
+}
 
 static int clamp_k(sv_state s, int max_local) {
     int k = max_local > 0 ? max_local : default_max_local(s->dt);
@@ -397,22 +565,125 @@ static void plan(int n, int kmax, int c0, const std::vector<PGate> &gates, std::
     }
 }
 
+// tile positions a gate must hold in registers
+static uint32_t op_targets(const FOp &f) {
+    if (f.type == OP_PHASE) return 0;
+    if (f.type == OP_SWAP) return (1u << f.p0) | (1u << f.p1);
+    return 1u << f.p0;
+}
+
+static uint32_t compress_bits(uint32_t x, uint32_t S) {   // tile bits in S -> register bits
+    uint32_t r = 0;
+    int j = 0;
+    for (int p = 0; p < 32; ++p)
+        if (S >> p & 1) {
+            if (x >> p & 1) r |= 1u << j;
+            ++j;
+        }
+    return r;
+}
+
+// cut a pass's gate list into register segments of at most RB target positions
+static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, std::vector<ROp> &rops) {
+    const int k = hp.hdr.k;
+    const std::vector<FOp> &ops = hp.ops;
+    size_t i = 0;
+    while (i < ops.size()) {
+        uint32_t S = 0;
+        size_t j = i;
+        while (j < ops.size() && popcount64(S | op_targets(ops[j])) <= RB) S |= op_targets(ops[j++]);
+        // fill with the highest free positions: the threads of a wavefront then
+        // differ in the low tile bits (contiguous LDS slots)
+        for (int p = k - 1; p >= 0 && popcount64(S) < RB; --p) S |= 1u << p;
+        FSeg g;
+        memset(&g, 0, sizeof g);
+        int n = 0;
+        for (int p = 0; p < k; ++p)
+            if (S >> p & 1) g.pos[n++] = p;
+        g.op_off = (int)rops.size();
+        g.nops = (int)(j - i);
+        for (size_t q = i; q < j; ++q) {
+            const FOp &f = ops[q];
+            ROp o;
+            memset(&o, 0, sizeof o);
+            o.type = f.type;
+            o.j0 = f.type == OP_PHASE ? 0 : __builtin_ctz(compress_bits(1u << f.p0, S));
+            o.j1 = f.type == OP_SWAP ? __builtin_ctz(compress_bits(1u << f.p1, S)) : 0;
+            o.rmask = compress_bits((uint32_t)f.lmask & S, S);
+            o.rval = compress_bits((uint32_t)f.lval & S, S);
+            o.tmask = (uint32_t)f.lmask & ~S;
+            o.tval = (uint32_t)f.lval & ~S;
+            o.gmask = f.gmask;
+            o.gval = f.gval;
+            if (f.type == OP_PHASE) {
+                const long double a = ldexpl((long double)(int64_t)f.turns, -64) * 2.0L * 3.14159265358979323846264338327950288L;
+                o.u[0] = (double)cosl(a);
+                o.u[1] = (double)sinl(a);
+            } else {
+                memcpy(o.u, f.u, sizeof o.u);
+            }
+            if (f.type == OP_SWAP) {
+                // SWAP(a, b) = CX(a -> b) CX(b -> a) CX(a -> b), each an X on
+                // a register bit controlled by the other
+                const int a = o.j0, b = o.j1;
+                ROp x = o;
+                x.type = OP_X;
+                for (int r = 0; r < 3; ++r) {
+                    const int tgt = r == 1 ? a : b, ctl = r == 1 ? b : a;
+                    x.j0 = tgt;
+                    x.j1 = 0;
+                    x.rmask = o.rmask | (1u << ctl);
+                    x.rval = o.rval | (1u << ctl);
+                    rops.push_back(x);
+                }
+                g.nops += 2;
+                continue;
+            }
+            rops.push_back(o);
+        }
+        segs.push_back(g);
+        i = j;
+    }
+}
+
+// amplitudes per thread in a segment: 2^5 (complex64) or 2^4 (complex128);
+// SV_FUSED_RB (3..5, complex128 at most 4) overrides
+static int reg_bits_for(sv_dtype dt, int k) {
+    int rb = dt == SV_C128 ? 4 : 5;
+    if (const char *e = getenv("SV_FUSED_RB")) {
+        const int v = atoi(e);
+        if (v >= 3 && v <= (dt == SV_C128 ? 4 : 5)) rb = v;
+    }
+    return rb < k ? rb : k;
+}
+
+template <typename R, int RB>
+static void launch_fused(dim3 grid, size_t lds, hipStream_t st, cvec<R> *psi, const FPass *dp, int i, const FSeg *ds,
+                         const ROp *dops) {
+    hipLaunchKernelGGL((k_fused<R, RB>), grid, dim3(FUSE_BLOCK), lds, st, psi, dp, i, ds, dops);
+}
+
 template <typename R>
 static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
     if (passes.empty()) return SV_OK;
-    size_t nops = 0;
-    for (auto &p : passes) nops += p.ops.size();
-    const size_t hbytes = passes.size() * sizeof(FPass);
-    const size_t obytes = std::max<size_t>(nops, 1) * sizeof(FOp);
-    std::vector<unsigned char> blob(hbytes + obytes);
-    size_t off = 0;
-    for (size_t i = 0; i < passes.size(); ++i) {
-        passes[i].hdr.nops = (int)passes[i].ops.size();
-        passes[i].hdr.op_off = (int)off;
-        memcpy(blob.data() + hbytes + off * sizeof(FOp), passes[i].ops.data(), passes[i].ops.size() * sizeof(FOp));
-        off += passes[i].ops.size();
-        memcpy(blob.data() + i * sizeof(FPass), &passes[i].hdr, sizeof(FPass));
+    const int RB = reg_bits_for(s->dt, passes[0].hdr.k);
+    if (RB < 3) return fail(SV_EUNSUPPORTED, "state too small for fused passes");
+    std::vector<FSeg> segs;
+    std::vector<ROp> rops;
+    for (auto &p : passes) {
+        if (p.hdr.k < RB) return fail(SV_EDEVICE, "pass with %d local qubits (< %d)", p.hdr.k, RB);
+        p.hdr.seg_off = (int)segs.size();
+        segment_pass(p, RB, segs, rops);
+        p.hdr.nseg = (int)segs.size() - p.hdr.seg_off;
     }
+    const size_t hbytes = passes.size() * sizeof(FPass);
+    const size_t sbytes = std::max<size_t>(segs.size(), 1) * sizeof(FSeg);
+    const size_t obytes = std::max<size_t>(rops.size(), 1) * sizeof(ROp);
+    const size_t soff = (hbytes + 255) & ~(size_t)255, ooff = (soff + sbytes + 255) & ~(size_t)255;
+    std::vector<unsigned char> blob(ooff + obytes, 0);
+    for (size_t i = 0; i < passes.size(); ++i) memcpy(blob.data() + i * sizeof(FPass), &passes[i].hdr, sizeof(FPass));
+    memcpy(blob.data() + soff, segs.data(), segs.size() * sizeof(FSeg));
+    memcpy(blob.data() + ooff, rops.data(), rops.size() * sizeof(ROp));
     void *dev = nullptr;
     SV_HIP(hipMallocAsync(&dev, blob.size(), s->stream));
     sv_status st = upload(s, dev, blob.data(), blob.size());
@@ -421,16 +692,17 @@ static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
         return st;
     }
     const FPass *dp = (const FPass *)dev;
-    const FOp *dops = (const FOp *)((unsigned char *)dev + hbytes);
+    const FSeg *ds = (const FSeg *)((unsigned char *)dev + soff);
+    const ROp *dops = (const ROp *)((unsigned char *)dev + ooff);
     for (size_t i = 0; i < passes.size(); ++i) {
         const FPass &h = passes[i].hdr;
         const uint64_t tiles = dim_of(s->n - h.k);
         const size_t lds = ((size_t)1 << h.k) * sizeof(cvec<R>);
-        {
-            TraceScope _ts(s->stream, "fused_pass", 2.0 * (double)dim_of(s->n) * sizeof(cvec<R>), 0.0);
-            hipLaunchKernelGGL(k_fused<R>, tile_grid(tiles), dim3(FUSE_BLOCK), lds, s->stream, (cvec<R> *)s->data, dp,
-                           (int)i, dops);
-        }
+        TraceScope _ts(s->stream, "fused_pass", 2.0 * (double)dim_of(s->n) * sizeof(cvec<R>), 0.0);
+        cvec<R> *psi = (cvec<R> *)s->data;
+        if (RB == 5 && sizeof(R) == 4) launch_fused<float, 5>(tile_grid(tiles), lds, s->stream, (cvec<float> *)psi, dp, (int)i, ds, dops);
+        else if (RB >= 4) launch_fused<R, 4>(tile_grid(tiles), lds, s->stream, psi, dp, (int)i, ds, dops);
+        else launch_fused<R, 3>(tile_grid(tiles), lds, s->stream, psi, dp, (int)i, ds, dops);
     }
     hipError_t e = hipGetLastError();
     hipFreeAsync(dev, s->stream);

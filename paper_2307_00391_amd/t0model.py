@@ -330,9 +330,9 @@ if __name__ == "__main__":
     import json
     import os
     ap = argparse.ArgumentParser(description="train and evaluate the learned T0 predictor on the GPU")
-    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--train", type=int, default=10000)
     ap.add_argument("--eval", type=int, default=256)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--smooth", type=int, default=1)
     ap.add_argument("--out", default="gpurun_out/t0model.json")
