@@ -11,8 +11,14 @@
 //
 //   k_pipe_a: generate the state after phase estimation (product state over
 //             the clock bits, relabelled so the cascades need no swaps), then
-//             the inverse-QFT cascade on G1          -> ancilla = 0 half
-//   k_pipe_b: inverse-QFT cascade on G2, eigenvalue inversion a1 = (1/y) a0
+//             the inverse-QFT cascade on G1.  The G1 stages act on G1 qubits
+//             only, so the result is still a product between the groups:
+//             psi(j, y1, y2) = T_j(y1) * B_j(y2), with T_j the G1 transform of
+//             the column's G1 factor and B_j(y2) the product of the phases of
+//             the set G2 bits.  k_pipe_a therefore runs for y2 = 0 only and
+//             leaves T in the clock rows y1 < 2^g1 of the ancilla = 0 half.
+//   k_pipe_b: every amplitude of the post-G1 state from T and the G2 phases,
+//             inverse-QFT cascade on G2, eigenvalue inversion a1 = (1/y) a0
 //             (FP64 sums of P(a=1) and the norm), QFT cascade on G2
 //                                                     -> ancilla = 1 half
 //   k_pipe_c: QFT cascade on G1, the conjugate phases of the uncompute, and
@@ -193,11 +199,20 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     double *s2t = reinterpret_cast<double *>(TW + (1 << G));        // [2^G] s_y^2 2^-G
     double *n2t = s2t + (1 << G);                                    // [2^G] (c_y^2 + s_y^2) 2^-G
     R *srt = reinterpret_cast<R *>(n2t + (1 << G));                  // [2^G] s_y 2^-G
+    cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
     __shared__ double red[2][NT / 64];
     uint64_t j0, o;
     tile_coords(A, j0, o);               // o = value of the G1 bits
-    const int g1 = A.g1;
+    const int g1 = A.g1, n_c = A.n_c;
+    const uint64_t *__restrict__ F = S.F;
+    // the G1 table entry of the thread's first phase-A line, read before the
+    // tables are built (its latency overlaps that work)
+    const cvec<R> t0 = psi[(o << A.n_s) | (j0 + (threadIdx.x & (C - 1)))];
     fill_twiddles<R>(TW, G, g1, o);
+    for (int e = threadIdx.x; e < G * C; e += NT) {     // one phase per thread
+        const int b = e / C, c = e - b * C;
+        om[b * C + c] = turn_phase<R>(F[(j0 + c) * n_c + (n_c - 1 - (g1 + b))]);
+    }
     // rotation of clock value y = o + l 2^g1 (natural order after the inverse
     // transform): sin = 1/y (y >= 1).  The two groups of G Hadamards around it
     // omit their 1/sqrt(2) each, so 2^-G is folded into the rotation (and into
@@ -212,20 +227,31 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         srt[l] = (R)(sd * fold);
     }
     __syncthreads();
+    // the phase-A stages use the first 2^RA - 1 twiddles with indices fixed by
+    // the register position: keep them in registers for the whole tile
+    cvec<R> twr[(1 << RA) - 1];
+#pragma unroll
+    for (int i = 0; i < (1 << RA) - 1; ++i) twr[i] = TW[i];
     const int nla = C << RB, nlb = C << RA;
-    // phase A (inverse cascade, low bits of G2), straight from the ancilla = 0 half
+    // phase A (inverse cascade, low bits of G2): the amplitudes at y1 = o and
+    // y2 = (lhi << RA) | k are T_j(o) times the phases of the set bits of y2
     for (int line = threadIdx.x; line < nla; line += NT) {
         const int c = line & (C - 1), lhi = line >> A.cl;
         const uint64_t col = j0 + c;
         cvec<R> v[1 << RA];
+        cvec<R> base = line == (int)threadIdx.x ? t0 : psi[(o << A.n_s) | col];
+        for (int b = 0; b < RB; ++b)
+            if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
+        v[0] = base;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) {
-            const uint64_t s = o | ((((uint64_t)lhi << RA) | k) << g1);
-            v[k] = psi[(s << A.n_s) | col];
+        for (int b = 0; b < RA; ++b) {
+            const cvec<R> w = om[b * C + c];
+#pragma unroll
+            for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
         }
 #pragma unroll
         for (int jb = 0; jb < RA; ++jb)
-            stage<R, RA, true>(v, jb, TW + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+            stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) tile[(((size_t)lhi << RA) | k) * C + c] = v[k];
     }
@@ -241,15 +267,20 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         for (int jb = RA; jb < G; ++jb)
             stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
                                [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        // weights times |a|^2 summed over the line in the amplitude precision,
+        // then accumulated in FP64
+        R lpa = 0, lnt = 0;
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) {
             const int l = (k << RA) | llo;
-            const double a2 = (double)v[k].x * (double)v[k].x + (double)v[k].y * (double)v[k].y;
-            pa += s2t[l] * a2;
-            nt += n2t[l] * a2;
+            const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
+            lpa += (R)s2t[l] * a2;
+            lnt += (R)n2t[l] * a2;
             const R sr = srt[l];
             v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
         }
+        pa += (double)lpa;
+        nt += (double)lnt;
 #pragma unroll
         for (int jb = G - 1; jb >= RA; --jb)
             stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
@@ -267,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
 #pragma unroll
         for (int jb = RA - 1; jb >= 0; --jb)
-            stage<R, RA, false>(v, jb, TW + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+            stage<R, RA, false>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) {
             const uint64_t s = o | ((((uint64_t)lhi << RA) | k) << g1);
@@ -315,26 +346,50 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     uint64_t j0, o;
     tile_coords(A, j0, o);               // o = value of the G2 bits
     const int n_c = A.n_c;
+    const int nla = C << RB, nlb = C << RA;
+    // the thread's first phase-B line is read before the tables are built, so
+    // the HBM latency overlaps that work
+    cvec<R> v0[1 << RB];
+    if ((int)threadIdx.x < nlb) {
+        const int c = threadIdx.x & (C - 1), llo = threadIdx.x >> A.cl;
+#pragma unroll
+        for (int k = 0; k < (1 << RB); ++k) {
+            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
+            v0[k] = psi[A.abit | (s << A.n_s) | (j0 + c)];
+        }
+    }
     fill_twiddles<R>(TW, G, 0, 0);
-    for (int c = threadIdx.x; c < C; c += NT) {
-        const uint64_t j = j0 + c;
-        uint64_t th = 0;
-        for (int b = G; b < n_c; ++b)
-            if (o >> (b - G) & 1) th += F[j * n_c + (n_c - 1 - b)];
-        cc[c] = turn_phase<R>(0ull - th);
-        for (int b = 0; b < G; ++b) om[b * C + c] = turn_phase<R>(0ull - F[j * n_c + (n_c - 1 - b)]);
+    // per-column phase tables, one entry per thread: om[b][c] for b < G and cc[c] (b = G)
+    for (int e = threadIdx.x; e < (G + 1) * C; e += NT) {
+        const int b = e / C, c = e - b * C;
+        const uint64_t *Fj = F + (j0 + c) * n_c;
+        if (b < G) {
+            om[b * C + c] = turn_phase<R>(0ull - Fj[n_c - 1 - b]);
+        } else {
+            uint64_t th = 0;
+            for (int q = G; q < n_c; ++q)
+                if (o >> (q - G) & 1) th += Fj[n_c - 1 - q];
+            cc[c] = turn_phase<R>(0ull - th);
+        }
     }
     __syncthreads();
-    const int nla = C << RB, nlb = C << RA;
+    cvec<R> twr[(1 << RA) - 1];          // phase-A twiddles (fixed by register position)
+#pragma unroll
+    for (int i = 0; i < (1 << RA) - 1; ++i) twr[i] = TW[i];
     // phase B first: the forward cascade starts at the top bit of G1
     for (int line = threadIdx.x; line < nlb; line += NT) {
         const int c = line & (C - 1), llo = line >> A.cl;
         const uint64_t col = j0 + c;
         cvec<R> v[1 << RB];
+        if (line == (int)threadIdx.x) {
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) {
-            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
-            v[k] = psi[A.abit | (s << A.n_s) | col];
+            for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < (1 << RB); ++k) {
+                const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
+                v[k] = psi[A.abit | (s << A.n_s) | col];
+            }
         }
 #pragma unroll
         for (int jb = G - 1; jb >= RA; --jb)
@@ -353,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
 #pragma unroll
         for (int jb = RA - 1; jb >= 0; --jb)
-            stage<R, RA, false>(v, jb, TW + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
+            stage<R, RA, false>(v, jb, twr + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
         // conj phase of clock index (o << G) | (lhi << RA) | k
         cvec<R> ph[1 << RA];
         cvec<R> base = cc[c];
@@ -366,12 +421,15 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
 #pragma unroll
             for (int k = 0; k < (1 << b); ++k) ph[k | (1 << b)] = cmul<R>(ph[k], w);
         }
+        R lr = 0, li = 0;                // the line's sum, then FP64
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) {
             const cvec<R> p = cmul<R>(v[k], ph[k]);
-            zr += (double)p.x;
-            zi += (double)p.y;
+            lr += p.x;
+            li += p.y;
         }
+        zr += (double)lr;
+        zi += (double)li;
     }
     // every line of a thread has the thread's column (the line stride NT is a multiple of C)
     zs[threadIdx.x] = make_double2(zr, zi);
@@ -410,12 +468,15 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
         attr_done = true;
     }
     if (lds > (size_t)kLim) return fail(SV_EUNSUPPORTED, "pipeline tile needs %zu bytes of LDS", lds);
+    // algorithmic bytes: the ancilla half is 2^(n_s + n_c) amplitudes; the G1
+    // table 2^(n_s + g1)
     const double half = (double)A.N * (double)(1ull << A.n_c) * sizeof(cvec<R>) * grid.z;
+    const double table = (double)A.N * (double)(1ull << A.g1) * sizeof(cvec<R>) * grid.z;
     if (which == 0) {
-        TraceScope ts(st, "pipe_a_init_iqft", half, 0.0);
+        TraceScope ts(st, "pipe_a_init_iqft", table, 0.0);
         hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else if (which == 1) {
-        TraceScope ts(st, "pipe_b_iqft_ry_qft", 2.0 * half, 0.0);
+        TraceScope ts(st, "pipe_b_iqft_ry_qft", half + table, 0.0);
         hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else {
         TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
@@ -467,7 +528,7 @@ static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
     const size_t C = (size_t)1 << cl;
     size_t b = ((C << g) + ((size_t)1 << g)) * e;
     if (which != 1) b += (size_t)(g + 1) * C * e;
-    if (which == 1) b += ((size_t)1 << g) * (2 * sizeof(double) + e / 2);
+    if (which == 1) b += ((size_t)1 << g) * (2 * sizeof(double) + e / 2) + (size_t)g * C * e;
     if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
     return b;
 }
@@ -493,7 +554,8 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
         P.A[w] = A;
         P.A[w].cl = cl[w];
         P.nt[w] = nt[w];
-        const uint64_t tiles = (A.N >> cl[w]) << (n_c - g);
+        // k_pipe_a writes the G1 table only (G2 value 0)
+        const uint64_t tiles = w == 0 ? (A.N >> cl[w]) : (A.N >> cl[w]) << (n_c - g);
         P.grid[w] = tiles <= 0x7fffffffull ? dim3((unsigned)tiles, 1, nsolves)
                                            : dim3(1u << 30, (unsigned)(tiles >> 30), nsolves);
         P.lds[w] = pipe_lds(w, cl[w], g, e, nt[w]);

@@ -283,4 +283,5 @@ def test_learned_t0_beats_textbook_choice():
     Fbest = Fte.max(axis=1)
     assert Fp.mean() - Ft.mean() > 0.02, (Fp.mean(), Ft.mean(), Fbest.mean())
     assert Fp.mean() - Fu.mean() > 0.02, (Fp.mean(), Fu.mean())
-    assert np.all(Fp <= Fbest + 0.05)
+    # a T0 between grid points may beat the grid's best; on average it does not
+    assert Fp.mean() <= Fbest.mean() + 0.01, (Fp.mean(), Fbest.mean())
