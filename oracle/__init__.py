@@ -35,6 +35,7 @@ def _load():
     lib.orc_qft.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc_apply_ctrl_unitary.argtypes = [_c128p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc_qsp.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, ctypes.c_int]
     lib.orc_norm2.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_norm2.restype = ctypes.c_double
     lib.orc_postselect.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -128,6 +129,18 @@ def eigh(A):
     V = np.zeros((N, N), dtype=np.complex128)
     _check(_load().orc_eigh(N, A, lam, V), "eigh")
     return lam, V
+
+
+def qsp(n, q_lo, b, levels=-1):
+    """QSP-1 binary-tree preparation of b on the register [q_lo, q_lo + m)
+    of an n-qubit state from |0...0> (see oracle.c); returns the state."""
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.complex128))
+    m = b.size.bit_length() - 1
+    if b.size != 1 << m:
+        raise ValueError("b must have 2^m entries")
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    _check(_load().orc_qsp(psi, int(n), int(q_lo), int(m), b, int(levels)), "qsp")
+    return psi
 
 
 def hhl(A, b, n_c, T0):

@@ -433,6 +433,75 @@ int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
     return rc;
 }
 
+/*
+ * QSP-1: the binary-tree state preparation of the appendix "Quantum State
+ * Preparation" (Grover-Rudolph tree in the form of Prakash), written as the
+ * circuit it describes.  From |0...0> it prepares b / |b| on the register
+ * [q_lo, q_lo + m) (register value r = sum of bit j of r times qubit q_lo + j).
+ *
+ * Tree: the leaves are the weights |b_r|^2; an inner node's weight is the sum
+ * of its two children.  Level l (0 = root) decides qubit q_lo + m - 1 - l, the
+ * register's most significant qubit first, so a node at level l is the value
+ * p of the l qubits above that one (p's most significant bit is the top
+ * qubit).  For every node with weight w > 0 the circuit applies
+ * Ry(t) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]], controlled on those l
+ * qubits taking the values of p, with cos^2(t/2) = (zero child) / w: the
+ * node's amplitude splits into its children's amplitudes.  A node of weight
+ * 0 gets no gate.  After the last level the amplitudes are |b_r| / |b|; one
+ * phase gate per basis state restores arg(b_r), a diag(e^{i a}, 1) or
+ * diag(1, e^{i a}) on qubit q_lo controlled on the other register qubits.
+ *
+ * levels < m stops after that many levels (no phases): the intermediate
+ * states of the appendix's worked example.
+ */
+int orc_qsp(cplx *psi, int n, int q_lo, int m, const cplx *b, int levels)
+{
+    if (m < 1 || q_lo < 0 || q_lo + m > n || m > 24) return ORC_EINVAL;
+    const uint64_t R = (uint64_t)1 << m, dim = (uint64_t)1 << n;
+    double *w = (double *)calloc(2 * R, sizeof(double));   /* heap order: node (l, p) at 2^l + p */
+    if (!w) return ORC_ENOMEM;
+    double tot = 0.0;
+    for (uint64_t r = 0; r < R; ++r) {
+        w[R + r] = creal(b[r]) * creal(b[r]) + cimag(b[r]) * cimag(b[r]);
+        tot += w[R + r];
+    }
+    if (!(tot > 0.0)) { free(w); return ORC_EINVAL; }
+    for (uint64_t k = R - 1; k >= 1; --k) w[k] = w[2 * k] + w[2 * k + 1];
+    for (uint64_t i = 0; i < dim; ++i) psi[i] = 0.0;
+    psi[0] = 1.0;
+    int ctrls[32], cvals[32];
+    const int L = levels < 0 || levels > m ? m : levels;
+    for (int l = 0; l < L; ++l) {
+        const int t = q_lo + m - 1 - l;
+        for (int j = 0; j < l; ++j) ctrls[j] = q_lo + m - 1 - j;   /* the qubits above t */
+        for (uint64_t p = 0; p < ((uint64_t)1 << l); ++p) {
+            const uint64_t node = ((uint64_t)1 << l) + p;
+            if (!(w[node] > 0.0)) continue;
+            const double c = sqrt(w[2 * node] / w[node]), s = sqrt(w[2 * node + 1] / w[node]);
+            for (int j = 0; j < l; ++j) cvals[j] = (int)((p >> (l - 1 - j)) & 1);
+            const double ry[8] = {c, 0.0, -s, 0.0, s, 0.0, c, 0.0};
+            int rc = orc_apply_gate(psi, n, t, ry, ctrls, cvals, l);
+            if (rc != ORC_OK) { free(w); return rc; }
+        }
+    }
+    if (L == m) {
+        for (uint64_t r = 0; r < R; ++r) {
+            if (w[R + r] == 0.0) continue;
+            const double a = carg(b[r]);
+            if (a == 0.0) continue;
+            const cplx e = cexp(I * a);
+            double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+            if (r & 1) { u[6] = creal(e); u[7] = cimag(e); }
+            else { u[0] = creal(e); u[1] = cimag(e); }
+            for (int j = 1; j < m; ++j) { ctrls[j - 1] = q_lo + j; cvals[j - 1] = (int)((r >> j) & 1); }
+            int rc = orc_apply_gate(psi, n, q_lo, u, ctrls, cvals, m - 1);
+            if (rc != ORC_OK) { free(w); return rc; }
+        }
+    }
+    free(w);
+    return ORC_OK;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
