@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--no-mfma", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-qsp", action="store_true")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -305,6 +306,35 @@ def main():
                         "best_factor_hist": np.bincount(Fm.argmax(1), minlength=16).tolist()}
         log(f"[bench] sweep {nsol} solves in {el * 1e3:.2f} ms per replay ({nsol / el:.0f} solves/s), "
             f"prepare {prep:.2f} s")
+
+    # ---------------- QSP-1 state preparation on a 24-qubit register ----------------
+    if not args.no_qsp:
+        m = 24
+        log(f"[bench] qsp-1: {m}-qubit register, gate by gate and in one pass")
+        rng = np.random.default_rng(2024)
+        bq = rng.standard_normal(1 << m) + 1j * rng.standard_normal(1 << m)
+        qs = B.State(m, "c64", device=dev)
+        rec = {"qubits": m}
+        for mode, name in ((0, "gate_by_gate"), (1, "one_pass")):
+            B.sv_qsp_prepare(qs.h, bq, 0, mode)
+            torch.cuda.synchronize()
+            B.sv_trace_enable(True)
+            t = time.perf_counter()
+            B.sv_qsp_prepare(qs.h, bq, 0, mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            tr = B.sv_trace_report()
+            B.sv_trace_enable(False)
+            kern = sum(v["ms"] for v in tr.values())
+            byts = sum(v["bytes"] for v in tr.values())
+            rec[name] = {"wall_ms": 1e3 * el, "kernel_ms": kern, "hbm_gbs": byts / (kern * 1e-3) / 1e9,
+                         "kernels": {k: v["launches"] for k, v in tr.items()}}
+        got = qs.get()
+        rec["max_abs_err_vs_b"] = float(np.abs(got - bq / np.linalg.norm(bq)).max())
+        out["qsp1"] = rec
+        qs.close()
+        del qs
+        torch.cuda.empty_cache()
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------
     if not args.no_cpu:

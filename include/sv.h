@@ -298,6 +298,27 @@ int sv_tune_report(char *buf, int len);
  * real symmetric A goes to the real routines).  "" before the first call. */
 const char *sv_last_eigensolver(void);
 
+/* QSP-1, the binary-tree state preparation of the appendix "Quantum State
+ * Preparation" (Grover-Rudolph, in Prakash's binary-tree form): prepares
+ * b / |b| on the register [q_lo, q_lo + m) (register value r: bit j of r is
+ * qubit q_lo + j), every other qubit |0>, overwriting the whole state.
+ * Tree: leaf r carries |b_r|^2, an inner node the sum of its two children;
+ * level l (0 = root) decides qubit q_lo + m - 1 - l, and node p of level l
+ * (the value of the l qubits above it) is the gate
+ * Ry(t) = [[cos t/2, -sin t/2], [sin t/2, cos t/2]] with
+ * cos^2(t/2) = zero-child / node weight, controlled on those qubits taking
+ * the value p (no gate for a node of weight 0).  A diagonal over the
+ * register then restores arg(b_r).  All angles are computed on the host in
+ * FP64 and rounded once to the state's precision.
+ *   mode 0: the circuit gate by gate: |0...0>, one Ry on the top qubit, one
+ *           uniformly controlled Ry pass per further level, the diagonal;
+ *   mode 1: the same circuit applied to |0...0> in one write pass (each
+ *           amplitude is the product of the rotation entries on its path).
+ * b: host, 2^m complex FP64 interleaved, borrowed.  1 <= m <= 26.
+ * Synchronises the state's stream.  Errors: SV_EINVAL (register, mode,
+ * non-finite b), SV_EZERONORM (b = 0), SV_ENOMEM. */
+sv_status sv_qsp_prepare(sv_state s, const double *b, int q_lo, int m, int mode);
+
 /* ------------------------------------------------------------------------
  * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
  * study of Fig. 4b): many HHL instances of uneven size, each over its own

@@ -90,6 +90,7 @@ _SIGS = {
     "sv_hhl_plan_spectrum": ([_P, _DP, _DP], _I),
     "sv_hhl_plan_free": ([_P], _I),
     "sv_last_eigensolver": ([], ctypes.c_char_p),
+    "sv_qsp_prepare": ([_P, _P, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
     "sv_batch_num_solves": ([_P], _I),
@@ -387,6 +388,15 @@ def sv_hhl_plan_free(plan):
 
 def sv_version():
     return lib().sv_version().decode()
+
+
+def sv_qsp_prepare(h, b, q_lo=0, mode=1):
+    """QSP-1 binary-tree preparation of b / |b| on the register [q_lo, q_lo + m)."""
+    b, bf = _f64(b)
+    m = b.size.bit_length() - 1
+    if b.size != 1 << m:
+        raise ValueError("b must have 2^m entries")
+    _check(lib().sv_qsp_prepare(h, _ptr(bf), int(q_lo), m, int(mode)), "sv_qsp_prepare")
 
 
 # --------------------------------------------------------------------------
