@@ -42,7 +42,7 @@ def _load():
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
     lib.orc_eigh.argtypes = [ctypes.c_int, _c128p, _f64p, _c128p]
     lib.orc_hhl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _c128p, _c128p, _c128p, _c128p,
-                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -143,8 +143,9 @@ def qsp(n, q_lo, b, levels=-1):
     return psi
 
 
-def hhl(A, b, n_c, T0):
-    """Gate-level HHL (see oracle.c): returns (psi, x, p_post, p_anc)."""
+def hhl(A, b, n_c, T0, signed_clock=False):
+    """Gate-level HHL (see oracle.c): returns (psi, x, p_post, p_anc).
+    signed_clock reads the clock as a two's-complement value (indefinite A)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     b = np.ascontiguousarray(b, dtype=np.complex128)
     N = A.shape[0]
@@ -154,5 +155,6 @@ def hhl(A, b, n_c, T0):
     psi = np.zeros(1 << (n_s + n_c + 1), dtype=np.complex128)
     x = np.zeros(N, dtype=np.complex128)
     pp, pa = ctypes.c_double(0), ctypes.c_double(0)
-    _check(_load().orc_hhl(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa)), "hhl")
+    _check(_load().orc_hhl(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa),
+                           int(bool(signed_clock))), "hhl")
     return psi, x, pp.value, pa.value

@@ -349,7 +349,8 @@ static void build_uk(int N, const cplx *V, const double *phi, int k, cplx *Uk)
  *      2^{-n_c} on lam T0 / 2 pi)
  *   5. inverse QFT on the clock register
  *   6. eigenvalue inversion: for clock value y >= 1, rotate the ancilla by
- *      Ry(theta_y) with sin(theta_y / 2) = C / lam~_y = 1 / y, where
+ *      Ry(theta_y) with sin(theta_y / 2) = C / lam~_y = 1 / y (y read as a
+ *      two's-complement value with signed_clock, for indefinite A), where
  *      lam~_y = 2 pi y / (2^n_c T0) and C = 2 pi / (2^n_c T0) is the least
  *      count; y = 0 is left untouched
  *   7. uncompute: QFT on the clock, controlled U_k^H for k = n_c-1..0,
@@ -360,7 +361,7 @@ static void build_uk(int N, const cplx *V, const double *phi, int k, cplx *Uk)
  * p_anc = P(a=1).
  */
 int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
-            cplx *psi, cplx *x_out, double *p_post, double *p_anc)
+            cplx *psi, cplx *x_out, double *p_post, double *p_anc, int signed_clock)
 {
     if (n_s < 1 || n_c < 1 || n_s + n_c + 1 > 30 || !(T0 > 0.0)) return ORC_EINVAL;
     const int N = 1 << n_s, n = n_s + n_c + 1;
@@ -402,10 +403,13 @@ int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
     /* 5. inverse QFT on the clock */
     orc_qft(psi, n, n_s, n_c, 1);
 
-    /* 6. controlled-Ry eigenvalue inversion, one clock value at a time */
+    /* 6. controlled-Ry eigenvalue inversion, one clock value at a time; with
+     *    a signed clock the values y >= 2^(n_c-1) stand for y - 2^n_c (two's
+     *    complement), so negative eigenvalues invert with their sign */
     const uint64_t Y = (uint64_t)1 << n_c;
     for (uint64_t y = 1; y < Y; ++y) {
-        double s = 1.0 / (double)y, c = sqrt(1.0 - s * s);
+        const double ys = (signed_clock && y >= Y / 2) ? (double)y - (double)Y : (double)y;
+        double s = 1.0 / ys, c = sqrt(1.0 - s * s);
         for (uint64_t x = 0; x < (uint64_t)N; ++x) {
             uint64_t i0 = x | (y << n_s), i1 = i0 | ((uint64_t)1 << anc);
             cplx a0 = psi[i0], a1 = psi[i1];

@@ -23,22 +23,24 @@ def fejer(delta, M):
     return out
 
 
-def g_of_phi(phi, n_c, chunk=64):
-    """g(phi) = sum_{y=1}^{M-1} K(phi - y/M) / y, vectorised in chunks of phi."""
+def g_of_phi(phi, n_c, chunk=64, signed=False):
+    """g(phi) = sum_{y=1}^{M-1} K(phi - y/M) / y, vectorised in chunks of phi.
+    signed: clock values y >= M/2 invert as y - M (K has period 1 in phi)."""
     M = 1 << n_c
     y = np.arange(1, M, dtype=np.float64)
+    ys = np.where(y >= M // 2, y - M, y) if signed else y
     phi = np.asarray(phi, dtype=np.float64)
     out = np.empty_like(phi)
     for a in range(0, phi.size, chunk):
         d = phi[a:a + chunk, None] - y[None, :] / M
-        out[a:a + chunk] = (fejer(d, M) / y[None, :]).sum(axis=1)
+        out[a:a + chunk] = (fejer(d, M) / ys[None, :]).sum(axis=1)
     return out
 
 
-def hhl_closed_form(A, b, n_c, T0):
+def hhl_closed_form(A, b, n_c, T0, signed=False):
     lam, V = np.linalg.eigh(A)
     beta = V.conj().T @ (b / np.linalg.norm(b))
-    g = g_of_phi(lam * T0 / (2 * math.pi), n_c)
+    g = g_of_phi(lam * T0 / (2 * math.pi), n_c, signed=signed)
     z = V @ (beta * g)
     p = float(np.sum(np.abs(beta * g) ** 2))
     return z / math.sqrt(p), p
