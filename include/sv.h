@@ -206,7 +206,12 @@ typedef struct {
                       2: eigen-frame, one kernel per step (state write, inverse QFT on
                       the ancilla = 0 half, rotation into the ancilla = 1 half, QFT there,
                       projection) */
-    int signed_clock;  /* must be 0: unsigned clock, A positive definite */
+    int signed_clock;  /* 0: unsigned clock, A must be positive definite;
+                          1: two's-complement clock, y >= 2^(n_c-1) stands for
+                          y - 2^n_c, so negative eigenvalues invert with their sign
+                          (A Hermitian and non-singular, e.g. the Hermitian dilation
+                          [[0, M], [M^H, 0]] of a non-Hermitian M); choose T0 so
+                          that |lambda| T0 / 2 pi < 1/2 */
 } sv_hhl_params;
 
 typedef struct {
@@ -231,7 +236,8 @@ typedef struct {
  * circuit leaves it).  After mode 0 the state holds the final circuit state;
  * after modes 1 and 2 its contents are unspecified.
  * Errors: SV_EINVAL, SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM (|b| = 0 or
- * p_post = 0), SV_EUNSUPPORTED (signed_clock != 0), SV_ENOMEM, SV_EDEVICE. */
+ * p_post = 0), SV_ENOTPOSDEF (lambda_min <= 0 with signed_clock = 0), SV_EINVAL
+ * (a zero eigenvalue with signed_clock = 1), SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm,
                  sv_hhl_result *res, double *x_out);
 

@@ -300,12 +300,12 @@ def sv_postselect(h, n, mask, value, want_vector=True):
     return p.value, out
 
 
-def sv_hhl(h, A, b, n_c, T0, mode=0):
+def sv_hhl(h, A, b, n_c, T0, mode=0, signed_clock=False):
     A, Af = _f64(A)
     b, bf = _f64(b)
     N = A.shape[0]
     n_s = N.bit_length() - 1
-    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), 0)
+    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), int(bool(signed_clock)))
     res = sv_hhl_result()
     x = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_hhl(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)), "sv_hhl")
@@ -366,10 +366,10 @@ def sv_hhl_prepare(h, A_hi, A_lo=None):
     return p
 
 
-def sv_hhl_run(plan, h, b, n_c, T0, mode=1):
+def sv_hhl_run(plan, h, b, n_c, T0, mode=1, signed_clock=False):
     b, bf = _f64(b)
     n_s = b.size.bit_length() - 1
-    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), 0)
+    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), int(bool(signed_clock)))
     res = sv_hhl_result()
     x = np.zeros(b.size, dtype=np.complex128)
     _check(lib().sv_hhl_run(plan, h, _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)), "sv_hhl_run")

@@ -45,7 +45,7 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
 template <typename R>
 sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
 template <typename R>
-sv_status pipe_run(sv_state s, int n_s, int n_c, const double2 *beta, const uint64_t *F, double *part,
+sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, const double2 *beta, const uint64_t *F, double *part,
                    double2 *zpart, uint64_t *nparts);
 
 // --------------------------------------------------------------------------
@@ -459,13 +459,15 @@ void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<
     }
 }
 
-// (cos, sin) of the inversion rotation for every clock value: sin = 1/y, y >= 1
-void inversion_table(int n_c, std::vector<double> &cs) {
+// (cos, sin) of the inversion rotation for every clock value: sin = 1/y,
+// y >= 1; a signed clock reads y >= 2^(n_c-1) as y - 2^n_c (two's complement)
+void inversion_table(int n_c, std::vector<double> &cs, bool sgn) {
     const size_t M = (size_t)1 << n_c;
     cs.assign(2 * M, 0.0);
     cs[0] = 1.0;
     for (size_t y = 1; y < M; ++y) {
-        const double sv = 1.0 / (double)y;
+        const double ys = (sgn && y >= M / 2) ? (double)y - (double)M : (double)y;
+        const double sv = 1.0 / ys;
         cs[2 * y] = sqrt(1.0 - sv * sv);
         cs[2 * y + 1] = sv;
     }
@@ -505,7 +507,7 @@ static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_
                             double *x_out);
 
 template <typename R>
-static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c,
+static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c, bool sgn,
                                double T0, bool fused, sv_hhl_result *res, double *x_out) {
     const int n_s = E.n_s;
     const uint64_t N = dim_of(n_s);
@@ -545,7 +547,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         SV_TRY(need(w.part, 2 * nbp * sizeof(double)));
         SV_TRY(need(w.zpart, (size_t)rows * N * sizeof(double2)));
         uint64_t nparts = 0;
-        SV_TRY(pipe_run<R>(s, n_s, n_c, (const double2 *)w.beta.p, (const uint64_t *)w.F.p, (double *)w.part.p,
+        SV_TRY(pipe_run<R>(s, n_s, n_c, sgn, (const double2 *)w.beta.p, (const uint64_t *)w.F.p, (double *)w.part.p,
                            (double2 *)w.zpart.p, &nparts));
         if (nparts > nbp) return fail(SV_EDEVICE, "pipeline partial count exceeds its buffer");
         SV_TRY(need(w.tmp2, 512 * sizeof(double)));
@@ -560,7 +562,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         return eig_finish(s, E, w, N, res, x_out);
     }
     std::vector<double> cs;
-    inversion_table(n_c, cs);
+    inversion_table(n_c, cs, sgn);
     SV_TRY(need(w.cs, cs.size() * sizeof(double)));
     SV_TRY(upload(s, w.cs.p, cs.data(), cs.size() * sizeof(double)));
     // 1. the state after phase estimation, written directly (ancilla = 0 half)
@@ -631,7 +633,7 @@ __global__ void k_kron_matrix(double2 *__restrict__ V, const double2 *__restrict
 }
 
 template <typename R>
-static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, Workspace &w,
+static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, Workspace &w, bool sgn,
                                    int n_s, int n_c, double T0, const double *b, sv_hhl_result *res, double *x_out) {
     const int N = 1 << n_s;
     const hipStream_t st = s->stream;
@@ -667,7 +669,7 @@ static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vec
     for (int k = 0; k < n_c; ++k) SV_TRY(ctrl_unitary_impl<R>(s, U + (size_t)k * NN, n_s, n_s + (n_c - 1 - k), 1, 0));
     SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, 0, 0}, 0));
     std::vector<double> cs;
-    inversion_table(n_c, cs);
+    inversion_table(n_c, cs, sgn);
     SV_TRY(sv_apply_uniform_ry(s, n_s + n_c, n_s, n_c, cs.data(), -1, 0));
     SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 0, 0, 0}, 0));
     for (int k = n_c - 1; k >= 0; --k)
@@ -683,7 +685,7 @@ static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vec
 
 static sv_status check_params(sv_state s, const sv_hhl_params *prm, sv_hhl_result *res) {
     if (!prm || !res) return fail(SV_EINVAL, "params/result is NULL");
-    if (prm->signed_clock) return fail(SV_EUNSUPPORTED, "signed clock register is not implemented");
+    if (prm->signed_clock != 0 && prm->signed_clock != 1) return fail(SV_EINVAL, "signed_clock must be 0 or 1");
     if (prm->n_s < 1 || prm->n_c < 1 || prm->n_s + prm->n_c + 1 != s->n)
         return fail(SV_EINVAL, "n_s %d + n_c %d + 1 != %d qubits", prm->n_s, prm->n_c, s->n);
     if (!(prm->T0 > 0.0) || !isfinite(prm->T0)) return fail(SV_EINVAL, "T0 must be positive");
@@ -774,11 +776,16 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
     std::vector<double> bhat;
     SV_TRY(normalise_b(b, N, bhat));
     SV_TRY(sv_hhl_plan_spectrum(p, &res->lambda_min, &res->lambda_max));
-    if (!(res->lambda_min > 0.0)) return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
+    const bool sgn = prm->signed_clock == 1;
+    if (!sgn && !(res->lambda_min > 0.0))
+        return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
+    if (sgn)
+        for (double v : p->E.lam)
+            if (!(v != 0.0)) return fail(SV_EINVAL, "A is singular (a zero eigenvalue)");
     if (prm->mode >= 1) {
         const bool fused = prm->mode == 1;
-        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, prm->T0, fused, res, x_out)
-                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, prm->T0, fused, res, x_out);
+        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, sgn, prm->T0, fused, res, x_out)
+                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, sgn, prm->T0, fused, res, x_out);
     }
     // gate-faithful: dense eigenvectors
     if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
@@ -793,8 +800,9 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
         dV = (const double2 *)p->V_dense.p;
     }
     if (s->dt == SV_C64)
-        return gate_faithful_run<float>(s, dV, p->E.lam, p->w, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
-    return gate_faithful_run<double>(s, dV, p->E.lam, p->w, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
+        return gate_faithful_run<float>(s, dV, p->E.lam, p->w, sgn, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res,
+                                        x_out);
+    return gate_faithful_run<double>(s, dV, p->E.lam, p->w, sgn, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
 }
 
 sv_status sv_hhl_plan_free(sv_hhl_plan p) {
