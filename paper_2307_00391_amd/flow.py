@@ -129,6 +129,76 @@ def rms(a, b):
     return float(np.sqrt(np.mean((np.asarray(a) - np.asarray(b)) ** 2)))
 
 
+def one_shot_system(ch: Channel, scheme: str, m: int, p: int):
+    """The unrolled systems of the appendix on finite differences: blocks
+    u^0 .. u^{m+p} of the field, row 0 u^0 = u_in, rows 1..m one time step,
+    rows m+1..m+p the copies u^i - u^{i-1} = 0 that lift the post-selection
+    probability.  FE: u^i - (I + A dt) u^{i-1} = f dt; BE: (I - A dt) u^i -
+    u^{i-1} = f dt (A_be1 = I - A dt).  Returns (A_os, b_os)."""
+    N = ch.N
+    K = m + p + 1
+    I = np.eye(N)
+    Adt = I - ch.A_be1                    # A dt
+    A_os = np.zeros((K * N, K * N))
+    b_os = np.zeros(K * N)
+    A_os[:N, :N] = I
+    b_os[:N] = ch.u0
+    for i in range(1, K):
+        r = slice(i * N, (i + 1) * N)
+        prev = slice((i - 1) * N, i * N)
+        if i <= m:
+            if scheme == "fe":
+                A_os[r, r] = I
+                A_os[r, prev] = -(I + Adt)
+            elif scheme == "be":
+                A_os[r, r] = ch.A_be1
+                A_os[r, prev] = -I
+            else:
+                raise ValueError(scheme)
+            b_os[r] = ch.src
+        else:
+            A_os[r, r] = I
+            A_os[r, prev] = -I
+    return A_os, b_os
+
+
+@dataclass
+class OneShot:
+    u: np.ndarray          # (m + p + 1, N) from the HHL solution
+    u_classical: np.ndarray
+    p_post: float
+    fidelity: float
+
+
+def one_shot(ch: Channel, scheme: str, m: int, p: int, n_c: int, dtype: str = "c64", mode: int = 1) -> OneShot:
+    """Solve the unrolled system in one HHL run: the system is not Hermitian,
+    so its Hermitian dilation H = [[0, A], [A^T, 0]] with right-hand side
+    [b; 0] is solved with a signed clock (H has eigenvalues +-sigma, the
+    singular values of A), and the lower half of the solution is A^-1 b.
+    The length again comes from p_post."""
+    A_os, b_os = one_shot_system(ch, scheme, m, p)
+    n = A_os.shape[0]
+    if n & (n - 1):
+        raise ValueError("(m + p + 1) N must be a power of two")
+    H = np.block([[np.zeros((n, n)), A_os], [A_os.T, np.zeros((n, n))]])
+    bb = np.concatenate([b_os, np.zeros(n)])
+    n_s = (2 * n).bit_length() - 1
+    smax = np.linalg.norm(A_os, 2)
+    T0 = 2 * math.pi * 0.45 / smax
+    st = B.State(n_s + n_c + 1, dtype)
+    try:
+        x, res = B.sv_hhl(st.h, H, bb, n_c, T0, mode, signed_clock=True)
+    finally:
+        st.close()
+    C = 2 * math.pi / (2 ** n_c * T0)
+    full = np.linalg.norm(bb) * math.sqrt(res.p_post) / C * x.real
+    u = full[n:].reshape(m + p + 1, ch.N)
+    uc = np.linalg.solve(A_os, b_os).reshape(m + p + 1, ch.N)
+    xc = uc.ravel() / np.linalg.norm(uc)
+    F = abs(np.vdot(xc, x[n:])) / np.linalg.norm(x[n:])
+    return OneShot(u, uc, res.p_post, float(F))
+
+
 def sweep_clock_qubits(kind="poiseuille", N=16, Re=10.0, dt=0.5, n_cs=range(4, 17), dtype="c64", tol=1e-6,
                        max_steps=600, log=print):
     """Converged iterative-BE profiles for several clock sizes (the main
@@ -153,6 +223,29 @@ def sweep_clock_qubits(kind="poiseuille", N=16, Re=10.0, dt=0.5, n_cs=range(4, 1
     return {"kind": kind, "N": N, "Re": Re, "dt": dt, "dtype": dtype, "tol": tol, "rows": rows}
 
 
+def sweep_one_shot(kind="poiseuille", N=4, Re=10.0, dt=0.18, m=27, p=4, n_cs=range(6, 15), dtype="c64",
+                   log=print):
+    """One-shot FE and BE (dilated, signed clock) for several clock sizes:
+    the final block against the classical solution of the same system and
+    against the analytical series, and the fidelity of the whole solution."""
+    import time
+    ch = channel(kind, N, Re, dt)
+    ua = analytic(ch, m * dt)
+    rows = []
+    for scheme in ("fe", "be"):
+        for n_c in n_cs:
+            t = time.perf_counter()
+            r = one_shot(ch, scheme, m, p, n_c, dtype)
+            el = time.perf_counter() - t
+            rows.append({"scheme": scheme, "n_c": int(n_c), "eps_rms_vs_classical": rms(r.u[-1], r.u_classical[-1]),
+                         "eps_rms_vs_analytic": rms(r.u[-1], ua),
+                         "classical_vs_analytic": rms(r.u_classical[-1], ua), "fidelity": r.fidelity,
+                         "p_post": r.p_post, "seconds": el})
+            log(f"[one-shot] {scheme} n_c {n_c:2d}: rms vs classical {rows[-1]['eps_rms_vs_classical']:.3e}, "
+                f"vs analytic {rows[-1]['eps_rms_vs_analytic']:.3e}, F {r.fidelity:.5f}, p {r.p_post:.2e}")
+    return {"kind": kind, "N": N, "Re": Re, "dt": dt, "m": m, "p": p, "dtype": dtype, "rows": rows}
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -166,9 +259,14 @@ if __name__ == "__main__":
     ap.add_argument("--nc-max", type=int, default=16)
     ap.add_argument("--dtype", default="c64")
     ap.add_argument("--out", default="gpurun_out/flow_sweep.json")
+    ap.add_argument("--one-shot", action="store_true", help="the unrolled FE/BE systems (N=4, m=27, p=4)")
     a = ap.parse_args()
-    res = sweep_clock_qubits(a.kind, a.N, a.Re, a.dt, range(a.nc_min, a.nc_max + 1), a.dtype,
+    if a.one_shot:
+        res = sweep_one_shot(a.kind, n_cs=range(a.nc_min, a.nc_max + 1), dtype=a.dtype,
                              log=lambda s: print(s, flush=True))
+    else:
+        res = sweep_clock_qubits(a.kind, a.N, a.Re, a.dt, range(a.nc_min, a.nc_max + 1), a.dtype,
+                                 log=lambda s: print(s, flush=True))
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(res, f, indent=1)

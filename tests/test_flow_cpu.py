@@ -41,3 +41,20 @@ def test_channel_matrix_is_spd_and_scaled():
     assert ev.min() > 1.0 and abs(ev.max() - (1 + 0.2 / 4.0 * 4 / h ** 2 * np.sin(8 * np.pi * h / 2) ** 2)) < 1e-9
     with pytest.raises(ValueError):
         flow.channel("poiseuille", N=12)
+
+
+@pytest.mark.parametrize("scheme", ["fe", "be"])
+@pytest.mark.parametrize("kind", ["poiseuille", "couette"])
+def test_one_shot_system_equals_marching(scheme, kind):
+    ch = flow.channel(kind, N=4, Re=10.0, dt=0.15)
+    m, p = 11, 4
+    A, b = flow.one_shot_system(ch, scheme, m, p)
+    u = np.linalg.solve(A, b).reshape(m + p + 1, 4)
+    march = [ch.u0]
+    I = np.eye(4)
+    Adt = I - ch.A_be1
+    for _ in range(m):
+        prev = march[-1]
+        march.append((I + Adt) @ prev + ch.src if scheme == "fe" else np.linalg.solve(ch.A_be1, prev + ch.src))
+    march += [march[-1]] * p
+    assert np.abs(u - np.array(march)).max() <= 1e-12

@@ -55,3 +55,31 @@ def test_converged_profile_improves_with_clock_qubits():
         assert run.converged_at > 0
         errs[n_c] = flow.rms(run.u[-1], steady)
     assert errs[12] < errs[6] and errs[12] < 0.05, errs
+
+
+@pytest.mark.parametrize("scheme", ["fe", "be"])
+def test_one_shot_matches_oracle(scheme):
+    ch = flow.channel("poiseuille", N=4, Re=10.0, dt=0.15)
+    m, p, n_c = 5, 2, 8
+    got = flow.one_shot(ch, scheme, m, p, n_c, dtype="c128")
+    A_os, b_os = flow.one_shot_system(ch, scheme, m, p)
+    n = A_os.shape[0]
+    H = np.block([[np.zeros((n, n)), A_os], [A_os.T, np.zeros((n, n))]])
+    bb = np.concatenate([b_os, np.zeros(n)])
+    T0 = 2 * math.pi * 0.45 / np.linalg.norm(A_os, 2)
+    _, x, pp, _ = oracle.hhl(H, bb, n_c, T0, signed_clock=True)
+    C = 2 * math.pi / (2 ** n_c * T0)
+    ref = (np.linalg.norm(bb) * math.sqrt(pp) / C * x.real)[n:].reshape(m + p + 1, ch.N)
+    assert abs(got.p_post - pp) <= 1e-12
+    assert np.abs(got.u - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_one_shot_converges_to_the_classical_solution():
+    ch = flow.channel("poiseuille", N=4, Re=10.0, dt=0.15)
+    m, p = 11, 4
+    errs = {}
+    for n_c in (8, 13):
+        r = flow.one_shot(ch, "be", m, p, n_c, dtype="c64")
+        errs[n_c] = np.abs(r.u[-1] - r.u_classical[-1]).max()
+        assert r.fidelity > 0.5
+    assert errs[13] < errs[8] and errs[13] < 0.1, errs
