@@ -199,8 +199,11 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         delete b;
         return s;
     };
-    // --- per instance: eigen-decomposition, beta, exact-solution coefficients
+    // --- eigen-decompositions: real symmetric instances of one size in one
+    // batched call, the others one at a time
     std::vector<DevBuf *> V(n_inst), lamd(n_inst), beta(n_inst), cex(n_inst);
+    std::vector<std::vector<double>> lams(n_inst);
+    std::map<int, std::vector<int>> real_by_n;
     for (int i = 0; i < n_inst; ++i) {
         const sv_batch_instance &I = inst[i];
         const int N = 1 << I.n_s;
@@ -214,9 +217,33 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         b->bufs.push_back(lamd[i]);
         b->bufs.push_back(beta[i]);
         b->bufs.push_back(cex[i]);
-        std::vector<double> lam;
-        st = eigh_device(&b->ctx, I.A, N, *V[i], lam);
+        bool real = true;
+        for (size_t k = 0; k < (size_t)N * N && real; ++k) real = I.A[2 * k + 1] == 0.0;
+        if (real && N > 1) {
+            real_by_n[N].push_back(i);
+        } else {
+            st = eigh_device(&b->ctx, I.A, N, *V[i], lams[i]);
+            if (st != SV_OK) return fail_del(st);
+        }
+    }
+    for (auto &kv : real_by_n) {
+        std::vector<const double *> As;
+        std::vector<DevBuf *> dVs;
+        std::vector<std::vector<double>> ls;
+        for (int i : kv.second) {
+            As.push_back(inst[i].A);
+            dVs.push_back(V[i]);
+        }
+        sv_status st = eigh_device_batched(&b->ctx, As, kv.first, dVs, ls);
         if (st != SV_OK) return fail_del(st);
+        for (size_t q = 0; q < kv.second.size(); ++q) lams[kv.second[q]] = std::move(ls[q]);
+    }
+    // --- per instance: beta = V^H b^ and the exact-solution coefficients
+    for (int i = 0; i < n_inst; ++i) {
+        const sv_batch_instance &I = inst[i];
+        const int N = 1 << I.n_s;
+        sv_status st = SV_OK;
+        const std::vector<double> &lam = lams[i];
         if (!(lam[0] > 0.0)) return fail_del(fail(SV_ENOTPOSDEF, "instance %d: lambda_min <= 0", i));
         double nb = 0.0;
         for (int j = 0; j < 2 * N; ++j) nb += I.b[j] * I.b[j];

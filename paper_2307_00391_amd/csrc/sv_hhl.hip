@@ -444,6 +444,57 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
 
 const char *eigh_last_solver() { return g_eigh_used.c_str(); }
 
+// Several real symmetric N x N matrices at once: one strided-batched
+// divide-and-conquer call, each result validated by eig_residual_ok; a
+// matrix whose result fails the check goes through eigh_device alone.
+sv_status eigh_device_batched(sv_state s, const std::vector<const double *> &As, int N, std::vector<DevBuf *> &dVs,
+                              std::vector<std::vector<double>> &lams) {
+    const int cnt = (int)As.size();
+    lams.assign(cnt, {});
+    if (!cnt) return SV_OK;
+    const size_t NN = (size_t)N * N;
+    std::vector<double> Ar(NN * cnt);
+    for (int i = 0; i < cnt; ++i)
+        for (size_t k = 0; k < NN; ++k) Ar[i * NN + k] = As[i][2 * k];   // symmetric: row- = column-major
+    DevBuf dA, dD, dE, dInfo;
+    SV_TRY(dA.alloc(NN * cnt * sizeof(double)));
+    SV_TRY(dD.alloc((size_t)N * cnt * sizeof(double)));
+    SV_TRY(dE.alloc((size_t)N * cnt * sizeof(double)));
+    SV_TRY(dInfo.alloc(cnt * sizeof(int)));
+    SV_TRY(upload(s, dA.p, Ar.data(), Ar.size() * sizeof(double)));
+    rocblas_handle h;
+    SV_TRY(blas_handle(s->stream, &h));
+    const rocblas_status rs = rocsolver_dsyevd_strided_batched(
+        h, rocblas_evect_original, rocblas_fill_upper, N, (double *)dA.p, N, (rocblas_stride)NN, (double *)dD.p,
+        (rocblas_stride)N, (double *)dE.p, (rocblas_stride)N, (rocblas_int *)dInfo.p, cnt);
+    std::vector<double> D((size_t)N * cnt);
+    std::vector<int> info(cnt, 1);
+    if (rs == rocblas_status_success) {
+        SV_TRY(download(s, D.data(), dD.p, D.size() * sizeof(double)));
+        SV_TRY(download(s, info.data(), dInfo.p, cnt * sizeof(int)));
+    }
+    std::vector<double> Vh(2 * NN);
+    for (int i = 0; i < cnt; ++i) {
+        bool ok = rs == rocblas_status_success && info[i] == 0;
+        if (ok) {
+            lams[i].assign(D.begin() + (size_t)i * N, D.begin() + (size_t)(i + 1) * N);
+            SV_TRY(dVs[i]->alloc(NN * sizeof(double2)));
+            hipLaunchKernelGGL(k_real_cm_to_complex, dim3(grid1(NN)), dim3(256), 0, s->stream, (double2 *)dVs[i]->p,
+                               (const double *)dA.p + (size_t)i * NN, N);
+            SV_HIP(hipGetLastError());
+            SV_TRY(download(s, Vh.data(), dVs[i]->p, Vh.size() * sizeof(double)));
+            double worst = 0.0;
+            ok = eig_residual_ok(As[i], N, lams[i], Vh, &worst);
+        }
+        if (ok) {
+            g_eigh_used = "dsyevd_strided_batched";
+        } else {
+            SV_TRY(eigh_device(s, As[i], N, *dVs[i], lams[i]));
+        }
+    }
+    return SV_OK;
+}
+
 // turn fractions frac(phi_j 2^k), phi_j = lam_j T0 / 2 pi, as 64-bit fixed point
 void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<uint64_t> &F) {
     const size_t N = lam.size();
