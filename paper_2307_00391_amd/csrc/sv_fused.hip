@@ -375,13 +375,13 @@ static int lds_limit_bytes() {
 }
 
 // low index bits every pass keeps local (contiguous HBM segments of 2^c
-// amplitudes): 128-byte segments by default; SV_FUSED_LOWBITS (2..10) overrides
+// amplitudes): 256-byte segments by default; SV_FUSED_LOWBITS (2..10) overrides
 static int low_bits_for(sv_dtype dt) {
     if (const char *e = getenv("SV_FUSED_LOWBITS")) {
         const int v = atoi(e);
         if (v >= 2 && v <= 10) return v;
     }
-    return dt == SV_C128 ? 3 : 4;
+    return dt == SV_C128 ? 4 : 5;
 }
 
 static int clamp_k(sv_state s, int max_local) {
@@ -583,26 +583,58 @@ static uint32_t compress_bits(uint32_t x, uint32_t S) {   // tile bits in S -> r
     return r;
 }
 
-// cut a pass's gate list into register segments of at most RB target positions
+// cut a pass's gate list into register segments of at most RB target
+// positions.  Gates that touch disjoint qubits commute, so a segment takes
+// every gate that is ready (all earlier gates it does not commute with are
+// placed) and whose targets fit, in program order, not only a contiguous run.
 static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, std::vector<ROp> &rops) {
     const int k = hp.hdr.k;
     const std::vector<FOp> &ops = hp.ops;
-    size_t i = 0;
-    while (i < ops.size()) {
+    const size_t n = ops.size();
+    // conflict: a target of one is a target or a local control of the other
+    // (controls on non-local bits never coincide with a target: targets are local)
+    std::vector<std::vector<int>> pred(n);
+    for (size_t b = 0; b < n; ++b) {
+        const uint32_t tb = op_targets(ops[b]), qb = tb | (uint32_t)ops[b].lmask;
+        for (size_t a = 0; a < b; ++a) {
+            const uint32_t ta = op_targets(ops[a]), qa = ta | (uint32_t)ops[a].lmask;
+            if ((ta & qb) || (tb & qa)) pred[b].push_back((int)a);
+        }
+    }
+    std::vector<char> done(n, 0);
+    size_t left = n;
+    while (left) {
         uint32_t S = 0;
-        size_t j = i;
-        while (j < ops.size() && popcount64(S | op_targets(ops[j])) <= RB) S |= op_targets(ops[j++]);
+        std::vector<int> seg;
+        for (bool progress = true; progress;) {
+            progress = false;
+            for (size_t b = 0; b < n; ++b) {
+                if (done[b]) continue;
+                bool ready = true;
+                for (int a : pred[b])
+                    if (!done[a]) {
+                        ready = false;
+                        break;
+                    }
+                if (!ready || popcount64(S | op_targets(ops[b])) > RB) continue;
+                S |= op_targets(ops[b]);
+                done[b] = 1;
+                --left;
+                seg.push_back((int)b);
+                progress = true;
+            }
+        }
         // fill with the highest free positions: the threads of a wavefront then
         // differ in the low tile bits (contiguous LDS slots)
         for (int p = k - 1; p >= 0 && popcount64(S) < RB; --p) S |= 1u << p;
         FSeg g;
         memset(&g, 0, sizeof g);
-        int n = 0;
+        int npos = 0;
         for (int p = 0; p < k; ++p)
-            if (S >> p & 1) g.pos[n++] = p;
+            if (S >> p & 1) g.pos[npos++] = p;
         g.op_off = (int)rops.size();
-        g.nops = (int)(j - i);
-        for (size_t q = i; q < j; ++q) {
+        g.nops = (int)seg.size();
+        for (int q : seg) {
             const FOp &f = ops[q];
             ROp o;
             memset(&o, 0, sizeof o);
@@ -642,7 +674,6 @@ static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, st
             rops.push_back(o);
         }
         segs.push_back(g);
-        i = j;
     }
 }
 
