@@ -538,6 +538,44 @@ sv_status kron_apply(hipStream_t st, double2 *out, const double2 *in, double2 *t
     return SV_OK;
 }
 
+// out[q][c] = conj(in[c][q]) for an n x n row-major matrix
+__global__ void k_conj_transpose(double2 *__restrict__ out, const double2 *__restrict__ in, int n) {
+    const uint64_t total = (uint64_t)n * n;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = i / n, c = i % n;
+        const double2 v = in[c * n + q];
+        out[i] = make_double2(v.x, -v.y);
+    }
+}
+
+// The basis change of a plan on the matrix cores (rocBLAS zgemm, FP64):
+// out = (V_hi (x) V_lo) in, or with the conjugate transposes (adjoint).  The
+// vector is the row-major n_hi x n_lo matrix X; column-major it is X^T, so
+//   along the low axis:  X V^T  ->  (X V^T)^T = V X^T = op_T(Vbuf) X^T
+//   along the high axis: V X    ->  (V X)^T  = X^T V^T = X^T Vbuf
+// where Vbuf, the row-major V, reads as V^T column-major.
+static sv_status kron_apply_frame(sv_state s, double2 *out, const double2 *in, double2 *tmp, const EigFrame &E,
+                                  int adjoint) {
+    rocblas_handle h;
+    SV_TRY(blas_handle(s->stream, &h));
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    const rocblas_int nh = E.n_hi, nl = E.n_lo;
+    const double2 *Whi = (const double2 *)(adjoint ? E.VH_hi.p : E.V_hi.p);
+    if (nl > 1) {
+        const double2 *Wlo = (const double2 *)(adjoint ? E.VH_lo.p : E.V_lo.p);
+        if (rocblas_zgemm(h, rocblas_operation_transpose, rocblas_operation_none, nl, nh, nl, &one,
+                          (const rocblas_double_complex *)Wlo, nl, (const rocblas_double_complex *)in, nl, &zero,
+                          (rocblas_double_complex *)tmp, nl) != rocblas_status_success)
+            return fail(SV_EDEVICE, "rocblas_zgemm (low axis) failed");
+        in = tmp;
+    }
+    if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, nl, nh, nh, &one,
+                      (const rocblas_double_complex *)in, nl, (const rocblas_double_complex *)Whi, nh, &zero,
+                      (rocblas_double_complex *)out, nl) != rocblas_status_success)
+        return fail(SV_EDEVICE, "rocblas_zgemm (high axis) failed");
+    return SV_OK;
+}
+
 static int pick_log_len(uint64_t N, int n_c) {
     // enough workgroups to fill the chip: ~8 per CU over the column blocks
     const uint64_t colblocks = (N + 63) / 64;
@@ -587,8 +625,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     SV_HIP(hipGetLastError());
     SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
     // beta = V^H b^
-    SV_TRY(kron_apply(st, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
-                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 1));
+    SV_TRY(kron_apply_frame(s, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, E, 1));
 
     if (fused && pipe_supported(n_s, n_c)) {
         // fused three-kernel pipeline: (state + inverse QFT on the low clock bits),
@@ -654,8 +691,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
 static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
                             double *x_out) {
     const hipStream_t st = s->stream;
-    SV_TRY(kron_apply(st, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, (const double2 *)E.V_hi.p,
-                      E.n_hi, (const double2 *)E.V_lo.p, E.n_lo, 0));
+    SV_TRY(kron_apply_frame(s, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, E, 0));
     std::vector<double> sums(2), xz(2 * N);
     SV_TRY(download(s, sums.data(), w.sum.p, 2 * sizeof(double)));
     SV_TRY(download(s, xz.data(), w.x.p, N * sizeof(double2)));
@@ -792,6 +828,18 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
             for (int a = 0; a < nh; ++a)
                 for (int q = 0; q < nl; ++q) p->E.lam[(size_t)a * nl + q] = mu[a] + nu[q];
         }
+    }
+    // conjugate transposes for the basis change into the eigen-frame
+    if (st == SV_OK) st = p->E.VH_hi.alloc((size_t)nh * nh * sizeof(double2));
+    if (st == SV_OK && m_lo) st = p->E.VH_lo.alloc((size_t)nl * nl * sizeof(double2));
+    if (st == SV_OK) {
+        hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nh * nh)), dim3(256), 0, s->stream,
+                           (double2 *)p->E.VH_hi.p, (const double2 *)p->E.V_hi.p, nh);
+        if (m_lo)
+            hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
+                               (double2 *)p->E.VH_lo.p, (const double2 *)p->E.V_lo.p, nl);
+        const hipError_t he = hipGetLastError();
+        if (he != hipSuccess) st = hip_fail(he, "k_conj_transpose");
     }
     if (st == SV_OK) st = p->E.lam_dev.alloc(p->E.lam.size() * sizeof(double));
     if (st == SV_OK) st = upload(s, p->E.lam_dev.p, p->E.lam.data(), p->E.lam.size() * sizeof(double));

@@ -50,6 +50,7 @@ __global__ void k_turn_table(uint64_t *__restrict__ F, const double *__restrict_
 struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;
     DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
+    DevBuf VH_hi, VH_lo;          // their conjugate transposes (for the V^H basis change)
     DevBuf lam_dev;               // the eigenvalues on the device (FP64)
     std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
 };
