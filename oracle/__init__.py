@@ -36,6 +36,8 @@ def _load():
     lib.orc_apply_ctrl_unitary.argtypes = [_c128p, ctypes.c_int, _c128p, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc_qsp.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, ctypes.c_int]
+    lib.orc_lcu_derivative.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc_spectral_derivative.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc_norm2.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_norm2.restype = ctypes.c_double
     lib.orc_postselect.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -158,3 +160,20 @@ def hhl(A, b, n_c, T0, signed_clock=False):
     _check(_load().orc_hhl(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa),
                            int(bool(signed_clock))), "hhl")
     return psi, x, pp.value, pa.value
+
+
+def lcu_derivative(psi, q_lo, m, sel_lo):
+    """QPP finite-difference gradient by LCU on the register [q_lo, q_lo + m)
+    with the two select qubits [sel_lo, sel_lo + 2) (see oracle.c), in place.
+    From select |00>, the select-|00> block ends as (S - S^T) phi / 2 = h D phi."""
+    _check(_load().orc_lcu_derivative(psi, _nqubits(psi), int(q_lo), int(m), int(sel_lo)), "lcu_derivative")
+    return psi
+
+
+def spectral_derivative(psi, q_lo, m, anc):
+    """QPP spectral gradient on the register [q_lo, q_lo + m) with the
+    block-encoding qubit `anc` (see oracle.c), in place.  From anc = |0>,
+    the anc = 1 block ends as dphi/dy / (2 pi (2^(m-1) - 1)), y_j = j / 2^m."""
+    _check(_load().orc_spectral_derivative(psi, _nqubits(psi), int(q_lo), int(m), int(anc)),
+           "spectral_derivative")
+    return psi

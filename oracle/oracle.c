@@ -506,6 +506,102 @@ int orc_qsp(cplx *psi, int n, int q_lo, int m, const cplx *b, int levels)
     return ORC_OK;
 }
 
+/*
+ * QPP velocity gradient by a linear combination of unitaries (appendix
+ * "Velocity gradients - LCU method").
+ *
+ * The finite-difference operator is the central first difference on the
+ * register's N = 2^m points with zero Dirichlet walls,
+ *     (D u)_j = (u_{j+1} - u_{j-1}) / 2h,   u_{-1} = u_N = 0.
+ * The paper does not spell out the unitaries; the decomposition used here:
+ * with the cyclic shift (C u)_j = u_{(j+1) mod N} and the reflection
+ * R0 = I - 2|0><0|, the truncated shift (S u)_j = u_{j+1} (0 past the end)
+ * is (C + C R0) / 2, so
+ *     4h D = 2 S - 2 S^T = C + C R0 - C^T - R0 C^T:
+ * four unitaries U_0..U_3 = C, C R0, -C^T, -R0 C^T with equal weights.
+ * The appendix's steps on the two select qubits [sel_lo, sel_lo + 2)
+ * (select value i = bit sel_lo + 2 bit sel_lo+1):
+ *     V  = H (x) H          (the equal-weight state of the coefficients),
+ *     G  = sum_i |i><i| (x) U_i on the register,
+ *     V^dagger = H (x) H.
+ * G is written out as the action of each U_i on the register amplitudes.
+ * A select register that starts in |00> ends with h D |phi> in its |00>
+ * component.
+ */
+int orc_lcu_derivative(cplx *psi, int n, int q_lo, int m, int sel_lo)
+{
+    if (n < 3 || n > 40 || m < 1 || q_lo < 0 || q_lo + m > n) return ORC_EINVAL;
+    if (sel_lo < 0 || sel_lo + 2 > n) return ORC_EINVAL;
+    if (sel_lo + 2 > q_lo && sel_lo < q_lo + m) return ORC_EINVAL;    /* overlaps the register */
+    const double r = 1.0 / sqrt(2.0);
+    const double h[8] = {r, 0.0, r, 0.0, r, 0.0, -r, 0.0};
+    int rc;
+    if ((rc = orc_apply_gate(psi, n, sel_lo, h, NULL, NULL, 0)) != ORC_OK) return rc;
+    if ((rc = orc_apply_gate(psi, n, sel_lo + 1, h, NULL, NULL, 0)) != ORC_OK) return rc;
+    const uint64_t dim = (uint64_t)1 << n, N = (uint64_t)1 << m, rmask = (N - 1) << q_lo;
+    cplx *src = (cplx *)malloc(sizeof(cplx) * dim);
+    if (!src) return ORC_ENOMEM;
+    memcpy(src, psi, sizeof(cplx) * dim);
+#pragma omp parallel for schedule(static)
+    for (int64_t ii = 0; ii < (int64_t)dim; ++ii) {
+        const uint64_t i = (uint64_t)ii;
+        const int sel = (int)((i >> sel_lo) & 3u);
+        const uint64_t j = (i >> q_lo) & (N - 1), rest = i & ~rmask;
+        const uint64_t up = (j + 1) & (N - 1), dn = (j + N - 1) & (N - 1);
+        cplx v;
+        switch (sel) {
+        case 0: v = src[rest | (up << q_lo)]; break;                              /* C       */
+        case 1: v = (up == 0 ? -1.0 : 1.0) * src[rest | (up << q_lo)]; break;      /* C R0    */
+        case 2: v = -src[rest | (dn << q_lo)]; break;                             /* -C^T    */
+        default: v = -(j == 0 ? -1.0 : 1.0) * src[rest | (dn << q_lo)]; break;     /* -R0 C^T */
+        }
+        psi[i] = v;
+    }
+    free(src);
+    if ((rc = orc_apply_gate(psi, n, sel_lo, h, NULL, NULL, 0)) != ORC_OK) return rc;
+    return orc_apply_gate(psi, n, sel_lo + 1, h, NULL, NULL, 0);
+}
+
+/*
+ * QPP velocity gradient in spectral space (appendix "Velocity gradients -
+ * spectral method"), in the order its text gives: the inverse QFT on the
+ * register (kernel exp(-2 pi i j k / N)), the diagonal
+ *     Lambda_k = 2 pi i k (k < N/2),  0 (k = N/2),  2 pi i (k - N) (k > N/2),
+ * then the QFT back.  Lambda is not unitary: it is applied as the |1> block
+ * of a rotation of qubit `anc` controlled on the register value k,
+ *     e^{i arg Lambda_k} Ry(t_k),  sin(t_k / 2) = |Lambda_k| / Lambda_max,
+ * with Lambda_max = 2 pi (N/2 - 1), one multi-controlled gate per k.
+ * With anc starting in |0>, its |1> component at the end is
+ * F Lambda F^-1 phi / Lambda_max: d/dy of phi on the periodic grid y_j = j/N.
+ * Needs m >= 2 (for N = 2 every Lambda_k is 0).
+ */
+int orc_spectral_derivative(cplx *psi, int n, int q_lo, int m, int anc)
+{
+    if (n < 3 || n > 40 || m < 2 || m > 30 || q_lo < 0 || q_lo + m > n) return ORC_EINVAL;
+    if (anc < 0 || anc >= n || (anc >= q_lo && anc < q_lo + m)) return ORC_EINVAL;
+    const uint64_t N = (uint64_t)1 << m;
+    int rc = orc_qft(psi, n, q_lo, m, 1);
+    if (rc != ORC_OK) return rc;
+    const double lmax = 2.0 * ORC_PI * ((double)(N / 2) - 1.0);
+    int ctrls[30], cvals[30];
+    for (int b = 0; b < m; ++b) ctrls[b] = q_lo + b;
+    for (uint64_t k = 0; k < N; ++k) {
+        double mag, arg;
+        if (k < N / 2) { mag = 2.0 * ORC_PI * (double)k; arg = ORC_PI / 2; }
+        else if (k == N / 2) { mag = 0.0; arg = 0.0; }
+        else { mag = 2.0 * ORC_PI * (double)(N - k); arg = -ORC_PI / 2; }
+        if (mag == 0.0) continue;                                   /* identity */
+        const double s = mag / lmax, c = sqrt(fmax(0.0, 1.0 - s * s));
+        const cplx e = cexp(I * arg);
+        const cplx u00 = c * e, u01 = -s * e, u10 = s * e, u11 = c * e;
+        const double u[8] = {creal(u00), cimag(u00), creal(u01), cimag(u01),
+                             creal(u10), cimag(u10), creal(u11), cimag(u11)};
+        for (int b = 0; b < m; ++b) cvals[b] = (int)((k >> b) & 1u);
+        if ((rc = orc_apply_gate(psi, n, anc, u, ctrls, cvals, m)) != ORC_OK) return rc;
+    }
+    return orc_qft(psi, n, q_lo, m, 0);
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
