@@ -325,6 +325,41 @@ const char *sv_last_eigensolver(void);
  * non-finite b), SV_EZERONORM (b = 0), SV_ENOMEM. */
 sv_status sv_qsp_prepare(sv_state s, const double *b, int q_lo, int m, int mode);
 
+/* QPP velocity gradient by a linear combination of unitaries (appendix
+ * "Velocity gradients - LCU method"; the derivative module of the main
+ * text's "Quantum Post-processing Protocol").  The finite-difference
+ * operator is the central first difference with zero Dirichlet walls on the
+ * N = 2^m points of the register [q_lo, q_lo + m) (point j = register value
+ * j): (D u)_j = (u_{j+1} - u_{j-1}) / 2h, u_{-1} = u_N = 0.  With the cyclic
+ * shift (C u)_j = u_{(j+1) mod N} and R0 = I - 2|0><0|, 4h D = C + C R0 - C^T
+ * - R0 C^T: four unitaries of equal weight.  The circuit on the select
+ * qubits [sel_lo, sel_lo + 2) (select value i = bit sel_lo + 2 * bit
+ * sel_lo+1) is V^dagger G V, V = H (x) H, G = sum_i |i><i| (x) U_i with
+ * U = (C, C R0, -C^T, -R0 C^T).  It is unitary and acts on any input; from
+ * select |00> the select-|00> block becomes h D u = (S - S^T) u / 2 (S the
+ * truncated shift), so the probability of select = 00 is h^2 |D u|^2 / |u|^2.
+ *   mode 0: gate by gate (Hadamards, multi-controlled X cascades for C and
+ *           C^T, a multi-controlled phase for R0, one Z for the signs);
+ *   mode 1: the whole circuit in one read and one write of the state (LDS
+ *           tiles); needs m <= 11 (complex64) or m <= 10 (complex128), else
+ *           SV_EUNSUPPORTED.
+ * Errors: SV_EINVAL (register or select outside the state, overlapping,
+ * m > 30, mode). */
+sv_status sv_lcu_derivative(sv_state s, int q_lo, int m, int sel_lo, int mode);
+
+/* QPP velocity gradient in spectral space (appendix "Velocity gradients -
+ * spectral method"), in the order its text gives: inverse QFT on the
+ * register [q_lo, q_lo + m) (exact index order), the wavenumber diagonal
+ * Lambda_k = 2 pi i k (k < N/2), 0 (k = N/2), 2 pi i (k - N) (k > N/2), and
+ * the QFT back.  Lambda is applied as the |1> block of a rotation of qubit
+ * `anc` controlled on the register value k: e^{i arg Lambda_k} Ry(t_k) with
+ * sin(t_k/2) = |Lambda_k| / Lambda_max, Lambda_max = 2 pi (N/2 - 1).  From
+ * anc = |0>, the anc = 1 block ends as (du/dy) / Lambda_max on the periodic
+ * grid y_j = j / N.  max_local as in sv_apply_circuit.
+ * Errors: SV_EINVAL (m < 2 or > 30, register outside the state, anc inside
+ * the register or outside the state). */
+sv_status sv_spectral_derivative(sv_state s, int q_lo, int m, int anc, int max_local);
+
 /* ------------------------------------------------------------------------
  * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
  * study of Fig. 4b): many HHL instances of uneven size, each over its own

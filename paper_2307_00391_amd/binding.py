@@ -91,6 +91,8 @@ _SIGS = {
     "sv_hhl_plan_free": ([_P], _I),
     "sv_last_eigensolver": ([], ctypes.c_char_p),
     "sv_qsp_prepare": ([_P, _P, _I, _I, _I], _I),
+    "sv_lcu_derivative": ([_P, _I, _I, _I, _I], _I),
+    "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
     "sv_batch_num_solves": ([_P], _I),
@@ -397,6 +399,18 @@ def sv_qsp_prepare(h, b, q_lo=0, mode=1):
     if b.size != 1 << m:
         raise ValueError("b must have 2^m entries")
     _check(lib().sv_qsp_prepare(h, _ptr(bf), int(q_lo), m, int(mode)), "sv_qsp_prepare")
+
+
+def sv_lcu_derivative(h, q_lo, m, sel_lo, mode=1):
+    """QPP LCU central-difference gradient on [q_lo, q_lo + m) with select
+    qubits [sel_lo, sel_lo + 2); mode 0 gate by gate, 1 one fused pass."""
+    _check(lib().sv_lcu_derivative(h, int(q_lo), int(m), int(sel_lo), int(mode)), "sv_lcu_derivative")
+
+
+def sv_spectral_derivative(h, q_lo, m, anc, max_local=0):
+    """QPP spectral gradient on [q_lo, q_lo + m), Lambda block-encoded on `anc`."""
+    _check(lib().sv_spectral_derivative(h, int(q_lo), int(m), int(anc), int(max_local)),
+           "sv_spectral_derivative")
 
 
 # --------------------------------------------------------------------------
