@@ -54,6 +54,40 @@ struct PipeArgs {
     int sgn;             // signed (two's-complement) clock for the inversion
 };
 
+// HBM pointers of a solve, in the global address space: the pointers come
+// from a descriptor, so without the cast every access would be a flat
+// instruction, which also counts against the LDS wait counter.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+
+// complex loads and stores through a global pointer (a native two-element
+// vector, so no class member is needed on an address-space-qualified object)
+template <typename R> using v2_t = R __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ cvec<R> gld(const cvec<R> *p, uint64_t i) {
+    const v2_t<R> x = ((gptr<const v2_t<R>>)p)[i];
+    return cmake<R>(x.x, x.y);
+}
+template <typename R>
+__device__ __forceinline__ void gst(cvec<R> *p, uint64_t i, cvec<R> v) {
+    v2_t<R> x;
+    x.x = v.x;
+    x.y = v.y;
+    ((gptr<v2_t<R>>)p)[i] = x;
+}
+
+// the solve of this block: the kernel argument, or entry blockIdx.z of a batch
+__device__ __forceinline__ PipeSolve solve_of(const PipeSolve &one, const PipeSolve *many) {
+    if (!many) return one;
+    const gptr<const PipeSolve> m = (gptr<const PipeSolve>)many + blockIdx.z;
+    PipeSolve r;
+    r.psi = m->psi;
+    r.beta = m->beta;
+    r.F = m->F;
+    r.part = m->part;
+    r.zpart = m->zpart;
+    return r;
+}
+
 template <typename R>
 __device__ __forceinline__ cvec<R> cconjmul(cvec<R> a, cvec<R> b) {   // a * conj(b)
     return cmake<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
@@ -114,10 +148,10 @@ __device__ __forceinline__ void tile_coords(const PipeArgs &A, uint64_t &j0, uin
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
-    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const double2 *__restrict__ beta = S.beta;
-    const uint64_t *__restrict__ F = S.F;
+    const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);          // [2^G][C]
@@ -137,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
         for (int b = G; b < n_c; ++b)
             if (o >> (b - G) & 1) th += F[j * n_c + (n_c - 1 - b)];
         const cvec<R> ph = turn_phase<R>(th);
-        const double2 bj = beta[j];
+        const double2 bj = gld<double>(beta, j);
         cc[c] = cmul<R>(cmake<R>((R)(bj.x * sc), (R)(bj.y * sc)), ph);
         for (int b = 0; b < G; ++b) om[b * C + c] = turn_phase<R>(F[j * n_c + (n_c - 1 - b)]);
     }
@@ -160,8 +194,9 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 #pragma unroll
         for (int jb = 0; jb < RA; ++jb)
             stage<R, RA, true>(v, jb, TW + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
+        cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) tile[(((size_t)lhi << RA) | k) * C + c] = v[k];
+        for (int k = 0; k < (1 << RA); ++k) lt[k << A.cl] = v[k];
     }
     __syncthreads();
     // phase B: line = (c, l_lo), register index = bits [RA, G)
@@ -169,18 +204,18 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
     for (int line = threadIdx.x; line < nlb; line += NT) {
         const int c = line & (C - 1), llo = line >> A.cl;
         cvec<R> v[1 << RB];
+        cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) v[k] = tile[(((size_t)k << RA) | llo) * C + c];
+        for (int k = 0; k < (1 << RB); ++k) v[k] = lt[(k << RA) << A.cl];
 #pragma unroll
         for (int jb = RA; jb < G; ++jb)
             stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
-                               [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
-        const uint64_t col = j0 + c;
+                               [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        // clock index (o << G) + (k << RA) + llo: a base for the line and a stride for k
+        cvec<R> *p = psi + (((((o << G) + (uint64_t)llo) << A.n_s)) + j0 + c);
+        const uint64_t ks = 1ull << (RA + A.n_s);
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) {
-            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
-            psi[(s << A.n_s) | col] = v[k];
-        }
+        for (int k = 0; k < (1 << RB); ++k) gst<R>(p, k * ks, v[k]);
     }
 }
 
@@ -190,25 +225,24 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
-    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
-    double *__restrict__ part = S.part;
+    const gptr<double> __restrict__ part = (gptr<double>)S.part;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
     cvec<R> *TW = tile + ((size_t)C << G);
-    double *s2t = reinterpret_cast<double *>(TW + (1 << G));        // [2^G] s_y^2 2^-G
-    double *n2t = s2t + (1 << G);                                    // [2^G] (c_y^2 + s_y^2) 2^-G
-    R *srt = reinterpret_cast<R *>(n2t + (1 << G));                  // [2^G] s_y 2^-G
+    R *s2t = reinterpret_cast<R *>(TW + (1 << G));                  // [2^G] s_y^2 2^-G
+    R *srt = s2t + (1 << G);                                         // [2^G] s_y 2^-G
     cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
     __shared__ double red[2][NT / 64];
     uint64_t j0, o;
     tile_coords(A, j0, o);               // o = value of the G1 bits
     const int g1 = A.g1, n_c = A.n_c;
-    const uint64_t *__restrict__ F = S.F;
+    const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
     // the G1 table entry of the thread's first phase-A line, read before the
     // tables are built (its latency overlaps that work)
-    const cvec<R> t0 = psi[(o << A.n_s) | (j0 + (threadIdx.x & (C - 1)))];
+    const cvec<R> t0 = gld<R>(psi, (o << A.n_s) | (j0 + (threadIdx.x & (C - 1))));
     fill_twiddles<R>(TW, G, g1, o);
     for (int e = threadIdx.x; e < G * C; e += NT) {     // one phase per thread
         const int b = e / C, c = e - b * C;
@@ -223,9 +257,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         const uint64_t y = o | ((uint64_t)l << g1);
         const double ys = (A.sgn && (y >> (n_c - 1))) ? (double)y - exp2((double)n_c) : (double)y;
         const double sd = y ? 1.0 / ys : 0.0;
-        const double cd = sqrt(1.0 - sd * sd);
-        s2t[l] = sd * sd * fold;
-        n2t[l] = (cd * cd + sd * sd) * fold;
+        s2t[l] = (R)(sd * sd * fold);
         srt[l] = (R)(sd * fold);
     }
     __syncthreads();
@@ -241,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         const int c = line & (C - 1), lhi = line >> A.cl;
         const uint64_t col = j0 + c;
         cvec<R> v[1 << RA];
-        cvec<R> base = line == (int)threadIdx.x ? t0 : psi[(o << A.n_s) | col];
+        cvec<R> base = line == (int)threadIdx.x ? t0 : gld<R>(psi, (o << A.n_s) | col);
         for (int b = 0; b < RB; ++b)
             if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
         v[0] = base;
@@ -254,8 +286,9 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
 #pragma unroll
         for (int jb = 0; jb < RA; ++jb)
             stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+        cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) tile[(((size_t)lhi << RA) | k) * C + c] = v[k];
+        for (int k = 0; k < (1 << RA); ++k) lt[k << A.cl] = v[k];
     }
     __syncthreads();
     // phase B: inverse cascade on the high bits, rotation, forward cascade on the high bits
@@ -263,49 +296,51 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     for (int line = threadIdx.x; line < nlb; line += NT) {
         const int c = line & (C - 1), llo = line >> A.cl;
         cvec<R> v[1 << RB];
+        cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) v[k] = tile[(((size_t)k << RA) | llo) * C + c];
+        for (int k = 0; k < (1 << RB); ++k) v[k] = lt[(k << RA) << A.cl];
 #pragma unroll
         for (int jb = RA; jb < G; ++jb)
             stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
-                               [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
-        // weights times |a|^2 summed over the line in the amplitude precision,
-        // then accumulated in FP64
+                               [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        // |a|^2 summed over the line in the amplitude precision (weighted by
+        // s_y^2 for P(a = 1); the rotation keeps each pair's norm, so the
+        // total is the plain sum), then accumulated in FP64
         R lpa = 0, lnt = 0;
+        const R *s2l = s2t + llo, *srl = srt + llo;
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) {
-            const int l = (k << RA) | llo;
             const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
-            lpa += (R)s2t[l] * a2;
-            lnt += (R)n2t[l] * a2;
-            const R sr = srt[l];
+            lpa += s2l[k << RA] * a2;
+            lnt += a2;
+            const R sr = srl[k << RA];
             v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
         }
         pa += (double)lpa;
-        nt += (double)lnt;
+        nt += (double)lnt * fold;
 #pragma unroll
         for (int jb = G - 1; jb >= RA; --jb)
             stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
-                                [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+                                [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) tile[(((size_t)k << RA) | llo) * C + c] = v[k];
+        for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
     }
     __syncthreads();
     // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
     for (int line = threadIdx.x; line < nla; line += NT) {
         const int c = line & (C - 1), lhi = line >> A.cl;
-        const uint64_t col = j0 + c;
         cvec<R> v[1 << RA];
+        const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
+        for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
 #pragma unroll
         for (int jb = RA - 1; jb >= 0; --jb)
             stage<R, RA, false>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+        // clock index o + (((lhi << RA) + k) << g1): a base for the line and a stride for k
+        cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
+        const uint64_t ks = 1ull << (g1 + A.n_s);
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) {
-            const uint64_t s = o | ((((uint64_t)lhi << RA) | k) << g1);
-            psi[A.abit | (s << A.n_s) | col] = v[k];
-        }
+        for (int k = 0; k < (1 << RA); ++k) gst<R>(p, k * ks, v[k]);
     }
     pa = wave_sum_f64(pa);
     nt = wave_sum_f64(nt);
@@ -333,9 +368,9 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
-    const PipeSolve &S = many ? many[blockIdx.z] : one;
+    const PipeSolve S = solve_of(one, many);
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
-    const uint64_t *__restrict__ F = S.F;
+    const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
@@ -351,20 +386,20 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     const int nla = C << RB, nlb = C << RA;
     // the thread's first phase-B line is read before the tables are built, so
     // the HBM latency overlaps that work
+    // clock index (o << G) + (k << RA) + llo: a base for the line and a stride for k
+    const uint64_t ks = 1ull << (RA + A.n_s);
     cvec<R> v0[1 << RB];
     if ((int)threadIdx.x < nlb) {
         const int c = threadIdx.x & (C - 1), llo = threadIdx.x >> A.cl;
+        const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) {
-            const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
-            v0[k] = psi[A.abit | (s << A.n_s) | (j0 + c)];
-        }
+        for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
     }
     fill_twiddles<R>(TW, G, 0, 0);
     // per-column phase tables, one entry per thread: om[b][c] for b < G and cc[c] (b = G)
     for (int e = threadIdx.x; e < (G + 1) * C; e += NT) {
         const int b = e / C, c = e - b * C;
-        const uint64_t *Fj = F + (j0 + c) * n_c;
+        const gptr<const uint64_t> Fj = F + (j0 + c) * n_c;
         if (b < G) {
             om[b * C + c] = turn_phase<R>(0ull - Fj[n_c - 1 - b]);
         } else {
@@ -381,24 +416,22 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     // phase B first: the forward cascade starts at the top bit of G1
     for (int line = threadIdx.x; line < nlb; line += NT) {
         const int c = line & (C - 1), llo = line >> A.cl;
-        const uint64_t col = j0 + c;
         cvec<R> v[1 << RB];
         if (line == (int)threadIdx.x) {
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
         } else {
+            const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
 #pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) {
-                const uint64_t s = (o << G) | ((uint64_t)k << RA) | (uint64_t)llo;
-                v[k] = psi[A.abit | (s << A.n_s) | col];
-            }
+            for (int k = 0; k < (1 << RB); ++k) v[k] = gld<R>(p, k * ks);
         }
 #pragma unroll
         for (int jb = G - 1; jb >= RA; --jb)
             stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
-                                [&](int k) { return llo | ((k & ((1 << (jb - RA)) - 1)) << RA); });
+                                [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) tile[(((size_t)k << RA) | llo) * C + c] = v[k];
+        for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
     }
     __syncthreads();
     // phase A: remaining stages, conjugate phases, sum over the line
@@ -406,8 +439,9 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     for (int line = threadIdx.x; line < nla; line += NT) {
         const int c = line & (C - 1), lhi = line >> A.cl;
         cvec<R> v[1 << RA];
+        const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) v[k] = tile[(((size_t)lhi << RA) | k) * C + c];
+        for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
 #pragma unroll
         for (int jb = RA - 1; jb >= 0; --jb)
             stage<R, RA, false>(v, jb, twr + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
@@ -442,7 +476,7 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
             r += zs[t].x;
             i += zs[t].y;
         }
-        zpart[o * A.N + j0 + c] = make_double2(r, i);
+        gst<double>(zpart, o * A.N + j0 + c, make_double2(r, i));
     }
 }
 
@@ -530,7 +564,7 @@ static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
     const size_t C = (size_t)1 << cl;
     size_t b = ((C << g) + ((size_t)1 << g)) * e;
     if (which != 1) b += (size_t)(g + 1) * C * e;
-    if (which == 1) b += ((size_t)1 << g) * (2 * sizeof(double) + e / 2) + (size_t)g * C * e;
+    if (which == 1) b += ((size_t)1 << g) * e + (size_t)g * C * e;
     if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
     return b;
 }
