@@ -175,6 +175,17 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
         cc[c] = cmul<R>(cmake<R>((R)(bj.x * sc), (R)(bj.y * sc)), ph);
         for (int b = 0; b < G; ++b) om[b * C + c] = turn_phase<R>(F[j * n_c + (n_c - 1 - b)]);
     }
+    // the clock-bit phases of every column for k_pipe_b and k_pipe_c, staged in
+    // clock rows 2^g1 + r (r < n_c) of the ancilla = 0 half, which the solve
+    // leaves unused otherwise (only the rows below 2^g1 hold the G1 table):
+    // row 2^g1 + r holds G2 bit r for r < g2 and G1 bit r - g2 after that
+    const int g2 = n_c - G;
+    for (int e = threadIdx.x; e < n_c * C; e += NT) {
+        const int r = e / C, c = e - r * C;
+        const uint64_t j = j0 + c;
+        const int q = r < g2 ? n_c - 1 - (G + r) : n_c - 1 - (r - g2);
+        gst<R>(psi, ((((uint64_t)1 << G) + (uint64_t)r) << A.n_s) + j, turn_phase<R>(F[j * n_c + q]));
+    }
     __syncthreads();
     // phase A: line = (c, l_hi), register index = bits [0, RA)
     const int nla = C << RB;
@@ -239,15 +250,15 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     uint64_t j0, o;
     tile_coords(A, j0, o);               // o = value of the G1 bits
     const int g1 = A.g1, n_c = A.n_c;
-    const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
-    // the G1 table entry of the thread's first phase-A line, read before the
-    // tables are built (its latency overlaps that work)
+    // the G1 table entry of the thread's first phase-A line and the column
+    // phases of the G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read
+    // before the twiddles are built so that their latency overlaps that work
     const cvec<R> t0 = gld<R>(psi, (o << A.n_s) | (j0 + (threadIdx.x & (C - 1))));
-    fill_twiddles<R>(TW, G, g1, o);
-    for (int e = threadIdx.x; e < G * C; e += NT) {     // one phase per thread
+    for (int e = threadIdx.x; e < G * C; e += NT) {
         const int b = e / C, c = e - b * C;
-        om[b * C + c] = turn_phase<R>(F[(j0 + c) * n_c + (n_c - 1 - (g1 + b))]);
+        om[b * C + c] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + c);
     }
+    fill_twiddles<R>(TW, G, g1, o);
     // rotation of clock value y = o + l 2^g1 (natural order after the inverse
     // transform): sin = 1/y (y >= 1).  The two groups of G Hadamards around it
     // omit their 1/sqrt(2) each, so 2^-G is folded into the rotation (and into
@@ -276,15 +287,19 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         cvec<R> base = line == (int)threadIdx.x ? t0 : gld<R>(psi, (o << A.n_s) | col);
         for (int b = 0; b < RB; ++b)
             if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-        v[0] = base;
+        // the first inverse stage (group bit 0) sees the product input only:
+        // the pair (1, om_0) becomes (1 + om_0 conj(tw_0), 1 - om_0 conj(tw_0))
+        const cvec<R> w0 = cconjmul<R>(om[c], twr[0]);
+        v[0] = cmul<R>(base, cmake<R>((R)1 + w0.x, w0.y));
+        v[1] = cmul<R>(base, cmake<R>((R)1 - w0.x, -w0.y));
 #pragma unroll
-        for (int b = 0; b < RA; ++b) {
+        for (int b = 1; b < RA; ++b) {
             const cvec<R> w = om[b * C + c];
 #pragma unroll
             for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
         }
 #pragma unroll
-        for (int jb = 0; jb < RA; ++jb)
+        for (int jb = 1; jb < RA; ++jb)
             stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
         cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
@@ -370,7 +385,6 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     constexpr int G = RA + RB;
     const PipeSolve S = solve_of(one, many);
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
-    const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
@@ -396,17 +410,22 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
     }
     fill_twiddles<R>(TW, G, 0, 0);
-    // per-column phase tables, one entry per thread: om[b][c] for b < G and cc[c] (b = G)
+    // per-column phase tables from the clock-bit phases k_pipe_a staged in
+    // rows 2^G + r of the ancilla = 0 half: om[b][c] (b < G) the conjugate
+    // phase of G1 bit b, cc[c] (b = G) the conjugate of the product of the
+    // phases of the G2 bits set in o
+    const int g2 = n_c - G;
     for (int e = threadIdx.x; e < (G + 1) * C; e += NT) {
         const int b = e / C, c = e - b * C;
-        const gptr<const uint64_t> Fj = F + (j0 + c) * n_c;
+        const uint64_t j = j0 + c;
         if (b < G) {
-            om[b * C + c] = turn_phase<R>(0ull - Fj[n_c - 1 - b]);
+            const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + j);
+            om[b * C + c] = cmake<R>(w.x, -w.y);
         } else {
-            uint64_t th = 0;
-            for (int q = G; q < n_c; ++q)
-                if (o >> (q - G) & 1) th += Fj[n_c - 1 - q];
-            cc[c] = turn_phase<R>(0ull - th);
+            cvec<R> p = cmake<R>((R)1, (R)0);
+            for (int q = 0; q < g2; ++q)
+                if (o >> q & 1) p = cmul<R>(p, gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)q) << A.n_s) + j));
+            cc[c] = cmake<R>(p.x, -p.y);
         }
     }
     __syncthreads();
@@ -443,24 +462,29 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
 #pragma unroll
-        for (int jb = RA - 1; jb >= 0; --jb)
-            stage<R, RA, false>(v, jb, twr + tw_off(jb), jb > 0, [&](int k) { return k & ((1 << jb) - 1); });
-        // conj phase of clock index (o << G) | (lhi << RA) | k
-        cvec<R> ph[1 << RA];
+        for (int jb = RA - 1; jb >= 1; --jb)
+            stage<R, RA, false>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+        // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
+        cvec<R> ph[1 << (RA - 1)];
         cvec<R> base = cc[c];
         for (int b = 0; b < RB; ++b)
             if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
         ph[0] = base;
 #pragma unroll
-        for (int b = 0; b < RA; ++b) {
+        for (int b = 1; b < RA; ++b) {
             const cvec<R> w = om[b * C + c];
 #pragma unroll
-            for (int k = 0; k < (1 << b); ++k) ph[k | (1 << b)] = cmul<R>(ph[k], w);
+            for (int k = 0; k < (1 << (b - 1)); ++k) ph[k | (1 << (b - 1))] = cmul<R>(ph[k], w);
         }
+        // the last forward stage (group bit 0, no twiddle) and the phase of
+        // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0))
+        const cvec<R> w0 = om[c];
+        const cvec<R> up = cmake<R>((R)1 + w0.x, w0.y), um = cmake<R>((R)1 - w0.x, -w0.y);
         R lr = 0, li = 0;                // the line's sum, then FP64
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) {
-            const cvec<R> p = cmul<R>(v[k], ph[k]);
+        for (int m = 0; m < (1 << (RA - 1)); ++m) {
+            const cvec<R> a = cmac2<R>(up, v[2 * m], um, v[2 * m + 1]);
+            const cvec<R> p = cmul<R>(a, ph[m]);
             lr += p.x;
             li += p.y;
         }
@@ -486,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
 
 template <typename R, int RA, int RB, int NT>
 static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
-                             const PipeArgs &A, int g, dim3 grid, size_t lds) {
+                             const PipeArgs &A, dim3 grid, size_t lds) {
     // tiles above 64 KiB need a larger dynamic LDS limit; the request plus the
     // kernels' static LDS must stay within the 160 KiB of a workgroup
     constexpr int kLim = 144 * 1024;
@@ -524,23 +548,23 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
 
 template <typename R, int RA, int RB>
 static sv_status launch_nt(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
-                           const PipeArgs &A, int g, int nt, dim3 grid, size_t lds) {
-    if (nt == 512) return launch_pipe<R, RA, RB, 512>(which, st, one, many, A, g, grid, lds);
-    return launch_pipe<R, RA, RB, 256>(which, st, one, many, A, g, grid, lds);
+                           const PipeArgs &A, int nt, dim3 grid, size_t lds) {
+    if (nt == 512) return launch_pipe<R, RA, RB, 512>(which, st, one, many, A, grid, lds);
+    return launch_pipe<R, RA, RB, 256>(which, st, one, many, A, grid, lds);
 }
 
 template <typename R>
 static sv_status dispatch_g(int which, hipStream_t st, const PipeSolve &one, const PipeSolve *many,
                             const PipeArgs &A, int g, int nt, dim3 grid, size_t lds) {
     switch (g) {
-    case 1: return launch_nt<R, 1, 0>(which, st, one, many, A, g, nt, grid, lds);
-    case 2: return launch_nt<R, 1, 1>(which, st, one, many, A, g, nt, grid, lds);
-    case 3: return launch_nt<R, 2, 1>(which, st, one, many, A, g, nt, grid, lds);
-    case 4: return launch_nt<R, 2, 2>(which, st, one, many, A, g, nt, grid, lds);
-    case 5: return launch_nt<R, 3, 2>(which, st, one, many, A, g, nt, grid, lds);
-    case 6: return launch_nt<R, 3, 3>(which, st, one, many, A, g, nt, grid, lds);
-    case 7: return launch_nt<R, 4, 3>(which, st, one, many, A, g, nt, grid, lds);
-    case 8: return launch_nt<R, 4, 4>(which, st, one, many, A, g, nt, grid, lds);
+    case 1: return launch_nt<R, 1, 0>(which, st, one, many, A, nt, grid, lds);
+    case 2: return launch_nt<R, 1, 1>(which, st, one, many, A, nt, grid, lds);
+    case 3: return launch_nt<R, 2, 1>(which, st, one, many, A, nt, grid, lds);
+    case 4: return launch_nt<R, 2, 2>(which, st, one, many, A, nt, grid, lds);
+    case 5: return launch_nt<R, 3, 2>(which, st, one, many, A, nt, grid, lds);
+    case 6: return launch_nt<R, 3, 3>(which, st, one, many, A, nt, grid, lds);
+    case 7: return launch_nt<R, 4, 3>(which, st, one, many, A, nt, grid, lds);
+    case 8: return launch_nt<R, 4, 4>(which, st, one, many, A, nt, grid, lds);
     }
     return fail(SV_EUNSUPPORTED, "clock group of %d bits", g);
 }
