@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-qsp", action="store_true")
+    ap.add_argument("--no-qpp", action="store_true")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -332,6 +333,33 @@ def main():
         got = qs.get()
         rec["max_abs_err_vs_b"] = float(np.abs(got - bq / np.linalg.norm(bq)).max())
         out["qsp1"] = rec
+        qs.close()
+        del qs
+        torch.cuda.empty_cache()
+
+    # ---------------- QPP gradient: one fused LCU pass on a 30-qubit state ----------------
+    if not args.no_qpp:
+        n, m = 30, 8
+        log(f"[bench] qpp: LCU gradient of 2^{n - m - 2} profiles of 2^{m} points (select qubits {m}, {m + 1})")
+        qs = B.State(n, "c64", device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2307)
+        qs.tensor.copy_(torch.randn(1 << n, dtype=torch.complex64, device=dev, generator=gen))
+        B.sv_lcu_derivative(qs.h, 0, m, m, 1)
+        torch.cuda.synchronize()
+        B.sv_trace_enable(True)
+        reps = 5
+        for _ in range(reps):
+            B.sv_lcu_derivative(qs.h, 0, m, m, 1)
+        torch.cuda.synchronize()
+        tr = B.sv_trace_report()
+        B.sv_trace_enable(False)
+        k = tr["lcu_derivative"]
+        ms = k["ms"] / k["launches"]
+        gbs = (k["bytes"] / k["launches"]) / (ms * 1e-3) / 1e9
+        out["qpp_lcu"] = {"qubits": n, "register": m, "columns": 1 << (n - m - 2), "ms_per_pass": ms,
+                          "bytes_per_pass": k["bytes"] / k["launches"], "hbm_gbs": gbs,
+                          "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "passes_timed": reps}
         qs.close()
         del qs
         torch.cuda.empty_cache()

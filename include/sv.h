@@ -341,10 +341,13 @@ sv_status sv_qsp_prepare(sv_state s, const double *b, int q_lo, int m, int mode)
  *   mode 0: gate by gate (Hadamards, multi-controlled X cascades for C and
  *           C^T, a multi-controlled phase for R0, one Z for the signs);
  *   mode 1: the whole circuit in one read and one write of the state (LDS
- *           tiles); needs m <= 11 (complex64) or m <= 10 (complex128), else
- *           SV_EUNSUPPORTED.
+ *           tiles).  A register wider than 11 qubits (complex64) or 10
+ *           (complex128) is cut into chunks of its low bits, and a first
+ *           small kernel copies the two outside neighbours of every chunk
+ *           into the state's scratch memory (2^(n - 10) or 2^(n - 9)
+ *           amplitudes).
  * Errors: SV_EINVAL (register or select outside the state, overlapping,
- * m > 30, mode). */
+ * m > 30, mode), SV_ENOMEM (scratch). */
 sv_status sv_lcu_derivative(sv_state s, int q_lo, int m, int sel_lo, int mode);
 
 /* QPP velocity gradient in spectral space (appendix "Velocity gradients -

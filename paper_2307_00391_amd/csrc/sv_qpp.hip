@@ -13,7 +13,11 @@
 //   mode 1: the whole circuit in one pass: tiles holding every register and
 //           select value of a few columns are staged in LDS, and each thread
 //           forms the four select outputs of one register point from the
-//           select values at its two neighbours.
+//           select values at its two neighbours.  A register too wide for one
+//           tile is cut into chunks of its low bits: a first kernel copies the
+//           two outside neighbours of every chunk (all select values) into
+//           scratch memory, so the in-place tile pass can read them after the
+//           neighbouring tiles have been overwritten.
 //
 // Spectral form.  Inverse QFT on the register, the wavenumber diagonal
 // Lambda_k as the |1> block of a rotation of one more qubit (controlled on the
@@ -35,19 +39,52 @@ struct LcuArgs {
     int tb;              // log2 tile size
     int rq, rs;          // rank of the register's lowest bit / select's lowest bit inside a tile index
     int m;               // register qubits
+    int cb;              // register bits inside a tile (cb < m: the register is chunked)
+    int q_lo;
     uint64_t sb1, sb2;   // the two select bits of a global index
     uint64_t ntiles;
+    int contig;          // the tile bits are the lowest tb bits: no bit deposit needed
 };
 
+// global index of tile element t of tile `tid`
+__device__ __forceinline__ uint64_t lcu_index(const LcuArgs &a, uint64_t tid, uint64_t t) {
+    return a.contig ? (tid << a.tb) | t : pdep64(tid, a.omask) | pdep64(t, a.tmask);
+}
+
+// index of the chunk-halo pair of the global index g: g without the low cb
+// register bits (the bits of a point inside its chunk)
+__device__ __forceinline__ uint64_t halo_slot(uint64_t g, int q_lo, int cb) {
+    return ((g >> (q_lo + cb)) << q_lo) | (g & ((1ull << q_lo) - 1ull));
+}
+
+// the two outside neighbours of every chunk, for every select value and column:
+// halo[2 t] = point chunk 2^cb - 1, halo[2 t + 1] = point (chunk + 1) 2^cb (cyclic)
 template <typename R>
-__global__ __launch_bounds__(256) void k_lcu(cvec<R> *__restrict__ psi, LcuArgs a) {
+__global__ __launch_bounds__(256) void k_lcu_halo(const cvec<R> *__restrict__ psi, cvec<R> *__restrict__ halo,
+                                                  uint64_t nslots, int q_lo, int m, int cb) {
+    const uint64_t N = 1ull << m, rmask = (N - 1ull) << q_lo;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nslots; t += stride) {
+        const uint64_t g0 = ((t >> q_lo) << (q_lo + cb)) | (t & ((1ull << q_lo) - 1ull));
+        const uint64_t first = ((g0 & rmask) >> q_lo);           // chunk * 2^cb
+        const uint64_t dn = (first + N - 1ull) & (N - 1ull), up = (first + (1ull << cb)) & (N - 1ull);
+        const uint64_t rest = g0 & ~rmask;
+        halo[2 * t] = psi[rest | (dn << q_lo)];
+        halo[2 * t + 1] = psi[rest | (up << q_lo)];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_lcu(cvec<R> *__restrict__ psi, const cvec<R> *__restrict__ halo, LcuArgs a) {
     extern __shared__ unsigned char lds_raw[];
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(lds_raw);
-    const uint32_t T = 1u << a.tb, N = 1u << a.m, jm = N - 1u;
+    const uint32_t T = 1u << a.tb, jm = (1u << a.cb) - 1u;     // points of one chunk
+    const uint64_t Nm = (1ull << a.m) - 1ull;                    // last point of the register
+    const bool chunked = a.cb < a.m;
     const uint32_t rmask = jm << a.rq;
     for (uint64_t tid = blockIdx.x; tid < a.ntiles; tid += gridDim.x) {
-        const uint64_t base = pdep64(tid, a.omask);
-        for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) tile[t] = psi[base | pdep64(t, a.tmask)];
+        const uint64_t base = lcu_index(a, tid, 0);
+        for (uint32_t t = threadIdx.x; t < T; t += blockDim.x) tile[t] = psi[a.contig ? base | t : base | pdep64(t, a.tmask)];
         __syncthreads();
         // one thread per (column, register point): tile indices with select = 0
         for (uint32_t q = threadIdx.x; q < (T >> 2); q += blockDim.x) {
@@ -57,21 +94,38 @@ __global__ __launch_bounds__(256) void k_lcu(cvec<R> *__restrict__ psi, LcuArgs 
             const uint32_t col = t0 & ~rmask;
             const uint32_t up = col | (((j + 1u) & jm) << a.rq), dn = col | (((j + jm) & jm) << a.rq);
             const uint32_t s1 = 1u << a.rs, s2 = 2u << a.rs;
+            const uint64_t g = a.contig ? base | t0 : base | pdep64(t0, a.tmask);   // select 0, this point
+            const uint64_t g1 = a.sb1, g2 = a.sb2;
+            const uint64_t jg = ((g >> a.q_lo) & Nm);                     // the point's register value
+            // the select values at the two neighbours (from the halo copy at a chunk edge)
+            cvec<R> u0, u1, u2, u3, d0, d1, d2, d3;
+            if (chunked && j == jm) {
+                u0 = halo[2 * halo_slot(g, a.q_lo, a.cb) + 1];
+                u1 = halo[2 * halo_slot(g | g1, a.q_lo, a.cb) + 1];
+                u2 = halo[2 * halo_slot(g | g2, a.q_lo, a.cb) + 1];
+                u3 = halo[2 * halo_slot(g | g1 | g2, a.q_lo, a.cb) + 1];
+            } else {
+                u0 = tile[up], u1 = tile[up | s1], u2 = tile[up | s2], u3 = tile[up | s1 | s2];
+            }
+            if (chunked && j == 0) {
+                d0 = halo[2 * halo_slot(g, a.q_lo, a.cb)];
+                d1 = halo[2 * halo_slot(g | g1, a.q_lo, a.cb)];
+                d2 = halo[2 * halo_slot(g | g2, a.q_lo, a.cb)];
+                d3 = halo[2 * halo_slot(g | g1 | g2, a.q_lo, a.cb)];
+            } else {
+                d0 = tile[dn], d1 = tile[dn | s1], d2 = tile[dn | s2], d3 = tile[dn | s1 | s2];
+            }
             // V at the two neighbours: w_0, w_1 at j + 1 (used by C, C R0), w_2, w_3 at j - 1
-            const cvec<R> u0 = tile[up], u1 = tile[up | s1], u2 = tile[up | s2], u3 = tile[up | s1 | s2];
-            const cvec<R> d0 = tile[dn], d1 = tile[dn | s1], d2 = tile[dn | s2], d3 = tile[dn | s1 | s2];
             const R h = (R)0.5;
             cvec<R> y0 = cmake<R>(h * (u0.x + u1.x + u2.x + u3.x), h * (u0.y + u1.y + u2.y + u3.y));
             cvec<R> y1 = cmake<R>(h * (u0.x - u1.x + u2.x - u3.x), h * (u0.y - u1.y + u2.y - u3.y));
             cvec<R> y2 = cmake<R>(h * (d0.x + d1.x - d2.x - d3.x), h * (d0.y + d1.y - d2.y - d3.y));
             cvec<R> y3 = cmake<R>(h * (d0.x - d1.x - d2.x + d3.x), h * (d0.y - d1.y - d2.y + d3.y));
             // G: C R0 flips the sign of the value that wrapped from 0; -C^T; -R0 C^T flips at j = 0
-            if (j == jm) y1 = cmake<R>(-y1.x, -y1.y);
+            if (jg == Nm) y1 = cmake<R>(-y1.x, -y1.y);
             y2 = cmake<R>(-y2.x, -y2.y);
-            if (j != 0) y3 = cmake<R>(-y3.x, -y3.y);
+            if (jg != 0) y3 = cmake<R>(-y3.x, -y3.y);
             // V^dagger
-            const uint64_t g = base | pdep64(t0, a.tmask);
-            const uint64_t g1 = a.sb1, g2 = a.sb2;
             psi[g] = cmake<R>(h * (y0.x + y1.x + y2.x + y3.x), h * (y0.y + y1.y + y2.y + y3.y));
             psi[g | g1] = cmake<R>(h * (y0.x - y1.x + y2.x - y3.x), h * (y0.y - y1.y + y2.y - y3.y));
             psi[g | g2] = cmake<R>(h * (y0.x + y1.x - y2.x - y3.x), h * (y0.y + y1.y - y2.y - y3.y));
@@ -86,13 +140,12 @@ static int lcu_max_tile_bits(sv_dtype dt) { return dt == SV_C128 ? 12 : 13; }
 
 static sv_status lcu_fused(sv_state s, int q_lo, int m, int sel_lo) {
     const int n = s->n;
-    const int need = m + 2, cap = lcu_max_tile_bits(s->dt);
-    if (need > cap)
-        return fail(SV_EUNSUPPORTED, "fused LCU pass: a register of %d qubits does not fit one LDS tile (at most %d)",
-                    m, cap - 2);
+    const int cap = lcu_max_tile_bits(s->dt);
+    const int cb = m + 2 <= cap ? m : cap - 2;      // register bits per tile
+    const int need = cb + 2;
     int tb = need < 10 ? 10 : need;
     if (tb > n) tb = n;
-    uint64_t tmask = (((1ull << m) - 1ull) << q_lo) | (3ull << sel_lo);
+    uint64_t tmask = (((1ull << cb) - 1ull) << q_lo) | (3ull << sel_lo);
     // fill the tile with the lowest remaining bits
     for (int b = 0, extra = tb - need; b < n && extra > 0; ++b)
         if (!((tmask >> b) & 1ull)) {
@@ -107,16 +160,38 @@ static sv_status lcu_fused(sv_state s, int q_lo, int m, int sel_lo) {
     a.rq = popcount64(tmask & ((1ull << q_lo) - 1ull));
     a.rs = popcount64(tmask & ((1ull << sel_lo) - 1ull));
     a.m = m;
+    a.cb = cb;
+    a.q_lo = q_lo;
     a.sb1 = 1ull << sel_lo;
     a.sb2 = 2ull << sel_lo;
     a.ntiles = 1ull << (n - tb);
+    a.contig = tmask == ((1ull << tb) - 1ull) ? 1 : 0;
     const size_t lds = ((size_t)1 << tb) * amp_bytes(s->dt);
     const unsigned grid = (unsigned)(a.ntiles < 4096 ? a.ntiles : 4096);
+    void *halo = nullptr;
+    if (cb < m) {
+        // one pair per (column, chunk, select value): 2^(n - cb) slots
+        const uint64_t nslots = dim_of(n - cb);
+        SV_TRY(ensure_scratch(s, 2 * nslots * amp_bytes(s->dt)));
+        halo = s->scratch;
+        uint64_t hg = (nslots + 255) / 256;
+        if (hg > 65536) hg = 65536;
+        TraceScope th(s->stream, "lcu_halo", 4.0 * (double)nslots * amp_bytes(s->dt), 0.0);
+        if (s->dt == SV_C64)
+            hipLaunchKernelGGL(k_lcu_halo<float>, dim3((unsigned)hg), dim3(256), 0, s->stream,
+                               (const float2 *)s->data, (float2 *)halo, nslots, q_lo, m, cb);
+        else
+            hipLaunchKernelGGL(k_lcu_halo<double>, dim3((unsigned)hg), dim3(256), 0, s->stream,
+                               (const double2 *)s->data, (double2 *)halo, nslots, q_lo, m, cb);
+        SV_HIP(hipGetLastError());
+    }
     TraceScope ts(s->stream, "lcu_derivative", 2.0 * (double)dim_of(n) * amp_bytes(s->dt), 0.0);
     if (s->dt == SV_C64)
-        hipLaunchKernelGGL(k_lcu<float>, dim3(grid), dim3(256), lds, s->stream, (float2 *)s->data, a);
+        hipLaunchKernelGGL(k_lcu<float>, dim3(grid), dim3(256), lds, s->stream, (float2 *)s->data,
+                           (const float2 *)halo, a);
     else
-        hipLaunchKernelGGL(k_lcu<double>, dim3(grid), dim3(256), lds, s->stream, (double2 *)s->data, a);
+        hipLaunchKernelGGL(k_lcu<double>, dim3(grid), dim3(256), lds, s->stream, (double2 *)s->data,
+                           (const double2 *)halo, a);
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
