@@ -6,7 +6,10 @@
   oracle in test_oracle_hhl.py); complex64 to 1e-5 and complex128 to 1e-12
   in state-amplitude units.
 * 33-qubit U3 + CNOT-ladder probe: the norm is preserved and the circuit
-  followed by its inverse returns |0...0>.
+  followed by its inverse returns |0...0>; and, through the same fused
+  passes, the probe's 20 U3 layers followed by one CNOT ladder, whose output
+  has a closed form (a product state permuted by the ladder), on 4096
+  sampled amplitudes.
 """
 import math
 
@@ -84,3 +87,36 @@ def test_probe_33_qubits_norm_and_roundtrip():
     p0 = B.sv_norm2(st.h, (1 << q) - 1, 0)
     assert p0 >= 1.0 - 1e-4, p0
     st.close()
+
+
+def test_probe_33_qubits_product_state_closed_form():
+    """The probe's U3 gates (20 layers on all 33 qubits) and then one CNOT
+    ladder q -> q+1, q = 0..31.  The U3 layers leave the product state
+    (x)_q m_q with m_q = (product of qubit q's 20 gates)|0>; the ladder maps
+    |x> to |y> with y_k = x_0 ^ ... ^ x_k, so the output amplitude at y is
+    prod_q m_q[y_q ^ y_(q-1)] (y_(-1) = 0)."""
+    torch = pytest.importorskip("torch")
+    q, layers = 33, 20
+    if _free_mem() < (1 << q) * 8 * 1.1:
+        pytest.skip("not enough device memory")
+    full = inputs.probe_layers(inputs.rng_for(3, 1000), q, layers)
+    us = [g for g in full if g[0] == "u"]
+    ladder = [("cx", k, k + 1) for k in range(q - 1)]
+    m = [np.array([1.0, 0.0], dtype=np.complex128) for _ in range(q)]
+    for _, t, u in us:
+        m[t] = u @ m[t]
+    st = B.State(q, "c64")
+    B.sv_init_basis(st.h, 0)
+    B.sv_apply_circuit(st.h, us + ladder)
+    rng = np.random.default_rng(33)
+    ys = np.unique(np.concatenate([rng.integers(0, 1 << q, size=4096, dtype=np.int64), [0, (1 << q) - 1]]))
+    got = st.tensor[torch.as_tensor(ys, device=st.tensor.device)].cpu().numpy().astype(np.complex128)
+    st.close()
+    bits = (ys[:, None] >> np.arange(q)[None, :]) & 1
+    xs = bits ^ np.concatenate([np.zeros((ys.size, 1), dtype=np.int64), bits[:, :-1]], axis=1)
+    want = np.ones(ys.size, dtype=np.complex128)
+    for k in range(q):
+        want *= np.where(xs[:, k] == 1, m[k][1], m[k][0])
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max()
+    assert err <= 1e-4 * scale, (err, scale)
