@@ -38,6 +38,10 @@ def _load():
     lib.orc_qsp.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, ctypes.c_int]
     lib.orc_lcu_derivative.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc_spectral_derivative.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc_qsp_apply.argtypes = [_c128p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, ctypes.c_int]
+    lib.orc_cks_coeffs.argtypes = [ctypes.c_int, ctypes.c_int, _f64p]
+    lib.orc_qlsa2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, _c128p, _c128p, _c128p,
+                              ctypes.POINTER(ctypes.c_double)]
     lib.orc_norm2.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_norm2.restype = ctypes.c_double
     lib.orc_postselect.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -177,3 +181,37 @@ def spectral_derivative(psi, q_lo, m, anc):
     _check(_load().orc_spectral_derivative(psi, _nqubits(psi), int(q_lo), int(m), int(anc)),
            "spectral_derivative")
     return psi
+
+
+def qsp_apply(psi, q_lo, b, inverse=False):
+    """The QSP-1 tree circuit for b on the register [q_lo, q_lo + m) of an
+    arbitrary state (or its adjoint), in place."""
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.complex128))
+    m = b.size.bit_length() - 1
+    if b.size != 1 << m:
+        raise ValueError("b must have 2^m entries")
+    _check(_load().orc_qsp_apply(psi, _nqubits(psi), int(q_lo), int(m), b, int(bool(inverse))), "qsp_apply")
+    return psi
+
+
+def cks_coeffs(B, J):
+    """alpha_j (j < J) of g(x) = (1 - (1 - x^2)^B) / x = sum_j alpha_j T_{2j+1}(x)."""
+    out = np.zeros(int(J), dtype=np.float64)
+    _check(_load().orc_cks_coeffs(int(B), int(J), out), "cks_coeffs")
+    return out
+
+
+def qlsa2(A, b, s, B):
+    """QLSA-2 by Chebyshev LCU (see oracle.c): returns (psi, z, p_post) with
+    z the post-selected (select = 0, walk = 0) amplitudes, unnormalised."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    if N != 1 << n_s or b.shape != (N,):
+        raise ValueError("A must be 2^n_s square and b of length 2^n_s")
+    psi = np.zeros(1 << (n_s + 1 + int(s)), dtype=np.complex128)
+    z = np.zeros(N, dtype=np.complex128)
+    p = ctypes.c_double(0.0)
+    _check(_load().orc_qlsa2(n_s, int(s), int(B), A, b, psi, z, ctypes.byref(p)), "qlsa2")
+    return psi, z, p.value

@@ -602,6 +602,199 @@ int orc_spectral_derivative(cplx *psi, int n, int q_lo, int m, int anc)
     return orc_qft(psi, n, q_lo, m, 0);
 }
 
+/*
+ * The QSP-1 tree circuit of orc_qsp applied to the register [q_lo, q_lo + m)
+ * of an arbitrary state (no initialisation), or its adjoint (inverse != 0:
+ * the phase diagonal conjugated first, then the rotations transposed in
+ * reverse order).  On a register in |0...0> the forward circuit prepares
+ * b / |b| there.  Used as the PREP step of the LCU solver below.
+ */
+int orc_qsp_apply(cplx *psi, int n, int q_lo, int m, const cplx *b, int inverse)
+{
+    if (m < 1 || q_lo < 0 || q_lo + m > n || m > 24) return ORC_EINVAL;
+    const uint64_t R = (uint64_t)1 << m;
+    double *w = (double *)calloc(2 * R, sizeof(double));
+    if (!w) return ORC_ENOMEM;
+    double tot = 0.0;
+    for (uint64_t r = 0; r < R; ++r) {
+        w[R + r] = creal(b[r]) * creal(b[r]) + cimag(b[r]) * cimag(b[r]);
+        tot += w[R + r];
+    }
+    if (!(tot > 0.0)) { free(w); return ORC_EINVAL; }
+    for (uint64_t k = R - 1; k >= 1; --k) w[k] = w[2 * k] + w[2 * k + 1];
+    int ctrls[32], cvals[32], rc = ORC_OK;
+    /* the phase diagonal: diag(e^{i a}, 1) or diag(1, e^{i a}) on qubit q_lo
+     * controlled on the other register qubits taking the value of r */
+    for (int pass = 0; pass < 2 && rc == ORC_OK; ++pass) {
+        const int phase_now = inverse ? pass == 0 : pass == 1;
+        if (phase_now) {
+            for (uint64_t r = 0; r < R && rc == ORC_OK; ++r) {
+                if (w[R + r] == 0.0) continue;
+                const double a = carg(b[r]) * (inverse ? -1.0 : 1.0);
+                if (a == 0.0) continue;
+                const cplx e = cexp(I * a);
+                double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+                if (r & 1) { u[6] = creal(e); u[7] = cimag(e); }
+                else { u[0] = creal(e); u[1] = cimag(e); }
+                for (int j = 1; j < m; ++j) { ctrls[j - 1] = q_lo + j; cvals[j - 1] = (int)((r >> j) & 1); }
+                rc = orc_apply_gate(psi, n, q_lo, u, ctrls, cvals, m - 1);
+            }
+        } else {
+            for (int li = 0; li < m && rc == ORC_OK; ++li) {
+                const int l = inverse ? m - 1 - li : li;        /* tree level */
+                const int t = q_lo + m - 1 - l;
+                for (int j = 0; j < l; ++j) ctrls[j] = q_lo + m - 1 - j;
+                for (uint64_t p = 0; p < ((uint64_t)1 << l) && rc == ORC_OK; ++p) {
+                    const uint64_t node = ((uint64_t)1 << l) + p;
+                    if (!(w[node] > 0.0)) continue;
+                    const double c = sqrt(w[2 * node] / w[node]), sn = sqrt(w[2 * node + 1] / w[node]);
+                    const double sg = inverse ? -1.0 : 1.0;
+                    for (int j = 0; j < l; ++j) cvals[j] = (int)((p >> (l - 1 - j)) & 1);
+                    const double ry[8] = {c, 0.0, -sg * sn, 0.0, sg * sn, 0.0, c, 0.0};
+                    rc = orc_apply_gate(psi, n, t, ry, ctrls, cvals, l);
+                }
+            }
+        }
+    }
+    free(w);
+    return rc;
+}
+
+/*
+ * Chebyshev coefficients of the linear-systems solver by a linear
+ * combination of unitaries (QLSA-2, built from the cited work of Childs,
+ * Kothari and Somma, since the paper defers its details): the odd function
+ *     g(x) = (1 - (1 - x^2)^B) / x = sum_{j=0}^{B-1} alpha_j T_{2j+1}(x),
+ *     alpha_j = 4 (-1)^j sum_{i=j+1}^{B} C(2B, B+i) / 4^B,
+ * approximates 1/x on [-1, -1/kappa] u [1/kappa, 1] to within (1 - 1/kappa^2)^B kappa.
+ * alpha[0..J) are written (zero for j >= B).  The binomial weights
+ * t_i = C(2B, B+i)/4^B come from t_0 = prod_{k=1}^{B} (2k-1)/(2k) and
+ * t_{i+1} = t_i (B-i)/(B+i+1); the tails are summed from the small end.
+ */
+int orc_cks_coeffs(int B, int J, double *alpha)
+{
+    if (B < 1 || B > 20000000 || J < 1) return ORC_EINVAL;
+    double *t = (double *)malloc(sizeof(double) * ((size_t)B + 2));
+    if (!t) return ORC_ENOMEM;
+    double t0 = 1.0;
+    for (int k = 1; k <= B; ++k) t0 *= (2.0 * k - 1.0) / (2.0 * k);
+    t[0] = t0;
+    for (int i = 0; i < B; ++i) t[i + 1] = t[i] * (double)(B - i) / (double)(B + i + 1);
+    t[B + 1] = 0.0;
+    /* tail[i] = sum_{i' >= i} t_i', overwriting t from the top */
+    double acc = 0.0;
+    for (int i = B; i >= 0; --i) { acc += t[i]; t[i] = acc; }
+    for (int j = 0; j < J; ++j) {
+        const double tail = j + 1 <= B ? t[j + 1] : 0.0;
+        alpha[j] = 4.0 * ((j & 1) ? -1.0 : 1.0) * tail;
+    }
+    free(t);
+    return ORC_OK;
+}
+
+/*
+ * QLSA-2 by Chebyshev LCU, gate level, in the order of the construction:
+ *   layout: bits [0, n_s) system, bit n_s the walk qubit, bits
+ *   [n_s + 1, n_s + 1 + s) the select register (J = 2^s terms);
+ *   1. |0>_sel |0>_walk |b / |b|>;
+ *   2. A~ = A / max|lambda|; U = [[A~, S], [S, -A~]] with S = sqrt(I - A~^2)
+ *      (walk qubit = the high bit of the (walk, system) register), a block
+ *      encoding of A~; the walk W = (Z on the walk qubit) U, whose walk-0 block
+ *      of W^k is the Chebyshev polynomial T_k(A~);
+ *   3. PREP: the QSP-1 tree on the select register with amplitudes
+ *      sqrt(|alpha_j| / sum |alpha|);
+ *   4. SELECT: W^(2j+1) on the (walk, system) register where the select
+ *      register holds j;
+ *   5. the signs (-1)^j: Z on the lowest select qubit;
+ *   6. PREP^dagger;
+ *   7. post-select select = 0 and walk = 0: z = the first 2^n_s amplitudes,
+ *      z = sum_j alpha_j T_{2j+1}(A~) b^ / sum |alpha|, p = |z|^2.
+ */
+int orc_qlsa2(int n_s, int s, int B, const cplx *A, const cplx *b, cplx *psi, cplx *z_out, double *p_post)
+{
+    if (n_s < 1 || s < 1 || n_s + 1 + s > 26 || B < 1) return ORC_EINVAL;
+    const int N = 1 << n_s, M = 2 * N, n = n_s + 1 + s, J = 1 << s;
+    const uint64_t dim = (uint64_t)1 << n;
+    double bn = 0.0;
+    for (int j = 0; j < N; ++j) bn += creal(b[j] * conj(b[j]));
+    bn = sqrt(bn);
+    if (!(bn > 0.0)) return ORC_EINVAL;
+    double *lam = (double *)malloc(sizeof(double) * N);
+    double *alpha = (double *)malloc(sizeof(double) * J);
+    cplx *V = (cplx *)malloc(sizeof(cplx) * (size_t)N * N);
+    cplx *W = (cplx *)malloc(sizeof(cplx) * (size_t)M * M);
+    cplx *pamp = (cplx *)malloc(sizeof(cplx) * J);
+    cplx *u = (cplx *)malloc(sizeof(cplx) * M), *v = (cplx *)malloc(sizeof(cplx) * M);
+    int rc = ORC_OK;
+    if (!lam || !alpha || !V || !W || !pamp || !u || !v) { rc = ORC_ENOMEM; goto done; }
+    /* 1 */
+    memset(psi, 0, sizeof(cplx) * dim);
+    for (int j = 0; j < N; ++j) psi[j] = b[j] / bn;
+    /* 2: the walk operator */
+    if ((rc = orc_eigh(N, A, lam, V)) != ORC_OK) goto done;
+    {
+        double lmax = 0.0;
+        for (int k = 0; k < N; ++k) lmax = fmax(lmax, fabs(lam[k]));
+        if (!(lmax > 0.0)) { rc = ORC_EINVAL; goto done; }
+        for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c) {
+                cplx a = 0, sq = 0;
+                for (int k = 0; k < N; ++k) {
+                    const double lt = lam[k] / lmax;
+                    const cplx vv = V[(size_t)r * N + k] * conj(V[(size_t)c * N + k]);
+                    a += lt * vv;
+                    sq += sqrt(fmax(0.0, 1.0 - lt * lt)) * vv;
+                }
+                /* U = [[a, sq], [sq, -a]]; W = Z_walk U negates the walk = 1 rows */
+                W[(size_t)r * M + c] = a;
+                W[(size_t)r * M + (N + c)] = sq;
+                W[(size_t)(N + r) * M + c] = -sq;
+                W[(size_t)(N + r) * M + (N + c)] = a;
+            }
+    }
+    /* 3: PREP */
+    if ((rc = orc_cks_coeffs(B, J, alpha)) != ORC_OK) goto done;
+    {
+        double l1 = 0.0;
+        for (int j = 0; j < J; ++j) l1 += fabs(alpha[j]);
+        for (int j = 0; j < J; ++j) pamp[j] = sqrt(fabs(alpha[j]) / l1);
+    }
+    if ((rc = orc_qsp_apply(psi, n, n_s + 1, s, pamp, 0)) != ORC_OK) goto done;
+    /* 4: SELECT, W applied 2j + 1 times to the (walk, system) vector of select value j */
+    for (int j = 0; j < J; ++j) {
+        const uint64_t off = (uint64_t)j << (n_s + 1);
+        for (int i = 0; i < M; ++i) u[i] = psi[off + i];
+        for (int rep = 0; rep < 2 * j + 1; ++rep) {
+            for (int r = 0; r < M; ++r) {
+                cplx acc = 0;
+                for (int c = 0; c < M; ++c) acc += W[(size_t)r * M + c] * u[c];
+                v[r] = acc;
+            }
+            memcpy(u, v, sizeof(cplx) * M);
+        }
+        for (int i = 0; i < M; ++i) psi[off + i] = u[i];
+    }
+    /* 5: signs */
+    {
+        const double z8[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0};
+        if ((rc = orc_apply_gate(psi, n, n_s + 1, z8, NULL, NULL, 0)) != ORC_OK) goto done;
+    }
+    /* 6: PREP^dagger */
+    if ((rc = orc_qsp_apply(psi, n, n_s + 1, s, pamp, 1)) != ORC_OK) goto done;
+    /* 7 */
+    {
+        double pp = 0.0;
+        for (int k = 0; k < N; ++k) {
+            z_out[k] = psi[k];
+            pp += creal(psi[k] * conj(psi[k]));
+        }
+        *p_post = pp;
+    }
+done:
+    free(lam); free(alpha); free(V); free(W); free(pamp); free(u); free(v);
+    return rc;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
