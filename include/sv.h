@@ -364,6 +364,56 @@ sv_status sv_lcu_derivative(sv_state s, int q_lo, int m, int sel_lo, int mode);
 sv_status sv_spectral_derivative(sv_state s, int q_lo, int m, int anc, int max_local);
 
 /* ------------------------------------------------------------------------
+ * QLSA-2 (main text, "Quantum Linear Systems Algorithm": the solver family
+ * built on a linear combination of unitaries, after the cited work of
+ * Childs, Kothari and Somma; the paper defers the construction, which is
+ * taken here in its Chebyshev form)
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+    int n_s;    /* system qubits: A is 2^n_s x 2^n_s (1..13) */
+    int s;      /* select qubits: J = 2^s Chebyshev terms (1..24) */
+    int B;      /* the polynomial (1 - (1 - x^2)^B) / x; B >= kappa^2 ln(kappa / eps)
+                   makes it eps-close to 1/x on 1/kappa <= |x| <= 1 (1..2e7) */
+    int mode;   /* 0: the circuit in the computational basis (PREP as the QSP-1 tree
+                      of uniformly controlled Ry passes, W once and one controlled
+                      W^(2^(m+1)) per select qubit as dense unitaries of the
+                      (walk, system) register on the matrix cores, the sign gate,
+                      PREP^dagger);
+                   1: the same circuit with the system register in the eigenbasis
+                      of A: one pass writes the state after PREP, SELECT and the
+                      signs, one FP64 reduction forms the select = 0 projection */
+} sv_qlsa2_params;
+
+typedef struct {
+    double p_post;          /* P(select = 0, walk = 0), FP64 */
+    double lambda_abs_max;  /* max |lambda(A)|: A~ = A / lambda_abs_max */
+    double lambda_abs_min;  /* min |lambda(A)|: kappa = lambda_abs_max / lambda_abs_min */
+    double alpha_l1;        /* sum_j |alpha_j| of the J terms used */
+} sv_qlsa2_result;
+
+/* Solve A x = b with the Chebyshev LCU solver on the state s, which must have
+ * n_s + 1 + s qubits: bits [0, n_s) system, bit n_s the walk qubit, bits
+ * [n_s + 1, n_s + 1 + s) the select register.  A~ = A / max|lambda| is
+ * block-encoded as U = [[A~, S], [S, -A~]], S = sqrt(I - A~^2) (walk qubit =
+ * the high bit of the (walk, system) register); the walk W = (Z on the walk
+ * qubit) U has T_k(A~) as its walk = 0 block of W^k.  alpha_j = 4 (-1)^j
+ * sum_{i=j+1}^{B} C(2B, B+i) / 4^B, j < J (zero for j >= B), so that
+ * sum_j alpha_j T_{2j+1}(x) is (1 - (1 - x^2)^B) / x when J >= B.  The circuit:
+ * |0>_sel |0>_walk |b^>, PREP (select amplitudes sqrt(|alpha_j| / |alpha|_1)),
+ * SELECT W^(2j+1), Z on the lowest select qubit (the signs), PREP^dagger.
+ * z_out (host, 2^n_s complex FP64 interleaved, may be NULL) receives the
+ * select = 0, walk = 0 amplitudes, unnormalised and in the computational
+ * basis: z = sum_j alpha_j T_{2j+1}(A~) b^ / |alpha|_1, p_post = |z|^2.
+ * A: host, 2^n_s x 2^n_s complex FP64 row-major, Hermitian, non-zero.
+ * After mode 0 the state holds the final circuit state; after mode 1 it holds
+ * the state after the signs, in the eigen frame.  Synchronises the stream.
+ * Errors: SV_EINVAL (sizes, B, mode, A = 0), SV_ENOTHERMITIAN,
+ * SV_EZERONORM (b = 0), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_qlsa2(sv_state s, const double *A, const double *b, const sv_qlsa2_params *prm,
+                   sv_qlsa2_result *res, double *z_out);
+
+/* ------------------------------------------------------------------------
  * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
  * study of Fig. 4b): many HHL instances of uneven size, each over its own
  * list of T0 values, solved in the fused eigen-frame mode with one launch per

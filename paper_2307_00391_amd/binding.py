@@ -47,6 +47,15 @@ class sv_hhl_result(ctypes.Structure):
                 ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
 
 
+class sv_qlsa2_params(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int), ("s", ctypes.c_int), ("B", ctypes.c_int), ("mode", ctypes.c_int)]
+
+
+class sv_qlsa2_result(ctypes.Structure):
+    _fields_ = [("p_post", ctypes.c_double), ("lambda_abs_max", ctypes.c_double),
+                ("lambda_abs_min", ctypes.c_double), ("alpha_l1", ctypes.c_double)]
+
+
 class sv_batch_instance(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int), ("n_c", ctypes.c_int), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("n_t0", ctypes.c_int), ("t0", ctypes.c_void_p)]
@@ -92,6 +101,7 @@ _SIGS = {
     "sv_last_eigensolver": ([], ctypes.c_char_p),
     "sv_qsp_prepare": ([_P, _P, _I, _I, _I], _I),
     "sv_lcu_derivative": ([_P, _I, _I, _I, _I], _I),
+    "sv_qlsa2": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
@@ -312,6 +322,20 @@ def sv_hhl(h, A, b, n_c, T0, mode=0, signed_clock=False):
     x = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_hhl(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)), "sv_hhl")
     return x, res
+
+
+def sv_qlsa2(h, A, b, s, B, mode=1):
+    """QLSA-2 (Chebyshev LCU): returns (z, result), z the post-selected
+    (select = 0, walk = 0) amplitudes, unnormalised, computational basis."""
+    A, Af = _f64(A)
+    b, bf = _f64(b)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    prm = sv_qlsa2_params(n_s, int(s), int(B), int(mode))
+    res = sv_qlsa2_result()
+    z = np.zeros(N, dtype=np.complex128)
+    _check(lib().sv_qlsa2(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(z)), "sv_qlsa2")
+    return z, res
 
 
 def sv_hhl_kron(h, A_hi, A_lo, b, n_c, T0, mode=1):

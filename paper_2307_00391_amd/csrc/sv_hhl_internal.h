@@ -42,6 +42,10 @@ uint64_t pipe_b_blocks_for(int n_s, int n_c, int cl);
 uint64_t pipe_b_blocks(int n_s, int n_c, size_t elem);
 int pipe_c_rows(int n_c);
 
+// W[r][j] = V[r][j] * E[j] for an N x N row-major V (sv_hhl.hip)
+__global__ void k_scale_cols(double2 *__restrict__ W, const double2 *__restrict__ V, const double2 *__restrict__ E,
+                             int N);
+
 // F[j][k] = frac(lam_j T0 / 2 pi 2^k) as 64-bit turn fractions (sv_hhl.hip)
 __global__ void k_turn_table(uint64_t *__restrict__ F, const double *__restrict__ lam, double T0, int n_c,
                              uint64_t N);

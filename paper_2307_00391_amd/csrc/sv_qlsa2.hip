@@ -1,0 +1,345 @@
+// QLSA-2: a linear-systems solver by a linear combination of unitaries over a
+// qubitized walk (main text, "Quantum Linear Systems Algorithm": the second
+// family of solvers, whose construction the paper takes from the cited work
+// of Childs, Kothari and Somma and does not spell out).
+//
+// The odd polynomial g(x) = (1 - (1 - x^2)^B) / x = sum_j alpha_j T_{2j+1}(x),
+// alpha_j = 4 (-1)^j sum_{i>j} C(2B, B+i) / 4^B, approximates 1/x on
+// 1/kappa <= |x| <= 1.  A~ = A / max|lambda| is block-encoded on one walk
+// qubit, U = [[A~, S], [S, -A~]] with S = sqrt(I - A~^2), and the walk
+// W = (Z on the walk qubit) U has T_k(A~) as the walk-0 block of W^k.  With
+// the select register (J = 2^s terms) prepared in sqrt(|alpha_j| / |alpha|_1),
+// SELECT W^(2j+1), the signs (-1)^j as one Z on the lowest select qubit and
+// PREP^dagger, the select = 0, walk = 0 block is g(A~) b^ / |alpha|_1.
+//
+// Layout: bits [0, n_s) system, bit n_s the walk qubit, [n_s + 1, n_s + 1 + s)
+// the select register.
+//   mode 0: the circuit in the computational basis: PREP and PREP^dagger as
+//           the QSP-1 tree of uniformly controlled Ry passes on the select
+//           register, W once and one controlled W^(2^(m+1)) per select qubit
+//           as dense unitaries of the (walk, system) register on the matrix
+//           cores (built in FP64 from the eigen-decomposition of A), the sign
+//           gate, post-selection;
+//   mode 1: the same circuit with the system register held in the eigenbasis
+//           of A, where W^(2j+1) is a rotation of the walk qubit by (2j+1)
+//           theta_k, theta_k = arccos(lambda~_k): one pass writes the state
+//           after PREP, SELECT and the signs, a second forms the select = 0
+//           projection of PREP^dagger (an FP64 sum over the select values).
+#include <math.h>
+
+#include <vector>
+
+#include "sv_device.h"
+#include "sv_hhl_internal.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+template <typename R>
+sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N, int K,
+                uint64_t row_mask, uint64_t row_fix, int trans, int conjb);
+template <typename R>
+sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
+
+static unsigned grid_for(uint64_t items) {
+    uint64_t g = (items + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+// alpha_j, j < J (zero for j >= B): t_i = C(2B, B+i) / 4^B from
+// t_0 = prod_{k<=B} (2k - 1) / (2k) and t_{i+1} = t_i (B - i) / (B + i + 1),
+// tails summed from the small end
+static void cheb_coeffs(int B, int J, std::vector<double> &alpha) {
+    std::vector<double> tail((size_t)B + 2, 0.0);
+    double t = 1.0;
+    for (int k = 1; k <= B; ++k) t *= (2.0 * k - 1.0) / (2.0 * k);
+    std::vector<double> term((size_t)B + 1);
+    term[0] = t;
+    for (int i = 0; i < B; ++i) term[i + 1] = term[i] * (double)(B - i) / (double)(B + i + 1);
+    double acc = 0.0;
+    for (int i = B; i >= 0; --i) {
+        acc += term[i];
+        tail[i] = acc;
+    }
+    alpha.assign(J, 0.0);
+    for (int j = 0; j < J && j + 1 <= B; ++j) alpha[j] = ((j & 1) ? -4.0 : 4.0) * tail[j + 1];
+}
+
+// the QSP-1 tree for real non-negative amplitudes w on the register
+// [q_lo, q_lo + m) of the current state (no initialisation), or its adjoint
+static sv_status tree_circuit(sv_state s, const std::vector<double> &amp, int q_lo, int m, bool adjoint) {
+    const uint64_t R = 1ull << m;
+    std::vector<double> w(2 * R, 0.0);
+    for (uint64_t r = 0; r < R; ++r) w[R + r] = amp[r] * amp[r];
+    for (uint64_t k = R - 1; k >= 1; --k) w[k] = w[2 * k] + w[2 * k + 1];
+    const double sg = adjoint ? -1.0 : 1.0;
+    const int top = q_lo + m - 1;
+    std::vector<double> lv;
+    for (int li = 0; li < m; ++li) {
+        const int l = adjoint ? m - 1 - li : li;
+        const uint64_t P = 1ull << l;
+        lv.assign(2 * P, 0.0);
+        for (uint64_t p = 0; p < P; ++p) {
+            const uint64_t node = P + p;
+            if (w[node] > 0.0) {
+                lv[2 * p] = sqrt(w[2 * node] / w[node]);
+                lv[2 * p + 1] = sg * sqrt(w[2 * node + 1] / w[node]);
+            } else {
+                lv[2 * p] = 1.0;
+                lv[2 * p + 1] = 0.0;
+            }
+        }
+        if (l == 0) {
+            const double u[8] = {lv[0], 0.0, -lv[1], 0.0, lv[1], 0.0, lv[0], 0.0};
+            SV_TRY(sv_apply_gate(s, top, u, nullptr, nullptr, 0));
+        } else {
+            SV_TRY(sv_apply_uniform_ry(s, top - l, top - l + 1, l, lv.data(), -1, 0));
+        }
+    }
+    return SV_OK;
+}
+
+// turn fraction (64-bit) of theta_k / 2 pi, theta_k = arccos(lambda_k / lmax)
+static void walk_turns(const std::vector<double> &lam, double lmax, std::vector<uint64_t> &t) {
+    t.resize(lam.size());
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (size_t k = 0; k < lam.size(); ++k) {
+        long double x = (long double)lam[k] / (long double)lmax;
+        if (x > 1.0L) x = 1.0L;
+        if (x < -1.0L) x = -1.0L;
+        const long double f = acosl(x) / two_pi;              // in [0, 1/2]
+        t[k] = (uint64_t)llroundl(ldexpl(f, 63)) << 1;         // f 2^64, even (exact for f = 1/2)
+    }
+}
+
+// (cos, sin) of the power-k walk angle as FP64, one row of E per block (c) and (s)
+__global__ void k_walk_cs(double2 *__restrict__ Ec, double2 *__restrict__ Es, const uint64_t *__restrict__ t,
+                          uint64_t power, int N) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+        const double2 e = turn_phase_f64(t[k] * power);
+        Ec[k] = make_double2(e.x, 0.0);
+        Es[k] = make_double2(e.y, 0.0);
+    }
+}
+
+// W^k = [[P, Q], [-Q, P]] with P = V C V^H, Q = V S V^H, in the state's dtype;
+// row/column index = (walk << n_s) | x
+template <typename R>
+__global__ void k_walk_assemble(cvec<R> *__restrict__ Wk, const double2 *__restrict__ P, const double2 *__restrict__ Q,
+                                int N) {
+    const uint64_t M = 2ull * N, total = M * M;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = i / M, c = i % M;
+        const uint64_t ra = r / N, ca = c / N, rx = r % N, cx = c % N;
+        double2 v = (ra == ca) ? P[rx * N + cx] : Q[rx * N + cx];
+        if (ra == 1 && ca == 0) v = make_double2(-v.x, -v.y);
+        Wk[i] = cmake<R>((R)v.x, (R)v.y);
+    }
+}
+
+// mode 1: the state after PREP, SELECT and the signs, in the eigen frame:
+// psi[j][walk][k] = (-1)^j p_j beta_k (cos, -sin)((2j+1) theta_k)
+template <typename R>
+__global__ __launch_bounds__(256) void k_cheb_select(cvec<R> *__restrict__ psi, const double2 *__restrict__ beta,
+                                                     const double *__restrict__ pj, const uint64_t *__restrict__ t,
+                                                     int n_s, uint64_t J) {
+    const uint64_t N = 1ull << n_s, total = J * N;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t j = i >> n_s, k = i & (N - 1);
+        const double2 bk = beta[k];
+        const double a = ((j & 1) ? -1.0 : 1.0) * pj[j];
+        const cvec<R> e = turn_phase<R>(t[k] * (2 * j + 1));
+        const cvec<R> amp = cmake<R>((R)(a * bk.x), (R)(a * bk.y));
+        const uint64_t base = (j << (n_s + 1)) | k;
+        psi[base] = cmake<R>(e.x * amp.x, e.x * amp.y);
+        psi[base | N] = cmake<R>(-e.y * amp.x, -e.y * amp.y);
+    }
+}
+
+// mode 1: z_k = sum_j p_j psi[j][0][k] (FP64, fixed order): one workgroup per k
+template <typename R>
+__global__ __launch_bounds__(256) void k_cheb_project(const cvec<R> *__restrict__ psi, const double *__restrict__ pj,
+                                                      double2 *__restrict__ z, int n_s, uint64_t J) {
+    __shared__ double sr[4], si[4];
+    const uint64_t k = blockIdx.x;
+    double ar = 0.0, ai = 0.0;
+    for (uint64_t j = threadIdx.x; j < J; j += blockDim.x) {
+        const cvec<R> v = psi[(j << (n_s + 1)) | k];
+        ar += pj[j] * (double)v.x;
+        ai += pj[j] * (double)v.y;
+    }
+    ar = wave_sum_f64(ar);
+    ai = wave_sum_f64(ai);
+    if ((threadIdx.x & 63) == 0) {
+        sr[threadIdx.x >> 6] = ar;
+        si[threadIdx.x >> 6] = ai;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) z[k] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
+}
+
+template <typename R>
+static sv_status run_mode0(sv_state s, int n_s, int sbits, const DevBuf &dV, const std::vector<uint64_t> &t,
+                           const std::vector<double> &pamp, const double *b) {
+    const int N = 1 << n_s, M = 2 * N;
+    const hipStream_t st = s->stream;
+    const uint64_t NN = (uint64_t)N * N, MM = (uint64_t)M * M;
+    DevBuf dt, Ec, Es, Wc, Ws, P, Q, Wk;
+    SV_TRY(dt.alloc(N * sizeof(uint64_t)));
+    SV_TRY(Ec.alloc(N * sizeof(double2)));
+    SV_TRY(Es.alloc(N * sizeof(double2)));
+    SV_TRY(Wc.alloc(NN * sizeof(double2)));
+    SV_TRY(Ws.alloc(NN * sizeof(double2)));
+    SV_TRY(P.alloc(NN * sizeof(double2)));
+    SV_TRY(Q.alloc(NN * sizeof(double2)));
+    SV_TRY(Wk.alloc(MM * sizeof(cvec<R>)));
+    SV_TRY(upload(s, dt.p, t.data(), N * sizeof(uint64_t)));
+    // one walk power as a dense unitary of the (walk, system) register
+    auto build = [&](uint64_t power) -> sv_status {
+        hipLaunchKernelGGL(k_walk_cs, dim3(grid_for(N)), dim3(256), 0, st, (double2 *)Ec.p, (double2 *)Es.p,
+                           (const uint64_t *)dt.p, power, N);
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(NN)), dim3(256), 0, st, (double2 *)Wc.p,
+                           (const double2 *)dV.p, (const double2 *)Ec.p, N);
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(NN)), dim3(256), 0, st, (double2 *)Ws.p,
+                           (const double2 *)dV.p, (const double2 *)Es.p, N);
+        SV_HIP(hipGetLastError());
+        SV_TRY(cgemm<double>(st, (const double2 *)Wc.p, (double2 *)P.p, (const double2 *)dV.p, (uint64_t)N, N, N,
+                             (uint64_t)(N - 1) << n_s, 0, 0, 1));
+        SV_TRY(cgemm<double>(st, (const double2 *)Ws.p, (double2 *)Q.p, (const double2 *)dV.p, (uint64_t)N, N, N,
+                             (uint64_t)(N - 1) << n_s, 0, 0, 1));
+        hipLaunchKernelGGL(k_walk_assemble<R>, dim3(grid_for(MM)), dim3(256), 0, st, (cvec<R> *)Wk.p,
+                           (const double2 *)P.p, (const double2 *)Q.p, N);
+        SV_HIP(hipGetLastError());
+        return SV_OK;
+    };
+    SV_TRY(sv_init_b(s, b, n_s, 0));
+    SV_TRY(tree_circuit(s, pamp, n_s + 1, sbits, false));
+    SV_TRY(build(1));
+    SV_TRY(ctrl_unitary_impl<R>(s, (const cvec<R> *)Wk.p, n_s + 1, -1, 1, 0));
+    for (int m = 0; m < sbits; ++m) {
+        SV_TRY(build(2ull << m));
+        SV_TRY(ctrl_unitary_impl<R>(s, (const cvec<R> *)Wk.p, n_s + 1, n_s + 1 + m, 1, 0));
+    }
+    static const double Z[8] = {1, 0, 0, 0, 0, 0, -1, 0};
+    SV_TRY(sv_apply_gate(s, n_s + 1, Z, nullptr, nullptr, 0));
+    SV_TRY(tree_circuit(s, pamp, n_s + 1, sbits, true));
+    SV_HIP(hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+template <typename R>
+static sv_status run_mode1(sv_state s, int n_s, int sbits, const DevBuf &dV, const std::vector<uint64_t> &t,
+                           const std::vector<double> &pamp, const std::vector<double> &bhat, double2 *z_dev) {
+    const uint64_t N = 1ull << n_s, J = 1ull << sbits;
+    const hipStream_t st = s->stream;
+    DevBuf db, dbeta, dtmp, dt, dp;
+    SV_TRY(db.alloc(N * sizeof(double2)));
+    SV_TRY(dbeta.alloc(N * sizeof(double2)));
+    SV_TRY(dtmp.alloc(N * sizeof(double2)));
+    SV_TRY(dt.alloc(N * sizeof(uint64_t)));
+    SV_TRY(dp.alloc(J * sizeof(double)));
+    SV_TRY(upload(s, db.p, bhat.data(), N * sizeof(double2)));
+    SV_TRY(upload(s, dt.p, t.data(), N * sizeof(uint64_t)));
+    SV_TRY(upload(s, dp.p, pamp.data(), J * sizeof(double)));
+    // beta = V^H b^
+    SV_TRY(kron_apply(st, (double2 *)dbeta.p, (const double2 *)db.p, (double2 *)dtmp.p, (const double2 *)dV.p,
+                      (int)N, nullptr, 1, 1));
+    {
+        TraceScope ts(st, "cheb_select", (double)(2 * J * N) * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_cheb_select<R>, dim3(grid_for(J * N)), dim3(256), 0, st, (cvec<R> *)s->data,
+                           (const double2 *)dbeta.p, (const double *)dp.p, (const uint64_t *)dt.p, n_s, J);
+    }
+    {
+        TraceScope ts(st, "cheb_project", (double)(J * N) * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_cheb_project<R>, dim3((unsigned)N), dim3(256), 0, st, (const cvec<R> *)s->data,
+                           (const double *)dp.p, (double2 *)dtmp.p, n_s, J);
+    }
+    SV_HIP(hipGetLastError());
+    // back to the computational basis: z = V z_eig
+    SV_TRY(kron_apply(st, z_dev, (const double2 *)dtmp.p, (double2 *)db.p, (const double2 *)dV.p, (int)N, nullptr,
+                      1, 0));
+    SV_HIP(hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_qlsa2(sv_state s, const double *A, const double *b, const sv_qlsa2_params *prm, sv_qlsa2_result *res,
+                   double *z_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!A || !b || !prm || !res) return fail(SV_EINVAL, "A, b, params or result is NULL");
+    const int n_s = prm->n_s, sbits = prm->s;
+    if (n_s < 1 || n_s > 13 || sbits < 1 || sbits > 24 || n_s + 1 + sbits != s->n)
+        return fail(SV_EINVAL, "n_s %d + 1 + s %d != %d qubits (1 <= n_s <= 13, 1 <= s <= 24)", n_s, sbits, s->n);
+    if (prm->B < 1 || prm->B > 20000000) return fail(SV_EINVAL, "B = %d outside [1, 2e7]", prm->B);
+    if (prm->mode != 0 && prm->mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    const int N = 1 << n_s;
+    const uint64_t J = 1ull << sbits;
+    SV_TRY(check_hermitian(A, N, "A"));
+    double bn = 0.0;
+    for (int j = 0; j < 2 * N; ++j) bn += b[j] * b[j];
+    bn = sqrt(bn);
+    if (!(bn > 0.0) || !isfinite(bn)) return fail(SV_EZERONORM, "|b| = 0 or not finite");
+    std::vector<double> bhat(2 * (size_t)N);
+    for (int j = 0; j < 2 * N; ++j) bhat[j] = b[j] / bn;
+    // spectrum and walk angles
+    DevBuf dV;
+    std::vector<double> lam;
+    SV_TRY(eigh_device(s, A, N, dV, lam));
+    double lmax = 0.0, lmin = INFINITY;
+    for (double l : lam) {
+        lmax = fmax(lmax, fabs(l));
+        lmin = fmin(lmin, fabs(l));
+    }
+    if (!(lmax > 0.0)) return fail(SV_EINVAL, "A = 0");
+    std::vector<uint64_t> turns;
+    walk_turns(lam, lmax, turns);
+    // LCU weights
+    std::vector<double> alpha;
+    cheb_coeffs(prm->B, (int)J, alpha);
+    double l1 = 0.0;
+    for (double a : alpha) l1 += fabs(a);
+    if (!(l1 > 0.0)) return fail(SV_EINVAL, "no Chebyshev term");
+    std::vector<double> pamp(J);
+    for (uint64_t j = 0; j < J; ++j) pamp[j] = sqrt(fabs(alpha[j]) / l1);
+    res->lambda_abs_max = lmax;
+    res->lambda_abs_min = lmin;
+    res->alpha_l1 = l1;
+    std::vector<double> z(2 * (size_t)N, 0.0);
+    if (prm->mode == 0) {
+        if (s->dt == SV_C64)
+            SV_TRY(run_mode0<float>(s, n_s, sbits, dV, turns, pamp, bhat.data()));
+        else
+            SV_TRY(run_mode0<double>(s, n_s, sbits, dV, turns, pamp, bhat.data()));
+        // the select = 0, walk = 0 block: the first 2^n_s amplitudes
+        double p = 0.0;
+        SV_TRY(sv_postselect(s, ((1ull << (sbits + 1)) - 1ull) << n_s, 0, &p, z.data(), 0));
+        const double sp = sqrt(p);
+        for (double &v : z) v *= sp;
+        res->p_post = p;
+    } else {
+        DevBuf dz;
+        SV_TRY(dz.alloc(N * sizeof(double2)));
+        if (s->dt == SV_C64)
+            SV_TRY(run_mode1<float>(s, n_s, sbits, dV, turns, pamp, bhat, (double2 *)dz.p));
+        else
+            SV_TRY(run_mode1<double>(s, n_s, sbits, dV, turns, pamp, bhat, (double2 *)dz.p));
+        SV_TRY(download(s, z.data(), dz.p, N * sizeof(double2)));
+        double p = 0.0;
+        for (int j = 0; j < 2 * N; ++j) p += z[j] * z[j];
+        res->p_post = p;
+    }
+    if (z_out)
+        for (int j = 0; j < 2 * N; ++j) z_out[j] = z[j];
+    return SV_OK;
+}
+
+}  // extern "C"
