@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-qsp", action="store_true")
     ap.add_argument("--no-qpp", action="store_true")
+    ap.add_argument("--no-qlsa2", action="store_true")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -363,6 +364,20 @@ def main():
         qs.close()
         del qs
         torch.cuda.empty_cache()
+
+    # ---------------- QLSA-2 (Chebyshev LCU) on the Poiseuille system ----------------
+    if not args.no_qlsa2:
+        from paper_2307_00391_amd import qlsa2
+        log("[bench] qlsa-2: Poiseuille, 16 points, eps = 1e-3, both modes")
+        sysm = inputs.poiseuille(16)
+        xref = np.linalg.solve(sysm.A, sysm.b)
+        rec = {"system": "Poiseuille, 16 points (kappa 116)", "eps": 1e-3}
+        for mode in (1, 0):
+            qlsa2.solve(sysm.A, sysm.b, 1e-3, "c64", mode)          # first use
+            xq, res, sq, Bq, el = qlsa2.solve(sysm.A, sysm.b, 1e-3, "c64", mode)
+            rec[f"mode{mode}"] = {"qubits": 4 + 1 + sq, "B": Bq, "terms": 1 << sq, "seconds": el,
+                                  "one_minus_F": 1.0 - qlsa2.fidelity(xq, xref), "p_post": res.p_post}
+        out["qlsa2"] = rec
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------
     if not args.no_cpu:

@@ -39,3 +39,14 @@ def test_parameters_grow_with_precision():
         assert cur[0] > prev[0] and cur[1] >= prev[1]
         prev = cur
     assert qlsa2.parameters(116.46, 1e-3) == (158216, 11)
+
+
+def test_tq_sample_system_condition_number():
+    """The stand-in for the paper's 8 x 8 sample system has kappa = 18.8795
+    and stays a shifted second difference (symmetric, tridiagonal)."""
+    from paper_2307_00391_amd import tq
+    A, b = tq.sample_system()
+    lam = np.linalg.eigvalsh(A)
+    assert abs(lam.max() / lam.min() - 18.8795) < 1e-10
+    assert np.allclose(A, A.T) and np.count_nonzero(np.triu(A, 2)) == 0
+    assert b.shape == (8,)
