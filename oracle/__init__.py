@@ -42,6 +42,8 @@ def _load():
     lib.orc_cks_coeffs.argtypes = [ctypes.c_int, ctypes.c_int, _f64p]
     lib.orc_qlsa2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _c128p, _c128p, _c128p, _c128p,
                               ctypes.POINTER(ctypes.c_double)]
+    lib.orc_qlsa2_fourier.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      _c128p, _c128p, _c128p, _c128p, ctypes.POINTER(ctypes.c_double)]
     lib.orc_norm2.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.orc_norm2.restype = ctypes.c_double
     lib.orc_postselect.argtypes = [_c128p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -214,4 +216,21 @@ def qlsa2(A, b, s, B):
     z = np.zeros(N, dtype=np.complex128)
     p = ctypes.c_double(0.0)
     _check(_load().orc_qlsa2(n_s, int(s), int(B), A, b, psi, z, ctypes.byref(p)), "qlsa2")
+    return psi, z, p.value
+
+
+def qlsa2_fourier(A, b, sy, sz, dy, dz):
+    """QLSA-2 in Fourier form (see oracle.c): returns (psi, z, p_post), z the
+    post-selected (select = 0) amplitudes, unnormalised."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    if N != 1 << n_s or b.shape != (N,):
+        raise ValueError("A must be 2^n_s square and b of length 2^n_s")
+    psi = np.zeros(1 << (n_s + int(sy) + int(sz)), dtype=np.complex128)
+    z = np.zeros(N, dtype=np.complex128)
+    p = ctypes.c_double(0.0)
+    _check(_load().orc_qlsa2_fourier(n_s, int(sy), int(sz), float(dy), float(dz), A, b, psi, z, ctypes.byref(p)),
+           "qlsa2_fourier")
     return psi, z, p.value

@@ -795,6 +795,92 @@ done:
     return rc;
 }
 
+/*
+ * QLSA-2, Fourier form (the cited Childs-Kothari-Somma construction; the
+ * paper defers it): the integral representation
+ *     1/x = (i / sqrt(2 pi)) int_0^inf dy int_-inf^inf dz z e^{-z^2/2} e^{-i x y z}
+ * discretised as h(x) = sum_{j,k} w_jk i sign(z_k) e^{-i x y_j z_k} with
+ *     y_j = j dy (j < 2^sy),  z_k = k dz,  k = m + 1 (m < K) or m - 2K (m >= K),
+ *     K = 2^(sz - 1),  w_jk = dy dz |z_k| e^{-z_k^2 / 2} / sqrt(2 pi),
+ * an LCU of the unitaries i sign(z_k) exp(-i A~ y_j z_k), A~ = A / max|lambda|.
+ *   layout: bits [0, n_s) system, [n_s, n_s + sy) the j register,
+ *   [n_s + sy, n_s + sy + sz) the m register (select value r = j + 2^sy m);
+ *   1. |0>_sel |b^>;  2. PREP: the QSP-1 tree with sqrt(w_r / |w|_1);
+ *   3. SELECT: the unitary of term r on the system sub-vector of select r,
+ *      exp(-i A~ t) = V diag(e^{-i lambda~ t}) V^dagger (the oracle's eigensolver);
+ *   4. PREP^dagger;  5. post-select select = 0: z = h(A~) b^ / |w|_1.
+ */
+int orc_qlsa2_fourier(int n_s, int sy, int sz, double dy, double dz, const cplx *A, const cplx *b, cplx *psi,
+                      cplx *z_out, double *p_post)
+{
+    if (n_s < 1 || sy < 1 || sz < 1 || n_s + sy + sz > 26 || !(dy > 0.0) || !(dz > 0.0)) return ORC_EINVAL;
+    const int N = 1 << n_s, n = n_s + sy + sz, S = sy + sz;
+    const uint64_t dim = (uint64_t)1 << n, R = (uint64_t)1 << S, Jn = (uint64_t)1 << sy;
+    const int64_t K = (int64_t)1 << (sz - 1);
+    double bn = 0.0;
+    for (int j = 0; j < N; ++j) bn += creal(b[j] * conj(b[j]));
+    bn = sqrt(bn);
+    if (!(bn > 0.0)) return ORC_EINVAL;
+    double *lam = (double *)malloc(sizeof(double) * N);
+    cplx *V = (cplx *)malloc(sizeof(cplx) * (size_t)N * N);
+    cplx *pamp = (cplx *)malloc(sizeof(cplx) * R);
+    cplx *u = (cplx *)malloc(sizeof(cplx) * N), *v = (cplx *)malloc(sizeof(cplx) * N);
+    int rc = ORC_OK;
+    double lmax = 0.0, l1 = 0.0;
+    if (!lam || !V || !pamp || !u || !v) { rc = ORC_ENOMEM; goto done; }
+    memset(psi, 0, sizeof(cplx) * dim);
+    for (int j = 0; j < N; ++j) psi[j] = b[j] / bn;
+    if ((rc = orc_eigh(N, A, lam, V)) != ORC_OK) goto done;
+    for (int k = 0; k < N; ++k) lmax = fmax(lmax, fabs(lam[k]));
+    if (!(lmax > 0.0)) { rc = ORC_EINVAL; goto done; }
+    /* the LCU weights */
+    for (uint64_t r = 0; r < R; ++r) {
+        const int64_t m = (int64_t)(r >> sy);
+        const int64_t k = m < K ? m + 1 : m - 2 * K;
+        const double zk = (double)k * dz;
+        const double w = dy * dz * fabs(zk) * exp(-0.5 * zk * zk) / sqrt(2.0 * ORC_PI);
+        pamp[r] = w;
+        l1 += w;
+    }
+    for (uint64_t r = 0; r < R; ++r) pamp[r] = sqrt(creal(pamp[r]) / l1);
+    /* PREP */
+    if ((rc = orc_qsp_apply(psi, n, n_s, S, pamp, 0)) != ORC_OK) goto done;
+    /* SELECT */
+    for (uint64_t r = 0; r < R; ++r) {
+        const uint64_t j = r & (Jn - 1);
+        const int64_t m = (int64_t)(r >> sy);
+        const int64_t k = m < K ? m + 1 : m - 2 * K;
+        const double t = (double)j * dy * (double)k * dz;
+        const cplx sgn = k > 0 ? I : -I;
+        const uint64_t off = r << n_s;
+        /* u = V^dagger psi_r, scaled by e^{-i lambda~ t}, then V u */
+        for (int a = 0; a < N; ++a) {
+            cplx acc = 0;
+            for (int c = 0; c < N; ++c) acc += conj(V[(size_t)c * N + a]) * psi[off + c];
+            u[a] = acc * cexp(-I * (lam[a] / lmax) * t);
+        }
+        for (int c = 0; c < N; ++c) {
+            cplx acc = 0;
+            for (int a = 0; a < N; ++a) acc += V[(size_t)c * N + a] * u[a];
+            v[c] = sgn * acc;
+        }
+        for (int c = 0; c < N; ++c) psi[off + c] = v[c];
+    }
+    /* PREP^dagger */
+    if ((rc = orc_qsp_apply(psi, n, n_s, S, pamp, 1)) != ORC_OK) goto done;
+    {
+        double pp = 0.0;
+        for (int k = 0; k < N; ++k) {
+            z_out[k] = psi[k];
+            pp += creal(psi[k] * conj(psi[k]));
+        }
+        *p_post = pp;
+    }
+done:
+    free(lam); free(V); free(pamp); free(u); free(v);
+    return rc;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

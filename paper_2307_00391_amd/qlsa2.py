@@ -28,6 +28,35 @@ def parameters(kappa: float, eps: float):
     return Bdeg, s
 
 
+def fourier_parameters(kappa: float, eps: float):
+    """(sy, sz, dy, dz) of the Fourier form, each of three error terms below eps / 3:
+    y-cut Y = kappa sqrt(2 ln(3 kappa / eps)) (the tail (1/x) e^{-x^2 Y^2 / 2});
+    dy = 2 sqrt(eps) (the left sum of x y e^{-x^2 y^2 / 2} from y = 0 is off by dy^2 x / 12);
+    2^sy >= Y / dy, so the sum runs to Y' = 2^sy dy >= Y;
+    z-cut Z = sqrt(2 ln(6 Y' / (sqrt(2 pi) eps))) (the Gaussian tail over y <= Y');
+    dz = 2 pi / (Y' + 2 Z) (the first alias of the z-sum lies 2 pi / dz - x y >= 2 Z away);
+    2^(sz - 1) >= Z / dz."""
+    Y = kappa * math.sqrt(2.0 * math.log(3.0 * kappa / eps))
+    dy = 2.0 * math.sqrt(eps)
+    sy = max(1, math.ceil(math.log2(Y / dy)))
+    Yr = (1 << sy) * dy
+    Z = math.sqrt(2.0 * math.log(6.0 * Yr / (math.sqrt(2.0 * math.pi) * eps)))
+    dz = 2.0 * math.pi / (Yr + 2.0 * Z)
+    sz = max(1, math.ceil(math.log2(Z / dz))) + 1
+    return sy, sz, dy, dz
+
+
+def fourier_terms(sy: int, sz: int, dy: float, dz: float):
+    """(w, t, sign): weights, times y_j z_k and the sign of z_k of every select value r = j + 2^sy m."""
+    J, K = 1 << sy, 1 << (sz - 1)
+    r = np.arange(J * 2 * K)
+    j, m = r & (J - 1), r >> sy
+    k = np.where(m < K, m + 1, m - 2 * K)
+    z = k * dz
+    w = dy * dz * np.abs(z) * np.exp(-0.5 * z * z) / math.sqrt(2 * math.pi)
+    return w, j * dy * z, np.sign(k)
+
+
 def solve(A, b, eps: float, dtype: str = "c64", mode: int = 1, kappa: float | None = None):
     """Run QLSA-2 for A x = b at target error eps; returns (x_unit, result, s, B, seconds)."""
     A = np.asarray(A)
