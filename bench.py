@@ -368,7 +368,7 @@ def main():
     # ---------------- QLSA-2 (Chebyshev LCU) on the Poiseuille system ----------------
     if not args.no_qlsa2:
         from paper_2307_00391_amd import qlsa2
-        log("[bench] qlsa-2: Poiseuille, 16 points, eps = 1e-3, both modes")
+        log("[bench] qlsa-2: Poiseuille, 16 points, eps = 1e-3, Chebyshev (both modes) and Fourier form")
         sysm = inputs.poiseuille(16)
         xref = np.linalg.solve(sysm.A, sysm.b)
         rec = {"system": "Poiseuille, 16 points (kappa 116)", "eps": 1e-3}
@@ -377,6 +377,17 @@ def main():
             xq, res, sq, Bq, el = qlsa2.solve(sysm.A, sysm.b, 1e-3, "c64", mode)
             rec[f"mode{mode}"] = {"qubits": 4 + 1 + sq, "B": Bq, "terms": 1 << sq, "seconds": el,
                                   "one_minus_F": 1.0 - qlsa2.fidelity(xq, xref), "p_post": res.p_post}
+        # the Fourier form at the same target error (29 qubits), with the select pass traced
+        qlsa2.solve_fourier(sysm.A, sysm.b, 1e-3, "c64")                 # first use
+        B.sv_trace_enable(True)
+        xq, res, (sy, sz, dy, dz), el = qlsa2.solve_fourier(sysm.A, sysm.b, 1e-3, "c64")
+        tr = B.sv_trace_report()
+        B.sv_trace_enable(False)
+        ks, kp = tr["fourier_select"], tr["fourier_project"]
+        rec["fourier"] = {"qubits": 4 + sy + sz, "sy": sy, "sz": sz, "dy": dy, "dz": dz, "seconds": el,
+                          "one_minus_F": 1.0 - qlsa2.fidelity(xq, xref), "p_post": res.p_post,
+                          "select_ms": ks["ms"], "select_hbm_gbs": ks["bytes"] / (ks["ms"] * 1e-3) / 1e9,
+                          "project_ms": kp["ms"], "project_hbm_gbs": kp["bytes"] / (kp["ms"] * 1e-3) / 1e9}
         out["qlsa2"] = rec
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------

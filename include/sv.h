@@ -413,6 +413,30 @@ typedef struct {
 sv_status sv_qlsa2(sv_state s, const double *A, const double *b, const sv_qlsa2_params *prm,
                    sv_qlsa2_result *res, double *z_out);
 
+typedef struct {
+    int n_s;        /* system qubits (1..13) */
+    int sy, sz;     /* select registers: j < 2^sy, and m < 2^sz for z_k (sy + sz <= 30) */
+    double dy, dz;  /* grid steps of the two integrals */
+} sv_qlsa2f_params;
+
+/* QLSA-2 in Fourier form: the integral representation
+ * 1/x = (i / sqrt(2 pi)) int_0^inf dy int dz z e^{-z^2/2} e^{-i x y z}, discretised
+ * as h(x) = sum_{j,k} w_jk i sign(z_k) e^{-i x y_j z_k}, y_j = j dy (j < 2^sy),
+ * z_k = k dz with k = m + 1 (m < 2^(sz-1)) or m - 2^sz, w_jk = dy dz |z_k|
+ * e^{-z_k^2/2} / sqrt(2 pi): a linear combination of the unitaries
+ * i sign(z_k) exp(-i A~ y_j z_k), A~ = A / max|lambda|.  The state must have
+ * n_s + sy + sz qubits: bits [0, n_s) system, [n_s, n_s + sy) the j register,
+ * [n_s + sy, n_s + sy + sz) the m register.  The circuit (PREP with
+ * sqrt(w / |w|_1), SELECT, PREP^dagger, post-selection of select = 0) runs
+ * with the system register in the eigenbasis of A: one pass writes the state
+ * after SELECT, one FP64 reduction forms the select = 0 projection.
+ * z_out as in sv_qlsa2: z = h(A~) b^ / |w|_1 in the computational basis,
+ * p_post = |z|^2; alpha_l1 of the result holds |w|_1.  Synchronises the stream.
+ * Errors: SV_EINVAL (sizes, steps, A = 0), SV_ENOTHERMITIAN, SV_EZERONORM,
+ * SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const sv_qlsa2f_params *prm,
+                           sv_qlsa2_result *res, double *z_out);
+
 /* ------------------------------------------------------------------------
  * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
  * study of Fig. 4b): many HHL instances of uneven size, each over its own

@@ -56,6 +56,11 @@ class sv_qlsa2_result(ctypes.Structure):
                 ("lambda_abs_min", ctypes.c_double), ("alpha_l1", ctypes.c_double)]
 
 
+class sv_qlsa2f_params(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int), ("sy", ctypes.c_int), ("sz", ctypes.c_int), ("dy", ctypes.c_double),
+                ("dz", ctypes.c_double)]
+
+
 class sv_batch_instance(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int), ("n_c", ctypes.c_int), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("n_t0", ctypes.c_int), ("t0", ctypes.c_void_p)]
@@ -102,6 +107,7 @@ _SIGS = {
     "sv_qsp_prepare": ([_P, _P, _I, _I, _I], _I),
     "sv_lcu_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_qlsa2": ([_P, _P, _P, _P, _P, _P], _I),
+    "sv_qlsa2_fourier": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
@@ -335,6 +341,20 @@ def sv_qlsa2(h, A, b, s, B, mode=1):
     res = sv_qlsa2_result()
     z = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_qlsa2(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(z)), "sv_qlsa2")
+    return z, res
+
+
+def sv_qlsa2_fourier(h, A, b, sy, sz, dy, dz):
+    """QLSA-2 in Fourier form: returns (z, result), z as in sv_qlsa2."""
+    A, Af = _f64(A)
+    b, bf = _f64(b)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    prm = sv_qlsa2f_params(n_s, int(sy), int(sz), float(dy), float(dz))
+    res = sv_qlsa2_result()
+    z = np.zeros(N, dtype=np.complex128)
+    _check(lib().sv_qlsa2_fourier(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(z)),
+           "sv_qlsa2_fourier")
     return z, res
 
 

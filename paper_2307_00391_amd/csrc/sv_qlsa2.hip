@@ -159,17 +159,52 @@ __global__ __launch_bounds__(256) void k_cheb_select(cvec<R> *__restrict__ psi, 
     }
 }
 
-// mode 1: z_k = sum_j p_j psi[j][0][k] (FP64, fixed order): one workgroup per k
+// The select = 0 projection of PREP^dagger, z_k = sum_r p_r psi[(r << shift) | k]
+// with p_r = pw[r >> wshift] (FP64, fixed order), in two passes.  Pass 1: block (x, y) takes the columns
+// [y W, y W + W), W = min(N, 256), and the select rows [x L, x L + L); its 256
+// threads read 256 / W rows per step, consecutive threads at consecutive
+// addresses when shift = n_s; part[x][k] holds the block's sum.
 template <typename R>
-__global__ __launch_bounds__(256) void k_cheb_project(const cvec<R> *__restrict__ psi, const double *__restrict__ pj,
-                                                      double2 *__restrict__ z, int n_s, uint64_t J) {
+__global__ __launch_bounds__(256) void k_select_partial(const cvec<R> *__restrict__ psi, const double *__restrict__ pr,
+                                                        double2 *__restrict__ part, int n_s, int shift, int wshift,
+                                                        uint64_t nsel, uint64_t rows) {
+    __shared__ double sr[256], si[256];
+    const int lw = n_s < 8 ? n_s : 8;
+    const uint64_t W = 1ull << lw, P = 256u >> lw;
+    const uint64_t lane = threadIdx.x & (W - 1), sub = threadIdx.x >> lw;
+    const uint64_t col = ((uint64_t)blockIdx.y << lw) | lane;
+    const uint64_t r0 = (uint64_t)blockIdx.x * rows, r1 = r0 + rows < nsel ? r0 + rows : nsel;
+    double ar = 0.0, ai = 0.0;
+    for (uint64_t r = r0 + sub; r < r1; r += P) {
+        const cvec<R> v = psi[(r << shift) | col];
+        const double w = pr[r >> wshift];
+        ar += w * (double)v.x;
+        ai += w * (double)v.y;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    if (sub == 0) {
+        double tr = 0.0, ti = 0.0;
+        for (uint64_t q = 0; q < P; ++q) {
+            tr += sr[(q << lw) | lane];
+            ti += si[(q << lw) | lane];
+        }
+        part[((uint64_t)blockIdx.x << n_s) | col] = make_double2(tr, ti);
+    }
+}
+
+// Pass 2: one block per column k sums part[x][k] over the chunks x (each
+// thread a fixed stride of chunks, then a fixed-shape tree)
+__global__ __launch_bounds__(256) void k_select_finish(const double2 *__restrict__ part, double2 *__restrict__ z,
+                                                       int n_s, unsigned chunks) {
     __shared__ double sr[4], si[4];
     const uint64_t k = blockIdx.x;
     double ar = 0.0, ai = 0.0;
-    for (uint64_t j = threadIdx.x; j < J; j += blockDim.x) {
-        const cvec<R> v = psi[(j << (n_s + 1)) | k];
-        ar += pj[j] * (double)v.x;
-        ai += pj[j] * (double)v.y;
+    for (unsigned x = threadIdx.x; x < chunks; x += blockDim.x) {
+        const double2 v = part[((uint64_t)x << n_s) | k];
+        ar += v.x;
+        ai += v.y;
     }
     ar = wave_sum_f64(ar);
     ai = wave_sum_f64(ai);
@@ -179,6 +214,107 @@ __global__ __launch_bounds__(256) void k_cheb_project(const cvec<R> *__restrict_
     }
     __syncthreads();
     if (threadIdx.x == 0) z[k] = make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
+}
+
+// z (N FP64 entries, device) from the state: chunking chosen for about 2048
+// blocks in pass 1; the partial sums take at most 2^20 complex entries
+template <typename R>
+static sv_status select_project(sv_state s, const double *pr, double2 *z, int n_s, int shift, int wshift,
+                                uint64_t nsel, const char *label) {
+    const hipStream_t st = s->stream;
+    const int lw = n_s < 8 ? n_s : 8;
+    const uint64_t N = 1ull << n_s, P = 256u >> lw, gy = N >> lw;
+    uint64_t chunks = 2048 / gy;
+    if (chunks < 1) chunks = 1;
+    const uint64_t steps = (nsel + P - 1) / P;
+    if (chunks > steps) chunks = steps;
+    const uint64_t rows = ((nsel + chunks - 1) / chunks + P - 1) / P * P;
+    chunks = (nsel + rows - 1) / rows;
+    DevBuf part;
+    SV_TRY(part.alloc(chunks * N * sizeof(double2)));
+    {
+        TraceScope ts(st, label, (double)(nsel * N) * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_select_partial<R>, dim3((unsigned)chunks, (unsigned)gy), dim3(256), 0, st,
+                           (const cvec<R> *)s->data, pr, (double2 *)part.p, n_s, shift, wshift, nsel, rows);
+        hipLaunchKernelGGL(k_select_finish, dim3((unsigned)N), dim3(256), 0, st, (const double2 *)part.p, z, n_s,
+                           (unsigned)chunks);
+    }
+    SV_HIP(hipGetLastError());
+    // the partial buffer is released by its destructor: wait for the kernels first
+    SV_HIP(hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+// Fourier form, eigen frame: psi[r][k] = p_m beta_k i sign(z) e^{-i lambda~_k y_j z_k}
+// for r = j + 2^sy m, y_j = j dy, z_k = k dz with k = m + 1 (m < K) or m - 2K (the
+// PREP amplitude p_m depends on m only).
+// complex128: the argument -lambda~_k (j dy k dz) in FP64 and an FP64 sincos;
+// complex64: the phase as an exact 64-bit turn count, -F_k j k mod 2^64 with
+// F_k = lambda~_k dy dz / 2 pi in units of 2^-64 turns, and an FP32 sincospi.
+// The factor i sign(z) swaps the components.
+template <typename R>
+__global__ __launch_bounds__(256) void k_fourier_select(cvec<R> *__restrict__ psi, const double2 *__restrict__ beta,
+                                                        const double *__restrict__ pr, const double *__restrict__ lamt,
+                                                        const uint64_t *__restrict__ F, int n_s, int sy, int sz,
+                                                        double dy, double dz) {
+    const uint64_t N = 1ull << n_s, total = (1ull << (sy + sz)) << n_s;
+    const int64_t K = (int64_t)1 << (sz - 1);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const uint64_t r = i >> n_s, k = i & (N - 1);
+        const int64_t j = (int64_t)(r & ((1ull << sy) - 1ull));
+        const int64_t m = (int64_t)(r >> sy);
+        const int64_t kk = m < K ? m + 1 : m - 2 * K;
+        cvec<R> e;
+        if (sizeof(R) == 8) {
+            const double t = (double)j * dy * (double)kk * dz;
+            double sd, cd;
+            sincos(-lamt[k] * t, &sd, &cd);
+            e = cmake<R>((R)cd, (R)sd);
+        } else {
+            e = turn_phase<R>((uint64_t)0 - F[k] * (uint64_t)(j * kk));
+        }
+        const double2 bk = beta[k];
+        const double a = pr[m];
+        const R ar = (R)(a * bk.x), ai = (R)(a * bk.y);
+        const R xr = e.x * ar - e.y * ai, xi = e.x * ai + e.y * ar;
+        psi[i] = kk > 0 ? cmake<R>(-xi, xr) : cmake<R>(xi, -xr);
+    }
+}
+
+template <typename R>
+static sv_status run_fourier(sv_state s, int n_s, int sy, int sz, double dy, double dz, const DevBuf &dV,
+                             const std::vector<double> &lamt, const std::vector<uint64_t> &F,
+                             const std::vector<double> &pr, const std::vector<double> &bhat, double2 *z_dev) {
+    const uint64_t N = 1ull << n_s, R2 = 1ull << (sy + sz);
+    const hipStream_t st = s->stream;
+    DevBuf db, dbeta, dtmp, dl, dF, dp;
+    SV_TRY(db.alloc(N * sizeof(double2)));
+    SV_TRY(dbeta.alloc(N * sizeof(double2)));
+    SV_TRY(dtmp.alloc(N * sizeof(double2)));
+    SV_TRY(dl.alloc(N * sizeof(double)));
+    SV_TRY(dF.alloc(N * sizeof(uint64_t)));
+    SV_TRY(dp.alloc(pr.size() * sizeof(double)));
+    SV_TRY(upload(s, db.p, bhat.data(), N * sizeof(double2)));
+    SV_TRY(upload(s, dl.p, lamt.data(), N * sizeof(double)));
+    SV_TRY(upload(s, dF.p, F.data(), N * sizeof(uint64_t)));
+    SV_TRY(upload(s, dp.p, pr.data(), pr.size() * sizeof(double)));
+    // beta = V^H b^
+    SV_TRY(kron_apply(st, (double2 *)dbeta.p, (const double2 *)db.p, (double2 *)dtmp.p, (const double2 *)dV.p,
+                      (int)N, nullptr, 1, 1));
+    {
+        TraceScope ts(st, "fourier_select", (double)(R2 * N) * sizeof(cvec<R>), 0.0);
+        hipLaunchKernelGGL(k_fourier_select<R>, dim3(grid_for(R2 * N)), dim3(256), 0, st, (cvec<R> *)s->data,
+                           (const double2 *)dbeta.p, (const double *)dp.p, (const double *)dl.p,
+                           (const uint64_t *)dF.p, n_s, sy, sz, dy, dz);
+    }
+    SV_HIP(hipGetLastError());
+    SV_TRY(select_project<R>(s, (const double *)dp.p, (double2 *)dtmp.p, n_s, n_s, sy, R2, "fourier_project"));
+    // back to the computational basis: z = V z_eig
+    SV_TRY(kron_apply(st, z_dev, (const double2 *)dtmp.p, (double2 *)db.p, (const double2 *)dV.p, (int)N, nullptr,
+                      1, 0));
+    SV_HIP(hipStreamSynchronize(st));
+    return SV_OK;
 }
 
 template <typename R>
@@ -252,12 +388,8 @@ static sv_status run_mode1(sv_state s, int n_s, int sbits, const DevBuf &dV, con
         hipLaunchKernelGGL(k_cheb_select<R>, dim3(grid_for(J * N)), dim3(256), 0, st, (cvec<R> *)s->data,
                            (const double2 *)dbeta.p, (const double *)dp.p, (const uint64_t *)dt.p, n_s, J);
     }
-    {
-        TraceScope ts(st, "cheb_project", (double)(J * N) * sizeof(cvec<R>), 0.0);
-        hipLaunchKernelGGL(k_cheb_project<R>, dim3((unsigned)N), dim3(256), 0, st, (const cvec<R> *)s->data,
-                           (const double *)dp.p, (double2 *)dtmp.p, n_s, J);
-    }
     SV_HIP(hipGetLastError());
+    SV_TRY(select_project<R>(s, (const double *)dp.p, (double2 *)dtmp.p, n_s, n_s + 1, 0, J, "cheb_project"));
     // back to the computational basis: z = V z_eig
     SV_TRY(kron_apply(st, z_dev, (const double2 *)dtmp.p, (double2 *)db.p, (const double2 *)dV.p, (int)N, nullptr,
                       1, 0));
@@ -337,6 +469,77 @@ sv_status sv_qlsa2(sv_state s, const double *A, const double *b, const sv_qlsa2_
         for (int j = 0; j < 2 * N; ++j) p += z[j] * z[j];
         res->p_post = p;
     }
+    if (z_out)
+        for (int j = 0; j < 2 * N; ++j) z_out[j] = z[j];
+    return SV_OK;
+}
+
+sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const sv_qlsa2f_params *prm,
+                           sv_qlsa2_result *res, double *z_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!A || !b || !prm || !res) return fail(SV_EINVAL, "A, b, params or result is NULL");
+    const int n_s = prm->n_s, sy = prm->sy, sz = prm->sz;
+    if (n_s < 1 || n_s > 13 || sy < 1 || sz < 1 || sy + sz > 30 || n_s + sy + sz != s->n)
+        return fail(SV_EINVAL, "n_s %d + sy %d + sz %d != %d qubits (1 <= n_s <= 13)", n_s, sy, sz, s->n);
+    if (!(prm->dy > 0.0) || !(prm->dz > 0.0) || !isfinite(prm->dy) || !isfinite(prm->dz))
+        return fail(SV_EINVAL, "dy and dz must be positive");
+    const int N = 1 << n_s;
+    SV_TRY(check_hermitian(A, N, "A"));
+    double bn = 0.0;
+    for (int j = 0; j < 2 * N; ++j) bn += b[j] * b[j];
+    bn = sqrt(bn);
+    if (!(bn > 0.0) || !isfinite(bn)) return fail(SV_EZERONORM, "|b| = 0 or not finite");
+    std::vector<double> bhat(2 * (size_t)N);
+    for (int j = 0; j < 2 * N; ++j) bhat[j] = b[j] / bn;
+    DevBuf dV;
+    std::vector<double> lam;
+    SV_TRY(eigh_device(s, A, N, dV, lam));
+    double lmax = 0.0, lmin = INFINITY;
+    for (double l : lam) {
+        lmax = fmax(lmax, fabs(l));
+        lmin = fmin(lmin, fabs(l));
+    }
+    if (!(lmax > 0.0)) return fail(SV_EINVAL, "A = 0");
+    std::vector<double> lamt(N);
+    std::vector<uint64_t> F(N);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int k = 0; k < N; ++k) {
+        lamt[k] = lam[k] / lmax;
+        // lambda~ dy dz / 2 pi as a signed 64-bit turn fraction (reduced to [-1/2, 1/2])
+        long double f = (long double)lamt[k] * (long double)prm->dy * (long double)prm->dz / two_pi;
+        f -= nearbyintl(f);
+        F[k] = (uint64_t)(int64_t)llroundl(ldexpl(f, 63)) * 2u;
+    }
+    // LCU weights w_r = dy dz |z_m| e^{-z_m^2/2} / sqrt(2 pi), the same for all 2^sy
+    // values of j; PREP amplitudes sqrt(w_r / |w|_1) per m; |w|_1 in long double
+    const int64_t K = (int64_t)1 << (sz - 1);
+    const uint64_t M = 1ull << sz;
+    std::vector<double> pr(M);
+    long double l1acc = 0.0L;
+    for (uint64_t m = 0; m < M; ++m) {
+        const int64_t kk = (int64_t)m < K ? (int64_t)m + 1 : (int64_t)m - 2 * K;
+        const double z = (double)kk * prm->dz;
+        pr[m] = prm->dy * prm->dz * fabs(z) * exp(-0.5 * z * z) / sqrt(2.0 * M_PI);
+        l1acc += pr[m];
+    }
+    const double l1 = (double)(l1acc * (long double)(1ull << sy));
+    if (!(l1 > 0.0)) return fail(SV_EINVAL, "no Fourier term");
+    for (uint64_t m = 0; m < M; ++m) pr[m] = sqrt(pr[m] / l1);
+    res->lambda_abs_max = lmax;
+    res->lambda_abs_min = lmin;
+    res->alpha_l1 = l1;
+    DevBuf dz;
+    SV_TRY(dz.alloc(N * sizeof(double2)));
+    if (s->dt == SV_C64)
+        SV_TRY(run_fourier<float>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
+    else
+        SV_TRY(run_fourier<double>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
+    std::vector<double> z(2 * (size_t)N);
+    SV_TRY(download(s, z.data(), dz.p, N * sizeof(double2)));
+    double p = 0.0;
+    for (int j = 0; j < 2 * N; ++j) p += z[j] * z[j];
+    res->p_post = p;
     if (z_out)
         for (int j = 0; j < 2 * N; ++j) z_out[j] = z[j];
     return SV_OK;

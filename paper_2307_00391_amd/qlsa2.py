@@ -1,5 +1,5 @@
-"""QLSA-2 (Chebyshev linear combination of unitaries) next to QLSA-1 (HHL) on
-the paper's steady channel-flow systems.
+"""QLSA-2 (Chebyshev, and Fourier form, linear combinations of unitaries) next
+to QLSA-1 (HHL) on the paper's steady channel-flow systems.
 
 Parameters of the Chebyshev solver from the condition number and a target
 error (after the cited Childs-Kothari-Somma analysis):
@@ -76,6 +76,30 @@ def solve(A, b, eps: float, dtype: str = "c64", mode: int = 1, kappa: float | No
     return z / np.linalg.norm(z), res, s, Bdeg, el
 
 
+def solve_fourier(A, b, eps: float, dtype: str = "c64", kappa: float | None = None):
+    """QLSA-2 in Fourier form at target error eps; returns (x_unit, result, (sy, sz, dy, dz), seconds)."""
+    A = np.asarray(A)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    if kappa is None:
+        lam = np.abs(np.linalg.eigvalsh(A))
+        kappa = lam.max() / lam.min()
+    sy, sz, dy, dz = fourier_parameters(kappa, eps)
+    st = B.State(n_s + sy + sz, dtype)
+    try:
+        t = time.perf_counter()
+        z, res = B.sv_qlsa2_fourier(st.h, A, b, sy, sz, dy, dz)
+        el = time.perf_counter() - t
+    finally:
+        st.close()
+    return z / np.linalg.norm(z), res, (sy, sz, dy, dz), el
+
+
+def A_kappa(A):
+    lam = np.abs(np.linalg.eigvalsh(np.asarray(A)))
+    return float(lam.max() / lam.min())
+
+
 def fidelity(x, ref):
     return float(abs(np.vdot(x / np.linalg.norm(x), ref / np.linalg.norm(ref))))
 
@@ -108,6 +132,13 @@ def compare(N: int = 16, eps_list=(1e-1, 1e-2, 1e-3, 1e-4), n_cs=(6, 8, 10, 12),
                          "qubits": n_s + 1 + s, "p_post": res.p_post, "one_minus_F": 1 - fidelity(xq, x),
                          "seconds": el})
             print(f"[qlsa] QLSA-2 mode {mode} eps {eps:.0e}: B {Bdeg}, s {s}, {n_s + 1 + s} qubits, "
+                  f"1-F {rows[-1]['one_minus_F']:.2e}, p {res.p_post:.2e}, {el * 1e3:.2f} ms", flush=True)
+        if N.bit_length() - 1 + sum(fourier_parameters(A_kappa(A), eps)[:2]) <= 30:
+            solve_fourier(A, b, eps, dtype)                          # first use
+            xq, res, (sy, sz, dy, dz), el = solve_fourier(A, b, eps, dtype)
+            rows.append({"solver": "QLSA-2 Fourier", "eps": eps, "sy": sy, "sz": sz, "qubits": n_s + sy + sz,
+                         "p_post": res.p_post, "one_minus_F": 1 - fidelity(xq, x), "seconds": el})
+            print(f"[qlsa] QLSA-2 Fourier eps {eps:.0e}: sy {sy}, sz {sz}, {n_s + sy + sz} qubits, "
                   f"1-F {rows[-1]['one_minus_F']:.2e}, p {res.p_post:.2e}, {el * 1e3:.2f} ms", flush=True)
     return rows
 
