@@ -36,6 +36,37 @@ def _herm(rng, N, kind):
     return H + H.conj().T
 
 
+def _terms(sy, sz, dy, dz):
+    """The select values written out one by one: r = j + 2^sy m, y = j dy, z = k dz
+    with k = 1 .. 2^(sz-1) for m < 2^(sz-1) and k = -2^(sz-1) .. -1 above."""
+    J, K = 1 << sy, 1 << (sz - 1)
+    w, t, sg = [], [], []
+    for r in range(J * 2 * K):
+        j, m = r % J, r // J
+        k = m + 1 if m < K else m - 2 * K
+        z = k * dz
+        w.append(dy * dz * abs(z) * math.exp(-z * z / 2) / math.sqrt(2 * math.pi))
+        t.append(j * dy * z)
+        sg.append(1.0 if k > 0 else -1.0)
+    return np.array(w), np.array(t), np.array(sg)
+
+
+@pytest.mark.parametrize("sy,sz,dy,dz", [(1, 1, 0.7, 0.9), (3, 4, 0.3, 0.2), (5, 2, 0.1, 1.3)])
+def test_fourier_terms_written_out(sy, sz, dy, dz):
+    got = qlsa2.fourier_terms(sy, sz, dy, dz)
+    for g, want in zip(got, _terms(sy, sz, dy, dz)):
+        np.testing.assert_allclose(g, want, rtol=1e-15, atol=0)
+
+
+def test_weights_integrate_to_the_gaussian_moment():
+    """sum over z of dz |z| e^{-z^2/2} / sqrt(2 pi) -> sqrt(2 / pi), the same for every y:
+    |w|_1 = 2^sy dy sqrt(2 / pi) up to the midpoint-free Riemann error O(dz^2)."""
+    sy, sz, dy, dz = 3, 12, 0.5, 0.004
+    w, _, _ = qlsa2.fourier_terms(sy, sz, dy, dz)
+    want = (1 << sy) * dy * math.sqrt(2 / math.pi)
+    assert abs(w.sum() - want) <= 1e-5 * want
+
+
 @pytest.mark.parametrize("kind", ["spd", "indefinite", "complex"])
 @pytest.mark.parametrize("sy,sz,dy,dz", [(1, 1, 0.7, 0.9), (2, 2, 0.4, 0.6), (3, 3, 0.3, 0.5)])
 def test_circuit_matches_matrix_exponentials(kind, sy, sz, dy, dz):
@@ -45,7 +76,7 @@ def test_circuit_matches_matrix_exponentials(kind, sy, sz, dy, dz):
     b = rng.standard_normal(N) + (1j * rng.standard_normal(N) if kind == "complex" else 0)
     psi, z, p = oracle.qlsa2_fourier(A, b, sy, sz, dy, dz)
     At = A / np.abs(np.linalg.eigvalsh(A)).max()
-    w, t, sg = qlsa2.fourier_terms(sy, sz, dy, dz)
+    w, t, sg = _terms(sy, sz, dy, dz)
     bh = b / np.linalg.norm(b)
     want = sum(w[r] * 1j * sg[r] * (expm(-1j * At * t[r]) @ bh) for r in range(w.size)) / w.sum()
     np.testing.assert_allclose(z, want, rtol=0, atol=1e-12)
