@@ -93,12 +93,17 @@ __device__ __forceinline__ cvec<R> cconjmul(cvec<R> a, cvec<R> b) {   // a * con
     return cmake<R>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // One cascade stage on a register line v[0..2^RL): pairs differ in bit kb of
 // the register index.  tw is the stage's twiddle table (entry m = phase for
 // the register bits below the stage's qubit equal to m); tidx(k) gives that
 // m for element k.  The 1/sqrt(2) of the Hadamard is left out here and
 // applied once per group by the caller (butterflies are add/sub only).
 // has_tw = false for the lowest qubit of the register (phase 1).
+// The inverse butterfly forms v0 = a0 + a1 conj(w) with four FMAs and
+// v1 = 2 a0 - v0 with two more (six operations instead of eight).
 template <typename R, int RL, bool INV, typename TIDX>
 __device__ __forceinline__ void stage(cvec<R> (&v)[1 << RL], int kb, const cvec<R> *__restrict__ tw, bool has_tw,
                                       TIDX tidx) {
@@ -108,13 +113,65 @@ __device__ __forceinline__ void stage(cvec<R> (&v)[1 << RL], int kb, const cvec<
         const int k1 = k0 | (1 << kb);
         cvec<R> a0 = v[k0], a1 = v[k1];
         if (INV) {
-            if (has_tw) a1 = cconjmul<R>(a1, tw[tidx(k0)]);
-            v[k0] = cmake<R>(a0.x + a1.x, a0.y + a1.y);
-            v[k1] = cmake<R>(a0.x - a1.x, a0.y - a1.y);
+            if (has_tw) {
+                const cvec<R> w = tw[tidx(k0)];
+                const R rx = ffma(a1.x, w.x, ffma(a1.y, w.y, a0.x));
+                const R ry = ffma(a1.y, w.x, ffma(-a1.x, w.y, a0.y));
+                v[k0] = cmake<R>(rx, ry);
+                v[k1] = cmake<R>(ffma((R)2, a0.x, -rx), ffma((R)2, a0.y, -ry));
+            } else {
+                v[k0] = cmake<R>(a0.x + a1.x, a0.y + a1.y);
+                v[k1] = cmake<R>(a0.x - a1.x, a0.y - a1.y);
+            }
         } else {
             const cvec<R> d = cmake<R>(a0.x - a1.x, a0.y - a1.y);
             v[k0] = cmake<R>(a0.x + a1.x, a0.y + a1.y);
             v[k1] = has_tw ? cmul<R>(d, tw[tidx(k0)]) : d;
+        }
+    }
+}
+
+// Two forward stages at once (radix 4): the stage on bit kb + 1, then the
+// stage on bit kb, for every group of four elements that differ in those two
+// bits.  With m the group's twiddle index (the same for both stages: the
+// bit-kb-clear entry of the upper stage), t = tlo[m], T = thi[m], and the
+// upper stage's twiddle for bit kb set equal to i T, the four outputs are
+//   z00 = s0 + s1, z01 = (s0 - s1) t, z10 = T (d0 + i d1), z11 = T t (d0 - i d1)
+// with s0, d0 = x00 +- x10 and s1, d1 = x01 +- x11 (x_ab: bit kb + 1 = a,
+// bit kb = b); tt[m] = T t.  Three twiddle products per four elements
+// instead of four.
+template <typename R, int RL, typename TIDX>
+__device__ __forceinline__ void stage4f(cvec<R> (&v)[1 << RL], int kb, const cvec<R> *__restrict__ tlo,
+                                        const cvec<R> *__restrict__ thi, const cvec<R> *__restrict__ tt, TIDX tidx) {
+    const int b0 = 1 << kb, b1 = 2 << kb;
+#pragma unroll
+    for (int k = 0; k < (1 << RL); ++k) {
+        if (k & (b0 | b1)) continue;
+        const cvec<R> x00 = v[k], x01 = v[k | b0], x10 = v[k | b1], x11 = v[k | b0 | b1];
+        const int m = tidx(k);
+        const cvec<R> s0 = cmake<R>(x00.x + x10.x, x00.y + x10.y), d0 = cmake<R>(x00.x - x10.x, x00.y - x10.y);
+        const cvec<R> s1 = cmake<R>(x01.x + x11.x, x01.y + x11.y), d1 = cmake<R>(x01.x - x11.x, x01.y - x11.y);
+        v[k] = cmake<R>(s0.x + s1.x, s0.y + s1.y);
+        v[k | b0] = cmul<R>(cmake<R>(s0.x - s1.x, s0.y - s1.y), tlo[m]);
+        v[k | b1] = cmul<R>(cmake<R>(d0.x - d1.y, d0.y + d1.x), thi[m]);
+        v[k | b0 | b1] = cmul<R>(cmake<R>(d0.x + d1.y, d0.y - d1.x), tt[m]);
+    }
+}
+
+// The forward cascade over stages hi down to lo of a register line, in
+// radix-4 pairs from the top (a last single stage when the count is odd);
+// tables at tw_off(jb) of TW (twiddles) and TT (pair products), with stage
+// jb acting on line bit jb - lo_bit and tidx(jb, k) its twiddle index.
+template <typename R, int RL, int HI, int LO, int LOBIT, typename TIDX>
+__device__ __forceinline__ void fwd_cascade(cvec<R> (&v)[1 << RL], const cvec<R> *TW, const cvec<R> *TT, TIDX tidx) {
+#pragma unroll
+    for (int jb = HI; jb >= LO; jb -= 2) {
+        if (jb - 1 >= LO) {
+            const int lo = jb - 1;
+            stage4f<R, RL>(v, lo - LOBIT, TW + ((1 << lo) - 1), TW + ((1 << jb) - 1), TT + ((1 << lo) - 1),
+                           [&](int k) { return tidx(lo, k); });
+        } else {
+            stage<R, RL, false>(v, jb - LOBIT, TW + ((1 << jb) - 1), true, [&](int k) { return tidx(jb, k); });
         }
     }
 }
@@ -133,6 +190,20 @@ __device__ __forceinline__ void fill_twiddles(cvec<R> *TW, int g, int gbase, uin
     }
 }
 __device__ __forceinline__ int tw_off(int jb) { return (1 << jb) - 1; }
+
+// The radix-4 pair products at offset 2^jb - 1 for jb <= g - 2: entry m is
+// (stage jb + 1 twiddle m) x (stage jb twiddle m), formed as one exact turn count
+template <typename R>
+__device__ __forceinline__ void fill_pair_twiddles(cvec<R> *TT, int g, int gbase, uint64_t vlow) {
+    for (int i = threadIdx.x; i < (1 << (g - 1)) - 1; i += blockDim.x) {
+        int jb = 0;
+        while ((2 << jb) - 1 <= i) ++jb;
+        const uint64_t m = (uint64_t)(i - ((1 << jb) - 1));
+        const int j = gbase + jb;
+        const uint64_t X = vlow + (m << gbase);
+        TT[i] = turn_phase<R>((X << (63 - j)) + (X << (62 - j)));
+    }
+}
 
 // tile decomposition: column block and the setting of the other group's bits
 __device__ __forceinline__ void tile_coords(const PipeArgs &A, uint64_t &j0, uint64_t &o) {
@@ -243,7 +314,8 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
     cvec<R> *TW = tile + ((size_t)C << G);
-    R *s2t = reinterpret_cast<R *>(TW + (1 << G));                  // [2^G] s_y^2 2^-G
+    cvec<R> *TT = TW + (1 << G);                                     // radix-4 pair products
+    R *s2t = reinterpret_cast<R *>(TT + (1 << G));                  // [2^G] s_y^2 2^-G
     R *srt = s2t + (1 << G);                                         // [2^G] s_y 2^-G
     cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
     __shared__ double red[2][NT / 64];
@@ -259,6 +331,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         om[b * C + c] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + c);
     }
     fill_twiddles<R>(TW, G, g1, o);
+    fill_pair_twiddles<R>(TT, G, g1, o);
     // rotation of clock value y = o + l 2^g1 (natural order after the inverse
     // transform): sin = 1/y (y >= 1).  The two groups of G Hadamards around it
     // omit their 1/sqrt(2) each, so 2^-G is folded into the rotation (and into
@@ -274,9 +347,12 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     __syncthreads();
     // the phase-A stages use the first 2^RA - 1 twiddles with indices fixed by
     // the register position: keep them in registers for the whole tile
-    cvec<R> twr[(1 << RA) - 1];
+    cvec<R> twr[(1 << RA) - 1], ttr[(1 << RA) - 1];
 #pragma unroll
-    for (int i = 0; i < (1 << RA) - 1; ++i) twr[i] = TW[i];
+    for (int i = 0; i < (1 << RA) - 1; ++i) {
+        twr[i] = TW[i];
+        ttr[i] = TT[i];
+    }
     const int nla = C << RB, nlb = C << RA;
     // phase A (inverse cascade, low bits of G2): the amplitudes at y1 = o and
     // y2 = (lhi << RA) | k are T_j(o) times the phases of the set bits of y2
@@ -333,10 +409,8 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         }
         pa += (double)lpa;
         nt += (double)lnt * fold;
-#pragma unroll
-        for (int jb = G - 1; jb >= RA; --jb)
-            stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
-                                [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
+                                          [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
     }
@@ -348,9 +422,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-#pragma unroll
-        for (int jb = RA - 1; jb >= 0; --jb)
-            stage<R, RA, false>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+        fwd_cascade<R, RA, RA - 1, 0, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
         // clock index o + (((lhi << RA) + k) << g1): a base for the line and a stride for k
         cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
         const uint64_t ks = 1ull << (g1 + A.n_s);
@@ -390,7 +462,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     const int C = 1 << A.cl;
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
     cvec<R> *TW = tile + ((size_t)C << G);
-    cvec<R> *om = TW + (1 << G);
+    cvec<R> *TT = TW + (1 << G);                                     // radix-4 pair products
+    cvec<R> *om = TT + (1 << G);
     cvec<R> *cc = om + G * C;
     const size_t zoff = (((size_t)((unsigned char *)(cc + C) - smem_raw)) + 15) & ~(size_t)15;
     double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [NT] per-thread partials
@@ -410,6 +483,7 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
     }
     fill_twiddles<R>(TW, G, 0, 0);
+    fill_pair_twiddles<R>(TT, G, 0, 0);
     // per-column phase tables from the clock-bit phases k_pipe_a staged in
     // rows 2^G + r of the ancilla = 0 half: om[b][c] (b < G) the conjugate
     // phase of G1 bit b, cc[c] (b = G) the conjugate of the product of the
@@ -429,9 +503,12 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         }
     }
     __syncthreads();
-    cvec<R> twr[(1 << RA) - 1];          // phase-A twiddles (fixed by register position)
+    cvec<R> twr[(1 << RA) - 1], ttr[(1 << RA) - 1];   // phase-A twiddles (fixed by register position)
 #pragma unroll
-    for (int i = 0; i < (1 << RA) - 1; ++i) twr[i] = TW[i];
+    for (int i = 0; i < (1 << RA) - 1; ++i) {
+        twr[i] = TW[i];
+        ttr[i] = TT[i];
+    }
     // phase B first: the forward cascade starts at the top bit of G1
     for (int line = threadIdx.x; line < nlb; line += NT) {
         const int c = line & (C - 1), llo = line >> A.cl;
@@ -444,10 +521,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) v[k] = gld<R>(p, k * ks);
         }
-#pragma unroll
-        for (int jb = G - 1; jb >= RA; --jb)
-            stage<R, RB, false>(v, jb - RA, TW + tw_off(jb), true,
-                                [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
+                                          [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
         cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
@@ -461,9 +536,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
         for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-#pragma unroll
-        for (int jb = RA - 1; jb >= 1; --jb)
-            stage<R, RA, false>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+        if (RA > 1)
+            fwd_cascade<R, RA, RA - 1, 1, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
         // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
         cvec<R> ph[1 << (RA - 1)];
         cvec<R> base = cc[c];
@@ -588,6 +662,7 @@ static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
     const size_t C = (size_t)1 << cl;
     size_t b = ((C << g) + ((size_t)1 << g)) * e;
     if (which != 1) b += (size_t)(g + 1) * C * e;
+    if (which != 0) b += ((size_t)1 << g) * e;                          // radix-4 pair products
     if (which == 1) b += ((size_t)1 << g) * e + (size_t)g * C * e;
     if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
     return b;
