@@ -51,6 +51,9 @@ def _load():
     lib.orc_eigh.argtypes = [ctypes.c_int, _c128p, _f64p, _c128p]
     lib.orc_hhl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _c128p, _c128p, _c128p, _c128p,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    lib.orc_gapped_pe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _c128p, _c128p, _c128p, _c128p,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                  ctypes.c_uint64]
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -165,6 +168,25 @@ def hhl(A, b, n_c, T0, signed_clock=False):
     pp, pa = ctypes.c_double(0), ctypes.c_double(0)
     _check(_load().orc_hhl(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa),
                            int(bool(signed_clock))), "hhl")
+    return psi, x, pp.value, pa.value
+
+
+def gapped_pe(A, b, n_c, T0, cut, signed_clock=False):
+    """Gapped phase estimation (see oracle.c): the HHL circuit with the flag
+    Ry(pi) on clock values |y| >= cut in place of the inversion rotation.
+    Returns (psi, x, p_post, p_anc): x the normalised flag = 1, clock = 0
+    system vector, p_post = P(flag = 1, clock = 0), p_anc = P(flag = 1)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    if N != 1 << n_s or b.shape != (N,):
+        raise ValueError("A must be 2^n_s square and b of length 2^n_s")
+    psi = np.zeros(1 << (n_s + n_c + 1), dtype=np.complex128)
+    x = np.zeros(N, dtype=np.complex128)
+    pp, pa = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_load().orc_gapped_pe(n_s, int(n_c), float(T0), A, b, psi, x, ctypes.byref(pp), ctypes.byref(pa),
+                                 int(bool(signed_clock)), ctypes.c_uint64(int(cut))), "gapped_pe")
     return psi, x, pp.value, pa.value
 
 

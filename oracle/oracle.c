@@ -360,8 +360,40 @@ static void build_uk(int N, const cplx *V, const double *phi, int k, cplx *Uk)
  * post-selected system vector x (2^n_s), p_post = P(a=1, y=0) and
  * p_anc = P(a=1).
  */
+static int hhl_circuit(int n_s, int n_c, double T0, const cplx *A, const cplx *b, cplx *psi, cplx *x_out,
+                       double *p_post, double *p_anc, int signed_clock, uint64_t cut);
+
 int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
             cplx *psi, cplx *x_out, double *p_post, double *p_anc, int signed_clock)
+{
+    return hhl_circuit(n_s, n_c, T0, A, b, psi, x_out, p_post, p_anc, signed_clock, 0);
+}
+
+/*
+ * Gapped phase estimation (GPE; the building block of the variable-time
+ * solver in the cited Childs-Kothari-Somma construction, which QLSA-2 names):
+ * the circuit of orc_hhl with step 6 replaced by a flag.  After the inverse
+ * QFT, every clock value y with |y| >= cut (y read as a two's-complement value
+ * with signed_clock) rotates the flag qubit (the ancilla position) by
+ * Ry(pi), |0> -> |1>; the others leave it alone.  The phase estimation is
+ * then uncomputed (step 7).  An eigenvector whose estimate lies well above
+ * the cut ends with flag 1 and the clock back at 0, one well below it with
+ * flag 0; near the cut the two branches mix and part of the amplitude stays
+ * on clock values != 0.  Outputs as orc_hhl: x is the normalised flag = 1,
+ * clock = 0 system vector, p_post = P(flag = 1, clock = 0), p_anc = P(flag = 1).
+ * cut >= 1.
+ */
+int orc_gapped_pe(int n_s, int n_c, double T0, const cplx *A, const cplx *b, cplx *psi, cplx *x_out,
+                  double *p_post, double *p_anc, int signed_clock, uint64_t cut)
+{
+    if (cut < 1) return ORC_EINVAL;
+    return hhl_circuit(n_s, n_c, T0, A, b, psi, x_out, p_post, p_anc, signed_clock, cut);
+}
+
+/* the HHL circuit; cut = 0 takes the inversion rotation of step 6, cut >= 1
+ * the gapped-phase-estimation flag */
+static int hhl_circuit(int n_s, int n_c, double T0, const cplx *A, const cplx *b, cplx *psi, cplx *x_out,
+                       double *p_post, double *p_anc, int signed_clock, uint64_t cut)
 {
     if (n_s < 1 || n_c < 1 || n_s + n_c + 1 > 30 || !(T0 > 0.0)) return ORC_EINVAL;
     const int N = 1 << n_s, n = n_s + n_c + 1;
@@ -409,7 +441,16 @@ int orc_hhl(int n_s, int n_c, double T0, const cplx *A, const cplx *b,
     const uint64_t Y = (uint64_t)1 << n_c;
     for (uint64_t y = 1; y < Y; ++y) {
         const double ys = (signed_clock && y >= Y / 2) ? (double)y - (double)Y : (double)y;
-        double s = 1.0 / ys, c = sqrt(1.0 - s * s);
+        double s, c;
+        if (cut == 0) {
+            s = 1.0 / ys;
+            c = sqrt(1.0 - s * s);
+        } else if (fabs(ys) >= (double)cut) {    /* flag: Ry(pi) */
+            s = 1.0;
+            c = 0.0;
+        } else {
+            continue;
+        }
         for (uint64_t x = 0; x < (uint64_t)N; ++x) {
             uint64_t i0 = x | (y << n_s), i1 = i0 | ((uint64_t)1 << anc);
             cplx a0 = psi[i0], a1 = psi[i1];

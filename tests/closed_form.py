@@ -58,3 +58,27 @@ def hhl_closed_form_kron(A_hi, A_lo, b, n_c, T0):
     p = float(np.sum(np.abs(Z) ** 2))
     X = P @ Z @ Q.T
     return X.reshape(-1) / math.sqrt(p), p
+
+
+def gpe_weights(phi, n_c, cut, signed=False):
+    """Gapped phase estimation: (g, h) per eigenphase, g = sum over the clock
+    values with |y| >= cut of K(phi - y/M) (the flag = 1, clock = 0 amplitude
+    after the uncompute: each flagged y returns to clock 0 with amplitude
+    |alpha_y|^2), h the same sum over the other values (flag = 0)."""
+    M = 1 << n_c
+    y = np.arange(M, dtype=np.float64)
+    ys = np.where(y >= M // 2, y - M, y) if signed else y
+    flag = np.abs(ys) >= cut
+    d = np.asarray(phi, dtype=np.float64)[:, None] - y[None, :] / M
+    K = fejer(d, M)
+    return (K * flag[None, :]).sum(axis=1), (K * ~flag[None, :]).sum(axis=1)
+
+
+def gpe_closed_form(A, b, n_c, T0, cut, signed=False):
+    """(z1, z0, p_post, p_flag): the flag = 1 and flag = 0 system vectors at
+    clock 0 (unnormalised amplitudes), P(flag = 1, clock = 0) and P(flag = 1)."""
+    lam, V = np.linalg.eigh(A)
+    beta = V.conj().T @ (b / np.linalg.norm(b))
+    g, h = gpe_weights(lam * T0 / (2 * math.pi), n_c, cut, signed)
+    z1, z0 = V @ (beta * g), V @ (beta * h)
+    return z1, z0, float(np.sum(np.abs(beta * g) ** 2)), float(np.sum(np.abs(beta) ** 2 * g))
