@@ -241,6 +241,37 @@ typedef struct {
 sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_params *prm,
                  sv_hhl_result *res, double *x_out);
 
+typedef struct {
+    int n_s, n_c;      /* system and clock qubits */
+    double T0;         /* as sv_hhl_params */
+    int mode;          /* 0, 1, 2 as sv_hhl_params */
+    int signed_clock;  /* as sv_hhl_params (a zero eigenvalue is allowed here) */
+    uint64_t cut;      /* flag clock values with |y| >= cut: 1 <= cut < 2^n_c,
+                          or < 2^(n_c-1) with a signed clock */
+} sv_gpe_params;
+
+/* Gapped phase estimation: the building block of the variable-time
+ * linear-systems solver in the Childs-Kothari-Somma construction that the
+ * paper names for QLSA-2.  It decides, coherently and per eigenvector of A,
+ * whether |lambda| T0 2^n_c / 2 pi lies above or below the cut, with a gap of
+ * a few clock units in which both answers mix.  The circuit is that of
+ * sv_hhl with the inversion rotation replaced by a flag on the ancilla
+ * position: Ry(pi), |0> -> |1>, for clock values |y| >= cut, nothing
+ * elsewhere; then the phase estimation is uncomputed.  An eigenvector whose
+ * estimate lies well above the cut ends with flag 1 and clock 0, one well
+ * below it with flag 0 and clock 0.  The state must hold n_s + n_c + 1 qubits
+ * (flag bit n_s + n_c).
+ * Results as sv_hhl: p_post = P(flag = 1, clock = 0), p_anc = P(flag = 1),
+ * x_out the normalised flag = 1, clock = 0 system vector; after mode 0 the
+ * state holds the final circuit state (the flag = 0, clock = 0 block is the
+ * other branch).  A: host, 2^n_s x 2^n_s complex FP64 row-major, Hermitian,
+ * n_s <= 13; b: host, 2^n_s complex FP64.
+ * Errors: SV_EINVAL (sizes, T0, cut out of range), SV_ENOTHERMITIAN,
+ * SV_ENOTPOSDEF (a negative eigenvalue on an unsigned clock), SV_EZERONORM
+ * (|b| = 0, or no amplitude with flag 1 at clock 0), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_gapped_pe(sv_state s, const double *A, const double *b, const sv_gpe_params *prm,
+                       sv_hhl_result *res, double *x_out);
+
 /* Classical preprocessing and the quantum solve, split so the FP64
  * eigen-decomposition is computed once per operator and reused for every
  * right-hand side and every T0 (the hybrid loop of the paper's Fig. 1b: the

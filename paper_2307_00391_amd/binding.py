@@ -56,6 +56,11 @@ class sv_qlsa2_result(ctypes.Structure):
                 ("lambda_abs_min", ctypes.c_double), ("alpha_l1", ctypes.c_double)]
 
 
+class sv_gpe_params(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int), ("n_c", ctypes.c_int), ("T0", ctypes.c_double), ("mode", ctypes.c_int),
+                ("signed_clock", ctypes.c_int), ("cut", ctypes.c_uint64)]
+
+
 class sv_qlsa2f_params(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int), ("sy", ctypes.c_int), ("sz", ctypes.c_int), ("dy", ctypes.c_double),
                 ("dz", ctypes.c_double)]
@@ -108,6 +113,7 @@ _SIGS = {
     "sv_lcu_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_qlsa2": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_qlsa2_fourier": ([_P, _P, _P, _P, _P, _P], _I),
+    "sv_gapped_pe": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
@@ -342,6 +348,21 @@ def sv_qlsa2(h, A, b, s, B, mode=1):
     z = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_qlsa2(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(z)), "sv_qlsa2")
     return z, res
+
+
+def sv_gapped_pe(h, A, b, n_c, T0, cut, mode=1, signed_clock=0):
+    """Gapped phase estimation: returns (x, result), x the normalised flag = 1,
+    clock = 0 system vector (result fields as sv_hhl)."""
+    A, Af = _f64(A)
+    b, bf = _f64(b)
+    N = A.shape[0]
+    n_s = N.bit_length() - 1
+    prm = sv_gpe_params(n_s, int(n_c), float(T0), int(mode), int(signed_clock), int(cut))
+    res = sv_hhl_result()
+    x = np.zeros(N, dtype=np.complex128)
+    _check(lib().sv_gapped_pe(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)),
+           "sv_gapped_pe")
+    return x, res
 
 
 def sv_qlsa2_fourier(h, A, b, sy, sz, dy, dz):

@@ -52,6 +52,7 @@ struct PipeArgs {
     uint64_t abit;       // ancilla bit
     double scale;        // 2^(-n_c/2)
     int sgn;             // signed (two's-complement) clock for the inversion
+    uint64_t gcut;       // 0: inversion sin = 1/y; >= 1: gapped-phase-estimation flag, sin = [|y| >= gcut]
 };
 
 // HBM pointers of a solve, in the global address space: the pointers come
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     for (int l = threadIdx.x; l < (1 << G); l += NT) {
         const uint64_t y = o | ((uint64_t)l << g1);
         const double ys = (A.sgn && (y >> (n_c - 1))) ? (double)y - exp2((double)n_c) : (double)y;
-        const double sd = y ? 1.0 / ys : 0.0;
+        const double sd = !y ? 0.0 : A.gcut ? (fabs(ys) >= (double)A.gcut ? 1.0 : 0.0) : 1.0 / ys;
         s2t[l] = (R)(sd * sd * fold);
         srt[l] = (R)(sd * fold);
     }
@@ -685,6 +686,7 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
     A.abit = 1ull << (n_s + n_c);
     A.scale = 1.0 / sqrt((double)(1ull << n_c));
     A.sgn = 0;
+    A.gcut = 0;
     for (int w = 0; w < 3; ++w) {
         const int g = w == 1 ? A.g2 : A.g1;
         P.A[w] = A;
@@ -776,23 +778,26 @@ sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on
 }
 
 template <typename R>
-sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, const double2 *beta, const uint64_t *F, double *part,
-                   double2 *zpart, uint64_t *nparts) {
+sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const double2 *beta, const uint64_t *F,
+                   double *part, double2 *zpart, uint64_t *nparts) {
     const size_t e = sizeof(cvec<R>);
     PipeSolve one{s->data, beta, F, part, zpart};
     int cl[3], nt[3];
     SV_TRY(pipe_config<R>(s->stream, n_s, n_c, &one, cl, nt));
     PipePlan P;
     make_plan(P, n_s, n_c, e, cl, nt, 1);
-    for (int w = 0; w < 3; ++w) P.A[w].sgn = sgn ? 1 : 0;
+    for (int w = 0; w < 3; ++w) {
+        P.A[w].sgn = sgn ? 1 : 0;
+        P.A[w].gcut = gcut;
+    }
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
     for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s->stream, P, w, one, nullptr));
     return SV_OK;
 }
-template sv_status pipe_run<float>(sv_state, int, int, bool, const double2 *, const uint64_t *, double *,
+template sv_status pipe_run<float>(sv_state, int, int, bool, uint64_t, const double2 *, const uint64_t *, double *,
                                    double2 *, uint64_t *);
-template sv_status pipe_run<double>(sv_state, int, int, bool, const double2 *, const uint64_t *, double *,
-                                    double2 *, uint64_t *);
+template sv_status pipe_run<double>(sv_state, int, int, bool, uint64_t, const double2 *, const uint64_t *,
+                                    double *, double2 *, uint64_t *);
 
 // a class of solves sharing (n_s, n_c): the three kernels once each, blockIdx.z = solve
 template <typename R>

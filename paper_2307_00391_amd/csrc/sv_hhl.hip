@@ -45,7 +45,8 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
 template <typename R>
 sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
 template <typename R>
-sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, const double2 *beta, const uint64_t *F, double *part,
+sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const double2 *beta, const uint64_t *F,
+                   double *part,
                    double2 *zpart, uint64_t *nparts);
 
 // --------------------------------------------------------------------------
@@ -511,14 +512,16 @@ void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<
 }
 
 // (cos, sin) of the inversion rotation for every clock value: sin = 1/y,
-// y >= 1; a signed clock reads y >= 2^(n_c-1) as y - 2^n_c (two's complement)
-void inversion_table(int n_c, std::vector<double> &cs, bool sgn) {
+// y >= 1; a signed clock reads y >= 2^(n_c-1) as y - 2^n_c (two's complement).
+// gcut >= 1 gives the gapped-phase-estimation flag instead: sin = 1 (Ry(pi))
+// where |y| >= gcut, sin = 0 elsewhere.
+void inversion_table(int n_c, std::vector<double> &cs, bool sgn, uint64_t gcut) {
     const size_t M = (size_t)1 << n_c;
     cs.assign(2 * M, 0.0);
     cs[0] = 1.0;
     for (size_t y = 1; y < M; ++y) {
         const double ys = (sgn && y >= M / 2) ? (double)y - (double)M : (double)y;
-        const double sv = 1.0 / ys;
+        const double sv = gcut ? (fabs(ys) >= (double)gcut ? 1.0 : 0.0) : 1.0 / ys;
         cs[2 * y] = sqrt(1.0 - sv * sv);
         cs[2 * y + 1] = sv;
     }
@@ -597,7 +600,7 @@ static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_
 
 template <typename R>
 static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c, bool sgn,
-                               double T0, bool fused, sv_hhl_result *res, double *x_out) {
+                               uint64_t gcut, double T0, bool fused, sv_hhl_result *res, double *x_out) {
     const int n_s = E.n_s;
     const uint64_t N = dim_of(n_s);
     const int anc = n_s + n_c;
@@ -635,7 +638,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         SV_TRY(need(w.part, 2 * nbp * sizeof(double)));
         SV_TRY(need(w.zpart, (size_t)rows * N * sizeof(double2)));
         uint64_t nparts = 0;
-        SV_TRY(pipe_run<R>(s, n_s, n_c, sgn, (const double2 *)w.beta.p, (const uint64_t *)w.F.p, (double *)w.part.p,
+        SV_TRY(pipe_run<R>(s, n_s, n_c, sgn, gcut, (const double2 *)w.beta.p, (const uint64_t *)w.F.p, (double *)w.part.p,
                            (double2 *)w.zpart.p, &nparts));
         if (nparts > nbp) return fail(SV_EDEVICE, "pipeline partial count exceeds its buffer");
         SV_TRY(need(w.tmp2, 512 * sizeof(double)));
@@ -650,7 +653,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         return eig_finish(s, E, w, N, res, x_out);
     }
     std::vector<double> cs;
-    inversion_table(n_c, cs, sgn);
+    inversion_table(n_c, cs, sgn, gcut);
     SV_TRY(need(w.cs, cs.size() * sizeof(double)));
     SV_TRY(upload(s, w.cs.p, cs.data(), cs.size() * sizeof(double)));
     // 1. the state after phase estimation, written directly (ancilla = 0 half)
@@ -721,7 +724,8 @@ __global__ void k_kron_matrix(double2 *__restrict__ V, const double2 *__restrict
 
 template <typename R>
 static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vector<double> &lam, Workspace &w, bool sgn,
-                                   int n_s, int n_c, double T0, const double *b, sv_hhl_result *res, double *x_out) {
+                                   uint64_t gcut, int n_s, int n_c, double T0, const double *b, sv_hhl_result *res,
+                                   double *x_out) {
     const int N = 1 << n_s;
     const hipStream_t st = s->stream;
     // U_k = V diag(E_k) V^H for k = 0..n_c-1, FP64, then rounded to the state's precision
@@ -756,7 +760,7 @@ static sv_status gate_faithful_run(sv_state s, const double2 *dV, const std::vec
     for (int k = 0; k < n_c; ++k) SV_TRY(ctrl_unitary_impl<R>(s, U + (size_t)k * NN, n_s, n_s + (n_c - 1 - k), 1, 0));
     SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 1, 0, 0}, 0));
     std::vector<double> cs;
-    inversion_table(n_c, cs, sgn);
+    inversion_table(n_c, cs, sgn, gcut);
     SV_TRY(sv_apply_uniform_ry(s, n_s + n_c, n_s, n_c, cs.data(), -1, 0));
     SV_TRY(run_qft_cascade(s, QftSpec{n_s, n_c, 0, 0, 0}, 0));
     for (int k = n_c - 1; k >= 0; --k)
@@ -863,9 +867,11 @@ sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda
     return SV_OK;
 }
 
-sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
-                     double *x_out) {
-    clear_error();
+// the solve on a prepared operator: gcut = 0 the HHL inversion, gcut >= 1 the
+// gapped-phase-estimation flag (which allows a zero eigenvalue on a signed
+// clock and lambda_min = 0 on an unsigned one)
+static sv_status hhl_run_impl(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm, uint64_t gcut,
+                              sv_hhl_result *res, double *x_out) {
     if (!p) return fail(SV_EINVAL, "null plan");
     SV_TRY(check_state(s));
     SV_TRY(check_params(s, prm, res));
@@ -876,15 +882,20 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
     SV_TRY(normalise_b(b, N, bhat));
     SV_TRY(sv_hhl_plan_spectrum(p, &res->lambda_min, &res->lambda_max));
     const bool sgn = prm->signed_clock == 1;
-    if (!sgn && !(res->lambda_min > 0.0))
-        return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
-    if (sgn)
-        for (double v : p->E.lam)
-            if (!(v != 0.0)) return fail(SV_EINVAL, "A is singular (a zero eigenvalue)");
+    if (gcut == 0) {
+        if (!sgn && !(res->lambda_min > 0.0))
+            return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
+        if (sgn)
+            for (double v : p->E.lam)
+                if (!(v != 0.0)) return fail(SV_EINVAL, "A is singular (a zero eigenvalue)");
+    } else if (!sgn && !(res->lambda_min >= 0.0)) {
+        return fail(SV_ENOTPOSDEF, "lambda_min = %g < 0 (unsigned clock)", res->lambda_min);
+    }
     if (prm->mode >= 1) {
         const bool fused = prm->mode == 1;
-        return s->dt == SV_C64 ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, sgn, prm->T0, fused, res, x_out)
-                               : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, sgn, prm->T0, fused, res, x_out);
+        return s->dt == SV_C64
+                   ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out)
+                   : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out);
     }
     // gate-faithful: dense eigenvectors
     if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
@@ -899,9 +910,16 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
         dV = (const double2 *)p->V_dense.p;
     }
     if (s->dt == SV_C64)
-        return gate_faithful_run<float>(s, dV, p->E.lam, p->w, sgn, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res,
-                                        x_out);
-    return gate_faithful_run<double>(s, dV, p->E.lam, p->w, sgn, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res, x_out);
+        return gate_faithful_run<float>(s, dV, p->E.lam, p->w, sgn, gcut, p->E.n_s, prm->n_c, prm->T0, bhat.data(),
+                                        res, x_out);
+    return gate_faithful_run<double>(s, dV, p->E.lam, p->w, sgn, gcut, p->E.n_s, prm->n_c, prm->T0, bhat.data(), res,
+                                     x_out);
+}
+
+sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm, sv_hhl_result *res,
+                     double *x_out) {
+    clear_error();
+    return hhl_run_impl(p, s, b, prm, 0, res, x_out);
 }
 
 sv_status sv_hhl_plan_free(sv_hhl_plan p) {
@@ -924,6 +942,29 @@ sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_para
     sv_hhl_plan p = nullptr;
     SV_TRY(sv_hhl_prepare(&p, s, A, prm->n_s, nullptr, 0));
     sv_status st = sv_hhl_run(p, s, b, prm, res, x_out);
+    std::string keep = sv_last_error();
+    sv_hhl_plan_free(p);
+    if (st != SV_OK) fail(st, "%s", keep.c_str());
+    return st;
+}
+
+sv_status sv_gapped_pe(sv_state s, const double *A, const double *b, const sv_gpe_params *g, sv_hhl_result *res,
+                       double *x_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!g) return fail(SV_EINVAL, "params is NULL");
+    const sv_hhl_params prm{g->n_s, g->n_c, g->T0, g->mode, g->signed_clock};
+    SV_TRY(check_params(s, &prm, res));
+    if (!A || !b) return fail(SV_EINVAL, "A/b is NULL");
+    if (prm.n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d", prm.n_s);
+    const uint64_t top = prm.signed_clock ? (1ull << (prm.n_c - 1)) : (1ull << prm.n_c);
+    if (g->cut < 1 || g->cut >= top)
+        return fail(SV_EINVAL, "cut %llu outside [1, %llu)", (unsigned long long)g->cut, (unsigned long long)top);
+    std::vector<double> bhat;
+    SV_TRY(normalise_b(b, dim_of(prm.n_s), bhat));
+    sv_hhl_plan p = nullptr;
+    SV_TRY(sv_hhl_prepare(&p, s, A, prm.n_s, nullptr, 0));
+    sv_status st = hhl_run_impl(p, s, b, &prm, g->cut, res, x_out);
     std::string keep = sv_last_error();
     sv_hhl_plan_free(p);
     if (st != SV_OK) fail(st, "%s", keep.c_str());

@@ -64,7 +64,7 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
 sv_status eigh_device_batched(sv_state s, const std::vector<const double *> &As, int N, std::vector<DevBuf *> &dVs,
                               std::vector<std::vector<double>> &lams);
 void turn_table(const std::vector<double> &lam, double T0, int n_c, std::vector<uint64_t> &F);
-void inversion_table(int n_c, std::vector<double> &cs, bool sgn = false);
+void inversion_table(int n_c, std::vector<double> &cs, bool sgn = false, uint64_t gcut = 0);
 sv_status kron_apply(hipStream_t st, double2 *out, const double2 *in, double2 *tmp, const double2 *V_hi, int n_hi,
                      const double2 *V_lo, int n_lo, int adjoint);
 const char *eigh_last_solver();

@@ -1,0 +1,156 @@
+"""GPU parity of gapped phase estimation (the HHL circuit with the flag
+Ry(pi) on clock values |y| >= cut, then the uncompute) against the oracle:
+the three library modes, complex128 to 1e-12 and complex64 to 1e-5
+(max-abs on the normalised flag = 1 vector and, in mode 0, on the whole final
+state; probabilities to the same bars); unsigned and signed clocks; the exact
+projection on a clock grid; at n_s = 10, n_c = 12 (mode 1) against the Fejer
+closed form that pins the oracle; the parameter rule's promise on an
+indefinite system; error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00391_amd import binding as B
+from paper_2307_00391_amd import gpe, inputs
+from tests.closed_form import gpe_closed_form, gpe_weights
+
+pytestmark = pytest.mark.gpu
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+def _system(kind, rng, n_s, n_c):
+    N = 1 << n_s
+    if kind == "spd":
+        A, _, lmax = inputs.random_spd_tridiag(rng, N, 30.0)
+        return A, inputs.t0_top_of_clock(lmax, n_c) * 0.9, False
+    if kind == "indefinite":
+        Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+        A = Q @ np.diag(np.linspace(-2.0, 3.0, N) + 0.13) @ Q.T
+    else:
+        Z = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+        A = Z + Z.conj().T
+    return A, 0.45 * 2 * math.pi / np.abs(np.linalg.eigvalsh(A)).max(), True
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("kind,n_s,n_c,cut", [("spd", 1, 4, 5), ("spd", 3, 6, 20), ("indefinite", 3, 5, 4),
+                                              ("complex", 4, 7, 17), ("indefinite", 2, 9, 60)])
+def test_gpe_matches_oracle(dt, mode, kind, n_s, n_c, cut):
+    rng = np.random.default_rng(n_s * 100 + n_c * 10 + cut)
+    A, T0, signed = _system(kind, rng, n_s, n_c)
+    N = 1 << n_s
+    b = rng.standard_normal(N) + (1j * rng.standard_normal(N) if kind == "complex" else 0)
+    print(f"[gpe] {dt} mode {mode} {kind} n_s {n_s} n_c {n_c} cut {cut}", flush=True)
+    psi_ref, x_ref, p_ref, pf_ref = oracle.gapped_pe(A, b, n_c, T0, cut, signed)
+    st = B.State(n_s + n_c + 1, dt)
+    try:
+        x, res = B.sv_gapped_pe(st.h, A, b, n_c, T0, cut, mode, int(signed))
+        if mode == 0:
+            assert np.abs(st.get() - psi_ref).max() <= TOL[dt]
+    finally:
+        st.close()
+    ph = np.vdot(x_ref, x)
+    ph = ph / abs(ph) if abs(ph) > 0 else 1.0
+    assert np.abs(x - ph * x_ref).max() <= 10 * TOL[dt]
+    assert abs(res.p_post - p_ref) <= TOL[dt]
+    assert abs(res.p_anc - pf_ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gpe_exact_on_clock_grid(dt, mode):
+    rng = np.random.default_rng(77)
+    n_s, n_c, T0, cut = 3, 6, 0.6, 12
+    N, M = 1 << n_s, 1 << n_c
+    yj = np.array([2, 5, 9, 11, 12, 17, 23, 30]) * np.where(rng.random(N) < 0.5, -1, 1)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    A = Q @ np.diag(2 * math.pi * yj / (M * T0)) @ Q.T
+    A = (A + A.T) / 2
+    b = rng.standard_normal(N)
+    st = B.State(n_s + n_c + 1, dt)
+    try:
+        x, res = B.sv_gapped_pe(st.h, A, b, n_c, T0, cut, mode, 1)
+    finally:
+        st.close()
+    beta = Q.T @ (b / np.linalg.norm(b))
+    big = np.abs(yj) >= cut
+    want = Q @ (beta * big)
+    p = float(np.sum(beta[big] ** 2))
+    assert abs(res.p_post - p) <= TOL[dt] and abs(res.p_anc - p) <= TOL[dt]
+    ph = np.vdot(want, x)
+    assert np.abs(x * np.conj(ph) / abs(ph) - want / math.sqrt(p)).max() <= 10 * TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_gpe_larger_against_closed_form(dt):
+    """n_s = 10, n_c = 12 (23 qubits, fused eigen-frame path): the Fejer
+    closed form of the flag = 1, clock = 0 vector and both probabilities."""
+    rng = np.random.default_rng(8)
+    n_s, n_c, cut = 10, 12, 700
+    A, _, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, 50.0)
+    T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.93
+    b = rng.standard_normal(1 << n_s)
+    z1, _, p_post, p_flag = gpe_closed_form(A, b, n_c, T0, cut)
+    st = B.State(n_s + n_c + 1, dt)
+    try:
+        x, res = B.sv_gapped_pe(st.h, A, b, n_c, T0, cut, 1, 0)
+    finally:
+        st.close()
+    want = z1 / np.linalg.norm(z1)
+    ph = np.vdot(want, x)
+    assert np.abs(x * np.conj(ph) / abs(ph) - want).max() <= 10 * TOL[dt]
+    assert abs(res.p_post - p_post) <= 10 * TOL[dt] and abs(res.p_anc - p_flag) <= 10 * TOL[dt]
+
+
+def test_gpe_parameter_rule_on_an_indefinite_system():
+    """eps = 0.1 lambda_max, delta = 0.2: the flag = 1 vector keeps the
+    eigencomponents with |lambda| >= 2 eps (weights >= 1 - delta^2) and drops
+    those with |lambda| <= eps (weights <= delta^2)."""
+    rng = np.random.default_rng(21)
+    N = 16
+    lam = np.array([-1.0, -0.8, -0.5, -0.31, -0.2, -0.09, -0.05, -0.01, 0.02, 0.06, 0.08, 0.25, 0.4, 0.6, 0.9, 1.0])
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    A = Q @ np.diag(lam) @ Q.T
+    A = (A + A.T) / 2
+    b = rng.standard_normal(N)
+    eps, delta = 0.1, 0.2
+    x, res, (n_c, T0, cut) = gpe.run(A, b, eps, delta, "c64", 1)
+    beta = Q.T @ (b / np.linalg.norm(b))
+    comp = np.abs(Q.T @ (x * math.sqrt(res.p_post)))
+    g, _ = gpe_weights(lam * T0 / (2 * math.pi), n_c, cut, signed=True)
+    np.testing.assert_allclose(comp, np.abs(beta * g), rtol=0, atol=1e-5)
+    w = comp / np.abs(beta)
+    assert np.all(w[np.abs(lam) >= 2 * eps] >= 1 - delta ** 2)
+    assert np.all(w[np.abs(lam) <= eps] <= delta ** 2)
+
+
+def test_gpe_errors():
+    A = np.diag([1.0, 2.0, 3.0, 4.0])
+    b = np.ones(4)
+    st = B.State(2 + 5 + 1, "c64")
+    try:
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A, b, 5, 0.5, 0, 1, 0)            # cut = 0
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A, b, 5, 0.5, 16, 1, 1)           # cut >= 2^(n_c-1), signed
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A, b, 5, 0.5, 32, 0, 0)           # cut >= 2^n_c
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A, b, 4, 0.5, 3, 1, 0)            # 2 + 4 + 1 != 8
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A - 2.5 * np.eye(4), b, 5, 0.5, 3, 1, 0)   # negative eigenvalue, unsigned
+        with pytest.raises(B.SvError):
+            B.sv_gapped_pe(st.h, A, np.zeros(4), 5, 0.5, 3, 1, 0)
+    finally:
+        st.close()
