@@ -389,6 +389,28 @@ def main():
                           "select_ms": ks["ms"], "select_hbm_gbs": ks["bytes"] / (ks["ms"] * 1e-3) / 1e9,
                           "project_ms": kp["ms"], "project_hbm_gbs": kp["bytes"] / (kp["ms"] * 1e-3) / 1e9}
         out["qlsa2"] = rec
+        # gapped phase estimation on a dense 4096-point operator (fused eigen-frame path)
+        from paper_2307_00391_amd import gpe
+        gr = inputs.rng_for(7, 2)
+        Ag, _, lmax_g = inputs.random_spd_tridiag(gr, 1 << 12, 100.0)
+        bg = gr.standard_normal(1 << 12)
+        n_cg, T0g, cutg = gpe.parameters(0.05 * lmax_g, 0.1, lmax_g)
+        log(f"[bench] gpe: 4096-point operator, eps = 0.05 lambda_max, delta = 0.1: n_c {n_cg}, cut {cutg}")
+        sg = B.State(12 + n_cg + 1, "c64", device=dev)
+        B.sv_gapped_pe(sg.h, Ag, bg, n_cg, T0g, cutg, 1, 1)                 # first use: tuning
+        B.sv_trace_enable(True)
+        t = time.perf_counter()
+        _, gres = B.sv_gapped_pe(sg.h, Ag, bg, n_cg, T0g, cutg, 1, 1)
+        el = time.perf_counter() - t
+        tr = B.sv_trace_report()
+        B.sv_trace_enable(False)
+        sg.close()
+        del sg
+        kms = sum(v["ms"] for k, v in tr.items() if k.startswith("pipe_"))
+        kby = sum(v["bytes"] for k, v in tr.items() if k.startswith("pipe_"))
+        out["gpe"] = {"qubits": 12 + n_cg + 1, "n_c": n_cg, "cut": cutg, "seconds": el, "pipeline_ms": kms,
+                      "pipeline_hbm_gbs": kby / (kms * 1e-3) / 1e9, "p_flag": gres.p_anc, "p_post": gres.p_post}
+        torch.cuda.empty_cache()
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------
     if not args.no_cpu:
