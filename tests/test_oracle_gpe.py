@@ -91,6 +91,8 @@ def test_gpe_wrong_flag_within_the_fejer_tail_bound():
         if yt == int(yt):
             assert abs(p - (1.0 if yt >= cut else 0.0)) < 1e-12, yt
         elif yt < cut:
+            if cut - yt < 1:            # within half a clock unit of the cut: no bound
+                continue
             bound = 1 / (math.pi ** 2 * (cut - yt - 0.5)) + 1 / (math.pi ** 2 * (yt + 0.5))
             assert p <= 1.2 * bound, (yt, p, bound)
         else:
