@@ -53,6 +53,8 @@ struct PipeArgs {
     double scale;        // 2^(-n_c/2)
     int sgn;             // signed (two's-complement) clock for the inversion
     uint64_t gcut;       // 0: inversion sin = 1/y; >= 1: gapped-phase-estimation flag, sin = [|y| >= gcut]
+    int pers;            // k_pipe_b: persistent blocks (one G1 value each, iters column blocks)
+    int pslog, iters;    // log2 of the blocks per G1 value; column blocks per block
 };
 
 // HBM pointers of a solve, in the global address space: the pointers come
@@ -308,6 +310,8 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
+    // phases of the G2 bits per thread (G C <= 8 * 64 <= 2 NT)
+    constexpr int OMR = 2;
     const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const gptr<double> __restrict__ part = (gptr<double>)S.part;
@@ -320,13 +324,26 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     R *srt = s2t + (1 << G);                                         // [2^G] s_y 2^-G
     cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
     __shared__ double red[2][NT / 64];
+    // tiles: one per block (tile_coords), or, persistent, a fixed G1 value
+    // o = blockIdx.x >> pslog per block and the column blocks
+    // (blockIdx.x mod 2^pslog) + it 2^pslog for it < iters, so the twiddle,
+    // pair and rotation tables (functions of o) are built once per block
     uint64_t j0, o;
-    tile_coords(A, j0, o);               // o = value of the G1 bits
+    int iters = 1;
+    uint64_t jstep = 0;
+    if (A.pers) {
+        o = blockIdx.x >> A.pslog;
+        j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
+        iters = A.iters;
+        jstep = 1ull << (A.pslog + A.cl);
+    } else {
+        tile_coords(A, j0, o);           // o = value of the G1 bits
+    }
     const int g1 = A.g1, n_c = A.n_c;
     // the G1 table entry of the thread's first phase-A line and the column
     // phases of the G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read
     // before the twiddles are built so that their latency overlaps that work
-    const cvec<R> t0 = gld<R>(psi, (o << A.n_s) | (j0 + (threadIdx.x & (C - 1))));
+    cvec<R> t0 = gld<R>(psi, (o << A.n_s) | (j0 + (threadIdx.x & (C - 1))));
     for (int e = threadIdx.x; e < G * C; e += NT) {
         const int b = e / C, c = e - b * C;
         om[b * C + c] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + c);
@@ -347,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     }
     __syncthreads();
     // the phase-A stages use the first 2^RA - 1 twiddles with indices fixed by
-    // the register position: keep them in registers for the whole tile
+    // the register position: keep them in registers for the whole block
     cvec<R> twr[(1 << RA) - 1], ttr[(1 << RA) - 1];
 #pragma unroll
     for (int i = 0; i < (1 << RA) - 1; ++i) {
@@ -355,80 +372,108 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         ttr[i] = TT[i];
     }
     const int nla = C << RB, nlb = C << RA;
-    // phase A (inverse cascade, low bits of G2): the amplitudes at y1 = o and
-    // y2 = (lhi << RA) | k are T_j(o) times the phases of the set bits of y2
-    for (int line = threadIdx.x; line < nla; line += NT) {
-        const int c = line & (C - 1), lhi = line >> A.cl;
-        const uint64_t col = j0 + c;
-        cvec<R> v[1 << RA];
-        cvec<R> base = line == (int)threadIdx.x ? t0 : gld<R>(psi, (o << A.n_s) | col);
-        for (int b = 0; b < RB; ++b)
-            if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-        // the first inverse stage (group bit 0) sees the product input only:
-        // the pair (1, om_0) becomes (1 + om_0 conj(tw_0), 1 - om_0 conj(tw_0))
-        const cvec<R> w0 = cconjmul<R>(om[c], twr[0]);
-        v[0] = cmul<R>(base, cmake<R>((R)1 + w0.x, w0.y));
-        v[1] = cmul<R>(base, cmake<R>((R)1 - w0.x, -w0.y));
-#pragma unroll
-        for (int b = 1; b < RA; ++b) {
-            const cvec<R> w = om[b * C + c];
-#pragma unroll
-            for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
-        }
-#pragma unroll
-        for (int jb = 1; jb < RA; ++jb)
-            stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
-        cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
-#pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) lt[k << A.cl] = v[k];
-    }
-    __syncthreads();
-    // phase B: inverse cascade on the high bits, rotation, forward cascade on the high bits
     double pa = 0.0, nt = 0.0;
-    for (int line = threadIdx.x; line < nlb; line += NT) {
-        const int c = line & (C - 1), llo = line >> A.cl;
-        cvec<R> v[1 << RB];
-        cvec<R> *lt = tile + (llo << A.cl) + c;
+    for (int it = 0; it < iters; ++it) {
+        // phase A (inverse cascade, low bits of G2): the amplitudes at y1 = o and
+        // y2 = (lhi << RA) | k are T_j(o) times the phases of the set bits of y2
+        for (int line = threadIdx.x; line < nla; line += NT) {
+            const int c = line & (C - 1), lhi = line >> A.cl;
+            const uint64_t col = j0 + c;
+            cvec<R> v[1 << RA];
+            cvec<R> base = line == (int)threadIdx.x ? t0 : gld<R>(psi, (o << A.n_s) | col);
+            for (int b = 0; b < RB; ++b)
+                if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
+            // the first inverse stage (group bit 0) sees the product input only:
+            // the pair (1, om_0) becomes (1 + om_0 conj(tw_0), 1 - om_0 conj(tw_0))
+            const cvec<R> w0 = cconjmul<R>(om[c], twr[0]);
+            v[0] = cmul<R>(base, cmake<R>((R)1 + w0.x, w0.y));
+            v[1] = cmul<R>(base, cmake<R>((R)1 - w0.x, -w0.y));
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) v[k] = lt[(k << RA) << A.cl];
+            for (int b = 1; b < RA; ++b) {
+                const cvec<R> w = om[b * C + c];
 #pragma unroll
-        for (int jb = RA; jb < G; ++jb)
-            stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
-                               [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
-        // |a|^2 summed over the line in the amplitude precision (weighted by
-        // s_y^2 for P(a = 1); the rotation keeps each pair's norm, so the
-        // total is the plain sum), then accumulated in FP64
-        R lpa = 0, lnt = 0;
-        const R *s2l = s2t + llo, *srl = srt + llo;
+                for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
+            }
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) {
-            const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
-            lpa += s2l[k << RA] * a2;
-            lnt += a2;
-            const R sr = srl[k << RA];
-            v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
+            for (int jb = 1; jb < RA; ++jb)
+                stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
+            cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
+#pragma unroll
+            for (int k = 0; k < (1 << RA); ++k) lt[k << A.cl] = v[k];
         }
-        pa += (double)lpa;
-        nt += (double)lnt * fold;
-        fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
-                                          [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+        // persistent: the next tile's G1 table entry and G2-bit phases, in
+        // flight during this tile's phase B
+        const bool more = it + 1 < iters;
+        cvec<R> omn[OMR];
+        if (more) {
+            t0 = gld<R>(psi, (o << A.n_s) | (j0 + jstep + (threadIdx.x & (C - 1))));
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
-    }
-    __syncthreads();
-    // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
-    for (int line = threadIdx.x; line < nla; line += NT) {
-        const int c = line & (C - 1), lhi = line >> A.cl;
-        cvec<R> v[1 << RA];
-        const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
+            for (int q = 0; q < OMR; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < G * C) {
+                    const int b = e / C, c = e - b * C;
+                    omn[q] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + jstep + c);
+                }
+            }
+        }
+        __syncthreads();
+        // phase B: inverse cascade on the high bits, rotation, forward cascade on the high bits
+        for (int line = threadIdx.x; line < nlb; line += NT) {
+            const int c = line & (C - 1), llo = line >> A.cl;
+            cvec<R> v[1 << RB];
+            cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-        fwd_cascade<R, RA, RA - 1, 0, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
-        // clock index o + (((lhi << RA) + k) << g1): a base for the line and a stride for k
-        cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
-        const uint64_t ks = 1ull << (g1 + A.n_s);
+            for (int k = 0; k < (1 << RB); ++k) v[k] = lt[(k << RA) << A.cl];
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) gst<R>(p, k * ks, v[k]);
+            for (int jb = RA; jb < G; ++jb)
+                stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
+                                   [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+            // |a|^2 summed over the line in the amplitude precision (weighted by
+            // s_y^2 for P(a = 1); the rotation keeps each pair's norm, so the
+            // total is the plain sum), then accumulated in FP64
+            R lpa = 0, lnt = 0;
+            const R *s2l = s2t + llo, *srl = srt + llo;
+#pragma unroll
+            for (int k = 0; k < (1 << RB); ++k) {
+                const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
+                lpa += s2l[k << RA] * a2;
+                lnt += a2;
+                const R sr = srl[k << RA];
+                v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
+            }
+            pa += (double)lpa;
+            nt += (double)lnt * fold;
+            fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
+                                              [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+#pragma unroll
+            for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
+        }
+        // the phases are read in phase A only: the next tile's go in now
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < OMR; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < G * C) om[e] = omn[q];
+            }
+        }
+        __syncthreads();
+        // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
+        for (int line = threadIdx.x; line < nla; line += NT) {
+            const int c = line & (C - 1), lhi = line >> A.cl;
+            cvec<R> v[1 << RA];
+            const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
+#pragma unroll
+            for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
+            fwd_cascade<R, RA, RA - 1, 0, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
+            // clock index o + (((lhi << RA) + k) << g1): a base for the line and a stride for k
+            cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
+            const uint64_t ks = 1ull << (g1 + A.n_s);
+#pragma unroll
+            for (int k = 0; k < (1 << RA); ++k) gst<R>(p, k * ks, v[k]);
+        }
+        j0 += jstep;
+        // the next tile's phase A rewrites the tile this one has just read
+        if (more) __syncthreads();
     }
     pa = wave_sum_f64(pa);
     nt = wave_sum_f64(nt);
@@ -687,6 +732,9 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
     A.scale = 1.0 / sqrt((double)(1ull << n_c));
     A.sgn = 0;
     A.gcut = 0;
+    A.pers = 0;
+    A.pslog = 0;
+    A.iters = 1;
     for (int w = 0; w < 3; ++w) {
         const int g = w == 1 ? A.g2 : A.g1;
         P.A[w] = A;
@@ -777,6 +825,34 @@ sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on
     return SV_OK;
 }
 
+// Persistent k_pipe_b for a single solve: 2^g1 x S blocks, S = 2^pslog
+// blocks per G1 value (about 512 blocks in all, two per CU), each walking
+// nb / S column blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose
+// phase prefetch would not fit keep one block per tile.
+static int pipe_b_persist_env() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("SV_PIPE_B_PERSIST");
+        v = (e && atoi(e) == 0) ? 0 : 1;
+    }
+    return v;
+}
+
+static void make_persistent(PipePlan &P) {
+    PipeArgs &A = P.A[1];
+    const int G = A.g2;
+    const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
+    if (!pipe_b_persist_env() || (uint64_t)G * C > 2ull * (uint64_t)P.nt[1]) return;
+    int pslog = 0;
+    while (pslog + A.g1 < 9 && (2ull << pslog) <= nb) ++pslog;
+    const uint64_t blocks = 1ull << (A.g1 + pslog);
+    if (blocks > 0x7fffffffull) return;
+    A.pers = 1;
+    A.pslog = pslog;
+    A.iters = (int)(nb >> pslog);
+    P.grid[1] = dim3((unsigned)blocks, 1, 1);
+}
+
 template <typename R>
 sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const double2 *beta, const uint64_t *F,
                    double *part, double2 *zpart, uint64_t *nparts) {
@@ -790,6 +866,7 @@ sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const 
         P.A[w].sgn = sgn ? 1 : 0;
         P.A[w].gcut = gcut;
     }
+    make_persistent(P);
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
     for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s->stream, P, w, one, nullptr));
     return SV_OK;
