@@ -53,8 +53,10 @@ struct PipeArgs {
     double scale;        // 2^(-n_c/2)
     int sgn;             // signed (two's-complement) clock for the inversion
     uint64_t gcut;       // 0: inversion sin = 1/y; >= 1: gapped-phase-estimation flag, sin = [|y| >= gcut]
-    int pers;            // k_pipe_b: persistent blocks (one G1 value each, iters column blocks)
-    int pslog, iters;    // log2 of the blocks per G1 value; column blocks per block
+    int pers;            // k_pipe_b / k_pipe_c: persistent blocks (one value of the other clock
+                         // group each, iters column blocks)
+    int pslog, iters;    // log2 of the blocks per group value; column blocks per block
+    int ccrows;          // k_pipe_a stages the G2-value phases for k_pipe_c (n_c >= 4)
 };
 
 // HBM pointers of a solve, in the global address space: the pointers come
@@ -259,6 +261,19 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
         const uint64_t j = j0 + c;
         const int q = r < g2 ? n_c - 1 - (G + r) : n_c - 1 - (r - g2);
         gst<R>(psi, ((((uint64_t)1 << G) + (uint64_t)r) << A.n_s) + j, turn_phase<R>(F[j * n_c + q]));
+    }
+    // for k_pipe_c: the conjugate phase of every G2 value o2 (the product of
+    // its set bits' phases, as one exact turn sum) per column, in clock rows
+    // 2^(g1+1) + o2 of the ancilla = 0 half (free for n_c >= 4)
+    if (A.ccrows) {
+        for (int e = threadIdx.x; e < (C << g2); e += NT) {
+            const int o2 = e >> A.cl, c = e & (C - 1);
+            const uint64_t j = j0 + c;
+            uint64_t th = 0;
+            for (int q = 0; q < g2; ++q)
+                if (o2 >> q & 1) th += F[j * n_c + (n_c - 1 - (G + q))];
+            gst<R>(psi, ((((uint64_t)2 << G) + (uint64_t)o2) << A.n_s) + j, turn_phase<R>((uint64_t)0 - th));
+        }
     }
     __syncthreads();
     // phase A: line = (c, l_hi), register index = bits [0, RA)
@@ -499,8 +514,11 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
 // (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+// (persistent: four waves per SIMD, as the LDS allows, beat the fewer that
+// the prefetched line's registers would otherwise leave)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
+    constexpr int OMR = 2;               // G1-bit phases per thread (G C <= 8 * 64 <= 2 NT)
     const PipeSolve S = solve_of(one, many);
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
@@ -513,18 +531,29 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     cvec<R> *cc = om + G * C;
     const size_t zoff = (((size_t)((unsigned char *)(cc + C) - smem_raw)) + 15) & ~(size_t)15;
     double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [NT] per-thread partials
+    // tiles: one per block, or, persistent, a fixed G2 value per block and
+    // the column blocks (blockIdx.x mod 2^pslog) + it 2^pslog
     uint64_t j0, o;
-    tile_coords(A, j0, o);               // o = value of the G2 bits
+    int iters = 1;
+    uint64_t jstep = 0;
+    if (A.pers) {
+        o = blockIdx.x >> A.pslog;
+        j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
+        iters = A.iters;
+        jstep = 1ull << (A.pslog + A.cl);
+    } else {
+        tile_coords(A, j0, o);           // o = value of the G2 bits
+    }
     const int n_c = A.n_c;
     const int nla = C << RB, nlb = C << RA;
     // the thread's first phase-B line is read before the tables are built, so
     // the HBM latency overlaps that work
     // clock index (o << G) + (k << RA) + llo: a base for the line and a stride for k
     const uint64_t ks = 1ull << (RA + A.n_s);
+    const uint64_t lrow = A.abit + (((o << G) + (uint64_t)(threadIdx.x >> A.cl)) << A.n_s) + (threadIdx.x & (C - 1));
     cvec<R> v0[1 << RB];
     if ((int)threadIdx.x < nlb) {
-        const int c = threadIdx.x & (C - 1), llo = threadIdx.x >> A.cl;
-        const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
+        const cvec<R> *p = psi + (lrow + j0);
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
     }
@@ -533,7 +562,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     // per-column phase tables from the clock-bit phases k_pipe_a staged in
     // rows 2^G + r of the ancilla = 0 half: om[b][c] (b < G) the conjugate
     // phase of G1 bit b, cc[c] (b = G) the conjugate of the product of the
-    // phases of the G2 bits set in o
+    // phases of the G2 bits set in o (staged whole in row 2^(G+1) + o when
+    // k_pipe_a wrote those rows)
     const int g2 = n_c - G;
     for (int e = threadIdx.x; e < (G + 1) * C; e += NT) {
         const int b = e / C, c = e - b * C;
@@ -541,6 +571,8 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         if (b < G) {
             const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + j);
             om[b * C + c] = cmake<R>(w.x, -w.y);
+        } else if (A.ccrows) {
+            cc[c] = gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + j);
         } else {
             cvec<R> p = cmake<R>((R)1, (R)0);
             for (int q = 0; q < g2; ++q)
@@ -555,72 +587,106 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
         twr[i] = TW[i];
         ttr[i] = TT[i];
     }
-    // phase B first: the forward cascade starts at the top bit of G1
-    for (int line = threadIdx.x; line < nlb; line += NT) {
-        const int c = line & (C - 1), llo = line >> A.cl;
-        cvec<R> v[1 << RB];
-        if (line == (int)threadIdx.x) {
+    for (int it = 0; it < iters; ++it) {
+        // phase B first: the forward cascade starts at the top bit of G1
+        for (int line = threadIdx.x; line < nlb; line += NT) {
+            const int c = line & (C - 1), llo = line >> A.cl;
+            cvec<R> v[1 << RB];
+            if (line == (int)threadIdx.x) {
 #pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
-        } else {
-            const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
+                for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
+            } else {
+                const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
 #pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) v[k] = gld<R>(p, k * ks);
+                for (int k = 0; k < (1 << RB); ++k) v[k] = gld<R>(p, k * ks);
+            }
+            fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
+                                              [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+            cvec<R> *lt = tile + (llo << A.cl) + c;
+#pragma unroll
+            for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
         }
-        fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
-                                          [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
-        cvec<R> *lt = tile + (llo << A.cl) + c;
+        __syncthreads();
+        // persistent: the next tile's first phase-B line and column phases,
+        // in flight during this tile's phase A
+        const bool more = it + 1 < iters;
+        cvec<R> omn[OMR], ccn = cmake<R>((R)1, (R)0);
+        if (more) {
+            const uint64_t jn = j0 + jstep;
+            if ((int)threadIdx.x < nlb) {
+                const cvec<R> *p = psi + (lrow + jn);
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
-    }
-    __syncthreads();
-    // phase A: remaining stages, conjugate phases, sum over the line
-    double zr = 0.0, zi = 0.0;
-    for (int line = threadIdx.x; line < nla; line += NT) {
-        const int c = line & (C - 1), lhi = line >> A.cl;
-        cvec<R> v[1 << RA];
-        const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
+                for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
+            }
 #pragma unroll
-        for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-        if (RA > 1)
-            fwd_cascade<R, RA, RA - 1, 1, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
-        // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
-        cvec<R> ph[1 << (RA - 1)];
-        cvec<R> base = cc[c];
-        for (int b = 0; b < RB; ++b)
-            if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-        ph[0] = base;
-#pragma unroll
-        for (int b = 1; b < RA; ++b) {
-            const cvec<R> w = om[b * C + c];
-#pragma unroll
-            for (int k = 0; k < (1 << (b - 1)); ++k) ph[k | (1 << (b - 1))] = cmul<R>(ph[k], w);
+            for (int q = 0; q < OMR; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < G * C) {
+                    const int b = e / C, c = e - b * C;
+                    omn[q] = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + jn + c);
+                }
+            }
+            if ((int)threadIdx.x < C) ccn = gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + jn + threadIdx.x);
         }
-        // the last forward stage (group bit 0, no twiddle) and the phase of
-        // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0))
-        const cvec<R> w0 = om[c];
-        const cvec<R> up = cmake<R>((R)1 + w0.x, w0.y), um = cmake<R>((R)1 - w0.x, -w0.y);
-        R lr = 0, li = 0;                // the line's sum, then FP64
+        // phase A: remaining stages, conjugate phases, sum over the line
+        double zr = 0.0, zi = 0.0;
+        for (int line = threadIdx.x; line < nla; line += NT) {
+            const int c = line & (C - 1), lhi = line >> A.cl;
+            cvec<R> v[1 << RA];
+            const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
-        for (int m = 0; m < (1 << (RA - 1)); ++m) {
-            const cvec<R> a = cmac2<R>(up, v[2 * m], um, v[2 * m + 1]);
-            const cvec<R> p = cmul<R>(a, ph[m]);
-            lr += p.x;
-            li += p.y;
+            for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
+            if (RA > 1)
+                fwd_cascade<R, RA, RA - 1, 1, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
+            // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
+            cvec<R> ph[1 << (RA - 1)];
+            cvec<R> base = cc[c];
+            for (int b = 0; b < RB; ++b)
+                if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
+            ph[0] = base;
+#pragma unroll
+            for (int b = 1; b < RA; ++b) {
+                const cvec<R> w = om[b * C + c];
+#pragma unroll
+                for (int k = 0; k < (1 << (b - 1)); ++k) ph[k | (1 << (b - 1))] = cmul<R>(ph[k], w);
+            }
+            // the last forward stage (group bit 0, no twiddle) and the phase of
+            // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0))
+            const cvec<R> w0 = om[c];
+            const cvec<R> up = cmake<R>((R)1 + w0.x, w0.y), um = cmake<R>((R)1 - w0.x, -w0.y);
+            R lr = 0, li = 0;                // the line's sum, then FP64
+#pragma unroll
+            for (int m = 0; m < (1 << (RA - 1)); ++m) {
+                const cvec<R> a = cmac2<R>(up, v[2 * m], um, v[2 * m + 1]);
+                const cvec<R> p = cmul<R>(a, ph[m]);
+                lr += p.x;
+                li += p.y;
+            }
+            zr += (double)lr;
+            zi += (double)li;
         }
-        zr += (double)lr;
-        zi += (double)li;
-    }
-    // every line of a thread has the thread's column (the line stride NT is a multiple of C)
-    zs[threadIdx.x] = make_double2(zr, zi);
-    __syncthreads();
-    for (int c = threadIdx.x; c < C; c += NT) {
-        double r = 0.0, i = 0.0;
-        for (int t = c; t < NT; t += C) {
-            r += zs[t].x;
-            i += zs[t].y;
+        // every line of a thread has the thread's column (the line stride NT is a multiple of C)
+        zs[threadIdx.x] = make_double2(zr, zi);
+        __syncthreads();
+        for (int c = threadIdx.x; c < C; c += NT) {
+            double r = 0.0, i = 0.0;
+            for (int t = c; t < NT; t += C) {
+                r += zs[t].x;
+                i += zs[t].y;
+            }
+            gst<double>(zpart, o * A.N + j0 + c, make_double2(r, i));
         }
-        gst<double>(zpart, o * A.N + j0 + c, make_double2(r, i));
+        // the column phases are read in phase A only: the next tile's go in
+        // now (visible after the next phase B's barrier)
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < OMR; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < G * C) om[e] = cmake<R>(omn[q].x, -omn[q].y);
+            }
+            if ((int)threadIdx.x < C) cc[threadIdx.x] = ccn;
+        }
+        j0 += jstep;
     }
 }
 
@@ -735,6 +801,7 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
     A.pers = 0;
     A.pslog = 0;
     A.iters = 1;
+    A.ccrows = n_c >= 4 ? 1 : 0;
     for (int w = 0; w < 3; ++w) {
         const int g = w == 1 ? A.g2 : A.g1;
         P.A[w] = A;
@@ -825,10 +892,11 @@ sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on
     return SV_OK;
 }
 
-// Persistent k_pipe_b for a single solve: 2^g1 x S blocks, S = 2^pslog
-// blocks per G1 value (about 512 blocks in all, two per CU), each walking
-// nb / S column blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose
-// phase prefetch would not fit keep one block per tile.
+// Persistent k_pipe_b and k_pipe_c for a single solve: 2^(other group) x S
+// blocks, S = 2^pslog blocks per value of the clock group the kernel does not
+// transform (about 512 blocks in all, two per CU), each walking nb / S column
+// blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose phase
+// prefetch would not fit keep one block per tile.
 static int pipe_b_persist_env() {
     static int v = -1;
     if (v < 0) {
@@ -839,18 +907,22 @@ static int pipe_b_persist_env() {
 }
 
 static void make_persistent(PipePlan &P) {
-    PipeArgs &A = P.A[1];
-    const int G = A.g2;
-    const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
-    if (!pipe_b_persist_env() || (uint64_t)G * C > 2ull * (uint64_t)P.nt[1]) return;
-    int pslog = 0;
-    while (pslog + A.g1 < 9 && (2ull << pslog) <= nb) ++pslog;
-    const uint64_t blocks = 1ull << (A.g1 + pslog);
-    if (blocks > 0x7fffffffull) return;
-    A.pers = 1;
-    A.pslog = pslog;
-    A.iters = (int)(nb >> pslog);
-    P.grid[1] = dim3((unsigned)blocks, 1, 1);
+    if (!pipe_b_persist_env()) return;
+    for (int w = 1; w <= 2; ++w) {
+        PipeArgs &A = P.A[w];
+        const int G = w == 1 ? A.g2 : A.g1, other = A.n_c - G;
+        const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
+        if ((uint64_t)G * C > 2ull * (uint64_t)P.nt[w]) continue;
+        if (w == 2 && !A.ccrows) continue;
+        int pslog = 0;
+        while (pslog + other < 9 && (2ull << pslog) <= nb) ++pslog;
+        const uint64_t blocks = 1ull << (other + pslog);
+        if (blocks > 0x7fffffffull) continue;
+        A.pers = 1;
+        A.pslog = pslog;
+        A.iters = (int)(nb >> pslog);
+        P.grid[w] = dim3((unsigned)blocks, 1, 1);
+    }
 }
 
 template <typename R>
