@@ -956,6 +956,9 @@ sv_status pipe_run_batch(hipStream_t st, int n_s, int n_c, const int cl[3], cons
     if (nsolves < 1 || nsolves > 65535) return fail(SV_EINVAL, "batch of %d solves", nsolves);
     PipePlan P;
     make_plan(P, n_s, n_c, e, cl, nt, nsolves);
+    // one block per tile here: k_pipe_c forms the G2-value phases itself, so
+    // k_pipe_a need not stage them
+    for (int w = 0; w < 3; ++w) P.A[w].ccrows = 0;
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
     PipeSolve none{};
     for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(st, P, w, none, dev_solves));
