@@ -322,8 +322,8 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 // ---------------------------------------------------------------------------
 // k_pipe_b: inverse cascade on G2, inversion rotation, forward cascade on G2
 // ---------------------------------------------------------------------------
-template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+template <typename R, int RA, int RB, int NT, bool PERS>
+__device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
     // phases of the G2 bits per thread (G C <= 8 * 64 <= 2 NT)
     constexpr int OMR = 2;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     uint64_t j0, o;
     int iters = 1;
     uint64_t jstep = 0;
-    if (A.pers) {
+    if (PERS) {
         o = blockIdx.x >> A.pslog;
         j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
         iters = A.iters;
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
         }
         // persistent: the next tile's G1 table entry and G2-bit phases, in
         // flight during this tile's phase B
-        const bool more = it + 1 < iters;
+        const bool more = PERS && it + 1 < iters;
         cvec<R> omn[OMR];
         if (more) {
             t0 = gld<R>(psi, (o << A.n_s) | (j0 + jstep + (threadIdx.x & (C - 1))));
@@ -509,14 +509,23 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
     }
 }
 
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+    pipe_b_body<R, RA, RB, NT, false>(A, one, many);
+}
+
+// the persistent form (single solves): one G1 value per block
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_bp(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+    pipe_b_body<R, RA, RB, NT, true>(A, one, many);
+}
+
 // ---------------------------------------------------------------------------
 // k_pipe_c: forward cascade on G1, conjugate phases, clock sum of the tile
 // (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
-template <typename R, int RA, int RB, int NT>
-// (persistent: four waves per SIMD, as the LDS allows, beat the fewer that
-// the prefetched line's registers would otherwise leave)
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+template <typename R, int RA, int RB, int NT, bool PERS>
+__device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
     constexpr int OMR = 2;               // G1-bit phases per thread (G C <= 8 * 64 <= 2 NT)
     const PipeSolve S = solve_of(one, many);
@@ -536,7 +545,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     uint64_t j0, o;
     int iters = 1;
     uint64_t jstep = 0;
-    if (A.pers) {
+    if (PERS) {
         o = blockIdx.x >> A.pslog;
         j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
         iters = A.iters;
@@ -609,7 +618,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         __syncthreads();
         // persistent: the next tile's first phase-B line and column phases,
         // in flight during this tile's phase A
-        const bool more = it + 1 < iters;
+        const bool more = PERS && it + 1 < iters;
         cvec<R> omn[OMR], ccn = cmake<R>((R)1, (R)0);
         if (more) {
             const uint64_t jn = j0 + jstep;
@@ -690,6 +699,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 }
 
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+    pipe_c_body<R, RA, RB, NT, false>(A, one, many);
+}
+
+// the persistent form (single solves): one G2 value per block; four waves per
+// SIMD, as the LDS allows, beat the fewer that the prefetched line's
+// registers would otherwise leave
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pipe_cp(
+    PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+    pipe_c_body<R, RA, RB, NT, true>(A, one, many);
+}
+
 // ---------------------------------------------------------------------------
 // host
 // ---------------------------------------------------------------------------
@@ -708,8 +731,12 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         hipError_t e2 = hipFuncSetAttribute((const void *)k_pipe_c<R, RA, RB, NT>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        hipError_t e3 = hipFuncSetAttribute((const void *)k_pipe_bp<R, RA, RB, NT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        hipError_t e4 = hipFuncSetAttribute((const void *)k_pipe_cp<R, RA, RB, NT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         (void)hipGetLastError();
-        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess)
+        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
             return fail(SV_EDEVICE, "cannot raise the LDS limit of the pipeline kernels");
         attr_done = true;
     }
@@ -723,10 +750,16 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
         hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else if (which == 1) {
         TraceScope ts(st, "pipe_b_iqft_ry_qft", half + table, 0.0);
-        hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        if (A.pers)
+            hipLaunchKernelGGL((k_pipe_bp<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        else
+            hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else {
         TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
-        hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        if (A.pers)
+            hipLaunchKernelGGL((k_pipe_cp<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        else
+            hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
