@@ -854,77 +854,6 @@ static sv_status run_one(hipStream_t st, const PipePlan &P, int w, const PipeSol
     return dispatch_g<R>(w, st, one, many, P.A[w], g, P.nt[w], P.grid[w], P.lds[w]);
 }
 
-// The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
-// tile, threads per workgroup) for each of the three kernels on the real
-// operands of one solve (each kernel is idempotent given its input half)
-// and keep the fastest; results live in the process-wide tuning cache.
-template <typename R>
-static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &one, int cl_out[3], int nt_out[3]) {
-    const size_t e = sizeof(cvec<R>);
-    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
-    for (int w = 0; w < 3; ++w) {
-        cl_out[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
-        nt_out[w] = 256;
-    }
-    for (int w = 0; w < 3; ++w) {
-        const int g = w == 1 ? g2 : g1;
-        float best = 1e30f;
-        int bcl = cl_out[w], bnt = nt_out[w];
-        for (int cl = 3; cl <= 6; ++cl) {
-            if (cl > n_s) break;
-            for (int nt : {256, 512}) {
-                if (pipe_lds(w, cl, g, e, nt) > (size_t)PIPE_LDS_LIMIT) continue;
-                int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
-                cls[w] = cl;
-                nts[w] = nt;
-                PipePlan P;
-                make_plan(P, n_s, n_c, e, cls, nts, 1);
-                float ms = 0.f;
-                SV_TRY(time_stream(st, 2, &ms, [&]() { return run_one<R>(st, P, w, one, nullptr); }));
-                if (ms < best) {
-                    best = ms;
-                    bcl = cl;
-                    bnt = nt;
-                }
-            }
-        }
-        cl_out[w] = bcl;
-        nt_out[w] = bnt;
-        // the next kernel reads what this one writes: leave its output in place
-        PipePlan P;
-        make_plan(P, n_s, n_c, e, cl_out, nt_out, 1);
-        SV_TRY(run_one<R>(st, P, w, one, nullptr));
-    }
-    return SV_OK;
-}
-
-// launch parameters for a shape: cached, tuned on `one` if allowed, else defaults
-template <typename R>
-sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]) {
-    const size_t e = sizeof(cvec<R>);
-    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
-    const std::string key = std::string("eigpipe/") + (e == 8 ? "c64/" : "c128/") + std::to_string(n_s) + "/" +
-                            std::to_string(n_c);
-    std::vector<int> cached;
-    if (tune_lookup(key, cached) && cached.size() == 6) {
-        for (int w = 0; w < 3; ++w) {
-            cl[w] = cached[2 * w];
-            nt[w] = cached[2 * w + 1];
-        }
-        return SV_OK;
-    }
-    if (tune_on && autotune_enabled()) {
-        SV_TRY(tune_pipe<R>(st, n_s, n_c, *tune_on, cl, nt));
-        tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
-        return SV_OK;
-    }
-    for (int w = 0; w < 3; ++w) {
-        cl[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
-        nt[w] = 256;
-    }
-    return SV_OK;
-}
-
 // Persistent k_pipe_b and k_pipe_c for a single solve: 2^(other group) x S
 // blocks, S = 2^pslog blocks per value of the clock group the kernel does not
 // transform (about 512 blocks in all, two per CU), each walking nb / S column
@@ -958,13 +887,95 @@ static void make_persistent(PipePlan &P) {
     }
 }
 
+// The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
+// tile, threads per workgroup) for each of the three kernels on the real
+// operands of one solve (each kernel is idempotent given its input half)
+// and keep the fastest; results live in the process-wide tuning cache.
+template <typename R>
+static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &one, bool pers, int cl_out[3],
+                           int nt_out[3]) {
+    const size_t e = sizeof(cvec<R>);
+    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
+    for (int w = 0; w < 3; ++w) {
+        cl_out[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
+        nt_out[w] = 256;
+    }
+    for (int w = 0; w < 3; ++w) {
+        const int g = w == 1 ? g2 : g1;
+        float best = 1e30f;
+        int bcl = cl_out[w], bnt = nt_out[w];
+        for (int cl = 3; cl <= 6; ++cl) {
+            if (cl > n_s) break;
+            for (int nt : {256, 512}) {
+                if (pipe_lds(w, cl, g, e, nt) > (size_t)PIPE_LDS_LIMIT) continue;
+                int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
+                cls[w] = cl;
+                nts[w] = nt;
+                PipePlan P;
+                make_plan(P, n_s, n_c, e, cls, nts, 1);
+                if (pers) make_persistent(P);
+                float ms = 0.f;
+                SV_TRY(time_stream(st, 2, &ms, [&]() { return run_one<R>(st, P, w, one, nullptr); }));
+                if (ms < best) {
+                    best = ms;
+                    bcl = cl;
+                    bnt = nt;
+                }
+            }
+        }
+        cl_out[w] = bcl;
+        nt_out[w] = bnt;
+        // the next kernel reads what this one writes: leave its output in place
+        PipePlan P;
+        make_plan(P, n_s, n_c, e, cl_out, nt_out, 1);
+        if (pers) make_persistent(P);
+        SV_TRY(run_one<R>(st, P, w, one, nullptr));
+    }
+    return SV_OK;
+}
+
+// launch parameters for a shape: cached, tuned on `one` if allowed, else defaults
+template <typename R>
+static sv_status pipe_config_impl(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, bool pers, int cl[3],
+                                  int nt[3]) {
+    const size_t e = sizeof(cvec<R>);
+    const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
+    // the persistent kernels of a single solve are tuned (and cached) apart
+    // from the per-tile kernels of batches
+    const std::string key = std::string("eigpipe/") + (e == 8 ? "c64/" : "c128/") + std::to_string(n_s) + "/" +
+                            std::to_string(n_c) + (pers ? "/p" : "");
+    std::vector<int> cached;
+    if (tune_lookup(key, cached) && cached.size() == 6) {
+        for (int w = 0; w < 3; ++w) {
+            cl[w] = cached[2 * w];
+            nt[w] = cached[2 * w + 1];
+        }
+        return SV_OK;
+    }
+    if (tune_on && autotune_enabled()) {
+        SV_TRY(tune_pipe<R>(st, n_s, n_c, *tune_on, pers, cl, nt));
+        tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
+        return SV_OK;
+    }
+    for (int w = 0; w < 3; ++w) {
+        cl[w] = default_cl(n_s, w == 1 ? g2 : g1, e);
+        nt[w] = 256;
+    }
+    return SV_OK;
+}
+
+template <typename R>
+sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]) {
+    return pipe_config_impl<R>(st, n_s, n_c, tune_on, false, cl, nt);
+}
+
 template <typename R>
 sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const double2 *beta, const uint64_t *F,
                    double *part, double2 *zpart, uint64_t *nparts) {
     const size_t e = sizeof(cvec<R>);
     PipeSolve one{s->data, beta, F, part, zpart};
     int cl[3], nt[3];
-    SV_TRY(pipe_config<R>(s->stream, n_s, n_c, &one, cl, nt));
+    SV_TRY(pipe_config_impl<R>(s->stream, n_s, n_c, &one, pipe_b_persist_env() != 0, cl, nt));
     PipePlan P;
     make_plan(P, n_s, n_c, e, cl, nt, 1);
     for (int w = 0; w < 3; ++w) {
