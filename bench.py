@@ -212,7 +212,8 @@ def main():
         "quality": {"fidelity_vs_classical": F, "one_minus_F": 1.0 - F, "p_post": res.p_post,
                     "norm_total": res.norm_total},
     }
-    out["autotune"] = [ln for ln in B.sv_tune_report().strip().splitlines() if f"/c64/{n_s}/{n_c} " in ln]
+    out["autotune"] = [ln for ln in B.sv_tune_report().strip().splitlines()
+                       if f"/c64/{n_s}/{n_c} " in ln or f"/c64/{n_s}/{n_c}/p " in ln]
     B.sv_hhl_plan_free(plan)
     st.close()
     del st
