@@ -28,39 +28,56 @@ namespace sv {
 // heap-ordered (cos, sin) of every node, node k = 2^l + p at 2k, 2k + 1.
 // A thread owns the 2^C leaves below one node of level m - C: it walks the
 // m - C levels above that node once, then expands its subtree in registers.
-// Amplitudes outside the register were cleared by the caller.
+// The leaves of a block's QSP_NT subtrees (QSP_NT 2^C consecutive register
+// values) go through LDS (one pad element per thread, so the row writes are
+// conflict-free) and leave in register order, so that each store and each
+// phase-table read of a wavefront covers consecutive addresses.
+constexpr int QSP_NT = 128;
+
 template <typename R, int C>
-__global__ __launch_bounds__(256) void k_qsp_tree(cvec<R> *__restrict__ psi, int q_lo, int m,
-                                                  const R *__restrict__ cs, const cvec<R> *__restrict__ ph) {
+__global__ __launch_bounds__(QSP_NT) void k_qsp_tree(cvec<R> *__restrict__ psi, int q_lo, int m,
+                                                     const R *__restrict__ cs, const cvec<R> *__restrict__ ph) {
+    constexpr int L = 1 << C, LP = L + 1;
+    __shared__ R leaves[QSP_NT * LP];
     const uint64_t nsub = 1ull << (m - C);          // subtrees
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nsub; t += stride) {
-        R a = 1;
-        uint64_t node = 1;
-        for (int l = 0; l < m - C; ++l) {
-            const uint64_t bit = (t >> (m - C - 1 - l)) & 1ull;
-            a *= cs[2 * node + bit];
-            node = 2 * node + bit;
-        }
-        R v[1 << C];
-        v[0] = a;
-#pragma unroll
-        for (int l = 0; l < C; ++l) {
-            // the 2^l values of this level, at nodes (node << l) + q, split into their children
-#pragma unroll
-            for (int q = (1 << l) - 1; q >= 0; --q) {
-                const uint64_t nd = (node << l) + (uint64_t)q;
-                const R x = v[q];
-                v[2 * q] = x * cs[2 * nd];
-                v[2 * q + 1] = x * cs[2 * nd + 1];
+    const uint64_t R_ = 1ull << m;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * QSP_NT; t0 < nsub; t0 += (uint64_t)gridDim.x * QSP_NT) {
+        const uint64_t t = t0 + threadIdx.x;
+        if (t < nsub) {
+            R a = 1;
+            uint64_t node = 1;
+            for (int l = 0; l < m - C; ++l) {
+                const uint64_t bit = (t >> (m - C - 1 - l)) & 1ull;
+                a *= cs[2 * node + bit];
+                node = 2 * node + bit;
             }
-        }
+            R v[L];
+            v[0] = a;
 #pragma unroll
-        for (int j = 0; j < (1 << C); ++j) {
-            const uint64_t r = (t << C) | (uint64_t)j;
-            const cvec<R> p = ph[r];
-            psi[r << q_lo] = cmake<R>(v[j] * p.x, v[j] * p.y);
+            for (int l = 0; l < C; ++l) {
+                // the 2^l values of this level, at nodes (node << l) + q, split into their children
+#pragma unroll
+                for (int q = (1 << l) - 1; q >= 0; --q) {
+                    const uint64_t nd = (node << l) + (uint64_t)q;
+                    const R x = v[q];
+                    v[2 * q] = x * cs[2 * nd];
+                    v[2 * q + 1] = x * cs[2 * nd + 1];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < L; ++j) leaves[threadIdx.x * LP + j] = v[j];
         }
+        __syncthreads();
+        // leaf e of the block is register value (t0 << C) + e
+        const uint64_t rbase = t0 << C;
+        for (int e = threadIdx.x; e < QSP_NT * L; e += QSP_NT) {
+            const uint64_t r = rbase + (uint64_t)e;
+            if (r >= R_) break;
+            const R x = leaves[(e >> C) * LP + (e & (L - 1))];
+            const cvec<R> p = ph[r];
+            psi[r << q_lo] = cmake<R>(x * p.x, x * p.y);
+        }
+        __syncthreads();
     }
 }
 
@@ -157,16 +174,18 @@ sv_status sv_qsp_prepare(sv_state s, const double *b, int q_lo, int m, int mode)
                 hipLaunchKernelGGL(k_zero<double>, dim3(grid_of(dim)), dim3(256), 0, s->stream, (double2 *)s->data,
                                    dim);
         }
-        TraceScope ts(s->stream, "qsp_tree", (double)R * amp_bytes(s->dt), 0.0);
+        // algorithmic bytes: the register written once, its (cos, sin) tree and phase table read once
+        TraceScope ts(s->stream, "qsp_tree", (double)R * (2.0 * amp_bytes(s->dt) + amp_bytes(s->dt)), 0.0);
         const uint64_t nsub = R >> (m < 5 ? m : 5);
-        const dim3 g((unsigned)((nsub + 255) / 256 < (1u << 20) ? (nsub + 255) / 256 : (1u << 20)));
+        const uint64_t nblk = (nsub + QSP_NT - 1) / QSP_NT;
+        const dim3 g((unsigned)(nblk < (1u << 20) ? nblk : (1u << 20)));
 #define SV_QSP_LAUNCH(Cb)                                                                                       \
     do {                                                                                                        \
         if (f32)                                                                                                \
-            hipLaunchKernelGGL((k_qsp_tree<float, Cb>), g, dim3(256), 0, s->stream, (float2 *)s->data, q_lo, m,  \
+            hipLaunchKernelGGL((k_qsp_tree<float, Cb>), g, dim3(QSP_NT), 0, s->stream, (float2 *)s->data, q_lo, m, \
                                (const float *)dcs, (const float2 *)dph);                                       \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_qsp_tree<double, Cb>), g, dim3(256), 0, s->stream, (double2 *)s->data, q_lo, m, \
+            hipLaunchKernelGGL((k_qsp_tree<double, Cb>), g, dim3(QSP_NT), 0, s->stream, (double2 *)s->data, q_lo, m, \
                                (const double *)dcs, (const double2 *)dph);                                     \
     } while (0)
         switch (m < 5 ? m : 5) {
