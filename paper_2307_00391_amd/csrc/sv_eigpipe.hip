@@ -590,12 +590,6 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
         }
     }
     __syncthreads();
-    cvec<R> twr[(1 << RA) - 1], ttr[(1 << RA) - 1];   // phase-A twiddles (fixed by register position)
-#pragma unroll
-    for (int i = 0; i < (1 << RA) - 1; ++i) {
-        twr[i] = TW[i];
-        ttr[i] = TT[i];
-    }
     for (int it = 0; it < iters; ++it) {
         // phase B first: the forward cascade starts at the top bit of G1
         for (int line = threadIdx.x; line < nlb; line += NT) {
@@ -645,29 +639,34 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
             const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll
             for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
+            // the phase-A twiddles come from the LDS tables line by line (the
+            // empty barrier keeps the compiler from hoisting them into
+            // registers for the whole loop, which the persistent form cannot spare)
+            asm volatile("" ::: "memory");
             if (RA > 1)
-                fwd_cascade<R, RA, RA - 1, 1, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
+                fwd_cascade<R, RA, RA - 1, 1, 0>(v, TW, TT, [&](int jb, int k) { return k & ((1 << jb) - 1); });
             // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
-            cvec<R> ph[1 << (RA - 1)];
             cvec<R> base = cc[c];
             for (int b = 0; b < RB; ++b)
                 if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-            ph[0] = base;
-#pragma unroll
-            for (int b = 1; b < RA; ++b) {
-                const cvec<R> w = om[b * C + c];
-#pragma unroll
-                for (int k = 0; k < (1 << (b - 1)); ++k) ph[k | (1 << (b - 1))] = cmul<R>(ph[k], w);
-            }
-            // the last forward stage (group bit 0, no twiddle) and the phase of
-            // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0))
             const cvec<R> w0 = om[c];
             const cvec<R> up = cmake<R>((R)1 + w0.x, w0.y), um = cmake<R>((R)1 - w0.x, -w0.y);
+            // the last forward stage (group bit 0, no twiddle) and the phase of
+            // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0));
+            // the conj phase p of the pair m (bits 1.. of k) is carried along the
+            // Gray-code order of m, one factor (or its conjugate) per step
             R lr = 0, li = 0;                // the line's sum, then FP64
+            cvec<R> ph = base;
 #pragma unroll
-            for (int m = 0; m < (1 << (RA - 1)); ++m) {
+            for (int g = 0; g < (1 << (RA - 1)); ++g) {
+                const int m = g ^ (g >> 1);
+                if (g > 0) {
+                    const int t = __builtin_ctz(g);
+                    const cvec<R> w = om[(t + 1) * C + c];
+                    ph = (m >> t & 1) ? cmul<R>(ph, w) : cconjmul<R>(ph, w);
+                }
                 const cvec<R> a = cmac2<R>(up, v[2 * m], um, v[2 * m + 1]);
-                const cvec<R> p = cmul<R>(a, ph[m]);
+                const cvec<R> p = cmul<R>(a, ph);
                 lr += p.x;
                 li += p.y;
             }
