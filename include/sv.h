@@ -445,9 +445,10 @@ sv_status sv_qlsa2(sv_state s, const double *A, const double *b, const sv_qlsa2_
                    sv_qlsa2_result *res, double *z_out);
 
 typedef struct {
-    int n_s;        /* system qubits (1..13) */
-    int sy, sz;     /* select registers: j < 2^sy, and m < 2^sz for z_k (sy + sz <= 30) */
+    int n_s;        /* system qubits (1..13; 1..10 in mode 0) */
+    int sy, sz;     /* select registers: j < 2^sy, and m < 2^sz for z_k (sy + sz <= 30; <= 24 in mode 0) */
     double dy, dz;  /* grid steps of the two integrals */
+    int mode;       /* 0: the circuit in the computational basis; 1: the eigen frame */
 } sv_qlsa2f_params;
 
 /* QLSA-2 in Fourier form: the integral representation
@@ -459,12 +460,19 @@ typedef struct {
  * n_s + sy + sz qubits: bits [0, n_s) system, [n_s, n_s + sy) the j register,
  * [n_s + sy, n_s + sy + sz) the m register.  The circuit (PREP with
  * sqrt(w / |w|_1), SELECT, PREP^dagger, post-selection of select = 0) runs
- * with the system register in the eigenbasis of A: one pass writes the state
- * after SELECT, one FP64 reduction forms the select = 0 projection.
+ *   mode 0: gate by gate in the computational basis: PREP and PREP^dagger as
+ *           the QSP-1 tree of uniformly controlled Ry passes; SELECT as
+ *           diag(i, -i) on the top m qubit (the factor i sign(z)) and, since
+ *           j k is bilinear in the bits of j and m, sy (sz + 1) singly or
+ *           doubly controlled dense exp(-i A~ dy dz t) on the matrix cores;
+ *           the state holds the final circuit state afterwards;
+ *   mode 1: with the system register in the eigenbasis of A: one pass writes
+ *           the state after SELECT, one FP64 reduction forms the select = 0
+ *           projection; the state's contents are unspecified afterwards.
  * z_out as in sv_qlsa2: z = h(A~) b^ / |w|_1 in the computational basis,
  * p_post = |z|^2; alpha_l1 of the result holds |w|_1.  Synchronises the stream.
  * Errors: SV_EINVAL (sizes, steps, A = 0), SV_ENOTHERMITIAN, SV_EZERONORM,
- * SV_ENOMEM, SV_EDEVICE. */
+ * SV_EUNSUPPORTED (mode 0 beyond its sizes), SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const sv_qlsa2f_params *prm,
                            sv_qlsa2_result *res, double *z_out);
 

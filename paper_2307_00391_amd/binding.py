@@ -63,7 +63,7 @@ class sv_gpe_params(ctypes.Structure):
 
 class sv_qlsa2f_params(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int), ("sy", ctypes.c_int), ("sz", ctypes.c_int), ("dy", ctypes.c_double),
-                ("dz", ctypes.c_double)]
+                ("dz", ctypes.c_double), ("mode", ctypes.c_int)]
 
 
 class sv_batch_instance(ctypes.Structure):
@@ -365,13 +365,13 @@ def sv_gapped_pe(h, A, b, n_c, T0, cut, mode=1, signed_clock=0):
     return x, res
 
 
-def sv_qlsa2_fourier(h, A, b, sy, sz, dy, dz):
+def sv_qlsa2_fourier(h, A, b, sy, sz, dy, dz, mode=1):
     """QLSA-2 in Fourier form: returns (z, result), z as in sv_qlsa2."""
     A, Af = _f64(A)
     b, bf = _f64(b)
     N = A.shape[0]
     n_s = N.bit_length() - 1
-    prm = sv_qlsa2f_params(n_s, int(sy), int(sz), float(dy), float(dz))
+    prm = sv_qlsa2f_params(n_s, int(sy), int(sz), float(dy), float(dz), int(mode))
     res = sv_qlsa2_result()
     z = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_qlsa2_fourier(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(z)),

@@ -178,14 +178,12 @@ template sv_status cgemm<double>(hipStream_t, const double2 *, double2 *, const 
                                  uint64_t, uint64_t, int, int);
 
 template <typename R>
-sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint) {
+sv_status ctrl_mask_unitary_impl(sv_state s, const cvec<R> *U, int m, uint64_t cmask, uint64_t cval, int adjoint) {
     const uint64_t all = (s->n >= 64) ? ~0ull : ((1ull << s->n) - 1ull);
-    uint64_t row_mask = all & ~((1ull << m) - 1ull);
-    uint64_t row_fix = 0;
-    if (ctrl >= 0) {
-        row_mask &= ~(1ull << ctrl);
-        row_fix = (uint64_t)(ctrl_val ? 1 : 0) << ctrl;
-    }
+    // rows: every value of the bits outside the register and the controls,
+    // with the controls fixed to cval
+    const uint64_t row_mask = all & ~((1ull << m) - 1ull) & ~cmask;
+    const uint64_t row_fix = cval & cmask;
     const uint64_t M = dim_of(popcount64(row_mask));
     const int N = 1 << m;
     SV_TRY(ensure_scratch(s, (size_t)M * N * sizeof(cvec<R>)));
@@ -201,6 +199,14 @@ sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int c
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
+}
+template sv_status ctrl_mask_unitary_impl<float>(sv_state, const float2 *, int, uint64_t, uint64_t, int);
+template sv_status ctrl_mask_unitary_impl<double>(sv_state, const double2 *, int, uint64_t, uint64_t, int);
+
+template <typename R>
+sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint) {
+    const uint64_t cm = ctrl >= 0 ? 1ull << ctrl : 0ull;
+    return ctrl_mask_unitary_impl<R>(s, U, m, cm, ctrl_val ? cm : 0ull, adjoint);
 }
 template sv_status ctrl_unitary_impl<float>(sv_state, const float2 *, int, int, int, int);
 template sv_status ctrl_unitary_impl<double>(sv_state, const double2 *, int, int, int, int);

@@ -40,6 +40,8 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
                 uint64_t row_mask, uint64_t row_fix, int trans, int conjb);
 template <typename R>
 sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
+template <typename R>
+sv_status ctrl_mask_unitary_impl(sv_state s, const cvec<R> *U, int m, uint64_t cmask, uint64_t cval, int adjoint);
 
 static unsigned grid_for(uint64_t items) {
     uint64_t g = (items + 255) / 256;
@@ -283,6 +285,78 @@ __global__ __launch_bounds__(256) void k_fourier_select(cvec<R> *__restrict__ ps
 }
 
 template <typename R>
+__global__ void k_round_unitary(cvec<R> *__restrict__ out, const double2 *__restrict__ in, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = cmake<R>((R)in[i].x, (R)in[i].y);
+}
+
+// Fourier form, gate by gate in the computational basis.  With k = m + 1
+// (m < K) or m - 2K written as k = sum_{b < sz-1} m_b 2^b + 1 - m_top (2^(sz-1) + 1),
+// j k is bilinear in the bits of j and m, so SELECT = diag(i, -i) on m_top (the
+// factor i sign(z)) times, for each bit a of j,
+//   controlled on j_a:          V(2^a)
+//   controlled on j_a and m_b:  V(2^(a+b))            (b < sz - 1)
+//   controlled on j_a and m_top: V(-2^a (2^(sz-1) + 1))
+// with V(t) = exp(-i A~ dy dz t) = V_A diag(exp(-i lambda~ dy dz t)) V_A^H, built
+// in FP64 on the device from phases reduced in long double.
+template <typename R>
+static sv_status run_fourier_gates(sv_state s, int n_s, int sy, int sz, double dy, double dz, const DevBuf &dV,
+                                   const std::vector<double> &lamt, const std::vector<double> &pm, const double *b) {
+    const int N = 1 << n_s, S = sy + sz;
+    const hipStream_t st = s->stream;
+    const uint64_t NN = (uint64_t)N * N;
+    DevBuf dE, W, P, Uk;
+    SV_TRY(dE.alloc(N * sizeof(double2)));
+    SV_TRY(W.alloc(NN * sizeof(double2)));
+    SV_TRY(P.alloc(NN * sizeof(double2)));
+    SV_TRY(Uk.alloc(NN * sizeof(cvec<R>)));
+    std::vector<double> E(2 * (size_t)N);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    auto build = [&](long double t) -> sv_status {
+        for (int k = 0; k < N; ++k) {
+            long double a = -(long double)lamt[k] * (long double)dy * (long double)dz * t;
+            a = fmodl(a, two_pi);
+            E[2 * k] = (double)cosl(a);
+            E[2 * k + 1] = (double)sinl(a);
+        }
+        SV_TRY(upload(s, dE.p, E.data(), E.size() * sizeof(double)));
+        hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(NN)), dim3(256), 0, st, (double2 *)W.p, (const double2 *)dV.p,
+                           (const double2 *)dE.p, N);
+        SV_HIP(hipGetLastError());
+        SV_TRY(cgemm<double>(st, (const double2 *)W.p, (double2 *)P.p, (const double2 *)dV.p, (uint64_t)N, N, N,
+                             (uint64_t)(N - 1) << n_s, 0, 0, 1));
+        hipLaunchKernelGGL(k_round_unitary<R>, dim3(grid_for(NN)), dim3(256), 0, st, (cvec<R> *)Uk.p,
+                           (const double2 *)P.p, NN);
+        SV_HIP(hipGetLastError());
+        return SV_OK;
+    };
+    std::vector<double> amp((size_t)1 << S);
+    for (size_t r = 0; r < amp.size(); ++r) amp[r] = pm[r >> sy];
+    SV_TRY(sv_init_b(s, b, n_s, 0));
+    SV_TRY(tree_circuit(s, amp, n_s, S, false));
+    const int top = n_s + S - 1;
+    static const double SG[8] = {0, 1, 0, 0, 0, 0, 0, -1};
+    SV_TRY(sv_apply_gate(s, top, SG, nullptr, nullptr, 0));
+    const cvec<R> *U = (const cvec<R> *)Uk.p;
+    for (int a = 0; a < sy; ++a) {
+        const uint64_t cj = 1ull << (n_s + a);
+        SV_TRY(build(ldexpl(1.0L, a)));
+        SV_TRY(ctrl_mask_unitary_impl<R>(s, U, n_s, cj, cj, 0));
+        for (int bb = 0; bb + 1 < sz; ++bb) {
+            const uint64_t cm = cj | (1ull << (n_s + sy + bb));
+            SV_TRY(build(ldexpl(1.0L, a + bb)));
+            SV_TRY(ctrl_mask_unitary_impl<R>(s, U, n_s, cm, cm, 0));
+        }
+        const uint64_t ct = cj | (1ull << top);
+        SV_TRY(build(-ldexpl(1.0L, a) * (ldexpl(1.0L, sz - 1) + 1.0L)));
+        SV_TRY(ctrl_mask_unitary_impl<R>(s, U, n_s, ct, ct, 0));
+    }
+    SV_TRY(tree_circuit(s, amp, n_s, S, true));
+    SV_HIP(hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+template <typename R>
 static sv_status run_fourier(sv_state s, int n_s, int sy, int sz, double dy, double dz, const DevBuf &dV,
                              const std::vector<double> &lamt, const std::vector<uint64_t> &F,
                              const std::vector<double> &pr, const std::vector<double> &bhat, double2 *z_dev) {
@@ -484,6 +558,9 @@ sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const s
         return fail(SV_EINVAL, "n_s %d + sy %d + sz %d != %d qubits (1 <= n_s <= 13)", n_s, sy, sz, s->n);
     if (!(prm->dy > 0.0) || !(prm->dz > 0.0) || !isfinite(prm->dy) || !isfinite(prm->dz))
         return fail(SV_EINVAL, "dy and dz must be positive");
+    if (prm->mode != 0 && prm->mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    if (prm->mode == 0 && (n_s > 10 || sy + sz > 24))
+        return fail(SV_EUNSUPPORTED, "gate-level mode with n_s = %d > 10 or sy + sz = %d > 24", n_s, sy + sz);
     const int N = 1 << n_s;
     SV_TRY(check_hermitian(A, N, "A"));
     double bn = 0.0;
@@ -529,17 +606,30 @@ sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const s
     res->lambda_abs_max = lmax;
     res->lambda_abs_min = lmin;
     res->alpha_l1 = l1;
-    DevBuf dz;
-    SV_TRY(dz.alloc(N * sizeof(double2)));
-    if (s->dt == SV_C64)
-        SV_TRY(run_fourier<float>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
-    else
-        SV_TRY(run_fourier<double>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
     std::vector<double> z(2 * (size_t)N);
-    SV_TRY(download(s, z.data(), dz.p, N * sizeof(double2)));
-    double p = 0.0;
-    for (int j = 0; j < 2 * N; ++j) p += z[j] * z[j];
-    res->p_post = p;
+    if (prm->mode == 0) {
+        if (s->dt == SV_C64)
+            SV_TRY(run_fourier_gates<float>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, pr, bhat.data()));
+        else
+            SV_TRY(run_fourier_gates<double>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, pr, bhat.data()));
+        // the select = 0 block: the first 2^n_s amplitudes
+        double p = 0.0;
+        SV_TRY(sv_postselect(s, ((1ull << (sy + sz)) - 1ull) << n_s, 0, &p, z.data(), 0));
+        const double sp = sqrt(p);
+        for (double &v : z) v *= sp;
+        res->p_post = p;
+    } else {
+        DevBuf dz;
+        SV_TRY(dz.alloc(N * sizeof(double2)));
+        if (s->dt == SV_C64)
+            SV_TRY(run_fourier<float>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
+        else
+            SV_TRY(run_fourier<double>(s, n_s, sy, sz, prm->dy, prm->dz, dV, lamt, F, pr, bhat, (double2 *)dz.p));
+        SV_TRY(download(s, z.data(), dz.p, N * sizeof(double2)));
+        double p = 0.0;
+        for (int j = 0; j < 2 * N; ++j) p += z[j] * z[j];
+        res->p_post = p;
+    }
     if (z_out)
         for (int j = 0; j < 2 * N; ++j) z_out[j] = z[j];
     return SV_OK;

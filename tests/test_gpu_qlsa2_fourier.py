@@ -1,5 +1,6 @@
-"""GPU parity of QLSA-2 in Fourier form (the eigen-frame library path) against
-the oracle's gate-by-gate circuit, complex128 and complex64, over Hermitian
+"""GPU parity of QLSA-2 in Fourier form against the oracle's gate-by-gate
+circuit: the eigen-frame path (mode 1) and the circuit in the computational
+basis (mode 0, the whole final state), complex128 and complex64, over Hermitian
 kinds, register widths from one system qubit up to 2^9 system states (the
 partial-sum reduction with more than one column block); at the Poiseuille
 sizes (27 and 29 qubits) against the spectral sum h(lambda~) = sum_r w_r
@@ -139,6 +140,56 @@ def test_fourier_poiseuille_29_qubits_inverse_property(dt):
     assert np.abs(prof - want).max() <= 1e-3
 
 
+def _tol_gates(dt, scale, n_s, sy, sz, dy, dz):
+    """Mode 0 applies sy (sz + 1) dense unitaries rounded to the state's
+    precision: complex64 adds 2^-24 sqrt(2^n_s) per unitary to the bar."""
+    if dt == "c128":
+        return _tol(dt, scale, sy, sz, dy, dz)
+    return _tol(dt, scale, sy, sz, dy, dz) + sy * (sz + 1) * 2.0 ** (n_s / 2) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kind", ["spd", "indefinite", "complex"])
+@pytest.mark.parametrize("n_s,sy,sz,dy,dz", [(1, 1, 1, 0.7, 0.9), (3, 4, 4, 0.3, 0.4), (4, 5, 3, 0.25, 0.2),
+                                             (2, 2, 6, 0.4, 0.15)])
+def test_fourier_gates_full_state_matches_oracle(dt, kind, n_s, sy, sz, dy, dz):
+    """Mode 0 (the circuit in the computational basis) against the oracle's
+    gate-by-gate circuit: the whole final state, z and p_post."""
+    rng = np.random.default_rng(11 * n_s + sy + 5 * sz + len(kind))
+    N = 1 << n_s
+    A = _matrix(kind, rng, N)
+    b = rng.standard_normal(N) + (1j * rng.standard_normal(N) if kind == "complex" else 0)
+    print(f"[fourier gates] {dt} {kind} n_s {n_s} sy {sy} sz {sz}", flush=True)
+    psi_ref, z_ref, p_ref = oracle.qlsa2_fourier(A, b, sy, sz, dy, dz)
+    st = B.State(n_s + sy + sz, dt)
+    try:
+        z, res = B.sv_qlsa2_fourier(st.h, A, b, sy, sz, dy, dz, mode=0)
+        psi = st.get()
+    finally:
+        st.close()
+    tol = _tol_gates(dt, np.abs(psi_ref).max(), n_s, sy, sz, dy, dz)
+    assert np.abs(psi - psi_ref).max() <= tol
+    assert np.abs(z - z_ref).max() <= _tol_gates(dt, np.abs(z_ref).max(), n_s, sy, sz, dy, dz)
+    assert abs(res.p_post - p_ref) <= 4 * tol * math.sqrt(N) * (1 + math.sqrt(p_ref))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_fourier_gates_and_eigen_frame_agree(dt):
+    """n_s = 6, 2^10 select values (16 qubits): the two library modes."""
+    rng = np.random.default_rng(3)
+    n_s, sy, sz, dy, dz = 6, 5, 5, 0.35, 0.12
+    A = _matrix("indefinite", rng, 1 << n_s)
+    b = rng.standard_normal(1 << n_s)
+    out = []
+    for mode in (0, 1):
+        st = B.State(n_s + sy + sz, dt)
+        try:
+            out.append(B.sv_qlsa2_fourier(st.h, A, b, sy, sz, dy, dz, mode=mode)[0])
+        finally:
+            st.close()
+    assert np.abs(out[0] - out[1]).max() <= _tol_gates(dt, np.abs(out[1]).max(), n_s, sy, sz, dy, dz)
+
+
 def test_fourier_errors():
     A = np.diag([1.0, 2.0, 3.0, 4.0])
     b = np.ones(4)
@@ -154,5 +205,14 @@ def test_fourier_errors():
             B.sv_qlsa2_fourier(st.h, A + np.triu(np.ones((4, 4)), 1), b, 2, 2, 0.1, 0.1)
         with pytest.raises(B.SvError):
             B.sv_qlsa2_fourier(st.h, A, np.zeros(4), 2, 2, 0.1, 0.1)
+        with pytest.raises(B.SvError):
+            B.sv_qlsa2_fourier(st.h, A, b, 2, 2, 0.1, 0.1, mode=2)
+    finally:
+        st.close()
+    big = np.diag(np.arange(1.0, 2049.0))
+    st = B.State(11 + 1 + 1, "c64")
+    try:
+        with pytest.raises(B.SvError):                                   # mode 0 with n_s = 11
+            B.sv_qlsa2_fourier(st.h, big, np.ones(2048), 1, 1, 0.1, 0.1, mode=0)
     finally:
         st.close()
