@@ -291,6 +291,17 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
  * not overlap. */
 sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm,
                      sv_hhl_result *res, double *x_out);
+/* sv_hhl_run with the right-hand side and the solution in device memory, so
+ * that a solve moves no vector over PCIe: b_dev is a device array of 2^n_s
+ * complex FP64 (interleaved, need not be normalised; its norm is reduced on
+ * the device), x_dev (may be NULL) a device array of 2^n_s complex FP64 that
+ * receives the normalised post-selected vector; both are borrowed and stay on
+ * the state's stream.  Only the result scalars are copied back (the call
+ * synchronises the stream).  Modes 1 and 2 only (mode 0 starts from a host
+ * b); other arguments, results and errors as sv_hhl_run, with SV_EUNSUPPORTED
+ * for mode 0 and SV_EZERONORM when |b| = 0 or p_post = 0. */
+sv_status sv_hhl_run_device(sv_hhl_plan p, sv_state s, const void *b_dev, const sv_hhl_params *prm,
+                            sv_hhl_result *res, void *x_dev);
 /* Smallest and largest eigenvalue of the prepared operator (FP64). */
 sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda_max);
 sv_status sv_hhl_plan_free(sv_hhl_plan p);

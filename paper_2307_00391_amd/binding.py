@@ -113,6 +113,7 @@ _SIGS = {
     "sv_lcu_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_qlsa2": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_qlsa2_fourier": ([_P, _P, _P, _P, _P, _P], _I),
+    "sv_hhl_run_device": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_gapped_pe": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
@@ -441,6 +442,19 @@ def sv_hhl_run(plan, h, b, n_c, T0, mode=1, signed_clock=False):
     x = np.zeros(b.size, dtype=np.complex128)
     _check(lib().sv_hhl_run(plan, h, _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)), "sv_hhl_run")
     return x, res
+
+
+def sv_hhl_run_device(plan, h, b_dev, n_c, T0, mode=1, signed_clock=False, x_dev=None):
+    """sv_hhl_run with b and x as device tensors (complex128, 2^n_s entries, on
+    the state's device); returns the result (x lands in x_dev when given)."""
+    n = int(b_dev.numel())
+    n_s = n.bit_length() - 1
+    prm = sv_hhl_params(n_s, int(n_c), float(T0), int(mode), int(bool(signed_clock)))
+    res = sv_hhl_result()
+    xp = ctypes.c_void_p(x_dev.data_ptr()) if x_dev is not None else None
+    _check(lib().sv_hhl_run_device(plan, h, ctypes.c_void_p(b_dev.data_ptr()), ctypes.byref(prm), ctypes.byref(res),
+                                   xp), "sv_hhl_run_device")
+    return res
 
 
 def sv_hhl_plan_spectrum(plan):

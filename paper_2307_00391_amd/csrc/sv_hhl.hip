@@ -596,11 +596,31 @@ struct Workspace {
 
 static sv_status need(DevBuf &b, size_t bytes) { return b.ensure(bytes); }
 static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
-                            double *x_out);
+                            double *x_out, bool dev, double2 *x_dev);
+
+// |v|^2 of an FP64 complex device vector, one workgroup, fixed order
+__global__ __launch_bounds__(256) void k_vec_norm2(const double2 *__restrict__ v, uint64_t n, double *__restrict__ out) {
+    __shared__ double red[4];
+    double a = 0.0;
+    for (uint64_t i = threadIdx.x; i < n; i += 256) a += v[i].x * v[i].x + v[i].y * v[i].y;
+    a = wave_sum_f64(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out = in / sqrt(nrm[0]) (nrm on the device)
+__global__ void k_vec_normalise(double2 *__restrict__ out, const double2 *__restrict__ in, uint64_t n,
+                                const double *__restrict__ nrm) {
+    const double sc = 1.0 / sqrt(nrm[0]);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = make_double2(in[i].x * sc, in[i].y * sc);
+}
 
 template <typename R>
 static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, const std::vector<double> &bhat, int n_c, bool sgn,
-                               uint64_t gcut, double T0, bool fused, sv_hhl_result *res, double *x_out) {
+                               uint64_t gcut, double T0, bool fused, sv_hhl_result *res, double *x_out,
+                               const double2 *b_dev = nullptr, double2 *x_dev = nullptr) {
     const int n_s = E.n_s;
     const uint64_t N = dim_of(n_s);
     const int anc = n_s + n_c;
@@ -626,7 +646,16 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     hipLaunchKernelGGL(k_turn_table, dim3(grid1(N * n_c)), dim3(256), 0, st, (uint64_t *)w.F.p,
                        (const double *)E.lam_dev.p, T0, n_c, N);
     SV_HIP(hipGetLastError());
-    SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
+    const bool dev = b_dev != nullptr;
+    if (dev) {
+        // b on the device: its norm (w.sum[2]) and b^ there
+        hipLaunchKernelGGL(k_vec_norm2, dim3(1), dim3(256), 0, st, b_dev, N, (double *)w.sum.p + 2);
+        hipLaunchKernelGGL(k_vec_normalise, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.x.p, b_dev, N,
+                           (const double *)w.sum.p + 2);
+        SV_HIP(hipGetLastError());
+    } else {
+        SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
+    }
     // beta = V^H b^
     SV_TRY(kron_apply_frame(s, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, E, 1));
 
@@ -650,7 +679,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.z.p,
                            (const double2 *)w.zpart.p, N, rows, exp2(-0.5 * (n_c + g1)));
         SV_HIP(hipGetLastError());
-        return eig_finish(s, E, w, N, res, x_out);
+        return eig_finish(s, E, w, N, res, x_out, dev, x_dev);
     }
     std::vector<double> cs;
     inversion_table(n_c, cs, sgn, gcut);
@@ -687,14 +716,30 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     hipLaunchKernelGGL(k_sum_cols, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.z.p, (const double2 *)w.zpart.p, N,
                        (int)(g2.y * 4), 1.0 / sqrt((double)(1ull << n_c)));
     SV_HIP(hipGetLastError());
-    return eig_finish(s, E, w, N, res, x_out);
+    return eig_finish(s, E, w, N, res, x_out, dev, x_dev);
 }
 
 // x = V z on the device, then P(a=1, clock=0) = |z|^2 and the normalised x on the host
 static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
-                            double *x_out) {
+                            double *x_out, bool dev, double2 *x_dev) {
     const hipStream_t st = s->stream;
     SV_TRY(kron_apply_frame(s, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, E, 0));
+    if (dev) {
+        // p = |x|^2 (w.sum[3]) and the normalised x on the device; only the scalars come back
+        hipLaunchKernelGGL(k_vec_norm2, dim3(1), dim3(256), 0, st, (const double2 *)w.x.p, N, (double *)w.sum.p + 3);
+        if (x_dev)
+            hipLaunchKernelGGL(k_vec_normalise, dim3(grid1(N)), dim3(256), 0, st, x_dev, (const double2 *)w.x.p, N,
+                               (const double *)w.sum.p + 3);
+        SV_HIP(hipGetLastError());
+        std::vector<double> sums(4);
+        SV_TRY(download(s, sums.data(), w.sum.p, 4 * sizeof(double)));
+        res->p_post = sums[3];
+        res->p_anc = sums[0];
+        res->norm_total = sums[1];
+        if (!(sums[2] > 0.0) || !isfinite(sums[2])) return fail(SV_EZERONORM, "|b| = 0 or not finite");
+        if (!(sums[3] > 0.0)) return fail(SV_EZERONORM, "post-selected outcome has probability 0");
+        return SV_OK;
+    }
     std::vector<double> sums(2), xz(2 * N);
     SV_TRY(download(s, sums.data(), w.sum.p, 2 * sizeof(double)));
     SV_TRY(download(s, xz.data(), w.x.p, N * sizeof(double2)));
@@ -871,15 +916,17 @@ sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda
 // gapped-phase-estimation flag (which allows a zero eigenvalue on a signed
 // clock and lambda_min = 0 on an unsigned one)
 static sv_status hhl_run_impl(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_params *prm, uint64_t gcut,
-                              sv_hhl_result *res, double *x_out) {
+                              sv_hhl_result *res, double *x_out, const double2 *b_dev = nullptr,
+                              double2 *x_dev = nullptr) {
     if (!p) return fail(SV_EINVAL, "null plan");
     SV_TRY(check_state(s));
     SV_TRY(check_params(s, prm, res));
-    if (!b) return fail(SV_EINVAL, "b is NULL");
+    if (!b && !b_dev) return fail(SV_EINVAL, "b is NULL");
     if (prm->n_s != p->E.n_s) return fail(SV_EINVAL, "plan has n_s = %d, params n_s = %d", p->E.n_s, prm->n_s);
+    if (b_dev && prm->mode == 0) return fail(SV_EUNSUPPORTED, "device-resident b and x need mode 1 or 2");
     const uint64_t N = dim_of(p->E.n_s);
     std::vector<double> bhat;
-    SV_TRY(normalise_b(b, N, bhat));
+    if (!b_dev) SV_TRY(normalise_b(b, N, bhat));
     SV_TRY(sv_hhl_plan_spectrum(p, &res->lambda_min, &res->lambda_max));
     const bool sgn = prm->signed_clock == 1;
     if (gcut == 0) {
@@ -894,8 +941,10 @@ static sv_status hhl_run_impl(sv_hhl_plan p, sv_state s, const double *b, const 
     if (prm->mode >= 1) {
         const bool fused = prm->mode == 1;
         return s->dt == SV_C64
-                   ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out)
-                   : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out);
+                   ? eig_frame_run<float>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out,
+                                          b_dev, x_dev)
+                   : eig_frame_run<double>(s, p->E, p->w, bhat, prm->n_c, sgn, gcut, prm->T0, fused, res, x_out,
+                                           b_dev, x_dev);
     }
     // gate-faithful: dense eigenvectors
     if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
@@ -920,6 +969,13 @@ sv_status sv_hhl_run(sv_hhl_plan p, sv_state s, const double *b, const sv_hhl_pa
                      double *x_out) {
     clear_error();
     return hhl_run_impl(p, s, b, prm, 0, res, x_out);
+}
+
+sv_status sv_hhl_run_device(sv_hhl_plan p, sv_state s, const void *b_dev, const sv_hhl_params *prm,
+                            sv_hhl_result *res, void *x_dev) {
+    clear_error();
+    if (!b_dev) return fail(SV_EINVAL, "b_dev is NULL");
+    return hhl_run_impl(p, s, nullptr, prm, 0, res, nullptr, (const double2 *)b_dev, (double2 *)x_dev);
 }
 
 sv_status sv_hhl_plan_free(sv_hhl_plan p) {

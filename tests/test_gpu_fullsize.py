@@ -36,8 +36,10 @@ def _free_mem():
     return torch.cuda.mem_get_info()[0]
 
 
-@pytest.mark.parametrize("dt,tol,mode", [("c64", 1e-5, 1), ("c128", 1e-12, 1), ("c64", 1e-5, 2)])
-def test_hhl_32_qubits_against_closed_form(dt, tol, mode):
+@pytest.mark.parametrize("dt,tol,mode,device", [("c64", 1e-5, 1, True), ("c64", 1e-5, 1, False),
+                                                ("c128", 1e-12, 1, False), ("c64", 1e-5, 2, False)])
+def test_hhl_32_qubits_against_closed_form(dt, tol, mode, device):
+    """device: b and x in HBM (sv_hhl_run_device), as the benchmark times it."""
     m_hi = m_lo = 8
     n_c = 15
     n = m_hi + m_lo + n_c + 1
@@ -48,7 +50,14 @@ def test_hhl_32_qubits_against_closed_form(dt, tol, mode):
     T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
     st = B.State(n, dt)
     plan = B.sv_hhl_prepare(st.h, ks.A_hi, ks.A_lo)
-    x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, mode)
+    if device:
+        import torch
+        b_dev = torch.tensor(np.asarray(ks.b, dtype=np.complex128), device="cuda")
+        x_dev = torch.empty(1 << (m_hi + m_lo), dtype=torch.complex128, device="cuda")
+        res = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, mode, x_dev=x_dev)
+        x = x_dev.cpu().numpy()
+    else:
+        x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, mode)
     B.sv_hhl_plan_free(plan)
     st.close()
     # eigen-basis view of the GPU result: z = V^H x sqrt(p)

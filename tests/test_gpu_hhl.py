@@ -218,3 +218,44 @@ def test_hhl_error_paths():
     with pytest.raises(B.SvError) as e:
         B.sv_hhl(st.h, A, np.ones(8), 3, 0.1)      # 3 + 3 + 1 != 8 qubits
     assert e.value.status == B.SV_EINVAL
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("kron", [True, False])
+def test_hhl_run_device_matches_host_buffers(dt, mode, kron):
+    """sv_hhl_run_device (b and x in HBM) against sv_hhl_run (host buffers):
+    the same solve, so x and the probabilities agree to rounding; b need not
+    be normalised."""
+    import torch
+    rng = np.random.default_rng(40 + mode + 2 * kron)
+    n_c = 8
+    if kron:
+        ks = inputs.kron_laplacian_system(rng, 4, 3, kappa=200.0)
+        n_s, A_hi, A_lo, b = 7, ks.A_hi, ks.A_lo, 3.0 * ks.b
+        T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
+    else:
+        A, _, lmax = inputs.random_spd_tridiag(rng, 32, 30.0)
+        n_s, A_hi, A_lo, b = 5, A, None, rng.standard_normal(32) + 1j * rng.standard_normal(32)
+        T0 = inputs.t0_top_of_clock(lmax, n_c)
+    st = B.State(n_s + n_c + 1, dt)
+    plan = B.sv_hhl_prepare(st.h, A_hi, A_lo)
+    try:
+        x_h, r_h = B.sv_hhl_run(plan, st.h, b, n_c, T0, mode)
+        b_dev = torch.tensor(np.asarray(b, dtype=np.complex128), device="cuda")
+        x_dev = torch.empty(1 << n_s, dtype=torch.complex128, device="cuda")
+        r_d = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, mode, x_dev=x_dev)
+        x_d = x_dev.cpu().numpy()
+        r_n = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, mode)           # x_dev = NULL
+        with pytest.raises(B.SvError):
+            B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, 0, x_dev=x_dev)   # mode 0 starts from a host b
+        with pytest.raises(B.SvError):
+            B.sv_hhl_run_device(plan, st.h, torch.zeros_like(b_dev), n_c, T0, mode, x_dev=x_dev)
+    finally:
+        B.sv_hhl_plan_free(plan)
+        st.close()
+    assert np.abs(x_d - x_h).max() <= TOL[dt]
+    for a, c in ((r_d, r_h), (r_n, r_h)):
+        assert abs(a.p_post - c.p_post) <= TOL[dt] * c.p_post
+        assert abs(a.p_anc - c.p_anc) <= TOL[dt] and abs(a.norm_total - c.norm_total) <= TOL[dt]
+
