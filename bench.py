@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-qsp", action="store_true")
     ap.add_argument("--no-qpp", action="store_true")
     ap.add_argument("--no-qlsa2", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -174,6 +175,31 @@ def main():
     ms_per_step = max(ms, 1e3 * t_wall) / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step")
     x = x_dev.cpu().numpy()
+    # mixed precision: the same solve on a complex128 state (FP64 amplitudes), and
+    # the complex64 result's error against it
+    mixed = None
+    if not args.no_mixed:
+        s128 = B.State(n, "c128", device=dev)
+        plan128 = B.sv_hhl_prepare(s128.h, ks.A_hi, ks.A_lo)
+        x128_dev = torch.empty(1 << n_s, dtype=torch.complex128, device=dev)
+        B.sv_hhl_run_device(plan128, s128.h, b_dev, n_c, T0, 1, x_dev=x128_dev)          # first use: tuning
+        torch.cuda.synchronize()
+        t128 = time.perf_counter()
+        r128 = B.sv_hhl_run_device(plan128, s128.h, b_dev, n_c, T0, 1, x_dev=x128_dev)
+        torch.cuda.synchronize()
+        t128 = time.perf_counter() - t128
+        x128 = x128_dev.cpu().numpy()
+        ph = np.vdot(x128, x)
+        ph = ph / abs(ph) if abs(ph) > 0 else 1.0
+        mixed = {"c128_ms_per_step": 1e3 * t128, "x_max_abs_diff_c64_vs_c128": float(np.abs(x - ph * x128).max()),
+                 "p_post_rel_diff_c64_vs_c128": abs(res.p_post - r128.p_post) / r128.p_post,
+                 "one_minus_F_c128": 1.0 - metrics.fidelity(x128, metrics.kron_solve(ks.A_hi, ks.A_lo, ks.b))}
+        B.sv_hhl_plan_free(plan128)
+        s128.close()
+        del s128
+        torch.cuda.empty_cache()
+        log(f"[bench] complex128 solve {1e3 * t128:.2f} ms; complex64 x differs by "
+            f"{mixed['x_max_abs_diff_c64_vs_c128']:.2e}")
     # the same solve from and to host buffers (PCIe included), for reference only
     t_host = time.perf_counter()
     for k in range(args.steps):
@@ -215,6 +241,7 @@ def main():
         "setup_s_eigendecomposition": t_setup,
         "traced_fraction_of_step": traced_ms / ms_per_step,
         "ms_per_step_host_buffers": ms_host,
+        "mixed_precision": mixed,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "ms_per_step": v["ms"] / args.steps,
                         "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
                     for k, v in trace.items()},
