@@ -306,6 +306,12 @@ sv_status sv_hhl_run_device(sv_hhl_plan p, sv_state s, const void *b_dev, const 
 sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda_max);
 sv_status sv_hhl_plan_free(sv_hhl_plan p);
 
+/* Gapped phase estimation on a prepared operator (sv_hhl_prepare, including
+ * the Kronecker-sum form, so n_s is bounded by the plan, not by 13): arguments,
+ * results and errors as sv_gapped_pe, with the plan's errors as sv_hhl_run. */
+sv_status sv_gapped_pe_run(sv_hhl_plan p, sv_state s, const double *b, const sv_gpe_params *prm,
+                           sv_hhl_result *res, double *x_out);
+
 /* HHL for a separable operator A = A_hi (x) I + I (x) A_lo (a Laplacian /
  * Poisson operator on a 2-D tensor grid, main text: "d-dimensional Laplace,
  * Poisson and heat equations"), A_hi 2^m_hi square acting on system bits

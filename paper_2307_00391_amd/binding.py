@@ -115,6 +115,7 @@ _SIGS = {
     "sv_qlsa2_fourier": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_hhl_run_device": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_gapped_pe": ([_P, _P, _P, _P, _P, _P], _I),
+    "sv_gapped_pe_run": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
@@ -363,6 +364,18 @@ def sv_gapped_pe(h, A, b, n_c, T0, cut, mode=1, signed_clock=0):
     x = np.zeros(N, dtype=np.complex128)
     _check(lib().sv_gapped_pe(h, _ptr(Af), _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)),
            "sv_gapped_pe")
+    return x, res
+
+
+def sv_gapped_pe_run(plan, h, b, n_c, T0, cut, mode=1, signed_clock=0):
+    """Gapped phase estimation on a prepared operator: returns (x, result)."""
+    b, bf = _f64(b)
+    n_s = b.size.bit_length() - 1
+    prm = sv_gpe_params(n_s, int(n_c), float(T0), int(mode), int(signed_clock), int(cut))
+    res = sv_hhl_result()
+    x = np.zeros(b.size, dtype=np.complex128)
+    _check(lib().sv_gapped_pe_run(plan, h, _ptr(bf), ctypes.byref(prm), ctypes.byref(res), _ptr(x)),
+           "sv_gapped_pe_run")
     return x, res
 
 

@@ -1004,18 +1004,33 @@ sv_status sv_hhl(sv_state s, const double *A, const double *b, const sv_hhl_para
     return st;
 }
 
+static sv_status gpe_check(sv_state s, const sv_gpe_params *g, sv_hhl_params &prm, sv_hhl_result *res) {
+    if (!g) return fail(SV_EINVAL, "params is NULL");
+    prm = sv_hhl_params{g->n_s, g->n_c, g->T0, g->mode, g->signed_clock};
+    SV_TRY(check_params(s, &prm, res));
+    const uint64_t top = prm.signed_clock ? (1ull << (prm.n_c - 1)) : (1ull << prm.n_c);
+    if (g->cut < 1 || g->cut >= top)
+        return fail(SV_EINVAL, "cut %llu outside [1, %llu)", (unsigned long long)g->cut, (unsigned long long)top);
+    return SV_OK;
+}
+
+sv_status sv_gapped_pe_run(sv_hhl_plan p, sv_state s, const double *b, const sv_gpe_params *g, sv_hhl_result *res,
+                           double *x_out) {
+    clear_error();
+    SV_TRY(check_state(s));
+    sv_hhl_params prm;
+    SV_TRY(gpe_check(s, g, prm, res));
+    return hhl_run_impl(p, s, b, &prm, g->cut, res, x_out);
+}
+
 sv_status sv_gapped_pe(sv_state s, const double *A, const double *b, const sv_gpe_params *g, sv_hhl_result *res,
                        double *x_out) {
     clear_error();
     SV_TRY(check_state(s));
-    if (!g) return fail(SV_EINVAL, "params is NULL");
-    const sv_hhl_params prm{g->n_s, g->n_c, g->T0, g->mode, g->signed_clock};
-    SV_TRY(check_params(s, &prm, res));
+    sv_hhl_params prm;
+    SV_TRY(gpe_check(s, g, prm, res));
     if (!A || !b) return fail(SV_EINVAL, "A/b is NULL");
-    if (prm.n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d", prm.n_s);
-    const uint64_t top = prm.signed_clock ? (1ull << (prm.n_c - 1)) : (1ull << prm.n_c);
-    if (g->cut < 1 || g->cut >= top)
-        return fail(SV_EINVAL, "cut %llu outside [1, %llu)", (unsigned long long)g->cut, (unsigned long long)top);
+    if (prm.n_s > 13) return fail(SV_EUNSUPPORTED, "dense A with n_s = %d (use sv_gapped_pe_run on a plan)", prm.n_s);
     std::vector<double> bhat;
     SV_TRY(normalise_b(b, dim_of(prm.n_s), bhat));
     sv_hhl_plan p = nullptr;

@@ -14,7 +14,7 @@ import pytest
 import oracle
 from paper_2307_00391_amd import binding as B
 from paper_2307_00391_amd import gpe, inputs
-from tests.closed_form import gpe_closed_form, gpe_weights
+from tests.closed_form import fejer, gpe_closed_form, gpe_weights
 
 pytestmark = pytest.mark.gpu
 TOL = {"c128": 1e-12, "c64": 1e-5}
@@ -133,6 +133,60 @@ def test_gpe_parameter_rule_on_an_indefinite_system():
     w = comp / np.abs(beta)
     assert np.all(w[np.abs(lam) >= 2 * eps] >= 1 - delta ** 2)
     assert np.all(w[np.abs(lam) <= eps] <= delta ** 2)
+
+
+def test_gpe_32_qubits_on_the_kronecker_operator():
+    """sv_gapped_pe_run on the benchmark's operator (2-D Laplacian on a 256 x 256
+    grid as a Kronecker sum + perturbation, kappa = 1000; n_c = 15, 32 qubits,
+    fused path, complex64): sampled eigencomponents of the flag = 1, clock = 0
+    vector against beta g with the Fejer weights g, and both probabilities."""
+    import torch
+    m_hi = m_lo = 8
+    n_c = 15
+    n = m_hi + m_lo + n_c + 1
+    if torch.cuda.mem_get_info()[0] < (1 << n) * 8 * 1.1:
+        pytest.skip("not enough device memory")
+    ks = inputs.kron_laplacian_system(inputs.rng_for(3, 0), m_hi, m_lo, kappa=1000.0)
+    T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
+    cut = 1 << 11                       # |lambda| above about 2^11 / 2^15 of the top of the clock
+    st = B.State(n, "c64")
+    plan = B.sv_hhl_prepare(st.h, ks.A_hi, ks.A_lo)
+    try:
+        x, res = B.sv_gapped_pe_run(plan, st.h, ks.b, n_c, T0, cut, 1, 0)
+    finally:
+        B.sv_hhl_plan_free(plan)
+        st.close()
+    mu, P = np.linalg.eigh(ks.A_hi)
+    nu, Q = np.linalg.eigh(ks.A_lo)
+    X = x.reshape(1 << m_hi, 1 << m_lo)
+    Z_gpu = (P.conj().T @ X @ Q.conj()) * math.sqrt(res.p_post)
+    Bm = (ks.b / np.linalg.norm(ks.b)).reshape(1 << m_hi, 1 << m_lo)
+    beta = P.conj().T @ Bm @ Q.conj()
+    lam = (mu[:, None] + nu[None, :]).ravel()
+    rng = np.random.default_rng(33)
+    idx = np.union1d(rng.choice(lam.size, size=2048, replace=False),
+                     [0, lam.size - 1, int(np.argmax(np.abs(beta).ravel()))])
+    # unsigned clock: the flagged values are y = cut .. M - 1, and the Fejer
+    # weights of one eigenphase sum to 1 over all y, so g = 1 - sum_{y < cut} K
+    M = 1 << n_c
+    ylo = np.arange(cut, dtype=np.float64) / M
+
+    def g_of(lams):
+        out = np.empty(lams.size)
+        ph = lams * T0 / (2 * math.pi)
+        for a in range(0, ph.size, 256):
+            out[a:a + 256] = 1.0 - fejer(ph[a:a + 256, None] - ylo[None, :], M).sum(axis=1)
+        return out
+
+    g = g_of(lam[idx])
+    g_chk, _ = gpe_weights(lam[idx[:8]] * T0 / (2 * math.pi), n_c, cut)
+    assert np.abs(g[:8] - g_chk).max() < 1e-12
+    z_true = beta.ravel()[idx] * g
+    assert np.abs(Z_gpu.ravel()[idx] - z_true).max() <= 1e-5
+    gall = g_of(lam)
+    ball = np.abs(beta.ravel()) ** 2
+    assert abs(res.p_anc - float(np.sum(ball * gall))) <= 1e-5
+    assert abs(res.p_post - float(np.sum(ball * gall ** 2))) <= 1e-5
 
 
 def test_gpe_errors():
