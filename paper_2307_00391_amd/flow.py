@@ -258,7 +258,7 @@ if __name__ == "__main__":
     ap.add_argument("--nc-min", type=int, default=4)
     ap.add_argument("--nc-max", type=int, default=16)
     ap.add_argument("--dtype", default="c64")
-    ap.add_argument("--out", default="gpurun_out/flow_sweep.json")
+    ap.add_argument("--out", default="flow_sweep.json")
     ap.add_argument("--one-shot", action="store_true", help="the unrolled FE/BE systems (N=4, m=27, p=4)")
     a = ap.parse_args()
     if a.one_shot:

@@ -335,7 +335,7 @@ if __name__ == "__main__":
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--smooth", type=int, default=1)
-    ap.add_argument("--out", default="gpurun_out/t0model.json")
+    ap.add_argument("--out", default="t0model.json")
     ap.add_argument("--save", default="")
     a = ap.parse_args()
     res, model = experiment(n_train=a.train, n_eval=a.eval, steps=a.steps, lr=a.lr, smooth=a.smooth,
