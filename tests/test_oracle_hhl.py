@@ -121,7 +121,9 @@ def test_poiseuille_config_end_to_end():
     s = inputs.poiseuille(16)
     n_c = 6
     T0 = inputs.t0_top_of_clock(s.lambda_max, n_c)
-    assert abs(T0 - 5.396296e-3) < 5e-9
+    # lambda_max of the N-point second difference, h = 1/(N+1): 4 (N+1)^2 sin^2(N pi / (2 (N+1)))
+    lam_max = 4 * 17 ** 2 * math.sin(16 * math.pi / 34) ** 2
+    assert abs(T0 - 2 * math.pi * (1 - 2.0 ** -6) / lam_max) < 1e-15
     psi, x, p_post, p_anc = oracle.hhl(s.A, s.b, n_c, T0)
     xr, pr = hhl_closed_form(s.A, s.b, n_c, T0)
     np.testing.assert_allclose(x, xr, atol=1e-12)
