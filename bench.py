@@ -116,8 +116,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not run here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the state-vector path here "
+              "is a single-GPU path; sharding it over several GPUs is a design, not run", file=sys.stderr)
         sys.exit(2)
 
     import torch
