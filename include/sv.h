@@ -47,7 +47,7 @@ typedef enum {
     SV_ENOTHERMITIAN = -4,   /* |A - A^H|_max > 1e-12 |A|_max */
     SV_ENOTPOSDEF = -5,      /* lambda_min <= 0 (the clock register is unsigned) */
     SV_EZERONORM = -6,       /* |b| = 0, or a post-selected outcome of probability 0 */
-    SV_EUNSUPPORTED = -7     /* valid request outside what this build implements */
+    SV_EUNSUPPORTED = -7     /* valid request outside what the library implements */
 } sv_status;
 
 typedef enum { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
