@@ -9,6 +9,7 @@ marshals numpy arrays.  `mlp` holds the FP64 reference of the T0 predictor.
 States are numpy complex128 arrays of length 2^n, qubit q = bit q of the index.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -256,3 +257,120 @@ def qlsa2_fourier(A, b, sy, sz, dy, dz):
     _check(_load().orc_qlsa2_fourier(n_s, int(sy), int(sz), float(dy), float(dz), A, b, psi, z, ctypes.byref(p)),
            "qlsa2_fourier")
     return psi, z, p.value
+
+
+def qadc_loader(zeta):
+    """U_V of the nonlinear transform (appendix "Nonlinear transform", step 2):
+    any unitary that loads the amplitudes from |0> will do; this one is the
+    real Householder reflection I - 2 v v^T / (v^T v), v = e_0 + sigma zeta,
+    sigma = +1 if zeta_0 >= 0 else -1, so U_V|0> = -sigma zeta.  It is
+    symmetric and its own inverse."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    sigma = 1.0 if zeta[0] >= 0.0 else -1.0
+    v = sigma * zeta
+    v[0] += 1.0
+    return np.eye(zeta.size) - 2.0 * np.outer(v, v) / np.dot(v, v)
+
+
+def qadc_square(u, r, avg=True):
+    """The QPP nonlinear transform sum_k u'_k |k> -> sum_k (u'_k)^2 |k>
+    (appendix "Nonlinear transform", steps 1-5), gate by gate.  u: 2^n real
+    values (normalised here); r: qubits of the phase-estimation register.
+    Qubits: ua [0, n), a1 [n, 2n), add [2n, 3n), a2 = 3n, ub [3n+1, 3n+1+r),
+    up = 3n+1+r.  Returns the final state (after U_avg = H on add if `avg`).
+
+    Step 1: H on add, then CNOT add_j -> a1_j copies the address.
+    Steps 2-3, W: U_V on ua, then the SWAP test of ua and a1 on a2 (H,
+    controlled swaps, H); the a2 = 0 part of W|0, s, 0> has probability
+    (1 + u_s^2) / 2 = sin^2(pi beta_s).
+    Step 4: phase estimation of the amplitude-estimation iterate
+    Q = -W S_0 W^dagger S_chi on ub (H, controlled Q^(2^k), inverse QFT).
+    S_chi flips the sign of a2 = 0; S_0 flips the sign of ua = 0, a1 = s,
+    a2 = 0 (the conditional phase shift of the appendix), written as CNOTs
+    add -> a1 around a phase on ua = a1 = a2 = 0.  Q's eigenphases are
+    +-beta_s, so ub holds beta_s or 1 - beta_s.
+    Step 5: Ry on up with sine -cos(2 pi y / 2^r) = 2 sin^2(pi y/2^r) - 1
+    for ub = y (u_s^2 at the exact phase), then phase estimation, W and the
+    address copy undone, so the up = 1, ancillas = 0 block holds the squares."""
+    u = np.asarray(u, dtype=np.float64)
+    N = u.size
+    n = N.bit_length() - 1
+    if N != 1 << n or n < 1 or r < 1:
+        raise ValueError("u must have 2^n >= 2 entries and r >= 1")
+    UV = qadc_loader(u / np.linalg.norm(u)).astype(np.complex128)
+    ua, a1, add = list(range(n)), list(range(n, 2 * n)), list(range(2 * n, 3 * n))
+    a2, ub0, up = 3 * n, 3 * n + 1, 3 * n + 1 + r
+    ub = list(range(ub0, ub0 + r))
+    psi = np.zeros(1 << (up + 1), dtype=np.complex128)
+    psi[0] = 1.0
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2.0)
+    X = np.array([[0, 1], [1, 0]])
+    Z = np.diag([1.0, -1.0])
+    FLIP0 = np.diag([-1.0, 1.0])
+
+    def copy_address():
+        for j in range(n):
+            apply_gate(psi, a1[j], X, [add[j]])
+
+    def swap_test():
+        apply_gate(psi, a2, H)
+        for j in range(n):
+            apply_swap(psi, ua[j], a1[j], [a2])
+        apply_gate(psi, a2, H)
+
+    def W():
+        apply_ctrl_unitary(psi, UV, 0, n)
+        swap_test()
+
+    def W_dagger():
+        swap_test()
+        apply_ctrl_unitary(psi, UV, 0, n, adjoint=True)
+
+    def S_chi(c):
+        apply_gate(psi, a2, FLIP0, [c])
+
+    def S_0(c):
+        copy_address()
+        apply_gate(psi, a2, FLIP0, ua + a1 + [c], [0] * (2 * n) + [1])
+        copy_address()
+
+    def controlled_Q(c, inverse):
+        if not inverse:          # Q = -W S_0 W^dagger S_chi
+            S_chi(c)
+            W_dagger()
+            S_0(c)
+            W()
+        else:                    # Q^dagger = -S_chi W S_0 W^dagger
+            W_dagger()
+            S_0(c)
+            W()
+            S_chi(c)
+        apply_gate(psi, c, Z)    # the minus sign, on the control
+
+    for q in add:                                   # step 1
+        apply_gate(psi, q, H)
+    copy_address()
+    W()                                             # steps 2-3
+    for q in ub:                                    # step 4
+        apply_gate(psi, q, H)
+    for k in range(r):
+        for _ in range(1 << k):
+            controlled_Q(ub[k], False)
+    qft(psi, ub0, r, inverse=True)
+    M = 1 << r
+    for y in range(M):                              # step 5
+        f = -math.cos(2.0 * math.pi * y / M)
+        c = abs(math.sin(2.0 * math.pi * y / M))
+        apply_gate(psi, up, np.array([[c, -f], [f, c]]), ub, [(y >> b) & 1 for b in range(r)])
+    qft(psi, ub0, r, inverse=False)                 # undo phase estimation
+    for k in reversed(range(r)):
+        for _ in range(1 << k):
+            controlled_Q(ub[k], True)
+    for q in ub:
+        apply_gate(psi, q, H)
+    W_dagger()
+    copy_address()
+    if avg:
+        for q in add:
+            apply_gate(psi, q, H)
+    return psi

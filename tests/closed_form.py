@@ -82,3 +82,20 @@ def gpe_closed_form(A, b, n_c, T0, cut, signed=False):
     g, h = gpe_weights(lam * T0 / (2 * math.pi), n_c, cut, signed)
     z1, z0 = V @ (beta * g), V @ (beta * h)
     return z1, z0, float(np.sum(np.abs(beta * g) ** 2)), float(np.sum(np.abs(beta) ** 2 * g))
+
+
+def qadc_weights(u, r):
+    """The QPP nonlinear transform: for each address s, the up = 1 amplitude
+    with every ancilla back at 0, times sqrt(N).  Amplitude estimation of the
+    SWAP test's a2 = 0 probability (1 + u_s^2) / 2 = sin^2(pi beta_s) puts
+    clock value y on the phase-estimation register with probability
+    K(beta_s - y/M) (the iterate's second eigenphase -beta_s gives the same
+    weights at M - y, where the rotation is the same), the rotation multiplies
+    the up = 1 part by f(y) = -cos(2 pi y / M), and the uncompute returns each
+    y to 0 with amplitude conj(alpha_y): g_s = sum_y K(beta_s - y/M) f(y)."""
+    u = np.asarray(u, dtype=np.float64)
+    z = u / np.linalg.norm(u)
+    M = 1 << r
+    beta = np.arcsin(np.sqrt((1.0 + z * z) / 2.0)) / math.pi
+    y = np.arange(M, dtype=np.float64)
+    return (fejer(beta[:, None] - y[None, :] / M, M) * (-np.cos(2 * math.pi * y / M))[None, :]).sum(axis=1)
