@@ -411,6 +411,46 @@ sv_status sv_lcu_derivative(sv_state s, int q_lo, int m, int sel_lo, int mode);
  * the register or outside the state). */
 sv_status sv_spectral_derivative(sv_state s, int q_lo, int m, int anc, int max_local);
 
+/* QPP nonlinear transform (appendix "Nonlinear transform", steps 1-5): the
+ * amplitudes of a real 2^n-point state zeta = u/|u| become their squares on
+ * an output qubit.  Qubits of the state (3n + r + 2 in all): ua [0, n) (the
+ * loaded amplitudes), a1 [n, 2n) (the address copy), add [2n, 3n) (the
+ * address), a2 = 3n (the SWAP-test qubit), ub [3n+1, 3n+1+r) (phase
+ * estimation), up = 3n+1+r (the output).  The circuit, from |0...0>:
+ *   1. H on add, CNOT add_j -> a1_j;
+ *   2-3. W = T U_V: U_V loads zeta on ua (the real Householder reflection
+ *      I - 2 v v^T / v^T v, v = e_0 + sigma zeta, sigma = +1 if zeta_0 >= 0
+ *      else -1, so U_V|0> = -sigma zeta), T = H(a2) CSWAP(ua <-> a1 | a2)
+ *      H(a2), the SWAP test, whose a2 = 0 part has probability
+ *      (1 + zeta_s^2) / 2 = sin^2(pi beta_s) at address s;
+ *   4. phase estimation on ub of the amplitude-estimation iterate
+ *      Q = -W S_0 W^H S_chi (S_chi: sign of a2 = 0; S_0: sign of ua = 0,
+ *      a1 = address, a2 = 0): H on ub, controlled Q^(2^k), inverse QFT;
+ *   5. Ry on up for ub = y with sine -cos(2 pi y / 2^r) (cosine |sin|), then
+ *      phase estimation, W and the address copy undone.
+ * The up = 1 amplitude at address s with every ancilla at 0 is
+ * g_s / sqrt(2^n), g_s = zeta_s^2 when beta_s lies on the 2^-r grid and
+ * within 2 / 2^r of it otherwise.
+ *   mode 0: gate by gate (U_V on the matrix cores, 2^r - 1 controlled
+ *           iterates and as many inverse ones);
+ *   mode 1: each (add, ub, up) column's controlled powers applied as Q^t
+ *           (t = its ub value) in LDS in one pass, and the same for the
+ *           uncompute; n <= 6.
+ * avg != 0 ends with U_avg = H on add, so the up = 1, all-zero amplitude is
+ * (1/2^n) sum_s g_s.  u: host, 2^n FP64 values, borrowed.  sq_out (host,
+ * 2^n doubles, may be NULL): sqrt(2^n) times the real part of the up = 1,
+ * ancillas = 0 amplitudes, i.e. g_s.  The final state stays in s.
+ * Synchronises the state's stream.  Errors: SV_EINVAL (n outside 1..10, r
+ * outside 1..16, 3n + r + 2 != the state's qubits, mode, non-finite u),
+ * SV_EZERONORM (u = 0), SV_EUNSUPPORTED (mode 1 with n > 6), SV_ENOMEM. */
+typedef struct {
+    double p_sq;   /* P(up = 1, every ancilla 0) before U_avg = (1/2^n) sum_s g_s^2 */
+    double p_up;   /* P(up = 1) before U_avg */
+    double avg;    /* with avg: the real up = 1, all-zero amplitude after U_avg */
+} sv_qadc_result;
+sv_status sv_qadc_square(sv_state s, const double *u, int n, int r, int mode, int avg, double *sq_out,
+                         sv_qadc_result *res);
+
 /* ------------------------------------------------------------------------
  * QLSA-2 (main text, "Quantum Linear Systems Algorithm": the solver family
  * built on a linear combination of unitaries, after the cited work of

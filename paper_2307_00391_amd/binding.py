@@ -66,6 +66,10 @@ class sv_qlsa2f_params(ctypes.Structure):
                 ("dz", ctypes.c_double), ("mode", ctypes.c_int)]
 
 
+class sv_qadc_result(ctypes.Structure):
+    _fields_ = [("p_sq", ctypes.c_double), ("p_up", ctypes.c_double), ("avg", ctypes.c_double)]
+
+
 class sv_batch_instance(ctypes.Structure):
     _fields_ = [("n_s", ctypes.c_int), ("n_c", ctypes.c_int), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("n_t0", ctypes.c_int), ("t0", ctypes.c_void_p)]
@@ -117,6 +121,7 @@ _SIGS = {
     "sv_gapped_pe": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_gapped_pe_run": ([_P, _P, _P, _P, _P, _P], _I),
     "sv_spectral_derivative": ([_P, _I, _I, _I, _I], _I),
+    "sv_qadc_square": ([_P, _DP, _I, _I, _I, _I, _DP, ctypes.POINTER(sv_qadc_result)], _I),
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
     "sv_batch_num_solves": ([_P], _I),
@@ -503,6 +508,20 @@ def sv_spectral_derivative(h, q_lo, m, anc, max_local=0):
     """QPP spectral gradient on [q_lo, q_lo + m), Lambda block-encoded on `anc`."""
     _check(lib().sv_spectral_derivative(h, int(q_lo), int(m), int(anc), int(max_local)),
            "sv_spectral_derivative")
+
+
+def sv_qadc_square(h, u, r, mode=1, avg=True):
+    """QPP nonlinear transform of the real 2^n-point u on a (3n + r + 2)-qubit
+    state.  Returns (g, result): g[s] ~ (u_s / |u|)^2."""
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+    n = u.size.bit_length() - 1
+    if u.size != 1 << n:
+        raise ValueError("u must have 2^n entries")
+    g = np.zeros(u.size)
+    res = sv_qadc_result()
+    _check(lib().sv_qadc_square(h, u.ctypes.data_as(_DP), n, int(r), int(mode), int(bool(avg)),
+                                g.ctypes.data_as(_DP), ctypes.byref(res)), "sv_qadc_square")
+    return g, res
 
 
 # --------------------------------------------------------------------------

@@ -15,7 +15,7 @@ OUT = os.path.join(PKG, "libsv.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["sv_core.hip", "sv_fused.hip", "sv_gemm.hip", "sv_hhl.hip", "sv_eigpipe.hip", "sv_batch.hip", "sv_mlp.hip",
-           "sv_spectrum.hip", "sv_qsp.hip", "sv_qpp.hip", "sv_qlsa2.hip", "sv_tune.cpp", "sv_trace.cpp"]
+           "sv_spectrum.hip", "sv_qsp.hip", "sv_qpp.hip", "sv_qlsa2.hip", "sv_qadc.hip", "sv_tune.cpp", "sv_trace.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -1,0 +1,468 @@
+// QPP nonlinear transform (appendix "Nonlinear transform", steps 1-5): the
+// amplitudes u'_s of a real 2^n-point state are turned into (u'_s)^2 on the
+// amplitude of an output qubit, by a SWAP test against the address, amplitude
+// estimation of the test's success probability (1 + u_s^2)/2 = sin^2(pi beta_s)
+// by phase estimation, a rotation driven by the estimated phase and the
+// uncompute.
+//
+// Layout: ua [0, n) (the loaded amplitudes), a1 [n, 2n) (the address copy),
+// add [2n, 3n) (the address), a2 = 3n (the SWAP-test qubit), ub [3n+1,
+// 3n+1+r) (the phase-estimation register), up = 3n+1+r (the output qubit).
+//
+// Operators: U_V is the real Householder reflection I - 2 v v^T / (v^T v),
+// v = e_0 + sigma zeta (sigma = sign of zeta_0, +1 at 0), so U_V|0> =
+// -sigma zeta; T = H(a2) CSWAP(ua <-> a1 | a2) H(a2); W = T U_V, W^dagger =
+// U_V T.  The iterate is Q = -W S_0 W^dagger S_chi, S_chi the sign flip of
+// a2 = 0, S_0 the sign flip of (ua = 0, a1 = address, a2 = 0).  The rotation
+// on up for ub = y has sine -cos(2 pi y / 2^r) and cosine |sin(2 pi y / 2^r)|.
+//
+//   mode 0: gate by gate: Hadamards, CNOT copies, the dense U_V on the matrix
+//           cores, the SWAP test and the reflections as fused gate passes,
+//           2^r - 1 controlled iterates for phase estimation and as many for
+//           its uncompute;
+//   mode 1: the controlled powers fused: a (add, ub, up) column of the state
+//           holds a 2^(2n+1)-amplitude (ua, a1, a2) block on which the
+//           controlled Q^(2^k) of every clock bit k compose to Q^t, t the
+//           column's ub value.  One workgroup keeps the block in LDS and
+//           applies the t iterates there (Q^dagger for the uncompute), so
+//           the 2^r - 1 iterates cost one read and one write of the state.
+//           The remaining steps are the mode-0 gates.
+#include <math.h>
+
+#include <cmath>
+#include <vector>
+
+#include "sv_device.h"
+#include "sv_hhl_internal.h"
+#include "sv_internal.h"
+
+namespace sv {
+
+template <typename R>
+sv_status ctrl_unitary_impl(sv_state s, const cvec<R> *U, int m, int ctrl, int ctrl_val, int adjoint);
+
+struct QadcArgs {
+    int n, r;
+    uint64_t ncols;      // 2^(n + r + 1) columns (add, ub, up)
+    int inverse;         // 0: Q^t, 1: (Q^dagger)^t
+};
+
+// One column per workgroup: rows a2 = 0 and a2 = 1 of the (ua, a1) block,
+// element e = i + (j << n) with i = ua, j = a1.
+template <typename R>
+__global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, const R *__restrict__ vhh, QadcArgs a) {
+    extern __shared__ unsigned char lds_raw[];
+    const int n = a.n;
+    const uint32_t N = 1u << n, B = N * N;
+    cvec<R> *row0 = reinterpret_cast<cvec<R> *>(lds_raw);
+    cvec<R> *row1 = row0 + B;
+    cvec<R> *dots = row1 + B;                       // [a2][j]
+    R *v = reinterpret_cast<R *>(dots + 2 * N);      // Householder vector, then its scale c = 2 / v.v
+    for (uint64_t col = blockIdx.x; col < a.ncols; col += gridDim.x) {
+        const uint64_t s = col & (N - 1u);
+        const uint32_t t = (uint32_t)((col >> n) & ((1ull << a.r) - 1ull));
+        if (t == 0) continue;                        // Q^0: the column is left as it is
+        const uint64_t hi = col >> n;                // (ub, up), placed above a2
+        const uint64_t base = (s << (2 * n)) | (hi << (3 * n + 1));
+        const uint64_t off1 = 1ull << (3 * n);
+        for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
+            row0[e] = psi[base | e];
+            row1[e] = psi[base | off1 | e];
+        }
+        for (uint32_t i = threadIdx.x; i <= N; i += blockDim.x) v[i] = vhh[i];
+        __syncthreads();
+        const R c = v[N];
+        const uint32_t flip = (uint32_t)s << n;     // (ua = 0, a1 = s) in row 0
+        for (uint32_t it = 0; it < t; ++it) {
+            // T (and, for Q, the -S_chi = sign of row 1 before it; for
+            // Q^dagger the same sign after the last T), then U_V, S_0, U_V, T
+            for (int half = 0; half < 2; ++half) {
+                const bool neg_before = !a.inverse && half == 0;
+                const bool neg_after = a.inverse && half == 1;
+                if (half == 1) {
+                    // U_V: dots over ua for every (a1, a2) column, then the update
+                    for (uint32_t q = threadIdx.x; q < 2 * N; q += blockDim.x) {
+                        const cvec<R> *rw = (q < N) ? row0 : row1;
+                        const uint32_t j = q & (N - 1u);
+                        R dx = 0, dy = 0;
+                        for (uint32_t i = 0; i < N; ++i) {
+                            const cvec<R> z = rw[i + (j << n)];
+                            dx += v[i] * z.x;
+                            dy += v[i] * z.y;
+                        }
+                        dots[q] = cmake<R>(c * dx, c * dy);
+                    }
+                    __syncthreads();
+                    for (uint32_t e = threadIdx.x; e < 2 * B; e += blockDim.x) {
+                        cvec<R> *rw = (e < B) ? row0 : row1;
+                        const uint32_t f = e & (B - 1u), i = f & (N - 1u), j = f >> n;
+                        const cvec<R> d = dots[(e < B ? 0u : N) + j];
+                        cvec<R> z = rw[f];
+                        z.x -= v[i] * d.x;
+                        z.y -= v[i] * d.y;
+                        rw[f] = z;
+                    }
+                    __syncthreads();
+                }
+                // T on the pairs (i, j), (j, i) with i < j (identity on i == j)
+                for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
+                    const uint32_t i = e & (N - 1u), j = e >> n;
+                    if (neg_before && i == j) row1[e] = cmake<R>(-row1[e].x, -row1[e].y);
+                    if (i >= j) continue;
+                    const uint32_t et = j + (i << n);
+                    cvec<R> p = row0[e], q = row0[et], P = row1[e], Qv = row1[et];
+                    if (neg_before) {
+                        P = cmake<R>(-P.x, -P.y);
+                        Qv = cmake<R>(-Qv.x, -Qv.y);
+                    }
+                    const R h = (R)0.5;
+                    const cvec<R> spP = cmake<R>(p.x + P.x, p.y + P.y), sqQ = cmake<R>(q.x + Qv.x, q.y + Qv.y);
+                    const cvec<R> dqQ = cmake<R>(q.x - Qv.x, q.y - Qv.y), dpP = cmake<R>(p.x - P.x, p.y - P.y);
+                    row0[e] = cmake<R>(h * (spP.x + dqQ.x), h * (spP.y + dqQ.y));
+                    cvec<R> r1e = cmake<R>(h * (spP.x - dqQ.x), h * (spP.y - dqQ.y));
+                    row0[et] = cmake<R>(h * (sqQ.x + dpP.x), h * (sqQ.y + dpP.y));
+                    cvec<R> r1t = cmake<R>(h * (sqQ.x - dpP.x), h * (sqQ.y - dpP.y));
+                    if (neg_after) {
+                        r1e = cmake<R>(-r1e.x, -r1e.y);
+                        r1t = cmake<R>(-r1t.x, -r1t.y);
+                    }
+                    row1[e] = r1e;
+                    row1[et] = r1t;
+                }
+                if (neg_after) {
+                    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+                        const uint32_t e = i + (i << n);
+                        row1[e] = cmake<R>(-row1[e].x, -row1[e].y);
+                    }
+                }
+                __syncthreads();
+                if (half == 0) {
+                    // U_V, then S_0 on (ua = 0, a1 = s, a2 = 0)
+                    for (uint32_t q = threadIdx.x; q < 2 * N; q += blockDim.x) {
+                        const cvec<R> *rw = (q < N) ? row0 : row1;
+                        const uint32_t j = q & (N - 1u);
+                        R dx = 0, dy = 0;
+                        for (uint32_t i = 0; i < N; ++i) {
+                            const cvec<R> z = rw[i + (j << n)];
+                            dx += v[i] * z.x;
+                            dy += v[i] * z.y;
+                        }
+                        dots[q] = cmake<R>(c * dx, c * dy);
+                    }
+                    __syncthreads();
+                    for (uint32_t e = threadIdx.x; e < 2 * B; e += blockDim.x) {
+                        cvec<R> *rw = (e < B) ? row0 : row1;
+                        const uint32_t f = e & (B - 1u), i = f & (N - 1u), j = f >> n;
+                        const cvec<R> d = dots[(e < B ? 0u : N) + j];
+                        cvec<R> z = rw[f];
+                        z.x -= v[i] * d.x;
+                        z.y -= v[i] * d.y;
+                        if (e == flip) z = cmake<R>(-z.x, -z.y);
+                        rw[f] = z;
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
+            psi[base | e] = row0[e];
+            psi[base | off1 | e] = row1[e];
+        }
+        __syncthreads();
+    }
+}
+
+namespace {
+
+struct Layout {
+    int n, r;
+    int ua() const { return 0; }
+    int a1() const { return n; }
+    int add() const { return 2 * n; }
+    int a2() const { return 3 * n; }
+    int ub() const { return 3 * n + 1; }
+    int up() const { return 3 * n + 1 + r; }
+};
+
+// the Householder vector v = e_0 + sigma zeta of the loader, FP64
+void loader_vector(const std::vector<double> &zeta, std::vector<double> &v, double &c) {
+    const double sigma = zeta[0] >= 0.0 ? 1.0 : -1.0;
+    v.resize(zeta.size());
+    double vv = 0.0;
+    for (size_t i = 0; i < zeta.size(); ++i) {
+        v[i] = sigma * zeta[i] + (i == 0 ? 1.0 : 0.0);
+        vv += v[i] * v[i];
+    }
+    c = 2.0 / vv;
+}
+
+sv_gate gate_u(int target, double a, double b, double cc, double d) {
+    sv_gate g{};
+    g.kind = SV_GATE_U;
+    g.target = target;
+    g.u[0] = a;
+    g.u[2] = b;
+    g.u[4] = cc;
+    g.u[6] = d;
+    return g;
+}
+sv_gate gate_ctrl(sv_gate g, int ctrl, int val) {
+    g.ctrls[g.n_ctrls] = ctrl;
+    g.ctrl_vals[g.n_ctrls] = val;
+    ++g.n_ctrls;
+    return g;
+}
+
+class Qadc {
+public:
+    Qadc(sv_state s, int n, int r) : s_(s), L{n, r} {}
+
+    sv_status prepare(const std::vector<double> &zeta) {
+        std::vector<double> v;
+        double c;
+        loader_vector(zeta, v, c);
+        const int N = 1 << L.n;
+        const size_t eb = amp_bytes(s_->dt);
+        // dense U_V in the state's precision (mode 0)
+        SV_TRY(U_.ensure((size_t)N * N * eb));
+        if (s_->dt == SV_C64) {
+            std::vector<float2> U((size_t)N * N);
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) U[(size_t)i * N + j] = make_float2((float)((i == j) - c * v[i] * v[j]), 0.f);
+            SV_TRY(upload(s_, U_.p, U.data(), U.size() * sizeof(float2)));
+            std::vector<float> vh(N + 1);
+            for (int i = 0; i < N; ++i) vh[i] = (float)v[i];
+            vh[N] = (float)c;
+            SV_TRY(vh_.ensure(vh.size() * sizeof(float)));
+            SV_TRY(upload(s_, vh_.p, vh.data(), vh.size() * sizeof(float)));
+        } else {
+            std::vector<double2> U((size_t)N * N);
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) U[(size_t)i * N + j] = make_double2((i == j) - c * v[i] * v[j], 0.0);
+            SV_TRY(upload(s_, U_.p, U.data(), U.size() * sizeof(double2)));
+            std::vector<double> vh(v);
+            vh.push_back(c);
+            SV_TRY(vh_.ensure(vh.size() * sizeof(double)));
+            SV_TRY(upload(s_, vh_.p, vh.data(), vh.size() * sizeof(double)));
+        }
+        return SV_OK;
+    }
+
+    // the queued gates, as one fused circuit
+    sv_status flush() {
+        if (q_.empty()) return SV_OK;
+        sv_status st = sv_apply_circuit(s_, q_.data(), (int)q_.size(), 0);
+        q_.clear();
+        return st;
+    }
+    void h(int q) {
+        const double k = M_SQRT1_2;
+        q_.push_back(gate_u(q, k, k, k, -k));
+    }
+    void copy_address() {
+        for (int j = 0; j < L.n; ++j) {
+            sv_gate g{};
+            g.kind = SV_GATE_X;
+            g.target = L.a1() + j;
+            q_.push_back(gate_ctrl(g, L.add() + j, 1));
+        }
+    }
+    void swap_test() {
+        h(L.a2());
+        for (int j = 0; j < L.n; ++j) {
+            sv_gate g{};
+            g.kind = SV_GATE_SWAP;
+            g.target = L.ua() + j;
+            g.target2 = L.a1() + j;
+            q_.push_back(gate_ctrl(g, L.a2(), 1));
+        }
+        h(L.a2());
+    }
+    sv_status loader() {
+        SV_TRY(flush());
+        if (s_->dt == SV_C64) return ctrl_unitary_impl<float>(s_, (const float2 *)U_.p, L.n, -1, 0, 0);
+        return ctrl_unitary_impl<double>(s_, (const double2 *)U_.p, L.n, -1, 0, 0);
+    }
+    sv_status W() {
+        SV_TRY(loader());
+        swap_test();
+        return SV_OK;
+    }
+    sv_status W_dagger() {
+        swap_test();
+        return loader();
+    }
+    void s_chi(int c) { q_.push_back(gate_ctrl(gate_u(L.a2(), -1, 0, 0, 1), c, 1)); }
+    sv_status s_0(int c) {
+        copy_address();
+        SV_TRY(flush());
+        int ctrls[32], vals[32];
+        int k = 0;
+        for (int j = 0; j < 2 * L.n; ++j) {
+            ctrls[k] = L.ua() + j;      // ua then a1: bits [0, 2n)
+            vals[k++] = 0;
+        }
+        ctrls[k] = c;
+        vals[k++] = 1;
+        const double flip0[8] = {-1, 0, 0, 0, 0, 0, 1, 0};
+        SV_TRY(sv_apply_gate(s_, L.a2(), flip0, ctrls, vals, k));
+        copy_address();
+        return SV_OK;
+    }
+    sv_status controlled_q(int c, bool inverse) {
+        if (!inverse) {
+            s_chi(c);
+            SV_TRY(W_dagger());
+            SV_TRY(s_0(c));
+            SV_TRY(W());
+        } else {
+            SV_TRY(W_dagger());
+            SV_TRY(s_0(c));
+            SV_TRY(W());
+            s_chi(c);
+        }
+        q_.push_back(gate_u(c, 1, 0, 0, -1));   // the iterate's minus sign, on its control
+        return SV_OK;
+    }
+
+    // every controlled power of the iterate at once: Q^t on the column with ub = t
+    sv_status fused_powers(bool inverse) {
+        SV_TRY(flush());
+        QadcArgs a;
+        a.n = L.n;
+        a.r = L.r;
+        a.ncols = dim_of(L.n + L.r + 1);
+        a.inverse = inverse ? 1 : 0;
+        const int N = 1 << L.n;
+        const size_t eb = amp_bytes(s_->dt);
+        const size_t lds = (2 * (size_t)N * N + 2 * (size_t)N) * eb + (N + 1) * (eb / 2);
+        uint64_t g = a.ncols;
+        if (g > (1u << 20)) g = 1u << 20;
+        // iterates per launch: every (add, up) pair runs t = 0 .. 2^r - 1 of them;
+        // one iterate is two Householder updates (16 N^2 flops each) and two
+        // SWAP-test butterflies (12 N^2 each) on the 2 N^2-amplitude block
+        const double iters = (double)((1ull << L.r) - 1ull) * (double)(1ull << L.r) / 2.0 * (double)(2ull * N);
+        TraceScope ts(s_->stream, "qadc_power", 2.0 * (double)dim_of(s_->n) * eb, iters * 56.0 * N * N);
+        if (s_->dt == SV_C64) {
+            if (lds > 65536)
+                SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+            hipLaunchKernelGGL(k_qadc_power<float>, dim3((unsigned)g), dim3(256), lds, s_->stream, (float2 *)s_->data,
+                               (const float *)vh_.p, a);
+        } else {
+            if (lds > 65536)
+                SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+            hipLaunchKernelGGL(k_qadc_power<double>, dim3((unsigned)g), dim3(256), lds, s_->stream,
+                               (double2 *)s_->data, (const double *)vh_.p, a);
+        }
+        SV_HIP(hipGetLastError());
+        return SV_OK;
+    }
+
+    sv_status run(int mode, int avg, const std::vector<double> &zeta, double *sq_out, sv_qadc_result *res) {
+        SV_TRY(prepare(zeta));
+        SV_TRY(sv_init_basis(s_, 0));
+        const int n = L.n, r = L.r;
+        const uint64_t M = 1ull << r;
+        for (int j = 0; j < n; ++j) h(L.add() + j);                  // step 1
+        copy_address();
+        SV_TRY(W());                                                 // steps 2-3
+        for (int k = 0; k < r; ++k) h(L.ub() + k);                   // step 4
+        if (mode == 1) {
+            SV_TRY(fused_powers(false));
+        } else {
+            for (int k = 0; k < r; ++k)
+                for (uint64_t i = 0; i < (1ull << k); ++i) SV_TRY(controlled_q(L.ub() + k, false));
+        }
+        SV_TRY(flush());
+        SV_TRY(sv_qft(s_, L.ub(), r, 1, 1, 0));
+        std::vector<double> cs(2 * M);                               // step 5
+        for (uint64_t y = 0; y < M; ++y) {
+            const double ang = 2.0 * M_PI * (double)y / (double)M;
+            cs[2 * y] = fabs(sin(ang));
+            cs[2 * y + 1] = -cos(ang);
+        }
+        SV_TRY(sv_apply_uniform_ry(s_, L.up(), L.ub(), r, cs.data(), -1, 0));
+        SV_TRY(sv_qft(s_, L.ub(), r, 0, 1, 0));                      // undo phase estimation
+        if (mode == 1) {
+            SV_TRY(fused_powers(true));
+        } else {
+            for (int k = r - 1; k >= 0; --k)
+                for (uint64_t i = 0; i < (1ull << k); ++i) SV_TRY(controlled_q(L.ub() + k, true));
+        }
+        for (int k = 0; k < r; ++k) h(L.ub() + k);
+        SV_TRY(W_dagger());
+        copy_address();
+        SV_TRY(flush());
+        // the squares: the up = 1 block with every ancilla at 0, times sqrt(N)
+        const uint64_t upbit = 1ull << L.up();
+        const uint64_t all = dim_of(s_->n) - 1ull;
+        const uint64_t addmask = ((1ull << n) - 1ull) << L.add();
+        const int N = 1 << n;
+        double p = 0.0;
+        SV_TRY(sv_norm2(s_, all & ~addmask, upbit, &p));
+        res->p_sq = p;
+        SV_TRY(sv_norm2(s_, upbit, upbit, &res->p_up));
+        if (sq_out) {
+            if (p > 0.0) {
+                std::vector<double> z(2 * (size_t)N);
+                SV_TRY(sv_postselect(s_, all & ~addmask, upbit, &p, z.data(), 0));
+                const double k = sqrt(p * (double)N);
+                for (int i = 0; i < N; ++i) sq_out[i] = z[2 * i] * k;
+            } else {
+                for (int i = 0; i < N; ++i) sq_out[i] = 0.0;
+            }
+        }
+        res->avg = 0.0;
+        if (avg) {
+            SV_TRY(run_hadamards(s_, L.add(), n, 0, 0));             // U_avg
+            double p0 = 0.0;
+            SV_TRY(sv_norm2(s_, all, upbit, &p0));
+            if (p0 > 0.0) {
+                double z[2];
+                SV_TRY(sv_postselect(s_, all, upbit, &p0, z, 0));
+                res->avg = z[0] * sqrt(p0);
+            }
+        }
+        return SV_OK;
+    }
+
+private:
+    sv_state s_;
+    Layout L;
+    DevBuf U_, vh_;
+    std::vector<sv_gate> q_;
+};
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" sv_status sv_qadc_square(sv_state s, const double *u, int n, int r, int mode, int avg, double *sq_out,
+                                    sv_qadc_result *res) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!u || !res) return fail(SV_EINVAL, "u and res must not be NULL");
+    if (n < 1 || n > 10) return fail(SV_EINVAL, "n = %d outside 1..10", n);
+    if (r < 1 || r > 16) return fail(SV_EINVAL, "r = %d outside 1..16", r);
+    if (3 * n + r + 2 != s->n)
+        return fail(SV_EINVAL, "the state has %d qubits; 3n + r + 2 = %d", s->n, 3 * n + r + 2);
+    if (mode != 0 && mode != 1) return fail(SV_EINVAL, "mode must be 0 or 1");
+    if (mode == 1 && n > 6) return fail(SV_EUNSUPPORTED, "mode 1 keeps the 2^(2n+1) block in LDS: n <= 6");
+    const int N = 1 << n;
+    std::vector<double> zeta(u, u + N);
+    double nrm = 0.0;
+    for (int i = 0; i < N; ++i) {
+        if (!std::isfinite(zeta[i])) return fail(SV_EINVAL, "u[%d] is not finite", i);
+        nrm += zeta[i] * zeta[i];
+    }
+    if (nrm == 0.0) return fail(SV_EZERONORM, "u = 0");
+    nrm = sqrt(nrm);
+    for (double &z : zeta) z /= nrm;
+    Qadc q(s, n, r);
+    SV_TRY(q.run(mode, avg, zeta, sq_out, res));
+    SV_HIP(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
