@@ -45,19 +45,91 @@ struct QadcArgs {
     int n, r;
     uint64_t ncols;      // 2^(n + r + 1) columns (add, ub, up)
     int inverse;         // 0: Q^t, 1: (Q^dagger)^t
+    int tl;              // log2 of the threads per (a1, a2) column in the U_V step
 };
 
+// The block in LDS: entry (ua = i, a1 = j) of row a2 at a2 N P + j P + i with
+// the padded row pitch P = N + 1, so that the SWAP test's transposed reads
+// (j, i) of consecutive i fall in distinct banks.
+
+// U_V on every (a1, a2) column of the block: 2^tl consecutive threads share a
+// column, each holding every 2^tl-th ua entry; they sum the dot v.z with
+// shuffles and update their own entries, so the step needs no barrier inside.
+// flip_col < 2N: negate entry ua = 0 of that column afterwards (S_0).
+template <typename R>
+__device__ __forceinline__ void qadc_householder(cvec<R> *__restrict__ blk, const R *__restrict__ v, R c, int n,
+                                                 int tl, uint32_t flip_col) {
+    const uint32_t N = 1u << n, tid = threadIdx.x;
+    if (tid >= ((2u * N) << tl)) return;
+    const uint32_t q = tid >> tl, sub = tid & ((1u << tl) - 1u);
+    const uint32_t P = N + 1u;
+    cvec<R> *col = blk + (q >> n) * (N * P) + (q & (N - 1u)) * P;
+    R dx = 0, dy = 0;
+    for (uint32_t i = sub; i < N; i += 1u << tl) {
+        const cvec<R> z = col[i];
+        dx += v[i] * z.x;
+        dy += v[i] * z.y;
+    }
+    for (int o = 1; o < (1 << tl); o <<= 1) {
+        dx += __shfl_xor(dx, o);
+        dy += __shfl_xor(dy, o);
+    }
+    dx *= c;
+    dy *= c;
+    for (uint32_t i = sub; i < N; i += 1u << tl) {
+        cvec<R> z = col[i];
+        z.x -= v[i] * dx;
+        z.y -= v[i] * dy;
+        if (q == flip_col && i == 0) z = cmake<R>(-z.x, -z.y);
+        col[i] = z;
+    }
+}
+
+// T = H(a2) CSWAP(ua <-> a1 | a2) H(a2) on the pairs (i, j), (j, i), i < j
+// (the identity on i == j).  neg_before: the sign of row 1 first (-S_chi);
+// neg_after: the same sign last.
+template <typename R>
+__device__ __forceinline__ void qadc_swap_test(cvec<R> *__restrict__ row0, cvec<R> *__restrict__ row1, int n,
+                                               bool neg_before, bool neg_after) {
+    const uint32_t N = 1u << n, B = N * N, P = N + 1u;
+    const R h = (R)0.5;
+    for (uint32_t f = threadIdx.x; f < B; f += blockDim.x) {
+        const uint32_t i = f & (N - 1u), j = f >> n;
+        const uint32_t e = i + j * P;
+        if (i == j) {
+            if (neg_before != neg_after) row1[e] = cmake<R>(-row1[e].x, -row1[e].y);
+            continue;
+        }
+        if (i > j) continue;
+        const uint32_t et = j + i * P;
+        const cvec<R> p = row0[e], q = row0[et];
+        cvec<R> P = row1[e], Qv = row1[et];
+        if (neg_before) {
+            P = cmake<R>(-P.x, -P.y);
+            Qv = cmake<R>(-Qv.x, -Qv.y);
+        }
+        const cvec<R> spP = cmake<R>(p.x + P.x, p.y + P.y), sqQ = cmake<R>(q.x + Qv.x, q.y + Qv.y);
+        const cvec<R> dqQ = cmake<R>(q.x - Qv.x, q.y - Qv.y), dpP = cmake<R>(p.x - P.x, p.y - P.y);
+        const R s1 = neg_after ? -h : h;
+        row0[e] = cmake<R>(h * (spP.x + dqQ.x), h * (spP.y + dqQ.y));
+        row0[et] = cmake<R>(h * (sqQ.x + dpP.x), h * (sqQ.y + dpP.y));
+        row1[e] = cmake<R>(s1 * (spP.x - dqQ.x), s1 * (spP.y - dqQ.y));
+        row1[et] = cmake<R>(s1 * (sqQ.x - dpP.x), s1 * (sqQ.y - dpP.y));
+    }
+}
+
 // One column per workgroup: rows a2 = 0 and a2 = 1 of the (ua, a1) block,
-// element e = i + (j << n) with i = ua, j = a1.
+// row 1 right after row 0.
+// Q = -W S_0 W^dagger S_chi applied as: sign of row 1, T, U_V, S_0, U_V, T;
+// Q^dagger as: T, U_V, S_0, U_V, T, sign of row 1.
 template <typename R>
 __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, const R *__restrict__ vhh, QadcArgs a) {
     extern __shared__ unsigned char lds_raw[];
     const int n = a.n;
-    const uint32_t N = 1u << n, B = N * N;
+    const uint32_t N = 1u << n, B = N * N, P = N + 1u;
     cvec<R> *row0 = reinterpret_cast<cvec<R> *>(lds_raw);
-    cvec<R> *row1 = row0 + B;
-    cvec<R> *dots = row1 + B;                       // [a2][j]
-    R *v = reinterpret_cast<R *>(dots + 2 * N);      // Householder vector, then its scale c = 2 / v.v
+    cvec<R> *row1 = row0 + N * P;
+    R *v = reinterpret_cast<R *>(row1 + N * P);          // Householder vector, then its scale c = 2 / v.v
     for (uint64_t col = blockIdx.x; col < a.ncols; col += gridDim.x) {
         const uint64_t s = col & (N - 1u);
         const uint32_t t = (uint32_t)((col >> n) & ((1ull << a.r) - 1ull));
@@ -66,107 +138,28 @@ __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, c
         const uint64_t base = (s << (2 * n)) | (hi << (3 * n + 1));
         const uint64_t off1 = 1ull << (3 * n);
         for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
-            row0[e] = psi[base | e];
-            row1[e] = psi[base | off1 | e];
+            const uint32_t l = (e & (N - 1u)) + (e >> n) * P;
+            row0[l] = psi[base | e];
+            row1[l] = psi[base | off1 | e];
         }
         for (uint32_t i = threadIdx.x; i <= N; i += blockDim.x) v[i] = vhh[i];
         __syncthreads();
         const R c = v[N];
-        const uint32_t flip = (uint32_t)s << n;     // (ua = 0, a1 = s) in row 0
+        const uint32_t none = 0xffffffffu;
         for (uint32_t it = 0; it < t; ++it) {
-            // T (and, for Q, the -S_chi = sign of row 1 before it; for
-            // Q^dagger the same sign after the last T), then U_V, S_0, U_V, T
-            for (int half = 0; half < 2; ++half) {
-                const bool neg_before = !a.inverse && half == 0;
-                const bool neg_after = a.inverse && half == 1;
-                if (half == 1) {
-                    // U_V: dots over ua for every (a1, a2) column, then the update
-                    for (uint32_t q = threadIdx.x; q < 2 * N; q += blockDim.x) {
-                        const cvec<R> *rw = (q < N) ? row0 : row1;
-                        const uint32_t j = q & (N - 1u);
-                        R dx = 0, dy = 0;
-                        for (uint32_t i = 0; i < N; ++i) {
-                            const cvec<R> z = rw[i + (j << n)];
-                            dx += v[i] * z.x;
-                            dy += v[i] * z.y;
-                        }
-                        dots[q] = cmake<R>(c * dx, c * dy);
-                    }
-                    __syncthreads();
-                    for (uint32_t e = threadIdx.x; e < 2 * B; e += blockDim.x) {
-                        cvec<R> *rw = (e < B) ? row0 : row1;
-                        const uint32_t f = e & (B - 1u), i = f & (N - 1u), j = f >> n;
-                        const cvec<R> d = dots[(e < B ? 0u : N) + j];
-                        cvec<R> z = rw[f];
-                        z.x -= v[i] * d.x;
-                        z.y -= v[i] * d.y;
-                        rw[f] = z;
-                    }
-                    __syncthreads();
-                }
-                // T on the pairs (i, j), (j, i) with i < j (identity on i == j)
-                for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
-                    const uint32_t i = e & (N - 1u), j = e >> n;
-                    if (neg_before && i == j) row1[e] = cmake<R>(-row1[e].x, -row1[e].y);
-                    if (i >= j) continue;
-                    const uint32_t et = j + (i << n);
-                    cvec<R> p = row0[e], q = row0[et], P = row1[e], Qv = row1[et];
-                    if (neg_before) {
-                        P = cmake<R>(-P.x, -P.y);
-                        Qv = cmake<R>(-Qv.x, -Qv.y);
-                    }
-                    const R h = (R)0.5;
-                    const cvec<R> spP = cmake<R>(p.x + P.x, p.y + P.y), sqQ = cmake<R>(q.x + Qv.x, q.y + Qv.y);
-                    const cvec<R> dqQ = cmake<R>(q.x - Qv.x, q.y - Qv.y), dpP = cmake<R>(p.x - P.x, p.y - P.y);
-                    row0[e] = cmake<R>(h * (spP.x + dqQ.x), h * (spP.y + dqQ.y));
-                    cvec<R> r1e = cmake<R>(h * (spP.x - dqQ.x), h * (spP.y - dqQ.y));
-                    row0[et] = cmake<R>(h * (sqQ.x + dpP.x), h * (sqQ.y + dpP.y));
-                    cvec<R> r1t = cmake<R>(h * (sqQ.x - dpP.x), h * (sqQ.y - dpP.y));
-                    if (neg_after) {
-                        r1e = cmake<R>(-r1e.x, -r1e.y);
-                        r1t = cmake<R>(-r1t.x, -r1t.y);
-                    }
-                    row1[e] = r1e;
-                    row1[et] = r1t;
-                }
-                if (neg_after) {
-                    for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-                        const uint32_t e = i + (i << n);
-                        row1[e] = cmake<R>(-row1[e].x, -row1[e].y);
-                    }
-                }
-                __syncthreads();
-                if (half == 0) {
-                    // U_V, then S_0 on (ua = 0, a1 = s, a2 = 0)
-                    for (uint32_t q = threadIdx.x; q < 2 * N; q += blockDim.x) {
-                        const cvec<R> *rw = (q < N) ? row0 : row1;
-                        const uint32_t j = q & (N - 1u);
-                        R dx = 0, dy = 0;
-                        for (uint32_t i = 0; i < N; ++i) {
-                            const cvec<R> z = rw[i + (j << n)];
-                            dx += v[i] * z.x;
-                            dy += v[i] * z.y;
-                        }
-                        dots[q] = cmake<R>(c * dx, c * dy);
-                    }
-                    __syncthreads();
-                    for (uint32_t e = threadIdx.x; e < 2 * B; e += blockDim.x) {
-                        cvec<R> *rw = (e < B) ? row0 : row1;
-                        const uint32_t f = e & (B - 1u), i = f & (N - 1u), j = f >> n;
-                        const cvec<R> d = dots[(e < B ? 0u : N) + j];
-                        cvec<R> z = rw[f];
-                        z.x -= v[i] * d.x;
-                        z.y -= v[i] * d.y;
-                        if (e == flip) z = cmake<R>(-z.x, -z.y);
-                        rw[f] = z;
-                    }
-                    __syncthreads();
-                }
-            }
+            qadc_swap_test<R>(row0, row1, n, !a.inverse, false);
+            __syncthreads();
+            qadc_householder<R>(row0, v, c, n, a.tl, (uint32_t)s);
+            __syncthreads();
+            qadc_householder<R>(row0, v, c, n, a.tl, none);
+            __syncthreads();
+            qadc_swap_test<R>(row0, row1, n, false, a.inverse != 0);
+            __syncthreads();
         }
         for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
-            psi[base | e] = row0[e];
-            psi[base | off1 | e] = row1[e];
+            const uint32_t l = (e & (N - 1u)) + (e >> n) * P;
+            psi[base | e] = row0[l];
+            psi[base | off1 | e] = row1[l];
         }
         __syncthreads();
     }
@@ -335,7 +328,14 @@ public:
         a.inverse = inverse ? 1 : 0;
         const int N = 1 << L.n;
         const size_t eb = amp_bytes(s_->dt);
-        const size_t lds = (2 * (size_t)N * N + 2 * (size_t)N) * eb + (N + 1) * (eb / 2);
+        const size_t lds = 2 * (size_t)N * (N + 1) * eb + (N + 1) * (eb / 2);
+        // one wavefront per column up to n = 4 (a 512-amplitude block: its
+        // barriers are nearly free and more columns stay in flight), four above
+        const int nt = L.n <= 4 ? 64 : 256;
+        // threads per column in the U_V step: nt over the 2N columns, at most N
+        int tl = 0;
+        while ((1 << (tl + 1)) <= N && ((2 * N) << (tl + 1)) <= nt) ++tl;
+        a.tl = tl;
         uint64_t g = a.ncols;
         if (g > (1u << 20)) g = 1u << 20;
         // iterates per launch: every (add, up) pair runs t = 0 .. 2^r - 1 of them;
@@ -347,13 +347,13 @@ public:
             if (lds > 65536)
                 SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds));
-            hipLaunchKernelGGL(k_qadc_power<float>, dim3((unsigned)g), dim3(256), lds, s_->stream, (float2 *)s_->data,
+            hipLaunchKernelGGL(k_qadc_power<float>, dim3((unsigned)g), dim3(nt), lds, s_->stream, (float2 *)s_->data,
                                (const float *)vh_.p, a);
         } else {
             if (lds > 65536)
                 SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds));
-            hipLaunchKernelGGL(k_qadc_power<double>, dim3((unsigned)g), dim3(256), lds, s_->stream,
+            hipLaunchKernelGGL(k_qadc_power<double>, dim3((unsigned)g), dim3(nt), lds, s_->stream,
                                (double2 *)s_->data, (const double *)vh_.p, a);
         }
         SV_HIP(hipGetLastError());
