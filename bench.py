@@ -39,7 +39,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 256 CUs x 128 B per clock x 2.4 GHz
 FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix
 METRIC = "gate-amplitude updates/s + HBM GB/s (30-qubit HHL); HHL solves/s at 1−F≤1e-4"
 
@@ -423,14 +422,13 @@ def main():
         el0 = time.perf_counter() - t0
         z2 = (ua / np.linalg.norm(ua)) ** 2
         Na, Ma = 1 << na, 1 << ra
-        iters = (Ma - 1) * Ma / 2 * 2 * Na                 # iterates per launch
-        lds = iters * 20 * Na * Na * 8                     # LDS bytes: 20 N^2 complex64 accesses per iterate
         ms_k = kq["ms"] / kq["launches"]
+        gbs_k = kq["bytes"] / kq["launches"] / (ms_k * 1e-3) / 1e9
         out["qpp_square"] = {"qubits": 3 * na + ra + 2, "points": Na, "r": ra, "dtype": "c64",
                              "mode1_s": el1, "mode0_s": el0, "qadc_power_ms": ms_k,
-                             "qadc_power_launches": kq["launches"], "iterates_per_launch": iters,
-                             "lds_tbs": lds / (ms_k * 1e-3) / 1e12, "lds_peak_tbs": LDS_PEAK_TBS,
-                             "gflops": kq["flops"] / kq["launches"] / (ms_k * 1e-3) / 1e9,
+                             "qadc_power_launches": kq["launches"],
+                             "reflections_per_launch": (Ma - 1) * Ma // 2 * 2 * Na,
+                             "qadc_power_hbm_gbs": gbs_k, "qadc_power_frac_of_hbm_peak": gbs_k / HBM_PEAK_GBS,
                              "max_abs_err_vs_u2": float(np.abs(g1 - z2).max()), "bound_2_over_2r": 2.0 / Ma,
                              "modes_max_diff": float(np.abs(g1 - g0).max()), "avg": res1.avg}
         log(f"[bench] qpp squaring: mode 1 {el1 * 1e3:.1f} ms ({ms_k:.2f} ms per fused launch), mode 0 "

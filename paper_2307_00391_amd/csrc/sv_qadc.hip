@@ -24,9 +24,11 @@
 //           holds a 2^(2n+1)-amplitude (ua, a1, a2) block on which the
 //           controlled Q^(2^k) of every clock bit k compose to Q^t, t the
 //           column's ub value.  One workgroup keeps the block in LDS and
-//           applies the t iterates there (Q^dagger for the uncompute), so
-//           the 2^r - 1 iterates cost one read and one write of the state.
-//           The remaining steps are the mode-0 gates.
+//           applies Q^t there (Q^dagger for the uncompute), reduced by exact
+//           identities of its factors to two SWAP tests around t reflections
+//           of one N-entry line (k_qadc_power), so the 2^r - 1 iterates cost
+//           one read and one write of the state.  The remaining steps are
+//           the mode-0 gates.
 #include <math.h>
 
 #include <cmath>
@@ -45,44 +47,36 @@ struct QadcArgs {
     int n, r;
     uint64_t ncols;      // 2^(n + r + 1) columns (add, ub, up)
     int inverse;         // 0: Q^t, 1: (Q^dagger)^t
-    int tl;              // log2 of the threads per (a1, a2) column in the U_V step
 };
 
 // The block in LDS: entry (ua = i, a1 = j) of row a2 at a2 N P + j P + i with
 // the padded row pitch P = N + 1, so that the SWAP test's transposed reads
 // (j, i) of consecutive i fall in distinct banks.
 
-// U_V on every (a1, a2) column of the block: 2^tl consecutive threads share a
-// column, each holding every 2^tl-th ua entry; they sum the dot v.z with
-// shuffles and update their own entries, so the step needs no barrier inside.
-// flip_col < 2N: negate entry ua = 0 of that column afterwards (S_0).
+// Sum over aligned groups of N lanes (N a power of two <= 64), every lane of
+// a group getting the group's sum.  Within a 16-lane row the partners come by
+// DPP (lane xor 1 and xor 2 inside each quad, then the half-row and row
+// mirrors), which needs no LDS round trip; 32- and 64-lane groups add the
+// other rows by shuffles.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 template <typename R>
-__device__ __forceinline__ void qadc_householder(cvec<R> *__restrict__ blk, const R *__restrict__ v, R c, int n,
-                                                 int tl, uint32_t flip_col) {
-    const uint32_t N = 1u << n, tid = threadIdx.x;
-    if (tid >= ((2u * N) << tl)) return;
-    const uint32_t q = tid >> tl, sub = tid & ((1u << tl) - 1u);
-    const uint32_t P = N + 1u;
-    cvec<R> *col = blk + (q >> n) * (N * P) + (q & (N - 1u)) * P;
-    R dx = 0, dy = 0;
-    for (uint32_t i = sub; i < N; i += 1u << tl) {
-        const cvec<R> z = col[i];
-        dx += v[i] * z.x;
-        dy += v[i] * z.y;
-    }
-    for (int o = 1; o < (1 << tl); o <<= 1) {
-        dx += __shfl_xor(dx, o);
-        dy += __shfl_xor(dy, o);
-    }
-    dx *= c;
-    dy *= c;
-    for (uint32_t i = sub; i < N; i += 1u << tl) {
-        cvec<R> z = col[i];
-        z.x -= v[i] * dx;
-        z.y -= v[i] * dy;
-        if (q == flip_col && i == 0) z = cmake<R>(-z.x, -z.y);
-        col[i] = z;
-    }
+__device__ __forceinline__ R group_sum(R x, uint32_t N) {
+    if (N >= 2) x += dpp_move<0xB1>(x);      // quad_perm [1, 0, 3, 2]
+    if (N >= 4) x += dpp_move<0x4E>(x);      // quad_perm [2, 3, 0, 1]
+    if (N >= 8) x += dpp_move<0x141>(x);     // row_half_mirror
+    if (N >= 16) x += dpp_move<0x140>(x);    // row_mirror
+    for (uint32_t o = 16; o < N; o <<= 1) x += __shfl_xor(x, (int)o);
+    return x;
 }
 
 // T = H(a2) CSWAP(ua <-> a1 | a2) H(a2) on the pairs (i, j), (j, i), i < j
@@ -103,13 +97,13 @@ __device__ __forceinline__ void qadc_swap_test(cvec<R> *__restrict__ row0, cvec<
         if (i > j) continue;
         const uint32_t et = j + i * P;
         const cvec<R> p = row0[e], q = row0[et];
-        cvec<R> P = row1[e], Qv = row1[et];
+        cvec<R> Pv = row1[e], Qv = row1[et];
         if (neg_before) {
-            P = cmake<R>(-P.x, -P.y);
+            Pv = cmake<R>(-Pv.x, -Pv.y);
             Qv = cmake<R>(-Qv.x, -Qv.y);
         }
-        const cvec<R> spP = cmake<R>(p.x + P.x, p.y + P.y), sqQ = cmake<R>(q.x + Qv.x, q.y + Qv.y);
-        const cvec<R> dqQ = cmake<R>(q.x - Qv.x, q.y - Qv.y), dpP = cmake<R>(p.x - P.x, p.y - P.y);
+        const cvec<R> spP = cmake<R>(p.x + Pv.x, p.y + Pv.y), sqQ = cmake<R>(q.x + Qv.x, q.y + Qv.y);
+        const cvec<R> dqQ = cmake<R>(q.x - Qv.x, q.y - Qv.y), dpP = cmake<R>(p.x - Pv.x, p.y - Pv.y);
         const R s1 = neg_after ? -h : h;
         row0[e] = cmake<R>(h * (spP.x + dqQ.x), h * (spP.y + dqQ.y));
         row0[et] = cmake<R>(h * (sqQ.x + dpP.x), h * (sqQ.y + dpP.y));
@@ -119,9 +113,18 @@ __device__ __forceinline__ void qadc_swap_test(cvec<R> *__restrict__ row0, cvec<
 }
 
 // One column per workgroup: rows a2 = 0 and a2 = 1 of the (ua, a1) block,
-// row 1 right after row 0.
-// Q = -W S_0 W^dagger S_chi applied as: sign of row 1, T, U_V, S_0, U_V, T;
-// Q^dagger as: T, U_V, S_0, U_V, T, sign of row 1.
+// row 1 right after row 0.  Q^t is applied through three exact identities of
+// its factors: U_V^2 = I, so U_V S_0 U_V is the identity except on the
+// (a2 = 0, a1 = s) column, where it is the reflection I - 2 w w^T about
+// w = U_V|0>; T^2 = I; and T (-S_chi) T = Z(a2) SWAP(ua, a1).  Hence
+//   Q^t = T . R . (Z SWAP) . R . ... . (Z SWAP) . R . T . (-S_chi)
+// with t reflections R.  A reflection after k swaps acts on column s of the
+// stored a2 = 0 plane for even k and on row s for odd k, and the (t - 1)
+// swaps, pushed through the closing T, leave one sign of row 1 when t - 1 is
+// odd.  The column and the row (2N - 1 entries) stay in the registers of N
+// lanes of the first wavefront for all t reflections, each a dot product
+// reduced across the lanes and an update.  (Q^dagger)^t is the same sequence with
+// -S_chi moved to the end.
 template <typename R>
 __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, const R *__restrict__ vhh, QadcArgs a) {
     extern __shared__ unsigned char lds_raw[];
@@ -129,33 +132,47 @@ __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, c
     const uint32_t N = 1u << n, B = N * N, P = N + 1u;
     cvec<R> *row0 = reinterpret_cast<cvec<R> *>(lds_raw);
     cvec<R> *row1 = row0 + N * P;
-    R *v = reinterpret_cast<R *>(row1 + N * P);          // Householder vector, then its scale c = 2 / v.v
     for (uint64_t col = blockIdx.x; col < a.ncols; col += gridDim.x) {
-        const uint64_t s = col & (N - 1u);
+        const uint32_t s = (uint32_t)(col & (N - 1u));
         const uint32_t t = (uint32_t)((col >> n) & ((1ull << a.r) - 1ull));
         if (t == 0) continue;                        // Q^0: the column is left as it is
         const uint64_t hi = col >> n;                // (ub, up), placed above a2
-        const uint64_t base = (s << (2 * n)) | (hi << (3 * n + 1));
+        const uint64_t base = ((uint64_t)s << (2 * n)) | (hi << (3 * n + 1));
         const uint64_t off1 = 1ull << (3 * n);
         for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
             const uint32_t l = (e & (N - 1u)) + (e >> n) * P;
             row0[l] = psi[base | e];
             row1[l] = psi[base | off1 | e];
         }
-        for (uint32_t i = threadIdx.x; i <= N; i += blockDim.x) v[i] = vhh[i];
         __syncthreads();
-        const R c = v[N];
-        const uint32_t none = 0xffffffffu;
-        for (uint32_t it = 0; it < t; ++it) {
-            qadc_swap_test<R>(row0, row1, n, !a.inverse, false);
-            __syncthreads();
-            qadc_householder<R>(row0, v, c, n, a.tl, (uint32_t)s);
-            __syncthreads();
-            qadc_householder<R>(row0, v, c, n, a.tl, none);
-            __syncthreads();
-            qadc_swap_test<R>(row0, row1, n, false, a.inverse != 0);
-            __syncthreads();
+        qadc_swap_test<R>(row0, row1, n, !a.inverse, false);
+        __syncthreads();
+        if (threadIdx.x < N) {
+            const uint32_t i = threadIdx.x;
+            const R c = vhh[N];
+            const R w = (i == 0 ? (R)1 : (R)0) - c * vhh[i] * vhh[0];   // U_V|0>
+            const R w2 = w + w;
+            cvec<R> cl = row0[i + s * P];            // column s: (i, s)
+            cvec<R> rw = row0[s + i * P];            // row s: (s, i)
+            for (uint32_t k = 0; k < t; ++k) {
+                const bool on_row = (k & 1u) != 0u;
+                const cvec<R> x = on_row ? rw : cl;
+                const R dx = group_sum<R>(w * x.x, N), dy = group_sum<R>(w * x.y, N);
+                const cvec<R> y = cmake<R>(x.x - w2 * dx, x.y - w2 * dy);
+                if (on_row) {
+                    rw = y;
+                    if (i == s) cl = y;                  // the shared entry (s, s)
+                } else {
+                    cl = y;
+                    if (i == s) rw = y;
+                }
+            }
+            row0[i + s * P] = cl;
+            row0[s + i * P] = rw;
         }
+        __syncthreads();
+        qadc_swap_test<R>(row0, row1, n, false, (((t - 1u) & 1u) != 0u) != (a.inverse != 0));
+        __syncthreads();
         for (uint32_t e = threadIdx.x; e < B; e += blockDim.x) {
             const uint32_t l = (e & (N - 1u)) + (e >> n) * P;
             psi[base | e] = row0[l];
@@ -328,21 +345,17 @@ public:
         a.inverse = inverse ? 1 : 0;
         const int N = 1 << L.n;
         const size_t eb = amp_bytes(s_->dt);
-        const size_t lds = 2 * (size_t)N * (N + 1) * eb + (N + 1) * (eb / 2);
-        // one wavefront per column up to n = 4 (a 512-amplitude block: its
-        // barriers are nearly free and more columns stay in flight), four above
+        const size_t lds = 2 * (size_t)N * (N + 1) * eb;
+        // one wavefront per column up to n = 4 (a 512-amplitude block), four above
         const int nt = L.n <= 4 ? 64 : 256;
-        // threads per column in the U_V step: nt over the 2N columns, at most N
-        int tl = 0;
-        while ((1 << (tl + 1)) <= N && ((2 * N) << (tl + 1)) <= nt) ++tl;
-        a.tl = tl;
         uint64_t g = a.ncols;
         if (g > (1u << 20)) g = 1u << 20;
-        // iterates per launch: every (add, up) pair runs t = 0 .. 2^r - 1 of them;
-        // one iterate is two Householder updates (16 N^2 flops each) and two
-        // SWAP-test butterflies (12 N^2 each) on the 2 N^2-amplitude block
-        const double iters = (double)((1ull << L.r) - 1ull) * (double)(1ull << L.r) / 2.0 * (double)(2ull * N);
-        TraceScope ts(s_->stream, "qadc_power", 2.0 * (double)dim_of(s_->n) * eb, iters * 56.0 * N * N);
+        // per launch: every (add, up) pair runs t = 0 .. 2^r - 1 reflections of
+        // 8 N flops each; every column with t > 0 two SWAP tests of 12 N^2 flops
+        const double M = (double)(1ull << L.r);
+        const double refl = (M - 1.0) * M / 2.0 * (double)(2ull * N);
+        const double cols = (double)a.ncols * (M - 1.0) / M;
+        TraceScope ts(s_->stream, "qadc_power", 2.0 * cols * 2.0 * N * N * eb, refl * 8.0 * N + cols * 24.0 * N * N);
         if (s_->dt == SV_C64) {
             if (lds > 65536)
                 SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<float>, hipFuncAttributeMaxDynamicSharedMemorySize,

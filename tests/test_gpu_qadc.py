@@ -1,6 +1,8 @@
 """GPU parity of the QPP nonlinear transform (squaring by SWAP test and
 amplitude estimation) against the oracle's gate-by-gate circuit: both library
-modes, complex128 and complex64, the whole final state; the squares, P(up = 1,
+modes, complex128 and complex64, the whole final state, for address registers
+of 1 to 6 qubits (lane groups of 2 to 64 in the fused reflections, blocks of
+up to 130 KiB of LDS); the squares, P(up = 1,
 ancillas 0) and the U_avg readout against the Fejer closed form; the modes
 against each other at 24 qubits; error paths.
 
@@ -45,7 +47,7 @@ def _u(n, seed):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("n,r", [(1, 1), (1, 4), (2, 3), (2, 5), (3, 3)])
+@pytest.mark.parametrize("n,r", [(1, 1), (1, 4), (2, 3), (2, 5), (3, 3), (5, 3), (6, 2)])
 def test_qadc_matches_oracle(dt, mode, n, r):
     u = _u(n, 10 * n + r)
     print(f"[qadc] {dt} mode {mode} n {n} r {r}", flush=True)
