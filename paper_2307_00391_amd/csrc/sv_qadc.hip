@@ -69,14 +69,22 @@ __device__ __forceinline__ double dpp_move(double x) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
-template <typename R>
-__device__ __forceinline__ R group_sum(R x, uint32_t N) {
+template <typename R, int N>
+__device__ __forceinline__ R group_sum(R x) {
     if (N >= 2) x += dpp_move<0xB1>(x);      // quad_perm [1, 0, 3, 2]
     if (N >= 4) x += dpp_move<0x4E>(x);      // quad_perm [2, 3, 0, 1]
     if (N >= 8) x += dpp_move<0x141>(x);     // row_half_mirror
     if (N >= 16) x += dpp_move<0x140>(x);    // row_mirror
-    for (uint32_t o = 16; o < N; o <<= 1) x += __shfl_xor(x, (int)o);
+    if (N >= 32) x += __shfl_xor(x, 16);
+    if (N >= 64) x += __shfl_xor(x, 32);
     return x;
+}
+
+// x <- x - 2 w (w . x) over the N lanes of a line
+template <typename R, int N>
+__device__ __forceinline__ cvec<R> reflect_line(cvec<R> x, R w, R w2) {
+    const R dx = group_sum<R, N>(w * x.x), dy = group_sum<R, N>(w * x.y);
+    return cmake<R>(x.x - w2 * dx, x.y - w2 * dy);
 }
 
 // T = H(a2) CSWAP(ua <-> a1 | a2) H(a2) on the pairs (i, j), (j, i), i < j
@@ -125,11 +133,11 @@ __device__ __forceinline__ void qadc_swap_test(cvec<R> *__restrict__ row0, cvec<
 // lanes of the first wavefront for all t reflections, each a dot product
 // reduced across the lanes and an update.  (Q^dagger)^t is the same sequence with
 // -S_chi moved to the end.
-template <typename R>
+template <typename R, int NL>
 __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, const R *__restrict__ vhh, QadcArgs a) {
     extern __shared__ unsigned char lds_raw[];
-    const int n = a.n;
-    const uint32_t N = 1u << n, B = N * N, P = N + 1u;
+    constexpr int n = NL;
+    constexpr uint32_t N = 1u << NL, B = N * N, P = N + 1u;
     cvec<R> *row0 = reinterpret_cast<cvec<R> *>(lds_raw);
     cvec<R> *row1 = row0 + N * P;
     for (uint64_t col = blockIdx.x; col < a.ncols; col += gridDim.x) {
@@ -154,18 +162,17 @@ __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, c
             const R w2 = w + w;
             cvec<R> cl = row0[i + s * P];            // column s: (i, s)
             cvec<R> rw = row0[s + i * P];            // row s: (s, i)
-            for (uint32_t k = 0; k < t; ++k) {
-                const bool on_row = (k & 1u) != 0u;
-                const cvec<R> x = on_row ? rw : cl;
-                const R dx = group_sum<R>(w * x.x, N), dy = group_sum<R>(w * x.y, N);
-                const cvec<R> y = cmake<R>(x.x - w2 * dx, x.y - w2 * dy);
-                if (on_row) {
-                    rw = y;
-                    if (i == s) cl = y;                  // the shared entry (s, s)
-                } else {
-                    cl = y;
-                    if (i == s) rw = y;
-                }
+            // reflections alternate: column s (even k), row s (odd k); lane s
+            // holds the shared entry (s, s) in both
+            for (uint32_t k = 0; k + 1 < t; k += 2) {
+                cl = reflect_line<R, N>(cl, w, w2);
+                if (i == s) rw = cl;
+                rw = reflect_line<R, N>(rw, w, w2);
+                if (i == s) cl = rw;
+            }
+            if (t & 1u) {
+                cl = reflect_line<R, N>(cl, w, w2);
+                if (i == s) rw = cl;
             }
             row0[i + s * P] = cl;
             row0[s + i * P] = rw;
@@ -335,6 +342,28 @@ public:
         return SV_OK;
     }
 
+    template <typename R, int NL>
+    sv_status launch_one(const QadcArgs &a, size_t lds, int nt, unsigned g) {
+        if (lds > 65536)
+            SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<R, NL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds));
+        hipLaunchKernelGGL((k_qadc_power<R, NL>), dim3(g), dim3(nt), lds, s_->stream, (cvec<R> *)s_->data,
+                           (const R *)vh_.p, a);
+        return SV_OK;
+    }
+    template <typename R>
+    sv_status launch_power(const QadcArgs &a, size_t lds, int nt, unsigned g) {
+        switch (a.n) {
+        case 1: return launch_one<R, 1>(a, lds, nt, g);
+        case 2: return launch_one<R, 2>(a, lds, nt, g);
+        case 3: return launch_one<R, 3>(a, lds, nt, g);
+        case 4: return launch_one<R, 4>(a, lds, nt, g);
+        case 5: return launch_one<R, 5>(a, lds, nt, g);
+        case 6: return launch_one<R, 6>(a, lds, nt, g);
+        default: return fail(SV_EUNSUPPORTED, "fused powers need n <= 6");
+        }
+    }
+
     // every controlled power of the iterate at once: Q^t on the column with ub = t
     sv_status fused_powers(bool inverse) {
         SV_TRY(flush());
@@ -356,19 +385,8 @@ public:
         const double refl = (M - 1.0) * M / 2.0 * (double)(2ull * N);
         const double cols = (double)a.ncols * (M - 1.0) / M;
         TraceScope ts(s_->stream, "qadc_power", 2.0 * cols * 2.0 * N * N * eb, refl * 8.0 * N + cols * 24.0 * N * N);
-        if (s_->dt == SV_C64) {
-            if (lds > 65536)
-                SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
-            hipLaunchKernelGGL(k_qadc_power<float>, dim3((unsigned)g), dim3(nt), lds, s_->stream, (float2 *)s_->data,
-                               (const float *)vh_.p, a);
-        } else {
-            if (lds > 65536)
-                SV_HIP(hipFuncSetAttribute((const void *)k_qadc_power<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
-            hipLaunchKernelGGL(k_qadc_power<double>, dim3((unsigned)g), dim3(nt), lds, s_->stream,
-                               (double2 *)s_->data, (const double *)vh_.p, a);
-        }
+        if (s_->dt == SV_C64) SV_TRY(launch_power<float>(a, lds, nt, (unsigned)g));
+        else SV_TRY(launch_power<double>(a, lds, nt, (unsigned)g));
         SV_HIP(hipGetLastError());
         return SV_OK;
     }
