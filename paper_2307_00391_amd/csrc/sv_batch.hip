@@ -7,7 +7,10 @@
 // A^{-1} b (beta_j / lambda_j, normalised) for the fidelity.
 // Per solve (instance, T0), inside the graph:
 //   turn tables (all solves, one kernel)
-//   -> per (n_s, n_c) class: the three pipeline kernels, blockIdx.z = solve
+//   -> per (n_s, n_c) class: the three pipeline kernels, blockIdx.z = solve;
+//      the classes spread over four streams (parallel branches of the graph),
+//      so that the many small classes overlap instead of each paying its
+//      launch latency in series
 //   -> one finishing kernel (all solves): FP64 sums of P(a=1) and the norm,
 //      the post-selected eigen-coefficients z_j (column sums of the clock
 //      projection), p_post = |z|^2 and F = |<x_C|x_Q>| = |sum conj(c_j) z_j| / |z|,
@@ -125,12 +128,23 @@ struct sv_batch_s {
         uint64_t nparts;      // k_pipe_b partial pairs per solve, as laid out for the finish
     };
     std::vector<Class> classes;
+    // the classes are independent: they run on kSide streams forked after the
+    // turn tables and joined before the finish (in the graph: parallel branches)
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+    std::vector<int> lane[kSide];          // class indices per side stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t own_stream = nullptr;
     ~sv_batch_s() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
+        for (int i = 0; i < kSide; ++i) {
+            if (join[i]) hipEventDestroy(join[i]);
+            if (side[i]) hipStreamDestroy(side[i]);
+        }
+        if (fork) hipEventDestroy(fork);
         if (own_stream) hipStreamDestroy(own_stream);
         for (auto *b : bufs) delete b;
         if (ctx.pinned) hipHostFree(ctx.pinned);
@@ -146,11 +160,19 @@ static sv_status enqueue_batch(sv_batch b) {
     const hipStream_t st = b->stream;
     hipLaunchKernelGGL(k_turn_batch, dim3(64, b->n_solves), dim3(256), 0, st, b->d_turn);
     SV_HIP(hipGetLastError());
-    for (auto &c : b->classes) {
-        uint64_t np = 0;
-        SV_TRY(pipe_run_batch<R>(st, c.n_s, c.n_c, c.cl, c.nt, c.d_solves, c.count, &np));
-        if (np != c.nparts) return fail(SV_EDEVICE, "partial count %llu != %llu", (unsigned long long)np,
-                                        (unsigned long long)c.nparts);
+    SV_HIP(hipEventRecord(b->fork, st));
+    for (int i = 0; i < sv_batch_s::kSide; ++i) {
+        if (b->lane[i].empty()) continue;
+        SV_HIP(hipStreamWaitEvent(b->side[i], b->fork, 0));
+        for (int ci : b->lane[i]) {
+            const auto &c = b->classes[ci];
+            uint64_t np = 0;
+            SV_TRY(pipe_run_batch<R>(b->side[i], c.n_s, c.n_c, c.cl, c.nt, c.d_solves, c.count, &np));
+            if (np != c.nparts) return fail(SV_EDEVICE, "partial count %llu != %llu", (unsigned long long)np,
+                                            (unsigned long long)c.nparts);
+        }
+        SV_HIP(hipEventRecord(b->join[i], b->side[i]));
+        SV_HIP(hipStreamWaitEvent(st, b->join[i], 0));
     }
     hipLaunchKernelGGL(k_batch_finish, dim3(b->n_solves), dim3(256), 0, st, b->d_finish);
     SV_HIP(hipGetLastError());
@@ -378,6 +400,35 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
     }
     if ((st = upload(&b->ctx, (void *)b->d_finish, fin.data(), total * sizeof(FinishJob))) != SV_OK)
         return fail_del(st);
+    // side streams (default priority) and the fork/join events; classes go to
+    // the least-loaded stream, largest first, weighed by amplitudes plus a
+    // fixed cost per class for its three launches
+    {
+        for (int i = 0; i < sv_batch_s::kSide; ++i) {
+            hipError_t e1 = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+            if (e1 != hipSuccess) return fail_del(hip_fail(e1, "hipStreamCreateWithFlags"));
+            e1 = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+            if (e1 != hipSuccess) return fail_del(hip_fail(e1, "hipEventCreateWithFlags"));
+        }
+        hipError_t e2 = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e2 != hipSuccess) return fail_del(hip_fail(e2, "hipEventCreateWithFlags"));
+        std::vector<int> order(b->classes.size());
+        std::vector<double> wgt(b->classes.size());
+        for (size_t i = 0; i < order.size(); ++i) {
+            const auto &c = b->classes[i];
+            order[i] = (int)i;
+            wgt[i] = (double)c.count * (double)dim_of(c.n_s + c.n_c) + (double)(1u << 20);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return wgt[x] > wgt[y]; });
+        double load[sv_batch_s::kSide] = {};
+        for (int ci : order) {
+            int best = 0;
+            for (int i = 1; i < sv_batch_s::kSide; ++i)
+                if (load[i] < load[best]) best = i;
+            b->lane[best].push_back(ci);
+            load[best] += wgt[ci];
+        }
+    }
     // record the whole sweep once (event tracing is paused while capturing)
     SV_HIP(hipStreamSynchronize(b->stream));
     const bool tr = trace_set(false);
