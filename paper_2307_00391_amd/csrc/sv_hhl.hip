@@ -598,15 +598,28 @@ static sv_status need(DevBuf &b, size_t bytes) { return b.ensure(bytes); }
 static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
                             double *x_out, bool dev, double2 *x_dev);
 
-// |v|^2 of an FP64 complex device vector, one workgroup, fixed order
-__global__ __launch_bounds__(256) void k_vec_norm2(const double2 *__restrict__ v, uint64_t n, double *__restrict__ out) {
+// |v|^2 of an FP64 complex device vector, first level: block b sums the
+// contiguous chunk [b*chunk, (b+1)*chunk) into tmp[b]
+__global__ __launch_bounds__(256) void k_vec_norm2(const double2 *__restrict__ v, uint64_t n, uint64_t chunk,
+                                                   double *__restrict__ tmp) {
     __shared__ double red[4];
+    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = beg + chunk < n ? beg + chunk : n;
     double a = 0.0;
-    for (uint64_t i = threadIdx.x; i < n; i += 256) a += v[i].x * v[i].x + v[i].y * v[i].y;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) a += v[i].x * v[i].x + v[i].y * v[i].y;
     a = wave_sum_f64(a);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[0] = |v|^2 in a fixed order: 64 chunk sums (tmp holds >= 64 doubles),
+// then their sum in one workgroup
+static void vec_norm2(hipStream_t st, const double2 *v, uint64_t n, double *tmp, double *out) {
+    const unsigned nb = 64;
+    const uint64_t chunk = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k_vec_norm2, dim3(nb), dim3(256), 0, st, v, n, chunk, tmp);
+    hipLaunchKernelGGL(k_sum_partials_strided, dim3(1), dim3(256), 0, st, (const double *)tmp, (int)nb, 1, out);
 }
 
 // out = in / sqrt(nrm[0]) (nrm on the device)
@@ -649,7 +662,8 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
     const bool dev = b_dev != nullptr;
     if (dev) {
         // b on the device: its norm (w.sum[2]) and b^ there
-        hipLaunchKernelGGL(k_vec_norm2, dim3(1), dim3(256), 0, st, b_dev, N, (double *)w.sum.p + 2);
+        SV_TRY(need(w.tmp2, 512 * sizeof(double)));
+        vec_norm2(st, b_dev, N, (double *)w.tmp2.p, (double *)w.sum.p + 2);
         hipLaunchKernelGGL(k_vec_normalise, dim3(grid1(N)), dim3(256), 0, st, (double2 *)w.x.p, b_dev, N,
                            (const double *)w.sum.p + 2);
         SV_HIP(hipGetLastError());
@@ -726,7 +740,8 @@ static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_
     SV_TRY(kron_apply_frame(s, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, E, 0));
     if (dev) {
         // p = |x|^2 (w.sum[3]) and the normalised x on the device; only the scalars come back
-        hipLaunchKernelGGL(k_vec_norm2, dim3(1), dim3(256), 0, st, (const double2 *)w.x.p, N, (double *)w.sum.p + 3);
+        SV_TRY(need(w.tmp2, 512 * sizeof(double)));
+        vec_norm2(st, (const double2 *)w.x.p, N, (double *)w.tmp2.p, (double *)w.sum.p + 3);
         if (x_dev)
             hipLaunchKernelGGL(k_vec_normalise, dim3(grid1(N)), dim3(256), 0, st, x_dev, (const double2 *)w.x.p, N,
                                (const double *)w.sum.p + 3);
