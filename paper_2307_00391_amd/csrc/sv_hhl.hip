@@ -238,15 +238,28 @@ __global__ __launch_bounds__(256) void k_eig_project(const cvec<R> *__restrict__
     part[((uint64_t)blockIdx.y * 4 + rg) * N + j] = make_double2(zr, zi);
 }
 
+// z[j] = scale * sum over the partial rows of column j: four interleaved
+// accumulators (rows r = k mod 4) keep four loads in flight per thread, and
+// are combined in a fixed order
 __global__ void k_sum_cols(double2 *__restrict__ z, const double2 *__restrict__ part, uint64_t N, int rows,
                            double scale) {
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (uint64_t)gridDim.x * blockDim.x) {
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < rows; ++r) {
-            re += part[(uint64_t)r * N + j].x;
-            im += part[(uint64_t)r * N + j].y;
+        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};
+        int r = 0;
+        for (; r + 4 <= rows; r += 4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double2 p = part[(uint64_t)(r + k) * N + j];
+                re[k] += p.x;
+                im[k] += p.y;
+            }
         }
-        z[j] = make_double2(re * scale, im * scale);
+        for (int k = 0; r < rows; ++r, ++k) {
+            const double2 p = part[(uint64_t)r * N + j];
+            re[k] += p.x;
+            im[k] += p.y;
+        }
+        z[j] = make_double2(((re[0] + re[1]) + (re[2] + re[3])) * scale, ((im[0] + im[1]) + (im[2] + im[3])) * scale);
     }
 }
 
