@@ -874,6 +874,20 @@ struct sv_hhl_plan_s {
     sv::EigFrame E;
     sv::DevBuf V_dense;     // V_hi (x) V_lo, built on first gate-faithful run of a Kronecker plan
     sv::Workspace w;
+    // the spectrum's range and whether it holds a zero, from E.lam (fixed once
+    // prepared), computed on first use instead of on every solve
+    bool have_range = false, has_zero = false;
+    double lam_lo = 0.0, lam_hi = 0.0;
+    void range() {
+        if (have_range) return;
+        lam_lo = lam_hi = E.lam[0];
+        for (double v : E.lam) {
+            lam_lo = fmin(lam_lo, v);
+            lam_hi = fmax(lam_hi, v);
+            if (!(v != 0.0)) has_zero = true;
+        }
+        have_range = true;
+    }
 };
 
 using namespace sv;
@@ -930,13 +944,9 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
 
 sv_status sv_hhl_plan_spectrum(sv_hhl_plan p, double *lambda_min, double *lambda_max) {
     if (!p) return fail(SV_EINVAL, "null plan");
-    double lo = p->E.lam[0], hi = p->E.lam[0];
-    for (double v : p->E.lam) {
-        lo = fmin(lo, v);
-        hi = fmax(hi, v);
-    }
-    if (lambda_min) *lambda_min = lo;
-    if (lambda_max) *lambda_max = hi;
+    p->range();
+    if (lambda_min) *lambda_min = p->lam_lo;
+    if (lambda_max) *lambda_max = p->lam_hi;
     return SV_OK;
 }
 
@@ -960,9 +970,7 @@ static sv_status hhl_run_impl(sv_hhl_plan p, sv_state s, const double *b, const 
     if (gcut == 0) {
         if (!sgn && !(res->lambda_min > 0.0))
             return fail(SV_ENOTPOSDEF, "lambda_min = %g <= 0 (unsigned clock)", res->lambda_min);
-        if (sgn)
-            for (double v : p->E.lam)
-                if (!(v != 0.0)) return fail(SV_EINVAL, "A is singular (a zero eigenvalue)");
+        if (sgn && p->has_zero) return fail(SV_EINVAL, "A is singular (a zero eigenvalue)");
     } else if (!sgn && !(res->lambda_min >= 0.0)) {
         return fail(SV_ENOTPOSDEF, "lambda_min = %g < 0 (unsigned clock)", res->lambda_min);
     }
