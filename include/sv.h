@@ -554,7 +554,10 @@ typedef struct sv_batch_s *sv_batch;
  * device buffers for every (instance, T0) state, launch configurations per
  * shape class (autotuned on first use), and the captured graph.  All inputs
  * are copied; the caller's arrays may be freed on return.  hip_stream NULL:
- * the batch creates and owns a stream.  Errors: SV_EINVAL, SV_EUNSUPPORTED,
+ * the batch creates and owns a stream.  The shape classes run on four side
+ * streams of default priority that the batch owns, forked from and joined
+ * back into its stream (parallel branches of the graph), so the batch's work
+ * stays ordered on that stream.  Errors: SV_EINVAL, SV_EUNSUPPORTED,
  * SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM, SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const sv_batch_instance *inst,
                            int n_inst);
