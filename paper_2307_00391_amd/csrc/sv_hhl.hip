@@ -564,12 +564,25 @@ __global__ void k_conj_transpose(double2 *__restrict__ out, const double2 *__res
     }
 }
 
+// out = in^T (transpose) or in, conjugated if conj, for an n x n row-major matrix
+__global__ void k_transpose_conj(double2 *__restrict__ out, const double2 *__restrict__ in, int n, int transpose,
+                                 int conj) {
+    const uint64_t total = (uint64_t)n * n;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = i / n, c = i % n;
+        const double2 v = in[transpose ? c * n + q : i];
+        out[i] = make_double2(v.x, conj ? -v.y : v.y);
+    }
+}
+
 // The basis change of a plan on the matrix cores (rocBLAS zgemm, FP64):
 // out = (V_hi (x) V_lo) in, or with the conjugate transposes (adjoint).  The
 // vector is the row-major n_hi x n_lo matrix X; column-major it is X^T, so
 //   along the low axis:  X V^T  ->  (X V^T)^T = V X^T = op_T(Vbuf) X^T
 //   along the high axis: V X    ->  (V X)^T  = X^T V^T = X^T Vbuf
-// where Vbuf, the row-major V, reads as V^T column-major.
+// where Vbuf, the row-major V, reads as V^T column-major.  The low axis takes
+// the row-major V^T (forward) or conj(V) (adjoint), read as V or V^H
+// column-major, so that both products run without a transposed operand.
 static sv_status kron_apply_frame(sv_state s, double2 *out, const double2 *in, double2 *tmp, const EigFrame &E,
                                   int adjoint) {
     rocblas_handle h;
@@ -578,8 +591,8 @@ static sv_status kron_apply_frame(sv_state s, double2 *out, const double2 *in, d
     const rocblas_int nh = E.n_hi, nl = E.n_lo;
     const double2 *Whi = (const double2 *)(adjoint ? E.VH_hi.p : E.V_hi.p);
     if (nl > 1) {
-        const double2 *Wlo = (const double2 *)(adjoint ? E.VH_lo.p : E.V_lo.p);
-        if (rocblas_zgemm(h, rocblas_operation_transpose, rocblas_operation_none, nl, nh, nl, &one,
+        const double2 *Wlo = (const double2 *)(adjoint ? E.VC_lo.p : E.VT_lo.p);
+        if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, nl, nh, nl, &one,
                           (const rocblas_double_complex *)Wlo, nl, (const rocblas_double_complex *)in, nl, &zero,
                           (rocblas_double_complex *)tmp, nl) != rocblas_status_success)
             return fail(SV_EDEVICE, "rocblas_zgemm (low axis) failed");
@@ -923,12 +936,19 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
     // conjugate transposes for the basis change into the eigen-frame
     if (st == SV_OK) st = p->E.VH_hi.alloc((size_t)nh * nh * sizeof(double2));
     if (st == SV_OK && m_lo) st = p->E.VH_lo.alloc((size_t)nl * nl * sizeof(double2));
+    if (st == SV_OK && m_lo) st = p->E.VT_lo.alloc((size_t)nl * nl * sizeof(double2));
+    if (st == SV_OK && m_lo) st = p->E.VC_lo.alloc((size_t)nl * nl * sizeof(double2));
     if (st == SV_OK) {
         hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nh * nh)), dim3(256), 0, s->stream,
                            (double2 *)p->E.VH_hi.p, (const double2 *)p->E.V_hi.p, nh);
-        if (m_lo)
+        if (m_lo) {
             hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
                                (double2 *)p->E.VH_lo.p, (const double2 *)p->E.V_lo.p, nl);
+            hipLaunchKernelGGL(k_transpose_conj, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
+                               (double2 *)p->E.VT_lo.p, (const double2 *)p->E.V_lo.p, nl, 1, 0);
+            hipLaunchKernelGGL(k_transpose_conj, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
+                               (double2 *)p->E.VC_lo.p, (const double2 *)p->E.V_lo.p, nl, 0, 1);
+        }
         const hipError_t he = hipGetLastError();
         if (he != hipSuccess) st = hip_fail(he, "k_conj_transpose");
     }

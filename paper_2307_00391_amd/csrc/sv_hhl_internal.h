@@ -55,6 +55,8 @@ struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;
     DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
     DevBuf VH_hi, VH_lo;          // their conjugate transposes (for the V^H basis change)
+    DevBuf VT_lo, VC_lo;          // V_lo^T and conj(V_lo), row-major: the low-axis GEMM's operand
+                                  // without a transpose, forward and adjoint
     DevBuf lam_dev;               // the eigenvalues on the device (FP64)
     std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
 };
