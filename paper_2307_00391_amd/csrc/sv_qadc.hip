@@ -30,6 +30,7 @@
 //           one read and one write of the state.  The remaining steps are
 //           the mode-0 gates.
 #include <math.h>
+#include <stdlib.h>
 
 #include <cmath>
 #include <vector>
@@ -189,6 +190,77 @@ __global__ __launch_bounds__(256) void k_qadc_power(cvec<R> *__restrict__ psi, c
     }
 }
 
+// The same Q^t for n = 3 and 4, with 64 / N columns of equal t in one
+// wavefront: the (address, up) pairs sharing a ub value t are consecutive in
+// groups of G = 64 / N, lane l works on line entry l mod N of column l / N, and
+// the DPP sums stay inside each N-lane group, so every lane of the wave takes
+// part in the reflections (one column per wave left 64 - N lanes idle).
+template <typename R, int NL>
+__global__ __launch_bounds__(64) void k_qadc_power_packed(cvec<R> *__restrict__ psi, const R *__restrict__ vhh,
+                                                          QadcArgs a) {
+    extern __shared__ unsigned char lds_raw[];
+    constexpr int n = NL;
+    constexpr uint32_t N = 1u << NL, B = N * N, P = N + 1u, G = 64u / N;
+    constexpr uint32_t per_t = 2u * N / G;           // groups per ub value
+    cvec<R> *blk = reinterpret_cast<cvec<R> *>(lds_raw);       // G blocks of 2 N P entries
+    const uint64_t ngroups = (1ull << a.r) * per_t;
+    const uint64_t off1 = 1ull << (3 * n);
+    for (uint64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const uint32_t t = (uint32_t)(grp / per_t);
+        if (t == 0) continue;                        // Q^0: the columns are left as they are
+        const uint32_t c0 = (uint32_t)(grp % per_t) * G;          // first (address, up) pair
+        // column j of the group: address (c0 + j) mod N, up = (c0 + j) / N
+        for (uint32_t e = threadIdx.x; e < G * B; e += 64) {
+            const uint32_t j = e / B, f = e % B, cc = c0 + j;
+            const uint64_t base = ((uint64_t)(cc & (N - 1u)) << (2 * n)) |
+                                  (((uint64_t)t | ((uint64_t)(cc >> n) << a.r)) << (3 * n + 1));
+            const uint32_t l = j * 2u * N * P + (f & (N - 1u)) + (f >> n) * P;
+            blk[l] = psi[base | f];
+            blk[l + N * P] = psi[base | off1 | f];
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < G; ++j)
+            qadc_swap_test<R>(blk + j * 2u * N * P, blk + j * 2u * N * P + N * P, n, !a.inverse, false);
+        __syncthreads();
+        {
+            const uint32_t l = threadIdx.x, j = l >> n, i = l & (N - 1u);
+            const uint32_t sj = (c0 + j) & (N - 1u);
+            cvec<R> *X = blk + j * 2u * N * P;
+            const R c = vhh[N];
+            const R w = (i == 0 ? (R)1 : (R)0) - c * vhh[i] * vhh[0];   // U_V|0>
+            const R w2 = w + w;
+            cvec<R> cl = X[i + sj * P];              // column sj: (i, sj)
+            cvec<R> rw = X[sj + i * P];              // row sj: (sj, i)
+            for (uint32_t k = 0; k + 1 < t; k += 2) {
+                cl = reflect_line<R, N>(cl, w, w2);
+                if (i == sj) rw = cl;
+                rw = reflect_line<R, N>(rw, w, w2);
+                if (i == sj) cl = rw;
+            }
+            if (t & 1u) {
+                cl = reflect_line<R, N>(cl, w, w2);
+                if (i == sj) rw = cl;
+            }
+            X[i + sj * P] = cl;
+            X[sj + i * P] = rw;
+        }
+        __syncthreads();
+        const bool neg = (((t - 1u) & 1u) != 0u) != (a.inverse != 0);
+        for (uint32_t j = 0; j < G; ++j)
+            qadc_swap_test<R>(blk + j * 2u * N * P, blk + j * 2u * N * P + N * P, n, false, neg);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < G * B; e += 64) {
+            const uint32_t j = e / B, f = e % B, cc = c0 + j;
+            const uint64_t base = ((uint64_t)(cc & (N - 1u)) << (2 * n)) |
+                                  (((uint64_t)t | ((uint64_t)(cc >> n) << a.r)) << (3 * n + 1));
+            const uint32_t l = j * 2u * N * P + (f & (N - 1u)) + (f >> n) * P;
+            psi[base | f] = blk[l];
+            psi[base | off1 | f] = blk[l + N * P];
+        }
+        __syncthreads();
+    }
+}
+
 namespace {
 
 struct Layout {
@@ -228,6 +300,16 @@ sv_gate gate_ctrl(sv_gate g, int ctrl, int val) {
     g.ctrl_vals[g.n_ctrls] = val;
     ++g.n_ctrls;
     return g;
+}
+
+// SV_QADC_PACKED=0 keeps one column per workgroup for every address width
+int packed_env() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("SV_QADC_PACKED");
+        v = (e && atoi(e) == 0) ? 0 : 1;
+    }
+    return v;
 }
 
 class Qadc {
@@ -351,8 +433,22 @@ public:
                            (const R *)vh_.p, a);
         return SV_OK;
     }
+    template <typename R, int NL>
+    sv_status launch_packed(const QadcArgs &a) {
+        constexpr uint32_t N = 1u << NL, G = 64u / N;
+        const size_t lds = (size_t)G * 2 * N * (N + 1) * sizeof(cvec<R>);
+        uint64_t groups = (1ull << a.r) * (2ull * N / G);
+        if (groups > (1u << 20)) groups = 1u << 20;
+        hipLaunchKernelGGL((k_qadc_power_packed<R, NL>), dim3((unsigned)groups), dim3(64), lds, s_->stream,
+                           (cvec<R> *)s_->data, (const R *)vh_.p, a);
+        return SV_OK;
+    }
     template <typename R>
     sv_status launch_power(const QadcArgs &a, size_t lds, int nt, unsigned g) {
+        if (packed_env()) {
+            if (a.n == 3) return launch_packed<R, 3>(a);
+            if (a.n == 4) return launch_packed<R, 4>(a);
+        }
         switch (a.n) {
         case 1: return launch_one<R, 1>(a, lds, nt, g);
         case 2: return launch_one<R, 2>(a, lds, nt, g);
