@@ -27,8 +27,9 @@
 //           applies Q^t there (Q^dagger for the uncompute), reduced by exact
 //           identities of its factors to two SWAP tests around t reflections
 //           of one N-entry line (k_qadc_power), so the 2^r - 1 iterates cost
-//           one read and one write of the state.  The remaining steps are
-//           the mode-0 gates.
+//           one read and one write of the state.  U_V is one pass of the
+//           reflection on each ua row (k_qadc_loader); the remaining steps
+//           are the mode-0 gates.
 #include <math.h>
 #include <stdlib.h>
 
@@ -261,6 +262,26 @@ __global__ __launch_bounds__(64) void k_qadc_power_packed(cvec<R> *__restrict__ 
     }
 }
 
+// U_V on the ua register ([0, n), contiguous) of every row in one pass: each
+// aligned group of N lanes holds one row, forms v.z with DPP sums and writes
+// z - c v (v.z).  The state has at least 64 amplitudes, a multiple of the
+// 64-lane stride, so every group runs its loop trips together.
+template <typename R, int NL>
+__global__ __launch_bounds__(256) void k_qadc_loader(cvec<R> *__restrict__ psi, const R *__restrict__ vhh,
+                                                     uint64_t total) {
+    constexpr uint32_t N = 1u << NL;
+    const uint32_t i = threadIdx.x & (N - 1u);
+    const R c = vhh[N], vi = vhh[i];
+    for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (uint64_t)gridDim.x * blockDim.x) {
+        cvec<R> z = psi[idx];
+        const R dx = c * group_sum<R, N>(vi * z.x), dy = c * group_sum<R, N>(vi * z.y);
+        z.x -= vi * dx;
+        z.y -= vi * dy;
+        psi[idx] = z;
+    }
+}
+
 namespace {
 
 struct Layout {
@@ -379,8 +400,35 @@ public:
     }
     sv_status loader() {
         SV_TRY(flush());
+        if (fused_ && L.n <= 6) {
+            if (s_->dt == SV_C64) return launch_loader<float>();
+            return launch_loader<double>();
+        }
         if (s_->dt == SV_C64) return ctrl_unitary_impl<float>(s_, (const float2 *)U_.p, L.n, -1, 0, 0);
         return ctrl_unitary_impl<double>(s_, (const double2 *)U_.p, L.n, -1, 0, 0);
+    }
+    template <typename R, int NL>
+    sv_status loader_one() {
+        const uint64_t total = dim_of(s_->n);
+        uint64_t g = total / 256;
+        if (g < 1) g = 1;
+        if (g > (1u << 20)) g = 1u << 20;
+        TraceScope ts(s_->stream, "qadc_loader", 2.0 * (double)total * sizeof(cvec<R>), 16.0 * (double)total);
+        hipLaunchKernelGGL((k_qadc_loader<R, NL>), dim3((unsigned)g), dim3(256), 0, s_->stream, (cvec<R> *)s_->data,
+                           (const R *)vh_.p, total);
+        SV_HIP(hipGetLastError());
+        return SV_OK;
+    }
+    template <typename R>
+    sv_status launch_loader() {
+        switch (L.n) {
+        case 1: return loader_one<R, 1>();
+        case 2: return loader_one<R, 2>();
+        case 3: return loader_one<R, 3>();
+        case 4: return loader_one<R, 4>();
+        case 5: return loader_one<R, 5>();
+        default: return loader_one<R, 6>();
+        }
     }
     sv_status W() {
         SV_TRY(loader());
@@ -488,6 +536,7 @@ public:
     }
 
     sv_status run(int mode, int avg, const std::vector<double> &zeta, double *sq_out, sv_qadc_result *res) {
+        fused_ = mode == 1;
         SV_TRY(prepare(zeta));
         SV_TRY(sv_init_basis(s_, 0));
         const int n = L.n, r = L.r;
@@ -560,6 +609,7 @@ private:
     Layout L;
     DevBuf U_, vh_;
     std::vector<sv_gate> q_;
+    bool fused_ = false;     // mode 1: U_V as the one-pass reflection kernel
 };
 
 }  // namespace
