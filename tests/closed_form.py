@@ -10,6 +10,8 @@ and p = sum_j |beta_j g_j|^2.  Pinned against the gate-level oracle in
 test_oracle_hhl.py.
 """
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -37,6 +39,43 @@ def g_of_phi(phi, n_c, chunk=64, signed=False):
     return out
 
 
+def g_h_of_phi_wide(phi, n_c, chunk=32, workers=None):
+    """(g, h) per eigenphase for wide clocks (n_c up to 15 on 2^16 phases):
+    g = sum_{y>=1} K(phi - y/M) / y as in g_of_phi, and
+    h = sum_{y>=1} K(phi - y/M) / y^2, the ancilla-1 weight (the rotation's
+    |1> amplitude is 1/y).  Written with u = M phi once: K(phi - y/M) =
+    sin^2(pi r) / (M^2 sin^2(pi (u - y) / M)) with r = u - rint(u), so the
+    numerator's argument reduction is exact and numerator and denominator
+    come from the same rounded u (no cancellation error near the clock grid).
+    Phases with u an exact integer (K = 1 at y = u, 0 elsewhere) are handled
+    apart.  Numpy releases the GIL in the ufuncs: chunks run on threads."""
+    M = 1 << n_c
+    y = np.arange(1, M, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    u = phi * M
+    r = u - np.rint(u)
+    g = np.empty_like(phi)
+    h = np.empty_like(phi)
+
+    def work(a):
+        uu = u[a:a + chunk, None]
+        s = np.sin((uu - y[None, :]) * (math.pi / M))
+        num = np.sin(math.pi * r[a:a + chunk]) ** 2 / (M * M)
+        with np.errstate(divide="ignore", invalid="ignore"):   # exact-grid rows, replaced below
+            w = 1.0 / (s * s)
+            g[a:a + chunk] = num * (w / y[None, :]).sum(axis=1)
+            h[a:a + chunk] = num * (w / (y * y)[None, :]).sum(axis=1)
+
+    with ThreadPoolExecutor(workers or min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, phi.size, chunk)))
+    exact = r == 0.0
+    if exact.any():
+        yy = np.mod(np.rint(u[exact]), M)
+        g[exact] = np.where(yy >= 1, 1.0 / np.maximum(yy, 1), 0.0)
+        h[exact] = np.where(yy >= 1, 1.0 / np.maximum(yy, 1) ** 2, 0.0)
+    return g, h
+
+
 def hhl_closed_form(A, b, n_c, T0, signed=False):
     lam, V = np.linalg.eigh(A)
     beta = V.conj().T @ (b / np.linalg.norm(b))
@@ -44,6 +83,17 @@ def hhl_closed_form(A, b, n_c, T0, signed=False):
     z = V @ (beta * g)
     p = float(np.sum(np.abs(beta * g) ** 2))
     return z / math.sqrt(p), p
+
+
+def hhl_probabilities(A, b, n_c, T0):
+    """(p_post, p_anc) of the unsigned-clock circuit: P(a = 1, clock = 0) =
+    sum_j |beta_j g_j|^2 and P(a = 1) = sum_j |beta_j|^2 h_j, with g, h as in
+    g_h_of_phi_wide (the ancilla-1 probability of clock value y is 1/y^2, and
+    phase estimation puts K(phi_j - y/M) of eigencomponent j on y)."""
+    lam, V = np.linalg.eigh(A)
+    beta = V.conj().T @ (b / np.linalg.norm(b))
+    g, h = g_h_of_phi_wide(lam * T0 / (2 * math.pi), n_c)
+    return float(np.sum(np.abs(beta * g) ** 2)), float(np.sum(np.abs(beta) ** 2 * h))
 
 
 def hhl_closed_form_kron(A_hi, A_lo, b, n_c, T0):

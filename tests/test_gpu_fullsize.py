@@ -1,10 +1,11 @@
 """Full-size GPU checks (the sizes bench.py times), where the oracle cannot run.
 
 * 32-qubit HHL (n_s = 16 Kronecker-sum Laplacian + perturbation, kappa = 1000,
-  n_c = 15): the post-selected amplitudes are compared, on 4096 sampled
-  eigen-components, with the circuit's closed form (pinned against the
-  oracle in test_oracle_hhl.py); complex64 to 1e-5 and complex128 to 1e-12
-  in state-amplitude units.
+  n_c = 15): the whole normalised post-selected vector (2^16 entries) against
+  the circuit's closed form over every eigencomponent (pinned against the
+  oracle in test_oracle_hhl.py), by relative l2 (1e-5 complex64, 1e-10
+  complex128) and max-abs; p_post and P(a = 1) relative to their closed
+  forms; the complex64 x against the complex128 x.
 * 33-qubit U3 + CNOT-ladder probe: the norm is preserved and the circuit
   followed by its inverse returns |0...0>; and, through the same fused
   passes, the probe's 20 U3 layers followed by one CNOT ladder, whose output
@@ -18,7 +19,7 @@ import pytest
 
 from paper_2307_00391_amd import binding as B
 from paper_2307_00391_amd import inputs
-from tests.closed_form import g_of_phi
+from tests.closed_form import g_h_of_phi_wide
 
 pytestmark = pytest.mark.gpu
 
@@ -36,48 +37,95 @@ def _free_mem():
     return torch.cuda.mem_get_info()[0]
 
 
-@pytest.mark.parametrize("dt,tol,mode,device", [("c64", 1e-5, 1, True), ("c64", 1e-5, 1, False),
-                                                ("c128", 1e-12, 1, False), ("c64", 1e-5, 2, False)])
-def test_hhl_32_qubits_against_closed_form(dt, tol, mode, device):
-    """device: b and x in HBM (sv_hhl_run_device), as the benchmark times it."""
+# relative-l2 bars on the whole post-selected vector and relative bars on the
+# probabilities: FP32 amplitudes carry ~1e-7 relative rounding per operation
+# over the ~30 dependent butterfly and rotation stages; FP64 stays near 1e-13.
+REL = {"c64": 1e-5, "c128": 1e-10}
+
+
+@pytest.fixture(scope="module")
+def hhl32_case():
+    """The 32-qubit workload and its closed form over all 2^16 eigencomponents:
+    x = V (beta g) / sqrt(p), p = sum |beta g|^2, p_anc = sum |beta|^2 h."""
     m_hi = m_lo = 8
     n_c = 15
-    n = m_hi + m_lo + n_c + 1
-    need = (1 << n) * (8 if dt == "c64" else 16)
-    if _free_mem() < need * 1.1:
-        pytest.skip("not enough device memory")
     ks = inputs.kron_laplacian_system(inputs.rng_for(3, 0), m_hi, m_lo, kappa=1000.0)
     T0 = inputs.t0_top_of_clock(ks.lambda_max, n_c)
-    st = B.State(n, dt)
-    plan = B.sv_hhl_prepare(st.h, ks.A_hi, ks.A_lo)
-    if device:
-        import torch
-        b_dev = torch.tensor(np.asarray(ks.b, dtype=np.complex128), device="cuda")
-        x_dev = torch.empty(1 << (m_hi + m_lo), dtype=torch.complex128, device="cuda")
-        res = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, mode, x_dev=x_dev)
-        x = x_dev.cpu().numpy()
-    else:
-        x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, mode)
-    B.sv_hhl_plan_free(plan)
-    st.close()
-    # eigen-basis view of the GPU result: z = V^H x sqrt(p)
     mu, P = np.linalg.eigh(ks.A_hi)
     nu, Q = np.linalg.eigh(ks.A_lo)
-    X = x.reshape(1 << m_hi, 1 << m_lo)
-    Z_gpu = (P.conj().T @ X @ Q.conj()) * math.sqrt(res.p_post)
     Bm = (ks.b / np.linalg.norm(ks.b)).reshape(1 << m_hi, 1 << m_lo)
     beta = P.conj().T @ Bm @ Q.conj()
     lam = mu[:, None] + nu[None, :]
-    rng = np.random.default_rng(32)
-    idx = rng.choice(lam.size, size=4096, replace=False)
-    idx = np.union1d(idx, [0, lam.size - 1, int(np.argmax(np.abs(beta).ravel()))])
-    g = g_of_phi(lam.ravel()[idx] * T0 / (2 * math.pi), n_c, chunk=128)
-    z_true = beta.ravel()[idx] * g
-    err = np.abs(Z_gpu.ravel()[idx] - z_true).max()
-    assert err <= tol, err
-    assert abs(res.lambda_min - lam.min()) <= 1e-12 * lam.max()
+    g, h = g_h_of_phi_wide((lam * T0 / (2 * math.pi)).ravel(), n_c)
+    Z = beta * g.reshape(lam.shape)
+    p_post = float(np.sum(np.abs(Z) ** 2))
+    p_anc = float(np.sum(np.abs(beta) ** 2 * h.reshape(lam.shape)))
+    x_true = (P @ Z @ Q.T).reshape(-1) / math.sqrt(p_post)
+    return dict(ks=ks, n_c=n_c, T0=T0, m_hi=m_hi, m_lo=m_lo, lam=lam, x=x_true, p_post=p_post,
+                p_anc=p_anc, got={})
+
+
+def _run32(case, dt, mode, device):
+    ks, n_c, T0 = case["ks"], case["n_c"], case["T0"]
+    n_s = case["m_hi"] + case["m_lo"]
+    n = n_s + n_c + 1
+    need = (1 << n) * (8 if dt == "c64" else 16)
+    if _free_mem() < need * 1.1:
+        pytest.skip("not enough device memory")
+    st = B.State(n, dt)
+    plan = B.sv_hhl_prepare(st.h, ks.A_hi, ks.A_lo)
+    try:
+        if device:
+            import torch
+            b_dev = torch.tensor(np.asarray(ks.b, dtype=np.complex128), device="cuda")
+            x_dev = torch.empty(1 << n_s, dtype=torch.complex128, device="cuda")
+            res = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, mode, x_dev=x_dev)
+            x = x_dev.cpu().numpy()
+        else:
+            x, res = B.sv_hhl_run(plan, st.h, ks.b, n_c, T0, mode)
+    finally:
+        B.sv_hhl_plan_free(plan)
+        st.close()
+    return x, res
+
+
+@pytest.mark.parametrize("dt,mode,device", [("c64", 1, True), ("c64", 1, False), ("c128", 1, False),
+                                            ("c64", 2, False)])
+def test_hhl_32_qubits_against_closed_form(hhl32_case, dt, mode, device):
+    """device: b and x in HBM (sv_hhl_run_device), as the benchmark times it.
+    The whole normalised x (2^16 entries) against the closed form: relative
+    l2 and max-abs; p_post and p_anc relative to their closed forms."""
+    c = hhl32_case
+    x, res = _run32(c, dt, mode, device)
+    c["got"][(dt, mode, device)] = x
+    rel = np.linalg.norm(x - c["x"]) / np.linalg.norm(c["x"])
+    amax = np.abs(x - c["x"]).max()
+    print(f"32q {dt} mode {mode} device {device}: rel-l2 {rel:.3e} max-abs {amax:.3e} "
+          f"p_post {res.p_post:.9e} (closed form {c['p_post']:.9e}) p_anc {res.p_anc:.9e} ({c['p_anc']:.9e})",
+          flush=True)
+    assert rel <= REL[dt], rel
+    assert amax <= (1e-5 if dt == "c64" else 1e-12), amax
+    assert abs(res.p_post - c["p_post"]) <= REL[dt] * c["p_post"], (res.p_post, c["p_post"])
+    assert abs(res.p_anc - c["p_anc"]) <= REL[dt] * c["p_anc"], (res.p_anc, c["p_anc"])
+    assert abs(res.lambda_min - c["lam"].min()) <= 1e-12 * c["lam"].max()
     assert abs(res.norm_total - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
-    assert 0 < res.p_post <= res.p_anc <= 1.0
+
+
+def test_hhl_32_qubits_c64_against_c128(hhl32_case):
+    """The mixed-precision claim at full size: the complex64 solve's x within
+    the FP32 bars of the complex128 solve's x (both from the same plan kind,
+    b and x on the host)."""
+    c = hhl32_case
+    x64 = c["got"].get(("c64", 1, False))
+    if x64 is None:
+        x64, _ = _run32(c, "c64", 1, False)
+    x128 = c["got"].get(("c128", 1, False))
+    if x128 is None:
+        x128, _ = _run32(c, "c128", 1, False)
+    rel = np.linalg.norm(x64 - x128) / np.linalg.norm(x128)
+    print(f"32q c64 vs c128: rel-l2 {rel:.3e} max-abs {np.abs(x64 - x128).max():.3e}", flush=True)
+    assert rel <= REL["c64"]
+    assert np.abs(x64 - x128).max() <= 1e-5
 
 
 def test_probe_33_qubits_norm_and_roundtrip():

@@ -1,0 +1,109 @@
+"""The batched T0 sweep at the sizes it is benchmarked on.
+
+Eight instances of the sweep family (n_s 4..10, n_c 8..12, kappa 13..7826,
+13 to 23 qubits, the last from beyond the first 64 so that the n_s = 10,
+n_c = 12 class is present) over their full 16-point T0 grids, 128 solves in
+one graph launch.  Every solve's P(a = 1, clock = 0), P(a = 1) and fidelity
+against the closed form of the circuit (tests/closed_form.py, pinned to the
+gate-level oracle in test_oracle_hhl.py); every instance's single-solve x
+against the closed form, and two of them (13 and 16 qubits) element by
+element against the oracle itself.
+
+Bars: the FP32 bar of 1e-5 relative l2 on the post-selected vector implies
+|dp|/p <= 2e-5 + (1e-5)^2 on p_post and |dF| <= 1e-5 on F; complex128 to
+1e-10 relative (the closed form's own Fejer sums are good to ~1e-12).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00391_amd import binding as B
+from paper_2307_00391_amd import inputs
+from tests.closed_form import g_h_of_phi_wide
+
+pytestmark = pytest.mark.gpu
+
+INSTANCES = [83, 0, 45, 12, 2, 15, 37, 17]
+REL = {"c64": 2e-5, "c128": 1e-10}
+FTOL = {"c64": 1e-5, "c128": 1e-10}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+@pytest.fixture(scope="module")
+def family():
+    ins = [inputs.sweep_instances(1, first=i)[0] for i in INSTANCES]
+    assert max(i.n_s + i.n_c + 1 for i in ins) == 23
+    ref = []
+    for it in ins:
+        lam, V = np.linalg.eigh(it.A)
+        beta = V.T @ (it.b / np.linalg.norm(it.b))
+        xc = np.linalg.solve(it.A, it.b)
+        xc /= np.linalg.norm(xc)
+        rows = []
+        for T0 in it.t0:
+            g, h = g_h_of_phi_wide(lam * T0 / (2 * math.pi), it.n_c, workers=4)
+            z = V @ (beta * g)
+            p_post = float(np.sum((beta * g) ** 2))
+            p_anc = float(np.sum(beta ** 2 * h))
+            rows.append((p_post, p_anc, abs(np.vdot(xc, z)) / np.linalg.norm(z), z / math.sqrt(p_post)))
+        ref.append(rows)
+    return ins, ref
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_sweep_family_batch_against_closed_form(family, dt):
+    ins, ref = family
+    probs = [(it.A, it.b, it.n_c, it.t0) for it in ins]
+    h = B.sv_batch_prepare(probs, dt)
+    try:
+        assert B.sv_batch_num_solves(h) == 16 * len(ins)
+        res = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    worst = [0.0, 0.0, 0.0]
+    k = 0
+    for it, rows in zip(ins, ref):
+        for m, (p_post, p_anc, F, _) in enumerate(rows):
+            pp, pa, nt, Fg = res[k]
+            e = (abs(pp - p_post) / p_post, abs(pa - p_anc) / p_anc, abs(Fg - F))
+            worst = [max(a, b) for a, b in zip(worst, e)]
+            assert e[0] <= REL[dt], (it.index, m, pp, p_post)
+            assert e[1] <= REL[dt], (it.index, m, pa, p_anc)
+            assert e[2] <= FTOL[dt], (it.index, m, Fg, F)
+            assert abs(nt - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
+            k += 1
+    print(f"sweep family {dt}: worst relative p_post {worst[0]:.2e}, p_anc {worst[1]:.2e}, |dF| {worst[2]:.2e}",
+          flush=True)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_sweep_family_single_solves(family, dt):
+    """x of single solves through sv_hhl_run against the closed form for every
+    instance at one T0, and against the gate-level oracle for the 13- and
+    16-qubit instances (the oracle's Jacobi eigensolver is cubic in N)."""
+    ins, ref = family
+    for it, rows in zip(ins, ref):
+        m = it.index % 16
+        T0 = it.t0[m]
+        st = B.State(it.n_s + it.n_c + 1, dt)
+        try:
+            x, r = B.sv_hhl(st.h, it.A, it.b, it.n_c, T0, 1)
+        finally:
+            st.close()
+        x_cf = rows[m][3]
+        rel = np.linalg.norm(x - x_cf)
+        assert rel <= (1e-5 if dt == "c64" else 1e-10), (it.index, rel)
+        if it.index in (17, 15):
+            _, x_o, pp_o, _ = oracle.hhl(it.A, it.b, it.n_c, T0)
+            tol = 1e-5 if dt == "c64" else 1e-12
+            assert np.abs(x - x_o).max() <= tol, (it.index, np.abs(x - x_o).max())
+            assert abs(r.p_post - pp_o) <= REL[dt] * pp_o

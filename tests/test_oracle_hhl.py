@@ -151,3 +151,60 @@ def test_couette_config_end_to_end():
     F = fidelity(x, np.linalg.solve(s.A, s.b))
     assert abs(F - fidelity(xr, np.linalg.solve(s.A, s.b))) < 1e-11
     assert F < 0.5                       # lam_min below the least count: low by construction
+
+
+def test_wide_clock_closed_form_matches_direct_sum():
+    """The wide-clock evaluation (one rounded u = M phi for numerator and
+    denominator) against the direct Fejer sum, off the grid, next to grid
+    points and exactly on them."""
+    from tests.closed_form import g_h_of_phi_wide, g_of_phi
+    rng = np.random.default_rng(21)
+    for n_c in (3, 6, 10):
+        M = 1 << n_c
+        phi = np.concatenate([rng.uniform(-0.2, 1.3, 64), (rng.integers(0, M, 8) + 1e-9) / M,
+                              (rng.integers(0, M, 8) - 3e-7) / M])
+        g, h = g_h_of_phi_wide(phi, n_c, workers=2)
+        y = np.arange(1, M, dtype=np.float64)
+        from tests.closed_form import fejer
+        K = fejer(phi[:, None] - y[None, :] / M, M)
+        np.testing.assert_allclose(g, g_of_phi(phi, n_c), rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(h, (K / (y * y)[None, :]).sum(axis=1), rtol=1e-11, atol=1e-14)
+        on = np.arange(M) / M                       # exactly on the grid: K is 1 at one clock value
+        g_on, h_on = g_h_of_phi_wide(on, n_c, workers=2)
+        yy = np.arange(M)
+        np.testing.assert_array_equal(g_on, np.where(yy > 0, 1.0 / np.maximum(yy, 1), 0.0))
+        np.testing.assert_array_equal(h_on, np.where(yy > 0, 1.0 / np.maximum(yy, 1) ** 2, 0.0))
+
+
+@pytest.mark.parametrize("seed,n_s,n_c", [(31, 2, 4), (32, 3, 6), (33, 4, 5)])
+def test_probabilities_closed_form_match_oracle(seed, n_s, n_c):
+    """P(a = 1, clock = 0) and P(a = 1) of the gate-level oracle against
+    sum_j |beta_j g_j|^2 and sum_j |beta_j|^2 sum_y K(phi_j - y/M) / y^2."""
+    from tests.closed_form import hhl_probabilities
+    rng = np.random.default_rng(seed)
+    A, _, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, 40.0)
+    b = rng.standard_normal(1 << n_s) + 1j * rng.standard_normal(1 << n_s)
+    T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.91
+    _, _, p_post, p_anc = oracle.hhl(A, b, n_c, T0)
+    pp, pa = hhl_probabilities(A, b, n_c, T0)
+    assert abs(pp - p_post) < 1e-13 and abs(pa - p_anc) < 1e-13, (pp, p_post, pa, p_anc)
+
+
+def test_workload_values_recorded_with_the_configs():
+    """Fidelity and post-selection probability of the two flow workloads, as
+    an independent closed-form evaluation recorded them when the workloads
+    were defined (printed to the digits given): Poiseuille (N = 16, n_c = 6)
+    F = 0.995352, p = 0.2255; Couette (N = 256, n_c = 10) F = 0.4070,
+    p = 1.74e-4.  The oracle's Poiseuille solve and the closed form of the
+    Couette one (pinned to the oracle above) must reproduce them."""
+    s = inputs.poiseuille(16)
+    T0 = inputs.t0_top_of_clock(s.lambda_max, 6)
+    _, x, p_post, _ = oracle.hhl(s.A, s.b, 6, T0)
+    assert abs(fidelity(x, np.linalg.solve(s.A, s.b)) - 0.995352) <= 5e-7
+    assert abs(p_post - 0.2255) <= 5e-5
+    c = inputs.couette(256)
+    T0 = inputs.t0_top_of_clock(c.lambda_max, 10)
+    xr, pr = hhl_closed_form(c.A, c.b, 10, T0)
+    assert abs(fidelity(xr, np.linalg.solve(c.A, c.b)) - 0.4070) <= 5e-5
+    assert abs(pr - 1.74e-4) <= 5e-7
+    assert abs(s.lambda_max - 1146.158452) <= 5e-7 and abs(T0 - 2.375995e-5) <= 5e-12
