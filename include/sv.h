@@ -185,6 +185,24 @@ sv_status sv_norm2(sv_state s, uint64_t mask, uint64_t value, double *out);
 sv_status sv_postselect(sv_state s, uint64_t mask, uint64_t value, double *prob, void *out,
                         int out_on_device);
 
+/* The post-selection of sv_postselect with every result left on the device,
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls no
+ * hipMalloc, hipFree or allocating library routine and never synchronises.
+ *   prob_dev: device, 1 double (caller-owned): P((i & mask) == value), FP64,
+ *             summed in the same fixed order as sv_postselect (the same bits).
+ *   out_dev:  device (caller-owned, may be NULL): 2^(n - popcount(mask))
+ *             amplitudes in the state's dtype, increasing index order, divided
+ *             by sqrt(*prob_dev).  A zero probability is not detected (the
+ *             call is asynchronous): out_dev then holds inf/NaN; check *prob_dev.
+ * Workspace: a fixed array of 4096 + 64 doubles (33 KiB) per device in the
+ * library's static device memory, held until the process ends; the reduction
+ * never needs more than 4096 partial sums, so every state size fits.  Calls
+ * that overlap on one device (different host threads or streams) share that
+ * array and race; serialise them.  Enqueued on the state's stream.
+ * Errors: SV_EINVAL (NULL prob_dev, value outside mask), SV_EDEVICE. */
+sv_status sv_postselect_noalloc(sv_state s, uint64_t mask, uint64_t value, double *prob_dev, void *out_dev);
+
 /* ------------------------------------------------------------------------
  * HHL (QLSA-1, main text "Quantum Linear Systems Algorithm"; phase
  * estimation with exp(i A T0) and least count 2^-n_c, "Flow simulation

@@ -106,6 +106,7 @@ _SIGS = {
     "sv_apply_uniform_ry": ([_P, _I, _I, _I, _P, _I, _I], _I),
     "sv_norm2": ([_P, _U64, _U64, _DP], _I),
     "sv_postselect": ([_P, _U64, _U64, _DP, _P, _I], _I),
+    "sv_postselect_noalloc": ([_P, _U64, _U64, _P, _P], _I),
     "sv_hhl": ([_P, _P, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
     "sv_hhl_kron": ([_P, _P, _I, _P, _I, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
     "sv_hhl_prepare": ([ctypes.POINTER(_P), _P, _P, _I, _P, _I], _I),
@@ -329,6 +330,22 @@ def sv_postselect(h, n, mask, value, want_vector=True):
         out = np.zeros(1 << (n - bin(int(mask)).count("1")), dtype=np.complex128)
     _check(lib().sv_postselect(h, int(mask), int(value), ctypes.byref(p), _ptr(out), 0), "sv_postselect")
     return p.value, out
+
+
+def sv_postselect_device(h, mask, value, out_dev=None):
+    """sv_postselect with the vector left on the device (out_on_device = 1):
+    out_dev is a contiguous tensor of the state's dtype, 2^(n - popcount(mask))
+    entries; returns the probability."""
+    p = ctypes.c_double()
+    _check(lib().sv_postselect(h, int(mask), int(value), ctypes.byref(p), _ptr(out_dev), 1), "sv_postselect")
+    return p.value
+
+
+def sv_postselect_noalloc(h, mask, value, prob_dev, out_dev=None):
+    """prob_dev: device tensor of >= 1 float64 (written asynchronously);
+    out_dev: device tensor of the state's dtype or None."""
+    _check(lib().sv_postselect_noalloc(h, int(mask), int(value), _ptr(prob_dev), _ptr(out_dev)),
+           "sv_postselect_noalloc")
 
 
 def sv_hhl(h, A, b, n_c, T0, mode=0, signed_clock=False):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "sv_device.h"
@@ -315,15 +316,22 @@ template <typename R> static inline cvec<R> hc(const double *u) {
     return z;
 }
 
-sv_status norm2_device(sv_state s, uint64_t mask, uint64_t value, double *dev_out) {
+// Reduction partials of norm2_into: at most this many blocks.
+constexpr int NORM_MAX_PARTS = 4096;
+
+static uint64_t norm_blocks(uint64_t count) {
+    const uint64_t per_block = 256 * 64;
+    const uint64_t nb = (count + per_block - 1) / per_block;
+    return nb > (uint64_t)NORM_MAX_PARTS ? (uint64_t)NORM_MAX_PARTS : (nb ? nb : 1);
+}
+
+// FP64 sum of |a_i|^2 over (i & mask) == value into dev_out[0], with `part`
+// (device, norm_blocks(count) doubles) holding the per-block partials.
+static sv_status norm2_into(sv_state s, uint64_t mask, uint64_t value, double *part, double *dev_out) {
     const Ins f = make_ins(mask, value);
     const uint64_t count = dim_of(s->n - popcount64(mask));
-    const uint64_t per_block = 256 * 64;
-    uint64_t nb = (count + per_block - 1) / per_block;
-    if (nb > 4096) nb = 4096;
+    const uint64_t nb = norm_blocks(count);
     const uint64_t chunk = (count + nb - 1) / nb;
-    SV_TRY(ensure_small(s, (nb + 8) * sizeof(double)));
-    double *part = (double *)s->small + 8;
     if (s->dt == SV_C64)
         {
             TraceScope _ts(s->stream, "norm_partial_c64", (double)count * 8, 0.0);
@@ -338,6 +346,42 @@ sv_status norm2_device(sv_state s, uint64_t mask, uint64_t value, double *dev_ou
         }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s->stream, (const double *)part, (int)nb, 1, dev_out);
     SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+sv_status norm2_device(sv_state s, uint64_t mask, uint64_t value, double *dev_out) {
+    const uint64_t nb = norm_blocks(dim_of(s->n - popcount64(mask)));
+    SV_TRY(ensure_small(s, (nb + 8) * sizeof(double)));
+    return norm2_into(s, mask, value, (double *)s->small + 8, dev_out);
+}
+
+// Workspace of the allocation-free post-selection: the reduction partials
+// (NORM_MAX_PARTS doubles) and the probability in the slot after them.  Each
+// device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+constexpr int NOALLOC_SLOTS = NORM_MAX_PARTS + 64;
+static __device__ __align__(256) double scratch[NOALLOC_SLOTS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of `scratch` on `dev`, looked up once per device with that
+// device current (the caller's current device is restored)
+static sv_status noalloc_workspace(int dev, double **out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(SV_EDEVICE, "device %d beyond the workspace table", dev);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        int cur = 0;
+        SV_HIP(hipGetDevice(&cur));
+        if (cur != dev) SV_HIP(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) SV_HIP(hipSetDevice(cur));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
     return SV_OK;
 }
 
@@ -680,6 +724,34 @@ sv_status sv_postselect(sv_state s, uint64_t mask, uint64_t value, double *prob,
                            (const double2 *)s->data, count, f, (const double *)dres);
     SV_HIP(hipGetLastError());
     return download(s, out, s->scratch, count * sizeof(double2));
+}
+
+sv_status sv_postselect_noalloc(sv_state s, uint64_t mask, uint64_t value, double *prob_dev, void *out_dev) {
+    clear_error();
+    SV_TRY(check_state(s));
+    if (!prob_dev) return fail(SV_EINVAL, "prob_dev is NULL");
+    if (mask >> s->n) return fail(SV_EINVAL, "mask has bits beyond the state");
+    if (value & ~mask) return fail(SV_EINVAL, "value has bits outside mask");
+    const uint64_t count = dim_of(s->n - popcount64(mask));
+    if (norm_blocks(count) > (uint64_t)NORM_MAX_PARTS)
+        return fail(SV_EINVAL, "reduction needs %llu partials, workspace holds %d",
+                    (unsigned long long)norm_blocks(count), NORM_MAX_PARTS);
+    double *ws = nullptr;
+    SV_TRY(noalloc_workspace(s->device, &ws));
+    // every partial slot the reduction reads is written by its own block first,
+    // so the workspace needs no clearing between calls
+    SV_TRY(norm2_into(s, mask, value, ws, prob_dev));
+    if (!out_dev) return SV_OK;
+    const Ins f = make_ins(mask, value);
+    const unsigned g = grid_for(count, 4);
+    if (s->dt == SV_C64)
+        hipLaunchKernelGGL(k_gather_dev<float>, dim3(g), dim3(256), 0, s->stream, (float2 *)out_dev,
+                           (const float2 *)s->data, count, f, (const double *)prob_dev);
+    else
+        hipLaunchKernelGGL(k_gather_dev<double>, dim3(g), dim3(256), 0, s->stream, (double2 *)out_dev,
+                           (const double2 *)s->data, count, f, (const double *)prob_dev);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
 }
 
 }  // extern "C"
