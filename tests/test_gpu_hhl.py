@@ -1,8 +1,11 @@
 """GPU parity for the controlled-U GEMM and for HHL (both modes) against the oracle.
 
-Bars: complex128 max-abs <= 1e-12, complex64 max-abs <= 1e-5 on the
-normalised post-selected vector and (mode 0) on the whole final state;
-probabilities to the same bars.
+Bars: complex128 max-abs <= 1e-12, complex64 max-abs <= 1e-5 in the units
+of the norm-1 state: on the whole final state (mode 0) and on the
+post-selected vector, where x = psi[1,0,:] / sqrt(p) widens the complex64 bar
+to 1e-5 / sqrt(p) (Couette); probabilities to the same bars.  The
+eigen-frame modes 1 and 2 also meet relative bars: l2 of x within 1e-5
+(complex64) / 1e-10 (complex128) and p_post within twice that, relatively.
 """
 import math
 
@@ -16,6 +19,15 @@ from paper_2307_00391_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL = {"c128": 1e-12, "c64": 1e-5}
+# eigen-frame modes form the post-selected amplitudes directly: relative bars
+# on x (l2) and on p_post as well
+REL = {"c128": 1e-10, "c64": 1e-5}
+
+
+def _relative_checks(x, x_r, p, p_r, dt):
+    rel = np.linalg.norm(x - x_r) / np.linalg.norm(x_r)
+    assert rel <= REL[dt], rel
+    assert abs(p - p_r) <= 2 * REL[dt] * p_r, (p, p_r)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -87,6 +99,8 @@ def test_poiseuille_hhl(poiseuille_ref, dt, mode):
     assert abs(res.norm_total - 1.0) <= TOL[dt] * 10
     if mode == 0:
         assert np.abs(st.get() - psi_r).max() <= TOL[dt]
+    else:
+        _relative_checks(x, x_r, res.p_post, pp_r, dt)
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
@@ -95,13 +109,16 @@ def test_couette_hhl(couette_ref, dt, mode):
     s, n_c, T0, (psi_r, x_r, pp_r, pa_r) = couette_ref
     st, x, res = _run(s.A, s.b, n_c, T0, dt, mode)
     # x is divided by sqrt(p_post) ~ 0.013: the FP32 path's absolute error on
-    # the state is amplified by 1/sqrt(p) on the post-selected vector
+    # the state is amplified by 1/sqrt(p) on the post-selected vector (bars in
+    # the units of the norm-1 state; modes 1 and 2 also meet relative bars)
     tol_x = TOL[dt] if dt == "c128" else 1e-5 / math.sqrt(pp_r) * 0.1
     assert np.abs(x - x_r).max() <= max(TOL[dt], tol_x)
     assert abs(res.p_post - pp_r) <= TOL[dt]
     assert abs(res.p_anc - pa_r) <= TOL[dt]
     if mode == 0:
         assert np.abs(st.get() - psi_r).max() <= TOL[dt]
+    else:
+        _relative_checks(x, x_r, res.p_post, pp_r, dt)
 
 
 @pytest.mark.parametrize("seed,n_s,n_c,kappa", [(1, 3, 5, 20.0), (2, 5, 7, 300.0), (3, 6, 9, 1000.0),
