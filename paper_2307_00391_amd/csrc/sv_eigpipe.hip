@@ -17,10 +17,12 @@
 //             the column's G1 factor and B_j(y2) the product of the phases of
 //             the set G2 bits.  k_pipe_a therefore runs for y2 = 0 only and
 //             leaves T in the clock rows y1 < 2^g1 of the ancilla = 0 half.
-//   k_pipe_b: every amplitude of the post-G1 state from T and the G2 phases,
-//             inverse-QFT cascade on G2, eigenvalue inversion a1 = (1/y) a0
-//             (FP64 sums of P(a=1) and the norm), QFT cascade on G2
-//                                                     -> ancilla = 1 half
+//   k_pipe_b: the inverse-QFT cascade on G2 of T_j(y1) B_j(y2): each stage
+//             maps a product state over the G2 bits to another, so the
+//             cascade's output is T_j(y1) times a product of one factor per
+//             G2 bit, formed directly; then eigenvalue inversion
+//             a1 = (1/y) a0 (FP64 sums of P(a=1) and the norm), QFT cascade
+//             on G2                                   -> ancilla = 1 half
 //   k_pipe_c: QFT cascade on G1, the conjugate phases of the uncompute, and
 //             the sum over the clock values of the tile (the Hadamard layer
 //             projected on clock = 0)                -> FP64 partial sums
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &one, const PipeSolve *__restrict__ many) {
     constexpr int G = RA + RB;
-    // phases of the G2 bits per thread (G C <= 8 * 64 <= 2 NT)
+    // column data of a tile per thread (G C <= 8 * 64 <= 2 NT phases, C <= NT table entries)
     constexpr int OMR = 2;
     const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
@@ -338,6 +340,7 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
     R *s2t = reinterpret_cast<R *>(TT + (1 << G));                  // [2^G] s_y^2 2^-G
     R *srt = s2t + (1 << G);                                         // [2^G] s_y 2^-G
     cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
+    cvec<R> *tT = om + G * C;                                        // [C] G1 table entries T_j(o)
     __shared__ double red[2][NT / 64];
     // tiles: one per block (tile_coords), or, persistent, a fixed G1 value
     // o = blockIdx.x >> pslog per block and the column blocks
@@ -355,14 +358,14 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
         tile_coords(A, j0, o);           // o = value of the G1 bits
     }
     const int g1 = A.g1, n_c = A.n_c;
-    // the G1 table entry of the thread's first phase-A line and the column
-    // phases of the G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read
-    // before the twiddles are built so that their latency overlaps that work
-    cvec<R> t0 = gld<R>(psi, (o << A.n_s) | (j0 + (threadIdx.x & (C - 1))));
+    // the tile's column data: the G1 table entries T_j(o) and the phases of the
+    // G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read before the
+    // twiddles are built so that their latency overlaps that work
     for (int e = threadIdx.x; e < G * C; e += NT) {
         const int b = e / C, c = e - b * C;
         om[b * C + c] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + c);
     }
+    for (int c = threadIdx.x; c < C; c += NT) tT[c] = gld<R>(psi, (o << A.n_s) | (j0 + c));
     fill_twiddles<R>(TW, G, g1, o);
     fill_pair_twiddles<R>(TT, G, g1, o);
     // rotation of clock value y = o + l 2^g1 (natural order after the inverse
@@ -389,39 +392,10 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
     const int nla = C << RB, nlb = C << RA;
     double pa = 0.0, nt = 0.0;
     for (int it = 0; it < iters; ++it) {
-        // phase A (inverse cascade, low bits of G2): the amplitudes at y1 = o and
-        // y2 = (lhi << RA) | k are T_j(o) times the phases of the set bits of y2
-        for (int line = threadIdx.x; line < nla; line += NT) {
-            const int c = line & (C - 1), lhi = line >> A.cl;
-            const uint64_t col = j0 + c;
-            cvec<R> v[1 << RA];
-            cvec<R> base = line == (int)threadIdx.x ? t0 : gld<R>(psi, (o << A.n_s) | col);
-            for (int b = 0; b < RB; ++b)
-                if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-            // the first inverse stage (group bit 0) sees the product input only:
-            // the pair (1, om_0) becomes (1 + om_0 conj(tw_0), 1 - om_0 conj(tw_0))
-            const cvec<R> w0 = cconjmul<R>(om[c], twr[0]);
-            v[0] = cmul<R>(base, cmake<R>((R)1 + w0.x, w0.y));
-            v[1] = cmul<R>(base, cmake<R>((R)1 - w0.x, -w0.y));
-#pragma unroll
-            for (int b = 1; b < RA; ++b) {
-                const cvec<R> w = om[b * C + c];
-#pragma unroll
-                for (int k = 0; k < (1 << b); ++k) v[k | (1 << b)] = cmul<R>(v[k], w);
-            }
-#pragma unroll
-            for (int jb = 1; jb < RA; ++jb)
-                stage<R, RA, true>(v, jb, twr + tw_off(jb), true, [&](int k) { return k & ((1 << jb) - 1); });
-            cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
-#pragma unroll
-            for (int k = 0; k < (1 << RA); ++k) lt[k << A.cl] = v[k];
-        }
-        // persistent: the next tile's G1 table entry and G2-bit phases, in
-        // flight during this tile's phase B
+        // persistent: the next tile's column data, in flight during this tile's phase B
         const bool more = PERS && it + 1 < iters;
-        cvec<R> omn[OMR];
+        cvec<R> omn[OMR], tn = cmake<R>((R)0, (R)0);
         if (more) {
-            t0 = gld<R>(psi, (o << A.n_s) | (j0 + jstep + (threadIdx.x & (C - 1))));
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
                 const int e = threadIdx.x + q * NT;
@@ -430,19 +404,40 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
                     omn[q] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + jstep + c);
                 }
             }
+            if ((int)threadIdx.x < C) tn = gld<R>(psi, (o << A.n_s) | (j0 + jstep + threadIdx.x));
         }
-        __syncthreads();
-        // phase B: inverse cascade on the high bits, rotation, forward cascade on the high bits
+        // phase B: the inverse-QFT output on the G2 register of column j at
+        // y = o + l 2^g1, l = llo + (k << RA), generated from its closed form,
+        // then the rotation and the forward cascade on the high bits of G2.
+        // The input of the G2 stages is T_j(o) times a product state over the
+        // G2 bits (phase w_b on bit b), and inverse stage b maps a product
+        // state to a product state: after all of them the amplitude is
+        //   T_j(o) prod_b (1 + (-1)^(l_b) w_b conj(tw_b(l mod 2^b))),
+        // tw_b the stage's twiddle.  The factors of the low RA bits are the
+        // line's, those of the RB high bits branch into the line's 2^RB
+        // entries (a product tree, one level per bit).
         for (int line = threadIdx.x; line < nlb; line += NT) {
             const int c = line & (C - 1), llo = line >> A.cl;
             cvec<R> v[1 << RB];
-            cvec<R> *lt = tile + (llo << A.cl) + c;
+            cvec<R> p = tT[c];
 #pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) v[k] = lt[(k << RA) << A.cl];
+            for (int b = 0; b < RA; ++b) {
+                const cvec<R> q = cconjmul<R>(om[b * C + c], TW[tw_off(b) + (llo & ((1 << b) - 1))]);
+                const cvec<R> f = (llo >> b & 1) ? cmake<R>((R)1 - q.x, -q.y) : cmake<R>((R)1 + q.x, q.y);
+                p = cmul<R>(p, f);
+            }
+            v[0] = p;
 #pragma unroll
-            for (int jb = RA; jb < G; ++jb)
-                stage<R, RB, true>(v, jb - RA, TW + tw_off(jb), true,
-                                   [&](int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+            for (int bb = 0; bb < RB; ++bb) {
+                const cvec<R> w = om[(RA + bb) * C + c];
+#pragma unroll
+                for (int m = 0; m < (1 << bb); ++m) {
+                    const cvec<R> q = cconjmul<R>(w, TW[tw_off(RA + bb) + llo + (m << RA)]);
+                    const cvec<R> a = v[m];
+                    v[m] = cmul<R>(a, cmake<R>((R)1 + q.x, q.y));
+                    v[m + (1 << bb)] = cmul<R>(a, cmake<R>((R)1 - q.x, -q.y));
+                }
+            }
             // |a|^2 summed over the line in the amplitude precision (weighted by
             // s_y^2 for P(a = 1); the rotation keeps each pair's norm, so the
             // total is the plain sum), then accumulated in FP64
@@ -460,18 +455,20 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             nt += (double)lnt * fold;
             fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
                                               [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
+            cvec<R> *lt = tile + (llo << A.cl) + c;
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
         }
-        // the phases are read in phase A only: the next tile's go in now
+        __syncthreads();
+        // the column data are read in phase B only: the next tile's go in now
         if (more) {
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
                 const int e = threadIdx.x + q * NT;
                 if (e < G * C) om[e] = omn[q];
             }
+            if ((int)threadIdx.x < C) tT[threadIdx.x] = tn;
         }
-        __syncthreads();
         // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
         for (int line = threadIdx.x; line < nla; line += NT) {
             const int c = line & (C - 1), lhi = line >> A.cl;
@@ -487,7 +484,7 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             for (int k = 0; k < (1 << RA); ++k) gst<R>(p, k * ks, v[k]);
         }
         j0 += jstep;
-        // the next tile's phase A rewrites the tile this one has just read
+        // the next tile's phase B rewrites the tile this one has just read
         if (more) __syncthreads();
     }
     pa = wave_sum_f64(pa);
@@ -807,7 +804,7 @@ static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
     size_t b = ((C << g) + ((size_t)1 << g)) * e;
     if (which != 1) b += (size_t)(g + 1) * C * e;
     if (which != 0) b += ((size_t)1 << g) * e;                          // radix-4 pair products
-    if (which == 1) b += ((size_t)1 << g) * e + (size_t)g * C * e;
+    if (which == 1) b += ((size_t)1 << g) * e + (size_t)(g + 1) * C * e;
     if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
     return b;
 }
