@@ -469,9 +469,17 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             }
             if ((int)threadIdx.x < C) tT[threadIdx.x] = tn;
         }
-        // phase A (forward cascade, low bits of G2), into the ancilla = 1 half
+        // phase A (forward cascade, low bits of G2), into the ancilla = 1 half.
+        // A wavefront takes 16 columns of four lines (lhi), so that each store
+        // instruction writes four rows of 128 B: that pattern streams faster
+        // than one row of 512 B.
         for (int line = threadIdx.x; line < nla; line += NT) {
-            const int c = line & (C - 1), lhi = line >> A.cl;
+            int c = line & (C - 1), lhi = line >> A.cl;
+            if (RB >= 2 && A.cl >= 4) {
+                const int wv = line >> 6;
+                c = (line & 15) | ((wv & ((1 << (A.cl - 4)) - 1)) << 4);
+                lhi = ((line >> 4) & 3) | ((wv >> (A.cl - 4)) << 2);
+            }
             cvec<R> v[1 << RA];
             const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
 #pragma unroll

@@ -276,3 +276,22 @@ def test_hhl_run_device_matches_host_buffers(dt, mode, kron):
         assert abs(a.p_post - c.p_post) <= TOL[dt] * c.p_post
         assert abs(a.p_anc - c.p_anc) <= TOL[dt] and abs(a.norm_total - c.norm_total) <= TOL[dt]
 
+
+
+@pytest.mark.parametrize("n_s,n_c", [(6, 12), (7, 13), (6, 14), (8, 15), (9, 12)])
+def test_fused_pipeline_wide_clock_shapes(n_s, n_c):
+    """Single complex64 solves with G2 groups of 6 and 7 bits (the shapes the
+    lane-resident inversion kernel takes) against the closed form, and
+    complex128 (the LDS-tile kernels) to the FP64 bar."""
+    from tests.closed_form import hhl_closed_form
+    rng = np.random.default_rng(300 + 16 * n_s + n_c)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, 300.0)
+    b = rng.standard_normal(1 << n_s) + 0.5j * rng.standard_normal(1 << n_s)
+    T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.93
+    x_r, pp_r = hhl_closed_form(A, b, n_c, T0)
+    for dt in ("c64", "c128"):
+        st, x, res = _run(A, b, n_c, T0, dt, 1)
+        st.close()
+        _relative_checks(x, x_r, res.p_post, pp_r, dt)
+        assert np.abs(x - x_r).max() <= (1e-5 if dt == "c64" else 1e-12)
+        assert abs(res.norm_total - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
