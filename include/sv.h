@@ -304,6 +304,19 @@ sv_status sv_gapped_pe(sv_state s, const double *A, const double *b, const sv_gp
 typedef struct sv_hhl_plan_s *sv_hhl_plan;
 sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m_hi, const double *A_lo,
                          int m_lo);
+/* A plan from an eigen-decomposition the caller has already computed:
+ * A = V diag(lam) V^T with V real orthogonal (the classical preprocessing of
+ * the hybrid loop, done outside the library).  For operators whose
+ * eigenbasis is dense and too large for sv_hhl_prepare's solvers (n_s up to
+ * 16: a 2^16 x 2^16 V is 32 GiB): the basis changes of modes 1 and 2 then run
+ * as two FP64 matrix-vector products over V, each reading V once from HBM.
+ *   V_dev: device, 2^n_s x 2^n_s FP64 row-major, column j the eigenvector of
+ *          lam[j]; borrowed for the plan's lifetime (not copied), unchanged.
+ *   lam:   host, 2^n_s FP64 eigenvalues (any order, copied).
+ * Checked: V V^T r = r to 1e-10 relative for a fixed pseudo-random r.  Mode 0
+ * (gate-faithful) is available for n_s <= 13.  Errors: SV_EINVAL (sizes, NULL,
+ * non-finite lam, V not orthogonal), SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_hhl_prepare_eig(sv_hhl_plan *out, sv_state s, const double *V_dev, const double *lam, int n_s);
 /* One HHL solve on a prepared operator; arguments and results as sv_hhl.
  * The plan keeps device workspaces between calls: calls sharing a plan must
  * not overlap. */
@@ -358,11 +371,21 @@ sv_status sv_trace_enable(int on);
 int sv_trace_report(char *buf, int len);
 
 /* The autotuner's current choices, one line per tuned shape:
- * "op/dtype/shape... values".  For the fused eigen-frame kernels the values
- * are (log2 columns per tile, threads per workgroup) for each of the three
- * kernels.  Tuning runs on first use of a shape (SV_AUTOTUNE=0: defaults);
- * SV_TUNE_CACHE=<file> persists the choices.  Returns the report length. */
+ * "op/dtype/shape... values".  Tuning runs on first use of a shape
+ * (SV_AUTOTUNE=0: defaults); SV_TUNE_CACHE=<file> persists the choices.
+ *   eigpipe/<dtype>/<n_s>/<n_c>[/p]  fused eigen-frame kernels: (log2 columns
+ *       per tile, threads per workgroup) for each of the three kernels ("/p":
+ *       the persistent forms of single solves);
+ *   cgemm/<dtype>/<M>/<N>/<K>/<trans>  the matrix-core GEMM's tile shape:
+ *       0 = 64 x 64 per workgroup, 1 = 16 x 16 per wavefront;
+ *   fused/<dtype>/<n>/<circuit>  sv_apply_circuit with max_local = 0: (k
+ *       local qubits, c contiguous low bits) per circuit structure.
+ * Returns the report length. */
 int sv_tune_report(char *buf, int len);
+/* Sets (n > 0: vals[0..n)) or removes (n == 0) one tuning entry, with the key
+ * format of sv_tune_report: pins a configuration (tests run every candidate
+ * this way).  A pinned entry is used as it is.  Errors: SV_EINVAL. */
+sv_status sv_tune_set(const char *key, const int *vals, int n);
 
 /* Name of the rocSOLVER routine whose eigen-decomposition was used by the
  * calling thread's last HHL call (each result is accepted only after a

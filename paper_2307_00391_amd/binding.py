@@ -111,6 +111,7 @@ _SIGS = {
     "sv_hhl_kron": ([_P, _P, _I, _P, _I, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
     "sv_hhl_prepare": ([ctypes.POINTER(_P), _P, _P, _I, _P, _I], _I),
     "sv_hhl_run": ([_P, _P, _P, ctypes.POINTER(sv_hhl_params), ctypes.POINTER(sv_hhl_result), _P], _I),
+    "sv_hhl_prepare_eig": ([ctypes.POINTER(_P), _P, _P, _P, _I], _I),
     "sv_hhl_plan_spectrum": ([_P, _DP, _DP], _I),
     "sv_hhl_plan_free": ([_P], _I),
     "sv_last_eigensolver": ([], ctypes.c_char_p),
@@ -135,6 +136,7 @@ _SIGS = {
     "sv_spectrum_lanczos": ([_P, _I, _I, _U64, _DP, _DP, _P], _I),
     "sv_trace_enable": ([_I], _I),
     "sv_tune_report": ([ctypes.c_char_p, _I], _I),
+    "sv_tune_set": ([ctypes.c_char_p, _P, _I], _I),
     "sv_trace_report": ([ctypes.c_char_p, _I], _I),
     "sv_last_error": ([], ctypes.c_char_p),
     "sv_version": ([], ctypes.c_char_p),
@@ -151,6 +153,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise FileNotFoundError(f"{LIB_PATH} is missing: run `python -m paper_2307_00391_amd.build` "
                                 "(there is no CPU fallback)")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (one runtime per process, so torch's streams and memory are the
+    # library's); loaded the other way round, two runtimes would coexist
+    _torch()
     L = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in _SIGS.items():
         fn = getattr(L, name, None)
@@ -452,6 +458,13 @@ def sv_tune_report():
     return buf.value.decode()
 
 
+def sv_tune_set(key, vals=()):
+    """Pin (vals) or remove (empty vals) one tuning-cache entry."""
+    vals = [int(v) for v in vals]
+    arr = (ctypes.c_int * max(1, len(vals)))(*vals)
+    _check(lib().sv_tune_set(key.encode(), ctypes.cast(arr, ctypes.c_void_p), len(vals)), "sv_tune_set")
+
+
 def sv_last_eigensolver():
     return lib().sv_last_eigensolver().decode()
 
@@ -466,6 +479,21 @@ def sv_hhl_prepare(h, A_hi, A_lo=None):
         m_lo = A_lo.shape[0].bit_length() - 1
     p = ctypes.c_void_p()
     _check(lib().sv_hhl_prepare(ctypes.byref(p), h, _ptr(Ahf), m_hi, _ptr(Alf), m_lo), "sv_hhl_prepare")
+    return p
+
+
+def sv_hhl_prepare_eig(h, V_dev, lam):
+    """V_dev: contiguous float64 device tensor (N x N, column j = eigenvector of
+    lam[j]), kept alive by the caller for the plan's lifetime; lam: N floats."""
+    lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+    n_s = lam.size.bit_length() - 1
+    torch = _torch()
+    if not (isinstance(V_dev, torch.Tensor) and V_dev.is_cuda and V_dev.dtype == torch.float64
+            and V_dev.is_contiguous() and V_dev.numel() == lam.size * lam.size):
+        raise ValueError("V_dev must be a contiguous float64 CUDA tensor of N x N entries")
+    p = ctypes.c_void_p()
+    _check(lib().sv_hhl_prepare_eig(ctypes.byref(p), h, ctypes.c_void_p(V_dev.data_ptr()),
+                                    lam.ctypes.data_as(ctypes.c_void_p), n_s), "sv_hhl_prepare_eig")
     return p
 
 

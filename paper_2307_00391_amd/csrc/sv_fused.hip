@@ -16,10 +16,12 @@
 // layout is XOR-swizzled so that threads whose amplitudes sit 2^p apart hit
 // distinct banks.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "sv_device.h"
@@ -842,6 +844,99 @@ sv_status run_qft_cascade(sv_state s, const QftSpec &q, int max_local) {
 
 }  // namespace sv
 
+namespace sv {
+
+// The fusion autotuner (sv_apply_circuit with max_local = 0, states of 2^22
+// amplitudes and more): the candidates are k local qubits in {K-1, K} (K the
+// default, bounded by the LDS) times c contiguous low bits in {C-1, C, C+1}
+// (C the default, c <= k - 2).  Each candidate's plan is made for the whole
+// circuit and its first passes are timed on a scratch copy of the state (the
+// state itself is not touched); the estimate (passes x mean pass time)
+// decides.  Cached per dtype, size and circuit structure (gate kinds and
+// qubits, not angles).  SV_FUSED_LOWBITS pins c and skips the tuning.
+static uint64_t circuit_signature(const std::vector<PGate> &pg) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(pg.size());
+    for (const PGate &g : pg) {
+        mix((uint64_t)g.kind);
+        mix((uint64_t)(int64_t)g.t0);
+        mix((uint64_t)(int64_t)g.t1);
+        mix(g.cmask);
+        mix(g.cval);
+        mix(g.need);
+    }
+    return h;
+}
+
+sv_status fusion_config(sv_state s, const std::vector<PGate> &pg, int &k, int &c) {
+    if (s->n < 22 || getenv("SV_FUSED_LOWBITS")) return SV_OK;
+    char sig[32];
+    snprintf(sig, sizeof sig, "%016llx", (unsigned long long)circuit_signature(pg));
+    const std::string key = std::string("fused/") + (s->dt == SV_C64 ? "c64/" : "c128/") + std::to_string(s->n) + "/" + sig;
+    std::vector<int> cached;
+    if (tune_lookup(key, cached) && cached.size() == 2) {
+        k = cached[0];
+        c = cached[1];
+        return SV_OK;
+    }
+    if (!autotune_enabled()) return SV_OK;
+    const size_t bytes = dim_of(s->n) * amp_bytes(s->dt);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b < bytes + bytes / 16) return SV_OK;
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return SV_OK;
+    }
+    sv_state t = new sv_state_s();
+    t->n = s->n;
+    t->dt = s->dt;
+    t->data = scratch;
+    t->owned = false;
+    t->stream = s->stream;
+    t->device = s->device;
+    sv_status st = SV_OK;
+    if (hipMemcpyAsync(scratch, s->data, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+        st = fail(SV_EDEVICE, "scratch copy for the fusion tuner");
+    const int K = k, C = c;
+    float best = 1e30f;
+    for (int kk = K - 1; kk <= K && st == SV_OK; ++kk) {
+        if (kk < 3 || reg_bits_for(s->dt, kk) < 3) continue;
+        for (int cc = C - 1; cc <= C + 1 && st == SV_OK; ++cc) {
+            if (cc < 0 || cc > kk - 2) continue;
+            std::vector<HostPass> passes;
+            plan(s->n, kk, cc, pg, passes);
+            if (passes.empty()) continue;
+            const size_t P = passes.size() < 3 ? passes.size() : 3;
+            float ms = 0.f;
+            st = time_stream(s->stream, 1, &ms, [&]() {
+                std::vector<HostPass> pre(passes.begin(), passes.begin() + P);
+                return s->dt == SV_C64 ? launch_passes<float>(t, pre) : launch_passes<double>(t, pre);
+            });
+            const float est = ms * (float)passes.size() / (float)P;
+            if (st == SV_OK && est < best) {
+                best = est;
+                k = kk;
+                c = cc;
+            }
+        }
+    }
+    hipStreamSynchronize(s->stream);
+    sv_free(t);
+    hipFree(scratch);
+    if (st != SV_OK) return st;
+    tune_store(key, {k, c});
+    return SV_OK;
+}
+
+}  // namespace sv
+
 using namespace sv;
 
 extern "C" {
@@ -867,10 +962,12 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, int n_gates, int ma
     if (!n_gates) return SV_OK;
     std::vector<PGate> pg;
     SV_TRY(to_pgates(s, gates, n_gates, pg));
-    const int k = clamp_k(s, max_local);
+    int k = clamp_k(s, max_local);
     if (k < 3) return fail(SV_EUNSUPPORTED, "state too small for fused passes");
+    int c = std::max(0, std::min(low_bits_for(s->dt), k - 2));
+    if (max_local == 0) SV_TRY(fusion_config(s, pg, k, c));
     std::vector<HostPass> passes;
-    plan(s->n, k, std::max(0, std::min(low_bits_for(s->dt), k - 2)), pg, passes);
+    plan(s->n, k, c, pg, passes);
     return s->dt == SV_C64 ? launch_passes<float>(s, passes) : launch_passes<double>(s, passes);
 }
 

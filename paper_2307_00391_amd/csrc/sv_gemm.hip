@@ -8,6 +8,9 @@
 // MFMAs: re += ar br - ai bi, im += ar bi + ai br.
 #include <string.h>
 
+#include <string>
+#include <vector>
+
 #include "sv_device.h"
 #include "sv_internal.h"
 
@@ -135,6 +138,47 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
             }
 }
 
+// The same product with one wavefront per 16 x 16 output tile and no LDS:
+// each lane loads its MFMA operands straight from memory (A[row][k] for row
+// l % 16, k = l / 16 of each 4-wide k step, and B[k][col] alike).  For small
+// products (the basis changes of a Kronecker plan: 256 x 256 x 256) the
+// 64 x 64 block tiles leave most of the chip idle; here every tile is a
+// wavefront.  The k steps and the four real MFMAs of a complex product run in
+// the same order as in k_cgemm, so both give the same bits.
+template <typename R>
+__global__ __launch_bounds__(256) void k_cgemm_w(GemmArgs<R> A) {
+    using M_ = MfmaT<R>;
+    using acc_t = typename M_::acc;
+    const int lane = threadIdx.x & 63;
+    const uint64_t tiles_n = (uint64_t)((A.N + 15) / 16);
+    const uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t tm = tile / tiles_n, tn = tile % tiles_n;
+    if (tm * 16 >= A.M) return;                       // the whole wavefront (no barriers below)
+    const uint64_t r = tm * 16 + (lane & 15);
+    const int c = (int)(tn * 16) + (lane & 15);
+    const int kq = lane >> 4;
+    const bool r_ok = r < A.M, c_ok = c < A.N;
+    const uint64_t a_base = r_ok ? (pdep64(r, A.row_mask) | A.row_fix) : 0;
+    const R csgn = A.conjb ? (R)-1 : (R)1;
+    acc_t acc_re, acc_im;
+    for (int v = 0; v < 4; ++v) acc_re[v] = acc_im[v] = (R)0;
+#pragma unroll 4
+    for (int k0 = 0; k0 < A.K; k0 += 4) {
+        const int kk = k0 + kq;
+        cvec<R> a = cmake<R>((R)0, (R)0), b = cmake<R>((R)0, (R)0);
+        if (r_ok && kk < A.K) a = A.in[a_base + kk];
+        if (c_ok && kk < A.K) b = A.trans ? A.U[(uint64_t)kk * A.N + c] : A.U[(uint64_t)c * A.K + kk];
+        acc_re = M_::mfma(a.x, b.x, acc_re);
+        acc_re = M_::mfma(-a.y, csgn * b.y, acc_re);
+        acc_im = M_::mfma(a.x, csgn * b.y, acc_im);
+        acc_im = M_::mfma(a.y, b.x, acc_im);
+    }
+    for (int v = 0; v < 4; ++v) {
+        const uint64_t rr = tm * 16 + M_::row(lane, v);
+        if (rr < A.M && c_ok) A.out[rr * A.N + c] = cmake<R>(acc_re[v], acc_im[v]);
+    }
+}
+
 template <typename R>
 __global__ void k_scatter_rows(cvec<R> *__restrict__ psi, const cvec<R> *__restrict__ src, uint64_t M, int mbits,
                                uint64_t row_mask, uint64_t row_fix) {
@@ -165,12 +209,42 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
     const uint64_t gm = (M + GBM - 1) / GBM;
     const unsigned gn = (unsigned)((N + GBN - 1) / GBN);
     if (gm > 0x7fffffffull) return fail(SV_EUNSUPPORTED, "GEMM with too many rows");
-    {
+    const uint64_t wtiles = ((M + 15) / 16) * (uint64_t)((N + 15) / 16);
+    const uint64_t wblocks = (wtiles + 3) / 4;
+    // the tile shape: 64 x 64 per workgroup (0) or 16 x 16 per wavefront (1).
+    // Tuned per shape by timing both on this call's operands (the product is
+    // out of place, so it can be run twice), cached; without tuning, the
+    // wavefront tiles wherever the workgroup tiles would not fill the chip.
+    const std::string key = std::string("cgemm/") + (sizeof(R) == 4 ? "c64/" : "c128/") + std::to_string(M) + "/" +
+                            std::to_string(N) + "/" + std::to_string(K) + "/" + std::to_string(trans);
+    auto launch = [&](int shape) -> sv_status {
         TraceScope _ts(st, "cgemm", ((double)M * (N + K) + (double)N * K) * sizeof(cvec<R>), 8.0 * (double)M * N * K);
-        hipLaunchKernelGGL(k_cgemm<R>, dim3((unsigned)gm, gn), dim3(256), 0, st, a);
+        if (shape == 1) {
+            if (wblocks > 0x7fffffffull) return fail(SV_EUNSUPPORTED, "GEMM with too many tiles");
+            hipLaunchKernelGGL(k_cgemm_w<R>, dim3((unsigned)wblocks), dim3(256), 0, st, a);
+        } else {
+            hipLaunchKernelGGL(k_cgemm<R>, dim3((unsigned)gm, gn), dim3(256), 0, st, a);
+        }
+        SV_HIP(hipGetLastError());
+        return SV_OK;
+    };
+    std::vector<int> cached;
+    int shape = gm * gn < 256 ? 1 : 0;
+    if (tune_lookup(key, cached) && cached.size() == 1 && (cached[0] == 0 || cached[0] == 1)) {
+        shape = cached[0];
+    } else if (autotune_enabled() && wblocks <= 0x7fffffffull) {
+        float best = 1e30f;
+        for (int c = 0; c < 2; ++c) {
+            float ms = 0.f;
+            SV_TRY(time_stream(st, 2, &ms, [&]() { return launch(c); }));
+            if (ms < best) {
+                best = ms;
+                shape = c;
+            }
+        }
+        tune_store(key, {shape});
     }
-    SV_HIP(hipGetLastError());
-    return SV_OK;
+    return launch(shape);
 }
 template sv_status cgemm<float>(hipStream_t, const float2 *, float2 *, const float2 *, uint64_t, int, int, uint64_t,
                                 uint64_t, int, int);

@@ -80,6 +80,11 @@ __global__ void k_real_cm_to_complex(double2 *__restrict__ V, const double *__re
     }
 }
 
+__global__ void k_real_to_complex(double2 *__restrict__ out, const double *__restrict__ in, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = make_double2(in[i], 0.0);
+}
+
 __global__ void k_c128_to_c64(float2 *__restrict__ out, const double2 *__restrict__ in, uint64_t count) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -267,15 +272,24 @@ __global__ void k_sum_cols(double2 *__restrict__ z, const double2 *__restrict__ 
 // host helpers
 // --------------------------------------------------------------------------
 
+// One rocBLAS handle (rocSOLVER's eigen-solvers) for the process.  A lease
+// holds its lock from setting the stream until the lease ends, so that two
+// host threads cannot move the handle to another stream in the middle of
+// each other's library call.
 static std::mutex g_blas_mu;
 static rocblas_handle g_blas = nullptr;
 
-static sv_status blas_handle(hipStream_t st, rocblas_handle *out) {
-    std::lock_guard<std::mutex> lk(g_blas_mu);
+struct BlasLease {
+    std::unique_lock<std::mutex> lk;
+    rocblas_handle h = nullptr;
+};
+
+static sv_status blas_lease(hipStream_t st, BlasLease &L) {
+    L.lk = std::unique_lock<std::mutex>(g_blas_mu);
     if (!g_blas && rocblas_create_handle(&g_blas) != rocblas_status_success)
         return fail(SV_EDEVICE, "rocblas_create_handle failed");
     if (rocblas_set_stream(g_blas, st) != rocblas_status_success) return fail(SV_EDEVICE, "rocblas_set_stream failed");
-    *out = g_blas;
+    L.h = g_blas;
     return SV_OK;
 }
 
@@ -405,8 +419,9 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
     SV_TRY(dRes.alloc(sizeof(double)));
     SV_TRY(dSweeps.alloc(sizeof(int)));
     SV_TRY(dV.alloc((size_t)N * N * sizeof(double2)));
-    rocblas_handle h;
-    SV_TRY(blas_handle(s->stream, &h));
+    BlasLease lease;
+    SV_TRY(blas_lease(s->stream, lease));
+    const rocblas_handle h = lease.h;
     std::vector<double> Vh(2 * (size_t)N * N);
     double worst = 0.0;
     std::string tried;
@@ -476,8 +491,9 @@ sv_status eigh_device_batched(sv_state s, const std::vector<const double *> &As,
     SV_TRY(dE.alloc((size_t)N * cnt * sizeof(double)));
     SV_TRY(dInfo.alloc(cnt * sizeof(int)));
     SV_TRY(upload(s, dA.p, Ar.data(), Ar.size() * sizeof(double)));
-    rocblas_handle h;
-    SV_TRY(blas_handle(s->stream, &h));
+    BlasLease lease;
+    SV_TRY(blas_lease(s->stream, lease));
+    const rocblas_handle h = lease.h;
     const rocblas_status rs = rocsolver_dsyevd_strided_batched(
         h, rocblas_evect_original, rocblas_fill_upper, N, (double *)dA.p, N, (rocblas_stride)NN, (double *)dD.p,
         (rocblas_stride)N, (double *)dE.p, (rocblas_stride)N, (rocblas_int *)dInfo.p, cnt);
@@ -488,6 +504,7 @@ sv_status eigh_device_batched(sv_state s, const std::vector<const double *> &As,
         SV_TRY(download(s, info.data(), dInfo.p, cnt * sizeof(int)));
     }
     std::vector<double> Vh(2 * NN);
+    lease.lk.unlock();          // eigh_device below takes the handle itself
     for (int i = 0; i < cnt; ++i) {
         bool ok = rs == rocblas_status_success && info[i] == 0;
         if (ok) {
@@ -564,45 +581,120 @@ __global__ void k_conj_transpose(double2 *__restrict__ out, const double2 *__res
     }
 }
 
-// out = in^T (transpose) or in, conjugated if conj, for an n x n row-major matrix
-__global__ void k_transpose_conj(double2 *__restrict__ out, const double2 *__restrict__ in, int n, int transpose,
-                                 int conj) {
-    const uint64_t total = (uint64_t)n * n;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t q = i / n, c = i % n;
-        const double2 v = in[transpose ? c * n + q : i];
-        out[i] = make_double2(v.x, conj ? -v.y : v.y);
+
+// Dense basis change, FP64, reading V once from HBM.
+// k_gemv_rows: out[i] = sum_j V[i][j] z[j].  A block of four wavefronts takes
+// 64 rows, 16 per wavefront; z passes through LDS in chunks of 2048 entries,
+// and the lanes of a wavefront read 64 consecutive entries of a row (512 B
+// real, 1 KiB complex) per load.  Each row's sum is reduced across the
+// wavefront in a fixed order.
+__device__ __forceinline__ double2 vmul_acc(double v, double2 z, double2 a) {
+    return make_double2(fma(v, z.x, a.x), fma(v, z.y, a.y));
+}
+__device__ __forceinline__ double2 vmul_acc(double2 v, double2 z, double2 a) {
+    return make_double2(fma(v.x, z.x, fma(-v.y, z.y, a.x)), fma(v.x, z.y, fma(v.y, z.x, a.y)));
+}
+// conj(v) * z + a
+__device__ __forceinline__ double2 vcmul_acc(double v, double2 z, double2 a) { return vmul_acc(v, z, a); }
+__device__ __forceinline__ double2 vcmul_acc(double2 v, double2 z, double2 a) {
+    return make_double2(fma(v.x, z.x, fma(v.y, z.y, a.x)), fma(v.x, z.y, fma(-v.y, z.x, a.y)));
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gemv_rows(double2 *__restrict__ out, const VT *__restrict__ V,
+                                                   const double2 *__restrict__ z, uint64_t N) {
+    constexpr int RPW = 16, ZC = 2048;
+    __shared__ double2 zs[ZC];
+    const int lane = threadIdx.x & 63;
+    const uint64_t r0 = (uint64_t)blockIdx.x * (4 * RPW) + (uint64_t)(threadIdx.x >> 6) * RPW;
+    double2 acc[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] = make_double2(0.0, 0.0);
+    for (uint64_t j0 = 0; j0 < N; j0 += ZC) {
+        const int J = (int)(N - j0 < (uint64_t)ZC ? N - j0 : (uint64_t)ZC);
+        __syncthreads();
+        for (int t = threadIdx.x; t < J; t += 256) zs[t] = z[j0 + t];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            if (r0 + r >= N) break;
+            const VT *row = V + (r0 + r) * N + j0;
+            double2 a = acc[r];
+            for (int t = lane; t < J; t += 64) a = vmul_acc(row[t], zs[t], a);
+            acc[r] = a;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const double re = wave_sum_f64(acc[r].x), im = wave_sum_f64(acc[r].y);
+        if (lane == 0 && r0 + r < N) out[r0 + r] = make_double2(re, im);
     }
 }
 
-// The basis change of a plan on the matrix cores (rocBLAS zgemm, FP64):
-// out = (V_hi (x) V_lo) in, or with the conjugate transposes (adjoint).  The
-// vector is the row-major n_hi x n_lo matrix X; column-major it is X^T, so
-//   along the low axis:  X V^T  ->  (X V^T)^T = V X^T = op_T(Vbuf) X^T
-//   along the high axis: V X    ->  (V X)^T  = X^T V^T = X^T Vbuf
-// where Vbuf, the row-major V, reads as V^T column-major.  The low axis takes
-// the row-major V^T (forward) or conj(V) (adjoint), read as V or V^H
-// column-major, so that both products run without a transposed operand.
+// k_gemv_cols: out[j] = sum_i conj(V[i][j]) b[i].  A block of four wavefronts
+// takes 64 columns, one per lane; wavefront w sums the rows i = w mod 4 (each
+// load a 512 B or 1 KiB row segment), and the four partial sums are added in
+// a fixed order.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gemv_cols(double2 *__restrict__ out, const VT *__restrict__ V,
+                                                   const double2 *__restrict__ b, uint64_t N) {
+    __shared__ double2 part[3][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t j = (uint64_t)blockIdx.x * 64 + lane;
+    const bool ok = j < N;
+    double2 acc = make_double2(0.0, 0.0);
+    if (ok) {
+#pragma unroll 8
+        for (uint64_t i = w; i < N; i += 4) acc = vcmul_acc(V[i * N + j], b[i], acc);
+    }
+    if (w > 0) part[w - 1][lane] = acc;
+    __syncthreads();
+    if (w == 0 && ok) {
+        const double2 p1 = part[0][lane], p2 = part[1][lane], p3 = part[2][lane];
+        out[j] = make_double2((acc.x + p1.x) + (p2.x + p3.x), (acc.y + p1.y) + (p2.y + p3.y));
+    }
+}
+
+// the dense basis change: out = V in (forward) or V^H in (adjoint), V N x N
+// row-major FP64, real (Vr) or complex (Vc)
+static sv_status gemv_apply(hipStream_t st, double2 *out, const double2 *in, const double *Vr, const double2 *Vc,
+                            uint64_t N, int adjoint) {
+    const double bytes = (double)N * (double)N * (Vr ? sizeof(double) : sizeof(double2));
+    TraceScope _ts(st, adjoint ? "gemv_vh" : "gemv_v", bytes, 8.0 * (double)N * (double)N);
+    if (adjoint) {
+        const unsigned g = (unsigned)((N + 63) / 64);
+        if (Vr) hipLaunchKernelGGL(k_gemv_cols<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
+        else hipLaunchKernelGGL(k_gemv_cols<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
+    } else {
+        const unsigned g = (unsigned)((N + 63) / 64);
+        if (Vr) hipLaunchKernelGGL(k_gemv_rows<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
+        else hipLaunchKernelGGL(k_gemv_rows<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
+    }
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+
+static int ilog2(uint64_t v) { return 63 - __builtin_clzll(v); }
+
+// The basis change of a plan: out = (V_hi (x) V_lo) in, or with the conjugate
+// transposes (adjoint).  The vector is the row-major n_hi x n_lo matrix X.
+// Kronecker plans: two complex FP64 GEMMs on the matrix cores (k_cgemm):
+//   low axis:  each row x_r of X -> V_lo x_r (forward) or V_lo^H x_r
+//              (k_cgemm with B(k, n) = V_lo[n][k], or conj(V_lo[k][n]));
+//   high axis: V_hi Y or V_hi^H Y, the rows of V_hi (or of its stored
+//              conjugate transpose) times Y.
+// Dense plans: one GEMV over V (real, a caller's eigenbasis, or complex).
 static sv_status kron_apply_frame(sv_state s, double2 *out, const double2 *in, double2 *tmp, const EigFrame &E,
                                   int adjoint) {
-    rocblas_handle h;
-    SV_TRY(blas_handle(s->stream, &h));
-    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-    const rocblas_int nh = E.n_hi, nl = E.n_lo;
-    const double2 *Whi = (const double2 *)(adjoint ? E.VH_hi.p : E.V_hi.p);
-    if (nl > 1) {
-        const double2 *Wlo = (const double2 *)(adjoint ? E.VC_lo.p : E.VT_lo.p);
-        if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, nl, nh, nl, &one,
-                          (const rocblas_double_complex *)Wlo, nl, (const rocblas_double_complex *)in, nl, &zero,
-                          (rocblas_double_complex *)tmp, nl) != rocblas_status_success)
-            return fail(SV_EDEVICE, "rocblas_zgemm (low axis) failed");
-        in = tmp;
-    }
-    if (rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, nl, nh, nh, &one,
-                      (const rocblas_double_complex *)in, nl, (const rocblas_double_complex *)Whi, nh, &zero,
-                      (rocblas_double_complex *)out, nl) != rocblas_status_success)
-        return fail(SV_EDEVICE, "rocblas_zgemm (high axis) failed");
-    return SV_OK;
+    const hipStream_t st = s->stream;
+    const uint64_t nh = (uint64_t)E.n_hi, nl = (uint64_t)E.n_lo;
+    if (E.Vr) return gemv_apply(st, out, in, E.Vr, nullptr, nh * nl, adjoint);
+    if (nl <= 1) return gemv_apply(st, out, in, nullptr, (const double2 *)E.V_hi.p, nh, adjoint);
+    SV_TRY(cgemm<double>(st, in, tmp, (const double2 *)E.V_lo.p, nh, (int)nl, (int)nl, (nh - 1) << ilog2(nl), 0,
+                         adjoint, adjoint));
+    const double2 *W = (const double2 *)(adjoint ? E.VH_hi.p : E.V_hi.p);
+    return cgemm<double>(st, W, out, tmp, nh, (int)nl, (int)nh, (nh - 1) << ilog2(nh), 0, 1, 0);
 }
 
 static int pick_log_len(uint64_t N, int n_c) {
@@ -933,27 +1025,82 @@ sv_status sv_hhl_prepare(sv_hhl_plan *out, sv_state s, const double *A_hi, int m
                 for (int q = 0; q < nl; ++q) p->E.lam[(size_t)a * nl + q] = mu[a] + nu[q];
         }
     }
-    // conjugate transposes for the basis change into the eigen-frame
-    if (st == SV_OK) st = p->E.VH_hi.alloc((size_t)nh * nh * sizeof(double2));
-    if (st == SV_OK && m_lo) st = p->E.VH_lo.alloc((size_t)nl * nl * sizeof(double2));
-    if (st == SV_OK && m_lo) st = p->E.VT_lo.alloc((size_t)nl * nl * sizeof(double2));
-    if (st == SV_OK && m_lo) st = p->E.VC_lo.alloc((size_t)nl * nl * sizeof(double2));
-    if (st == SV_OK) {
+    // V_hi^H: the rows of the high-axis GEMM of the V^H basis change (Kronecker plans)
+    if (st == SV_OK && m_lo) st = p->E.VH_hi.alloc((size_t)nh * nh * sizeof(double2));
+    if (st == SV_OK && m_lo) {
         hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nh * nh)), dim3(256), 0, s->stream,
                            (double2 *)p->E.VH_hi.p, (const double2 *)p->E.V_hi.p, nh);
-        if (m_lo) {
-            hipLaunchKernelGGL(k_conj_transpose, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
-                               (double2 *)p->E.VH_lo.p, (const double2 *)p->E.V_lo.p, nl);
-            hipLaunchKernelGGL(k_transpose_conj, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
-                               (double2 *)p->E.VT_lo.p, (const double2 *)p->E.V_lo.p, nl, 1, 0);
-            hipLaunchKernelGGL(k_transpose_conj, dim3(grid1((uint64_t)nl * nl)), dim3(256), 0, s->stream,
-                               (double2 *)p->E.VC_lo.p, (const double2 *)p->E.V_lo.p, nl, 0, 1);
-        }
         const hipError_t he = hipGetLastError();
         if (he != hipSuccess) st = hip_fail(he, "k_conj_transpose");
     }
     if (st == SV_OK) st = p->E.lam_dev.alloc(p->E.lam.size() * sizeof(double));
     if (st == SV_OK) st = upload(s, p->E.lam_dev.p, p->E.lam.data(), p->E.lam.size() * sizeof(double));
+    if (st != SV_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return SV_OK;
+}
+
+sv_status sv_hhl_prepare_eig(sv_hhl_plan *out, sv_state s, const double *V_dev, const double *lam, int n_s) {
+    clear_error();
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    SV_TRY(check_state(s));
+    if (!V_dev || !lam) return fail(SV_EINVAL, "V_dev/lam is NULL");
+    if (n_s < 1 || n_s > 16) return fail(SV_EINVAL, "n_s = %d outside [1, 16]", n_s);
+    const uint64_t N = dim_of(n_s);
+    for (uint64_t j = 0; j < N; ++j)
+        if (!isfinite(lam[j])) return fail(SV_EINVAL, "eigenvalue %llu is not finite", (unsigned long long)j);
+    sv_hhl_plan p = new sv_hhl_plan_s();
+    p->E.n_s = n_s;
+    p->E.n_hi = (int)N;
+    p->E.n_lo = 1;
+    p->E.lam.assign(lam, lam + N);
+    p->E.Vr = V_dev;
+    sv_status st = p->E.lam_dev.alloc(N * sizeof(double));
+    if (st == SV_OK) st = upload(s, p->E.lam_dev.p, lam, N * sizeof(double));
+    // orthogonality probe through the basis-change kernels: V V^T r = r for a
+    // fixed pseudo-random r (splitmix64 draws in [-1, 1))
+    if (st == SV_OK) {
+        std::vector<double> r(2 * N), u(2 * N);
+        uint64_t x = 0x9e3779b97f4a7c15ull;
+        for (uint64_t i = 0; i < 2 * N; ++i) {
+            x += 0x9e3779b97f4a7c15ull;
+            uint64_t z = x;
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            z ^= z >> 31;
+            r[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+        }
+        DevBuf dr, dt, du;
+        st = dr.alloc(N * sizeof(double2));
+        if (st == SV_OK) st = dt.alloc(N * sizeof(double2));
+        if (st == SV_OK) st = du.alloc(N * sizeof(double2));
+        if (st == SV_OK) st = upload(s, dr.p, r.data(), N * sizeof(double2));
+        if (st == SV_OK) st = gemv_apply(s->stream, (double2 *)dt.p, (const double2 *)dr.p, V_dev, nullptr, N, 1);
+        if (st == SV_OK) st = gemv_apply(s->stream, (double2 *)du.p, (const double2 *)dt.p, V_dev, nullptr, N, 0);
+        if (st == SV_OK) st = download(s, u.data(), du.p, N * sizeof(double2));
+        if (st == SV_OK) {
+            double e2 = 0.0, r2 = 0.0;
+            for (uint64_t i = 0; i < 2 * N; ++i) {
+                e2 += (u[i] - r[i]) * (u[i] - r[i]);
+                r2 += r[i] * r[i];
+            }
+            if (!(e2 <= 1e-20 * r2)) st = fail(SV_EINVAL, "V is not orthogonal (|V V^T r - r| / |r| = %g)", sqrt(e2 / r2));
+        }
+    }
+    // the gate-faithful mode needs the complex V (small operators only)
+    if (st == SV_OK && n_s <= 13) {
+        st = p->E.V_hi.alloc(N * N * sizeof(double2));
+        if (st == SV_OK) {
+            hipLaunchKernelGGL(k_real_to_complex, dim3(grid1(N * N)), dim3(256), 0, s->stream, (double2 *)p->E.V_hi.p,
+                               V_dev, N * N);
+            const hipError_t he = hipGetLastError();
+            if (he != hipSuccess) st = hip_fail(he, "k_real_to_complex");
+        }
+    }
     if (st != SV_OK) {
         delete p;
         return st;
@@ -1003,7 +1150,7 @@ static sv_status hhl_run_impl(sv_hhl_plan p, sv_state s, const double *b, const 
                                            b_dev, x_dev);
     }
     // gate-faithful: dense eigenvectors
-    if (p->E.n_s > 13) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
+    if (p->E.n_s > 13 || !p->E.V_hi.p) return fail(SV_EUNSUPPORTED, "gate-faithful mode with n_s = %d > 13", p->E.n_s);
     const double2 *dV = (const double2 *)p->E.V_hi.p;
     if (p->E.n_lo > 1) {
         if (!p->V_dense.p) {

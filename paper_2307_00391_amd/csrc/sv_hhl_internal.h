@@ -54,11 +54,11 @@ __global__ void k_turn_table(uint64_t *__restrict__ F, const double *__restrict_
 struct EigFrame {
     int n_s = 0, n_hi = 0, n_lo = 1;
     DevBuf V_hi, V_lo;            // FP64 complex, row-major, column j = eigenvector j
-    DevBuf VH_hi, VH_lo;          // their conjugate transposes (for the V^H basis change)
-    DevBuf VT_lo, VC_lo;          // V_lo^T and conj(V_lo), row-major: the low-axis GEMM's operand
-                                  // without a transpose, forward and adjoint
+    DevBuf VH_hi;                 // V_hi^H (Kronecker plans: the rows of the high-axis GEMM of V^H)
     DevBuf lam_dev;               // the eigenvalues on the device (FP64)
     std::vector<double> lam;      // ascending for dense; mu_p + nu_q (p major) for Kronecker
+    const double *Vr = nullptr;   // a caller's real orthogonal V (device, row-major, borrowed):
+                                  // the basis change then runs as two FP64 GEMVs over it
 };
 
 sv_status check_hermitian(const double *A, int N, const char *name);

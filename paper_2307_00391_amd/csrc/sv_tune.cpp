@@ -95,6 +95,15 @@ sv_status time_stream(hipStream_t st, int reps, float *ms_out, const std::functi
 
 using namespace sv;
 
+extern "C" sv_status sv_tune_set(const char *key, const int *vals, int n) {
+    if (!key || !key[0] || n < 0 || (n > 0 && !vals)) return fail(SV_EINVAL, "bad tuning entry");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    load_file();
+    if (n == 0) g_tune.erase(key);
+    else g_tune[key] = std::vector<int>(vals, vals + n);
+    return SV_OK;
+}
+
 extern "C" int sv_tune_report(char *buf, int len) {
     std::lock_guard<std::mutex> lk(g_tmu);
     std::string out;

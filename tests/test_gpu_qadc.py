@@ -47,7 +47,7 @@ def _u(n, seed):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("n,r", [(1, 1), (1, 4), (2, 3), (2, 5), (3, 3), (5, 3), (6, 2)])
+@pytest.mark.parametrize("n,r", [(1, 1), (1, 4), (2, 3), (2, 5), (3, 3), (4, 3), (5, 3), (6, 2)])
 def test_qadc_matches_oracle(dt, mode, n, r):
     u = _u(n, 10 * n + r)
     print(f"[qadc] {dt} mode {mode} n {n} r {r}", flush=True)
@@ -132,3 +132,31 @@ def test_qadc_errors():
             B.sv_qadc_square(st.h, np.ones(128), 1, mode=1)
     finally:
         st.close()
+
+
+def test_qadc_unpacked_kernels_in_a_child_process():
+    """SV_QADC_PACKED=0 (read once per process): the one-column-per-wavefront
+    kernels for the packed shapes n = 3 and 4, against the oracle."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r"""
+import numpy as np, oracle
+from paper_2307_00391_amd import binding as B
+from tests.test_gpu_qadc import _u, _tol
+B.lib()
+for dt in ("c128", "c64"):
+    for n, r in ((3, 3), (4, 3)):
+        u = _u(n, 10 * n + r)
+        ref = oracle.qadc_square(u, r, avg=True)
+        st = B.State(3 * n + r + 2, dt)
+        B.sv_qadc_square(st.h, u, r, mode=1, avg=True)
+        err = np.abs(st.get() - ref).max()
+        st.close()
+        assert err <= _tol(dt, n, r), (dt, n, r, err)
+print("unpacked ok")
+"""
+    env = dict(os.environ, SV_QADC_PACKED="0")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "unpacked ok" in r.stdout, r.stdout + r.stderr
