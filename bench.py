@@ -89,6 +89,187 @@ def cpu_baseline(seconds: float):
                       f"kappa=1000), n_c=10, 17 qubits, full circuit on the full state, {el:.1f} s"}
 
 
+def cpu_legs():
+    """The oracle on the host cores, 1 thread and all threads: the two flow
+    workloads (Poiseuille, 11 qubits; Couette, 19 qubits), an 8-instance
+    subset of the sweep family (the first 8 of the 64 with n_s <= 6: the
+    oracle's Jacobi eigen-solver is cubic in N) on 4 T0 each, and the
+    U3 + CNOT probe at reduced n (26 qubits, one layer).  Returns the records
+    and the all-thread Couette solve (the on-box parity reference)."""
+    import oracle
+    from paper_2307_00391_amd import inputs
+    X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    allt = oracle.num_threads()
+    legs = []
+    couette_ref = None
+    for threads in (1, allt):
+        oracle.set_num_threads(threads)
+        s = inputs.poiseuille(16)
+        T0 = inputs.t0_top_of_clock(s.lambda_max, 6)
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            oracle.hhl(s.A, s.b, 6, T0)
+            n += 1
+        el = time.perf_counter() - t0
+        legs.append({"workload": "Poiseuille HHL, N=16, n_c=6, 11 qubits (complex128)", "threads": threads,
+                     "solves": n, "seconds": el, "solves_per_s": n / el})
+        c = inputs.couette(256)
+        T0 = inputs.t0_top_of_clock(c.lambda_max, 10)
+        t0 = time.perf_counter()
+        r = oracle.hhl(c.A, c.b, 10, T0)
+        el = time.perf_counter() - t0
+        legs.append({"workload": "Couette HHL, N=256, n_c=10, 19 qubits (complex128)", "threads": threads,
+                     "solves": 1, "seconds": el, "solves_per_s": 1.0 / el})
+        if threads == allt:
+            couette_ref = r
+    oracle.set_num_threads(allt)
+    sub = [i for i in inputs.sweep_instances(64) if i.n_s <= 6][:8]
+    t0 = time.perf_counter()
+    for i in sub:
+        for T0 in i.t0[::5][:4]:
+            oracle.hhl(i.A, i.b, i.n_c, T0)
+    el = time.perf_counter() - t0
+    legs.append({"workload": "sweep family, 8 instances x 4 T0 (instances " + ",".join(str(i.index) for i in sub) +
+                 ", n_s <= 6, n_c 8..12)", "threads": allt, "solves": 4 * len(sub), "seconds": el,
+                 "solves_per_s": 4 * len(sub) / el})
+    q = 26
+    gates = inputs.probe_layers(inputs.rng_for(3, 1000), q, 1)
+    psi = np.zeros(1 << q, dtype=np.complex128)
+    psi[0] = 1.0
+    t0 = time.perf_counter()
+    for g in gates:
+        if g[0] == "u":
+            oracle.apply_gate(psi, g[1], g[2])
+        else:
+            oracle.apply_gate(psi, g[2], X, [g[1]], [1])
+    el = time.perf_counter() - t0
+    from paper_2307_00391_amd import metrics
+    legs.append({"workload": f"U3 + CNOT probe at reduced n: {q} qubits, one layer ({len(gates)} gates), complex128",
+                 "threads": allt, "seconds": el, "updates_per_s": metrics.probe_updates(q, 1) / el})
+    del psi
+    return legs, couette_ref
+
+
+def dense_basis_record(args, dev, ks, T0, b_dev, n_c, steps=5):
+    """The 32-qubit step on a dense eigenbasis: V = H (P_hi (x) P_lo), the
+    Kronecker eigenbasis turned by a Householder reflection H about a dense
+    random vector, so that A = V diag(lam) V^T is a dense, non-separable
+    2^16 x 2^16 operator with the same spectrum.  V (FP64, 32 GiB) is formed on
+    the device (untimed setup); the basis changes are FP64 GEMVs over it."""
+    import torch
+    from paper_2307_00391_amd import binding as B
+    from paper_2307_00391_amd import inputs, metrics
+    n_s = args.m_hi + args.m_lo
+    n = n_s + n_c + 1
+    mu, P = np.linalg.eigh(ks.A_hi)
+    nu, Q = np.linalg.eigh(ks.A_lo)
+    lam = (mu[:, None] + nu[None, :]).ravel()
+    w = inputs.rng_for(3, 3).standard_normal(1 << n_s)
+    t_setup = time.perf_counter()
+    Pt = torch.tensor(P, dtype=torch.float64, device=dev)
+    Qt = torch.tensor(Q, dtype=torch.float64, device=dev)
+    wt = torch.tensor(w, dtype=torch.float64, device=dev)
+    V = torch.kron(Pt, Qt)
+    u = torch.mv(V.t(), wt)
+    V.addr_(wt, u, alpha=-2.0 / float(torch.dot(wt, wt)))
+    del Pt, Qt, u
+    st = B.State(n, "c64", device=dev)
+    plan = B.sv_hhl_prepare_eig(st.h, V, lam)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    x_dev = torch.empty(1 << n_s, dtype=torch.complex128, device=dev)
+    res = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, 1, x_dev=x_dev)     # warm-up
+    torch.cuda.synchronize()
+    B.sv_trace_enable(True)
+    t = time.perf_counter()
+    for _ in range(steps):
+        res = B.sv_hhl_run_device(plan, st.h, b_dev, n_c, T0, 1, x_dev=x_dev)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / steps
+    tr = B.sv_trace_report()
+    B.sv_trace_enable(False)
+    x = x_dev.cpu().numpy()
+    B.sv_hhl_plan_free(plan)
+    st.close()
+    del V, st
+    torch.cuda.empty_cache()
+    # the classical solution through the factors: x_C = H (P_hi (Lam^-1 .) P_lo^T) (P^T (H b))
+    bh = ks.b / np.linalg.norm(ks.b)
+    c = bh - 2.0 * w * (w @ bh) / (w @ w)
+    gam = (P.T @ c.reshape(P.shape[0], Q.shape[0]) @ Q).ravel() / lam
+    y = (P @ gam.reshape(P.shape[0], Q.shape[0]) @ Q.T).ravel()
+    xc = y - 2.0 * w * (w @ y) / (w @ w)
+    F = metrics.fidelity(x, xc)
+    gv = {k: v for k, v in tr.items() if k.startswith("gemv")}
+    gbytes = sum(v["bytes"] for v in gv.values())
+    gms = sum(v["ms"] for v in gv.values())
+    ach = gbytes / (gms * 1e-3) / 1e9 if gms > 0 else None
+    rec = {"workload": f"HHL {n} qubits, n_s={n_s}, n_c={n_c}, complex64, eigen-frame mode: the operator "
+                       "V diag(lam) V^T with V = H (V_hi (x) V_lo) dense (H a Householder reflection about a "
+                       "seeded Gaussian vector), the Kronecker-sum spectrum (kappa=1000); V real FP64 in HBM",
+           "ms_per_step": 1e3 * el, "steps": steps, "solves_per_s": 1.0 / el, "setup_s_V_on_device": t_setup,
+           "kernels": {k: {"launches_per_step": v["launches"] / steps, "ms_per_step": v["ms"] / steps,
+                           "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
+                       for k, v in tr.items()},
+           "roofline_basis_change": {"bound": "hbm", "kernels": sorted(gv), "achieved": ach, "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
+                                     "bytes_per_launch": gbytes / max(1, sum(v["launches"] for v in gv.values()))},
+           "one_minus_F": 1.0 - F, "p_post": res.p_post}
+    log(f"[bench] dense basis: {1e3 * el:.2f} ms per step, basis change {ach:.0f} GB/s, 1-F {1.0 - F:.2e}")
+    return rec
+
+
+def flow_records(dev, couette_ref):
+    """The flow workloads on the GPU: Poiseuille (11 qubits, complex128) and
+    Couette (19 qubits, complex128 and complex64), gate-faithful (mode 0) and
+    fused eigen-frame (mode 1): solves/s of sv_hhl (eigen-decomposition
+    included) and of a prepared plan, and parity with the oracle on the box."""
+    import oracle
+    import torch
+    from paper_2307_00391_amd import binding as B
+    from paper_2307_00391_amd import inputs, metrics
+    out = {}
+    cases = [("poiseuille", inputs.poiseuille(16), 6, ("c128", "c64")), ("couette", inputs.couette(256), 10,
+                                                                          ("c128", "c64"))]
+    for name, sysm, n_c, dts in cases:
+        n_s = sysm.A.shape[0].bit_length() - 1
+        T0 = inputs.t0_top_of_clock(sysm.lambda_max, n_c)
+        ref = couette_ref if (name == "couette" and couette_ref is not None) else oracle.hhl(sysm.A, sysm.b, n_c, T0)
+        _, x_r, pp_r, pa_r = ref
+        xc = np.linalg.solve(sysm.A, sysm.b)
+        rec = {"qubits": n_s + n_c + 1, "n_s": n_s, "n_c": n_c, "T0": T0,
+               "F_oracle_vs_classical": metrics.fidelity(x_r, xc), "p_post_oracle": pp_r}
+        for dt in dts:
+            st = B.State(n_s + n_c + 1, dt, device=dev)
+            plan = B.sv_hhl_prepare(st.h, sysm.A)
+            for mode in (0, 1):
+                x, res = B.sv_hhl(st.h, sysm.A, sysm.b, n_c, T0, mode)          # first use (tuning)
+                reps = 20 if n_s <= 4 else 5
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(reps):
+                    x, res = B.sv_hhl(st.h, sysm.A, sysm.b, n_c, T0, mode)
+                el_full = (time.perf_counter() - t) / reps
+                B.sv_hhl_run(plan, st.h, sysm.b, n_c, T0, mode)
+                t = time.perf_counter()
+                for _ in range(reps):
+                    xp, resp = B.sv_hhl_run(plan, st.h, sysm.b, n_c, T0, mode)
+                el_run = (time.perf_counter() - t) / reps
+                rec[f"{dt}_mode{mode}"] = {
+                    "solves_per_s_sv_hhl": 1.0 / el_full, "solves_per_s_prepared": 1.0 / el_run,
+                    "x_max_abs_err_vs_oracle": float(np.abs(x - x_r).max()),
+                    "x_rel_l2_vs_oracle": float(np.linalg.norm(x - x_r) / np.linalg.norm(x_r)),
+                    "p_post_rel_err_vs_oracle": abs(res.p_post - pp_r) / pp_r,
+                    "p_anc_abs_err_vs_oracle": abs(res.p_anc - pa_r),
+                    "F_vs_classical": metrics.fidelity(x, xc), "F_vs_analytic": metrics.fidelity(x, sysm.profile)}
+            B.sv_hhl_plan_free(plan)
+            st.close()
+        out[name] = rec
+        log(f"[bench] {name}: " + ", ".join(f"{k} {v['solves_per_s_prepared']:.0f}/s err {v['x_max_abs_err_vs_oracle']:.1e}"
+                                            for k, v in rec.items() if isinstance(v, dict)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +289,8 @@ def main():
     ap.add_argument("--no-qpp", action="store_true")
     ap.add_argument("--no-qlsa2", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-flow", action="store_true")
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -175,8 +358,9 @@ def main():
     ms_per_step = max(ms, 1e3 * t_wall) / args.steps
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step")
     x = x_dev.cpu().numpy()
-    # mixed precision: the same solve on a complex128 state (FP64 amplitudes), and
-    # the complex64 result's error against it
+    # mixed precision: the same solve on a complex128 state (FP64 amplitudes),
+    # timed over a few steps with its own kernel roofline, and the complex64
+    # result's error against it
     mixed = None
     if not args.no_mixed:
         s128 = B.State(n, "c128", device=dev)
@@ -184,21 +368,38 @@ def main():
         x128_dev = torch.empty(1 << n_s, dtype=torch.complex128, device=dev)
         B.sv_hhl_run_device(plan128, s128.h, b_dev, n_c, T0, 1, x_dev=x128_dev)          # first use: tuning
         torch.cuda.synchronize()
+        steps128 = 3
+        B.sv_trace_enable(True)
         t128 = time.perf_counter()
-        r128 = B.sv_hhl_run_device(plan128, s128.h, b_dev, n_c, T0, 1, x_dev=x128_dev)
+        for _ in range(steps128):
+            r128 = B.sv_hhl_run_device(plan128, s128.h, b_dev, n_c, T0, 1, x_dev=x128_dev)
         torch.cuda.synchronize()
-        t128 = time.perf_counter() - t128
+        t128 = (time.perf_counter() - t128) / steps128
+        tr128 = B.sv_trace_report()
+        B.sv_trace_enable(False)
         x128 = x128_dev.cpu().numpy()
         ph = np.vdot(x128, x)
         ph = ph / abs(ph) if abs(ph) > 0 else 1.0
-        mixed = {"c128_ms_per_step": 1e3 * t128, "x_max_abs_diff_c64_vs_c128": float(np.abs(x - ph * x128).max()),
+        dn, dk = max(tr128.items(), key=lambda kv: kv[1]["ms"])
+        ach128 = (dk["bytes"] / dk["launches"]) / (dk["ms"] / dk["launches"] * 1e-3) / 1e9
+        mixed = {"c128_ms_per_step": 1e3 * t128, "c128_steps_timed": steps128,
+                 "c128_kernels": {k: {"ms_per_step": v["ms"] / steps128,
+                                      "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
+                                  for k, v in tr128.items()},
+                 "c128_roofline": {"bound": "hbm", "kernel": dn, "achieved": ach128, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": ach128 / HBM_PEAK_GBS,
+                                   "bytes_per_launch": dk["bytes"] / dk["launches"],
+                                   "ms_per_launch": dk["ms"] / dk["launches"]},
+                 "c128_hbm_gbs_step": sum(v["bytes"] for v in tr128.values()) / steps128 / t128 / 1e9,
+                 "x_max_abs_diff_c64_vs_c128": float(np.abs(x - ph * x128).max()),
+                 "x_rel_l2_diff_c64_vs_c128": float(np.linalg.norm(x - ph * x128) / np.linalg.norm(x128)),
                  "p_post_rel_diff_c64_vs_c128": abs(res.p_post - r128.p_post) / r128.p_post,
                  "one_minus_F_c128": 1.0 - metrics.fidelity(x128, metrics.kron_solve(ks.A_hi, ks.A_lo, ks.b))}
         B.sv_hhl_plan_free(plan128)
         s128.close()
         del s128
         torch.cuda.empty_cache()
-        log(f"[bench] complex128 solve {1e3 * t128:.2f} ms; complex64 x differs by "
+        log(f"[bench] complex128 solve {1e3 * t128:.2f} ms ({dn} {ach128:.0f} GB/s); complex64 x differs by "
             f"{mixed['x_max_abs_diff_c64_vs_c128']:.2e}")
     # the same solve from and to host buffers (PCIe included), for reference only
     t_host = time.perf_counter()
@@ -230,9 +431,13 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 (fp32 amplitudes, fp64 eigendecomposition/phases/post-selected norm)",
         "data": "synthetic",
-        "config": {"workload": f"HHL {n} qubits: n_s={n_s} (2-D Laplacian on a {1 << m_hi}x{1 << m_lo} grid as a "
-                               f"Kronecker sum + random symmetric perturbation |E|=0.1, kappa=1000), n_c={n_c}, "
-                               "1 ancilla, complex64, eigen-frame mode (fused kernels)",
+        "config": {"workload": f"HHL {n} qubits: n_s={n_s}, n_c={n_c}, 1 ancilla, complex64, eigen-frame mode "
+                               f"(fused kernels). Operator: a Kronecker sum A_hi(x)I + I(x)A_lo - the 2-D Laplacian "
+                               f"on a {1 << m_hi}x{1 << m_lo} grid plus a random symmetric banded perturbation that is "
+                               "itself a Kronecker sum E_hi(x)I + I(x)E_lo (|E|=0.1), shifted to kappa=1000 - so its "
+                               "eigenbasis factors as V_hi(x)V_lo and the basis changes are two 256-point "
+                               "transforms; the same step on a dense non-separable 2^16 eigenbasis is the "
+                               "dense_basis record",
                    "global_batch": 1, "parallelism": "single GPU"},
         "hbm_gbs_step": step_bytes / (ms_per_step * 1e-3) / 1e9,
         "updates_per_step": upd,
@@ -258,6 +463,12 @@ def main():
     del st
     torch.cuda.empty_cache()
 
+    # ---------------- the same step on a dense (non-separable) eigenbasis ----------------
+    if not args.no_dense:
+        out["dense_basis"] = dense_basis_record(args, dev, ks, T0, b_dev, n_c)
+    del b_dev, x_dev
+    torch.cuda.empty_cache()
+
     # ---------------- 33-qubit U3 + CNOT-ladder probe ----------------
     if not args.no_probe:
         q = args.probe_qubits
@@ -279,12 +490,14 @@ def main():
         nrm = B.sv_norm2(ps.h)
         fp = tr.get("fused_pass", {"bytes": 0.0, "ms": 1.0, "launches": 1})
         pu = metrics.probe_updates(q, args.probe_layers)
-        out["probe"] = {"qubits": q, "layers": args.probe_layers, "gates": len(gates), "passes": passes,
+        out["probe"] = {"qubits": q, "layers": args.probe_layers, "gates": len(gates), "passes": fp["launches"],
+                        "passes_default_plan": passes,
+                        "fusion_tuned": [ln for ln in B.sv_tune_report().splitlines() if ln.startswith(f"fused/c64/{q}/")],
                         "seconds": t, "updates_per_s": pu / t, "hbm_gbs": fp["bytes"] / t / 1e9,
                         "fused_pass_gbs": fp["bytes"] / (fp["ms"] * 1e-3) / 1e9,
                         "frac_of_hbm_peak": fp["bytes"] / (fp["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "norm_after_2_runs": nrm}
-        log(f"[bench] probe {t:.3f} s, {passes} passes, norm {nrm:.8f}")
+        log(f"[bench] probe {t:.3f} s, {fp['launches']} passes, norm {nrm:.8f}")
         ps.close()
         del ps
         torch.cuda.empty_cache()
@@ -485,9 +698,16 @@ def main():
         torch.cuda.empty_cache()
 
     # ---------------- CPU baseline: the oracle on the host cores ----------------
+    couette_ref = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        log("[bench] cpu legs: 1 thread and all threads (oracle)")
+        out["cpu_baseline_legs"], couette_ref = cpu_legs()
+
+    # ---------------- the flow workloads: Poiseuille and Couette ----------------
+    if not args.no_flow:
+        out["flow"] = flow_records(dev, couette_ref)
     print(json.dumps(out), flush=True)
 
 

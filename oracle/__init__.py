@@ -56,6 +56,7 @@ def _load():
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                   ctypes.c_uint64]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -84,6 +85,11 @@ def _nqubits(psi):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def apply_gate(psi, target, u, ctrls=(), cvals=None):

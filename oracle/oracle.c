@@ -931,3 +931,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the following calls (the CPU baseline times 1 and all) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

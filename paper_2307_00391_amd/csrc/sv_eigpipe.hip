@@ -708,11 +708,12 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     pipe_c_body<R, RA, RB, NT, false>(A, one, many);
 }
 
-// the persistent form (single solves): one G2 value per block; four waves per
-// SIMD, as the LDS allows, beat the fewer that the prefetched line's
-// registers would otherwise leave
+// the persistent form (single solves): one G2 value per block.  complex64:
+// four waves per SIMD, as the LDS allows, beat the fewer that the prefetched
+// line's registers would otherwise leave; complex128 lines need the
+// registers (held to four waves they spill)
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_pipe_cp(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, sizeof(R) == 4 ? 4 : 8))) void k_pipe_cp(
     PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
     pipe_c_body<R, RA, RB, NT, true>(A, one, many);
 }

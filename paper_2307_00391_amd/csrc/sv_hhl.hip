@@ -583,11 +583,7 @@ __global__ void k_conj_transpose(double2 *__restrict__ out, const double2 *__res
 
 
 // Dense basis change, FP64, reading V once from HBM.
-// k_gemv_rows: out[i] = sum_j V[i][j] z[j].  A block of four wavefronts takes
-// 64 rows, 16 per wavefront; z passes through LDS in chunks of 2048 entries,
-// and the lanes of a wavefront read 64 consecutive entries of a row (512 B
-// real, 1 KiB complex) per load.  Each row's sum is reduced across the
-// wavefront in a fixed order.
+// Dense basis change, FP64, reading V once from HBM.
 __device__ __forceinline__ double2 vmul_acc(double v, double2 z, double2 a) {
     return make_double2(fma(v, z.x, a.x), fma(v, z.y, a.y));
 }
@@ -600,34 +596,56 @@ __device__ __forceinline__ double2 vcmul_acc(double2 v, double2 z, double2 a) {
     return make_double2(fma(v.x, z.x, fma(v.y, z.y, a.x)), fma(v.x, z.y, fma(-v.y, z.x, a.y)));
 }
 
+// k_gemv_rows: the partial sums part[i][s] = sum_{j in segment s} V[i][j] z[j]
+// over segments of 1024 columns.  A block of four wavefronts takes 16 rows
+// (four per wavefront) of one segment, with z's segment in LDS; each lane
+// reads 16 entries of each of its wavefront's rows, 64 consecutive entries
+// (512 B real, 1 KiB complex) per load.  Blocks are numbered segment-fastest,
+// so the blocks in flight read whole rows of a few row groups, as a linear
+// sweep of V would (per-row streams spread over all of V read at half speed).
+constexpr int GV_SEG = 1024, GV_ROWS = 16;
+
 template <typename VT>
-__global__ __launch_bounds__(256) void k_gemv_rows(double2 *__restrict__ out, const VT *__restrict__ V,
-                                                   const double2 *__restrict__ z, uint64_t N) {
-    constexpr int RPW = 16, ZC = 2048;
-    __shared__ double2 zs[ZC];
-    const int lane = threadIdx.x & 63;
-    const uint64_t r0 = (uint64_t)blockIdx.x * (4 * RPW) + (uint64_t)(threadIdx.x >> 6) * RPW;
-    double2 acc[RPW];
+__global__ __launch_bounds__(256) void k_gemv_rows(double2 *__restrict__ part, const VT *__restrict__ V,
+                                                   const double2 *__restrict__ z, uint64_t N, int nseg) {
+    __shared__ double2 zs[GV_SEG];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t rg = (uint64_t)blockIdx.x / nseg;
+    const int seg = (int)((uint64_t)blockIdx.x % nseg);
+    const uint64_t j0 = (uint64_t)seg * GV_SEG;
+    const int J = (int)(N - j0 < (uint64_t)GV_SEG ? N - j0 : (uint64_t)GV_SEG);
+    for (int t = threadIdx.x; t < J; t += 256) zs[t] = z[j0 + t];
+    __syncthreads();
+    const uint64_t r0 = rg * GV_ROWS + (uint64_t)w * 4;
+    double2 acc[4];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) acc[r] = make_double2(0.0, 0.0);
-    for (uint64_t j0 = 0; j0 < N; j0 += ZC) {
-        const int J = (int)(N - j0 < (uint64_t)ZC ? N - j0 : (uint64_t)ZC);
-        __syncthreads();
-        for (int t = threadIdx.x; t < J; t += 256) zs[t] = z[j0 + t];
-        __syncthreads();
+    for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
+    const int nr = r0 >= N ? 0 : (N - r0 < 4 ? (int)(N - r0) : 4);
+#pragma unroll 4
+    for (int t = lane; t < J; t += 64) {
+        const double2 zt = zs[t];
+        const VT *col = V + r0 * N + j0 + t;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            if (r0 + r >= N) break;
-            const VT *row = V + (r0 + r) * N + j0;
-            double2 a = acc[r];
-            for (int t = lane; t < J; t += 64) a = vmul_acc(row[t], zs[t], a);
-            acc[r] = a;
-        }
+        for (int r = 0; r < 4; ++r)
+            if (r < nr) acc[r] = vmul_acc(col[(uint64_t)r * N], zt, acc[r]);
     }
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
+    for (int r = 0; r < 4; ++r) {
         const double re = wave_sum_f64(acc[r].x), im = wave_sum_f64(acc[r].y);
-        if (lane == 0 && r0 + r < N) out[r0 + r] = make_double2(re, im);
+        if (lane == 0 && r < nr) part[(r0 + r) * nseg + seg] = make_double2(re, im);
+    }
+}
+
+// out[i] = sum over s of part[i][s], in segment order
+__global__ void k_gemv_reduce(double2 *__restrict__ out, const double2 *__restrict__ part, uint64_t N, int nseg) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) {
+            const double2 v = part[i * nseg + sg];
+            re += v.x;
+            im += v.y;
+        }
+        out[i] = make_double2(re, im);
     }
 }
 
@@ -657,9 +675,10 @@ __global__ __launch_bounds__(256) void k_gemv_cols(double2 *__restrict__ out, co
 }
 
 // the dense basis change: out = V in (forward) or V^H in (adjoint), V N x N
-// row-major FP64, real (Vr) or complex (Vc)
+// row-major FP64, real (Vr) or complex (Vc); part holds N * ceil(N / 1024)
+// complex partial sums (forward only)
 static sv_status gemv_apply(hipStream_t st, double2 *out, const double2 *in, const double *Vr, const double2 *Vc,
-                            uint64_t N, int adjoint) {
+                            uint64_t N, int adjoint, double2 *part) {
     const double bytes = (double)N * (double)N * (Vr ? sizeof(double) : sizeof(double2));
     TraceScope _ts(st, adjoint ? "gemv_vh" : "gemv_v", bytes, 8.0 * (double)N * (double)N);
     if (adjoint) {
@@ -667,13 +686,18 @@ static sv_status gemv_apply(hipStream_t st, double2 *out, const double2 *in, con
         if (Vr) hipLaunchKernelGGL(k_gemv_cols<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
         else hipLaunchKernelGGL(k_gemv_cols<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
     } else {
-        const unsigned g = (unsigned)((N + 63) / 64);
-        if (Vr) hipLaunchKernelGGL(k_gemv_rows<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
-        else hipLaunchKernelGGL(k_gemv_rows<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
+        const int nseg = (int)((N + GV_SEG - 1) / GV_SEG);
+        const uint64_t blocks = ((N + GV_ROWS - 1) / GV_ROWS) * (uint64_t)nseg;
+        if (blocks > 0x7fffffffull) return fail(SV_EUNSUPPORTED, "GEMV of %llu rows", (unsigned long long)N);
+        if (Vr) hipLaunchKernelGGL(k_gemv_rows<double>, dim3((unsigned)blocks), dim3(256), 0, st, part, Vr, in, N, nseg);
+        else hipLaunchKernelGGL(k_gemv_rows<double2>, dim3((unsigned)blocks), dim3(256), 0, st, part, Vc, in, N, nseg);
+        hipLaunchKernelGGL(k_gemv_reduce, dim3(grid1(N)), dim3(256), 0, st, out, (const double2 *)part, N, nseg);
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
 }
+
+static size_t gemv_part_bytes(uint64_t N) { return (size_t)N * ((N + GV_SEG - 1) / GV_SEG) * sizeof(double2); }
 
 static int ilog2(uint64_t v) { return 63 - __builtin_clzll(v); }
 
@@ -686,11 +710,15 @@ static int ilog2(uint64_t v) { return 63 - __builtin_clzll(v); }
 //              conjugate transpose) times Y.
 // Dense plans: one GEMV over V (real, a caller's eigenbasis, or complex).
 static sv_status kron_apply_frame(sv_state s, double2 *out, const double2 *in, double2 *tmp, const EigFrame &E,
-                                  int adjoint) {
+                                  int adjoint, DevBuf &gpart) {
     const hipStream_t st = s->stream;
     const uint64_t nh = (uint64_t)E.n_hi, nl = (uint64_t)E.n_lo;
-    if (E.Vr) return gemv_apply(st, out, in, E.Vr, nullptr, nh * nl, adjoint);
-    if (nl <= 1) return gemv_apply(st, out, in, nullptr, (const double2 *)E.V_hi.p, nh, adjoint);
+    if (E.Vr || nl <= 1) {
+        const uint64_t N = nh * nl;
+        if (!adjoint) SV_TRY(gpart.ensure(gemv_part_bytes(N)));
+        return gemv_apply(st, out, in, E.Vr, E.Vr ? nullptr : (const double2 *)E.V_hi.p, N, adjoint,
+                          (double2 *)gpart.p);
+    }
     SV_TRY(cgemm<double>(st, in, tmp, (const double2 *)E.V_lo.p, nh, (int)nl, (int)nl, (nh - 1) << ilog2(nl), 0,
                          adjoint, adjoint));
     const double2 *W = (const double2 *)(adjoint ? E.VH_hi.p : E.V_hi.p);
@@ -709,7 +737,7 @@ static int pick_log_len(uint64_t N, int n_c) {
 
 // device workspaces of a plan, grown on demand and reused by every solve
 struct Workspace {
-    DevBuf F, cs, beta, tmp, tmp2, z, x, part, zpart, sum, E, W, U64, Uk;
+    DevBuf F, cs, beta, tmp, tmp2, z, x, part, zpart, sum, E, W, U64, Uk, gpart;
 };
 
 static sv_status need(DevBuf &b, size_t bytes) { return b.ensure(bytes); }
@@ -789,7 +817,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
         SV_TRY(upload(s, w.x.p, bhat.data(), N * sizeof(double2)));
     }
     // beta = V^H b^
-    SV_TRY(kron_apply_frame(s, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, E, 1));
+    SV_TRY(kron_apply_frame(s, (double2 *)w.beta.p, (const double2 *)w.x.p, (double2 *)w.tmp.p, E, 1, w.gpart));
 
     if (fused && pipe_supported(n_s, n_c)) {
         // fused three-kernel pipeline: (state + inverse QFT on the low clock bits),
@@ -855,7 +883,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
 static sv_status eig_finish(sv_state s, const EigFrame &E, Workspace &w, uint64_t N, sv_hhl_result *res,
                             double *x_out, bool dev, double2 *x_dev) {
     const hipStream_t st = s->stream;
-    SV_TRY(kron_apply_frame(s, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, E, 0));
+    SV_TRY(kron_apply_frame(s, (double2 *)w.x.p, (const double2 *)w.z.p, (double2 *)w.tmp.p, E, 0, w.gpart));
     if (dev) {
         // p = |x|^2 (w.sum[3]) and the normalised x on the device; only the scalars come back
         SV_TRY(need(w.tmp2, 512 * sizeof(double)));
@@ -1074,13 +1102,16 @@ sv_status sv_hhl_prepare_eig(sv_hhl_plan *out, sv_state s, const double *V_dev, 
             z ^= z >> 31;
             r[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
         }
-        DevBuf dr, dt, du;
+        DevBuf dr, dt, du, dp;
         st = dr.alloc(N * sizeof(double2));
         if (st == SV_OK) st = dt.alloc(N * sizeof(double2));
         if (st == SV_OK) st = du.alloc(N * sizeof(double2));
+        if (st == SV_OK) st = dp.alloc(gemv_part_bytes(N));
         if (st == SV_OK) st = upload(s, dr.p, r.data(), N * sizeof(double2));
-        if (st == SV_OK) st = gemv_apply(s->stream, (double2 *)dt.p, (const double2 *)dr.p, V_dev, nullptr, N, 1);
-        if (st == SV_OK) st = gemv_apply(s->stream, (double2 *)du.p, (const double2 *)dt.p, V_dev, nullptr, N, 0);
+        if (st == SV_OK)
+            st = gemv_apply(s->stream, (double2 *)dt.p, (const double2 *)dr.p, V_dev, nullptr, N, 1, nullptr);
+        if (st == SV_OK)
+            st = gemv_apply(s->stream, (double2 *)du.p, (const double2 *)dt.p, V_dev, nullptr, N, 0, (double2 *)dp.p);
         if (st == SV_OK) st = download(s, u.data(), du.p, N * sizeof(double2));
         if (st == SV_OK) {
             double e2 = 0.0, r2 = 0.0;
