@@ -291,6 +291,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--no-t0", action="store_true")
+    ap.add_argument("--t0-train", type=int, default=2000)
+    ap.add_argument("--t0-eval", type=int, default=128)
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -708,6 +711,22 @@ def main():
     # ---------------- the flow workloads: Poiseuille and Couette ----------------
     if not args.no_flow:
         out["flow"] = flow_records(dev, couette_ref)
+
+    # ---------------- learned T0 against the plain 16-point sweep ----------------
+    if not args.no_t0:
+        from paper_2307_00391_amd import t0model
+        log(f"[bench] learned T0: train on {args.t0_train} sweep-family instances, evaluate {args.t0_eval} held out")
+        r, _ = t0model.experiment(n_train=args.t0_train, n_eval=args.t0_eval, steps=2000, log=log)
+        keep = ("n_train", "n_eval", "train_n_s", "eval_n_s", "n_c", "train_records", "train_generate_s", "fit_s",
+                "F_sweep_best_mean", "F_learned_mean", "F_prediction_only_mean", "F_textbook_mean",
+                "F_untrained_mean", "gap_mean", "gap_median", "gap_p90", "gap_max", "frac_gap_le_1e-4",
+                "prediction_only_frac_gap_le_1e-4", "one_minus_F_best_median", "one_minus_F_learned_median",
+                "sweep_s", "sweep_timings", "sweep_solves", "learned_s", "learned_timings", "learned_solves",
+                "candidates_per_instance", "speedup_end_to_end", "speedup_solve_only",
+                "solves_per_s_at_1mF_le_1e-4_sweep", "solves_per_s_at_1mF_le_1e-4_learned")
+        out["learned_t0"] = {k: r[k] for k in keep if k in r}
+        out["learned_t0"]["criterion"] = ("per instance (1-F_learned) <= (1-F_sweep) + 1e-4, F_sweep the best of "
+                                          "the complex128 16-point sweep, F_learned the complex64 learned path")
     print(json.dumps(out), flush=True)
 
 

@@ -656,6 +656,15 @@ sv_status sv_mlp_adam(float *params, float *m, float *v, const float *grad, int 
  * SV_EINVAL, SV_ENOTHERMITIAN, SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, double *lambda_min,
                               double *lambda_max, void *hip_stream);
+/* sv_spectrum_lanczos for a banded Hermitian matrix given by its 2 bw + 1
+ * diagonals (host, complex FP64, band[d][r] = A[r][r + d - bw], entries
+ * outside the matrix ignored; bw = 1 for the tridiagonal systems of the flow
+ * problems): each Lanczos step's matrix-vector product costs O(N bw) instead
+ * of O(N^2), and only the band crosses PCIe.  The same start vector, steps
+ * and bisection.  Errors: SV_EINVAL (sizes, bw >= N, non-finite entries),
+ * SV_ENOTHERMITIAN, SV_ENOMEM, SV_EDEVICE. */
+sv_status sv_spectrum_lanczos_band(const double *band, int N, int bw, int iters, uint64_t seed, double *lambda_min,
+                                   double *lambda_max, void *hip_stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char *sv_last_error(void);

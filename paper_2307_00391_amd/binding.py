@@ -134,6 +134,7 @@ _SIGS = {
     "sv_mlp_adam": ([_P, _P, _P, _P, _I, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
                     _I),
     "sv_spectrum_lanczos": ([_P, _I, _I, _U64, _DP, _DP, _P], _I),
+    "sv_spectrum_lanczos_band": ([_P, _I, _I, _I, _U64, _DP, _DP, _P], _I),
     "sv_trace_enable": ([_I], _I),
     "sv_tune_report": ([ctypes.c_char_p, _I], _I),
     "sv_tune_set": ([ctypes.c_char_p, _P, _I], _I),
@@ -680,6 +681,32 @@ def sv_spectrum_lanczos(A, iters=96, seed=0, stream=None):
     lo, hi = ctypes.c_double(), ctypes.c_double()
     _check(lib().sv_spectrum_lanczos(_ptr(Af), A.shape[0], int(iters), int(seed), ctypes.byref(lo),
                                      ctypes.byref(hi), _stream_ptr(stream)), "sv_spectrum_lanczos")
+    return lo.value, hi.value
+
+
+def band_of(A, bw):
+    """The 2 bw + 1 diagonals of A as the band layout of sv_spectrum_lanczos_band:
+    band[d][r] = A[r][r + d - bw] (zero outside the matrix)."""
+    A = np.asarray(A)
+    N = A.shape[0]
+    band = np.zeros((2 * bw + 1, N), dtype=np.complex128)
+    for d in range(2 * bw + 1):
+        off = d - bw
+        diag = np.diagonal(A, off)
+        if off >= 0:
+            band[d, :N - off] = diag
+        else:
+            band[d, -off:] = diag
+    return band
+
+
+def sv_spectrum_lanczos_band(band, iters=96, seed=0, stream=None):
+    band, bf = _f64(band)
+    nd, N = band.shape
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sv_spectrum_lanczos_band(_ptr(bf), int(N), int((nd - 1) // 2), int(iters), int(seed),
+                                          ctypes.byref(lo), ctypes.byref(hi), _stream_ptr(stream)),
+           "sv_spectrum_lanczos_band")
     return lo.value, hi.value
 
 

@@ -38,6 +38,24 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const double2 *__restrict__ A
     if (lane == 0) w[row] = make_double2(sr, si);
 }
 
+// banded form: w[r] = sum_d B[d][r] q[r + d - bw] for a Hermitian matrix of
+// half-bandwidth bw stored by diagonals (B[d][r] = A[r][r + d - bw], zero
+// outside the matrix); one thread per row
+__global__ __launch_bounds__(256) void k_lz_matvec_band(const double2 *__restrict__ Bd, const double2 *__restrict__ q,
+                                                        double2 *__restrict__ w, int N, int bw) {
+    const int row = blockIdx.x * 256 + threadIdx.x;
+    if (row >= N) return;
+    double sr = 0.0, si = 0.0;
+    for (int d = 0; d <= 2 * bw; ++d) {
+        const int c = row + d - bw;
+        if (c < 0 || c >= N) continue;
+        const double2 x = Bd[(size_t)d * N + row], y = q[c];
+        sr += x.x * y.x - x.y * y.y;
+        si += x.x * y.y + x.y * y.x;
+    }
+    w[row] = make_double2(sr, si);
+}
+
 __device__ __forceinline__ double block_sum_256(double v, double *ws) {
     v = wave_sum_f64(v);
     __syncthreads();
@@ -124,20 +142,12 @@ static double sturm_extreme(const std::vector<double> &a, const std::vector<doub
     return 0.5 * (lo + hi);
 }
 
-}  // namespace sv
-
-using namespace sv;
-
-extern "C" {
-
-sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, double *lambda_min,
-                              double *lambda_max, void *hip_stream) {
-    clear_error();
-    if (!A || !lambda_min || !lambda_max || iters < 1) return fail(SV_EINVAL, "bad Lanczos arguments");
-    if (N < 1 || N > LZ_MAX_N) return fail(SV_EINVAL, "N = %d outside 1..%d", N, LZ_MAX_N);
-    SV_TRY(check_hermitian(A, N, "A"));
+// the Lanczos iteration and the Sturm bisection of its tridiagonal matrix;
+// matvec(q, w) enqueues w = A q on st
+template <typename MV>
+static sv_status lanczos_run(hipStream_t st, int N, int iters, uint64_t seed, double *lambda_min, double *lambda_max,
+                             MV matvec) {
     const int k = iters < N ? iters : N;
-    const hipStream_t st = (hipStream_t)hip_stream;
     // seeded start vector: xorshift64* stream, uniform in [-1/2, 1/2), normalised
     std::vector<double> q0(2 * (size_t)N, 0.0);
     uint64_t x = seed ^ 0x9e3779b97f4a7c15ull;
@@ -153,21 +163,19 @@ sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, 
     nrm = sqrt(nrm);
     if (!(nrm > 0.0)) q0[0] = nrm = 1.0;
     for (int i = 0; i < N; ++i) q0[2 * i] /= nrm;
-    DevBuf dA, dQ, dw, dh, dab;
-    SV_TRY(dA.alloc((size_t)N * N * sizeof(double2)));
+    DevBuf dQ, dw, dh, dab;
     SV_TRY(dQ.alloc((size_t)(k + 1) * N * sizeof(double2)));
     SV_TRY(dw.alloc((size_t)N * sizeof(double2)));
     SV_TRY(dh.alloc((size_t)(k + 1) * sizeof(double2)));
     SV_TRY(dab.alloc(2 * (size_t)k * sizeof(double)));
     double2 *Q = (double2 *)dQ.p, *w = (double2 *)dw.p, *h = (double2 *)dh.p;
     double *alpha = (double *)dab.p, *beta = alpha + k;
-    SV_HIP(hipMemcpyAsync(dA.p, A, (size_t)N * N * sizeof(double2), hipMemcpyHostToDevice, st));
     SV_HIP(hipMemcpyAsync(Q, q0.data(), (size_t)N * sizeof(double2), hipMemcpyHostToDevice, st));
     SV_HIP(hipMemsetAsync(dab.p, 0, 2 * (size_t)k * sizeof(double), st));
-    const int rows_grid = (N + 3) / 4, vec_grid = (N + 255) / 256;
+    const int vec_grid = (N + 255) / 256;
     for (int j = 0; j < k; ++j) {
         const double2 *qj = Q + (size_t)j * N;
-        hipLaunchKernelGGL(k_lz_matvec, dim3(rows_grid), dim3(256), 0, st, (const double2 *)dA.p, qj, w, N);
+        matvec(qj, w);
         for (int pass = 0; pass < 2; ++pass) {
             hipLaunchKernelGGL(k_lz_dots, dim3(j + 1), dim3(256), 0, st, (const double2 *)Q, (const double2 *)w, h,
                                N);
@@ -197,6 +205,57 @@ sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, 
     *lambda_min = sturm_extreme(a, b, true);
     *lambda_max = sturm_extreme(a, b, false);
     return SV_OK;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+sv_status sv_spectrum_lanczos(const double *A, int N, int iters, uint64_t seed, double *lambda_min,
+                              double *lambda_max, void *hip_stream) {
+    clear_error();
+    if (!A || !lambda_min || !lambda_max || iters < 1) return fail(SV_EINVAL, "bad Lanczos arguments");
+    if (N < 1 || N > LZ_MAX_N) return fail(SV_EINVAL, "N = %d outside 1..%d", N, LZ_MAX_N);
+    SV_TRY(check_hermitian(A, N, "A"));
+    const hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf dA;
+    SV_TRY(dA.alloc((size_t)N * N * sizeof(double2)));
+    SV_HIP(hipMemcpyAsync(dA.p, A, (size_t)N * N * sizeof(double2), hipMemcpyHostToDevice, st));
+    const int rows_grid = (N + 3) / 4;
+    return lanczos_run(st, N, iters, seed, lambda_min, lambda_max, [&](const double2 *q, double2 *w) {
+        hipLaunchKernelGGL(k_lz_matvec, dim3(rows_grid), dim3(256), 0, st, (const double2 *)dA.p, q, w, N);
+    });
+}
+
+sv_status sv_spectrum_lanczos_band(const double *band, int N, int bw, int iters, uint64_t seed, double *lambda_min,
+                                   double *lambda_max, void *hip_stream) {
+    clear_error();
+    if (!band || !lambda_min || !lambda_max || iters < 1 || bw < 0) return fail(SV_EINVAL, "bad Lanczos arguments");
+    if (N < 1 || N > LZ_MAX_N || bw >= N) return fail(SV_EINVAL, "N = %d (1..%d), bw = %d", N, LZ_MAX_N, bw);
+    // Hermitian: B[bw + e][r] = conj(B[bw - e][r + e]) for every stored pair
+    double amax = 0.0, dmax = 0.0;
+    for (int d = 0; d <= 2 * bw; ++d)
+        for (int r = 0; r < N; ++r) {
+            const double *x = band + 2 * ((size_t)d * N + r);
+            if (!isfinite(x[0]) || !isfinite(x[1])) return fail(SV_EINVAL, "band has a non-finite entry");
+            const int c = r + d - bw;
+            if (c < 0 || c >= N) continue;
+            const double *y = band + 2 * ((size_t)(2 * bw - d) * N + c);
+            amax = fmax(amax, hypot(x[0], x[1]));
+            dmax = fmax(dmax, hypot(x[0] - y[0], x[1] + y[1]));
+        }
+    if (dmax > 1e-12 * amax) return fail(SV_ENOTHERMITIAN, "band is not Hermitian (|B - B^H| = %g)", dmax);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf dB;
+    const size_t bytes = (size_t)(2 * bw + 1) * N * sizeof(double2);
+    SV_TRY(dB.alloc(bytes));
+    SV_HIP(hipMemcpyAsync(dB.p, band, bytes, hipMemcpyHostToDevice, st));
+    const int grid = (N + 255) / 256;
+    return lanczos_run(st, N, iters, seed, lambda_min, lambda_max, [&](const double2 *q, double2 *w) {
+        hipLaunchKernelGGL(k_lz_matvec_band, dim3(grid), dim3(256), 0, st, (const double2 *)dB.p, q, w, N, bw);
+    });
 }
 
 }  // extern "C"

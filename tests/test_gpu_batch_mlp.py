@@ -249,6 +249,34 @@ def test_lanczos_extremes(N, iters, kind):
     assert abs(lo - ev[0]) <= 1e-6 * abs(ev[0])
 
 
+@pytest.mark.parametrize("N,bw", [(8, 1), (256, 1), (1024, 1), (512, 3)])
+def test_lanczos_band_matches_dense(N, bw):
+    """The banded form on the same matrix: the same start vector and steps,
+    so the extremes agree with the dense form and with numpy."""
+    rng = np.random.default_rng(60 + N + bw)
+    if bw == 1:
+        A, _, _ = inputs.random_spd_tridiag(rng, N, 500.0)
+    else:
+        A = np.zeros((N, N), dtype=np.complex128)
+        for k in range(bw + 1):
+            v = rng.standard_normal(N - k)
+            A += np.diag(v, k) + (np.diag(v, -k) if k else 0)
+        A += 1j * np.triu(rng.standard_normal((N, N)), 1) * (np.abs(np.subtract.outer(np.arange(N), np.arange(N))) <= bw)
+        A = 0.5 * (A + A.conj().T)
+    ev = np.linalg.eigvalsh(A)
+    lo_b, hi_b = B.sv_spectrum_lanczos_band(B.band_of(A, bw), 96, seed=5)
+    lo_d, hi_d = B.sv_spectrum_lanczos(A, 96, seed=5)
+    assert abs(hi_b - hi_d) <= 1e-10 * abs(hi_d) and abs(lo_b - lo_d) <= 1e-8 * max(abs(lo_d), 1e-12 * abs(hi_d))
+    assert abs(hi_b - ev[-1]) <= 1e-10 * abs(ev[-1])
+    if bw == 1:
+        assert abs(lo_b - ev[0]) <= 1e-6 * abs(ev[0])
+    bad = B.band_of(A, bw)
+    bad[0, 3] += 1.0                                   # breaks the Hermitian pairing
+    with pytest.raises(B.SvError) as e:
+        B.sv_spectrum_lanczos_band(bad, 16)
+    assert e.value.status == B.SV_ENOTHERMITIAN
+
+
 def test_lanczos_error_paths():
     with pytest.raises(B.SvError) as e:
         B.sv_spectrum_lanczos(np.array([[1.0, 2.0], [0.0, 1.0]]))
