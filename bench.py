@@ -537,20 +537,45 @@ def main():
         log(f"[bench] sweep: {ni} instances x 16 T0 (n_s 4..10, n_c 8..12), complex64")
         insts = inputs.sweep_instances(ni)
         probs = [(i.A, i.b, i.n_c, i.t0) for i in insts]
-        t = time.perf_counter()
-        h = B.sv_batch_prepare(probs, "c64")
-        prep = time.perf_counter() - t
-        for _ in range(3):                         # warm-up replays
-            B.sv_batch_run(h, use_graph=True)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(args.sweep_replays):
-            t = time.perf_counter()
-            B.sv_batch_run(h, use_graph=True, want_results=False)   # synchronises the batch stream
-            times.append(time.perf_counter() - t)
-        el = float(np.median(times))
-        res = B.sv_batch_run(h, use_graph=True)
-        B.sv_batch_free(h)
+        # algorithmic HBM bytes of one sweep: per solve, the ancilla = 1 half
+        # (2^(n_s + n_c) amplitudes) written by k_pipe_b and read by k_pipe_c,
+        # the G1 table (2^(n_s + g1)) written by k_pipe_a and read by k_pipe_b
+        alg = sum(16 * 8 * (2 * (1 << (i.n_s + i.n_c)) + 2 * (1 << (i.n_s + (i.n_c + 1) // 2))) for i in insts)
+
+        def sweep_replays(form):
+            """prepare with SV_BATCH_QUEUE = form ("": timed choice), replay"""
+            old = os.environ.pop("SV_BATCH_QUEUE", None)
+            if form:
+                os.environ["SV_BATCH_QUEUE"] = form
+            try:
+                t = time.perf_counter()
+                h = B.sv_batch_prepare(probs, "c64")
+                prep = time.perf_counter() - t
+            finally:
+                os.environ.pop("SV_BATCH_QUEUE", None)
+                if old is not None:
+                    os.environ["SV_BATCH_QUEUE"] = old
+            for _ in range(3):                         # warm-up replays
+                B.sv_batch_run(h, use_graph=True)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(args.sweep_replays):
+                t = time.perf_counter()
+                B.sv_batch_run(h, use_graph=True, want_results=False)   # synchronises the batch stream
+                times.append(time.perf_counter() - t)
+            res = B.sv_batch_run(h, use_graph=True)
+            form_info = B.sv_batch_form(h)
+            B.sv_batch_free(h)
+            return float(np.median(times)), prep, res, form_info
+
+        el, prep, res, (chosen, ms_s, ms_q) = sweep_replays("")
+        forms = {}
+        for name, f in (("work_queue", "1"), ("side_streams", "0")):
+            e2, _, r2, _ = sweep_replays(f)
+            forms[name] = {"graph_replay_s": e2, "solves_per_s": res.shape[0] / e2,
+                           "roofline": {"bound": "hbm", "achieved": alg / e2 / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                        "frac": alg / e2 / 8e12},
+                           "max_abs_diff_vs_chosen": float(np.abs(r2 - res).max())}
         nsol = res.shape[0]
         Fm = res[:, 3].reshape(ni, 16)
         upd = sum(metrics.hhl_updates(i.n_s, i.n_c, 1)["total"] * 16 for i in insts)
@@ -558,12 +583,20 @@ def main():
         good = int(np.sum(res[:, 3] >= 1.0 - 1e-4))
         out["sweep"] = {"instances": ni, "solves": nsol, "graph_replay_s": el, "replay_timing": "median of "
                         f"{args.sweep_replays} replays after 3 warm-ups", "solves_per_s": nsol / el,
+                        "launch_form": "work_queue" if chosen == 1 else "side_streams",
+                        "launch_form_choice": {"eager_ms_side_streams": ms_s, "eager_ms_work_queue": ms_q,
+                                               "rule": "the faster of three timed eager runs each, at prepare"},
+                        "forms": forms,
+                        "algorithmic_bytes": alg,
+                        "roofline": {"bound": "hbm", "achieved": alg / el / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                     "frac": alg / el / 8e12},
                         "solves_at_1mF_le_1e-4": good, "solves_per_s_at_1mF_le_1e-4": good / el,
                         "updates_per_s": upd / el, "amplitudes": amps, "prepare_s": prep,
                         "best_F_mean": float(Fm.max(1).mean()),
                         "best_factor_hist": np.bincount(Fm.argmax(1), minlength=16).tolist()}
-        log(f"[bench] sweep {nsol} solves in {el * 1e3:.2f} ms per replay ({nsol / el:.0f} solves/s), "
-            f"prepare {prep:.2f} s")
+        log(f"[bench] sweep {nsol} solves in {el * 1e3:.2f} ms per replay ({nsol / el:.0f} solves/s, "
+            f"{out['sweep']['launch_form']}; work queue {forms['work_queue']['graph_replay_s'] * 1e3:.2f} ms, "
+            f"side streams {forms['side_streams']['graph_replay_s'] * 1e3:.2f} ms), prepare {prep:.2f} s")
 
     # ---------------- QSP-1 state preparation on a 24-qubit register ----------------
     if not args.no_qsp:

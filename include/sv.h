@@ -577,8 +577,12 @@ sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const s
 /* ------------------------------------------------------------------------
  * Batched T0 sweep (the T Q phase-diagram scans of Fig. 3c and the T0*-kappa
  * study of Fig. 4b): many HHL instances of uneven size, each over its own
- * list of T0 values, solved in the fused eigen-frame mode with one launch per
- * kernel and shape class, recorded once as a hipGraph and replayed.
+ * list of T0 values, solved in the fused eigen-frame mode and recorded once
+ * as a hipGraph that is replayed.  Two launch forms (the Quantum Flow
+ * Simulator section's many parallel runs): one persistent kernel that takes
+ * every solve's tiles from per-XCC device work queues, with a dependency
+ * counter per solve and phase; or one launch per kernel and shape class on
+ * side streams.
  * --------------------------------------------------------------------- */
 typedef struct {
     int n_s, n_c;          /* 1 <= n_s <= 13, 2 <= n_c <= 16, n_s + n_c + 1 <= 32 */
@@ -595,11 +599,18 @@ typedef struct sv_batch_s *sv_batch;
  * device buffers for every (instance, T0) state, launch configurations per
  * shape class (autotuned on first use), and the captured graph.  All inputs
  * are copied; the caller's arrays may be freed on return.  hip_stream NULL:
- * the batch creates and owns a stream.  The shape classes run on four side
- * streams of default priority that the batch owns, forked from and joined
- * back into its stream (parallel branches of the graph), so the batch's work
- * stays ordered on that stream.  Errors: SV_EINVAL, SV_EUNSUPPORTED,
- * SV_ENOTHERMITIAN, SV_ENOTPOSDEF, SV_EZERONORM, SV_ENOMEM, SV_EDEVICE. */
+ * the batch creates and owns a stream.  The launch form is the faster of
+ * the two in three timed eager runs each, unless the environment variable
+ * SV_BATCH_QUEUE is 1 (the work queues) or 0 (the side streams).  The queue
+ * kernel serves one queue per XCC with that XCC's blocks, so the producers
+ * and consumers of a solve share one L2; a dependency wait is bounded (a
+ * quarter second), and an expired wait or an undrained queue makes
+ * sv_batch_run fail with SV_EDEVICE instead of hanging.  In the stream form
+ * the shape classes run on four side streams of default priority that the
+ * batch owns, forked from and joined back into its stream (parallel branches
+ * of the graph).  Either way the batch's work stays ordered on its stream.
+ * Errors: SV_EINVAL, SV_EUNSUPPORTED, SV_ENOTHERMITIAN, SV_ENOTPOSDEF,
+ * SV_EZERONORM, SV_ENOMEM, SV_EDEVICE. */
 sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const sv_batch_instance *inst,
                            int n_inst);
 
@@ -610,6 +621,10 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
  * all accumulated in FP64.  Synchronises the batch's stream. */
 sv_status sv_batch_run(sv_batch b, int use_graph, double *results);
 int sv_batch_num_solves(sv_batch b);
+/* The batch's launch form: 1 the work-queue kernel, 0 the side streams, -1
+ * for a NULL batch.  ms_streams / ms_queue (may be NULL): the eager run
+ * times of the two forms measured at prepare (0 when not timed). */
+int sv_batch_form(sv_batch b, float *ms_streams, float *ms_queue);
 sv_status sv_batch_free(sv_batch b);
 
 /* prepare + one graph replay + free */

@@ -127,6 +127,7 @@ _SIGS = {
     "sv_batch_prepare": ([ctypes.POINTER(_P), _I, _P, ctypes.POINTER(sv_batch_instance), _I], _I),
     "sv_batch_run": ([_P, _I, _P], _I),
     "sv_batch_num_solves": ([_P], _I),
+    "sv_batch_form": ([_P, _P, _P], _I),
     "sv_batch_free": ([_P], _I),
     "sv_hhl_batch": ([_I, _P, ctypes.POINTER(sv_batch_instance), _I, _P], _I),
     "sv_mlp_forward": ([_P, _P, _I, _P, _P], _I),
@@ -603,6 +604,15 @@ def sv_batch_prepare(instances, dtype="c64", stream=None):
 
 def sv_batch_num_solves(b):
     return int(lib().sv_batch_num_solves(b))
+
+
+def sv_batch_form(b):
+    """(form, ms_streams, ms_queue): 1 = the work-queue kernel, 0 = side
+    streams; the eager times measured at prepare (0 when not timed)."""
+    ms = (ctypes.c_float * 2)()
+    a = ctypes.addressof(ms)
+    f = int(lib().sv_batch_form(b, a, a + ctypes.sizeof(ctypes.c_float)))
+    return f, float(ms[0]), float(ms[1])
 
 
 def sv_batch_run(b, use_graph=True, want_results=True):

@@ -1,20 +1,26 @@
 // Batched T0 sweep: many HHL instances of uneven size (each with its own
-// grid of T0 values) solved by the fused eigen-frame kernels with one launch
-// per kernel and shape class, recorded once as a hipGraph and replayed.
+// grid of T0 values) solved by the fused eigen-frame kernels, recorded once
+// as a hipGraph and replayed.
 //
 // Per instance (classical preprocessing, once): FP64 eigen-decomposition,
 // beta = V^H b^, and the eigen-basis coefficients of the exact solution
 // A^{-1} b (beta_j / lambda_j, normalised) for the fidelity.
 // Per solve (instance, T0), inside the graph:
-//   turn tables (all solves, one kernel)
-//   -> per (n_s, n_c) class: the three pipeline kernels, blockIdx.z = solve;
-//      the classes spread over four streams (parallel branches of the graph),
-//      so that the many small classes overlap instead of each paying its
-//      launch latency in series
-//   -> one finishing kernel (all solves): FP64 sums of P(a=1) and the norm,
-//      the post-selected eigen-coefficients z_j (column sums of the clock
-//      projection), p_post = |z|^2 and F = |<x_C|x_Q>| = |sum conj(c_j) z_j| / |z|,
-//      all in FP64, fixed summation order.
+//   turn tables (all solves, one kernel; it also clears the queue counters)
+//   -> the three pipeline kernels' tiles and the finish, in one of two forms:
+//      * work queues: one persistent kernel; the solves are spread over one
+//        queue per XCC, each item a run of tiles of one phase of one solve,
+//        ordered by a done counter per solve and phase
+//      * side streams: per (n_s, n_c) class the three pipeline kernels with
+//        blockIdx.z = solve, the classes over four streams (parallel branches
+//        of the graph) so that small classes overlap instead of each paying
+//        its launch latency in series, then one finishing kernel
+//      prepare times both and keeps the faster (or the one SV_BATCH_QUEUE
+//      names)
+//   the finish: FP64 sums of P(a=1) and the norm, the post-selected
+//   eigen-coefficients z_j (column sums of the clock projection),
+//   p_post = |z|^2 and F = |<x_C|x_Q>| = |sum conj(c_j) z_j| / |z|, all in
+//   FP64, fixed summation order.
 #include <math.h>
 #include <string.h>
 
@@ -36,8 +42,12 @@ struct TurnJob {
     uint64_t N;
 };
 
-// all turn tables of the batch: blockIdx.y = solve
-__global__ void k_turn_batch(const TurnJob *__restrict__ jobs) {
+// all turn tables of the batch (blockIdx.y = solve); also clears the work
+// queue's counters for the launch that follows
+__global__ void k_turn_batch(const TurnJob *__restrict__ jobs, unsigned *__restrict__ cnt, uint64_t ncnt) {
+    for (uint64_t i = ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x; i < ncnt;
+         i += (uint64_t)gridDim.x * gridDim.y * blockDim.x)
+        cnt[i] = 0u;
     const TurnJob J = jobs[blockIdx.y];
     const uint64_t total = J.N * (uint64_t)J.n_c;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -51,59 +61,9 @@ __global__ void k_turn_batch(const TurnJob *__restrict__ jobs) {
     }
 }
 
-struct FinishJob {
-    const double *part;     // k_pipe_b partials, 2 per block
-    uint64_t nparts;
-    const double2 *zpart;   // [rows][N]
-    int rows;
-    uint64_t N;
-    double scale;           // 2^(-(n_c + g1)/2)
-    const double2 *cexact;  // normalised eigen-coefficients of A^{-1} b
-    double *out;            // p_post, p_anc, norm_total, fidelity
-};
-
-__device__ __forceinline__ double block_sum(double v, double *ws) {
-    v = wave_sum_f64(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
-    __syncthreads();
-    return (ws[0] + ws[1]) + (ws[2] + ws[3]);
-}
-
-// one block (256 threads) per solve
+// the finish of every solve, one block each (the stream path)
 __global__ __launch_bounds__(256) void k_batch_finish(const FinishJob *__restrict__ jobs) {
-    __shared__ double ws[4];
-    const FinishJob J = jobs[blockIdx.x];
-    double pa = 0.0, nt = 0.0, pp = 0.0, orr = 0.0, oi = 0.0;
-    for (uint64_t i = threadIdx.x; i < J.nparts; i += blockDim.x) {
-        pa += J.part[2 * i];
-        nt += J.part[2 * i + 1];
-    }
-    for (uint64_t j = threadIdx.x; j < J.N; j += blockDim.x) {
-        double zr = 0.0, zi = 0.0;
-        for (int r = 0; r < J.rows; ++r) {
-            const double2 v = J.zpart[(uint64_t)r * J.N + j];
-            zr += v.x;
-            zi += v.y;
-        }
-        zr *= J.scale;
-        zi *= J.scale;
-        pp += zr * zr + zi * zi;
-        const double2 c = J.cexact[j];
-        orr += c.x * zr + c.y * zi;      // conj(c) z
-        oi += c.x * zi - c.y * zr;
-    }
-    pa = block_sum(pa, ws);
-    nt = block_sum(nt, ws);
-    pp = block_sum(pp, ws);
-    orr = block_sum(orr, ws);
-    oi = block_sum(oi, ws);
-    if (threadIdx.x == 0) {
-        J.out[0] = pp;
-        J.out[1] = pa;
-        J.out[2] = nt;
-        J.out[3] = pp > 0.0 ? sqrt(orr * orr + oi * oi) / sqrt(pp) : 0.0;
-    }
+    batch_finish_body(jobs[blockIdx.x]);
 }
 
 }  // namespace sv
@@ -119,7 +79,8 @@ struct sv_batch_s {
     DevBuf *arena = nullptr;              // states, tables, partials
     DevBuf *desc = nullptr;               // descriptor arrays
     const TurnJob *d_turn = nullptr;
-    const FinishJob *d_finish = nullptr;
+    const FinishJob *d_finish = nullptr;     // the finish jobs of the stream form
+    const FinishJob *d_finish_q = nullptr;   // the same for the work-queue form (its own partial counts)
     double *d_out = nullptr;
     struct Class {
         int n_s, n_c, cl[3], nt[3];
@@ -128,6 +89,17 @@ struct sv_batch_s {
         uint64_t nparts;      // k_pipe_b partial pairs per solve, as laid out for the finish
     };
     std::vector<Class> classes;
+    // the launch form: every solve in one persistent kernel over per-XCC
+    // work queues, or the classes' kernels on side streams; chosen by timing
+    // both at prepare unless SV_BATCH_QUEUE is 1 or 0
+    bool use_queue = true;
+    bool have_queue = false;
+    float form_ms[2] = {0.f, 0.f};           // timed eager runs: streams, queue (0: not timed)
+    PipeQueue queue;
+    DevBuf qdesc;
+    unsigned *d_cnt = nullptr;            // queue counters (cleared by the turn-table kernel)
+    uint64_t n_cnt = 0;
+    unsigned *d_flag = nullptr;           // set if a queue wait expired
     // the classes are independent: they run on kSide streams forked after the
     // turn tables and joined before the finish (in the graph: parallel branches)
     static constexpr int kSide = 4;
@@ -158,8 +130,9 @@ namespace sv {
 template <typename R>
 static sv_status enqueue_batch(sv_batch b) {
     const hipStream_t st = b->stream;
-    hipLaunchKernelGGL(k_turn_batch, dim3(64, b->n_solves), dim3(256), 0, st, b->d_turn);
+    hipLaunchKernelGGL(k_turn_batch, dim3(64, b->n_solves), dim3(256), 0, st, b->d_turn, b->d_cnt, b->n_cnt);
     SV_HIP(hipGetLastError());
+    if (b->use_queue) return pipe_queue_launch<R>(st, b->queue, b->d_finish_q);
     SV_HIP(hipEventRecord(b->fork, st));
     for (int i = 0; i < sv_batch_s::kSide; ++i) {
         if (b->lane[i].empty()) continue;
@@ -325,12 +298,27 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         }
     }
     const size_t out_off = take((size_t)total * 4 * sizeof(double));
+    const uint64_t n_cnt = pipe_queue_counters(total);
+    const size_t cnt_off = take(n_cnt * sizeof(unsigned));
+    const size_t flag_off = take(sizeof(unsigned));
     b->arena = new DevBuf();
     b->bufs.push_back(b->arena);
     sv_status st = b->arena->alloc(off);
     if (st != SV_OK) return fail_del(st);
     char *base = (char *)b->arena->p;
     b->d_out = (double *)(base + out_off);
+    b->d_cnt = (unsigned *)(base + cnt_off);
+    b->n_cnt = n_cnt;
+    b->d_flag = (unsigned *)(base + flag_off);
+    {
+        const hipError_t me = hipMemsetAsync(b->d_flag, 0, sizeof(unsigned), b->stream);
+        if (me != hipSuccess) return fail_del(hip_fail(me, "hipMemsetAsync"));
+    }
+    int form = -1;     // -1: time both
+    {
+        const char *qe = getenv("SV_BATCH_QUEUE");
+        if (qe && *qe) form = atoi(qe) != 0 ? 1 : 0;
+    }
     // --- classes by (n_s, n_c)
     std::map<std::pair<int, int>, std::vector<int>> cls;
     for (int k = 0; k < total; ++k) cls[{inst[lay[k].inst].n_s, inst[lay[k].inst].n_c}].push_back(k);
@@ -353,19 +341,23 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
     // descriptor arena: turn jobs, finish jobs, per-class solve arrays
     b->desc = new DevBuf();
     b->bufs.push_back(b->desc);
-    const size_t dbytes = total * (sizeof(TurnJob) + sizeof(FinishJob) + sizeof(PipeSolve)) + 4096;
+    const size_t dbytes = total * (sizeof(TurnJob) + 2 * sizeof(FinishJob) + sizeof(PipeSolve)) + 4096;
     if ((st = b->desc->alloc(dbytes)) != SV_OK) return fail_del(st);
     char *dbase = (char *)b->desc->p;
     b->d_turn = (const TurnJob *)dbase;
     b->d_finish = (const FinishJob *)(dbase + ((total * sizeof(TurnJob) + 255) & ~(size_t)255));
-    char *dsol = (char *)b->d_finish + ((total * sizeof(FinishJob) + 255) & ~(size_t)255);
+    b->d_finish_q = (const FinishJob *)((const char *)b->d_finish + ((total * sizeof(FinishJob) + 255) & ~(size_t)255));
+    char *dsol = (char *)b->d_finish_q + ((total * sizeof(FinishJob) + 255) & ~(size_t)255);
     if ((st = upload(&b->ctx, (void *)b->d_turn, turn.data(), total * sizeof(TurnJob))) != SV_OK) return fail_del(st);
-    hipLaunchKernelGGL(k_turn_batch, dim3(64, total), dim3(256), 0, b->stream, b->d_turn);
+    hipLaunchKernelGGL(k_turn_batch, dim3(64, total), dim3(256), 0, b->stream, b->d_turn, b->d_cnt, b->n_cnt);
     {
         const hipError_t ke = hipGetLastError();
         if (ke != hipSuccess) return fail_del(hip_fail(ke, "k_turn_batch"));
     }
     size_t sol_off = 0;
+    std::vector<QueueClassIn> qcls;
+    std::vector<int> qsolve_cls(total, 0);
+    std::vector<PipeSolve> qsolves(total);
     for (size_t c = 0; c < class_keys.size(); ++c) {
         const int n_s = class_keys[c].first, n_c = class_keys[c].second;
         std::vector<PipeSolve> ps;
@@ -389,17 +381,37 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         const uint64_t np = pipe_b_blocks_for(n_s, n_c, C.cl[1]);
         if (np > pipe_b_blocks(n_s, n_c, e)) return fail_del(fail(SV_EDEVICE, "partials exceed their buffer"));
         C.nparts = np;
-        for (int k : class_members[c]) {
+        for (size_t q = 0; q < class_members[c].size(); ++q) {
+            const int k = class_members[c][q];
             const SolveLay &L = lay[k];
             const int g1 = (n_c + 1) / 2;
             fin[k] = FinishJob{(const double *)(base + L.part), np, (const double2 *)(base + L.zpart),
                                pipe_c_rows(n_c), dim_of(n_s), exp2(-0.5 * (n_c + g1)),
                                (const double2 *)cex[L.inst]->p, b->d_out + 4 * (size_t)k};
+            qsolve_cls[k] = (int)c;
+            qsolves[k] = ps[q];
         }
+        qcls.push_back(QueueClassIn{n_s, n_c, {C.cl[0], C.cl[1], C.cl[2]}});
         b->classes.push_back(C);
     }
     if ((st = upload(&b->ctx, (void *)b->d_finish, fin.data(), total * sizeof(FinishJob))) != SV_OK)
         return fail_del(st);
+    if (form != 0) {
+        st = dt == SV_C64 ? pipe_queue_build<float>(&b->ctx, b->stream, b->queue, b->qdesc, qcls, qsolve_cls,
+                                                    qsolves, b->d_cnt, b->d_flag)
+                          : pipe_queue_build<double>(&b->ctx, b->stream, b->queue, b->qdesc, qcls, qsolve_cls,
+                                                     qsolves, b->d_cnt, b->d_flag);
+        if (st == SV_OK) {
+            b->have_queue = true;
+            for (int k = 0; k < total; ++k) fin[k].nparts = b->queue.nparts[k];
+            if ((st = upload(&b->ctx, (void *)b->d_finish_q, fin.data(), total * sizeof(FinishJob))) != SV_OK)
+                return fail_del(st);
+        } else if (form == 1 || st != SV_EUNSUPPORTED) {
+            return fail_del(st);
+        } else {
+            clear_error();      // a shape the queue does not carry: the stream form
+        }
+    }
     // side streams (default priority) and the fork/join events; classes go to
     // the least-loaded stream, largest first, weighed by amplitudes plus a
     // fixed cost per class for its three launches
@@ -428,6 +440,21 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
             b->lane[best].push_back(ci);
             load[best] += wgt[ci];
         }
+    }
+    // the launch form: as asked, or the faster of three timed eager runs each
+    // (after an untimed one)
+    if (form >= 0 || !b->have_queue) {
+        b->use_queue = form != 0 && b->have_queue;
+    } else {
+        const bool tr0 = trace_set(false);
+        for (int f = 0; f < 2 && st == SV_OK; ++f) {
+            b->use_queue = f == 1;
+            auto run = [&]() { return dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b); };
+            st = time_stream(b->stream, 3, &b->form_ms[f], run);
+        }
+        trace_set(tr0);
+        if (st != SV_OK) return fail_del(st);
+        b->use_queue = b->form_ms[1] < b->form_ms[0];
     }
     // record the whole sweep once (event tracing is paused while capturing)
     SV_HIP(hipStreamSynchronize(b->stream));
@@ -463,6 +490,16 @@ sv_status sv_batch_run(sv_batch b, int use_graph, double *results) {
     }
     if (results) {
         SV_TRY(download(&b->ctx, results, b->d_out, (size_t)b->n_solves * 4 * sizeof(double)));
+        // a wait of the work queue that expired (this run or an earlier one
+        // without results) leaves the flag set: the results are not trusted
+        if (b->use_queue) {
+            unsigned flag = 0, finished = 0;
+            SV_TRY(download(&b->ctx, &flag, b->d_flag, sizeof(unsigned)));
+            SV_TRY(download(&b->ctx, &finished, b->d_cnt + b->n_cnt - 1, sizeof(unsigned)));
+            if (flag) return fail(SV_EDEVICE, "a work-queue dependency wait expired; the results are invalid");
+            if (finished != (unsigned)b->n_solves)
+                return fail(SV_EDEVICE, "the work queues finished %u of %d solves", finished, b->n_solves);
+        }
     } else {
         SV_HIP(hipStreamSynchronize(b->stream));
     }
@@ -470,6 +507,13 @@ sv_status sv_batch_run(sv_batch b, int use_graph, double *results) {
 }
 
 int sv_batch_num_solves(sv_batch b) { return b ? b->n_solves : 0; }
+
+int sv_batch_form(sv_batch b, float *ms_streams, float *ms_queue) {
+    if (!b) return -1;
+    if (ms_streams) *ms_streams = b->form_ms[0];
+    if (ms_queue) *ms_queue = b->form_ms[1];
+    return b->use_queue ? 1 : 0;
+}
 
 sv_status sv_batch_free(sv_batch b) {
     if (b) {

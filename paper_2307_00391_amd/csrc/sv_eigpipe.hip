@@ -36,6 +36,7 @@
 // outside the tile is one exact-turn phase per stage and tile.
 #include <math.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -224,9 +225,8 @@ __device__ __forceinline__ void tile_coords(const PipeArgs &A, uint64_t &j0, uin
 // k_pipe_a: phase-estimation state + inverse cascade on G1
 // ---------------------------------------------------------------------------
 template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+__device__ __forceinline__ void pipe_a_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
     constexpr int G = RA + RB;
-    const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const double2 *__restrict__ beta = S.beta;
     const gptr<const uint64_t> __restrict__ F = (gptr<const uint64_t>)S.F;
@@ -236,8 +236,6 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
     cvec<R> *TW = tile + ((size_t)C << G);                           // [2^G - 1] (+1 pad)
     cvec<R> *om = TW + (1 << G);                                     // [G][C] exp(2 pi i F) of the local bits
     cvec<R> *cc = om + G * C;                                        // [C] column constants
-    uint64_t j0, o;
-    tile_coords(A, j0, o);
     const int n_c = A.n_c;
     fill_twiddles<R>(TW, G, 0, 0);
     // the tile holds clock index s = (o << G) | l; bit b of s carries F[j][n_c-1-b].
@@ -321,15 +319,24 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
     }
 }
 
+template <typename R, int RA, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
+    uint64_t j0, o;
+    tile_coords(A, j0, o);
+    pipe_a_body<R, RA, RB, NT>(A, solve_of(one, many), j0, o);
+}
+
 // ---------------------------------------------------------------------------
 // k_pipe_b: inverse cascade on G2, inversion rotation, forward cascade on G2
 // ---------------------------------------------------------------------------
+// Tile: columns [j0, j0 + C) at G1 value o; persistent, A.iters column
+// blocks j0 + it 2^(pslog + cl).  The FP64 partial pair goes to slot `slot`.
 template <typename R, int RA, int RB, int NT, bool PERS>
-__device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &one, const PipeSolve *__restrict__ many) {
+__device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o,
+                                            uint64_t slot) {
     constexpr int G = RA + RB;
     // column data of a tile per thread (G C <= 8 * 64 <= 2 NT phases, C <= NT table entries)
     constexpr int OMR = 2;
-    const PipeSolve S = solve_of(one, many);
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const gptr<double> __restrict__ part = (gptr<double>)S.part;
     extern __shared__ unsigned char smem_raw[];
@@ -342,21 +349,10 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
     cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
     cvec<R> *tT = om + G * C;                                        // [C] G1 table entries T_j(o)
     __shared__ double red[2][NT / 64];
-    // tiles: one per block (tile_coords), or, persistent, a fixed G1 value
-    // o = blockIdx.x >> pslog per block and the column blocks
-    // (blockIdx.x mod 2^pslog) + it 2^pslog for it < iters, so the twiddle,
-    // pair and rotation tables (functions of o) are built once per block
-    uint64_t j0, o;
-    int iters = 1;
-    uint64_t jstep = 0;
-    if (PERS) {
-        o = blockIdx.x >> A.pslog;
-        j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
-        iters = A.iters;
-        jstep = 1ull << (A.pslog + A.cl);
-    } else {
-        tile_coords(A, j0, o);           // o = value of the G1 bits
-    }
+    // persistent: the twiddle, pair and rotation tables (functions of o) are
+    // built once for all the block's column blocks
+    const int iters = PERS ? A.iters : 1;
+    const uint64_t jstep = PERS ? 1ull << (A.pslog + A.cl) : 0;
     const int g1 = A.g1, n_c = A.n_c;
     // the tile's column data: the G1 table entries T_j(o) and the phases of the
     // G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read before the
@@ -508,32 +504,38 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             sp += red[0][w];
             sn += red[1][w];
         }
-        const uint64_t bid = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-        part[2 * bid] = sp;
-        part[2 * bid + 1] = sn;
+        part[2 * slot] = sp;
+        part[2 * slot + 1] = sn;
     }
 }
 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    pipe_b_body<R, RA, RB, NT, false>(A, one, many);
+    uint64_t j0, o;
+    tile_coords(A, j0, o);               // o = value of the G1 bits
+    pipe_b_body<R, RA, RB, NT, false>(A, solve_of(one, many), j0, o,
+                                      (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x);
 }
 
-// the persistent form (single solves): one G1 value per block
+// the persistent form (single solves): one G1 value o = blockIdx.x >> pslog
+// per block and the column blocks (blockIdx.x mod 2^pslog) + it 2^pslog
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_bp(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    pipe_b_body<R, RA, RB, NT, true>(A, one, many);
+    const uint64_t o = blockIdx.x >> A.pslog;
+    const uint64_t j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
+    pipe_b_body<R, RA, RB, NT, true>(A, solve_of(one, many), j0, o, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // k_pipe_c: forward cascade on G1, conjugate phases, clock sum of the tile
 // (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
+// Tile: columns [j0, j0 + C) at G2 value o; persistent, A.iters column
+// blocks j0 + it 2^(pslog + cl)
 template <typename R, int RA, int RB, int NT, bool PERS>
-__device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &one, const PipeSolve *__restrict__ many) {
+__device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
     constexpr int G = RA + RB;
     constexpr int OMR = 2;               // G1-bit phases per thread (G C <= 8 * 64 <= 2 NT)
-    const PipeSolve S = solve_of(one, many);
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
@@ -545,19 +547,8 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
     cvec<R> *cc = om + G * C;
     const size_t zoff = (((size_t)((unsigned char *)(cc + C) - smem_raw)) + 15) & ~(size_t)15;
     double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [NT] per-thread partials
-    // tiles: one per block, or, persistent, a fixed G2 value per block and
-    // the column blocks (blockIdx.x mod 2^pslog) + it 2^pslog
-    uint64_t j0, o;
-    int iters = 1;
-    uint64_t jstep = 0;
-    if (PERS) {
-        o = blockIdx.x >> A.pslog;
-        j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
-        iters = A.iters;
-        jstep = 1ull << (A.pslog + A.cl);
-    } else {
-        tile_coords(A, j0, o);           // o = value of the G2 bits
-    }
+    const int iters = PERS ? A.iters : 1;
+    const uint64_t jstep = PERS ? 1ull << (A.pslog + A.cl) : 0;
     const int n_c = A.n_c;
     const int nla = C << RB, nlb = C << RA;
     // the thread's first phase-B line is read before the tables are built, so
@@ -705,7 +696,9 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    pipe_c_body<R, RA, RB, NT, false>(A, one, many);
+    uint64_t j0, o;
+    tile_coords(A, j0, o);               // o = value of the G2 bits
+    pipe_c_body<R, RA, RB, NT, false>(A, solve_of(one, many), j0, o);
 }
 
 // the persistent form (single solves): one G2 value per block.  complex64:
@@ -715,7 +708,179 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
 template <typename R, int RA, int RB, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, sizeof(R) == 4 ? 4 : 8))) void k_pipe_cp(
     PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    pipe_c_body<R, RA, RB, NT, true>(A, one, many);
+    const uint64_t o = blockIdx.x >> A.pslog;
+    const uint64_t j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
+    pipe_c_body<R, RA, RB, NT, true>(A, solve_of(one, many), j0, o);
+}
+
+// ---------------------------------------------------------------------------
+// a batch as one persistent kernel over device work queues
+// ---------------------------------------------------------------------------
+struct QClass {
+    PipeArgs A[3];            // launch parameters of the three kernels' items
+    int g[3];                 // the group each transforms: g1, g2, g1
+    uint32_t per_o[3];        // items per value of the other clock group
+};
+struct QSolve {
+    PipeSolve S;
+    uint32_t cls;
+    uint32_t items[3];        // items of the three kernels (the finish waits for the last)
+};
+constexpr int kMaxQueues = 8;
+struct QueueArgs {
+    const QClass *cls;
+    const QSolve *solves;
+    const uint64_t *items;    // the queues' item codes, queue after queue
+    const FinishJob *fin;
+    unsigned *cnt;            // [3 nsolves] done counters, [kMaxQueues] heads, finished solves
+    unsigned *flag;
+    uint64_t wait_ticks;      // bound of one dependency wait, in wall-clock ticks
+    uint32_t nsolves;
+    int local;                // 1: one queue per XCC, served by that XCC's blocks; 0: one queue for all
+                              // blocks, with device-scope synchronisation
+    uint32_t qstart[kMaxQueues + 1];
+    int qof[16];              // local: the queue of every XCC id (-1: none)
+};
+
+// the accelerator complex die (its own L2) the wave runs on
+__device__ __forceinline__ int xcc_id() { return (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11)) & 15u); }
+
+// Wait for *c >= target, bounded by `ticks` of the constant-rate wall clock
+// (a quarter second): on expiry the flag is set and the item runs anyway,
+// and once the flag is set no wait blocks any more, so every block drains.
+// Then the acquire: a queue served by one XCC shares that XCC's L2 with its
+// producers, so only the CU's vector L1 is invalidated (a line there may
+// hold data another phase has since rewritten); otherwise the device-scope
+// acquire (L1 and the XCC's L2).  The block barrier follows.
+__device__ __forceinline__ void queue_wait(unsigned *c, unsigned target, unsigned *flag, uint64_t ticks, bool local) {
+    if (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (wall_clock64() - t0 > ticks) {
+                __hip_atomic_fetch_or(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    if (local) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        asm volatile("buffer_inv sc0" ::: "memory");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+}
+
+template <typename R, int G>
+__device__ __forceinline__ void queue_item(int ph, const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o,
+                                           uint64_t slot) {
+    constexpr int RA = (G + 1) / 2, RB = G / 2;     // the register split of dispatch_g
+    if (ph == 0)
+        pipe_a_body<R, RA, RB, 256>(A, S, j0, o);
+    else if (ph == 1)
+        pipe_b_body<R, RA, RB, 256, true>(A, S, j0, o, slot);
+    else
+        pipe_c_body<R, RA, RB, 256, true>(A, S, j0, o);
+}
+
+// Every block serves one queue and takes its items from the queue's head
+// until it is empty; the next item's code and the position of the one after
+// it are fetched while the current one runs.  An item code holds the phase (bits 62-63: 0-2 the three
+// kernels, 3 the finish), the solve (bits 42-61), the number of items of the
+// previous phase of the solve that it waits for (bits 21-41) and the item's
+// index within its phase of the solve (bits 0-20).  With one queue per XCC, a block reads the XCC it runs on and
+// serves that XCC's queue: every producer and consumer of a solve then
+// share one L2, and no L2 write-back or invalidation is needed (the XCCs
+// present are probed when the queues are built; dispatch spreads the
+// blocks of a launch over all of them, from a starting XCC that varies
+// between launches).  GMAX bounds the clock groups of the batch: the registers of
+// a kernel are those of its widest group, so batches of groups <= 6 bits
+// get a form without the 7- and 8-bit bodies, held to four waves per SIMD
+// for complex64 (128 VGPRs, a few spilled) and two for complex128 (256).
+template <typename R, int GMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX == 6 ? (sizeof(R) == 4 ? 4 : 2) : 1))) void
+k_pipe_queue(QueueArgs Q) {
+    __shared__ uint64_t sh_code;
+    const bool local = Q.local != 0;
+    const int q = local ? Q.qof[xcc_id()] : 0;
+    if (q < 0) return;
+    unsigned *const head = Q.cnt + 3 * (size_t)Q.nsolves + q;
+    unsigned *const finished = Q.cnt + 3 * (size_t)Q.nsolves + kMaxQueues;
+    const uint32_t base = Q.qstart[q], nitems = Q.qstart[q + 1] - base;
+    // thread 0: the code of the block's next item (~0: none left) and the
+    // queue position of the one after, both in flight during an item
+    uint64_t next_code = ~0ull;
+    uint32_t pend = 0;
+    if (threadIdx.x == 0) {
+        const uint32_t i = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (i < nitems) next_code = Q.items[base + i];
+        pend = i < nitems ? __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : nitems;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint64_t code = next_code;
+            if (code != ~0ull) {
+                next_code = pend < nitems ? Q.items[base + pend] : ~0ull;
+                if (pend < nitems) pend = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned ph = (unsigned)(code >> 62), sv = (unsigned)(code >> 42) & 0xFFFFFu;
+                if (ph > 0)
+                    queue_wait(Q.cnt + 3 * (size_t)sv + ph - 1, (unsigned)(code >> 21) & 0x1FFFFFu, Q.flag,
+                               Q.wait_ticks, local);
+            }
+            sh_code = code;
+        }
+        // also the barrier between the last item's LDS reads and this one's writes
+        __syncthreads();
+        const uint64_t code = sh_code;
+        if (code == ~0ull) break;
+        const int ph = (int)(code >> 62);
+        const uint32_t sv = (uint32_t)(code >> 42) & 0xFFFFFu;
+        const uint64_t t = code & 0x1FFFFFu;
+        if (ph == 3) {
+            batch_finish_body(Q.fin[sv]);
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
+        const QSolve &qs = Q.solves[sv];
+        const QClass &c = Q.cls[qs.cls];
+        const PipeArgs A = c.A[ph];
+        const PipeSolve S = qs.S;
+        const uint64_t per = c.per_o[ph];
+        const uint64_t o = t / per;
+        const uint64_t j0 = ((t - o * per) * (uint64_t)A.iters) << A.cl;
+        switch (c.g[ph]) {
+        case 1: queue_item<R, 1>(ph, A, S, j0, o, t); break;
+        case 2: queue_item<R, 2>(ph, A, S, j0, o, t); break;
+        case 3: queue_item<R, 3>(ph, A, S, j0, o, t); break;
+        case 4: queue_item<R, 4>(ph, A, S, j0, o, t); break;
+        case 5: queue_item<R, 5>(ph, A, S, j0, o, t); break;
+        case 6: queue_item<R, 6>(ph, A, S, j0, o, t); break;
+        case 7:
+            if (GMAX >= 7) queue_item<R, 7>(ph, A, S, j0, o, t);
+            break;
+        default:
+            if (GMAX >= 8) queue_item<R, 8>(ph, A, S, j0, o, t);
+            break;
+        }
+        // publish the item: every wave's stores complete (the block barrier
+        // alone waits for LDS traffic only): in the XCC's L2 for a local
+        // queue, else released at device scope; then one thread counts it
+        if (local) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(Q.cnt + 3 * (size_t)sv + ph, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// the XCC of every block of a grid (one wave per block)
+__global__ void k_xcc_probe(int *__restrict__ out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 // ---------------------------------------------------------------------------
@@ -1019,6 +1184,211 @@ template sv_status pipe_run_batch<double>(hipStream_t, int, int, const int *, co
                                           uint64_t *);
 template sv_status pipe_config<float>(hipStream_t, int, int, const PipeSolve *, int *, int *);
 template sv_status pipe_config<double>(hipStream_t, int, int, const PipeSolve *, int *, int *);
+
+// ---------------------------------------------------------------------------
+// the work queues' plan: items of about 2^15 amplitudes (runs of consecutive
+// column blocks for k_pipe_b and k_pipe_c); the solves spread over one
+// queue per XCC, each queue numbered phase-major, its solves largest first
+// ---------------------------------------------------------------------------
+template <typename R>
+sv_status pipe_queue_build(sv_state ctx, hipStream_t st, PipeQueue &q, DevBuf &desc,
+                           const std::vector<QueueClassIn> &cls, const std::vector<int> &solve_cls,
+                           const std::vector<PipeSolve> &solves, unsigned *cnt, unsigned *flag) {
+    (void)st;
+    const size_t e = sizeof(cvec<R>);
+    const int ns = (int)solves.size();
+    if (ns < 1 || ns >= (1 << 20) || solve_cls.size() != solves.size())
+        return fail(SV_EINVAL, "work queue of %d solves", ns);
+    constexpr int kLim = 144 * 1024;
+    static bool attr_done = false;
+    if (!attr_done) {
+        const hipError_t h6 =
+            hipFuncSetAttribute((const void *)k_pipe_queue<R, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        const hipError_t h8 =
+            hipFuncSetAttribute((const void *)k_pipe_queue<R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
+        (void)hipGetLastError();
+        if (h6 != hipSuccess || h8 != hipSuccess) return fail(SV_EDEVICE, "cannot raise the LDS limit of the queue kernel");
+        attr_done = true;
+    }
+    std::vector<QClass> qc(cls.size());
+    size_t lds = 0;
+    int gmax = 1;
+    for (size_t k = 0; k < cls.size(); ++k) {
+        const QueueClassIn &ci = cls[k];
+        const int nt[3] = {256, 256, 256};
+        PipePlan P;
+        make_plan(P, ci.n_s, ci.n_c, e, ci.cl, nt, 1);
+        for (int w = 0; w < 3; ++w) {
+            PipeArgs A = P.A[w];
+            const int g = w == 1 ? A.g2 : A.g1;
+            // tiles of at most 2^11 amplitudes: LDS for four blocks per CU
+            while (A.cl > 0 && ((1ull << A.cl) << g) > (1ull << 11)) --A.cl;
+            const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
+            int iters = 1;
+            // a run of column blocks prefetches each next block's column data
+            // (G C <= 2 x 256 entries; k_pipe_c also needs the staged G2 phases)
+            if (w > 0 && (w == 1 || A.ccrows) && (uint64_t)g * C <= 512)
+                while ((uint64_t)iters < nb && (((uint64_t)iters * 2 * C) << g) <= (1ull << 15)) iters *= 2;
+            A.pers = w > 0 ? 1 : 0;
+            A.pslog = 0;
+            A.iters = iters;
+            qc[k].A[w] = A;
+            qc[k].g[w] = g;
+            if (g > gmax) gmax = g;
+            qc[k].per_o[w] = (uint32_t)(nb / (uint64_t)iters);
+            const size_t b = pipe_lds(w, A.cl, g, e, 256);
+            if (b > lds) lds = b;
+        }
+    }
+    if (lds > (size_t)kLim) return fail(SV_EUNSUPPORTED, "queue items need %zu bytes of LDS", lds);
+    std::vector<QSolve> qs(ns);
+    std::vector<double> cost(ns);
+    q.nparts.assign(ns, 0);
+    double bytes = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        const QClass &c = qc[solve_cls[k]];
+        qs[k].S = solves[k];
+        qs[k].cls = (uint32_t)solve_cls[k];
+        const int g1 = c.A[0].g1, g2 = c.A[0].g2;
+        qs[k].items[0] = c.per_o[0];
+        qs[k].items[1] = c.per_o[1] << g1;
+        qs[k].items[2] = c.per_o[2] << g2;
+        q.nparts[k] = qs[k].items[1];
+        if (q.nparts[k] > pipe_b_blocks(c.A[0].n_s, c.A[0].n_c, e))
+            return fail(SV_EDEVICE, "queue partials exceed their buffer");
+        const double half = (double)c.A[0].N * (double)(1ull << c.A[0].n_c) * e;
+        const double table = (double)c.A[0].N * (double)(1ull << g1) * e;
+        cost[k] = 2.0 * half + 2.0 * table;
+        bytes += cost[k];
+    }
+    // resident blocks, and the XCC each of them lands on
+    q.gmax = gmax <= 6 ? 6 : 8;
+    const void *kfn = q.gmax == 6 ? (const void *)k_pipe_queue<R, 6> : (const void *)k_pipe_queue<R, 8>;
+    int per_cu = 0, dev = 0, ncu = 0, khz = 0;
+    SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, lds));
+    SV_HIP(hipGetDevice(&dev));
+    SV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    SV_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (per_cu < 1) return fail(SV_EUNSUPPORTED, "the queue kernel does not fit a CU with %zu bytes of LDS", lds);
+    q.wait_ticks = (uint64_t)(khz > 0 ? khz : 100000) * 250;     // 0.25 s
+    q.blocks = per_cu * ncu;
+    std::vector<int> ids(q.blocks);
+    {
+        DevBuf probe;
+        SV_TRY(probe.alloc(ids.size() * sizeof(int)));
+        hipLaunchKernelGGL(k_xcc_probe, dim3((unsigned)q.blocks), dim3(256), 0, ctx->stream, (int *)probe.p);
+        SV_HIP(hipGetLastError());
+        SV_TRY(download(ctx, ids.data(), probe.p, ids.size() * sizeof(int)));
+    }
+    // queues: one per XCC that the probe's blocks landed on (each held an
+    // even share of them), else one queue with device-scope synchronisation
+    std::vector<int> distinct, count;
+    for (int b = 0; b < q.blocks; ++b) {
+        const auto it = std::find(distinct.begin(), distinct.end(), ids[b]);
+        if (it == distinct.end()) {
+            distinct.push_back(ids[b]);
+            count.push_back(1);
+        } else {
+            ++count[it - distinct.begin()];
+        }
+    }
+    const int D = (int)distinct.size();
+    bool even = D >= 1 && D <= kMaxQueues;
+    for (int i = 0; i < D && even; ++i) even = distinct[i] >= 0 && distinct[i] < 16 && count[i] * D >= q.blocks / 2;
+    if (even) {
+        std::sort(distinct.begin(), distinct.end());
+        q.nq = D;
+        for (int i = 0; i < D; ++i) q.xcc[i] = distinct[i];
+    } else {
+        q.nq = 1;
+        q.xcc[0] = -1;
+    }
+    // solves to queues, longest first to the least loaded queue
+    std::vector<int> order(ns);
+    for (int k = 0; k < ns; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<std::vector<int>> members(q.nq);
+    std::vector<double> load(q.nq, 0.0);
+    for (int k : order) {
+        int best = 0;
+        for (int i = 1; i < q.nq; ++i)
+            if (load[i] < load[best]) best = i;
+        members[best].push_back(k);
+        load[best] += cost[k];
+    }
+    // each queue phase-major, its solves largest first; a code carries the
+    // item count its wait targets (that of the solve's previous phase)
+    for (int k = 0; k < ns; ++k)
+        for (int ph = 0; ph < 3; ++ph)
+            if (qs[k].items[ph] >= (1u << 21))
+                return fail(SV_EUNSUPPORTED, "%u items in one phase of a solve", qs[k].items[ph]);
+    std::vector<uint64_t> items;
+    for (int i = 0; i < q.nq; ++i) {
+        q.qstart[i] = (uint32_t)items.size();
+        for (int ph = 0; ph < 3; ++ph)
+            for (int k : members[i]) {
+                q.items_per_phase[ph] += qs[k].items[ph];
+                const uint64_t wait = ph > 0 ? qs[k].items[ph - 1] : 0;
+                for (uint64_t t = 0; t < qs[k].items[ph]; ++t)
+                    items.push_back(((uint64_t)ph << 62) | ((uint64_t)k << 42) | (wait << 21) | t);
+            }
+        for (int k : members[i]) items.push_back((3ull << 62) | ((uint64_t)k << 42) | ((uint64_t)qs[k].items[2] << 21));
+        if (items.size() >= 0xffffffffull) return fail(SV_EUNSUPPORTED, "work queue of %zu items", items.size());
+    }
+    q.qstart[q.nq] = (uint32_t)items.size();
+    q.items_per_phase[3] = (uint64_t)ns;
+    // descriptors: classes, solves, item codes
+    const size_t o_cls = 0, o_sol = (qc.size() * sizeof(QClass) + 255) & ~(size_t)255;
+    const size_t o_items = o_sol + ((qs.size() * sizeof(QSolve) + 255) & ~(size_t)255);
+    SV_TRY(desc.alloc(o_items + items.size() * sizeof(uint64_t)));
+    char *d = (char *)desc.p;
+    SV_TRY(upload(ctx, d + o_cls, qc.data(), qc.size() * sizeof(QClass)));
+    SV_TRY(upload(ctx, d + o_sol, qs.data(), qs.size() * sizeof(QSolve)));
+    SV_TRY(upload(ctx, d + o_items, items.data(), items.size() * sizeof(uint64_t)));
+    q.d_cls = d + o_cls;
+    q.d_solves = d + o_sol;
+    q.d_items = (const uint64_t *)(d + o_items);
+    q.nitems = (uint32_t)items.size();
+    q.nsolves = (uint32_t)ns;
+    q.cnt = cnt;
+    q.flag = flag;
+    q.lds = lds;
+    q.bytes = bytes;
+    return SV_OK;
+}
+
+template <typename R>
+sv_status pipe_queue_launch(hipStream_t st, const PipeQueue &q, const FinishJob *d_fin) {
+    QueueArgs Q;
+    Q.cls = (const QClass *)q.d_cls;
+    Q.solves = (const QSolve *)q.d_solves;
+    Q.items = q.d_items;
+    Q.fin = d_fin;
+    Q.cnt = q.cnt;
+    Q.flag = q.flag;
+    Q.wait_ticks = q.wait_ticks;
+    Q.nsolves = q.nsolves;
+    Q.local = q.xcc[0] >= 0 ? 1 : 0;
+    for (int i = 0; i <= kMaxQueues; ++i) Q.qstart[i] = i <= q.nq ? q.qstart[i] : q.qstart[q.nq];
+    for (int i = 0; i < 16; ++i) Q.qof[i] = -1;
+    if (Q.local)
+        for (int i = 0; i < q.nq; ++i) Q.qof[q.xcc[i]] = i;
+    TraceScope ts(st, "pipe_queue", q.bytes, 0.0);
+    if (q.gmax == 6)
+        hipLaunchKernelGGL((k_pipe_queue<R, 6>), dim3((unsigned)q.blocks), dim3(256), q.lds, st, Q);
+    else
+        hipLaunchKernelGGL((k_pipe_queue<R, 8>), dim3((unsigned)q.blocks), dim3(256), q.lds, st, Q);
+    SV_HIP(hipGetLastError());
+    return SV_OK;
+}
+template sv_status pipe_queue_build<float>(sv_state, hipStream_t, PipeQueue &, DevBuf &,
+                                           const std::vector<QueueClassIn> &, const std::vector<int> &,
+                                           const std::vector<PipeSolve> &, unsigned *, unsigned *);
+template sv_status pipe_queue_build<double>(sv_state, hipStream_t, PipeQueue &, DevBuf &,
+                                            const std::vector<QueueClassIn> &, const std::vector<int> &,
+                                            const std::vector<PipeSolve> &, unsigned *, unsigned *);
+template sv_status pipe_queue_launch<float>(hipStream_t, const PipeQueue &, const FinishJob *);
+template sv_status pipe_queue_launch<double>(hipStream_t, const PipeQueue &, const FinishJob *);
 
 uint64_t pipe_b_blocks_for(int n_s, int n_c, int cl) {
     const int g1 = (n_c + 1) / 2;

@@ -6,6 +6,7 @@
 
 #include <vector>
 
+#include "sv_device.h"
 #include "sv_internal.h"
 
 namespace sv {
@@ -31,6 +32,104 @@ struct PipeSolve {
     double *part;           // k_pipe_b partial sums (2 per block)
     double2 *zpart;         // k_pipe_c partial column sums [2^g2][N]
 };
+
+// the last step of a batched solve: FP64 sums of P(a=1) and the norm, the
+// post-selected eigen-coefficients z_j (column sums of the clock projection),
+// p_post = |z|^2 and F = |<x_C|x_Q>| = |sum conj(c_j) z_j| / |z|
+struct FinishJob {
+    const double *part;     // k_pipe_b partials, 2 per block (or queue item)
+    uint64_t nparts;
+    const double2 *zpart;   // [rows][N]
+    int rows;
+    uint64_t N;
+    double scale;           // 2^(-(n_c + g1)/2)
+    const double2 *cexact;  // normalised eigen-coefficients of A^{-1} b
+    double *out;            // p_post, p_anc, norm_total, fidelity
+};
+
+__device__ __forceinline__ double finish_block_sum(double v, double *ws) {
+    v = wave_sum_f64(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// one block of 256 threads per solve; fixed summation order
+__device__ __forceinline__ void batch_finish_body(const FinishJob &J) {
+    __shared__ double ws[4];
+    double pa = 0.0, nt = 0.0, pp = 0.0, orr = 0.0, oi = 0.0;
+    for (uint64_t i = threadIdx.x; i < J.nparts; i += blockDim.x) {
+        pa += J.part[2 * i];
+        nt += J.part[2 * i + 1];
+    }
+    for (uint64_t j = threadIdx.x; j < J.N; j += blockDim.x) {
+        double zr = 0.0, zi = 0.0;
+        for (int r = 0; r < J.rows; ++r) {
+            const double2 v = J.zpart[(uint64_t)r * J.N + j];
+            zr += v.x;
+            zi += v.y;
+        }
+        zr *= J.scale;
+        zi *= J.scale;
+        pp += zr * zr + zi * zi;
+        const double2 c = J.cexact[j];
+        orr += c.x * zr + c.y * zi;      // conj(c) z
+        oi += c.x * zi - c.y * zr;
+    }
+    pa = finish_block_sum(pa, ws);
+    nt = finish_block_sum(nt, ws);
+    pp = finish_block_sum(pp, ws);
+    orr = finish_block_sum(orr, ws);
+    oi = finish_block_sum(oi, ws);
+    if (threadIdx.x == 0) {
+        J.out[0] = pp;
+        J.out[1] = pa;
+        J.out[2] = nt;
+        J.out[3] = pp > 0.0 ? sqrt(orr * orr + oi * oi) / sqrt(pp) : 0.0;
+    }
+}
+
+// A batch as one persistent kernel over device work queues.  Every solve
+// has four phases: the k_pipe_a tiles, the k_pipe_b tiles, the k_pipe_c
+// tiles (each item a run of consecutive column blocks of one clock-group
+// value) and the finish; an item of phase p > 0 waits until every item of
+// phase p - 1 of its solve is done (one counter per solve and phase).  The
+// solves are spread over one queue per XCC; a queue's items are numbered
+// phase-major, so a wait only ever targets items taken before.
+struct QueueClassIn {
+    int n_s, n_c;
+    int cl[3];              // log2 columns per tile of the three kernels
+};
+struct PipeQueue {
+    const void *d_cls = nullptr;        // class table (launch parameters per phase)
+    const void *d_solves = nullptr;     // solve table
+    const uint64_t *d_items = nullptr;  // item codes: phase (2 bits), solve (20), wait target (21), index (21)
+    uint32_t nitems = 0, nsolves = 0;
+    int nq = 1;                         // queues (one per XCC)
+    uint32_t qstart[9] = {};            // item range of every queue
+    int xcc[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // the XCC serving each queue (-1: any)
+    unsigned *cnt = nullptr;            // counters (pipe_queue_counters); zeroed before a run
+    unsigned *flag = nullptr;           // set (never cleared by the kernel) if a bounded wait expired
+    int blocks = 0;                     // resident blocks of 256 threads
+    int gmax = 8;                       // widest clock group the kernel form carries (6 or 8)
+    uint64_t wait_ticks = 0;            // bound of one dependency wait (wall-clock ticks)
+    size_t lds = 0;
+    std::vector<uint64_t> nparts;       // k_pipe_b partial pairs of every solve
+    uint64_t items_per_phase[4] = {0, 0, 0, 0};
+    double bytes = 0.0;                 // algorithmic HBM bytes of one run
+};
+// counters the queue needs for `nsolves` solves: three per solve, eight
+// queue heads, the count of finished solves (the last)
+inline size_t pipe_queue_counters(int nsolves) { return 3 * (size_t)nsolves + 8 + 1; }
+// plan and upload the queue (descriptors into `desc`); solve k uses class solve_cls[k]
+template <typename R>
+sv_status pipe_queue_build(sv_state ctx, hipStream_t st, PipeQueue &q, DevBuf &desc,
+                           const std::vector<QueueClassIn> &cls, const std::vector<int> &solve_cls,
+                           const std::vector<PipeSolve> &solves, unsigned *cnt, unsigned *flag);
+// one launch over every item; the counters must be zero
+template <typename R>
+sv_status pipe_queue_launch(hipStream_t st, const PipeQueue &q, const FinishJob *d_fin);
 
 template <typename R>
 sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]);

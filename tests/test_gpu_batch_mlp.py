@@ -89,9 +89,13 @@ def test_batch_matches_oracle(dt):
             k += 1
 
 
-def test_batch_graph_replays_match_eager_bitwise():
+@pytest.mark.parametrize("form", ["1", "0"])
+def test_batch_graph_replays_match_eager_bitwise(form, monkeypatch):
+    """form 1: the work-queue kernel, 0: the side streams"""
+    monkeypatch.setenv("SV_BATCH_QUEUE", form)
     probs = _batch_problems()
     h = B.sv_batch_prepare(probs, "c64")
+    assert B.sv_batch_form(h)[0] == int(form)
     try:
         eager = B.sv_batch_run(h, use_graph=False)
         for _ in range(3):
@@ -103,6 +107,86 @@ def test_batch_graph_replays_match_eager_bitwise():
         B.sv_batch_free(h)
     once = B.sv_hhl_batch(probs, "c64")
     assert np.array_equal(once, eager)
+
+
+def _wide_problems():
+    """the clock groups at the ends of the queue kernel's two forms: 1 bit
+    (n_c 2, 3) and 7, 8 bits (n_c 13..15), on one- and three-qubit systems;
+    T0 puts lambda_max at 1/2 or 9/10 of a turn"""
+    rng = inputs.rng_for(11, 0)
+    probs = []
+    for N, n_c, kappa, fs in ((2, 2, 3.0, (0.5, 0.9)), (2, 3, 5.0, (0.5, 0.9)), (8, 13, 30.0, (0.5, 0.9)),
+                              (2, 14, 4.0, (0.9,)), (2, 15, 6.0, (0.5,))):
+        A, lmin, lmax = inputs.random_spd_tridiag(rng, N, kappa)
+        probs.append((A, rng.standard_normal(N), n_c, np.array(fs) * 2 * math.pi / lmax))
+    return probs
+
+
+@pytest.fixture(scope="module")
+def wide_ref():
+    probs = _wide_problems()
+    ref = []
+    for A, b, n_c, t0s in probs:
+        for T0 in t0s:
+            psi, x, p_post, p_anc = oracle.hhl(A, b, n_c, T0)
+            ref.append((p_post, p_anc, _fidelity_ref(A, b, x)))
+    return probs, ref
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_wide_and_narrow_clock_groups_match_oracle(dt, wide_ref):
+    """Relative bars, as p_post falls to 1e-9 at n_c = 15: complex128 1e-10,
+    complex64 the sweep family's 2e-5 on the probabilities and 1e-5 on F
+    (from 1e-5 relative l2 on the post-selected vector)."""
+    probs, ref = wide_ref
+    print(f"[batch] wide/narrow groups {dt}", flush=True)
+    res = B.sv_hhl_batch(probs, dt)
+    rel = 1e-10 if dt == "c128" else 2e-5
+    ftol = 1e-10 if dt == "c128" else 1e-5
+    for k, (p_post, p_anc, Fr) in enumerate(ref):
+        pp, pa, nt, F = res[k]
+        assert abs(pp - p_post) <= rel * p_post, (k, pp, p_post)
+        assert abs(pa - p_anc) <= rel * p_anc, (k, pa, p_anc)
+        assert abs(nt - 1.0) <= TOL[dt]
+        assert abs(F - Fr) <= ftol, (k, F, Fr)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_queue_matches_stream_launches(dt, monkeypatch):
+    """The one-kernel work queues (SV_BATCH_QUEUE=1, read at prepare) against
+    the per-class kernels on side streams (=0): the same tile arithmetic, but
+    the FP64 partial sums are grouped differently and complex64 phase tables
+    are formed in another order."""
+    probs = _batch_problems() + _wide_problems()
+    monkeypatch.setenv("SV_BATCH_QUEUE", "1")
+    queue = B.sv_hhl_batch(probs, dt)
+    monkeypatch.setenv("SV_BATCH_QUEUE", "0")
+    streams = B.sv_hhl_batch(probs, dt)
+    bar = 1e-13 if dt == "c128" else 2e-6
+    assert np.abs(queue[:, :3] - streams[:, :3]).max() <= bar
+    assert np.abs(queue[:, 3] - streams[:, 3]).max() <= (1e-11 if dt == "c128" else 1e-4)
+
+
+def test_batch_form_is_timed_or_forced(monkeypatch):
+    probs = _batch_problems()
+    monkeypatch.delenv("SV_BATCH_QUEUE", raising=False)
+    h = B.sv_batch_prepare(probs, "c64")
+    try:
+        f, ms_s, ms_q = B.sv_batch_form(h)
+        assert ms_s > 0 and ms_q > 0
+        assert f == (1 if ms_q < ms_s else 0)
+        auto = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    monkeypatch.setenv("SV_BATCH_QUEUE", "1" if f == 0 else "0")
+    h = B.sv_batch_prepare(probs, "c64")
+    try:
+        assert B.sv_batch_form(h) == (1 - f, 0.0, 0.0)
+        other = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    assert np.abs(auto[:, :3] - other[:, :3]).max() <= 2e-6
+    assert np.abs(auto[:, 3] - other[:, 3]).max() <= 1e-4
 
 
 def test_batch_matches_single_solves():

@@ -59,10 +59,15 @@ def family():
     return ins, ref
 
 
+@pytest.mark.parametrize("path", ["queue", "streams"])
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-def test_sweep_family_batch_against_closed_form(family, dt):
+def test_sweep_family_batch_against_closed_form(family, dt, path, monkeypatch):
+    """path: the one-kernel work queues (SV_BATCH_QUEUE=1), or the per-class
+    kernels on side streams (0)"""
     ins, ref = family
     probs = [(it.A, it.b, it.n_c, it.t0) for it in ins]
+    monkeypatch.setenv("SV_BATCH_QUEUE", "1" if path == "queue" else "0")
+    print(f"[sweep family] {dt} {path}", flush=True)
     h = B.sv_batch_prepare(probs, dt)
     try:
         assert B.sv_batch_num_solves(h) == 16 * len(ins)
@@ -81,7 +86,7 @@ def test_sweep_family_batch_against_closed_form(family, dt):
             assert e[2] <= FTOL[dt], (it.index, m, Fg, F)
             assert abs(nt - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
             k += 1
-    print(f"sweep family {dt}: worst relative p_post {worst[0]:.2e}, p_anc {worst[1]:.2e}, |dF| {worst[2]:.2e}",
+    print(f"sweep family {dt} {path}: worst relative p_post {worst[0]:.2e}, p_anc {worst[1]:.2e}, |dF| {worst[2]:.2e}",
           flush=True)
 
 
