@@ -283,6 +283,7 @@ def main():
     ap.add_argument("--mfma-m", type=int, default=12)
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-mfma", action="store_true")
+    ap.add_argument("--no-mfma32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-qsp", action="store_true")
@@ -530,6 +531,63 @@ def main():
                               "ms_per_apply": g["ms"] / g["launches"],
                               "scatter_ms_per_apply": tr.get("scatter_rows", {"ms": 0})["ms"] / reps}
         ms_.close()
+        del ms_, dU
+        torch.cuda.empty_cache()
+
+    # ---- one controlled-U^(2^k) of phase estimation at the 32-qubit shape ----
+    # (system register of 16 qubits, control on a clock qubit: 2^15 rows of a
+    # 2^16 x 2^16 complex64 product).  U is the unitary DFT of order 2^16, a
+    # dense unitary with a closed form: it is filled on the device, and sampled
+    # rows of the result are checked against numpy's FFT of the same rows.
+    if not args.no_mfma and not args.no_mfma32:
+        m, nq = 16, 32
+        N = 1 << m
+        log(f"[bench] mfma: controlled 2^{m} unitary on {nq} qubits (DFT matrix, one application)")
+        dU = torch.empty((N, N), dtype=torch.complex64, device=dev)
+        kk = torch.arange(N, device=dev, dtype=torch.int64)
+        for r0 in range(0, N, 4096):
+            jj = torch.arange(r0, r0 + 4096, device=dev, dtype=torch.int64)
+            ph = ((jj[:, None] * kk[None, :]) % N).to(torch.float64) * (-2.0 * math.pi / N)
+            dU[r0:r0 + 4096] = (torch.polar(torch.ones_like(ph), ph) / math.sqrt(N)).to(torch.complex64)
+            del ph, jj
+        ms_ = B.State(nq, "c64", device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(3203)
+        ms_.tensor.copy_(torch.randn(1 << nq, dtype=torch.complex64, device=dev, generator=gen) / math.sqrt(1 << nq))
+        rows = [0, 12345, (1 << (nq - m - 1)) - 1]            # rows with the control (qubit 31) set
+        base = [(1 << (nq - 1)) | (r << m) for r in rows]
+        before = [ms_.tensor[b0:b0 + N].cpu().numpy().astype(np.complex128) for b0 in base]
+        untouched = ms_.tensor[:N].cpu().numpy()             # control clear: unchanged
+        rows_total = 1 << (nq - m - 1)
+        # the product's tile shape is pinned (workgroup tiles) so that no
+        # tuning runs of this 10-second product are made
+        B.sv_tune_set(f"cgemm/c64/{rows_total}/{N}/{N}/0", [0])
+        torch.cuda.synchronize()
+        B.sv_trace_enable(True)
+        t = time.perf_counter()
+        B.sv_apply_ctrl_unitary(ms_.h, dU, 0, m, nq - 1, 1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tr = B.sv_trace_report()
+        B.sv_trace_enable(False)
+        g = tr["cgemm"]
+        tflops = g["flops"] / (g["ms"] * 1e-3) / 1e12
+        errs = []
+        for b0, v in zip(base, before):
+            got = ms_.tensor[b0:b0 + N].cpu().numpy().astype(np.complex128)
+            want = np.fft.fft(v) / math.sqrt(N)
+            errs.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+        same = bool(np.array_equal(ms_.tensor[:N].cpu().numpy(), untouched))
+        out["mfma_ctrl_u_32q"] = {"qubits": nq, "m": m, "rows": rows_total, "U": "unitary DFT of order 2^16",
+                                  "tflops": tflops, "peak_fp32_matrix_tflops": FP32_MFMA_PEAK_TFLOPS,
+                                  "frac": tflops / FP32_MFMA_PEAK_TFLOPS, "gemm_s": g["ms"] * 1e-3,
+                                  "scatter_s": tr.get("scatter_rows", {"ms": 0})["ms"] * 1e-3, "wall_s": wall,
+                                  "sampled_rows_rel_l2_vs_fft": errs, "control_clear_rows_unchanged": same}
+        log(f"[bench] mfma 32q: {tflops:.1f} TFLOP/s, {g['ms'] * 1e-3:.2f} s GEMM, row errors "
+            f"{max(errs):.2e}, unchanged {same}")
+        ms_.close()
+        del ms_, dU, kk
+        torch.cuda.empty_cache()
 
     # ---------------- batched T0 sweep: one graph of 64 x 16 solves ----------------
     if not args.no_sweep:

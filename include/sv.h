@@ -145,8 +145,11 @@ int sv_plan_passes(int n_qubits, sv_dtype dt, const sv_gate *gates, int n_gates,
  * `adjoint`.  U: device, 2^m x 2^m, row-major, in the state's dtype.  This
  * is the controlled-U^(2^k) of phase estimation (main text: the operator is
  * exponentiated as exp(i A T0)), computed as a complex GEMM on the matrix
- * cores.  Only sys_lo == 0 is implemented (SV_EUNSUPPORTED otherwise).
- * Errors: SV_EINVAL (register outside the state, ctrl inside it). */
+ * cores; element k of a row sits at stride 2^sys_lo, so for sys_lo > 0 the
+ * GEMM reads 64 neighbouring rows per wavefront instead of a contiguous row.
+ * Errors: SV_EINVAL (register outside the state, ctrl inside it),
+ * SV_EUNSUPPORTED (m > 16), SV_ENOMEM (the staging buffer of rows x 2^m
+ * amplitudes that the product is written to before the scatter). */
 sv_status sv_apply_ctrl_unitary(sv_state s, const void *U, int sys_lo, int m, int ctrl,
                                 int ctrl_val, int adjoint);
 

@@ -1,9 +1,9 @@
-// Controlled dense unitary on the system register as a complex GEMM on the
-// matrix cores (MFMA): every amplitude row whose control bit matches is a
-// length-2^m vector v, replaced by U v.  Rows are gathered straight from
-// the state (row r lives at pdep(r, row_mask) | row_fix, its 2^m elements
-// contiguous), multiplied out of place into a compact buffer and scattered
-// back.  complex64 uses v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate);
+// Controlled dense unitary on a register of m qubits [lo, lo + m) as a
+// complex GEMM on the matrix cores (MFMA): every amplitude row whose control
+// bits match is a length-2^m vector v, replaced by U v.  Rows are gathered
+// straight from the state (row r starts at pdep(r, row_mask) | row_fix, its
+// element k at stride 2^lo), multiplied out of place into a compact buffer
+// and scattered back.  complex64 uses v_mfma_f32_16x16x4f32 (FP32 in, FP32 accumulate);
 // complex128 uses v_mfma_f64_16x16x4f64.  A complex product is four real
 // MFMAs: re += ar br - ai bi, im += ar bi + ai br.
 #include <string.h>
@@ -49,6 +49,7 @@ struct GemmArgs {
     uint64_t M;
     int N, K;
     uint64_t row_mask, row_fix;   // row r starts at pdep(r, row_mask) | row_fix
+    int ksh;                      // element k of a row at offset k << ksh
     int trans, conjb;
 };
 
@@ -67,8 +68,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
     const uint64_t row0 = (uint64_t)blockIdx.x * GBM;
     const int n0 = blockIdx.y * GBN;
 
-    // this thread's A-load row and its base offset in the state
-    const int a_row = tid >> 2, a_k = (tid & 3) * 4;
+    // this thread's A-load row and its base offset in the state: four
+    // threads along k per row when the row is contiguous (ksh = 0), else one
+    // row per lane, so that a wavefront reads 64 neighbouring rows
+    const int a_row = A.ksh ? (tid & 63) : tid >> 2, a_k = A.ksh ? (tid >> 6) * 4 : (tid & 3) * 4;
     const uint64_t ar = row0 + a_row;
     const bool a_ok = ar < A.M;
     const uint64_t a_base = a_ok ? (pdep64(ar, A.row_mask) | A.row_fix) : 0;
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
         for (int i = 0; i < 4; ++i) {
             const int kk = k0 + a_k + i;
             cvec<R> v = cmake<R>((R)0, (R)0);
-            if (a_ok && kk < A.K) v = A.in[a_base + kk];
+            if (a_ok && kk < A.K) v = A.in[a_base + ((uint64_t)kk << A.ksh)];
             As_re[a_k + i][a_row] = v.x;
             As_im[a_k + i][a_row] = v.y;
         }
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) void k_cgemm_w(GemmArgs<R> A) {
     for (int k0 = 0; k0 < A.K; k0 += 4) {
         const int kk = k0 + kq;
         cvec<R> a = cmake<R>((R)0, (R)0), b = cmake<R>((R)0, (R)0);
-        if (r_ok && kk < A.K) a = A.in[a_base + kk];
+        if (r_ok && kk < A.K) a = A.in[a_base + ((uint64_t)kk << A.ksh)];
         if (c_ok && kk < A.K) b = A.trans ? A.U[(uint64_t)kk * A.N + c] : A.U[(uint64_t)c * A.K + kk];
         acc_re = M_::mfma(a.x, b.x, acc_re);
         acc_re = M_::mfma(-a.y, csgn * b.y, acc_re);
@@ -181,20 +184,20 @@ __global__ __launch_bounds__(256) void k_cgemm_w(GemmArgs<R> A) {
 
 template <typename R>
 __global__ void k_scatter_rows(cvec<R> *__restrict__ psi, const cvec<R> *__restrict__ src, uint64_t M, int mbits,
-                               uint64_t row_mask, uint64_t row_fix) {
+                               uint64_t row_mask, uint64_t row_fix, int ksh) {
     const uint64_t total = M << mbits;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t cm = (1ull << mbits) - 1ull;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const uint64_t r = i >> mbits;
-        psi[(pdep64(r, row_mask) | row_fix) + (i & cm)] = src[i];
+        psi[(pdep64(r, row_mask) | row_fix) + ((i & cm) << ksh)] = src[i];
     }
 }
 
 // host: Out(M x N) = rows(In) * B, with B as described in GemmArgs
 template <typename R>
-sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N, int K,
-                uint64_t row_mask, uint64_t row_fix, int trans, int conjb) {
+static sv_status cgemm_ks(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N,
+                          int K, uint64_t row_mask, uint64_t row_fix, int ksh, int trans, int conjb) {
     GemmArgs<R> a;
     a.in = in;
     a.out = out;
@@ -204,6 +207,7 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
     a.K = K;
     a.row_mask = row_mask;
     a.row_fix = row_fix;
+    a.ksh = ksh;
     a.trans = trans;
     a.conjb = conjb;
     const uint64_t gm = (M + GBM - 1) / GBM;
@@ -216,7 +220,8 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
     // out of place, so it can be run twice), cached; without tuning, the
     // wavefront tiles wherever the workgroup tiles would not fill the chip.
     const std::string key = std::string("cgemm/") + (sizeof(R) == 4 ? "c64/" : "c128/") + std::to_string(M) + "/" +
-                            std::to_string(N) + "/" + std::to_string(K) + "/" + std::to_string(trans);
+                            std::to_string(N) + "/" + std::to_string(K) + "/" + std::to_string(trans) +
+                            (ksh ? "/s" + std::to_string(ksh) : std::string());
     auto launch = [&](int shape) -> sv_status {
         TraceScope _ts(st, "cgemm", ((double)M * (N + K) + (double)N * K) * sizeof(cvec<R>), 8.0 * (double)M * N * K);
         if (shape == 1) {
@@ -246,33 +251,46 @@ sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *
     }
     return launch(shape);
 }
+
+template <typename R>
+sv_status cgemm(hipStream_t st, const cvec<R> *in, cvec<R> *out, const cvec<R> *U, uint64_t M, int N, int K,
+                uint64_t row_mask, uint64_t row_fix, int trans, int conjb) {
+    return cgemm_ks<R>(st, in, out, U, M, N, K, row_mask, row_fix, 0, trans, conjb);
+}
 template sv_status cgemm<float>(hipStream_t, const float2 *, float2 *, const float2 *, uint64_t, int, int, uint64_t,
                                 uint64_t, int, int);
 template sv_status cgemm<double>(hipStream_t, const double2 *, double2 *, const double2 *, uint64_t, int, int,
                                  uint64_t, uint64_t, int, int);
 
+// the register [lo, lo + m), controls cmask fixed to cval
 template <typename R>
-sv_status ctrl_mask_unitary_impl(sv_state s, const cvec<R> *U, int m, uint64_t cmask, uint64_t cval, int adjoint) {
+static sv_status ctrl_mask_unitary_at(sv_state s, const cvec<R> *U, int lo, int m, uint64_t cmask, uint64_t cval,
+                                      int adjoint) {
     const uint64_t all = (s->n >= 64) ? ~0ull : ((1ull << s->n) - 1ull);
     // rows: every value of the bits outside the register and the controls,
     // with the controls fixed to cval
-    const uint64_t row_mask = all & ~((1ull << m) - 1ull) & ~cmask;
+    const uint64_t row_mask = all & ~(((1ull << m) - 1ull) << lo) & ~cmask;
     const uint64_t row_fix = cval & cmask;
     const uint64_t M = dim_of(popcount64(row_mask));
     const int N = 1 << m;
     SV_TRY(ensure_scratch(s, (size_t)M * N * sizeof(cvec<R>)));
     cvec<R> *out = (cvec<R> *)s->scratch;
-    SV_TRY(cgemm<R>(s->stream, (const cvec<R> *)s->data, out, U, M, N, N, row_mask, row_fix, adjoint, adjoint));
+    SV_TRY(cgemm_ks<R>(s->stream, (const cvec<R> *)s->data, out, U, M, N, N, row_mask, row_fix, lo, adjoint, adjoint));
     const uint64_t total = M * (uint64_t)N;
     uint64_t g = (total + 1023) / 1024;
     if (g > (1u << 20)) g = 1u << 20;
     {
         TraceScope _ts(s->stream, "scatter_rows", 2.0 * (double)total * sizeof(cvec<R>), 0.0);
         hipLaunchKernelGGL(k_scatter_rows<R>, dim3((unsigned)g), dim3(256), 0, s->stream, (cvec<R> *)s->data,
-                       (const cvec<R> *)out, M, m, row_mask, row_fix);
+                       (const cvec<R> *)out, M, m, row_mask, row_fix, lo);
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
+}
+
+template <typename R>
+sv_status ctrl_mask_unitary_impl(sv_state s, const cvec<R> *U, int m, uint64_t cmask, uint64_t cval, int adjoint) {
+    return ctrl_mask_unitary_at<R>(s, U, 0, m, cmask, cval, adjoint);
 }
 template sv_status ctrl_mask_unitary_impl<float>(sv_state, const float2 *, int, uint64_t, uint64_t, int);
 template sv_status ctrl_mask_unitary_impl<double>(sv_state, const double2 *, int, uint64_t, uint64_t, int);
@@ -296,8 +314,9 @@ extern "C" sv_status sv_apply_ctrl_unitary(sv_state s, const void *U, int sys_lo
     if (!U) return fail(SV_EINVAL, "U is NULL");
     if (m < 1 || sys_lo < 0 || sys_lo + m > s->n) return fail(SV_EINVAL, "register [%d,%d) outside the state", sys_lo, sys_lo + m);
     if (ctrl >= s->n || (ctrl >= sys_lo && ctrl < sys_lo + m)) return fail(SV_EINVAL, "control %d invalid", ctrl);
-    if (sys_lo != 0) return fail(SV_EUNSUPPORTED, "only sys_lo == 0 is implemented");
     if (m > 16) return fail(SV_EUNSUPPORTED, "dense register of %d qubits", m);
-    if (s->dt == SV_C64) return ctrl_unitary_impl<float>(s, (const float2 *)U, m, ctrl, ctrl_val, adjoint ? 1 : 0);
-    return ctrl_unitary_impl<double>(s, (const double2 *)U, m, ctrl, ctrl_val, adjoint ? 1 : 0);
+    const uint64_t cm = ctrl >= 0 ? 1ull << ctrl : 0ull, cv = ctrl_val ? cm : 0ull;
+    if (s->dt == SV_C64)
+        return ctrl_mask_unitary_at<float>(s, (const float2 *)U, sys_lo, m, cm, cv, adjoint ? 1 : 0);
+    return ctrl_mask_unitary_at<double>(s, (const double2 *)U, sys_lo, m, cm, cv, adjoint ? 1 : 0);
 }

@@ -45,10 +45,14 @@ def _dev_matrix(U, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("n,m,ctrl,cval", [(6, 1, 3, 1), (9, 4, 8, 0), (12, 6, -1, 1), (14, 8, 10, 1),
-                                           (11, 10, 10, 1), (13, 5, 12, 1), (22, 10, 21, 1)])
-def test_ctrl_unitary_matches_oracle(dt, n, m, ctrl, cval):
-    rng = np.random.default_rng(50 + n + m)
+@pytest.mark.parametrize("n,lo,m,ctrl,cval", [(6, 0, 1, 3, 1), (9, 0, 4, 8, 0), (12, 0, 6, -1, 1), (14, 0, 8, 10, 1),
+                                              (11, 0, 10, 10, 1), (13, 0, 5, 12, 1), (22, 0, 10, 21, 1),
+                                              (9, 2, 4, 8, 0), (12, 3, 6, 0, 1), (14, 5, 8, -1, 1),
+                                              (13, 1, 5, 12, 1), (17, 7, 9, 3, 1), (22, 6, 10, 21, 1)])
+def test_ctrl_unitary_matches_oracle(dt, n, lo, m, ctrl, cval):
+    """the register at the bottom of the state (contiguous rows) and above
+    it (rows strided by 2^lo, controls below or above the register)"""
+    rng = np.random.default_rng(50 + n + m + 7 * lo)
     U = inputs.random_unitary(rng, 1 << m)
     Ur = U.astype(np.complex64).astype(np.complex128) if dt == "c64" else U
     psi0 = inputs.random_state(rng, n)
@@ -56,10 +60,10 @@ def test_ctrl_unitary_matches_oracle(dt, n, m, ctrl, cval):
         psi0 = psi0.astype(np.complex64).astype(np.complex128)
     dU = _dev_matrix(U, dt)
     for adjoint in (False, True):
-        ref = oracle.apply_ctrl_unitary(psi0.copy(), Ur, 0, m, ctrl, cval, adjoint)
+        ref = oracle.apply_ctrl_unitary(psi0.copy(), Ur, lo, m, ctrl, cval, adjoint)
         s = B.State(n, dt)
         s.set(psi0)
-        B.sv_apply_ctrl_unitary(s.h, dU, 0, m, ctrl, cval, adjoint)
+        B.sv_apply_ctrl_unitary(s.h, dU, lo, m, ctrl, cval, adjoint)
         assert np.abs(s.get() - ref).max() <= TOL[dt]
 
 
