@@ -51,7 +51,7 @@ struct ROp {
     int j0, j1;            // register bits of the target(s)
     uint32_t rmask, rval;  // condition on the register index
     uint32_t tmask, tval;  // condition on the tile bits outside the segment's set
-    uint32_t pad;
+    uint32_t onm;          // bit m set: register index m meets the register condition
     uint64_t gmask, gval;  // condition on non-local bits
     double u[8];           // OP_U matrix; OP_PHASE: (cos, sin) of the phase in u[0], u[1]
 };
@@ -59,8 +59,9 @@ struct ROp {
 constexpr int MAX_RB = 5;
 
 struct FSeg {
-    int pos[MAX_RB];       // tile positions held in registers (register bit i = pos[i])
+    int pos[MAX_RB];       // tile positions held in registers (register bit i = pos[i]), ascending
     int nops, op_off;
+    uint32_t off[1 << MAX_RB];   // LDS byte offset of register index m: swz of its tile bits x amplitude size
 };
 
 struct FPass {
@@ -84,14 +85,17 @@ __device__ __forceinline__ uint32_t insert0(uint32_t p, int pos) {
     return ((p >> pos) << (pos + 1)) | (p & ((1u << pos) - 1u));
 }
 
-// LDS slot of tile coordinate t: the bank index (low log2(256 B / elem) bits)
-// is XOR-ed with the folded higher bits
-template <typename R>
-__device__ __forceinline__ uint32_t swz(uint32_t t) {
-    constexpr int e = sizeof(cvec<R>) == 8 ? 5 : 4;
-    constexpr uint32_t m = (1u << e) - 1u;
+// LDS slot of tile coordinate t: the bank index (the low e = log2(256 B /
+// elem) bits) is XOR-ed with the folded higher bits.  The segment tables
+// are built on the host with the same function.
+__host__ __device__ __forceinline__ uint32_t swz_e(uint32_t t, int e) {
+    const uint32_t m = (1u << e) - 1u;
     const uint32_t h = t >> e;
     return t ^ ((h ^ (h >> e) ^ (h >> (2 * e))) & m);
+}
+template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t t) {
+    return swz_e(t, sizeof(cvec<R>) == 8 ? 5 : 4);
 }
 
 __device__ __forceinline__ uint32_t pdep32(uint32_t v, uint32_t mask) {
@@ -109,15 +113,15 @@ __device__ __forceinline__ cvec<R> csel(bool c, cvec<R> a, cvec<R> b) {
     return cmake<R>(c ? a.x : b.x, c ? a.y : b.y);
 }
 
-// the register-bit condition of an op is uniform: without one every pair is
-// updated (no branches, so the pairs interleave); with one, results are
-// selected per pair
+// The register-bit condition of an op is uniform.  Without one every pair
+// is updated (no branches, so the pairs interleave); with one, a uniform
+// branch per pair (on the op's precomputed mask of the register indices
+// that meet it) skips the pairs it leaves alone.
 template <typename R, int RB, int J>
 __device__ __forceinline__ void reg_u(cvec<R> (&v)[1 << RB], const ROp &f) {
     const cvec<R> u00 = cmake<R>((R)f.u[0], (R)f.u[1]), u01 = cmake<R>((R)f.u[2], (R)f.u[3]);
     const cvec<R> u10 = cmake<R>((R)f.u[4], (R)f.u[5]), u11 = cmake<R>((R)f.u[6], (R)f.u[7]);
-    const uint32_t rm = f.rmask, rv = f.rval;
-    if (rm == 0) {
+    if (f.rmask == 0) {
 #pragma unroll
         for (int m = 0; m < (1 << RB); ++m) {
             if (m & (1 << J)) continue;
@@ -126,40 +130,38 @@ __device__ __forceinline__ void reg_u(cvec<R> (&v)[1 << RB], const ROp &f) {
             v[m | (1 << J)] = cmac2<R>(u10, a0, u11, a1);
         }
     } else {
+        const uint32_t on = f.onm;
 #pragma unroll
         for (int m = 0; m < (1 << RB); ++m) {
             if (m & (1 << J)) continue;
-            const bool on = (m & rm) == rv;
+            if (!(on >> m & 1u)) continue;
             const cvec<R> a0 = v[m], a1 = v[m | (1 << J)];
-            const cvec<R> b0 = cmac2<R>(u00, a0, u01, a1), b1 = cmac2<R>(u10, a0, u11, a1);
-            v[m] = csel<R>(on, b0, a0);
-            v[m | (1 << J)] = csel<R>(on, b1, a1);
+            v[m] = cmac2<R>(u00, a0, u01, a1);
+            v[m | (1 << J)] = cmac2<R>(u10, a0, u11, a1);
         }
     }
 }
 
 template <typename R, int RB, int J>
 __device__ __forceinline__ void reg_x(cvec<R> (&v)[1 << RB], const ROp &f) {
-    const uint32_t rm = f.rmask, rv = f.rval;
+    const uint32_t on = f.onm;
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) {
         if (m & (1 << J)) continue;
-        const bool on = (m & rm) == rv;
-        const cvec<R> a0 = v[m], a1 = v[m | (1 << J)];
-        v[m] = csel<R>(on, a1, a0);
-        v[m | (1 << J)] = csel<R>(on, a0, a1);
+        if (!(on >> m & 1u)) continue;
+        const cvec<R> a0 = v[m];
+        v[m] = v[m | (1 << J)];
+        v[m | (1 << J)] = a0;
     }
 }
 
 template <typename R, int RB>
 __device__ __forceinline__ void reg_phase(cvec<R> (&v)[1 << RB], const ROp &f) {
     const cvec<R> ph = cmake<R>((R)f.u[0], (R)f.u[1]);
-    const uint32_t rm = f.rmask, rv = f.rval;
+    const uint32_t on = f.onm;
 #pragma unroll
-    for (int m = 0; m < (1 << RB); ++m) {
-        const cvec<R> p = cmul<R>(v[m], ph);
-        v[m] = csel<R>((m & rm) == rv, p, v[m]);
-    }
+    for (int m = 0; m < (1 << RB); ++m)
+        if (on >> m & 1u) v[m] = cmul<R>(v[m], ph);
 }
 
 template <typename R, int RB>
@@ -201,17 +203,46 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     const int *hpos = P.hpos;
 
     // HBM -> LDS with U loads in flight per thread.  scatter_t is a bit
-    // deposit, so the thread's part (bits below log2 FUSE_BLOCK) and the
-    // uniform part of t combine by OR.
+    // deposit, so the thread's part (bits below log2 FUSE_BLOCK), the part
+    // of the unrolled index u and that of the outer step t0 combine by OR;
+    // the offsets of u's bits are formed once.
     constexpr int U = sizeof(R) == 4 ? 16 : 8;
+    constexpr int LB = 8, LU = sizeof(R) == 4 ? 4 : 3;      // log2 FUSE_BLOCK, log2 U
     const uint64_t gthr = scatter_t(threadIdx.x & (T - 1u), c, r, hpos);
+    // swz is XOR-linear too: the LDS slot of t0 + u 256 + thread is
+    // swz(thread) ^ swz(t0) ^ swz(u 256)
+    uint64_t uoff[U];
+    uint32_t uswz[U];
+    const uint32_t sthr = swz<R>(threadIdx.x);
     if (T >= FUSE_BLOCK * U) {
+        uint64_t hb[LU];
+        uint32_t hs[LU];
+#pragma unroll
+        for (int i = 0; i < LU; ++i) {
+            hb[i] = scatter_t(1u << (LB + i), c, r, hpos);
+            hs[i] = swz<R>(1u << (LB + i));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint64_t o = 0;
+            uint32_t w = 0;
+#pragma unroll
+            for (int i = 0; i < LU; ++i)
+                if (u >> i & 1) {
+                    o |= hb[i];
+                    w ^= hs[i];
+                }
+            uoff[u] = o;
+            uswz[u] = w;
+        }
         for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
+            const uint32_t s0 = sthr ^ swz<R>(t0);
             cvec<R> buf[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) buf[u] = psi[base | gthr | scatter_t(t0 + u * FUSE_BLOCK, c, r, hpos)];
+            for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff[u]];
 #pragma unroll
-            for (int u = 0; u < U; ++u) tile[swz<R>(t0 + u * FUSE_BLOCK + threadIdx.x)] = buf[u];
+            for (int u = 0; u < U; ++u) tile[s0 ^ uswz[u]] = buf[u];
         }
     } else {
         for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
@@ -221,45 +252,44 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     const uint32_t lines = T >> RB;                  // register lines per tile
     for (int sg = 0; sg < P.nseg; ++sg) {
         const FSeg &S = segs[P.seg_off + sg];
-        uint32_t smask = 0;
-#pragma unroll
-        for (int i = 0; i < RB; ++i) smask |= 1u << S.pos[i];
-        // swz is XOR-linear and bt, off[m] have disjoint bits, so the slot of
-        // bt | off[m] is swz(bt) ^ swz(off[m]) (the second part is uniform)
+        // swz is XOR-linear and bt and the register bits are disjoint, so the
+        // slot of bt | (bits of m) is swz(bt) ^ S.off[m] (the table is uniform,
+        // in bytes, as the slot is used)
+        unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
         uint32_t off[1 << RB];
 #pragma unroll
-        for (int m = 0; m < (1 << RB); ++m) {
-            uint32_t o = 0;
-#pragma unroll
-            for (int i = 0; i < RB; ++i)
-                if (m >> i & 1) o |= 1u << S.pos[i];
-            off[m] = swz<R>(o);
-        }
+        for (int m = 0; m < (1 << RB); ++m) off[m] = S.off[m];
         const ROp *op0 = ops + S.op_off;
         for (uint32_t line = threadIdx.x; line < lines; line += FUSE_BLOCK) {
-            const uint32_t bt = pdep32(line, (T - 1u) & ~smask);
-            const uint32_t sbt = swz<R>(bt);
+            // the tile bits outside the register positions: the line index
+            // with a zero inserted at each position, lowest first
+            uint32_t bt = line;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) bt = insert0(bt, S.pos[i]);
+            const uint32_t sbt = swz<R>(bt) * (uint32_t)sizeof(cvec<R>);
             cvec<R> v[1 << RB];
 #pragma unroll
-            for (int m = 0; m < (1 << RB); ++m) v[m] = tile[sbt ^ off[m]];
+            for (int m = 0; m < (1 << RB); ++m) v[m] = *reinterpret_cast<const cvec<R> *>(tb + (sbt ^ off[m]));
             for (int o = 0; o < S.nops; ++o) {
                 const ROp &f = op0[o];
                 if ((base & f.gmask) != f.gval || (bt & f.tmask) != f.tval) continue;
                 reg_apply<R, RB>(v, f);
             }
 #pragma unroll
-            for (int m = 0; m < (1 << RB); ++m) tile[sbt ^ off[m]] = v[m];
+            for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ off[m])) = v[m];
         }
         __syncthreads();
     }
 
     if (T >= FUSE_BLOCK * U) {
         for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
+            const uint32_t s0 = sthr ^ swz<R>(t0);
             cvec<R> buf[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) buf[u] = tile[swz<R>(t0 + u * FUSE_BLOCK + threadIdx.x)];
+            for (int u = 0; u < U; ++u) buf[u] = tile[s0 ^ uswz[u]];
 #pragma unroll
-            for (int u = 0; u < U; ++u) psi[base | gthr | scatter_t(t0 + u * FUSE_BLOCK, c, r, hpos)] = buf[u];
+            for (int u = 0; u < U; ++u) psi[g0 | uoff[u]] = buf[u];
         }
     } else {
         for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
@@ -585,11 +615,19 @@ static uint32_t compress_bits(uint32_t x, uint32_t S) {   // tile bits in S -> r
     return r;
 }
 
+// bit m set for the register indices m < 2^RB with (m & rmask) == rval
+static uint32_t on_mask(uint32_t rmask, uint32_t rval, int RB) {
+    uint32_t on = 0;
+    for (uint32_t m = 0; m < (1u << RB); ++m)
+        if ((m & rmask) == rval) on |= 1u << m;
+    return on;
+}
+
 // cut a pass's gate list into register segments of at most RB target
 // positions.  Gates that touch disjoint qubits commute, so a segment takes
 // every gate that is ready (all earlier gates it does not commute with are
 // placed) and whose targets fit, in program order, not only a contiguous run.
-static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, std::vector<ROp> &rops) {
+static void segment_pass(const HostPass &hp, int RB, int swz_bits, std::vector<FSeg> &segs, std::vector<ROp> &rops) {
     const int k = hp.hdr.k;
     const std::vector<FOp> &ops = hp.ops;
     const size_t n = ops.size();
@@ -634,6 +672,12 @@ static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, st
         int npos = 0;
         for (int p = 0; p < k; ++p)
             if (S >> p & 1) g.pos[npos++] = p;
+        for (int m = 0; m < (1 << RB); ++m) {
+            uint32_t o = 0;
+            for (int i = 0; i < RB; ++i)
+                if (m >> i & 1) o |= 1u << g.pos[i];
+            g.off[m] = swz_e(o, swz_bits) * (swz_bits == 5 ? 8u : 16u);   // bytes
+        }
         g.op_off = (int)rops.size();
         g.nops = (int)seg.size();
         for (int q : seg) {
@@ -647,6 +691,7 @@ static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, st
             o.rval = compress_bits((uint32_t)f.lval & S, S);
             o.tmask = (uint32_t)f.lmask & ~S;
             o.tval = (uint32_t)f.lval & ~S;
+            o.onm = on_mask(o.rmask, o.rval, RB);
             o.gmask = f.gmask;
             o.gval = f.gval;
             if (f.type == OP_PHASE) {
@@ -668,6 +713,7 @@ static void segment_pass(const HostPass &hp, int RB, std::vector<FSeg> &segs, st
                     x.j1 = 0;
                     x.rmask = o.rmask | (1u << ctl);
                     x.rval = o.rval | (1u << ctl);
+                    x.onm = on_mask(x.rmask, x.rval, RB);
                     rops.push_back(x);
                 }
                 g.nops += 2;
@@ -706,7 +752,7 @@ static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
     for (auto &p : passes) {
         if (p.hdr.k < RB) return fail(SV_EDEVICE, "pass with %d local qubits (< %d)", p.hdr.k, RB);
         p.hdr.seg_off = (int)segs.size();
-        segment_pass(p, RB, segs, rops);
+        segment_pass(p, RB, sizeof(R) == 4 ? 5 : 4, segs, rops);
         p.hdr.nseg = (int)segs.size() - p.hdr.seg_off;
     }
     const size_t hbytes = passes.size() * sizeof(FPass);
