@@ -643,7 +643,7 @@ def main():
                         f"{args.sweep_replays} replays after 3 warm-ups", "solves_per_s": nsol / el,
                         "launch_form": "work_queue" if chosen == 1 else "side_streams",
                         "launch_form_choice": {"eager_ms_side_streams": ms_s, "eager_ms_work_queue": ms_q,
-                                               "rule": "the faster of three timed eager runs each, at prepare"},
+                                               "rule": "the faster of one timed eager run each, at prepare (cached per mix of shape classes)"},
                         "forms": forms,
                         "algorithmic_bytes": alg,
                         "roofline": {"bound": "hbm", "achieved": alg / el / 1e9, "peak": 8000.0, "unit": "GB/s",

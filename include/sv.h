@@ -603,8 +603,12 @@ typedef struct sv_batch_s *sv_batch;
  * shape class (autotuned on first use), and the captured graph.  All inputs
  * are copied; the caller's arrays may be freed on return.  hip_stream NULL:
  * the batch creates and owns a stream.  The launch form is the faster of
- * the two in three timed eager runs each, unless the environment variable
- * SV_BATCH_QUEUE is 1 (the work queues) or 0 (the side streams).  The queue
+ * the two in one timed eager run each (after an untimed one), remembered in
+ * the tuning cache under key "batchform/<c64|c128>/<n_s>.<n_c>x<solves>/..."
+ * (one entry per shape class, in increasing (n_s, n_c)); with autotuning
+ * off (SV_AUTOTUNE=0) and no cached choice, the side streams.  The
+ * environment variable SV_BATCH_QUEUE = 1 (the work queues) or 0 (the side
+ * streams) overrides both.  The queue
  * kernel serves one queue per XCC with that XCC's blocks, so the producers
  * and consumers of a solve share one L2; a dependency wait is bounded (a
  * quarter second), and an expired wait or an undrained queue makes
@@ -626,7 +630,8 @@ sv_status sv_batch_run(sv_batch b, int use_graph, double *results);
 int sv_batch_num_solves(sv_batch b);
 /* The batch's launch form: 1 the work-queue kernel, 0 the side streams, -1
  * for a NULL batch.  ms_streams / ms_queue (may be NULL): the eager run
- * times of the two forms measured at prepare (0 when not timed). */
+ * times of the two forms measured at prepare (0 when not timed: pinned,
+ * cached, or tuning off). */
 int sv_batch_form(sv_batch b, float *ms_streams, float *ms_queue);
 sv_status sv_batch_free(sv_batch b);
 

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <map>
+#include <string>
 #include <vector>
 
 #include "sv_device.h"
@@ -441,20 +442,32 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
             load[best] += wgt[ci];
         }
     }
-    // the launch form: as asked, or the faster of three timed eager runs each
-    // (after an untimed one)
+    // the launch form: as asked; else the cached choice for this mix of
+    // shape classes; else the faster of one timed eager run each (after an
+    // untimed one), cached; with tuning off, the side streams
     if (form >= 0 || !b->have_queue) {
         b->use_queue = form != 0 && b->have_queue;
     } else {
-        const bool tr0 = trace_set(false);
-        for (int f = 0; f < 2 && st == SV_OK; ++f) {
-            b->use_queue = f == 1;
-            auto run = [&]() { return dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b); };
-            st = time_stream(b->stream, 3, &b->form_ms[f], run);
+        std::string key = std::string("batchform/") + (dt == SV_C64 ? "c64" : "c128");
+        for (const auto &c : b->classes)
+            key += "/" + std::to_string(c.n_s) + "." + std::to_string(c.n_c) + "x" + std::to_string(c.count);
+        std::vector<int> cached;
+        if (tune_lookup(key, cached) && cached.size() == 1) {
+            b->use_queue = cached[0] == 1;
+        } else if (!autotune_enabled()) {
+            b->use_queue = false;
+        } else {
+            const bool tr0 = trace_set(false);
+            for (int f = 0; f < 2 && st == SV_OK; ++f) {
+                b->use_queue = f == 1;
+                auto run = [&]() { return dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b); };
+                st = time_stream(b->stream, 1, &b->form_ms[f], run);
+            }
+            trace_set(tr0);
+            if (st != SV_OK) return fail_del(st);
+            b->use_queue = b->form_ms[1] < b->form_ms[0];
+            tune_store(key, {b->use_queue ? 1 : 0});
         }
-        trace_set(tr0);
-        if (st != SV_OK) return fail_del(st);
-        b->use_queue = b->form_ms[1] < b->form_ms[0];
     }
     // record the whole sweep once (event tracing is paused while capturing)
     SV_HIP(hipStreamSynchronize(b->stream));

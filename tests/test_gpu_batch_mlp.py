@@ -167,15 +167,33 @@ def test_batch_queue_matches_stream_launches(dt, monkeypatch):
     assert np.abs(queue[:, 3] - streams[:, 3]).max() <= (1e-11 if dt == "c128" else 1e-4)
 
 
+def _form_key(probs, dt):
+    """the tuning-cache key of a batch's launch form (one entry per (n_s, n_c)
+    shape class, in increasing order, with its number of solves)"""
+    cls = {}
+    for A, b, n_c, t0 in probs:
+        k = (A.shape[0].bit_length() - 1, n_c)
+        cls[k] = cls.get(k, 0) + len(t0)
+    return f"batchform/{dt}" + "".join(f"/{n_s}.{n_c}x{c}" for (n_s, n_c), c in sorted(cls.items()))
+
+
 def test_batch_form_is_timed_or_forced(monkeypatch):
     probs = _batch_problems()
     monkeypatch.delenv("SV_BATCH_QUEUE", raising=False)
+    key = _form_key(probs, "c64")
+    B.sv_tune_set(key, ())                 # forget a choice an earlier test made
     h = B.sv_batch_prepare(probs, "c64")
     try:
         f, ms_s, ms_q = B.sv_batch_form(h)
         assert ms_s > 0 and ms_q > 0
         assert f == (1 if ms_q < ms_s else 0)
         auto = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    # the choice is cached: a second prepare of the same mix does not time
+    h = B.sv_batch_prepare(probs, "c64")
+    try:
+        assert B.sv_batch_form(h) == (f, 0.0, 0.0)
     finally:
         B.sv_batch_free(h)
     monkeypatch.setenv("SV_BATCH_QUEUE", "1" if f == 0 else "0")
