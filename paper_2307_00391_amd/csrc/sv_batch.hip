@@ -111,8 +111,14 @@ struct sv_batch_s {
     hipGraphExec_t exec = nullptr;
     hipStream_t own_stream = nullptr;
     ~sv_batch_s() {
+        // a replayed graph with side-stream branches kept the batch's memory
+        // from being released unless the device was idle when the graph and
+        // then the buffers went (prepare/replay/free loops lost one arena per
+        // batch otherwise)
+        hipDeviceSynchronize();
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
+        hipDeviceSynchronize();
         for (int i = 0; i < kSide; ++i) {
             if (join[i]) hipEventDestroy(join[i]);
             if (side[i]) hipStreamDestroy(side[i]);

@@ -207,6 +207,28 @@ def test_batch_form_is_timed_or_forced(monkeypatch):
     assert np.abs(auto[:, 3] - other[:, 3]).max() <= 1e-4
 
 
+@pytest.mark.parametrize("form", ["0", "1"])
+def test_batch_free_releases_device_memory(form, monkeypatch):
+    """prepare, graph replay and free, four times over a 16-instance sweep
+    batch (about 2 GiB of states each): the device's free memory comes back
+    (the side-stream graph once held one batch's memory per round trip)"""
+    import torch
+    monkeypatch.setenv("SV_BATCH_QUEUE", form)
+    probs = [(i.A, i.b, i.n_c, i.t0) for i in inputs.sweep_instances(16)]
+    h = B.sv_batch_prepare(probs, "c64")         # first-use setup (tuning, library workspaces)
+    B.sv_batch_run(h, use_graph=True)
+    B.sv_batch_free(h)
+    torch.cuda.synchronize()
+    f0 = torch.cuda.mem_get_info()[0]
+    for _ in range(4):
+        h = B.sv_batch_prepare(probs, "c64")
+        B.sv_batch_run(h, use_graph=True)
+        B.sv_batch_free(h)
+    torch.cuda.synchronize()
+    f1 = torch.cuda.mem_get_info()[0]
+    assert f1 >= f0 - (256 << 20), (f0 / 2**30, f1 / 2**30)
+
+
 def test_batch_matches_single_solves():
     probs = _batch_problems()
     res = B.sv_hhl_batch(probs, "c128")
