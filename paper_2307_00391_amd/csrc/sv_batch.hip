@@ -201,8 +201,8 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         delete b;
         return s;
     };
-    // --- eigen-decompositions: real symmetric instances of one size in one
-    // batched call, the others one at a time
+    // --- eigen-decompositions: dense real symmetric instances of one size in
+    // one batched call, the others one at a time
     std::vector<DevBuf *> V(n_inst), lamd(n_inst), beta(n_inst), cex(n_inst);
     std::vector<std::vector<double>> lams(n_inst);
     std::map<int, std::vector<int>> real_by_n;
@@ -221,7 +221,10 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         b->bufs.push_back(cex[i]);
         bool real = true;
         for (size_t k = 0; k < (size_t)N * N && real; ++k) real = I.A[2 * k + 1] == 0.0;
-        if (real && N > 1) {
+        // dense real instances of one size share a strided-batched solve;
+        // tridiagonal ones (and complex ones) go one at a time, the
+        // tridiagonal ones to the tridiagonal divide and conquer
+        if (real && N > 1 && !is_tridiagonal(I.A, N)) {
             real_by_n[N].push_back(i);
         } else {
             st = eigh_device(&b->ctx, I.A, N, *V[i], lams[i]);

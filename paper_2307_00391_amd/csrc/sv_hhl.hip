@@ -368,15 +368,27 @@ static bool eig_residual_ok(const double *A, int N, const std::vector<double> &l
 }
 
 // Hermitian eigen-decomposition in FP64 on the device (rocSOLVER), validated
-// by eig_residual_ok.  Real symmetric input goes to the real solvers.  The
-// solvers are tried in order (divide and conquer, Jacobi, QR iteration)
+// by eig_residual_ok.  Real symmetric input goes to the real solvers, and a
+// real tridiagonal matrix first to the tridiagonal divide and conquer (no
+// reduction to tridiagonal form, which dominates the dense solvers' time).
+// The solvers are tried in order (divide and conquer, Jacobi, QR iteration)
 // until one passes the check; SV_EIGH_ORDER (comma-separated names) can
 // override the order.  dV receives V row-major (column j = eigenvector j);
 // lam ascending.
-enum EigSolver { ES_ZHEEVD, ES_ZHEEVJ, ES_ZHEEV, ES_DSYEVD, ES_DSYEVJ, ES_DSYEV };
+enum EigSolver { ES_ZHEEVD, ES_ZHEEVJ, ES_ZHEEV, ES_DSYEVD, ES_DSYEVJ, ES_DSYEV, ES_DSTEDC };
+constexpr int ES_COUNT = 7;
 static const char *es_name(int e) {
-    static const char *n[] = {"zheevd", "zheevj", "zheev", "dsyevd", "dsyevj", "dsyev"};
+    static const char *n[] = {"zheevd", "zheevj", "zheev", "dsyevd", "dsyevj", "dsyev", "dstedc"};
     return n[e];
+}
+
+// zero outside the diagonal and the first off-diagonals (real and imaginary parts)
+bool is_tridiagonal(const double *A, int N) {
+    for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c)
+            if ((c > r + 1 || r > c + 1) && (A[2 * ((size_t)r * N + c)] != 0.0 || A[2 * ((size_t)r * N + c) + 1] != 0.0))
+                return false;
+    return true;
 }
 
 static thread_local std::string g_eigh_used;
@@ -384,6 +396,7 @@ static thread_local std::string g_eigh_used;
 sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vector<double> &lam) {
     bool real = true;
     for (size_t i = 0; i < (size_t)N * N && real; ++i) real = A[2 * i + 1] == 0.0;
+    const bool tri = real && N > 1 && is_tridiagonal(A, N);
     std::vector<int> order;
     if (const char *env = getenv("SV_EIGH_ORDER")) {
         std::string e(env);
@@ -392,14 +405,23 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
             size_t q = e.find(',', pos);
             if (q == std::string::npos) q = e.size();
             std::string name = e.substr(pos, q - pos);
-            for (int k = 0; k < 6; ++k)
-                if (name == es_name(k) && (real || k < 3)) order.push_back(k);
+            for (int k = 0; k < ES_COUNT; ++k)
+                if (name == es_name(k) && (k == ES_DSTEDC ? tri : (real || k < 3))) order.push_back(k);
             pos = q + 1;
         }
     }
     if (order.empty()) {
-        if (real) order = {ES_DSYEVD, ES_DSYEVJ, ES_ZHEEVJ, ES_DSYEV};
+        if (tri) order = {ES_DSTEDC, ES_DSYEVD, ES_DSYEVJ, ES_ZHEEVJ, ES_DSYEV};
+        else if (real) order = {ES_DSYEVD, ES_DSYEVJ, ES_ZHEEVJ, ES_DSYEV};
         else order = {ES_ZHEEVD, ES_ZHEEVJ, ES_ZHEEV};
+    }
+    // the tridiagonal solver's input: the diagonal and the off-diagonal
+    std::vector<double> td, te;
+    if (tri) {
+        td.resize(N);
+        te.assign(N, 0.0);
+        for (int i = 0; i < N; ++i) td[i] = A[2 * ((size_t)i * N + i)];
+        for (int i = 0; i + 1 < N; ++i) te[i] = A[2 * ((size_t)i * N + i + 1)];
     }
     // rocSOLVER is column-major: the row-major conj(A) is A in column-major order
     std::vector<double> Ac(2 * (size_t)N * N), Ar;
@@ -427,8 +449,14 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
     std::string tried;
     for (int e : order) {
         const bool rs_real = e >= ES_DSYEVD;
-        if (rs_real) SV_TRY(upload(s, dA.p, Ar.data(), Ar.size() * sizeof(double)));
-        else SV_TRY(upload(s, dA.p, Ac.data(), Ac.size() * sizeof(double)));
+        if (e == ES_DSTEDC) {
+            SV_TRY(upload(s, dD.p, td.data(), N * sizeof(double)));
+            SV_TRY(upload(s, dE.p, te.data(), N * sizeof(double)));
+        } else if (rs_real) {
+            SV_TRY(upload(s, dA.p, Ar.data(), Ar.size() * sizeof(double)));
+        } else {
+            SV_TRY(upload(s, dA.p, Ac.data(), Ac.size() * sizeof(double)));
+        }
         rocblas_double_complex *zA = (rocblas_double_complex *)dA.p;
         double *rA = (double *)dA.p, *D = (double *)dD.p, *E = (double *)dE.p;
         rocblas_int *info_p = (rocblas_int *)dInfo.p;
@@ -445,6 +473,9 @@ sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vecto
         case ES_DSYEVJ:
             rs = rocsolver_dsyevj(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, N, rA, N, 0.0,
                                   (double *)dRes.p, 100, (rocblas_int *)dSweeps.p, D, info_p);
+            break;
+        case ES_DSTEDC:   // eigenvectors of the tridiagonal matrix itself, column-major into dA
+            rs = rocsolver_dstedc(h, rocblas_evect_tridiagonal, N, D, E, rA, N, info_p);
             break;
         }
         tried += std::string(tried.empty() ? "" : ",") + es_name(e);

@@ -161,6 +161,7 @@ struct EigFrame {
 };
 
 sv_status check_hermitian(const double *A, int N, const char *name);
+bool is_tridiagonal(const double *A, int N);
 sv_status eigh_device(sv_state s, const double *A, int N, DevBuf &dV, std::vector<double> &lam);
 sv_status eigh_device_batched(sv_state s, const std::vector<const double *> &As, int N, std::vector<DevBuf *> &dVs,
                               std::vector<std::vector<double>> &lams);

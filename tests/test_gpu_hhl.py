@@ -299,3 +299,20 @@ def test_fused_pipeline_wide_clock_shapes(n_s, n_c):
         _relative_checks(x, x_r, res.p_post, pp_r, dt)
         assert np.abs(x - x_r).max() <= (1e-5 if dt == "c64" else 1e-12)
         assert abs(res.norm_total - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
+
+
+def test_tridiagonal_operator_uses_the_tridiagonal_eigensolver():
+    """A real tridiagonal A goes to rocSOLVER's tridiagonal divide and
+    conquer; the solution still matches the oracle (Poiseuille, 16 points)."""
+    s = inputs.poiseuille(16)
+    n_c = 6
+    T0 = inputs.t0_top_of_clock(s.lambda_max, n_c)
+    st = B.State(4 + n_c + 1, "c128")
+    try:
+        x, r = B.sv_hhl(st.h, s.A, s.b, n_c, T0, 1)
+    finally:
+        st.close()
+    assert B.sv_last_eigensolver() == "dstedc"
+    psi, xr, p_post, p_anc = oracle.hhl(s.A, s.b, n_c, T0)
+    assert abs(r.p_post - p_post) <= 1e-12
+    assert np.abs(x - xr).max() <= 1e-10
