@@ -612,7 +612,9 @@ typedef struct sv_batch_s *sv_batch;
  * kernel serves one queue per XCC with that XCC's blocks, so the producers
  * and consumers of a solve share one L2; a dependency wait is bounded (a
  * quarter second), and an expired wait or an undrained queue makes
- * sv_batch_run fail with SV_EDEVICE instead of hanging.  In the stream form
+ * sv_batch_run fail with SV_EDEVICE instead of hanging.  SV_QUEUE_LOCAL=0
+ * forces a single queue for all blocks with device-scope synchronisation
+ * (the fallback for an XCC layout the probe does not recognise).  In the stream form
  * the shape classes run on four side streams of default priority that the
  * batch owns, forked from and joined back into its stream (parallel branches
  * of the graph).  Either way the batch's work stays ordered on its stream.

@@ -1293,7 +1293,10 @@ sv_status pipe_queue_build(sv_state ctx, hipStream_t st, PipeQueue &q, DevBuf &d
         }
     }
     const int D = (int)distinct.size();
-    bool even = D >= 1 && D <= kMaxQueues;
+    // SV_QUEUE_LOCAL=0 forces the single queue with device-scope
+    // synchronisation (the fallback), so that it can be tested on any box
+    const char *lenv = getenv("SV_QUEUE_LOCAL");
+    bool even = D >= 1 && D <= kMaxQueues && !(lenv && atoi(lenv) == 0);
     for (int i = 0; i < D && even; ++i) even = distinct[i] >= 0 && distinct[i] < 16 && count[i] * D >= q.blocks / 2;
     if (even) {
         std::sort(distinct.begin(), distinct.end());

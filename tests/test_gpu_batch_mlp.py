@@ -177,6 +177,20 @@ def _form_key(probs, dt):
     return f"batchform/{dt}" + "".join(f"/{n_s}.{n_c}x{c}" for (n_s, n_c), c in sorted(cls.items()))
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_queue_device_scope_fallback(dt, monkeypatch):
+    """SV_QUEUE_LOCAL=0: one queue for all blocks with device-scope release
+    and acquire per item (what the kernel falls back to when the XCCs are not
+    probed as expected) against the per-XCC queues, bit for bit: the same
+    items, tiles and partial slots, only the synchronisation differs."""
+    probs = _batch_problems() + _wide_problems()
+    monkeypatch.setenv("SV_BATCH_QUEUE", "1")
+    local = B.sv_hhl_batch(probs, dt)
+    monkeypatch.setenv("SV_QUEUE_LOCAL", "0")
+    shared = B.sv_hhl_batch(probs, dt)
+    assert np.array_equal(local, shared)
+
+
 def test_batch_form_is_timed_or_forced(monkeypatch):
     probs = _batch_problems()
     monkeypatch.delenv("SV_BATCH_QUEUE", raising=False)
