@@ -83,6 +83,22 @@ __device__ __forceinline__ void gst(cvec<R> *p, uint64_t i, cvec<R> v) {
     ((gptr<v2_t<R>>)p)[i] = x;
 }
 
+// non-temporal forms for the ancilla = 1 half, written by k_pipe_b and read
+// back only by k_pipe_c after every tile is written: far more than the L2
+// and MALL hold, so they are streamed (the nt bit) instead of cached
+template <typename R>
+__device__ __forceinline__ void gst_nt(cvec<R> *p, uint64_t i, cvec<R> v) {
+    v2_t<R> x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, &((gptr<v2_t<R>>)p)[i]);
+}
+template <typename R>
+__device__ __forceinline__ cvec<R> gld_nt(const cvec<R> *p, uint64_t i) {
+    const v2_t<R> x = __builtin_nontemporal_load(&((gptr<const v2_t<R>>)p)[i]);
+    return cmake<R>(x.x, x.y);
+}
+
 // the solve of this block: the kernel argument, or entry blockIdx.z of a batch
 __device__ __forceinline__ PipeSolve solve_of(const PipeSolve &one, const PipeSolve *many) {
     if (!many) return one;
@@ -485,7 +501,7 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
             const uint64_t ks = 1ull << (g1 + A.n_s);
 #pragma unroll
-            for (int k = 0; k < (1 << RA); ++k) gst<R>(p, k * ks, v[k]);
+            for (int k = 0; k < (1 << RA); ++k) gst_nt<R>(p, k * ks, v[k]);
         }
         j0 += jstep;
         // the next tile's phase B rewrites the tile this one has just read
@@ -560,7 +576,7 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
     if ((int)threadIdx.x < nlb) {
         const cvec<R> *p = psi + (lrow + j0);
 #pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
+        for (int k = 0; k < (1 << RB); ++k) v0[k] = gld_nt<R>(p, k * ks);
     }
     fill_twiddles<R>(TW, G, 0, 0);
     fill_pair_twiddles<R>(TT, G, 0, 0);
@@ -597,7 +613,7 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
             } else {
                 const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
 #pragma unroll
-                for (int k = 0; k < (1 << RB); ++k) v[k] = gld<R>(p, k * ks);
+                for (int k = 0; k < (1 << RB); ++k) v[k] = gld_nt<R>(p, k * ks);
             }
             fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
                                               [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
@@ -615,7 +631,7 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
             if ((int)threadIdx.x < nlb) {
                 const cvec<R> *p = psi + (lrow + jn);
 #pragma unroll
-                for (int k = 0; k < (1 << RB); ++k) v0[k] = gld<R>(p, k * ks);
+                for (int k = 0; k < (1 << RB); ++k) v0[k] = gld_nt<R>(p, k * ks);
             }
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
