@@ -642,8 +642,9 @@ def main():
         out["sweep"] = {"instances": ni, "solves": nsol, "graph_replay_s": el, "replay_timing": "median of "
                         f"{args.sweep_replays} replays after 3 warm-ups", "solves_per_s": nsol / el,
                         "launch_form": "work_queue" if chosen == 1 else "side_streams",
-                        "launch_form_choice": {"eager_ms_side_streams": ms_s, "eager_ms_work_queue": ms_q,
-                                               "rule": "the faster of one timed eager run each, at prepare (cached per mix of shape classes)"},
+                        "launch_form_choice": {"replay_ms_side_streams": ms_s, "replay_ms_work_queue": ms_q,
+                                               "rule": "the faster graph replay (best of three alternating rounds of two "
+                                                       "replays each), at prepare (cached per mix of shape classes)"},
                         "forms": forms,
                         "algorithmic_bytes": alg,
                         "roofline": {"bound": "hbm", "achieved": alg / el / 1e9, "peak": 8000.0, "unit": "GB/s",

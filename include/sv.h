@@ -603,7 +603,8 @@ typedef struct sv_batch_s *sv_batch;
  * shape class (autotuned on first use), and the captured graph.  All inputs
  * are copied; the caller's arrays may be freed on return.  hip_stream NULL:
  * the batch creates and owns a stream.  The launch form is the faster of
- * the two in one timed eager run each (after an untimed one), remembered in
+ * the two in graph replays (both forms captured, replayed alternately after
+ * an untimed replay each, best of three rounds of two), remembered in
  * the tuning cache under key "batchform/<c64|c128>/<n_s>.<n_c>x<solves>/..."
  * (one entry per shape class, in increasing (n_s, n_c)); with autotuning
  * off (SV_AUTOTUNE=0) and no cached choice, the side streams.  The
@@ -631,8 +632,8 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
 sv_status sv_batch_run(sv_batch b, int use_graph, double *results);
 int sv_batch_num_solves(sv_batch b);
 /* The batch's launch form: 1 the work-queue kernel, 0 the side streams, -1
- * for a NULL batch.  ms_streams / ms_queue (may be NULL): the eager run
- * times of the two forms measured at prepare (0 when not timed: pinned,
+ * for a NULL batch.  ms_streams / ms_queue (may be NULL): the graph
+ * replay times of the two forms measured at prepare (0 when not timed: pinned,
  * cached, or tuning off). */
 int sv_batch_form(sv_batch b, float *ms_streams, float *ms_queue);
 sv_status sv_batch_free(sv_batch b);

@@ -608,7 +608,7 @@ def sv_batch_num_solves(b):
 
 def sv_batch_form(b):
     """(form, ms_streams, ms_queue): 1 = the work-queue kernel, 0 = side
-    streams; the eager times measured at prepare (0 when not timed)."""
+    streams; the graph replay times measured at prepare (0 when not timed)."""
     ms = (ctypes.c_float * 2)()
     a = ctypes.addressof(ms)
     f = int(lib().sv_batch_form(b, a, a + ctypes.sizeof(ctypes.c_float)))

@@ -95,7 +95,7 @@ struct sv_batch_s {
     // both at prepare unless SV_BATCH_QUEUE is 1 or 0
     bool use_queue = true;
     bool have_queue = false;
-    float form_ms[2] = {0.f, 0.f};           // timed eager runs: streams, queue (0: not timed)
+    float form_ms[2] = {0.f, 0.f};           // timed graph replays: streams, queue (0: not timed)
     PipeQueue queue;
     DevBuf qdesc;
     unsigned *d_cnt = nullptr;            // queue counters (cleared by the turn-table kernel)
@@ -451,9 +451,31 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
             load[best] += wgt[ci];
         }
     }
+    // record the whole sweep in a graph, in the given launch form (event
+    // tracing is paused while capturing)
+    auto capture = [&](bool q, hipGraph_t *g, hipGraphExec_t *ex) -> sv_status {
+        b->use_queue = q;
+        SV_HIP(hipStreamSynchronize(b->stream));
+        const bool tr = trace_set(false);
+        hipError_t he = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (he != hipSuccess) {
+            trace_set(tr);
+            return hip_fail(he, "hipStreamBeginCapture");
+        }
+        sv_status cs = dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b);
+        he = hipStreamEndCapture(b->stream, g);
+        trace_set(tr);
+        if (cs != SV_OK) return cs;
+        if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+        he = hipGraphInstantiate(ex, *g, nullptr, nullptr, 0);
+        if (he != hipSuccess) return hip_fail(he, "hipGraphInstantiate");
+        return SV_OK;
+    };
     // the launch form: as asked; else the cached choice for this mix of
-    // shape classes; else the faster of one timed eager run each (after an
-    // untimed one), cached; with tuning off, the side streams
+    // shape classes; else the faster graph replay (both forms captured and
+    // replayed alternately, after an untimed replay each; best of three
+    // rounds), cached; with tuning off, the side streams
+    bool timed = false;
     if (form >= 0 || !b->have_queue) {
         b->use_queue = form != 0 && b->have_queue;
     } else {
@@ -466,38 +488,41 @@ sv_status sv_batch_prepare(sv_batch *out, sv_dtype dt, void *hip_stream, const s
         } else if (!autotune_enabled()) {
             b->use_queue = false;
         } else {
+            timed = true;
+            hipGraph_t g[2] = {};
+            hipGraphExec_t ex[2] = {};
+            for (int f = 0; f < 2 && st == SV_OK; ++f) st = capture(f == 1, &g[f], &ex[f]);
             const bool tr0 = trace_set(false);
-            for (int f = 0; f < 2 && st == SV_OK; ++f) {
-                b->use_queue = f == 1;
-                auto run = [&]() { return dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b); };
-                st = time_stream(b->stream, 1, &b->form_ms[f], run);
-            }
+            for (int r = 0; r < 3 && st == SV_OK; ++r)
+                for (int f = 0; f < 2 && st == SV_OK; ++f) {
+                    float ms = 0.f;
+                    st = time_stream(b->stream, 2, &ms, [&]() -> sv_status {
+                        SV_HIP(hipGraphLaunch(ex[f], b->stream));
+                        return SV_OK;
+                    });
+                    if (st == SV_OK && (r == 0 || ms < b->form_ms[f])) b->form_ms[f] = ms;
+                }
             trace_set(tr0);
+            const int keep = st == SV_OK && b->form_ms[1] < b->form_ms[0] ? 1 : 0;
+            // the replays above must be over before a graph goes (see the
+            // destructor)
+            hipDeviceSynchronize();
+            for (int f = 0; f < 2; ++f) {
+                if (f == keep && st == SV_OK) continue;
+                if (ex[f]) hipGraphExecDestroy(ex[f]);
+                if (g[f]) hipGraphDestroy(g[f]);
+            }
             if (st != SV_OK) return fail_del(st);
-            b->use_queue = b->form_ms[1] < b->form_ms[0];
-            tune_store(key, {b->use_queue ? 1 : 0});
+            b->use_queue = keep == 1;
+            b->graph = g[keep];
+            b->exec = ex[keep];
+            tune_store(key, {keep});
         }
     }
-    // record the whole sweep once (event tracing is paused while capturing)
-    SV_HIP(hipStreamSynchronize(b->stream));
-    const bool tr = trace_set(false);
-    hipError_t he = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    if (he != hipSuccess) {
-        trace_set(tr);
-        return fail_del(hip_fail(he, "hipStreamBeginCapture"));
+    if (!timed) {
+        st = capture(b->use_queue, &b->graph, &b->exec);
+        if (st != SV_OK) return fail_del(st);
     }
-    st = dt == SV_C64 ? enqueue_batch<float>(b) : enqueue_batch<double>(b);
-    hipGraph_t g = nullptr;
-    he = hipStreamEndCapture(b->stream, &g);
-    trace_set(tr);
-    if (st != SV_OK) {
-        if (g) hipGraphDestroy(g);
-        return fail_del(st);
-    }
-    if (he != hipSuccess) return fail_del(hip_fail(he, "hipStreamEndCapture"));
-    b->graph = g;
-    he = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    if (he != hipSuccess) return fail_del(hip_fail(he, "hipGraphInstantiate"));
     *out = b;
     return SV_OK;
 }
