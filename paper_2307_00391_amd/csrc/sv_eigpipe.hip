@@ -56,8 +56,8 @@ struct PipeArgs {
     double scale;        // 2^(-n_c/2)
     int sgn;             // signed (two's-complement) clock for the inversion
     uint64_t gcut;       // 0: inversion sin = 1/y; >= 1: gapped-phase-estimation flag, sin = [|y| >= gcut]
-    int pers;            // k_pipe_b / k_pipe_c: persistent blocks (one value of the other clock
-                         // group each, iters column blocks)
+    int pers;            // persistent blocks walking iters column blocks: k_pipe_b of a single
+                         // solve (one G1 value each), and work-queue items
     int pslog, iters;    // log2 of the blocks per group value; column blocks per block
     int ccrows;          // k_pipe_a stages the G2-value phases for k_pipe_c (n_c >= 4)
 };
@@ -546,68 +546,94 @@ __global__ __launch_bounds__(NT) void k_pipe_bp(PipeArgs A, PipeSolve one, const
 // k_pipe_c: forward cascade on G1, conjugate phases, clock sum of the tile
 // (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
+// Only the clock sum of each transformed column is needed,
+//   z = sum_y ph(y) (F v)(y),
+// F the forward cascade on G1 and ph(y) = cc prod_b om_b^(y_b) the conjugate
+// phases of the uncompute, a product over the G1 bits (cc: the G2 bits').
+// Moved onto the input, z = sum_y v(y) K(y) with K the transposed cascade
+// applied to ph.  A transposed stage on bit b maps the pair (p0, p1) to
+// (p0 + t p1, p0 - t p1), t its twiddle of the bits below b; run from bit 0
+// upwards on a product state it leaves
+//   K(y) = cc prod_b (1 + (-1)^(y_b) t_b(y mod 2^b) om_b),
+// so no transform is formed.  A thread takes a line (one column, one value
+// llo of the low RA bits, the 2^RB values of the high bits), contracts it from
+// its top bit down, each step halving it,
+//   u(m) = (v(m) + v(m + h)) + q (v(m) - v(m + h)),  q = t_b(llo + m 2^RA) om_b,
+// and multiplies what is left by the factors of the low bits and cc.  The
+// threads exchange nothing but the column sums.
 // Tile: columns [j0, j0 + C) at G2 value o; persistent, A.iters column
 // blocks j0 + it 2^(pslog + cl)
 template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
     constexpr int G = RA + RB;
-    constexpr int OMR = 2;               // G1-bit phases per thread (G C <= 8 * 64 <= 2 NT)
+    constexpr int OMR = 3;               // column phases per thread ((G + 1) C <= 2 NT + C <= 3 NT)
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
-    cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
-    cvec<R> *TW = tile + ((size_t)C << G);
-    cvec<R> *TT = TW + (1 << G);                                     // radix-4 pair products
-    cvec<R> *om = TT + (1 << G);
-    cvec<R> *cc = om + G * C;
-    const size_t zoff = (((size_t)((unsigned char *)(cc + C) - smem_raw)) + 15) & ~(size_t)15;
-    double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [NT] per-thread partials
+    // LDS: the G1 twiddles, then two sets (alternate tiles) of the column
+    // phases om[G][C], cc[C] and of the threads' partial sums
+    cvec<R> *TW = reinterpret_cast<cvec<R> *>(smem_raw);
+    const int nph = (G + 1) * C;
+    cvec<R> *phs = TW + (1 << G);
+    const size_t zoff = (((size_t)((unsigned char *)(phs + 2 * nph) - smem_raw)) + 15) & ~(size_t)15;
+    double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);
     const int iters = PERS ? A.iters : 1;
     const uint64_t jstep = PERS ? 1ull << (A.pslog + A.cl) : 0;
-    const int n_c = A.n_c;
-    const int nla = C << RB, nlb = C << RA;
-    // the thread's first phase-B line is read before the tables are built, so
-    // the HBM latency overlaps that work
-    // clock index (o << G) + (k << RA) + llo: a base for the line and a stride for k
+    const int g2 = A.n_c - G;
+    const int nl = C << RA;
+    // every line of a thread has the thread's column (the line stride NT is a multiple of C)
+    const int c = threadIdx.x & (C - 1);
+    // clock index (o << G) + llo + (k << RA): a base for the line and a stride for k
     const uint64_t ks = 1ull << (RA + A.n_s);
-    const uint64_t lrow = A.abit + (((o << G) + (uint64_t)(threadIdx.x >> A.cl)) << A.n_s) + (threadIdx.x & (C - 1));
+    const uint64_t lrow = A.abit + (((o << G) + (uint64_t)(threadIdx.x >> A.cl)) << A.n_s) + c;
+    // column phase e of the tile at column j: om_b (b = e / C < G) the
+    // conjugate phase of G1 bit b, staged by k_pipe_a in row 2^G + g2 + b of
+    // the ancilla = 0 half; b = G: cc, the conjugate of the product of the
+    // phases of the G2 bits set in o (staged whole in row 2^(G+1) + o when
+    // k_pipe_a wrote those rows)
+    auto col_phase = [&](int e, uint64_t j) -> cvec<R> {
+        const int b = e / C, cq = e - b * C;
+        if (b < G) {
+            const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + j + cq);
+            return cmake<R>(w.x, -w.y);
+        }
+        if (A.ccrows) return gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + j + cq);
+        cvec<R> p = cmake<R>((R)1, (R)0);
+        for (int q = 0; q < g2; ++q)
+            if (o >> q & 1) p = cmul<R>(p, gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)q) << A.n_s) + j + cq));
+        return cmake<R>(p.x, -p.y);
+    };
+    // the thread's first line is read before the tables are built, so the
+    // HBM latency overlaps that work
     cvec<R> v0[1 << RB];
-    if ((int)threadIdx.x < nlb) {
+    if ((int)threadIdx.x < nl) {
         const cvec<R> *p = psi + (lrow + j0);
 #pragma unroll
         for (int k = 0; k < (1 << RB); ++k) v0[k] = gld_nt<R>(p, k * ks);
     }
+    for (int e = threadIdx.x; e < nph; e += NT) phs[e] = col_phase(e, j0);
     fill_twiddles<R>(TW, G, 0, 0);
-    fill_pair_twiddles<R>(TT, G, 0, 0);
-    // per-column phase tables from the clock-bit phases k_pipe_a staged in
-    // rows 2^G + r of the ancilla = 0 half: om[b][c] (b < G) the conjugate
-    // phase of G1 bit b, cc[c] (b = G) the conjugate of the product of the
-    // phases of the G2 bits set in o (staged whole in row 2^(G+1) + o when
-    // k_pipe_a wrote those rows)
-    const int g2 = n_c - G;
-    for (int e = threadIdx.x; e < (G + 1) * C; e += NT) {
-        const int b = e / C, c = e - b * C;
-        const uint64_t j = j0 + c;
-        if (b < G) {
-            const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + j);
-            om[b * C + c] = cmake<R>(w.x, -w.y);
-        } else if (A.ccrows) {
-            cc[c] = gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + j);
-        } else {
-            cvec<R> p = cmake<R>((R)1, (R)0);
-            for (int q = 0; q < g2; ++q)
-                if (o >> q & 1) p = cmul<R>(p, gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)q) << A.n_s) + j));
-            cc[c] = cmake<R>(p.x, -p.y);
-        }
-    }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
-        // phase B first: the forward cascade starts at the top bit of G1
-        for (int line = threadIdx.x; line < nlb; line += NT) {
-            const int c = line & (C - 1), llo = line >> A.cl;
+        const bool more = PERS && it + 1 < iters;
+        const cvec<R> *om = phs + (it & 1) * nph, *cc = om + G * C;
+        // persistent: the next tile's column phases, in flight during this
+        // tile.  Its lines are read when it starts: holding the next tile's
+        // lines in registers as well cost more in occupancy than it hid.
+        cvec<R> phn[OMR];
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < OMR; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e < nph) phn[q] = col_phase(e, j0 + jstep);
+            }
+        }
+        double zr = 0.0, zi = 0.0;
+        for (int line = threadIdx.x; line < nl; line += NT) {
+            const int llo = line >> A.cl;
             cvec<R> v[1 << RB];
-            if (line == (int)threadIdx.x) {
+            if (it == 0 && line == (int)threadIdx.x) {
 #pragma unroll
                 for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
             } else {
@@ -615,96 +641,52 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
 #pragma unroll
                 for (int k = 0; k < (1 << RB); ++k) v[k] = gld_nt<R>(p, k * ks);
             }
-            fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
-                                              [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
-            cvec<R> *lt = tile + (llo << A.cl) + c;
+            // the line's bits, top first
 #pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
-        }
-        __syncthreads();
-        // persistent: the next tile's first phase-B line and column phases,
-        // in flight during this tile's phase A
-        const bool more = PERS && it + 1 < iters;
-        cvec<R> omn[OMR], ccn = cmake<R>((R)1, (R)0);
-        if (more) {
-            const uint64_t jn = j0 + jstep;
-            if ((int)threadIdx.x < nlb) {
-                const cvec<R> *p = psi + (lrow + jn);
+            for (int kb = RB - 1; kb >= 0; --kb) {
+                const int h = 1 << kb;
+                const cvec<R> w = om[(RA + kb) * C + c];
+                const cvec<R> *t = TW + tw_off(RA + kb) + llo;
 #pragma unroll
-                for (int k = 0; k < (1 << RB); ++k) v0[k] = gld_nt<R>(p, k * ks);
+                for (int m = 0; m < h; ++m) {
+                    const cvec<R> q = cmul<R>(w, t[m << RA]);
+                    const cvec<R> a = v[m], b = v[m + h];
+                    const R sx = a.x + b.x, sy = a.y + b.y, dx = a.x - b.x, dy = a.y - b.y;
+                    v[m] = cmake<R>(ffma(q.x, dx, ffma(-q.y, dy, sx)), ffma(q.x, dy, ffma(q.y, dx, sy)));
+                }
             }
+            // the factors of the low bits (bit 0: twiddle 1) and cc
+            cvec<R> f = cc[c];
+#pragma unroll
+            for (int b = 0; b < RA; ++b) {
+                const cvec<R> w = om[b * C + c];
+                const cvec<R> q = b == 0 ? w : cmul<R>(w, TW[tw_off(b) + (llo & ((1 << b) - 1))]);
+                f = cmul<R>(f, (llo >> b & 1) ? cmake<R>((R)1 - q.x, -q.y) : cmake<R>((R)1 + q.x, q.y));
+            }
+            const cvec<R> u = cmul<R>(v[0], f);
+            zr += (double)u.x;
+            zi += (double)u.y;
+        }
+        // the next tile's phases go to the other set: it was last read in the
+        // previous tile, before the last barrier
+        if (more) {
+            cvec<R> *nxt = phs + ((it + 1) & 1) * nph;
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
                 const int e = threadIdx.x + q * NT;
-                if (e < G * C) {
-                    const int b = e / C, c = e - b * C;
-                    omn[q] = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + jn + c);
-                }
+                if (e < nph) nxt[e] = phn[q];
             }
-            if ((int)threadIdx.x < C) ccn = gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + jn + threadIdx.x);
         }
-        // phase A: remaining stages, conjugate phases, sum over the line
-        double zr = 0.0, zi = 0.0;
-        for (int line = threadIdx.x; line < nla; line += NT) {
-            const int c = line & (C - 1), lhi = line >> A.cl;
-            cvec<R> v[1 << RA];
-            const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
-#pragma unroll
-            for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-            // the phase-A twiddles come from the LDS tables line by line (the
-            // empty barrier keeps the compiler from hoisting them into
-            // registers for the whole loop, which the persistent form cannot spare)
-            asm volatile("" ::: "memory");
-            if (RA > 1)
-                fwd_cascade<R, RA, RA - 1, 1, 0>(v, TW, TT, [&](int jb, int k) { return k & ((1 << jb) - 1); });
-            // conj phase of clock index (o << G) | (lhi << RA) | k, for even k (group bit 0 clear)
-            cvec<R> base = cc[c];
-            for (int b = 0; b < RB; ++b)
-                if (lhi >> b & 1) base = cmul<R>(base, om[(RA + b) * C + c]);
-            const cvec<R> w0 = om[c];
-            const cvec<R> up = cmake<R>((R)1 + w0.x, w0.y), um = cmake<R>((R)1 - w0.x, -w0.y);
-            // the last forward stage (group bit 0, no twiddle) and the phase of
-            // bit 0 together: (a0 + a1) p + (a0 - a1) p om_0 = p (a0 (1 + om_0) + a1 (1 - om_0));
-            // the conj phase p of the pair m (bits 1.. of k) is carried along the
-            // Gray-code order of m, one factor (or its conjugate) per step
-            R lr = 0, li = 0;                // the line's sum, then FP64
-            cvec<R> ph = base;
-#pragma unroll
-            for (int g = 0; g < (1 << (RA - 1)); ++g) {
-                const int m = g ^ (g >> 1);
-                if (g > 0) {
-                    const int t = __builtin_ctz(g);
-                    const cvec<R> w = om[(t + 1) * C + c];
-                    ph = (m >> t & 1) ? cmul<R>(ph, w) : cconjmul<R>(ph, w);
-                }
-                const cvec<R> a = cmac2<R>(up, v[2 * m], um, v[2 * m + 1]);
-                const cvec<R> p = cmul<R>(a, ph);
-                lr += p.x;
-                li += p.y;
-            }
-            zr += (double)lr;
-            zi += (double)li;
-        }
-        // every line of a thread has the thread's column (the line stride NT is a multiple of C)
-        zs[threadIdx.x] = make_double2(zr, zi);
+        double2 *zt = zs + (it & 1) * NT;
+        zt[threadIdx.x] = make_double2(zr, zi);
         __syncthreads();
-        for (int c = threadIdx.x; c < C; c += NT) {
+        for (int cq = threadIdx.x; cq < C; cq += NT) {
             double r = 0.0, i = 0.0;
-            for (int t = c; t < NT; t += C) {
-                r += zs[t].x;
-                i += zs[t].y;
+            for (int t = cq; t < NT; t += C) {
+                r += zt[t].x;
+                i += zt[t].y;
             }
-            gst<double>(zpart, o * A.N + j0 + c, make_double2(r, i));
-        }
-        // the column phases are read in phase A only: the next tile's go in
-        // now (visible after the next phase B's barrier)
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < OMR; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e < G * C) om[e] = cmake<R>(omn[q].x, -omn[q].y);
-            }
-            if ((int)threadIdx.x < C) cc[threadIdx.x] = ccn;
+            gst<double>(zpart, o * A.N + j0 + cq, make_double2(r, i));
         }
         j0 += jstep;
     }
@@ -717,17 +699,6 @@ __global__ __launch_bounds__(NT) void k_pipe_c(PipeArgs A, PipeSolve one, const 
     pipe_c_body<R, RA, RB, NT, false>(A, solve_of(one, many), j0, o);
 }
 
-// the persistent form (single solves): one G2 value per block.  complex64:
-// four waves per SIMD, as the LDS allows, beat the fewer that the prefetched
-// line's registers would otherwise leave; complex128 lines need the
-// registers (held to four waves they spill)
-template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, sizeof(R) == 4 ? 4 : 8))) void k_pipe_cp(
-    PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    const uint64_t o = blockIdx.x >> A.pslog;
-    const uint64_t j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
-    pipe_c_body<R, RA, RB, NT, true>(A, solve_of(one, many), j0, o);
-}
 
 // ---------------------------------------------------------------------------
 // a batch as one persistent kernel over device work queues
@@ -919,10 +890,8 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         hipError_t e3 = hipFuncSetAttribute((const void *)k_pipe_bp<R, RA, RB, NT>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
-        hipError_t e4 = hipFuncSetAttribute((const void *)k_pipe_cp<R, RA, RB, NT>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         (void)hipGetLastError();
-        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
             return fail(SV_EDEVICE, "cannot raise the LDS limit of the pipeline kernels");
         attr_done = true;
     }
@@ -942,10 +911,7 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
             hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else {
         TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
-        if (A.pers)
-            hipLaunchKernelGGL((k_pipe_cp<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
-        else
-            hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     }
     SV_HIP(hipGetLastError());
     return SV_OK;
@@ -991,11 +957,12 @@ static int default_cl(int n_s, int g, size_t elem) {
 
 static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
     const size_t C = (size_t)1 << cl;
+    // k_pipe_c: the twiddles, two sets of column phases and of partial sums
+    if (which == 2) return ((size_t)1 << g) * e + 2 * (size_t)(g + 1) * C * e + 2 * (size_t)nt * sizeof(double2) + 16;
     size_t b = ((C << g) + ((size_t)1 << g)) * e;
-    if (which != 1) b += (size_t)(g + 1) * C * e;
-    if (which != 0) b += ((size_t)1 << g) * e;                          // radix-4 pair products
+    if (which == 0) b += (size_t)(g + 1) * C * e;
+    else b += ((size_t)1 << g) * e;                                      // radix-4 pair products
     if (which == 1) b += ((size_t)1 << g) * e + (size_t)(g + 1) * C * e;
-    if (which == 2) b += (size_t)nt * sizeof(double2) + 16;
     return b;
 }
 
@@ -1040,11 +1007,12 @@ static sv_status run_one(hipStream_t st, const PipePlan &P, int w, const PipeSol
     return dispatch_g<R>(w, st, one, many, P.A[w], g, P.nt[w], P.grid[w], P.lds[w]);
 }
 
-// Persistent k_pipe_b and k_pipe_c for a single solve: 2^(other group) x S
-// blocks, S = 2^pslog blocks per value of the clock group the kernel does not
-// transform (about 512 blocks in all, two per CU), each walking nb / S column
-// blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose phase
-// prefetch would not fit keep one block per tile.
+// Persistent k_pipe_b for a single solve: 2^g1 x S blocks, S = 2^pslog
+// blocks per G1 value (about 512 blocks in all, two per CU), each walking
+// nb / S column blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose
+// phase prefetch would not fit keep one block per tile.  k_pipe_c keeps one
+// block per tile: it holds no LDS tile, so there is nothing to amortise, and
+// its blocks run more waves than a persistent form's would.
 static int pipe_b_persist_env() {
     static int v = -1;
     if (v < 0) {
@@ -1056,21 +1024,18 @@ static int pipe_b_persist_env() {
 
 static void make_persistent(PipePlan &P) {
     if (!pipe_b_persist_env()) return;
-    for (int w = 1; w <= 2; ++w) {
-        PipeArgs &A = P.A[w];
-        const int G = w == 1 ? A.g2 : A.g1, other = A.n_c - G;
-        const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
-        if ((uint64_t)G * C > 2ull * (uint64_t)P.nt[w]) continue;
-        if (w == 2 && !A.ccrows) continue;
-        int pslog = 0;
-        while (pslog + other < 9 && (2ull << pslog) <= nb) ++pslog;
-        const uint64_t blocks = 1ull << (other + pslog);
-        if (blocks > 0x7fffffffull) continue;
-        A.pers = 1;
-        A.pslog = pslog;
-        A.iters = (int)(nb >> pslog);
-        P.grid[w] = dim3((unsigned)blocks, 1, 1);
-    }
+    PipeArgs &A = P.A[1];
+    const int G = A.g2, other = A.n_c - G;
+    const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
+    if ((uint64_t)G * C > 2ull * (uint64_t)P.nt[1]) return;
+    int pslog = 0;
+    while (pslog + other < 9 && (2ull << pslog) <= nb) ++pslog;
+    const uint64_t blocks = 1ull << (other + pslog);
+    if (blocks > 0x7fffffffull) return;
+    A.pers = 1;
+    A.pslog = pslog;
+    A.iters = (int)(nb >> pslog);
+    P.grid[1] = dim3((unsigned)blocks, 1, 1);
 }
 
 // The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
