@@ -461,7 +461,7 @@ def main():
                     "norm_total": res.norm_total},
     }
     out["autotune"] = [ln for ln in B.sv_tune_report().strip().splitlines()
-                       if f"/c64/{n_s}/{n_c} " in ln or f"/c64/{n_s}/{n_c}/p " in ln]
+                       if f"/c64/{n_s}/{n_c} " in ln]
     B.sv_hhl_plan_free(plan)
     st.close()
     del st

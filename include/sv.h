@@ -376,9 +376,8 @@ int sv_trace_report(char *buf, int len);
 /* The autotuner's current choices, one line per tuned shape:
  * "op/dtype/shape... values".  Tuning runs on first use of a shape
  * (SV_AUTOTUNE=0: defaults); SV_TUNE_CACHE=<file> persists the choices.
- *   eigpipe/<dtype>/<n_s>/<n_c>[/p]  fused eigen-frame kernels: (log2 columns
- *       per tile, threads per workgroup) for each of the three kernels ("/p":
- *       the persistent forms of single solves);
+ *   eigpipe/<dtype>/<n_s>/<n_c>  fused eigen-frame kernels: (log2 columns
+ *       per tile, threads per workgroup) for each of the three kernels;
  *   cgemm/<dtype>/<M>/<N>/<K>/<trans>  the matrix-core GEMM's tile shape:
  *       0 = 64 x 64 per workgroup, 1 = 16 x 16 per wavefront;
  *   fused/<dtype>/<n>/<circuit>  sv_apply_circuit with max_local = 0: (k

@@ -56,10 +56,8 @@ struct PipeArgs {
     double scale;        // 2^(-n_c/2)
     int sgn;             // signed (two's-complement) clock for the inversion
     uint64_t gcut;       // 0: inversion sin = 1/y; >= 1: gapped-phase-estimation flag, sin = [|y| >= gcut]
-    int pers;            // persistent blocks walking iters column blocks: k_pipe_b of a single
-                         // solve (one G1 value each), and work-queue items
-    int pslog, iters;    // log2 of the blocks per group value; column blocks per block
-    int ccrows;          // k_pipe_a stages the G2-value phases for k_pipe_c (n_c >= 4)
+    int pslog, iters;    // work-queue items: log2 of the column-block stride in blocks (0);
+                         // column blocks per item
 };
 
 // HBM pointers of a solve, in the global address space: the pointers come
@@ -278,19 +276,6 @@ __device__ __forceinline__ void pipe_a_body(const PipeArgs &A, const PipeSolve &
         const int q = r < g2 ? n_c - 1 - (G + r) : n_c - 1 - (r - g2);
         gst<R>(psi, ((((uint64_t)1 << G) + (uint64_t)r) << A.n_s) + j, turn_phase<R>(F[j * n_c + q]));
     }
-    // for k_pipe_c: the conjugate phase of every G2 value o2 (the product of
-    // its set bits' phases, as one exact turn sum) per column, in clock rows
-    // 2^(g1+1) + o2 of the ancilla = 0 half (free for n_c >= 4)
-    if (A.ccrows) {
-        for (int e = threadIdx.x; e < (C << g2); e += NT) {
-            const int o2 = e >> A.cl, c = e & (C - 1);
-            const uint64_t j = j0 + c;
-            uint64_t th = 0;
-            for (int q = 0; q < g2; ++q)
-                if (o2 >> q & 1) th += F[j * n_c + (n_c - 1 - (G + q))];
-            gst<R>(psi, ((((uint64_t)2 << G) + (uint64_t)o2) << A.n_s) + j, turn_phase<R>((uint64_t)0 - th));
-        }
-    }
     __syncthreads();
     // phase A: line = (c, l_hi), register index = bits [0, RA)
     const int nla = C << RB;
@@ -343,47 +328,48 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 }
 
 // ---------------------------------------------------------------------------
-// k_pipe_b: inverse cascade on G2, inversion rotation, forward cascade on G2
+// k_pipe_b: inverse cascade on G2 and the inversion rotation
 // ---------------------------------------------------------------------------
-// Tile: columns [j0, j0 + C) at G1 value o; persistent, A.iters column
-// blocks j0 + it 2^(pslog + cl).  The FP64 partial pair goes to slot `slot`.
+// Writes the state after the rotation (the ancilla = 1 half), as
+// 2^-G2 s_y a(y): the forward cascade of the uncompute that follows is left
+// to k_pipe_c, which needs only its projection.  Tile: columns [j0, j0 + C)
+// at G1 value o; a work-queue item (PERS) runs A.iters column blocks j0 + it 2^(pslog + cl).
+// The FP64 partial pair goes to slot `slot`.
 template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o,
                                             uint64_t slot) {
     constexpr int G = RA + RB;
-    // column data of a tile per thread (G C <= 8 * 64 <= 2 NT phases, C <= NT table entries)
-    constexpr int OMR = 2;
+    // column data per thread when the next tile's are read ahead ((G + 1) C <= 9 * 64)
+    constexpr int OMR = (9 * 64 + NT - 1) / NT;
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const gptr<double> __restrict__ part = (gptr<double>)S.part;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
-    cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
-    cvec<R> *TW = tile + ((size_t)C << G);
-    cvec<R> *TT = TW + (1 << G);                                     // radix-4 pair products
-    R *s2t = reinterpret_cast<R *>(TT + (1 << G));                  // [2^G] s_y^2 2^-G
+    cvec<R> *TW = reinterpret_cast<cvec<R> *>(smem_raw);            // [2^G] twiddles of G2 at G1 value o
+    R *s2t = reinterpret_cast<R *>(TW + (1 << G));                  // [2^G] s_y^2 2^-G
     R *srt = s2t + (1 << G);                                         // [2^G] s_y 2^-G
-    cvec<R> *om = reinterpret_cast<cvec<R> *>(srt + (1 << G));      // [G][C] phases of the G2 bits
-    cvec<R> *tT = om + G * C;                                        // [C] G1 table entries T_j(o)
+    // two sets (alternate tiles) of the column data: om[G][C] the phases of
+    // the G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), then tT[C] the
+    // G1 table entries T_j(o)
+    const int ncd = (G + 1) * C;
+    cvec<R> *cd = reinterpret_cast<cvec<R> *>(srt + (1 << G));
     __shared__ double red[2][NT / 64];
-    // persistent: the twiddle, pair and rotation tables (functions of o) are
-    // built once for all the block's column blocks
     const int iters = PERS ? A.iters : 1;
     const uint64_t jstep = PERS ? 1ull << (A.pslog + A.cl) : 0;
     const int g1 = A.g1, n_c = A.n_c;
-    // the tile's column data: the G1 table entries T_j(o) and the phases of the
-    // G2 bits (staged by k_pipe_a in clock rows 2^g1 + b), read before the
-    // twiddles are built so that their latency overlaps that work
-    for (int e = threadIdx.x; e < G * C; e += NT) {
-        const int b = e / C, c = e - b * C;
-        om[b * C + c] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + c);
-    }
-    for (int c = threadIdx.x; c < C; c += NT) tT[c] = gld<R>(psi, (o << A.n_s) | (j0 + c));
+    auto col_data = [&](int e, uint64_t j) -> cvec<R> {
+        const int b = e / C, cq = e - b * C;
+        return b < G ? gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j + cq)
+                     : gld<R>(psi, (o << A.n_s) | (j + cq));
+    };
+    // read before the twiddles are built, so that their latency overlaps that work
+    for (int e = threadIdx.x; e < ncd; e += NT) cd[e] = col_data(e, j0);
     fill_twiddles<R>(TW, G, g1, o);
-    fill_pair_twiddles<R>(TT, G, g1, o);
     // rotation of clock value y = o + l 2^g1 (natural order after the inverse
-    // transform): sin = 1/y (y >= 1).  The two groups of G Hadamards around it
-    // omit their 1/sqrt(2) each, so 2^-G is folded into the rotation (and into
-    // the FP64 weights of the sums, taken where the amplitudes are 2^(G/2) too large).
+    // transform): sin = 1/y (y >= 1).  The G Hadamards of the inverse cascade
+    // and the G of the forward one omit their 1/sqrt(2) each, so 2^-G is
+    // folded into the rotation (and into the FP64 weights of the sums, taken
+    // where the amplitudes are 2^(G/2) too large).
     const double fold = exp2(-(double)G);
     for (int l = threadIdx.x; l < (1 << G); l += NT) {
         const uint64_t y = o | ((uint64_t)l << g1);
@@ -393,43 +379,41 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
         srt[l] = (R)(sd * fold);
     }
     __syncthreads();
-    // the phase-A stages use the first 2^RA - 1 twiddles with indices fixed by
-    // the register position: keep them in registers for the whole block
-    cvec<R> twr[(1 << RA) - 1], ttr[(1 << RA) - 1];
-#pragma unroll
-    for (int i = 0; i < (1 << RA) - 1; ++i) {
-        twr[i] = TW[i];
-        ttr[i] = TT[i];
-    }
-    const int nla = C << RB, nlb = C << RA;
+    const int nl = C << RA;
+    // clock index o + ((llo + (k << RA)) << g1): a base for the line and a stride for k
+    const uint64_t ks = 1ull << (RA + g1 + A.n_s);
     double pa = 0.0, nt = 0.0;
     for (int it = 0; it < iters; ++it) {
-        // persistent: the next tile's column data, in flight during this tile's phase B
         const bool more = PERS && it + 1 < iters;
-        cvec<R> omn[OMR], tn = cmake<R>((R)0, (R)0);
+        const cvec<R> *om = cd + (it & 1) * ncd, *tT = om + G * C;
+        // an item's run: the next tile's column data, in flight during this tile
+        cvec<R> cdn[OMR];
         if (more) {
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
                 const int e = threadIdx.x + q * NT;
-                if (e < G * C) {
-                    const int b = e / C, c = e - b * C;
-                    omn[q] = gld<R>(psi, ((((uint64_t)1 << g1) + (uint64_t)b) << A.n_s) + j0 + jstep + c);
-                }
+                if (e < ncd) cdn[q] = col_data(e, j0 + jstep);
             }
-            if ((int)threadIdx.x < C) tn = gld<R>(psi, (o << A.n_s) | (j0 + jstep + threadIdx.x));
         }
-        // phase B: the inverse-QFT output on the G2 register of column j at
-        // y = o + l 2^g1, l = llo + (k << RA), generated from its closed form,
-        // then the rotation and the forward cascade on the high bits of G2.
-        // The input of the G2 stages is T_j(o) times a product state over the
-        // G2 bits (phase w_b on bit b), and inverse stage b maps a product
-        // state to a product state: after all of them the amplitude is
+        // the inverse-QFT output on the G2 register of column j at
+        // y = o + l 2^g1, l = llo + (k << RA), from its closed form.  The
+        // input of the G2 stages is T_j(o) times a product state over the G2
+        // bits (phase w_b on bit b), and inverse stage b maps a product state
+        // to a product state: after all of them the amplitude is
         //   T_j(o) prod_b (1 + (-1)^(l_b) w_b conj(tw_b(l mod 2^b))),
         // tw_b the stage's twiddle.  The factors of the low RA bits are the
         // line's, those of the RB high bits branch into the line's 2^RB
         // entries (a product tree, one level per bit).
-        for (int line = threadIdx.x; line < nlb; line += NT) {
-            const int c = line & (C - 1), llo = line >> A.cl;
+        for (int line = threadIdx.x; line < nl; line += NT) {
+            int c = line & (C - 1), llo = line >> A.cl;
+            // a wavefront takes 16 columns of four lines, so that each store
+            // instruction writes four rows of 128 B: that pattern streams
+            // faster than one row of 512 B
+            if (RA >= 2 && A.cl >= 4) {
+                const int wv = line >> 6;
+                c = (line & 15) | ((wv & ((1 << (A.cl - 4)) - 1)) << 4);
+                llo = ((line >> 4) & 3) | ((wv >> (A.cl - 4)) << 2);
+            }
             cvec<R> v[1 << RB];
             cvec<R> p = tT[c];
 #pragma unroll
@@ -455,57 +439,30 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             // total is the plain sum), then accumulated in FP64
             R lpa = 0, lnt = 0;
             const R *s2l = s2t + llo, *srl = srt + llo;
+            cvec<R> *ps = psi + (A.abit + ((o + ((uint64_t)llo << g1)) << A.n_s) + j0 + c);
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) {
                 const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
                 lpa += s2l[k << RA] * a2;
                 lnt += a2;
                 const R sr = srl[k << RA];
-                v[k] = cmake<R>(v[k].x * sr, v[k].y * sr);
+                gst_nt<R>(ps, k * ks, cmake<R>(v[k].x * sr, v[k].y * sr));
             }
             pa += (double)lpa;
             nt += (double)lnt * fold;
-            fwd_cascade<R, RB, G - 1, RA, RA>(v, TW, TT,
-                                              [&](int jb, int k) { return llo + ((k & ((1 << (jb - RA)) - 1)) << RA); });
-            cvec<R> *lt = tile + (llo << A.cl) + c;
-#pragma unroll
-            for (int k = 0; k < (1 << RB); ++k) lt[(k << RA) << A.cl] = v[k];
         }
-        __syncthreads();
-        // the column data are read in phase B only: the next tile's go in now
+        // the next tile's column data go to the other set, last read in the
+        // previous tile (before the last barrier)
         if (more) {
+            cvec<R> *nxt = cd + ((it + 1) & 1) * ncd;
 #pragma unroll
             for (int q = 0; q < OMR; ++q) {
                 const int e = threadIdx.x + q * NT;
-                if (e < G * C) om[e] = omn[q];
+                if (e < ncd) nxt[e] = cdn[q];
             }
-            if ((int)threadIdx.x < C) tT[threadIdx.x] = tn;
-        }
-        // phase A (forward cascade, low bits of G2), into the ancilla = 1 half.
-        // A wavefront takes 16 columns of four lines (lhi), so that each store
-        // instruction writes four rows of 128 B: that pattern streams faster
-        // than one row of 512 B.
-        for (int line = threadIdx.x; line < nla; line += NT) {
-            int c = line & (C - 1), lhi = line >> A.cl;
-            if (RB >= 2 && A.cl >= 4) {
-                const int wv = line >> 6;
-                c = (line & 15) | ((wv & ((1 << (A.cl - 4)) - 1)) << 4);
-                lhi = ((line >> 4) & 3) | ((wv >> (A.cl - 4)) << 2);
-            }
-            cvec<R> v[1 << RA];
-            const cvec<R> *lt = tile + ((lhi << RA) << A.cl) + c;
-#pragma unroll
-            for (int k = 0; k < (1 << RA); ++k) v[k] = lt[k << A.cl];
-            fwd_cascade<R, RA, RA - 1, 0, 0>(v, twr, ttr, [&](int jb, int k) { return k & ((1 << jb) - 1); });
-            // clock index o + (((lhi << RA) + k) << g1): a base for the line and a stride for k
-            cvec<R> *p = psi + (A.abit + ((o + ((uint64_t)lhi << (RA + g1))) << A.n_s) + j0 + c);
-            const uint64_t ks = 1ull << (g1 + A.n_s);
-#pragma unroll
-            for (int k = 0; k < (1 << RA); ++k) gst_nt<R>(p, k * ks, v[k]);
+            __syncthreads();
         }
         j0 += jstep;
-        // the next tile's phase B rewrites the tile this one has just read
-        if (more) __syncthreads();
     }
     pa = wave_sum_f64(pa);
     nt = wave_sum_f64(nt);
@@ -533,94 +490,99 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
                                       (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x);
 }
 
-// the persistent form (single solves): one G1 value o = blockIdx.x >> pslog
-// per block and the column blocks (blockIdx.x mod 2^pslog) + it 2^pslog
-template <typename R, int RA, int RB, int NT>
-__global__ __launch_bounds__(NT) void k_pipe_bp(PipeArgs A, PipeSolve one, const PipeSolve *__restrict__ many) {
-    const uint64_t o = blockIdx.x >> A.pslog;
-    const uint64_t j0 = (uint64_t)(blockIdx.x & ((1u << A.pslog) - 1u)) << A.cl;
-    pipe_b_body<R, RA, RB, NT, true>(A, solve_of(one, many), j0, o, blockIdx.x);
-}
 
 // ---------------------------------------------------------------------------
-// k_pipe_c: forward cascade on G1, conjugate phases, clock sum of the tile
-// (the missing 2^(-G/2) of the Hadamards is applied with the final scale)
+// k_pipe_c: forward cascade on the clock, conjugate phases, clock sum
+// (the missing 2^(-G/2) of the G1 Hadamards is applied with the final scale)
 // ---------------------------------------------------------------------------
 // Only the clock sum of each transformed column is needed,
 //   z = sum_y ph(y) (F v)(y),
-// F the forward cascade on G1 and ph(y) = cc prod_b om_b^(y_b) the conjugate
-// phases of the uncompute, a product over the G1 bits (cc: the G2 bits').
-// Moved onto the input, z = sum_y v(y) K(y) with K the transposed cascade
-// applied to ph.  A transposed stage on bit b maps the pair (p0, p1) to
-// (p0 + t p1, p0 - t p1), t its twiddle of the bits below b; run from bit 0
-// upwards on a product state it leaves
-//   K(y) = cc prod_b (1 + (-1)^(y_b) t_b(y mod 2^b) om_b),
-// so no transform is formed.  A thread takes a line (one column, one value
-// llo of the low RA bits, the 2^RB values of the high bits), contracts it from
-// its top bit down, each step halving it,
-//   u(m) = (v(m) + v(m + h)) + q (v(m) - v(m + h)),  q = t_b(llo + m 2^RA) om_b,
-// and multiplies what is left by the factors of the low bits and cc.  The
-// threads exchange nothing but the column sums.
-// Tile: columns [j0, j0 + C) at G2 value o; persistent, A.iters column
-// blocks j0 + it 2^(pslog + cl)
+// F the forward cascade on the whole clock (the QFT of the uncompute, from
+// the top bit down) and ph(y) = prod_b om_b^(y_b) the conjugate phases of
+// the controlled powers, a product over the clock bits.  Moved onto the
+// input, z = sum_y v(y) K(y) with K the transposed cascade applied to ph.  A
+// transposed stage on bit b maps the pair (p0, p1) to (p0 + t p1, p0 - t p1),
+// t = exp(2 pi i (y mod 2^b) / 2^(b+1)) its twiddle; run from bit 0 upwards
+// on a product state it leaves
+//   K(y) = prod_b (1 + (-1)^(y_b) t_b(y mod 2^b) om_b),
+// so no transform is formed.  A thread takes a line: one column, one value lo
+// of the clock bits below L = n_c - RB, the 2^RB values of the top RB bits.
+// It contracts the line from its top bit down, each step halving it,
+//   u(m) = (v(m) + v(m + h)) + q (v(m) - v(m + h)),  q = t_b(lo + m 2^L) om_b,
+// and multiplies what is left by the factors of the bits below L.  With
+// lo = llo + (o << RA): the tile is columns [j0, j0 + C) at o (< 2^g2), its
+// lines the 2^RA values llo; a work-queue item (PERS) runs A.iters column
+// blocks j0 + it 2^(pslog + cl).  The threads exchange only the column sums.
+// cos(2 pi k / 16) and sin(2 pi k / 16): the roots of the line bits in
+// k_pipe_c (RB <= 4), folded into the code as constants
+__device__ constexpr double cos16(int k) {
+    // cos(0), cos(pi/8), cos(pi/4), cos(3 pi/8), cos(pi/2)
+    constexpr double c[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
+    k &= 15;
+    return k <= 4 ? c[k] : k <= 8 ? -c[8 - k] : k <= 12 ? -c[k - 8] : c[16 - k];
+}
+__device__ constexpr double sin16(int k) { return cos16(k - 4); }
+
 template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
-    constexpr int G = RA + RB;
-    constexpr int OMR = 3;               // column phases per thread ((G + 1) C <= 2 NT + C <= 3 NT)
+    constexpr int G = RA + RB;           // = g1
+    static_assert(RB <= 4, "the line bits' roots are 16th roots of unity");
+    constexpr int OMR = (16 * 64 + NT - 1) / NT;   // column phases per thread (n_c C <= 16 * 64)
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
     const int C = 1 << A.cl;
-    // LDS: the G1 twiddles, then two sets (alternate tiles) of the column
-    // phases om[G][C], cc[C] and of the threads' partial sums
-    cvec<R> *TW = reinterpret_cast<cvec<R> *>(smem_raw);
-    const int nph = (G + 1) * C;
-    cvec<R> *phs = TW + (1 << G);
+    const int n_c = A.n_c, g2 = n_c - G, L = n_c - RB;
+    // LDS: the twiddles of the low bits t_b(x) (b < RA), per o the twiddles
+    // of the bits [RA, L) and the line's base phases exp(2 pi i lo / 2^(b+1))
+    // (b >= L), then two sets (alternate tiles) of the column phases
+    // om[n_c][C] and of the threads' partial sums
+    cvec<R> *TWa = reinterpret_cast<cvec<R> *>(smem_raw);           // [2^RA]
+    cvec<R> *T2 = TWa + (1 << RA);                                   // [g2][2^RA]
+    cvec<R> *T3 = T2 + (g2 << RA);                                   // [RB][2^RA]
+    const int nph = n_c * C;
+    cvec<R> *phs = T3 + (RB << RA);                                  // [2][n_c][C]
     const size_t zoff = (((size_t)((unsigned char *)(phs + 2 * nph) - smem_raw)) + 15) & ~(size_t)15;
-    double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);
+    double2 *zs = reinterpret_cast<double2 *>(smem_raw + zoff);      // [2][NT]
     const int iters = PERS ? A.iters : 1;
     const uint64_t jstep = PERS ? 1ull << (A.pslog + A.cl) : 0;
-    const int g2 = A.n_c - G;
     const int nl = C << RA;
     // every line of a thread has the thread's column (the line stride NT is a multiple of C)
     const int c = threadIdx.x & (C - 1);
-    // clock index (o << G) + llo + (k << RA): a base for the line and a stride for k
-    const uint64_t ks = 1ull << (RA + A.n_s);
-    const uint64_t lrow = A.abit + (((o << G) + (uint64_t)(threadIdx.x >> A.cl)) << A.n_s) + c;
-    // column phase e of the tile at column j: om_b (b = e / C < G) the
-    // conjugate phase of G1 bit b, staged by k_pipe_a in row 2^G + g2 + b of
-    // the ancilla = 0 half; b = G: cc, the conjugate of the product of the
-    // phases of the G2 bits set in o (staged whole in row 2^(G+1) + o when
-    // k_pipe_a wrote those rows)
+    // clock index lo + (k << L): a base for the line and a stride for k
+    const uint64_t ks = 1ull << (L + A.n_s);
+    // conjugate phase of clock bit b (= e / C) of the column at j: staged by
+    // k_pipe_a in clock row 2^g1 + g2 + b (G1 bits) or 2^g1 + b - g1 (G2
+    // bits) of the ancilla = 0 half
     auto col_phase = [&](int e, uint64_t j) -> cvec<R> {
         const int b = e / C, cq = e - b * C;
-        if (b < G) {
-            const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)(g2 + b)) << A.n_s) + j + cq);
-            return cmake<R>(w.x, -w.y);
-        }
-        if (A.ccrows) return gld<R>(psi, ((((uint64_t)2 << G) + o) << A.n_s) + j + cq);
-        cvec<R> p = cmake<R>((R)1, (R)0);
-        for (int q = 0; q < g2; ++q)
-            if (o >> q & 1) p = cmul<R>(p, gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)q) << A.n_s) + j + cq));
-        return cmake<R>(p.x, -p.y);
+        const int r = b < G ? g2 + b : b - G;
+        const cvec<R> w = gld<R>(psi, ((((uint64_t)1 << G) + (uint64_t)r) << A.n_s) + j + cq);
+        return cmake<R>(w.x, -w.y);
     };
-    // the thread's first line is read before the tables are built, so the
-    // HBM latency overlaps that work
-    cvec<R> v0[1 << RB];
-    if ((int)threadIdx.x < nl) {
-        const cvec<R> *p = psi + (lrow + j0);
-#pragma unroll
-        for (int k = 0; k < (1 << RB); ++k) v0[k] = gld_nt<R>(p, k * ks);
-    }
     for (int e = threadIdx.x; e < nph; e += NT) phs[e] = col_phase(e, j0);
-    fill_twiddles<R>(TW, G, 0, 0);
+    fill_twiddles<R>(TWa, RA, 0, 0);
+    for (int e = threadIdx.x; e < ((g2 + RB) << RA); e += NT) {
+        const int i = e >> RA, llo = e & ((1 << RA) - 1);
+        if (i < g2) {
+            // bit b = RA + i: t_b(lo mod 2^b), lo mod 2^b = llo + ((o mod 2^i) << RA)
+            const int b = RA + i;
+            const uint64_t x = (uint64_t)llo + ((o & ((1ull << i) - 1)) << RA);
+            T2[e] = turn_phase<R>(x << (63 - b));
+        } else {
+            // bit b = L + kb: exp(2 pi i lo / 2^(b+1))
+            const int b = L + (i - g2);
+            T3[((i - g2) << RA) + llo] = turn_phase<R>(((uint64_t)llo + (o << RA)) << (63 - b));
+        }
+    }
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
         const bool more = PERS && it + 1 < iters;
-        const cvec<R> *om = phs + (it & 1) * nph, *cc = om + G * C;
-        // persistent: the next tile's column phases, in flight during this
-        // tile.  Its lines are read when it starts: holding the next tile's
-        // lines in registers as well cost more in occupancy than it hid.
+        const cvec<R> *om = phs + (it & 1) * nph;
+        // an item's run: the next tile's column phases, in flight during this
+        // tile.  Lines are read where they are used: lines held in registers
+        // across the table set-up or the previous tile cost more in occupancy
+        // than they hide.
         cvec<R> phn[OMR];
         if (more) {
 #pragma unroll
@@ -633,35 +595,38 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
         for (int line = threadIdx.x; line < nl; line += NT) {
             const int llo = line >> A.cl;
             cvec<R> v[1 << RB];
-            if (it == 0 && line == (int)threadIdx.x) {
+            const cvec<R> *p = psi + (A.abit + (((o << RA) + (uint64_t)llo) << A.n_s) + j0 + c);
 #pragma unroll
-                for (int k = 0; k < (1 << RB); ++k) v[k] = v0[k];
-            } else {
-                const cvec<R> *p = psi + (A.abit + (((o << G) + (uint64_t)llo) << A.n_s) + j0 + c);
-#pragma unroll
-                for (int k = 0; k < (1 << RB); ++k) v[k] = gld_nt<R>(p, k * ks);
-            }
-            // the line's bits, top first
+            for (int k = 0; k < (1 << RB); ++k) v[k] = gld_nt<R>(p, k * ks);
+            // the line's bits, top first: q = om_b exp(2 pi i lo / 2^(b+1)) times
+            // the root exp(2 pi i m / 2^(kb+1)) of the line bits below
 #pragma unroll
             for (int kb = RB - 1; kb >= 0; --kb) {
                 const int h = 1 << kb;
-                const cvec<R> w = om[(RA + kb) * C + c];
-                const cvec<R> *t = TW + tw_off(RA + kb) + llo;
+                const cvec<R> Q = cmul<R>(om[(L + kb) * C + c], T3[(kb << RA) + llo]);
 #pragma unroll
                 for (int m = 0; m < h; ++m) {
-                    const cvec<R> q = cmul<R>(w, t[m << RA]);
+                    const int r = m << (3 - kb);
+                    const cvec<R> q = r == 0   ? Q
+                                      : r == 4 ? cmake<R>(-Q.y, Q.x)
+                                               : cmul<R>(Q, cmake<R>((R)cos16(r), (R)sin16(r)));
                     const cvec<R> a = v[m], b = v[m + h];
                     const R sx = a.x + b.x, sy = a.y + b.y, dx = a.x - b.x, dy = a.y - b.y;
                     v[m] = cmake<R>(ffma(q.x, dx, ffma(-q.y, dy, sx)), ffma(q.x, dy, ffma(q.y, dx, sy)));
                 }
             }
-            // the factors of the low bits (bit 0: twiddle 1) and cc
-            cvec<R> f = cc[c];
+            // the factors of the bits below L: the low RA bits (bit 0: twiddle
+            // 1), then the g2 bits of o
+            cvec<R> f = cmake<R>((R)1, (R)0);
 #pragma unroll
             for (int b = 0; b < RA; ++b) {
                 const cvec<R> w = om[b * C + c];
-                const cvec<R> q = b == 0 ? w : cmul<R>(w, TW[tw_off(b) + (llo & ((1 << b) - 1))]);
+                const cvec<R> q = b == 0 ? w : cmul<R>(w, TWa[tw_off(b) + (llo & ((1 << b) - 1))]);
                 f = cmul<R>(f, (llo >> b & 1) ? cmake<R>((R)1 - q.x, -q.y) : cmake<R>((R)1 + q.x, q.y));
+            }
+            for (int i = 0; i < g2; ++i) {
+                const cvec<R> q = cmul<R>(om[(RA + i) * C + c], T2[(i << RA) + llo]);
+                f = cmul<R>(f, (o >> i & 1) ? cmake<R>((R)1 - q.x, -q.y) : cmake<R>((R)1 + q.x, q.y));
             }
             const cvec<R> u = cmul<R>(v[0], f);
             zr += (double)u.x;
@@ -888,10 +853,8 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         hipError_t e2 = hipFuncSetAttribute((const void *)k_pipe_c<R, RA, RB, NT>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
-        hipError_t e3 = hipFuncSetAttribute((const void *)k_pipe_bp<R, RA, RB, NT>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, kLim);
         (void)hipGetLastError();
-        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess)
             return fail(SV_EDEVICE, "cannot raise the LDS limit of the pipeline kernels");
         attr_done = true;
     }
@@ -904,11 +867,8 @@ static sv_status launch_pipe(int which, hipStream_t st, const PipeSolve &one, co
         TraceScope ts(st, "pipe_a_init_iqft", table, 0.0);
         hipLaunchKernelGGL((k_pipe_a<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else if (which == 1) {
-        TraceScope ts(st, "pipe_b_iqft_ry_qft", half + table, 0.0);
-        if (A.pers)
-            hipLaunchKernelGGL((k_pipe_bp<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
-        else
-            hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
+        TraceScope ts(st, "pipe_b_iqft_ry", half + table, 0.0);
+        hipLaunchKernelGGL((k_pipe_b<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
     } else {
         TraceScope ts(st, "pipe_c_qft_project", half, 0.0);
         hipLaunchKernelGGL((k_pipe_c<R, RA, RB, NT>), grid, dim3(NT), lds, st, A, one, many);
@@ -955,15 +915,15 @@ static int default_cl(int n_s, int g, size_t elem) {
     return cl;
 }
 
-static size_t pipe_lds(int which, int cl, int g, size_t e, int nt) {
+static size_t pipe_lds(int which, int cl, int g, int n_c, size_t e, int nt) {
     const size_t C = (size_t)1 << cl;
-    // k_pipe_c: the twiddles, two sets of column phases and of partial sums
-    if (which == 2) return ((size_t)1 << g) * e + 2 * (size_t)(g + 1) * C * e + 2 * (size_t)nt * sizeof(double2) + 16;
-    size_t b = ((C << g) + ((size_t)1 << g)) * e;
-    if (which == 0) b += (size_t)(g + 1) * C * e;
-    else b += ((size_t)1 << g) * e;                                      // radix-4 pair products
-    if (which == 1) b += ((size_t)1 << g) * e + (size_t)(g + 1) * C * e;
-    return b;
+    const size_t RA = (size_t)(g + 1) / 2, RB = (size_t)g / 2, g2 = (size_t)(n_c - g);
+    if (which == 0)        // the tile, the twiddles, the column phases and constants
+        return ((C << g) + ((size_t)1 << g) + (size_t)(g + 1) * C) * e;
+    if (which == 1)        // the twiddles, two rotation tables, two sets of column data
+        return ((size_t)1 << g) * e + 2 * ((size_t)1 << g) * (e / 2) + 2 * (size_t)(g + 1) * C * e;
+    // k_pipe_c: the twiddle tables, two sets of column phases and of partial sums
+    return (((size_t)1 << RA) + ((g2 + RB) << RA) + 2 * (size_t)n_c * C) * e + 2 * (size_t)nt * sizeof(double2) + 16;
 }
 
 struct PipePlan {
@@ -984,10 +944,8 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
     A.scale = 1.0 / sqrt((double)(1ull << n_c));
     A.sgn = 0;
     A.gcut = 0;
-    A.pers = 0;
     A.pslog = 0;
     A.iters = 1;
-    A.ccrows = n_c >= 4 ? 1 : 0;
     for (int w = 0; w < 3; ++w) {
         const int g = w == 1 ? A.g2 : A.g1;
         P.A[w] = A;
@@ -997,7 +955,7 @@ static void make_plan(PipePlan &P, int n_s, int n_c, size_t e, const int cl[3], 
         const uint64_t tiles = w == 0 ? (A.N >> cl[w]) : (A.N >> cl[w]) << (n_c - g);
         P.grid[w] = tiles <= 0x7fffffffull ? dim3((unsigned)tiles, 1, nsolves)
                                            : dim3(1u << 30, (unsigned)(tiles >> 30), nsolves);
-        P.lds[w] = pipe_lds(w, cl[w], g, e, nt[w]);
+        P.lds[w] = pipe_lds(w, cl[w], g, n_c, e, nt[w]);
     }
 }
 
@@ -1007,43 +965,12 @@ static sv_status run_one(hipStream_t st, const PipePlan &P, int w, const PipeSol
     return dispatch_g<R>(w, st, one, many, P.A[w], g, P.nt[w], P.grid[w], P.lds[w]);
 }
 
-// Persistent k_pipe_b for a single solve: 2^g1 x S blocks, S = 2^pslog
-// blocks per G1 value (about 512 blocks in all, two per CU), each walking
-// nb / S column blocks.  Batched solves, SV_PIPE_B_PERSIST=0, and shapes whose
-// phase prefetch would not fit keep one block per tile.  k_pipe_c keeps one
-// block per tile: it holds no LDS tile, so there is nothing to amortise, and
-// its blocks run more waves than a persistent form's would.
-static int pipe_b_persist_env() {
-    static int v = -1;
-    if (v < 0) {
-        const char *e = getenv("SV_PIPE_B_PERSIST");
-        v = (e && atoi(e) == 0) ? 0 : 1;
-    }
-    return v;
-}
-
-static void make_persistent(PipePlan &P) {
-    if (!pipe_b_persist_env()) return;
-    PipeArgs &A = P.A[1];
-    const int G = A.g2, other = A.n_c - G;
-    const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
-    if ((uint64_t)G * C > 2ull * (uint64_t)P.nt[1]) return;
-    int pslog = 0;
-    while (pslog + other < 9 && (2ull << pslog) <= nb) ++pslog;
-    const uint64_t blocks = 1ull << (other + pslog);
-    if (blocks > 0x7fffffffull) return;
-    A.pers = 1;
-    A.pslog = pslog;
-    A.iters = (int)(nb >> pslog);
-    P.grid[1] = dim3((unsigned)blocks, 1, 1);
-}
-
 // The autotuner: per (dtype, n_s, n_c) time every feasible (columns per
 // tile, threads per workgroup) for each of the three kernels on the real
 // operands of one solve (each kernel is idempotent given its input half)
 // and keep the fastest; results live in the process-wide tuning cache.
 template <typename R>
-static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &one, bool pers, int cl_out[3],
+static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &one, int cl_out[3],
                            int nt_out[3]) {
     const size_t e = sizeof(cvec<R>);
     const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
@@ -1058,13 +985,12 @@ static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &on
         for (int cl = 3; cl <= 6; ++cl) {
             if (cl > n_s) break;
             for (int nt : {256, 512}) {
-                if (pipe_lds(w, cl, g, e, nt) > (size_t)PIPE_LDS_LIMIT) continue;
+                if (pipe_lds(w, cl, g, n_c, e, nt) > (size_t)PIPE_LDS_LIMIT) continue;
                 int cls[3] = {cl_out[0], cl_out[1], cl_out[2]}, nts[3] = {nt_out[0], nt_out[1], nt_out[2]};
                 cls[w] = cl;
                 nts[w] = nt;
                 PipePlan P;
                 make_plan(P, n_s, n_c, e, cls, nts, 1);
-                if (pers) make_persistent(P);
                 float ms = 0.f;
                 SV_TRY(time_stream(st, 2, &ms, [&]() { return run_one<R>(st, P, w, one, nullptr); }));
                 if (ms < best) {
@@ -1079,7 +1005,6 @@ static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &on
         // the next kernel reads what this one writes: leave its output in place
         PipePlan P;
         make_plan(P, n_s, n_c, e, cl_out, nt_out, 1);
-        if (pers) make_persistent(P);
         SV_TRY(run_one<R>(st, P, w, one, nullptr));
     }
     return SV_OK;
@@ -1087,14 +1012,12 @@ static sv_status tune_pipe(hipStream_t st, int n_s, int n_c, const PipeSolve &on
 
 // launch parameters for a shape: cached, tuned on `one` if allowed, else defaults
 template <typename R>
-static sv_status pipe_config_impl(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, bool pers, int cl[3],
+static sv_status pipe_config_impl(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3],
                                   int nt[3]) {
     const size_t e = sizeof(cvec<R>);
     const int g1 = (n_c + 1) / 2, g2 = n_c - g1;
-    // the persistent kernels of a single solve are tuned (and cached) apart
-    // from the per-tile kernels of batches
     const std::string key = std::string("eigpipe/") + (e == 8 ? "c64/" : "c128/") + std::to_string(n_s) + "/" +
-                            std::to_string(n_c) + (pers ? "/p" : "");
+                            std::to_string(n_c);
     std::vector<int> cached;
     if (tune_lookup(key, cached) && cached.size() == 6) {
         for (int w = 0; w < 3; ++w) {
@@ -1104,7 +1027,7 @@ static sv_status pipe_config_impl(hipStream_t st, int n_s, int n_c, const PipeSo
         return SV_OK;
     }
     if (tune_on && autotune_enabled()) {
-        SV_TRY(tune_pipe<R>(st, n_s, n_c, *tune_on, pers, cl, nt));
+        SV_TRY(tune_pipe<R>(st, n_s, n_c, *tune_on, cl, nt));
         tune_store(key, {cl[0], nt[0], cl[1], nt[1], cl[2], nt[2]});
         return SV_OK;
     }
@@ -1117,7 +1040,7 @@ static sv_status pipe_config_impl(hipStream_t st, int n_s, int n_c, const PipeSo
 
 template <typename R>
 sv_status pipe_config(hipStream_t st, int n_s, int n_c, const PipeSolve *tune_on, int cl[3], int nt[3]) {
-    return pipe_config_impl<R>(st, n_s, n_c, tune_on, false, cl, nt);
+    return pipe_config_impl<R>(st, n_s, n_c, tune_on, cl, nt);
 }
 
 template <typename R>
@@ -1126,14 +1049,13 @@ sv_status pipe_run(sv_state s, int n_s, int n_c, bool sgn, uint64_t gcut, const 
     const size_t e = sizeof(cvec<R>);
     PipeSolve one{s->data, beta, F, part, zpart};
     int cl[3], nt[3];
-    SV_TRY(pipe_config_impl<R>(s->stream, n_s, n_c, &one, pipe_b_persist_env() != 0, cl, nt));
+    SV_TRY(pipe_config_impl<R>(s->stream, n_s, n_c, &one, cl, nt));
     PipePlan P;
     make_plan(P, n_s, n_c, e, cl, nt, 1);
     for (int w = 0; w < 3; ++w) {
         P.A[w].sgn = sgn ? 1 : 0;
         P.A[w].gcut = gcut;
     }
-    make_persistent(P);
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
     for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(s->stream, P, w, one, nullptr));
     return SV_OK;
@@ -1151,9 +1073,6 @@ sv_status pipe_run_batch(hipStream_t st, int n_s, int n_c, const int cl[3], cons
     if (nsolves < 1 || nsolves > 65535) return fail(SV_EINVAL, "batch of %d solves", nsolves);
     PipePlan P;
     make_plan(P, n_s, n_c, e, cl, nt, nsolves);
-    // one block per tile here: k_pipe_c forms the G2-value phases itself, so
-    // k_pipe_a need not stage them
-    for (int w = 0; w < 3; ++w) P.A[w].ccrows = 0;
     *nparts = (uint64_t)P.grid[1].x * P.grid[1].y;
     PipeSolve none{};
     for (int w = 0; w < 3; ++w) SV_TRY(run_one<R>(st, P, w, none, dev_solves));
@@ -1206,18 +1125,16 @@ sv_status pipe_queue_build(sv_state ctx, hipStream_t st, PipeQueue &q, DevBuf &d
             while (A.cl > 0 && ((1ull << A.cl) << g) > (1ull << 11)) --A.cl;
             const uint64_t C = 1ull << A.cl, nb = A.N >> A.cl;
             int iters = 1;
-            // a run of column blocks prefetches each next block's column data
-            // (G C <= 2 x 256 entries; k_pipe_c also needs the staged G2 phases)
-            if (w > 0 && (w == 1 || A.ccrows) && (uint64_t)g * C <= 512)
+            // a run of column blocks reads each next block's column data ahead
+            if (w > 0)
                 while ((uint64_t)iters < nb && (((uint64_t)iters * 2 * C) << g) <= (1ull << 15)) iters *= 2;
-            A.pers = w > 0 ? 1 : 0;
             A.pslog = 0;
             A.iters = iters;
             qc[k].A[w] = A;
             qc[k].g[w] = g;
             if (g > gmax) gmax = g;
             qc[k].per_o[w] = (uint32_t)(nb / (uint64_t)iters);
-            const size_t b = pipe_lds(w, A.cl, g, e, 256);
+            const size_t b = pipe_lds(w, A.cl, g, A.n_c, e, 256);
             if (b > lds) lds = b;
         }
     }

@@ -3,7 +3,7 @@
 Every configuration the tuner can pick is pinned through sv_tune_set (or the
 explicit max_local / SV_FUSED_LOWBITS of the fused passes) and run:
 * the eigen-frame kernels: every (log2 columns per tile, threads) of each of
-  the three kernels, for single solves (persistent forms) and for a batch,
+  the three kernels, for single solves and for a batch,
   against the oracle at the usual bars;
 * the matrix-core GEMM: both tile shapes, bit for bit against each other
   (same k order) and against the oracle;
@@ -69,7 +69,7 @@ def test_pipeline_candidates_single_solves(dt, n_s, n_c):
     b = rng.standard_normal(1 << n_s)
     T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.87
     _, x_r, pp_r, pa_r = oracle.hhl(A, b, n_c, T0)
-    key = f"eigpipe/{dt}/{n_s}/{n_c}/p"
+    key = f"eigpipe/{dt}/{n_s}/{n_c}"
     tol = TOL[dt] if dt == "c128" else max(1e-5, 2e-6 / math.sqrt(pp_r))
     ran = 0
     try:
