@@ -133,7 +133,9 @@ typedef struct {
  * it can there, so a run of g gates costs one read and one write of the
  * state instead of g.  Gates are only moved past gates on disjoint qubits;
  * the result equals the in-order product.  max_local <= 0 lets the
- * autotuner choose k. */
+ * autotuner choose k.  A pass runs as many workgroups as the device holds at
+ * once, each walking a strided run of tiles; SV_FUSED_PERSIST=0 launches one
+ * workgroup per tile instead (same results, bit for bit). */
 sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, int n_gates, int max_local);
 
 /* Number of fused passes sv_apply_circuit would run (planning only). */

@@ -189,23 +189,26 @@ __device__ __forceinline__ void reg_apply(cvec<R> (&v)[1 << RB], const ROp &f) {
     }
 }
 
+// One fused pass.  Blocks walk the tiles tile = block + i * (blocks in the
+// grid): the grid is what the device holds at once, or one tile per block
+// when that covers them all.  (Reading the next tile into registers during
+// this tile's segments cost more in registers than it hid.)
 template <typename R, int RB>
 __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi, const FPass *__restrict__ passes,
                                                        int pi, const FSeg *__restrict__ segs,
-                                                       const ROp *__restrict__ ops) {
+                                                       const ROp *__restrict__ ops, uint64_t ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cvec<R> *tile = reinterpret_cast<cvec<R> *>(smem_raw);
     const FPass &P = passes[pi];
     const int k = P.k, c = P.c, r = P.r;
     const uint32_t T = 1u << k;
-    const uint64_t tid = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
-    const uint64_t base = pdep64(tid, P.nl_mask) | P.fix_val;
+    const uint64_t tstride = (uint64_t)gridDim.x * gridDim.y;
     const int *hpos = P.hpos;
 
-    // HBM -> LDS with U loads in flight per thread.  scatter_t is a bit
-    // deposit, so the thread's part (bits below log2 FUSE_BLOCK), the part
-    // of the unrolled index u and that of the outer step t0 combine by OR;
-    // the offsets of u's bits are formed once.
+    // HBM <-> LDS with U loads in flight per thread.  scatter_t is a bit
+    // deposit, so the thread's part (bits below log2 FUSE_BLOCK), the part of
+    // the unrolled index u and that of the outer step t0 combine by OR; the
+    // offsets of u's bits are formed once.
     constexpr int U = sizeof(R) == 4 ? 16 : 8;
     constexpr int LB = 8, LU = sizeof(R) == 4 ? 4 : 3;      // log2 FUSE_BLOCK, log2 U
     const uint64_t gthr = scatter_t(threadIdx.x & (T - 1u), c, r, hpos);
@@ -214,7 +217,8 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     uint64_t uoff[U];
     uint32_t uswz[U];
     const uint32_t sthr = swz<R>(threadIdx.x);
-    if (T >= FUSE_BLOCK * U) {
+    const bool big = T >= FUSE_BLOCK * U;
+    if (big) {
         uint64_t hb[LU];
         uint32_t hs[LU];
 #pragma unroll
@@ -235,64 +239,71 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
             uoff[u] = o;
             uswz[u] = w;
         }
-        for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
-            const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
-            const uint32_t s0 = sthr ^ swz<R>(t0);
-            cvec<R> buf[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff[u]];
-#pragma unroll
-            for (int u = 0; u < U; ++u) tile[s0 ^ uswz[u]] = buf[u];
-        }
-    } else {
-        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
     }
-    __syncthreads();
-
-    const uint32_t lines = T >> RB;                  // register lines per tile
-    for (int sg = 0; sg < P.nseg; ++sg) {
-        const FSeg &S = segs[P.seg_off + sg];
-        // swz is XOR-linear and bt and the register bits are disjoint, so the
-        // slot of bt | (bits of m) is swz(bt) ^ S.off[m] (the table is uniform,
-        // in bytes, as the slot is used)
-        unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
-        uint32_t off[1 << RB];
+    for (uint64_t tl = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x; tl < ntiles; tl += tstride) {
+        const uint64_t base = pdep64(tl, P.nl_mask) | P.fix_val;
+        if (big) {
+            for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+                const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
+                const uint32_t s0 = sthr ^ swz<R>(t0);
+                cvec<R> buf[U];
 #pragma unroll
-        for (int m = 0; m < (1 << RB); ++m) off[m] = S.off[m];
-        const ROp *op0 = ops + S.op_off;
-        for (uint32_t line = threadIdx.x; line < lines; line += FUSE_BLOCK) {
-            // the tile bits outside the register positions: the line index
-            // with a zero inserted at each position, lowest first
-            uint32_t bt = line;
+                for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff[u]];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) bt = insert0(bt, S.pos[i]);
-            const uint32_t sbt = swz<R>(bt) * (uint32_t)sizeof(cvec<R>);
-            cvec<R> v[1 << RB];
-#pragma unroll
-            for (int m = 0; m < (1 << RB); ++m) v[m] = *reinterpret_cast<const cvec<R> *>(tb + (sbt ^ off[m]));
-            for (int o = 0; o < S.nops; ++o) {
-                const ROp &f = op0[o];
-                if ((base & f.gmask) != f.gval || (bt & f.tmask) != f.tval) continue;
-                reg_apply<R, RB>(v, f);
+                for (int u = 0; u < U; ++u) tile[s0 ^ uswz[u]] = buf[u];
             }
-#pragma unroll
-            for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ off[m])) = v[m];
+        } else {
+            for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
         }
         __syncthreads();
-    }
 
-    if (T >= FUSE_BLOCK * U) {
-        for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
-            const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
-            const uint32_t s0 = sthr ^ swz<R>(t0);
-            cvec<R> buf[U];
+        const uint32_t lines = T >> RB;                  // register lines per tile
+        for (int sg = 0; sg < P.nseg; ++sg) {
+            const FSeg &S = segs[P.seg_off + sg];
+            // swz is XOR-linear and bt and the register bits are disjoint, so the
+            // slot of bt | (bits of m) is swz(bt) ^ S.off[m] (the table is uniform,
+            // in bytes, as the slot is used)
+            unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
+            uint32_t off[1 << RB];
 #pragma unroll
-            for (int u = 0; u < U; ++u) buf[u] = tile[s0 ^ uswz[u]];
+            for (int m = 0; m < (1 << RB); ++m) off[m] = S.off[m];
+            const ROp *op0 = ops + S.op_off;
+            for (uint32_t line = threadIdx.x; line < lines; line += FUSE_BLOCK) {
+                // the tile bits outside the register positions: the line index
+                // with a zero inserted at each position, lowest first
+                uint32_t bt = line;
 #pragma unroll
-            for (int u = 0; u < U; ++u) psi[g0 | uoff[u]] = buf[u];
+                for (int i = 0; i < RB; ++i) bt = insert0(bt, S.pos[i]);
+                const uint32_t sbt = swz<R>(bt) * (uint32_t)sizeof(cvec<R>);
+                cvec<R> v[1 << RB];
+#pragma unroll
+                for (int m = 0; m < (1 << RB); ++m) v[m] = *reinterpret_cast<const cvec<R> *>(tb + (sbt ^ off[m]));
+                for (int o = 0; o < S.nops; ++o) {
+                    const ROp &f = op0[o];
+                    if ((base & f.gmask) != f.gval || (bt & f.tmask) != f.tval) continue;
+                    reg_apply<R, RB>(v, f);
+                }
+#pragma unroll
+                for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ off[m])) = v[m];
+            }
+            __syncthreads();
         }
-    } else {
-        for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
+
+        if (big) {
+            for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+                const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
+                const uint32_t s0 = sthr ^ swz<R>(t0);
+                cvec<R> buf[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) buf[u] = tile[s0 ^ uswz[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) psi[g0 | uoff[u]] = buf[u];
+            }
+        } else {
+            for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
+        }
+        // the next tile is written into the LDS this one was read from
+        if (tl + tstride < ntiles) __syncthreads();
     }
 }
 
@@ -736,10 +747,31 @@ static int reg_bits_for(sv_dtype dt, int k) {
     return rb < k ? rb : k;
 }
 
+// persistent fused passes (the blocks the device holds at once walk the
+// tiles); SV_FUSED_PERSIST=0 launches one block per tile
+static int fused_persist_env() {
+    static int v = -1;
+    if (v < 0) {
+        const char *e = getenv("SV_FUSED_PERSIST");
+        v = (e && atoi(e) == 0) ? 0 : 1;
+    }
+    return v;
+}
+
 template <typename R, int RB>
-static void launch_fused(dim3 grid, size_t lds, hipStream_t st, cvec<R> *psi, const FPass *dp, int i, const FSeg *ds,
-                         const ROp *dops) {
-    hipLaunchKernelGGL((k_fused<R, RB>), grid, dim3(FUSE_BLOCK), lds, st, psi, dp, i, ds, dops);
+static void launch_fused(uint64_t tiles, size_t lds, hipStream_t st, cvec<R> *psi, const FPass *dp, int i,
+                         const FSeg *ds, const ROp *dops) {
+    dim3 grid = tile_grid(tiles);
+    if (fused_persist_env()) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_fused<R, RB>, FUSE_BLOCK, lds);
+        (void)hipGetLastError();
+        const uint64_t slots = (uint64_t)(cus > 0 ? cus : 1) * (uint64_t)(per > 0 ? per : 1);
+        if (slots < tiles) grid = dim3((unsigned)slots);
+    }
+    hipLaunchKernelGGL((k_fused<R, RB>), grid, dim3(FUSE_BLOCK), lds, st, psi, dp, i, ds, dops, tiles);
 }
 
 template <typename R>
@@ -779,9 +811,9 @@ static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
         const size_t lds = ((size_t)1 << h.k) * sizeof(cvec<R>);
         TraceScope _ts(s->stream, "fused_pass", 2.0 * (double)dim_of(s->n) * sizeof(cvec<R>), 0.0);
         cvec<R> *psi = (cvec<R> *)s->data;
-        if (RB == 5 && sizeof(R) == 4) launch_fused<float, 5>(tile_grid(tiles), lds, s->stream, (cvec<float> *)psi, dp, (int)i, ds, dops);
-        else if (RB >= 4) launch_fused<R, 4>(tile_grid(tiles), lds, s->stream, psi, dp, (int)i, ds, dops);
-        else launch_fused<R, 3>(tile_grid(tiles), lds, s->stream, psi, dp, (int)i, ds, dops);
+        if (RB == 5 && sizeof(R) == 4) launch_fused<float, 5>(tiles, lds, s->stream, (cvec<float> *)psi, dp, (int)i, ds, dops);
+        else if (RB >= 4) launch_fused<R, 4>(tiles, lds, s->stream, psi, dp, (int)i, ds, dops);
+        else launch_fused<R, 3>(tiles, lds, s->stream, psi, dp, (int)i, ds, dops);
     }
     hipError_t e = hipGetLastError();
     hipFreeAsync(dev, s->stream);

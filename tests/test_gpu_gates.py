@@ -112,6 +112,53 @@ def test_fused_circuit_matches_oracle(dt, n, kmax):
     assert B.sv_plan_passes(n, B.SV_C64 if dt == "c64" else B.SV_C128, gates, kmax) >= 1
 
 
+_PERSIST_CHILD = r"""
+import sys, numpy as np
+from paper_2307_00391_amd import binding as B, inputs
+n, kmax, dt, seed, out = int(sys.argv[1]), int(sys.argv[2]), sys.argv[3], int(sys.argv[4]), sys.argv[5]
+rng = np.random.default_rng(seed)
+psi0 = inputs.random_state(rng, n)
+if dt == "c64":
+    psi0 = psi0.astype(np.complex64).astype(np.complex128)
+gates = inputs.random_circuit(rng, n, 40, max_ctrls=2)
+s = B.State(n, dt)
+s.set(psi0)
+B.sv_apply_circuit(s.h, gates, kmax)
+np.save(out, s.get())
+print("child ok")
+"""
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_fused_persistent_tiles_match_one_tile_per_block(dt, tmp_path):
+    """A pass walks strided runs of tiles with as many workgroups as the
+    device holds (here 2^20 amplitudes in 2^12 tiles of 2^8: several tiles
+    per workgroup); SV_FUSED_PERSIST=0 launches one workgroup per tile.  Both
+    equal the oracle, and each other bit for bit."""
+    import os
+    import subprocess
+    import sys
+    n, kmax, seed = 20, 8, 4242
+    rng = np.random.default_rng(seed)
+    psi0 = _rounded(inputs.random_state(rng, n), dt)
+    gates = inputs.random_circuit(rng, n, 40, max_ctrls=2)
+    ref = psi0.copy()
+    for g in gates:
+        _oracle_apply(ref, g)
+    s = _state(n, dt, psi0)
+    B.sv_apply_circuit(s.h, gates, kmax)
+    got = s.get()
+    s.close()
+    assert np.abs(got - ref).max() <= TOL[dt]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = str(tmp_path / "one_tile_per_block.npy")
+    env = dict(os.environ, SV_FUSED_PERSIST="0")
+    r = subprocess.run([sys.executable, "-c", _PERSIST_CHILD, str(n), str(kmax), dt, str(seed), out], cwd=root,
+                       env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "child ok" in r.stdout, r.stdout + r.stderr
+    assert np.array_equal(np.load(out), got)
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("n,lo,m,kmax", [(6, 0, 6, 0), (12, 3, 7, 8), (16, 4, 10, 9), (17, 6, 11, 0),
                                          (14, 2, 12, 11)])
