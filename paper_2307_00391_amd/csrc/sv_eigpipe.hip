@@ -332,7 +332,11 @@ __global__ __launch_bounds__(NT) void k_pipe_a(PipeArgs A, PipeSolve one, const 
 // ---------------------------------------------------------------------------
 // Writes the state after the rotation (the ancilla = 1 half), as
 // 2^-G2 s_y a(y): the forward cascade of the uncompute that follows is left
-// to k_pipe_c, which needs only its projection.  Tile: columns [j0, j0 + C)
+// to k_pipe_c, which needs only its projection.  In the half the clock's two
+// groups trade places: clock value y1 + (y2 << g1) is row y2 + (y1 << g2), so
+// the rows of a tile (one G1 value) form one block of 2^g2 rows, which
+// streams faster than rows 2^g1 apart (a relabelling of the clock qubits in
+// memory; both kernels use it).  Tile: columns [j0, j0 + C)
 // at G1 value o; a work-queue item (PERS) runs A.iters column blocks j0 + it 2^(pslog + cl).
 // The FP64 partial pair goes to slot `slot`.
 template <typename R, int RA, int RB, int NT, bool PERS>
@@ -380,8 +384,9 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
     }
     __syncthreads();
     const int nl = C << RA;
-    // clock index o + ((llo + (k << RA)) << g1): a base for the line and a stride for k
-    const uint64_t ks = 1ull << (RA + g1 + A.n_s);
+    // clock value o + (l << g1), l = llo + (k << RA), is row l + (o << g2) of
+    // the half: a base for the line and a stride for k
+    const uint64_t ks = 1ull << (RA + A.n_s);
     double pa = 0.0, nt = 0.0;
     for (int it = 0; it < iters; ++it) {
         const bool more = PERS && it + 1 < iters;
@@ -439,7 +444,7 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             // total is the plain sum), then accumulated in FP64
             R lpa = 0, lnt = 0;
             const R *s2l = s2t + llo, *srl = srt + llo;
-            cvec<R> *ps = psi + (A.abit + ((o + ((uint64_t)llo << g1)) << A.n_s) + j0 + c);
+            cvec<R> *ps = psi + (A.abit + (((uint64_t)llo + (o << G)) << A.n_s) + j0 + c);
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) {
                 const R a2 = v[k].x * v[k].x + v[k].y * v[k].y;
@@ -549,8 +554,10 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
     const int nl = C << RA;
     // every line of a thread has the thread's column (the line stride NT is a multiple of C)
     const int c = threadIdx.x & (C - 1);
-    // clock index lo + (k << L): a base for the line and a stride for k
-    const uint64_t ks = 1ull << (L + A.n_s);
+    // clock value y = lo + (k << L) is row (y >> g1) + ((y mod 2^g1) << g2) of
+    // the half (k_pipe_b's layout); k's bits lie above g1, so a line is a
+    // base row and a stride for k
+    const uint64_t ks = 1ull << (L - G + A.n_s);
     // conjugate phase of clock bit b (= e / C) of the column at j: staged by
     // k_pipe_a in clock row 2^g1 + g2 + b (G1 bits) or 2^g1 + b - g1 (G2
     // bits) of the ancilla = 0 half
@@ -595,7 +602,9 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
         for (int line = threadIdx.x; line < nl; line += NT) {
             const int llo = line >> A.cl;
             cvec<R> v[1 << RB];
-            const cvec<R> *p = psi + (A.abit + (((o << RA) + (uint64_t)llo) << A.n_s) + j0 + c);
+            const uint64_t y = (o << RA) + (uint64_t)llo;
+            const uint64_t row = (y >> G) + ((y & ((1ull << G) - 1)) << g2);
+            const cvec<R> *p = psi + (A.abit + (row << A.n_s) + j0 + c);
 #pragma unroll
             for (int k = 0; k < (1 << RB); ++k) v[k] = gld_nt<R>(p, k * ks);
             // the line's bits, top first: q = om_b exp(2 pi i lo / 2^(b+1)) times
