@@ -343,8 +343,6 @@ template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o,
                                             uint64_t slot) {
     constexpr int G = RA + RB;
-    // column data per thread when the next tile's are read ahead ((G + 1) C <= 9 * 64)
-    constexpr int OMR = (9 * 64 + NT - 1) / NT;
     cvec<R> *__restrict__ psi = (cvec<R> *)S.psi;
     const gptr<double> __restrict__ part = (gptr<double>)S.part;
     extern __shared__ unsigned char smem_raw[];
@@ -391,15 +389,6 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
     for (int it = 0; it < iters; ++it) {
         const bool more = PERS && it + 1 < iters;
         const cvec<R> *om = cd + (it & 1) * ncd, *tT = om + G * C;
-        // an item's run: the next tile's column data, in flight during this tile
-        cvec<R> cdn[OMR];
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < OMR; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e < ncd) cdn[q] = col_data(e, j0 + jstep);
-            }
-        }
         // the inverse-QFT output on the G2 register of column j at
         // y = o + l 2^g1, l = llo + (k << RA), from its closed form.  The
         // input of the G2 stages is T_j(o) times a product state over the G2
@@ -456,15 +445,13 @@ __device__ __forceinline__ void pipe_b_body(const PipeArgs &A, const PipeSolve &
             pa += (double)lpa;
             nt += (double)lnt * fold;
         }
-        // the next tile's column data go to the other set, last read in the
-        // previous tile (before the last barrier)
+        // an item's run: the next tile's column data go to the other set, last
+        // read in the previous tile (before the last barrier).  (Reading them
+        // into registers during the tile cost the work-queue kernel more in
+        // spills than it hid.)
         if (more) {
             cvec<R> *nxt = cd + ((it + 1) & 1) * ncd;
-#pragma unroll
-            for (int q = 0; q < OMR; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e < ncd) nxt[e] = cdn[q];
-            }
+            for (int e = threadIdx.x; e < ncd; e += NT) nxt[e] = col_data(e, j0 + jstep);
             __syncthreads();
         }
         j0 += jstep;
@@ -532,7 +519,6 @@ template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
     constexpr int G = RA + RB;           // = g1
     static_assert(RB <= 4, "the line bits' roots are 16th roots of unity");
-    constexpr int OMR = (16 * 64 + NT - 1) / NT;   // column phases per thread (n_c C <= 16 * 64)
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
@@ -586,18 +572,9 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
     for (int it = 0; it < iters; ++it) {
         const bool more = PERS && it + 1 < iters;
         const cvec<R> *om = phs + (it & 1) * nph;
-        // an item's run: the next tile's column phases, in flight during this
-        // tile.  Lines are read where they are used: lines held in registers
-        // across the table set-up or the previous tile cost more in occupancy
-        // than they hide.
-        cvec<R> phn[OMR];
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < OMR; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e < nph) phn[q] = col_phase(e, j0 + jstep);
-            }
-        }
+        // lines are read where they are used: lines held in registers across
+        // the table set-up or the previous tile cost more in occupancy than
+        // they hide
         double zr = 0.0, zi = 0.0;
         for (int line = threadIdx.x; line < nl; line += NT) {
             const int llo = line >> A.cl;
@@ -641,15 +618,11 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
             zr += (double)u.x;
             zi += (double)u.y;
         }
-        // the next tile's phases go to the other set: it was last read in the
-        // previous tile, before the last barrier
+        // an item's run: the next tile's phases go to the other set, last read
+        // in the previous tile (before the last barrier)
         if (more) {
             cvec<R> *nxt = phs + ((it + 1) & 1) * nph;
-#pragma unroll
-            for (int q = 0; q < OMR; ++q) {
-                const int e = threadIdx.x + q * NT;
-                if (e < nph) nxt[e] = phn[q];
-            }
+            for (int e = threadIdx.x; e < nph; e += NT) nxt[e] = col_phase(e, j0 + jstep);
         }
         double2 *zt = zs + (it & 1) * NT;
         zt[threadIdx.x] = make_double2(zr, zi);
