@@ -4,28 +4,29 @@
 // register bits [0, g1) and a high group G2 = [g1, n_c) (g1, g2 <= 8).  A
 // tile holds C consecutive system columns j (contiguous in memory) times the
 // 2^g clock values of one group, for one setting of the other group's bits
-// (and the ancilla).  Inside a tile every column is an independent length-2^g
-// line of the clock DFT: its butterflies run in registers, RA bits at a time
-// ("phase A": the register index k spans group bits [0, RA); "phase B": it
-// spans [RA, g)), with one LDS exchange between the two.
+// (and the ancilla).
 //
 //   k_pipe_a: generate the state after phase estimation (product state over
 //             the clock bits, relabelled so the cascades need no swaps), then
-//             the inverse-QFT cascade on G1.  The G1 stages act on G1 qubits
-//             only, so the result is still a product between the groups:
-//             psi(j, y1, y2) = T_j(y1) * B_j(y2), with T_j the G1 transform of
-//             the column's G1 factor and B_j(y2) the product of the phases of
-//             the set G2 bits.  k_pipe_a therefore runs for y2 = 0 only and
-//             leaves T in the clock rows y1 < 2^g1 of the ancilla = 0 half.
+//             the inverse-QFT cascade on G1 (butterflies in registers, RA
+//             bits at a time, one LDS exchange).  The G1 stages act on G1
+//             qubits only, so the result is still a product between the
+//             groups: psi(j, y1, y2) = T_j(y1) * B_j(y2), with T_j the G1
+//             transform of the column's G1 factor and B_j(y2) the product of
+//             the phases of the set G2 bits.  k_pipe_a therefore runs for
+//             y2 = 0 only and leaves T in the clock rows y1 < 2^g1 of the
+//             ancilla = 0 half, and stages every column's clock-bit phases.
 //   k_pipe_b: the inverse-QFT cascade on G2 of T_j(y1) B_j(y2): each stage
 //             maps a product state over the G2 bits to another, so the
 //             cascade's output is T_j(y1) times a product of one factor per
 //             G2 bit, formed directly; then eigenvalue inversion
-//             a1 = (1/y) a0 (FP64 sums of P(a=1) and the norm), QFT cascade
-//             on G2                                   -> ancilla = 1 half
-//   k_pipe_c: QFT cascade on G1, the conjugate phases of the uncompute, and
-//             the sum over the clock values of the tile (the Hadamard layer
-//             projected on clock = 0)                -> FP64 partial sums
+//             a1 = (1/y) a0 (FP64 sums of P(a=1) and the norm)
+//                                                     -> ancilla = 1 half
+//   k_pipe_c: the uncompute projected on clock 0 (the QFT on the whole
+//             clock, the conjugate phases, the Hadamard layer onto |0>), as
+//             a contraction of the half against the transposed QFT applied
+//             to the phase product state, itself a closed-form product
+//                                                     -> FP64 partial sums
 //
 // Cascade stages on register qubit j (relative to the clock register):
 //   inverse: a1 *= conj(phase), then (a0 + a1, a0 - a1)/sqrt 2

@@ -852,7 +852,7 @@ static sv_status eig_frame_run(sv_state s, const EigFrame &E, Workspace &w, cons
 
     if (fused && pipe_supported(n_s, n_c)) {
         // fused three-kernel pipeline: (state + inverse QFT on the low clock bits),
-        // (inverse QFT high + rotation + QFT high), (QFT low + conj phases + projection)
+        // (inverse QFT high + rotation), (uncompute projected on clock 0)
         const uint64_t nbp = pipe_b_blocks(n_s, n_c, sizeof(cvec<R>));
         const int rows = pipe_c_rows(n_c);
         SV_TRY(need(w.part, 2 * nbp * sizeof(double)));
