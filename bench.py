@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--no-flow", action="store_true")
     ap.add_argument("--no-t0", action="store_true")
     ap.add_argument("--t0-train", type=int, default=2000)
-    ap.add_argument("--t0-eval", type=int, default=128)
+    ap.add_argument("--t0-eval", type=int, default=256)
     ap.add_argument("--sweep-instances", type=int, default=64)
     ap.add_argument("--sweep-replays", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
