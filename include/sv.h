@@ -225,7 +225,7 @@ typedef struct {
                       estimation is generated inside the first inverse-QFT kernel, the
                       rotation sits between the two halves of the clock transforms, and
                       the uncompute ends in the clock = 0 projection: three passes over
-                      half the state (n_c <= 16; larger n_c runs as mode 2);
+                      half the state (n_c <= 20; larger n_c runs as mode 2);
                       2: eigen-frame, one kernel per step (state write, inverse QFT on
                       the ancilla = 0 half, rotation into the ancilla = 1 half, QFT there,
                       projection) */
@@ -589,7 +589,7 @@ sv_status sv_qlsa2_fourier(sv_state s, const double *A, const double *b, const s
  * side streams.
  * --------------------------------------------------------------------- */
 typedef struct {
-    int n_s, n_c;          /* 1 <= n_s <= 13, 2 <= n_c <= 16, n_s + n_c + 1 <= 32 */
+    int n_s, n_c;          /* 1 <= n_s <= 13, 2 <= n_c <= 20, n_s + n_c + 1 <= 32 */
     const double *A;       /* host, 2^n_s x 2^n_s complex FP64 row-major, Hermitian positive definite */
     const double *b;       /* host, 2^n_s complex FP64 */
     int n_t0;              /* number of T0 values (>= 1) */

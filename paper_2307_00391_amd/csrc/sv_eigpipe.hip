@@ -1,7 +1,7 @@
 // Eigen-frame HHL as three fused column-tile kernels.
 //
 // The clock register [n_s, n_s + n_c) is split into a low group G1 =
-// register bits [0, g1) and a high group G2 = [g1, n_c) (g1, g2 <= 8).  A
+// register bits [0, g1) and a high group G2 = [g1, n_c) (g1, g2 <= 10).  A
 // tile holds C consecutive system columns j (contiguous in memory) times the
 // 2^g clock values of one group, for one setting of the other group's bits
 // (and the ancilla).
@@ -506,20 +506,28 @@ __global__ __launch_bounds__(NT) void k_pipe_b(PipeArgs A, PipeSolve one, const 
 // lo = llo + (o << RA): the tile is columns [j0, j0 + C) at o (< 2^g2), its
 // lines the 2^RA values llo; a work-queue item (PERS) runs A.iters column
 // blocks j0 + it 2^(pslog + cl).  The threads exchange only the column sums.
-// cos(2 pi k / 16) and sin(2 pi k / 16): the roots of the line bits in
-// k_pipe_c (RB <= 4), folded into the code as constants
-__device__ constexpr double cos16(int k) {
-    // cos(0), cos(pi/8), cos(pi/4), cos(3 pi/8), cos(pi/2)
-    constexpr double c[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
-    k &= 15;
-    return k <= 4 ? c[k] : k <= 8 ? -c[8 - k] : k <= 12 ? -c[k - 8] : c[16 - k];
+// cos(2 pi k / 32) and sin(2 pi k / 32): the roots of the line bits in
+// k_pipe_c (RB <= 5), folded into the code as constants
+__device__ constexpr double cos32(int k) {
+    // cos(j pi / 16), j = 0..8
+    constexpr double c[9] = {1.0,
+                             0.98078528040323044913,
+                             0.92387953251128675613,
+                             0.83146961230254523708,
+                             0.70710678118654752440,
+                             0.55557023301960222474,
+                             0.38268343236508977173,
+                             0.19509032201612826785,
+                             0.0};
+    k &= 31;
+    return k <= 8 ? c[k] : k <= 16 ? -c[16 - k] : k <= 24 ? -c[k - 16] : c[32 - k];
 }
-__device__ constexpr double sin16(int k) { return cos16(k - 4); }
+__device__ constexpr double sin32(int k) { return cos32(k - 8); }
 
 template <typename R, int RA, int RB, int NT, bool PERS>
 __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &S, uint64_t j0, uint64_t o) {
     constexpr int G = RA + RB;           // = g1
-    static_assert(RB <= 4, "the line bits' roots are 16th roots of unity");
+    static_assert(RB <= 5, "the line bits' roots are 32nd roots of unity");
     const cvec<R> *__restrict__ psi = (const cvec<R> *)S.psi;
     double2 *__restrict__ zpart = S.zpart;
     extern __shared__ unsigned char smem_raw[];
@@ -593,10 +601,10 @@ __device__ __forceinline__ void pipe_c_body(const PipeArgs &A, const PipeSolve &
                 const cvec<R> Q = cmul<R>(om[(L + kb) * C + c], T3[(kb << RA) + llo]);
 #pragma unroll
                 for (int m = 0; m < h; ++m) {
-                    const int r = m << (3 - kb);
+                    const int r = m << (4 - kb);
                     const cvec<R> q = r == 0   ? Q
-                                      : r == 4 ? cmake<R>(-Q.y, Q.x)
-                                               : cmul<R>(Q, cmake<R>((R)cos16(r), (R)sin16(r)));
+                                      : r == 8 ? cmake<R>(-Q.y, Q.x)
+                                               : cmul<R>(Q, cmake<R>((R)cos32(r), (R)sin32(r)));
                     const cvec<R> a = v[m], b = v[m + h];
                     const R sx = a.x + b.x, sy = a.y + b.y, dx = a.x - b.x, dy = a.y - b.y;
                     v[m] = cmake<R>(ffma(q.x, dx, ffma(-q.y, dy, sx)), ffma(q.x, dy, ffma(q.y, dx, sy)));
@@ -879,11 +887,13 @@ static sv_status dispatch_g(int which, hipStream_t st, const PipeSolve &one, con
     case 6: return launch_nt<R, 3, 3>(which, st, one, many, A, nt, grid, lds);
     case 7: return launch_nt<R, 4, 3>(which, st, one, many, A, nt, grid, lds);
     case 8: return launch_nt<R, 4, 4>(which, st, one, many, A, nt, grid, lds);
+    case 9: return launch_nt<R, 5, 4>(which, st, one, many, A, nt, grid, lds);
+    case 10: return launch_nt<R, 5, 5>(which, st, one, many, A, nt, grid, lds);
     }
     return fail(SV_EUNSUPPORTED, "clock group of %d bits", g);
 }
 
-int pipe_supported(int n_s, int n_c) { return n_c >= 2 && n_c <= 16 && n_s >= 0; }
+int pipe_supported(int n_s, int n_c) { return n_c >= 2 && n_c <= 20 && n_s >= 0; }
 
 static const int PIPE_LDS_LIMIT = 144 * 1024;
 
@@ -1143,6 +1153,9 @@ sv_status pipe_queue_build(sv_state ctx, hipStream_t st, PipeQueue &q, DevBuf &d
         bytes += cost[k];
     }
     // resident blocks, and the XCC each of them lands on
+    // the queue kernel carries bodies for clock groups of up to 8 bits; a
+    // batch with wider groups runs its classes' own kernels instead
+    if (gmax > 8) return fail(SV_EUNSUPPORTED, "work queue for clock groups of %d bits", gmax);
     q.gmax = gmax <= 6 ? 6 : 8;
     const void *kfn = q.gmax == 6 ? (const void *)k_pipe_queue<R, 6> : (const void *)k_pipe_queue<R, 8>;
     int per_cu = 0, dev = 0, ncu = 0, khz = 0;

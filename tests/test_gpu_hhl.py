@@ -301,6 +301,44 @@ def test_fused_pipeline_wide_clock_shapes(n_s, n_c):
         assert abs(res.norm_total - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
 
 
+@pytest.mark.parametrize("n_s,n_c", [(3, 17), (4, 18), (2, 20)])
+def test_fused_pipeline_clock_groups_above_8_bits(n_s, n_c):
+    """Clocks of 17 to 20 qubits: clock groups of 9 and 10 bits (register
+    lines of 32 values, the 32nd roots of unity of the contraction) against
+    the closed form, both precisions."""
+    from tests.closed_form import hhl_closed_form
+    rng = np.random.default_rng(500 + 16 * n_s + n_c)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 1 << n_s, 40.0)
+    b = rng.standard_normal(1 << n_s)
+    T0 = inputs.t0_top_of_clock(lmax, n_c) * 0.91
+    x_r, pp_r = hhl_closed_form(A, b, n_c, T0)
+    for dt in ("c64", "c128"):
+        st, x, res = _run(A, b, n_c, T0, dt, 1)
+        st.close()
+        _relative_checks(x, x_r, res.p_post, pp_r, dt)
+        assert abs(res.norm_total - 1.0) <= (1e-5 if dt == "c64" else 1e-12)
+
+
+def test_batch_with_an_18_bit_clock_runs_on_side_streams():
+    """The work-queue kernel carries clock groups of up to 8 bits: a batch
+    with an 18-bit clock (9-bit groups) runs its classes' own kernels and
+    matches the closed form."""
+    from tests.closed_form import hhl_closed_form
+    rng = np.random.default_rng(777)
+    A, lmin, lmax = inputs.random_spd_tridiag(rng, 8, 30.0)
+    b = rng.standard_normal(8)
+    t0s = [inputs.t0_top_of_clock(lmax, 18) * f for f in (0.6, 0.8, 0.95)]
+    h = B.sv_batch_prepare([(A, b, 18, t0s)], "c64")
+    try:
+        assert B.sv_batch_form(h)[0] == 0
+        res = B.sv_batch_run(h, use_graph=True)
+    finally:
+        B.sv_batch_free(h)
+    for k, T0 in enumerate(t0s):
+        _, pp_r = hhl_closed_form(A, b, 18, T0)
+        assert abs(res[k, 0] - pp_r) <= 2 * REL["c64"] * pp_r, (k, res[k, 0], pp_r)
+
+
 def test_tridiagonal_operator_uses_the_tridiagonal_eigensolver():
     """A real tridiagonal A goes to rocSOLVER's tridiagonal divide and
     conquer; the solution still matches the oracle (Poiseuille, 16 points)."""
