@@ -51,7 +51,7 @@ def _pipe_candidates(n_s, n_c, dt):
         base += [_default_cl(n_s, g2 if w == 1 else g1, dt), 256]
     out = []
     for w in range(3):
-        for cl in range(3, 7):
+        for cl in range(3, 8):
             if cl > n_s:
                 break
             for nt in (256, 512):
