@@ -630,8 +630,8 @@ __device__ __forceinline__ double2 vcmul_acc(double2 v, double2 z, double2 a) {
 // k_gemv_rows: the partial sums part[i][s] = sum_{j in segment s} V[i][j] z[j]
 // over segments of 1024 columns.  A block of four wavefronts takes 16 rows
 // (four per wavefront) of one segment, with z's segment in LDS; each lane
-// reads 16 entries of each of its wavefront's rows, 64 consecutive entries
-// (512 B real, 1 KiB complex) per load.  Blocks are numbered segment-fastest,
+// reads 16 entries of each of its wavefront's rows, 1 KiB of a row per
+// wavefront load (two real entries, or one complex entry, per lane).  Blocks are numbered segment-fastest,
 // so the blocks in flight read whole rows of a few row groups, as a linear
 // sweep of V would (per-row streams spread over all of V read at half speed).
 constexpr int GV_SEG = 1024, GV_ROWS = 16;
@@ -652,13 +652,29 @@ __global__ __launch_bounds__(256) void k_gemv_rows(double2 *__restrict__ part, c
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
     const int nr = r0 >= N ? 0 : (N - r0 < 4 ? (int)(N - r0) : 4);
-#pragma unroll 4
-    for (int t = lane; t < J; t += 64) {
-        const double2 zt = zs[t];
-        const VT *col = V + r0 * N + j0 + t;
+    if (sizeof(VT) == sizeof(double) && (N & 1) == 0) {
+        // a real V with an even row length: two entries (16 B) per lane and
+        // load, 1 KiB of a row per wavefront instruction; J is even too
+#pragma unroll 2
+        for (int t = 2 * lane; t < J; t += 128) {
+            const double2 z0 = zs[t], z1 = zs[t + 1];
+            const double2 *col = reinterpret_cast<const double2 *>(V + r0 * N + j0 + t);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (r < nr) acc[r] = vmul_acc(col[(uint64_t)r * N], zt, acc[r]);
+            for (int r = 0; r < 4; ++r)
+                if (r < nr) {
+                    const double2 v = col[(uint64_t)r * (N / 2)];
+                    acc[r] = vmul_acc(v.y, z1, vmul_acc(v.x, z0, acc[r]));
+                }
+        }
+    } else {
+#pragma unroll 4
+        for (int t = lane; t < J; t += 64) {
+            const double2 zt = zs[t];
+            const VT *col = V + r0 * N + j0 + t;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < nr) acc[r] = vmul_acc(col[(uint64_t)r * N], zt, acc[r]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
