@@ -702,6 +702,44 @@ __global__ void k_gemv_reduce(double2 *__restrict__ out, const double2 *__restri
 // a fixed order.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_gemv_cols(double2 *__restrict__ out, const VT *__restrict__ V,
+                                                   const double2 *__restrict__ b, uint64_t N);
+
+// the same for a real V with an even row length, two columns per lane (one
+// 16 B load per row, 1 KiB of a row per wavefront instruction, 128 columns
+// per block); every column's sum runs in the same order as above
+__global__ __launch_bounds__(256) void k_gemv_cols2(double2 *__restrict__ out, const double *__restrict__ V,
+                                                    const double2 *__restrict__ b, uint64_t N) {
+    __shared__ double2 part[3][2][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t j = (uint64_t)blockIdx.x * 128 + 2 * (uint64_t)lane;
+    const bool ok = j < N;
+    double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+    if (ok) {
+        const double2 *V2 = reinterpret_cast<const double2 *>(V);
+#pragma unroll 8
+        for (uint64_t i = w; i < N; i += 4) {
+            const double2 v = V2[(i * N + j) >> 1];
+            const double2 bi = b[i];
+            a0 = vcmul_acc(v.x, bi, a0);
+            a1 = vcmul_acc(v.y, bi, a1);
+        }
+    }
+    if (w > 0) {
+        part[w - 1][0][lane] = a0;
+        part[w - 1][1][lane] = a1;
+    }
+    __syncthreads();
+    if (w == 0 && ok) {
+        const double2 p1 = part[0][0][lane], p2 = part[1][0][lane], p3 = part[2][0][lane];
+        const double2 q1 = part[0][1][lane], q2 = part[1][1][lane], q3 = part[2][1][lane];
+        out[j] = make_double2((a0.x + p1.x) + (p2.x + p3.x), (a0.y + p1.y) + (p2.y + p3.y));
+        out[j + 1] = make_double2((a1.x + q1.x) + (q2.x + q3.x), (a1.y + q1.y) + (q2.y + q3.y));
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gemv_cols(double2 *__restrict__ out, const VT *__restrict__ V,
                                                    const double2 *__restrict__ b, uint64_t N) {
     __shared__ double2 part[3][64];
     const int lane = threadIdx.x & 63;
@@ -730,8 +768,12 @@ static sv_status gemv_apply(hipStream_t st, double2 *out, const double2 *in, con
     TraceScope _ts(st, adjoint ? "gemv_vh" : "gemv_v", bytes, 8.0 * (double)N * (double)N);
     if (adjoint) {
         const unsigned g = (unsigned)((N + 63) / 64);
-        if (Vr) hipLaunchKernelGGL(k_gemv_cols<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
-        else hipLaunchKernelGGL(k_gemv_cols<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
+        if (Vr && (N & 1) == 0)
+            hipLaunchKernelGGL(k_gemv_cols2, dim3((unsigned)((N + 127) / 128)), dim3(256), 0, st, out, Vr, in, N);
+        else if (Vr)
+            hipLaunchKernelGGL(k_gemv_cols<double>, dim3(g), dim3(256), 0, st, out, Vr, in, N);
+        else
+            hipLaunchKernelGGL(k_gemv_cols<double2>, dim3(g), dim3(256), 0, st, out, Vc, in, N);
     } else {
         const int nseg = (int)((N + GV_SEG - 1) / GV_SEG);
         const uint64_t blocks = ((N + GV_ROWS - 1) / GV_ROWS) * (uint64_t)nseg;
