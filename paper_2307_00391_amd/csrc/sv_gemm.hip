@@ -56,7 +56,8 @@ struct GemmArgs {
 // 256 threads: 4 waves as 2 x 2, each wave a 32 x 32 output block made of
 // 2 x 2 MFMA 16 x 16 tiles.  Operands are staged in LDS as separate real and
 // imaginary planes, k-major, so the 16 lanes that share a k read 16
-// consecutive words.
+// consecutive words; the next k step's operands are in flight (in
+// registers) while a step's MFMAs run.
 template <typename R>
 __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
     using M_ = MfmaT<R>;
@@ -82,36 +83,43 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs<R> A) {
             for (int v = 0; v < 4; ++v) acc_re[i][j][v] = acc_im[i][j][v] = (R)0;
 
     const R csgn = A.conjb ? (R)-1 : (R)1;
-    for (int k0 = 0; k0 < A.K; k0 += GBK) {
-        // A tile: 64 rows x 16 k
+    // The next k step's operands are loaded into registers while this step's
+    // MFMAs run, and written to the LDS after the step's closing barrier.
+    // Thread roles: A rows as above; B as (n, four k) or (k, four n).
+    const int b_n = A.trans ? (tid & 15) * 4 : tid >> 2, b_k = A.trans ? tid >> 4 : (tid & 3) * 4;
+    cvec<R> pa[4], pb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int kk = k0 + a_k + i;
-            cvec<R> v = cmake<R>((R)0, (R)0);
-            if (a_ok && kk < A.K) v = A.in[a_base + ((uint64_t)kk << A.ksh)];
-            As_re[a_k + i][a_row] = v.x;
-            As_im[a_k + i][a_row] = v.y;
+            pa[i] = cmake<R>((R)0, (R)0);
+            if (a_ok && kk < A.K) pa[i] = A.in[a_base + ((uint64_t)kk << A.ksh)];
         }
-        // B tile: 16 k x 64 n
-        if (!A.trans) {
-            const int bn = tid >> 2, bk = (tid & 3) * 4;
-            for (int i = 0; i < 4; ++i) {
-                const int kk = k0 + bk + i, nn = n0 + bn;
-                cvec<R> v = cmake<R>((R)0, (R)0);
-                if (kk < A.K && nn < A.N) v = A.U[(uint64_t)nn * A.K + kk];
-                Bs_re[bk + i][bn] = v.x;
-                Bs_im[bk + i][bn] = csgn * v.y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            pb[i] = cmake<R>((R)0, (R)0);
+            if (!A.trans) {
+                const int kk = k0 + b_k + i, nn = n0 + b_n;
+                if (kk < A.K && nn < A.N) pb[i] = A.U[(uint64_t)nn * A.K + kk];
+            } else {
+                const int kk = k0 + b_k, nn = n0 + b_n + i;
+                if (kk < A.K && nn < A.N) pb[i] = A.U[(uint64_t)kk * A.N + nn];
             }
-        } else {
-            const int bk = tid >> 4, bn = (tid & 15) * 4;
-            for (int i = 0; i < 4; ++i) {
-                const int kk = k0 + bk, nn = n0 + bn + i;
-                cvec<R> v = cmake<R>((R)0, (R)0);
-                if (kk < A.K && nn < A.N) v = A.U[(uint64_t)kk * A.N + nn];
-                Bs_re[bk][bn + i] = v.x;
-                Bs_im[bk][bn + i] = csgn * v.y;
-            }
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < A.K; k0 += GBK) {
+        // A tile: 64 rows x 16 k; B tile: 16 k x 64 n
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            As_re[a_k + i][a_row] = pa[i].x;
+            As_im[a_k + i][a_row] = pa[i].y;
+            const int bk = A.trans ? b_k : b_k + i, bn = A.trans ? b_n + i : b_n;
+            Bs_re[bk][bn] = pb[i].x;
+            Bs_im[bk][bn] = csgn * pb[i].y;
         }
         __syncthreads();
+        if (k0 + GBK < A.K) fetch(k0 + GBK);
 #pragma unroll
         for (int kc = 0; kc < GBK / 4; ++kc) {
             const int kr = kc * 4 + (lane >> 4), li = lane & 15;
