@@ -61,7 +61,13 @@ constexpr int MAX_RB = 5;
 struct FSeg {
     int pos[MAX_RB];       // tile positions held in registers (register bit i = pos[i]), ascending
     int nops, op_off;
-    uint32_t off[1 << MAX_RB];   // LDS byte offset of register index m: swz of its tile bits x amplitude size
+    // LDS byte offsets (swz of the tile bits times the amplitude size) that
+    // register index m is read from and written to.  They differ from the
+    // slot of m itself where the segment's register permutations at its
+    // start or end (register-controlled NOTs that commute there) were
+    // folded into them.
+    uint32_t off[1 << MAX_RB];
+    uint32_t offw[1 << MAX_RB];
 };
 
 struct FPass {
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                     reg_apply<R, RB>(v, f);
                 }
 #pragma unroll
-                for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ off[m])) = v[m];
+                for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ S.offw[m])) = v[m];
             }
             __syncthreads();
         }
@@ -571,6 +577,9 @@ constexpr int MAX_OPS_PER_PASS = 96;
 
 static void plan(int n, int kmax, int c0, const std::vector<PGate> &gates, std::vector<HostPass> &passes) {
     passes.clear();
+    // a gate needs at most two local bits besides the low run, so every pass
+    // takes at least the first gate left (callers pass c0 <= kmax - 2)
+    c0 = std::max(0, std::min(c0, kmax - 2));
     std::vector<char> done(gates.size(), 0);
     size_t left = gates.size();
     const uint64_t low = (1ull << std::min(c0, n)) - 1ull;
@@ -632,6 +641,58 @@ static uint32_t on_mask(uint32_t rmask, uint32_t rval, int RB) {
     for (uint32_t m = 0; m < (1u << RB); ++m)
         if ((m & rmask) == rval) on |= 1u << m;
     return on;
+}
+
+// Register-controlled NOTs at either end of a segment permute the register
+// indices only, so they need no arithmetic: those that commute to the start
+// (with every op before them that is not moved) become the read offsets,
+// those that commute to the end the write offsets, and both leave the op
+// list.  A NOT moves only if its condition is on register bits alone (no
+// tile or non-local control); an op touches its target and condition bits,
+// a phase every register bit.  If P is the product of the leading NOTs in
+// program order, register m holds the amplitude of P^-1(m) after them; if T
+// is that of the trailing ones, the value in register m ends at T(m).
+static void fold_permutations(FSeg &g, std::vector<ROp> &rops, int RB) {
+    const size_t n = (size_t)g.nops, b0 = (size_t)g.op_off;
+    const uint32_t all = (1u << RB) - 1u;
+    auto movable = [](const ROp &f) { return f.type == OP_X && f.tmask == 0 && f.gmask == 0; };
+    auto touched = [&](const ROp &f) { return f.type == OP_PHASE ? all : ((1u << f.j0) | f.rmask); };
+    auto xmap = [](const ROp &f, uint32_t m) { return (m & f.rmask) == f.rval ? m ^ (1u << f.j0) : m; };
+    std::vector<char> lead(n, 0), trail(n, 0);
+    uint32_t blocked = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const ROp &f = rops[b0 + i];
+        if (movable(f) && !(touched(f) & blocked))
+            lead[i] = 1;
+        else
+            blocked |= touched(f);
+    }
+    blocked = 0;
+    for (size_t i = n; i-- > 0;) {
+        const ROp &f = rops[b0 + i];
+        if (lead[i]) continue;
+        if (movable(f) && !(touched(f) & blocked))
+            trail[i] = 1;
+        else
+            blocked |= touched(f);
+    }
+    uint32_t base[1 << MAX_RB];
+    for (uint32_t m = 0; m <= all; ++m) base[m] = g.off[m];
+    for (uint32_t m = 0; m <= all; ++m) {
+        uint32_t p = m;      // P^-1(m): the leading NOTs from the last to the first
+        for (size_t i = n; i-- > 0;)
+            if (lead[i]) p = xmap(rops[b0 + i], p);
+        uint32_t q = m;      // T(m), where the value in register m ends: the trailing NOTs from the first
+        for (size_t i = 0; i < n; ++i)
+            if (trail[i]) q = xmap(rops[b0 + i], q);
+        g.off[m] = base[p];
+        g.offw[m] = base[q];
+    }
+    size_t w = b0;
+    for (size_t i = 0; i < n; ++i)
+        if (!lead[i] && !trail[i]) rops[w++] = rops[b0 + i];
+    rops.resize(w);
+    g.nops = (int)(w - b0);
 }
 
 // cut a pass's gate list into register segments of at most RB target
@@ -732,6 +793,7 @@ static void segment_pass(const HostPass &hp, int RB, int swz_bits, std::vector<F
             }
             rops.push_back(o);
         }
+        fold_permutations(g, rops, RB);
         segs.push_back(g);
     }
 }
