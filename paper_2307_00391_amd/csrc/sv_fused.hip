@@ -148,16 +148,33 @@ __device__ __forceinline__ void reg_u(cvec<R> (&v)[1 << RB], const ROp &f) {
     }
 }
 
+// A conditional swap in place on the bits, d = (a ^ b) & mask, a ^= d,
+// b ^= d: three instructions per pair of words (the AND folds into one
+// three-input bit op), where selects of both words into fresh registers and
+// moves back took four, with no register permutation for the compiler to resolve
+__device__ __forceinline__ void cswap_bits(float &a, float &b, uint32_t mask) {
+    const uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+    const uint32_t d = (x ^ y) & mask;
+    a = __builtin_bit_cast(float, x ^ d);
+    b = __builtin_bit_cast(float, y ^ d);
+}
+__device__ __forceinline__ void cswap_bits(double &a, double &b, uint32_t mask) {
+    const uint64_t m64 = mask ? ~0ull : 0ull;
+    const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    const uint64_t d = (x ^ y) & m64;
+    a = __builtin_bit_cast(double, x ^ d);
+    b = __builtin_bit_cast(double, y ^ d);
+}
+
 template <typename R, int RB, int J>
 __device__ __forceinline__ void reg_x(cvec<R> (&v)[1 << RB], const ROp &f) {
     const uint32_t on = f.onm;
 #pragma unroll
     for (int m = 0; m < (1 << RB); ++m) {
         if (m & (1 << J)) continue;
-        if (!(on >> m & 1u)) continue;
-        const cvec<R> a0 = v[m];
-        v[m] = v[m | (1 << J)];
-        v[m | (1 << J)] = a0;
+        const uint32_t mask = 0u - (on >> m & 1u);
+        cswap_bits(v[m].x, v[m | (1 << J)].x, mask);
+        cswap_bits(v[m].y, v[m | (1 << J)].y, mask);
     }
 }
 
