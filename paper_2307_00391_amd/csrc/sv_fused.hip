@@ -212,6 +212,24 @@ __device__ __forceinline__ void reg_apply(cvec<R> (&v)[1 << RB], const ROp &f) {
     }
 }
 
+// LDS access by byte address.  The kernels that use these have no static LDS,
+// so their dynamic area starts at address 0 (the host checks this): a slot's
+// byte offset, formed by XOR, is then its address with no base added.
+template <typename R> using v2r = R __attribute__((ext_vector_type(2)));
+template <typename T> using lptr = __attribute__((address_space(3))) T *;
+template <typename R>
+__device__ __forceinline__ cvec<R> lds_ld(uint32_t a) {
+    const v2r<R> x = *(lptr<v2r<R>>)(uintptr_t)a;
+    return cmake<R>(x.x, x.y);
+}
+template <typename R>
+__device__ __forceinline__ void lds_st(uint32_t a, cvec<R> v) {
+    v2r<R> x;
+    x.x = v.x;
+    x.y = v.y;
+    *(lptr<v2r<R>>)(uintptr_t)a = x;
+}
+
 // One fused pass.  Blocks walk the tiles tile = block + i * (blocks in the
 // grid): the grid is what the device holds at once, or one tile per block
 // when that covers them all.  (Reading the next tile into registers during
@@ -260,7 +278,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                     w ^= hs[i];
                 }
             uoff[u] = o;
-            uswz[u] = w;
+            uswz[u] = w * (uint32_t)sizeof(cvec<R>);     // bytes
         }
     }
     for (uint64_t tl = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x; tl < ntiles; tl += tstride) {
@@ -268,12 +286,12 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
         if (big) {
             for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
                 const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
-                const uint32_t s0 = sthr ^ swz<R>(t0);
+                const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff[u]];
 #pragma unroll
-                for (int u = 0; u < U; ++u) tile[s0 ^ uswz[u]] = buf[u];
+                for (int u = 0; u < U; ++u) lds_st<R>(s0 ^ uswz[u], buf[u]);
             }
         } else {
             for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
@@ -286,7 +304,6 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
             // swz is XOR-linear and bt and the register bits are disjoint, so the
             // slot of bt | (bits of m) is swz(bt) ^ S.off[m] (the table is uniform,
             // in bytes, as the slot is used)
-            unsigned char *tb = reinterpret_cast<unsigned char *>(tile);
             uint32_t off[1 << RB];
 #pragma unroll
             for (int m = 0; m < (1 << RB); ++m) off[m] = S.off[m];
@@ -300,14 +317,14 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                 const uint32_t sbt = swz<R>(bt) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> v[1 << RB];
 #pragma unroll
-                for (int m = 0; m < (1 << RB); ++m) v[m] = *reinterpret_cast<const cvec<R> *>(tb + (sbt ^ off[m]));
+                for (int m = 0; m < (1 << RB); ++m) v[m] = lds_ld<R>(sbt ^ off[m]);
                 for (int o = 0; o < S.nops; ++o) {
                     const ROp &f = op0[o];
                     if ((base & f.gmask) != f.gval || (bt & f.tmask) != f.tval) continue;
                     reg_apply<R, RB>(v, f);
                 }
 #pragma unroll
-                for (int m = 0; m < (1 << RB); ++m) *reinterpret_cast<cvec<R> *>(tb + (sbt ^ S.offw[m])) = v[m];
+                for (int m = 0; m < (1 << RB); ++m) lds_st<R>(sbt ^ S.offw[m], v[m]);
             }
             __syncthreads();
         }
@@ -315,10 +332,10 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
         if (big) {
             for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
                 const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
-                const uint32_t s0 = sthr ^ swz<R>(t0);
+                const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) buf[u] = tile[s0 ^ uswz[u]];
+                for (int u = 0; u < U; ++u) buf[u] = lds_ld<R>(s0 ^ uswz[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u) psi[g0 | uoff[u]] = buf[u];
             }
@@ -415,6 +432,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_qft_pass(cvec<R> *__restrict__ p
 // ---------------------------------------------------------------------------
 
 static int g_lds_limit = 0;
+static bool g_fused_lds_at_0 = false;   // k_fused has no static LDS: its tile starts at address 0
 
 static int lds_limit_bytes() {
     if (g_lds_limit) return g_lds_limit;
@@ -434,8 +452,14 @@ static int lds_limit_bytes() {
           hipSuccess;
     ok &= hipFuncSetAttribute((const void *)k_qft_pass<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
           hipSuccess;
+    bool at0 = true;
+    for (const void *f : fk) {
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, f) != hipSuccess || fa.sharedSizeBytes != 0) at0 = false;
+    }
     (void)hipGetLastError();
     if (!ok) lim = 65536;
+    g_fused_lds_at_0 = at0;
     g_lds_limit = lim;
     return lim;
 }
@@ -856,6 +880,8 @@ static void launch_fused(uint64_t tiles, size_t lds, hipStream_t st, cvec<R> *ps
 template <typename R>
 static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
     if (passes.empty()) return SV_OK;
+    lds_limit_bytes();
+    if (!g_fused_lds_at_0) return fail(SV_EDEVICE, "the fused-pass kernels carry static LDS; their tile addressing needs none");
     const int RB = reg_bits_for(s->dt, passes[0].hdr.k);
     if (RB < 3) return fail(SV_EUNSUPPORTED, "state too small for fused passes");
     std::vector<FSeg> segs;
