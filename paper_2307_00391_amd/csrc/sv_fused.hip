@@ -249,38 +249,38 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     // HBM <-> LDS with U loads in flight per thread.  scatter_t is a bit
     // deposit, so the thread's part (bits below log2 FUSE_BLOCK), the part of
     // the unrolled index u and that of the outer step t0 combine by OR; the
-    // offsets of u's bits are formed once.
+    // offsets of u's bits are formed once and combined per load (uniform
+    // values: a table of all U combinations held 48 more vector registers
+    // through the whole kernel).
     constexpr int U = sizeof(R) == 4 ? 16 : 8;
     constexpr int LB = 8, LU = sizeof(R) == 4 ? 4 : 3;      // log2 FUSE_BLOCK, log2 U
     const uint64_t gthr = scatter_t(threadIdx.x & (T - 1u), c, r, hpos);
     // swz is XOR-linear too: the LDS slot of t0 + u 256 + thread is
     // swz(thread) ^ swz(t0) ^ swz(u 256)
-    uint64_t uoff[U];
-    uint32_t uswz[U];
     const uint32_t sthr = swz<R>(threadIdx.x);
     const bool big = T >= FUSE_BLOCK * U;
-    if (big) {
-        uint64_t hb[LU];
-        uint32_t hs[LU];
+    // the offsets of the bits of u (HBM and LDS), combined per load
+    uint64_t hb[LU];
+    uint32_t hs[LU];
 #pragma unroll
-        for (int i = 0; i < LU; ++i) {
-            hb[i] = scatter_t(1u << (LB + i), c, r, hpos);
-            hs[i] = swz<R>(1u << (LB + i));
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            uint64_t o = 0;
-            uint32_t w = 0;
-#pragma unroll
-            for (int i = 0; i < LU; ++i)
-                if (u >> i & 1) {
-                    o |= hb[i];
-                    w ^= hs[i];
-                }
-            uoff[u] = o;
-            uswz[u] = w * (uint32_t)sizeof(cvec<R>);     // bytes
-        }
+    for (int i = 0; i < LU; ++i) {
+        hb[i] = big ? scatter_t(1u << (LB + i), c, r, hpos) : 0;
+        hs[i] = swz<R>(1u << (LB + i)) * (uint32_t)sizeof(cvec<R>);
     }
+    auto uoff = [&](int u) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int i = 0; i < LU; ++i)
+            if (u >> i & 1) o |= hb[i];
+        return o;
+    };
+    auto uswz = [&](int u) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int i = 0; i < LU; ++i)
+            if (u >> i & 1) w ^= hs[i];
+        return w;
+    };
     for (uint64_t tl = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x; tl < ntiles; tl += tstride) {
         const uint64_t base = pdep64(tl, P.nl_mask) | P.fix_val;
         if (big) {
@@ -289,9 +289,9 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                 const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff[u]];
+                for (int u = 0; u < U; ++u) buf[u] = psi[g0 | uoff(u)];
 #pragma unroll
-                for (int u = 0; u < U; ++u) lds_st<R>(s0 ^ uswz[u], buf[u]);
+                for (int u = 0; u < U; ++u) lds_st<R>(s0 ^ uswz(u), buf[u]);
             }
         } else {
             for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
@@ -335,9 +335,9 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                 const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) buf[u] = lds_ld<R>(s0 ^ uswz[u]);
+                for (int u = 0; u < U; ++u) buf[u] = lds_ld<R>(s0 ^ uswz(u));
 #pragma unroll
-                for (int u = 0; u < U; ++u) psi[g0 | uoff[u]] = buf[u];
+                for (int u = 0; u < U; ++u) psi[g0 | uoff(u)] = buf[u];
             }
         } else {
             for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
