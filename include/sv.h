@@ -383,7 +383,9 @@ int sv_trace_report(char *buf, int len);
  *   cgemm/<dtype>/<M>/<N>/<K>/<trans>  the matrix-core GEMM's tile shape:
  *       0 = 64 x 64 per workgroup, 1 = 16 x 16 per wavefront;
  *   fused/<dtype>/<n>/<circuit>  sv_apply_circuit with max_local = 0: (k
- *       local qubits, c contiguous low bits) per circuit structure.
+ *       local qubits, c contiguous low bits, rb register bits per segment
+ *       line: 5 or 4 for complex64, 4 or 3 for complex128) per circuit
+ *       structure; an entry of (k, c) takes the default rb.
  * Returns the report length. */
 int sv_tune_report(char *buf, int len);
 /* Sets (n > 0: vals[0..n)) or removes (n == 0) one tuning entry, with the key

@@ -877,12 +877,18 @@ static void launch_fused(uint64_t tiles, size_t lds, hipStream_t st, cvec<R> *ps
     hipLaunchKernelGGL((k_fused<R, RB>), grid, dim3(FUSE_BLOCK), lds, st, psi, dp, i, ds, dops, tiles);
 }
 
+// rb_req: amplitudes per thread in a segment as 2^rb_req (the fusion tuner's
+// choice), 0 for the default of reg_bits_for
 template <typename R>
-static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes) {
+static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes, int rb_req = 0) {
     if (passes.empty()) return SV_OK;
     lds_limit_bytes();
     if (!g_fused_lds_at_0) return fail(SV_EDEVICE, "the fused-pass kernels carry static LDS; their tile addressing needs none");
-    const int RB = reg_bits_for(s->dt, passes[0].hdr.k);
+    int RB = reg_bits_for(s->dt, passes[0].hdr.k);
+    if (rb_req > 0) {
+        if (rb_req < 3 || rb_req > (sizeof(R) == 4 ? 5 : 4)) return fail(SV_EINVAL, "%d register bits per segment line", rb_req);
+        RB = std::min(rb_req, passes[0].hdr.k);
+    }
     if (RB < 3) return fail(SV_EUNSUPPORTED, "state too small for fused passes");
     std::vector<FSeg> segs;
     std::vector<ROp> rops;
@@ -1032,11 +1038,14 @@ namespace sv {
 // The fusion autotuner (sv_apply_circuit with max_local = 0, states of 2^22
 // amplitudes and more): the candidates are k local qubits in {K-1, K} (K the
 // default, bounded by the LDS) times c contiguous low bits in {C-1, C, C+1}
-// (C the default, c <= k - 2).  Each candidate's plan is made for the whole
+// (C the default, c <= k - 2) times rb register bits per segment line (the
+// default and one fewer).  Each candidate's plan is made for the whole
 // circuit and its first passes are timed on a scratch copy of the state (the
-// state itself is not touched); the estimate (passes x mean pass time)
-// decides.  Cached per dtype, size and circuit structure (gate kinds and
-// qubits, not angles).  SV_FUSED_LOWBITS pins c and skips the tuning.
+// state itself is not touched): the first pass, plus the mean of up to eight
+// others spread over the plan times their number.  The two best estimates
+// then run their whole plan, and the faster is kept.  Cached per dtype, size and circuit
+// structure (gate kinds and qubits, not angles) as (k, c, rb); an entry of
+// (k, c) takes the default rb.  SV_FUSED_LOWBITS pins c and skips the tuning.
 static uint64_t circuit_signature(const std::vector<PGate> &pg) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t v) {
@@ -1057,15 +1066,16 @@ static uint64_t circuit_signature(const std::vector<PGate> &pg) {
     return h;
 }
 
-sv_status fusion_config(sv_state s, const std::vector<PGate> &pg, int &k, int &c) {
+sv_status fusion_config(sv_state s, const std::vector<PGate> &pg, int &k, int &c, int &rb) {
     if (s->n < 22 || getenv("SV_FUSED_LOWBITS")) return SV_OK;
     char sig[32];
     snprintf(sig, sizeof sig, "%016llx", (unsigned long long)circuit_signature(pg));
     const std::string key = std::string("fused/") + (s->dt == SV_C64 ? "c64/" : "c128/") + std::to_string(s->n) + "/" + sig;
     std::vector<int> cached;
-    if (tune_lookup(key, cached) && cached.size() == 2) {
+    if (tune_lookup(key, cached) && (cached.size() == 2 || cached.size() == 3)) {
         k = cached[0];
         c = cached[1];
+        rb = cached.size() == 3 ? cached[2] : 0;
         return SV_OK;
     }
     if (!autotune_enabled()) return SV_OK;
@@ -1087,34 +1097,67 @@ sv_status fusion_config(sv_state s, const std::vector<PGate> &pg, int &k, int &c
     sv_status st = SV_OK;
     if (hipMemcpyAsync(scratch, s->data, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
         st = fail(SV_EDEVICE, "scratch copy for the fusion tuner");
-    const int K = k, C = c;
+    // Candidates: tile depth k, contiguous low bits c and register bits per
+    // segment line rb.  Fewer register bits mean more segments but far fewer
+    // registers, so a smaller tile can run three or more workgroups per CU.
+    // A plan's time is estimated from its first pass (which holds the most
+    // ops) plus a sample of the others scaled to their number.
+    const int K = k, C = c, RB0 = s->dt == SV_C64 ? 5 : 4;
+    struct Cand {
+        float est;
+        int k, c, rb;
+    };
+    std::vector<Cand> cands;
     float best = 1e30f;
-    for (int kk = K - 1; kk <= K && st == SV_OK; ++kk) {
-        if (kk < 3 || reg_bits_for(s->dt, kk) < 3) continue;
-        for (int cc = C - 1; cc <= C + 1 && st == SV_OK; ++cc) {
-            if (cc < 0 || cc > kk - 2) continue;
-            std::vector<HostPass> passes;
-            plan(s->n, kk, cc, pg, passes);
-            if (passes.empty()) continue;
-            const size_t P = passes.size() < 3 ? passes.size() : 3;
-            float ms = 0.f;
-            st = time_stream(s->stream, 1, &ms, [&]() {
-                std::vector<HostPass> pre(passes.begin(), passes.begin() + P);
-                return s->dt == SV_C64 ? launch_passes<float>(t, pre) : launch_passes<double>(t, pre);
-            });
-            const float est = ms * (float)passes.size() / (float)P;
-            if (st == SV_OK && est < best) {
-                best = est;
-                k = kk;
-                c = cc;
+    for (int rr = RB0; rr >= RB0 - 1 && st == SV_OK; --rr) {
+        for (int kk = K - 1; kk <= K && st == SV_OK; ++kk) {
+            if (kk < 3 || kk < rr) continue;
+            for (int cc = C - 1; cc <= C + 1 && st == SV_OK; ++cc) {
+                if (cc < 0 || cc > kk - 2) continue;
+                std::vector<HostPass> passes;
+                plan(s->n, kk, cc, pg, passes);
+                if (passes.empty()) continue;
+                // the first pass, and up to eight of the others spread evenly
+                // over the plan (pass times vary several-fold along it)
+                const size_t N = passes.size(), S = N - 1 < 8 ? N - 1 : 8;
+                std::vector<HostPass> first(passes.begin(), passes.begin() + 1), sample;
+                for (size_t j = 0; j < S; ++j) sample.push_back(passes[1 + j * (N - 1) / S]);
+                float ms0 = 0.f, ms1 = 0.f;
+                st = time_stream(s->stream, 1, &ms0, [&]() {
+                    return s->dt == SV_C64 ? launch_passes<float>(t, first, rr) : launch_passes<double>(t, first, rr);
+                });
+                if (st == SV_OK && S > 0)
+                    st = time_stream(s->stream, 1, &ms1, [&]() {
+                        return s->dt == SV_C64 ? launch_passes<float>(t, sample, rr) : launch_passes<double>(t, sample, rr);
+                    });
+                const float est = ms0 + (S > 0 ? ms1 * (float)(N - 1) / (float)S : 0.f);
+                if (st == SV_OK) cands.push_back({est, kk, cc, rr});
             }
+        }
+    }
+    // the two best estimates are close more often than the sample can tell
+    // apart: both run their whole plan, and the faster is kept
+    std::sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.est < y.est; });
+    for (size_t i = 0; i < cands.size() && i < 2 && st == SV_OK; ++i) {
+        const Cand &cd = cands[i];
+        std::vector<HostPass> passes;
+        plan(s->n, cd.k, cd.c, pg, passes);
+        float ms = 0.f;
+        st = time_stream(s->stream, 1, &ms, [&]() {
+            return s->dt == SV_C64 ? launch_passes<float>(t, passes, cd.rb) : launch_passes<double>(t, passes, cd.rb);
+        });
+        if (st == SV_OK && ms < best) {
+            best = ms;
+            k = cd.k;
+            c = cd.c;
+            rb = cd.rb;
         }
     }
     hipStreamSynchronize(s->stream);
     sv_free(t);
     hipFree(scratch);
     if (st != SV_OK) return st;
-    tune_store(key, {k, c});
+    tune_store(key, {k, c, rb});
     return SV_OK;
 }
 
@@ -1147,11 +1190,11 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, int n_gates, int ma
     SV_TRY(to_pgates(s, gates, n_gates, pg));
     int k = clamp_k(s, max_local);
     if (k < 3) return fail(SV_EUNSUPPORTED, "state too small for fused passes");
-    int c = std::max(0, std::min(low_bits_for(s->dt), k - 2));
-    if (max_local == 0) SV_TRY(fusion_config(s, pg, k, c));
+    int c = std::max(0, std::min(low_bits_for(s->dt), k - 2)), rb = 0;
+    if (max_local == 0) SV_TRY(fusion_config(s, pg, k, c, rb));
     std::vector<HostPass> passes;
     plan(s->n, k, c, pg, passes);
-    return s->dt == SV_C64 ? launch_passes<float>(s, passes) : launch_passes<double>(s, passes);
+    return s->dt == SV_C64 ? launch_passes<float>(s, passes, rb) : launch_passes<double>(s, passes, rb);
 }
 
 sv_status sv_qft(sv_state s, int q_lo, int m, int inverse, int swaps, int max_local) {

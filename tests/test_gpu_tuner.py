@@ -156,7 +156,8 @@ def _oracle_apply(psi, g):
 def _fusion_candidates(dt):
     K = 13 if dt == "c64" else 12
     C = 5 if dt == "c64" else 4
-    return [(k, c) for k in (K - 1, K) for c in (C - 1, C, C + 1) if c <= k - 2]
+    RB = 5 if dt == "c64" else 4
+    return [(k, c, rb) for rb in (RB, RB - 1) for k in (K - 1, K) for c in (C - 1, C, C + 1) if c <= k - 2]
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
@@ -175,12 +176,13 @@ def test_fusion_candidates(dt, monkeypatch):
     for g in perm:
         _oracle_apply(ref_p, g)
     outs_p = []
-    for k, c in _fusion_candidates(dt):
+    for k, c, rb in _fusion_candidates(dt):
         monkeypatch.setenv("SV_FUSED_LOWBITS", str(c))
+        monkeypatch.setenv("SV_FUSED_RB", str(rb))
         s = B.State(n, dt)
         s.set(psi0)
         B.sv_apply_circuit(s.h, gates, k)
-        assert np.abs(s.get() - ref).max() <= TOL[dt], (k, c)
+        assert np.abs(s.get() - ref).max() <= TOL[dt], (k, c, rb)
         s.set(psi0)
         B.sv_apply_circuit(s.h, perm, k)
         outs_p.append(s.get())
@@ -189,6 +191,7 @@ def test_fusion_candidates(dt, monkeypatch):
         assert np.array_equal(o, ref_p)
     # the tuner's own choice
     monkeypatch.delenv("SV_FUSED_LOWBITS")
+    monkeypatch.delenv("SV_FUSED_RB")
     s = B.State(n, dt)
     s.set(psi0)
     B.sv_apply_circuit(s.h, gates, 0)
