@@ -1042,8 +1042,8 @@ namespace sv {
 // default and one fewer).  Each candidate's plan is made for the whole
 // circuit and its first passes are timed on a scratch copy of the state (the
 // state itself is not touched): the first pass, plus the mean of up to eight
-// others spread over the plan times their number.  The two best estimates
-// then run their whole plan, and the faster is kept.  Cached per dtype, size and circuit
+// others spread over the plan times their number.  When the two best
+// estimates are within 10 %, both run their whole plan, and the faster is kept.  Cached per dtype, size and circuit
 // structure (gate kinds and qubits, not angles) as (k, c, rb); an entry of
 // (k, c) takes the default rb.  SV_FUSED_LOWBITS pins c and skips the tuning.
 static uint64_t circuit_signature(const std::vector<PGate> &pg) {
@@ -1135,10 +1135,16 @@ sv_status fusion_config(sv_state s, const std::vector<PGate> &pg, int &k, int &c
             }
         }
     }
-    // the two best estimates are close more often than the sample can tell
-    // apart: both run their whole plan, and the faster is kept
+    // the two best estimates, when within 10 % of each other (closer than the
+    // sample can tell apart), both run their whole plan, and the faster is kept
     std::sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.est < y.est; });
-    for (size_t i = 0; i < cands.size() && i < 2 && st == SV_OK; ++i) {
+    const size_t nfull = cands.size() > 1 && cands[1].est <= 1.1f * cands[0].est ? 2 : 1;
+    if (nfull == 1 && !cands.empty()) {
+        k = cands[0].k;
+        c = cands[0].c;
+        rb = cands[0].rb;
+    }
+    for (size_t i = 0; i < cands.size() && i < nfull && nfull > 1 && st == SV_OK; ++i) {
         const Cand &cd = cands[i];
         std::vector<HostPass> passes;
         plan(s->n, cd.k, cd.c, pg, passes);
