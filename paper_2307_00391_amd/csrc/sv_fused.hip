@@ -234,8 +234,8 @@ __device__ __forceinline__ void lds_st(uint32_t a, cvec<R> v) {
 // grid): the grid is what the device holds at once, or one tile per block
 // when that covers them all.  (Reading the next tile into registers during
 // this tile's segments cost more in registers than it hid.)
-template <typename R, int RB>
-__global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi, const FPass *__restrict__ passes,
+template <typename R, int RB, int NT = FUSE_BLOCK>
+__global__ __launch_bounds__(NT) void k_fused(cvec<R> *__restrict__ psi, const FPass *__restrict__ passes,
                                                        int pi, const FSeg *__restrict__ segs,
                                                        const ROp *__restrict__ ops, uint64_t ntiles) {
     extern __shared__ unsigned char smem_raw[];
@@ -247,18 +247,18 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     const int *hpos = P.hpos;
 
     // HBM <-> LDS with U loads in flight per thread.  scatter_t is a bit
-    // deposit, so the thread's part (bits below log2 FUSE_BLOCK), the part of
+    // deposit, so the thread's part (bits below log2 NT), the part of
     // the unrolled index u and that of the outer step t0 combine by OR; the
     // offsets of u's bits are formed once and combined per load (uniform
     // values: a table of all U combinations held 48 more vector registers
     // through the whole kernel).
     constexpr int U = sizeof(R) == 4 ? 16 : 8;
-    constexpr int LB = 8, LU = sizeof(R) == 4 ? 4 : 3;      // log2 FUSE_BLOCK, log2 U
+    constexpr int LB = NT == 512 ? 9 : 8, LU = sizeof(R) == 4 ? 4 : 3;      // log2 NT, log2 U
     const uint64_t gthr = scatter_t(threadIdx.x & (T - 1u), c, r, hpos);
     // swz is XOR-linear too: the LDS slot of t0 + u 256 + thread is
     // swz(thread) ^ swz(t0) ^ swz(u 256)
     const uint32_t sthr = swz<R>(threadIdx.x);
-    const bool big = T >= FUSE_BLOCK * U;
+    const bool big = T >= NT * U;
     // the offsets of the bits of u (HBM and LDS), combined per load
     uint64_t hb[LU];
     uint32_t hs[LU];
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
     for (uint64_t tl = (uint64_t)blockIdx.x + (uint64_t)blockIdx.y * gridDim.x; tl < ntiles; tl += tstride) {
         const uint64_t base = pdep64(tl, P.nl_mask) | P.fix_val;
         if (big) {
-            for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            for (uint32_t t0 = 0; t0 < T; t0 += NT * U) {
                 const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
                 const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                 for (int u = 0; u < U; ++u) lds_st<R>(s0 ^ uswz(u), buf[u]);
             }
         } else {
-            for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
+            for (uint32_t t = threadIdx.x; t < T; t += NT) tile[swz<R>(t)] = psi[base | scatter_t(t, c, r, hpos)];
         }
         __syncthreads();
 
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
 #pragma unroll
             for (int m = 0; m < (1 << RB); ++m) off[m] = S.off[m];
             const ROp *op0 = ops + S.op_off;
-            for (uint32_t line = threadIdx.x; line < lines; line += FUSE_BLOCK) {
+            for (uint32_t line = threadIdx.x; line < lines; line += NT) {
                 // the tile bits outside the register positions: the line index
                 // with a zero inserted at each position, lowest first
                 uint32_t bt = line;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
         }
 
         if (big) {
-            for (uint32_t t0 = 0; t0 < T; t0 += FUSE_BLOCK * U) {
+            for (uint32_t t0 = 0; t0 < T; t0 += NT * U) {
                 const uint64_t g0 = base | gthr | scatter_t(t0, c, r, hpos);
                 const uint32_t s0 = (sthr ^ swz<R>(t0)) * (uint32_t)sizeof(cvec<R>);
                 cvec<R> buf[U];
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(FUSE_BLOCK) void k_fused(cvec<R> *__restrict__ psi,
                 for (int u = 0; u < U; ++u) psi[g0 | uoff(u)] = buf[u];
             }
         } else {
-            for (uint32_t t = threadIdx.x; t < T; t += FUSE_BLOCK) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
+            for (uint32_t t = threadIdx.x; t < T; t += NT) psi[base | scatter_t(t, c, r, hpos)] = tile[swz<R>(t)];
         }
         // the next tile is written into the LDS this one was read from
         if (tl + tstride < ntiles) __syncthreads();
@@ -445,8 +445,8 @@ static int lds_limit_bytes() {
     if (lim > 147456) lim = 147456;   // the largest power-of-two tile (128 KiB) plus headroom
     bool ok = true;
     const void *fk[] = {(const void *)k_fused<float, 5>, (const void *)k_fused<float, 4>,
-                        (const void *)k_fused<float, 3>, (const void *)k_fused<double, 4>,
-                        (const void *)k_fused<double, 3>};
+                        (const void *)k_fused<float, 4, 512>, (const void *)k_fused<float, 3>,
+                        (const void *)k_fused<double, 4>, (const void *)k_fused<double, 3>};
     for (const void *f : fk) ok &= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) == hipSuccess;
     ok &= hipFuncSetAttribute((const void *)k_qft_pass<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) ==
           hipSuccess;
@@ -861,7 +861,7 @@ static int fused_persist_env() {
     return v;
 }
 
-template <typename R, int RB>
+template <typename R, int RB, int NT = FUSE_BLOCK>
 static void launch_fused(uint64_t tiles, size_t lds, hipStream_t st, cvec<R> *psi, const FPass *dp, int i,
                          const FSeg *ds, const ROp *dops) {
     dim3 grid = tile_grid(tiles);
@@ -869,12 +869,12 @@ static void launch_fused(uint64_t tiles, size_t lds, hipStream_t st, cvec<R> *ps
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_fused<R, RB>, FUSE_BLOCK, lds);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_fused<R, RB, NT>, NT, lds);
         (void)hipGetLastError();
         const uint64_t slots = (uint64_t)(cus > 0 ? cus : 1) * (uint64_t)(per > 0 ? per : 1);
         if (slots < tiles) grid = dim3((unsigned)slots);
     }
-    hipLaunchKernelGGL((k_fused<R, RB>), grid, dim3(FUSE_BLOCK), lds, st, psi, dp, i, ds, dops, tiles);
+    hipLaunchKernelGGL((k_fused<R, RB, NT>), grid, dim3(NT), lds, st, psi, dp, i, ds, dops, tiles);
 }
 
 // rb_req: amplitudes per thread in a segment as 2^rb_req (the fusion tuner's
@@ -922,7 +922,12 @@ static sv_status launch_passes(sv_state s, std::vector<HostPass> &passes, int rb
         const size_t lds = ((size_t)1 << h.k) * sizeof(cvec<R>);
         TraceScope _ts(s->stream, "fused_pass", 2.0 * (double)dim_of(s->n) * sizeof(cvec<R>), 0.0);
         cvec<R> *psi = (cvec<R> *)s->data;
+        // complex64 lines of 16 amplitudes on tiles of 2^13 or more: 512
+        // threads, so that each has one line per segment and two workgroups
+        // of a 64 KiB tile keep four waves on every SIMD
         if (RB == 5 && sizeof(R) == 4) launch_fused<float, 5>(tiles, lds, s->stream, (cvec<float> *)psi, dp, (int)i, ds, dops);
+        else if (RB >= 4 && sizeof(R) == 4 && (1u << (h.k - 4)) >= 512u)
+            launch_fused<float, 4, 512>(tiles, lds, s->stream, (cvec<float> *)psi, dp, (int)i, ds, dops);
         else if (RB >= 4) launch_fused<R, 4>(tiles, lds, s->stream, psi, dp, (int)i, ds, dops);
         else launch_fused<R, 3>(tiles, lds, s->stream, psi, dp, (int)i, ds, dops);
     }
